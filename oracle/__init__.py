@@ -1,0 +1,179 @@
+"""CPU oracle for RAK label propagation, modularity and NMI.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The GPU library never imports this
+package and the two share no code.
+
+Paper: Sahu, arXiv 2301.09125.  RAK/LPA, weighted (Section 3.2): unique
+initial labels, each vertex adopts the label with the most interconnecting
+weight, stop when at most a `tolerance` fraction of vertices changed
+(Sections 3.2 and 4).  Modularity (Section 1) and NMI (Section 2) are the
+quality measures the paper names.
+
+Readings where the paper is silent (shared with the C source): synchronous
+rounds, lowest-label tie-break for the strict mode, the paper's per-vertex
+self-loop modelled by `self_weight` added to the vertex's own label, stop
+after round t iff changed_t <= floor(tol * n), iteration cap `max_iter`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so (gcc -O2, no OpenMP: the oracle is sequential)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-std=c11", "-o", tmp,
+                               os.path.join(_HERE, "oracle.c"), "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        vp, u32, u64, dbl = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+        lib.orc_rak.argtypes = [u32, vp, vp, vp, u32, dbl, u32, vp, vp, vp, vp, vp]
+        lib.orc_rak.restype = ctypes.c_int
+        lib.orc_rak_round.argtypes = [u32, vp, vp, vp, u32, vp, vp, vp]
+        lib.orc_rak_round.restype = ctypes.c_int64
+        lib.orc_rak_masked.argtypes = [u32, vp, vp, vp, u32, u32, vp, vp, vp, vp]
+        lib.orc_rak_masked.restype = ctypes.c_int
+        lib.orc_modularity.argtypes = [u32, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.orc_modularity.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__({-1: "invalid input", -2: "weighted degree overflows 32 bits",
+                          -3: "out of memory"}.get(code, f"error {code}"))
+        self.code = code
+
+
+def _arrs(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.uint64)
+    col = np.ascontiguousarray(g.col, dtype=np.uint32)
+    w = None if g.w is None else np.ascontiguousarray(g.w, dtype=np.uint32)
+    return rp, col, w
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+@dataclass
+class RakResult:
+    labels: np.ndarray
+    iterations: int
+    converged: bool
+    changed: list = field(default_factory=list)
+
+
+def rak(g, tol: float = 0.05, max_iter: int = 20, self_weight: int = 1,
+        init_labels: np.ndarray | None = None) -> RakResult:
+    """Synchronous RAK (Section 3.2) with the lowest-label tie-break."""
+    rp, col, w = _arrs(g)
+    out = np.empty(g.n, dtype=np.uint32)
+    ch = np.zeros(max(max_iter, 1), dtype=np.uint64)
+    it = ctypes.c_uint32(0)
+    cv = ctypes.c_int32(0)
+    init = None if init_labels is None else np.ascontiguousarray(init_labels, dtype=np.uint32)
+    rc = _load().orc_rak(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight, float(tol), max_iter,
+                         _p(init), out.ctypes.data, ch.ctypes.data, ctypes.byref(it), ctypes.byref(cv))
+    if rc:
+        raise OracleError(rc)
+    return RakResult(out, int(it.value), bool(cv.value), [int(x) for x in ch[: it.value]])
+
+
+def rak_round(g, labels: np.ndarray, self_weight: int = 1, active: np.ndarray | None = None):
+    """One synchronous round from `labels`; returns (new_labels, changed)."""
+    rp, col, w = _arrs(g)
+    old = np.ascontiguousarray(labels, dtype=np.uint32)
+    new = np.empty_like(old)
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    ch = _load().orc_rak_round(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight,
+                               old.ctypes.data, new.ctypes.data, _p(act))
+    if ch < 0:
+        raise OracleError(int(ch))
+    return new, int(ch)
+
+
+def rak_masked(g, masks: np.ndarray, self_weight: int = 1, init_labels=None):
+    """Replay rounds restricted to masks[t] (uint8 [rounds, n])."""
+    rp, col, w = _arrs(g)
+    masks = np.ascontiguousarray(masks, dtype=np.uint8)
+    rounds = masks.shape[0] if masks.ndim == 2 else 0
+    out = np.empty(g.n, dtype=np.uint32)
+    ch = np.zeros(max(rounds, 1), dtype=np.uint64)
+    init = None if init_labels is None else np.ascontiguousarray(init_labels, dtype=np.uint32)
+    rc = _load().orc_rak_masked(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight, rounds,
+                                masks.ctypes.data, _p(init), out.ctypes.data, ch.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return out, [int(x) for x in ch[:rounds]]
+
+
+@dataclass
+class ModResult:
+    q: float
+    two_m: int
+    sigma_in: int
+    sum_k2: int
+
+
+def modularity(g, labels: np.ndarray) -> ModResult:
+    """Weighted Newman-Girvan modularity (Section 1), exact integer sums."""
+    rp, col, w = _arrs(g)
+    lab = np.ascontiguousarray(labels, dtype=np.uint32)
+    q = ctypes.c_double(0)
+    tm = ctypes.c_uint64(0)
+    si = ctypes.c_uint64(0)
+    sk = (ctypes.c_uint64 * 2)()
+    rc = _load().orc_modularity(g.n, rp.ctypes.data, col.ctypes.data, _p(w), lab.ctypes.data,
+                                ctypes.byref(q), ctypes.byref(tm), ctypes.byref(si), sk)
+    if rc:
+        raise OracleError(rc)
+    return ModResult(q.value, tm.value, si.value, int(sk[0]) + (int(sk[1]) << 64))
+
+
+def nmi(a, b) -> float:
+    """Normalised mutual information of two partitions (Section 2 names the
+    measure): 2 I(A;B) / (H(A) + H(B)), natural logarithm; 1 when both
+    entropies are 0 (both partitions a single block)."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    if a.size != b.size:
+        raise ValueError("partitions differ in size")
+    N = a.size
+    if N == 0:
+        return 1.0
+    _, ai = np.unique(a, return_inverse=True)
+    _, bi = np.unique(b, return_inverse=True)
+    pa = np.bincount(ai).astype(np.float64) / N
+    pb = np.bincount(bi).astype(np.float64) / N
+    joint = ai.astype(np.int64) * (int(bi.max()) + 1) + bi
+    _, nij = np.unique(joint, return_counts=True)
+    ja = _ // (int(bi.max()) + 1)
+    jb = _ % (int(bi.max()) + 1)
+    pij = nij.astype(np.float64) / N
+    ha = -np.sum(pa * np.log(pa))
+    hb = -np.sum(pb * np.log(pb))
+    mi = np.sum(pij * (np.log(pij) - np.log(pa[ja]) - np.log(pb[jb])))
+    if ha + hb == 0.0:
+        return 1.0
+    return float(2.0 * mi / (ha + hb))

@@ -1,0 +1,232 @@
+/*
+ * oracle.c -- plain, sequential, deliberately slow CPU reference for the RAK
+ * label propagation method and the modularity measure.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this code.  It shares nothing with
+ * the GPU library: no headers, no helpers, no tables.
+ *
+ * What is computed (Sahu, "Selecting a suitable Parallel Label-propagation
+ * based algorithm for Disjoint Community Detection", arXiv 2301.09125):
+ *
+ *  - RAK / LPA, weighted form (Section 3.2; Section 2 for the method): every
+ *    vertex starts with a unique label; in each iteration every vertex takes
+ *    the label whose incident edge weight is largest.  Readings taken where
+ *    the paper leaves the detail open:
+ *      * synchronous rounds: round t reads only the labels of round t-1;
+ *      * "strict" tie-break (pick the first of the tied labels) made
+ *        order-free as: the lowest label value among the tied ones;
+ *      * the paper adds a self-loop to every vertex (Section 3.1.2); the CSR
+ *        holds none and a self_weight is added to the vertex's own label
+ *        (self_weight = 1 mirrors the paper, 0 gives the open neighbourhood);
+ *      * a vertex with nothing to vote on keeps its label;
+ *      * convergence (Section 3.2 and Section 4): the tolerance is the largest
+ *        fraction of vertices allowed to change; stop after round t when
+ *        changed_t <= floor(tol * n), n counting every vertex;
+ *      * an iteration cap max_iter; hitting it is reported, not an error.
+ *  - Modularity (Newman-Girvan, Section 1): with 2m = sum of all arc weights,
+ *    Sigma_in = weight of arcs whose endpoints share a label and
+ *    K_c = sum of weighted degrees in community c,
+ *    Q = Sigma_in / 2m - sum_c K_c^2 / (2m)^2, evaluated on the CSR as given.
+ *    All sums are exact integers; only the final expression is FP64.
+ *
+ * The vote is the textbook definition: gather (label, weight) pairs of the
+ * closed neighbourhood, sort them by label, add up equal labels, keep the
+ * heaviest (lowest label on ties).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+typedef struct { uint32_t label; uint32_t weight; } pair_lw;
+
+static int by_label(const void *a, const void *b) {
+    uint32_t x = ((const pair_lw *)a)->label, y = ((const pair_lw *)b)->label;
+    return (x > y) - (x < y);
+}
+
+/* Validation shared by every entry: returns 0 or -1 (bad CSR) / -2 (a
+ * vertex's weighted degree plus self weight does not fit 32 bits). */
+static int check_csr(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                     uint32_t self_weight) {
+    if (!rp) return -1;
+    if (rp[0] != 0) return -1;
+    for (uint32_t v = 0; v < n; ++v) {
+        if (rp[v + 1] < rp[v]) return -1;
+        uint64_t tot = self_weight;
+        for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) {
+            if (col[e] >= n) return -1;
+            tot += w ? w[e] : 1u;
+        }
+        if (tot > 0xFFFFFFFFull) return -2;
+    }
+    return 0;
+}
+
+/* The label vertex v takes from L_old.  buf must hold deg(v)+1 pairs. */
+static uint32_t vote(uint32_t v, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                     uint32_t self_weight, const uint32_t *L_old, pair_lw *buf) {
+    uint64_t k = 0;
+    if (self_weight > 0) {
+        buf[k].label = L_old[v];
+        buf[k].weight = self_weight;
+        ++k;
+    }
+    for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) {
+        buf[k].label = L_old[col[e]];
+        buf[k].weight = w ? w[e] : 1u;
+        ++k;
+    }
+    if (k == 0) return L_old[v];
+    qsort(buf, (size_t)k, sizeof(pair_lw), by_label);
+    uint32_t best_label = 0;
+    uint64_t best_weight = 0;
+    int have = 0;
+    uint64_t i = 0;
+    while (i < k) {
+        uint32_t lab = buf[i].label;
+        uint64_t sum = 0;
+        while (i < k && buf[i].label == lab) sum += buf[i++].weight;
+        /* labels arrive in increasing order, so a strictly larger sum is
+         * needed to displace the current best: ties keep the lower label */
+        if (!have || sum > best_weight) {
+            best_label = lab;
+            best_weight = sum;
+            have = 1;
+        }
+    }
+    return best_label;
+}
+
+static uint64_t max_degree(uint32_t n, const uint64_t *rp) {
+    uint64_t d = 0;
+    for (uint32_t v = 0; v < n; ++v)
+        if (rp[v + 1] - rp[v] > d) d = rp[v + 1] - rp[v];
+    return d;
+}
+
+/* One synchronous round over the vertices with active[v] != 0 (all if
+ * active == NULL); inactive vertices copy their label.  Returns the number
+ * of vertices whose label changed, or a negative code. */
+int64_t orc_rak_round(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                      uint32_t self_weight, const uint32_t *L_old, uint32_t *L_new,
+                      const uint8_t *active) {
+    pair_lw *buf = (pair_lw *)malloc((size_t)(max_degree(n, rp) + 1) * sizeof(pair_lw));
+    if (!buf) return -3;
+    int64_t changed = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+        uint32_t lab = (active && !active[v]) ? L_old[v] : vote(v, rp, col, w, self_weight, L_old, buf);
+        L_new[v] = lab;
+        changed += (lab != L_old[v]);
+    }
+    free(buf);
+    return changed;
+}
+
+/* Full RAK run.
+ *   init_labels: NULL for the unique initial labels L0(v) = v, else the
+ *                labels to resume from (copied, not modified);
+ *   labels_out:  n labels after the last executed round;
+ *   changed_per_iter: max_iter entries (may be NULL);
+ *   iterations:  rounds executed; converged: 1 if the tolerance test passed.
+ * Returns 0, -1 (invalid input), -2 (weight overflow), -3 (out of memory). */
+int orc_rak(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+            uint32_t self_weight, double tol, uint32_t max_iter, const uint32_t *init_labels,
+            uint32_t *labels_out, uint64_t *changed_per_iter, uint32_t *iterations,
+            int32_t *converged) {
+    if (!(tol >= 0.0 && tol <= 1.0) || !labels_out || !iterations || !converged) return -1;
+    if (n > 0xFFFFFFFEu) return -1;
+    int rc = check_csr(n, rp, col, w, self_weight);
+    if (rc) return rc;
+    if (init_labels)
+        for (uint32_t v = 0; v < n; ++v)
+            if (init_labels[v] >= n) return -1;
+    const uint64_t thr = (uint64_t)floor(tol * (double)n);
+    uint32_t *a = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    uint32_t *b = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    if (!a || !b) { free(a); free(b); return -3; }
+    for (uint32_t v = 0; v < n; ++v) a[v] = init_labels ? init_labels[v] : v;
+    *iterations = 0;
+    *converged = 0;
+    for (uint32_t t = 1; t <= max_iter; ++t) {
+        int64_t ch = orc_rak_round(n, rp, col, w, self_weight, a, b, NULL);
+        if (ch < 0) { free(a); free(b); return (int)ch; }
+        uint32_t *s = a; a = b; b = s;
+        if (changed_per_iter) changed_per_iter[t - 1] = (uint64_t)ch;
+        *iterations = t;
+        if ((uint64_t)ch <= thr) { *converged = 1; break; }
+    }
+    memcpy(labels_out, a, (size_t)n * sizeof(uint32_t));
+    free(a);
+    free(b);
+    return 0;
+}
+
+/* Rounds restricted to given vertex sets: round t votes only the vertices
+ * with masks[(t-1)*n + v] != 0 and copies the others.  Used to replay a run
+ * that skipped vertices.  changed_per_iter gets rounds entries. */
+int orc_rak_masked(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                   uint32_t self_weight, uint32_t rounds, const uint8_t *masks,
+                   const uint32_t *init_labels, uint32_t *labels_out, uint64_t *changed_per_iter) {
+    if (!labels_out || (rounds && !masks)) return -1;
+    int rc = check_csr(n, rp, col, w, self_weight);
+    if (rc) return rc;
+    uint32_t *a = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    uint32_t *b = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    if (!a || !b) { free(a); free(b); return -3; }
+    for (uint32_t v = 0; v < n; ++v) a[v] = init_labels ? init_labels[v] : v;
+    for (uint32_t t = 0; t < rounds; ++t) {
+        int64_t ch = orc_rak_round(n, rp, col, w, self_weight, a, b, masks + (size_t)t * n);
+        if (ch < 0) { free(a); free(b); return (int)ch; }
+        uint32_t *s = a; a = b; b = s;
+        if (changed_per_iter) changed_per_iter[t] = (uint64_t)ch;
+    }
+    memcpy(labels_out, a, (size_t)n * sizeof(uint32_t));
+    free(a);
+    free(b);
+    return 0;
+}
+
+/* Weighted Newman-Girvan modularity of `labels` on the CSR as stored.
+ * Outputs the exact integer sums too: two_m = sum of arc weights,
+ * sigma_in = weight of same-label arcs, sum_k2 = sum_c K_c^2 as two 64-bit
+ * halves (lo, hi).  Q = 0 when two_m = 0.  Returns 0 or -1. */
+int orc_modularity(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                   const uint32_t *labels, double *q_out, uint64_t *two_m_out,
+                   uint64_t *sigma_in_out, uint64_t *sum_k2_out) {
+    if (!q_out || !labels) return -1;
+    int rc = check_csr(n, rp, col, w, 0);
+    if (rc) return rc;
+    for (uint32_t v = 0; v < n; ++v)
+        if (labels[v] >= n) return -1;
+    uint64_t *K = (uint64_t *)calloc((size_t)(n ? n : 1), sizeof(uint64_t));
+    if (!K) return -3;
+    uint64_t two_m = 0, sigma_in = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+        uint64_t k_v = 0;
+        for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) {
+            uint64_t we = w ? w[e] : 1u;
+            k_v += we;
+            if (labels[col[e]] == labels[v]) sigma_in += we;
+        }
+        two_m += k_v;
+        K[labels[v]] += k_v;
+    }
+    unsigned __int128 sk2 = 0;
+    for (uint32_t c = 0; c < n; ++c) sk2 += (unsigned __int128)K[c] * K[c];
+    free(K);
+    double q = 0.0;
+    if (two_m > 0) {
+        double W = (double)two_m;
+        q = (double)sigma_in / W - (double)sk2 / (W * W);
+    }
+    *q_out = q;
+    if (two_m_out) *two_m_out = two_m;
+    if (sigma_in_out) *sigma_in_out = sigma_in;
+    if (sum_k2_out) {
+        sum_k2_out[0] = (uint64_t)sk2;
+        sum_k2_out[1] = (uint64_t)(sk2 >> 64);
+    }
+    return 0;
+}
