@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark: plain RAK label propagation (arXiv 2301.09125, Section 3.2) on
+one MI355X through the library's C ABI.
+
+A step is one whole hot-path pass over the resident graph: lpa_run from the
+unique initial labels (degree binning, init, synchronous vote rounds with the
+device changed-count until changed <= floor(0.05 n) or 20 rounds) followed by
+lpa_modularity of the result.  The graph is generated on the host (seeded,
+synthetic) and copied to HBM before the timed region.
+
+value = arcs voted per second over the timed steps (GE/s; an undirected edge
+is two arcs, as in the paper's Table 1).  The JSON line also carries the
+roofline of the dominant kernel (HIP events around each launch, algorithmic
+bytes per launch) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+METRIC = "LPA edges/s (GE/s) + HBM GB/s at tol 0.05; modularity Δ vs plain RAK"
+
+WORKLOADS = {
+    # name: (description, generator)
+    "rmat22": ("R-MAT scale 22, edge factor 16, (a,b,c)=(0.57,0.19,0.19), permuted, symmetrised, "
+               "deduplicated, unit weights, seed 22",
+               lambda gg: gg.rmat(22, 16, 0.57, 0.19, 0.19, seed=22)),
+    "rmat24": ("R-MAT scale 24, edge factor 16, same (a,b,c), unit weights, seed 24",
+               lambda gg: gg.rmat(24, 16, 0.57, 0.19, 0.19, seed=24)),
+    "road4096": ("4096x4096 lattice, 30% edges deleted, 1% diagonal shortcuts, weights uniform in [1,8], "
+                 "seed 4096", lambda gg: gg.road(4096, 4096, 0.3, 0.01, 1, 8, seed=4096)),
+    "sbm10k": ("planted partition, 10000 vertices, 100 blocks, p_in 0.1, p_out 0.001, seed 1",
+               lambda gg: gg.sbm(10000, 100, 0.1, 0.001, seed=1)),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(g, rounds: int):
+    """The oracle as it stands (sequential C, one core) on a bounded sample:
+    its first `rounds` rounds on the same graph."""
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.rak(g, tol=0.0, max_iter=rounds, self_weight=1)
+    dt = time.perf_counter() - t0
+    arcs = g.m * r.iterations
+    return {"value": arcs / dt / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {r.iterations} rounds of the sequential oracle on the same graph "
+                      f"({arcs} arcs voted in {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--tol", type=float, default=0.05)
+    ap.add_argument("--max-iter", type=int, default=20)
+    ap.add_argument("--cpu-rounds", type=int, default=3, help="oracle rounds for cpu_baseline (0 = skip)")
+    ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import graphgen as gg
+    import paper_2301_09125_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    desc, gen = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    g = gen(gg)
+    log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
+    dg = P.DeviceGraph.from_csr(g, "cuda")
+    torch.cuda.synchronize()
+    ctx = P.Context(0, profile=0 if args.no_profile else 1)
+    labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    def step():
+        _, st = ctx.run(dg, tol=args.tol, max_iter=args.max_iter, labels_out=labels)
+        q, _ = ctx.modularity(dg, labels)
+        return st, q
+
+    for i in range(args.warmup):
+        st, q = step()
+        log(f"[bench] warmup {i}: {st.iterations} rounds, changed {st.changed}, Q={q:.6f}, "
+            f"{st.ms_total:.2f} ms")
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    arcs = 0
+    bytes_alg = 0
+    wb = 12 if g.w is not None else 8
+    t_start = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        st, q = step()
+        arcs += st.arcs_processed
+        stats.append((st, q))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st0, q0 = stats[0]
+    for st, q in stats:
+        if st.changed != st0.changed or q != q0:
+            raise SystemExit("non-deterministic result across steps")
+    deg_nonzero = int(np.count_nonzero(np.diff(g.row_ptr)))
+    bytes_alg = (wb * g.m + 16 * deg_nonzero) * st0.iterations * args.steps
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = arcs / elapsed / 1e9
+    log(f"[bench] {args.steps} steps in {elapsed:.3f}s: {ms_per_step:.3f} ms/step, {value:.2f} GE/s, "
+        f"rounds {st0.iterations}, Q {q0:.6f}")
+
+    roofline = None
+    prof = [] if args.no_profile else ctx.profile()
+    votes = [p for p in prof if p["launches"] and p["bytes"]]
+    if votes:
+        dom = max(votes, key=lambda p: p["ms"])
+        achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None,
+                    "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
+                    "bytes_per_launch": dom["bytes"] // dom["launches"]}
+        for p in prof:
+            if p["launches"]:
+                gbs = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
+                log(f"[bench]   {p['name']:12s} launches {p['launches']:5d}  avg {p['ms'] / p['launches']:.4f} ms"
+                    f"  {gbs:8.1f} GB/s alg")
+    round_ms = float(np.median([st0.ms_rounds / max(st0.iterations, 1)]))
+    cpu = None
+    if args.cpu_rounds > 0:
+        log(f"[bench] cpu baseline: {args.cpu_rounds} oracle rounds ...")
+        cpu = cpu_baseline(g, args.cpu_rounds)
+        log(f"[bench] cpu baseline {cpu['value']:.4f} GE/s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GE/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n": g.n, "m_arcs": g.m, "tol": args.tol,
+                   "max_iter": args.max_iter, "self_weight": 1, "tie_break": "lowest label",
+                   "rounds": st0.iterations, "changed": st0.changed, "modularity": q0,
+                   "hbm_gbs_effective": round(bytes_alg / elapsed / 1e9, 1),
+                   "round_ms_device": round(round_ms, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

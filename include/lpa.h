@@ -1,0 +1,155 @@
+/*
+ * lpa.h -- C ABI of the MI355X (gfx950) RAK label-propagation library.
+ *
+ * Method: Sahu, "Selecting a suitable Parallel Label-propagation based
+ * algorithm for Disjoint Community Detection", arXiv 2301.09125.
+ *   - RAK / LPA, weighted (Section 3.2): every vertex starts with a unique
+ *     label and, each iteration, adopts the label with the largest total
+ *     weight among its neighbours; stop once at most a `tolerance` fraction
+ *     of the vertices changed label (Section 3.2, restated in Section 4).
+ *   - Modularity (Section 1) as the quality measure.
+ *
+ * Semantics fixed by this library where the paper leaves them open:
+ *   - rounds are synchronous (round t reads only round t-1's labels), so the
+ *     result is a deterministic function of the inputs;
+ *   - the strict tie-break ("the first" tied label) is the lowest label value;
+ *   - the paper's per-vertex self-loop (Section 3.1.2) is `self_weight`, a
+ *     weight added to the vertex's own current label (default 1; 0 = vote of
+ *     the open neighbourhood).  The CSR itself must not need self-loops;
+ *   - a vertex with nothing to vote on keeps its label;
+ *   - the run stops after round t when changed_t <= floor(tol * n), n
+ *     counting every vertex; `max_iter` caps the rounds.  Hitting the cap is
+ *     not an error (`converged` = 0).
+ *
+ * Conventions for every entry point:
+ *   - Graphs are CSR in DEVICE memory, owned by the caller and only read:
+ *     row_ptr u64[n+1] (row_ptr[0] = 0, non-decreasing, row_ptr[n] = m),
+ *     col u32[m] (values < n), w u32[m] or NULL for unit weights.  The graph
+ *     must be symmetric (every arc stored in both directions, equal weights);
+ *     symmetry is the caller's contract and is not checked.
+ *   - Label buffers are DEVICE memory of n u32, owned by the caller.
+ *   - Work is enqueued on the context's HIP stream; every call returns only
+ *     once its results are final (it synchronises that stream).
+ *   - Errors are negative lpa_status codes; nothing aborts or throws.  After
+ *     an error the contents of output buffers are unspecified.
+ *   - A context is not thread-safe: use one per host thread / stream.
+ */
+#ifndef LPA_H
+#define LPA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LPA_OK = 0,
+    LPA_EINVAL = -1,       /* bad argument or malformed CSR / labels */
+    LPA_EOVERFLOW = -2,    /* a vertex's weighted degree + self_weight >= 2^32 */
+    LPA_ENOMEM = -3,       /* device or host allocation failed */
+    LPA_EDEVICE = -4,      /* a HIP runtime call failed */
+    LPA_EUNSUPPORTED = -5  /* option or size this build does not handle */
+} lpa_status;
+
+typedef struct lpa_ctx lpa_ctx;
+
+/* Graph in device memory (see conventions above). */
+typedef struct {
+    uint32_t n;                /* vertices, n <= 2^32 - 2 */
+    uint64_t m;                /* arcs (each undirected edge counts twice) */
+    const uint64_t *row_ptr;   /* device, n + 1 */
+    const uint32_t *col;       /* device, m; may be NULL only when m == 0 */
+    const uint32_t *w;         /* device, m, or NULL = every weight is 1 */
+} lpa_csr;
+
+/* Degree bins: a vertex of degree d is voted by
+ *   one lane                                   if 1 <= d <= thread_max,
+ *   a 16-lane group with an LDS hashtable      if d <= group_max,
+ *   one 64-lane wavefront with an LDS table    if d <= wave_max,
+ *   256-thread blocks over chunks of `chunk` arcs (LDS table per chunk;
+ *   rows longer than one chunk merge through global hashtable slabs) else.
+ * Any valid thresholds give the same labels; they only change speed.
+ * 0 selects the default. */
+typedef struct {
+    uint32_t self_weight;  /* weight of the vertex's own label (default 1) */
+    uint32_t thread_max;   /* <= 8    (default 8)    */
+    uint32_t group_max;    /* <= 32   (default 32)   */
+    uint32_t wave_max;     /* <= 256  (default 256)  */
+    uint32_t chunk;        /* 256..2048, power of two (default 2048) */
+    uint32_t profile;      /* nonzero: time every kernel launch with HIP events */
+} lpa_options;
+
+/* Run statistics.  The arrays are optional and owned by the caller; when
+ * given they receive min(iterations, cap) entries. */
+typedef struct {
+    uint32_t iterations;        /* rounds executed */
+    int32_t converged;          /* 1 if changed_last <= floor(tol * n) */
+    uint64_t changed_last;      /* vertices changed in the last round */
+    uint64_t arcs_processed;    /* sum over rounds of the arcs voted */
+    double ms_total;            /* host wall time of the call */
+    double ms_rounds;           /* device time of the rounds (HIP events) */
+    uint64_t *changed_per_iter; /* host, cap entries, or NULL */
+    float *ms_per_iter;         /* host, cap entries, or NULL */
+    uint32_t cap;
+} lpa_stats;
+
+/* Per-kernel device time collected when options.profile != 0. */
+typedef struct {
+    char name[32];
+    uint64_t launches;
+    double ms;          /* summed device time (HIP events around the launch) */
+    uint64_t bytes;     /* summed algorithmic bytes of the launches */
+    uint64_t arcs;      /* summed arcs the launches voted */
+} lpa_kernel_prof;
+
+/* Fill *opt with the defaults listed above. */
+void lpa_default_options(lpa_options *opt);
+
+/* Create a context on HIP device `device` that enqueues on `stream`
+ * (a hipStream_t; NULL = the device's null stream).  opt may be NULL for the
+ * defaults.  Invalid option values give LPA_EINVAL. */
+lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *opt);
+
+/* RAK from the unique initial labels L0(v) = v (Section 3.2).
+ * labels_out: device u32[n], receives the labels after the last round.
+ * tol in [0, 1]; max_iter = 0 returns the initial labels.
+ * Errors: LPA_EINVAL (null pointer, tol outside [0,1] or NaN, n too large,
+ * malformed row_ptr, col value >= n), LPA_EOVERFLOW, LPA_ENOMEM,
+ * LPA_EDEVICE. */
+lpa_status lpa_run(lpa_ctx *ctx, const lpa_csr *g, uint32_t *labels_out, double tol,
+                   uint32_t max_iter, lpa_stats *stats);
+
+/* Same as lpa_run but starts from the labels already in labels_inout
+ * (device u32[n], every value < n), e.g. to resume an interrupted run.
+ * Running k rounds and resuming for the rest equals one uninterrupted run. */
+lpa_status lpa_run_resume(lpa_ctx *ctx, const lpa_csr *g, uint32_t *labels_inout, double tol,
+                          uint32_t max_iter, lpa_stats *stats);
+
+/* Weighted Newman-Girvan modularity (Section 1) of `labels` (device u32[n],
+ * values < n) on the CSR as stored:
+ *   Q = Sigma_in / 2m - sum_c K_c^2 / (2m)^2,
+ * 2m = sum of arc weights, Sigma_in = weight of arcs whose ends share a
+ * label, K_c = summed weighted degree of community c; Q = 0 when 2m = 0.
+ * The sums are exact integers; only that last expression is FP64.
+ * q_out: host double.  terms: host u64[4] or NULL, receives
+ * {2m, Sigma_in, low 64 bits of sum K_c^2, high 64 bits}. */
+lpa_status lpa_modularity(lpa_ctx *ctx, const lpa_csr *g, const uint32_t *labels,
+                          double *q_out, uint64_t *terms);
+
+/* Copy up to `cap` per-kernel profile records into out (host); *count gets
+ * the number of records available.  lpa_profile_reset clears them. */
+lpa_status lpa_profile_get(lpa_ctx *ctx, lpa_kernel_prof *out, uint32_t cap, uint32_t *count);
+lpa_status lpa_profile_reset(lpa_ctx *ctx);
+
+/* Release every device and host resource of the context (NULL is a no-op). */
+void lpa_destroy(lpa_ctx *ctx);
+
+/* Static description of a status code. */
+const char *lpa_strerror(lpa_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPA_H */

@@ -1,0 +1,259 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bar: bit-exact labels, identical per-round changed counts, iteration counts
+and convergence flags; modularity with identical integer terms (Q within
+1e-9, expected equal).  RAK of arXiv 2301.09125 Section 3.2, modularity of
+Section 1.
+"""
+import itertools
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lpa(torch_mod):
+    import paper_2301_09125_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(lpa):
+    c = lpa.Context(0)
+    yield c
+    c.close()
+
+
+def dev(lpa, g, weights=True):
+    return lpa.DeviceGraph.from_csr(g, "cuda", weights=weights)
+
+
+def gpu_run(lpa, ctx, g, tol, max_iter, sw, **opts):
+    dg = dev(lpa, g)
+    c = ctx if (sw == 1 and not opts) else lpa.Context(0, self_weight=sw, **opts)
+    lab, st = c.run(dg, tol=tol, max_iter=max_iter)
+    return lpa.labels_to_numpy(lab), st
+
+
+def assert_same(orc, lpa, ctx, g, tol=0.05, max_iter=20, sw=1, **opts):
+    ref = orc.rak(g, tol=tol, max_iter=max_iter, self_weight=sw)
+    lab, st = gpu_run(lpa, ctx, g, tol, max_iter, sw, **opts)
+    assert st.iterations == ref.iterations, (g.name, st.changed, ref.changed)
+    assert st.changed == ref.changed, (g.name, st.changed, ref.changed)
+    assert st.converged == ref.converged
+    mism = np.flatnonzero(lab != ref.labels)
+    assert mism.size == 0, f"{g.name}: {mism.size} labels differ, first {mism[:8]}"
+    return ref, lab, st
+
+
+# ------------------------------------------------------------ small corpus --
+
+def test_golden_fixture_on_gpu(gg, orc, lpa, ctx):
+    import json
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "weighted6.json")))
+    n = fx["n"]
+    g = gg.from_edges(n, [(a, b) for a, b, _ in fx["edges"]])
+    wmap = {}
+    for a, b, w in fx["edges"]:
+        wmap[(a, b)] = wmap[(b, a)] = w
+    src = np.repeat(np.arange(n), np.diff(g.row_ptr).astype(np.int64))
+    g.w = np.array([wmap[(int(s), int(d))] for s, d in zip(src, g.col)], dtype=np.uint32)
+    for run in fx["runs"]:
+        lab, st = gpu_run(lpa, ctx, g, run["tol"], run["max_iter"], fx["self_weight"])
+        assert lab.tolist() == run["labels"]
+        assert st.changed == run["changed"] and st.converged == run["converged"]
+    m = fx["modularity"]
+    q, terms = ctx.modularity(dev(lpa, g), _t(np.array(m["labels"], np.uint32)))
+    assert (terms["two_m"], terms["sigma_in"], terms["sum_k2"]) == (m["two_m"], m["sigma_in"], m["sum_k2"])
+    assert abs(q - m["q_num"] / m["q_den"]) < 1e-12
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def test_small_graph_corpus(gg, orc, lpa, ctx):
+    rng = np.random.default_rng(100)
+    graphs = []
+    for n in (1, 2, 3, 5, 9):
+        graphs.append(gg.from_edges(n, itertools.combinations(range(n), 2)))
+    graphs.append(gg.from_edges(17, [(i, i + 1) for i in range(16)]))
+    graphs.append(gg.from_edges(10, [(0, i) for i in range(1, 10)]))
+    graphs.append(gg.from_edges(6, []))
+    for t in range(40):
+        n = int(rng.integers(2, 40))
+        p = rng.uniform(0.05, 0.8)
+        edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+        lo = int(rng.integers(0, 2))
+        graphs.append(gg.from_edges(n, edges, weights=(t, lo, int(rng.integers(lo, 9)))))
+    say("corpus", len(graphs))
+    for g in graphs:
+        for sw in (0, 1, 3):
+            for tol in (0.0, 0.05):
+                assert_same(orc, lpa, ctx, g, tol=tol, max_iter=12, sw=sw)
+
+
+# --------------------------------------------------- every bin, ragged sizes --
+
+@pytest.mark.parametrize("case", ["sbm_cfg", "rmat14", "rmat16_w", "road64_w", "road_ragged"])
+def test_mid_graphs_all_bins(gg, orc, lpa, ctx, case):
+    if case == "sbm_cfg":
+        g = gg.sbm(10000, 100, 0.1, 0.001, 1)
+    elif case == "rmat14":
+        g = gg.rmat(14, seed=14)
+    elif case == "rmat16_w":
+        g = gg.with_weights(gg.rmat(16, seed=16), 7, 1, 8)
+    elif case == "road64_w":
+        g = gg.road(64, 64, seed=64)
+    else:
+        g = gg.road(37, 211, seed=5)
+    say(case, g.n, g.m)
+    for sw in (0, 1):
+        assert_same(orc, lpa, ctx, g, tol=0.05, max_iter=20, sw=sw)
+    assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=30, sw=1)
+
+
+def test_long_rows_split_into_chunks(gg, orc, lpa, ctx):
+    # chunk 256 makes rows above 256 arcs go through the global slab path
+    g = gg.rmat(15, seed=15)
+    deg = np.diff(g.row_ptr)
+    assert (deg > 256).sum() > 20 and deg.max() > 2048
+    for sw in (0, 1):
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=15, sw=sw, chunk=256)
+        assert_same(orc, lpa, ctx, g, tol=0.05, max_iter=15, sw=sw, chunk=2048)
+
+
+def test_random_bin_thresholds_give_same_labels(gg, orc, lpa, ctx):
+    g = gg.with_weights(gg.rmat(13, seed=21), 3, 1, 5)
+    ref = orc.rak(g, tol=0.0, max_iter=12, self_weight=1)
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        t = int(rng.integers(1, 9))
+        gm = int(rng.integers(t, 33))
+        wm = int(rng.integers(gm, 257))
+        ch = int(2 ** rng.integers(8, 12))
+        lab, st = gpu_run(lpa, ctx, g, 0.0, 12, 1, thread_max=t, group_max=gm, wave_max=wm, chunk=ch)
+        assert np.array_equal(lab, ref.labels), (t, gm, wm, ch)
+        assert st.changed == ref.changed
+
+
+def test_repeated_runs_bit_identical(gg, lpa, ctx):
+    g = dev(lpa, gg.rmat(15, seed=3))
+    first, st0 = ctx.run(g, tol=0.0, max_iter=10)
+    first = lpa.labels_to_numpy(first)
+    for _ in range(3):
+        lab, st = ctx.run(g, tol=0.0, max_iter=10)
+        assert np.array_equal(lpa.labels_to_numpy(lab), first)
+        assert st.changed == st0.changed
+
+
+def test_resume_equals_uninterrupted(gg, orc, lpa, ctx):
+    g = gg.rmat(13, seed=9)
+    dg = dev(lpa, g)
+    full, stf = ctx.run(dg, tol=0.0, max_iter=8)
+    part, st1 = ctx.run(dg, tol=0.0, max_iter=3)
+    rest, st2 = ctx.run_resume(dg, part, tol=0.0, max_iter=5)
+    assert np.array_equal(lpa.labels_to_numpy(rest), lpa.labels_to_numpy(full))
+    assert st1.changed + st2.changed == stf.changed
+    ref = orc.rak(g, tol=0.0, max_iter=5, init_labels=lpa.labels_to_numpy(part))
+    assert np.array_equal(lpa.labels_to_numpy(rest), ref.labels)
+
+
+# ------------------------------------------------------------- modularity --
+
+@pytest.mark.parametrize("case", ["sbm", "rmat15", "road_w", "singletons", "one"])
+def test_modularity_matches_oracle(gg, orc, lpa, ctx, case):
+    if case in ("sbm", "singletons", "one"):
+        g = gg.sbm(3000, 30, 0.1, 0.002, 2)
+    elif case == "rmat15":
+        g = gg.rmat(15, seed=4)
+    else:
+        g = gg.road(100, 80, seed=8)
+    dg = dev(lpa, g)
+    if case == "singletons":
+        lab = np.arange(g.n, dtype=np.uint32)
+    elif case == "one":
+        lab = np.zeros(g.n, dtype=np.uint32)
+    else:
+        lab = orc.rak(g).labels
+    ref = orc.modularity(g, lab)
+    q, terms = ctx.modularity(dg, _t(lab))
+    assert (terms["two_m"], terms["sigma_in"], terms["sum_k2"]) == (ref.two_m, ref.sigma_in, ref.sum_k2)
+    assert abs(q - ref.q) <= 1e-9
+    assert q == ref.q  # same exact integers, same FP64 expression
+
+
+# ---------------------------------------------------------- edge + errors --
+
+def test_degenerate_inputs(gg, lpa, ctx):
+    import torch
+    g0 = dev(lpa, gg.from_edges(0, []))
+    lab, st = ctx.run(g0, tol=0.05, max_iter=5)
+    assert lab.numel() == 0 and st.iterations == 0
+    iso = dev(lpa, gg.from_edges(7, []))
+    lab, st = ctx.run(iso, tol=0.0, max_iter=5)
+    assert lpa.labels_to_numpy(lab).tolist() == list(range(7)) and st.changed == [0]
+    q, terms = ctx.modularity(iso, lab)
+    assert q == 0.0 and terms["two_m"] == 0
+    g = dev(lpa, gg.sbm(500, 5, 0.2, 0.01, 3))
+    lab, st = ctx.run(g, tol=0.05, max_iter=0)
+    assert st.iterations == 0 and lpa.labels_to_numpy(lab).tolist() == list(range(500))
+    assert torch.cuda.is_available()
+
+
+def test_error_codes(gg, lpa, ctx):
+    import torch
+
+    def mk(n, rp, col, w=None):
+        return lpa.DeviceGraph(n, torch.tensor(rp, dtype=torch.int64).cuda(),
+                               torch.tensor(col, dtype=torch.int32).cuda(),
+                               None if w is None else torch.tensor(w, dtype=torch.int64).to(torch.int32).cuda())
+
+    with pytest.raises(lpa.LpaError) as e:
+        ctx.run(mk(3, [0, 1, 2, 2], [1, 7]))  # col out of range
+    assert e.value.code == -1
+    with pytest.raises(lpa.LpaError) as e:
+        ctx.run(mk(3, [0, 2, 1, 2], [1, 0]))  # row_ptr not monotone
+    assert e.value.code == -1
+    with pytest.raises(lpa.LpaError) as e:
+        ctx.run(mk(2, [0, 1, 3], [1, 0]))  # row_ptr[n] != m
+    assert e.value.code == -1
+    heavy = mk(2, [0, 1, 2], [1, 0], [0xFFFFFFFF - 0x80000000, 0xFFFFFFFF - 0x80000000])
+    with pytest.raises(lpa.LpaError) as e:
+        lpa.Context(0, self_weight=0x80000001).run(heavy)
+    assert e.value.code == -2
+    ok = mk(3, [0, 1, 2, 2], [1, 0])
+    with pytest.raises(lpa.LpaError):
+        ctx.run(ok, tol=1.5)
+    with pytest.raises(lpa.LpaError):
+        ctx.run(ok, tol=float("nan"))
+    bad = torch.tensor([0, 5, 1], dtype=torch.int32).cuda()
+    with pytest.raises(lpa.LpaError):
+        ctx.modularity(ok, bad)
+    with pytest.raises(lpa.LpaError):
+        ctx.run_resume(ok, bad.clone(), tol=0.0, max_iter=2)
+    with pytest.raises(lpa.LpaError):
+        lpa.Context(0, thread_max=9)
+    with pytest.raises(lpa.LpaError):
+        lpa.Context(0, chunk=3000)
+    # the context still works after errors
+    lab, st = ctx.run(ok, tol=0.0, max_iter=2)
+    assert st.iterations >= 1
