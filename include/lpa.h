@@ -64,20 +64,30 @@ typedef struct {
 } lpa_csr;
 
 /* Degree bins: a vertex of degree d is voted by
- *   one lane                                   if 1 <= d <= thread_max,
- *   a 16-lane group with an LDS hashtable      if d <= group_max,
- *   one 64-lane wavefront with an LDS table    if d <= wave_max,
- *   256-thread blocks over chunks of `chunk` arcs (LDS table per chunk;
- *   rows longer than one chunk merge through global hashtable slabs) else.
+ *   one lane                                        if 1 <= d <= thread_max,
+ *   a 16-lane group with a 64-slot LDS hashtable    if d <= group_max,
+ *   one wavefront with a 256-slot LDS hashtable     if d <= wave_max,
+ *   one wavefront with a 1024-slot LDS hashtable    if d <= wide_max,
+ *   one wavefront per 512-arc segment, the segments' tallies merged
+ *   exactly per row                                 otherwise: each segment
+ *   reports its 4 heaviest labels and a bound on the rest; a row whose
+ *   leader provably wins is decided from the reports, any other row merges
+ *   its segments' full tallies in a global hashtable slab.
  * Any valid thresholds give the same labels; they only change speed.
  * 0 selects the default. */
 typedef struct {
     uint32_t self_weight;  /* weight of the vertex's own label (default 1) */
-    uint32_t thread_max;   /* <= 8    (default 8)    */
-    uint32_t group_max;    /* <= 32   (default 32)   */
-    uint32_t wave_max;     /* <= 256  (default 256)  */
-    uint32_t chunk;        /* 256..2048, power of two (default 2048) */
+    uint32_t thread_max;   /* 1..8                    (default 8)   */
+    uint32_t group_max;    /* thread_max..32          (default 32)  */
+    uint32_t wave_max;     /* group_max..128          (default 128) */
+    uint32_t wide_max;     /* wave_max..512           (default 512) */
+    uint32_t merge_max;    /* 1..512 (default 512): rows of more segments than
+                              this merge their segments' full tallies in a
+                              global slab instead of top-K reports */
     uint32_t profile;      /* nonzero: time every kernel launch with HIP events */
+    uint32_t modularity;   /* nonzero: lpa_run also reports the modularity of
+                              its result in lpa_stats (same definition as
+                              lpa_modularity) */
 } lpa_options;
 
 /* Run statistics.  The arrays are optional and owned by the caller; when
@@ -89,6 +99,8 @@ typedef struct {
     uint64_t arcs_processed;    /* sum over rounds of the arcs voted */
     double ms_total;            /* host wall time of the call */
     double ms_rounds;           /* device time of the rounds (HIP events) */
+    double modularity;          /* with options.modularity: Q of the result */
+    uint64_t mod_terms[4];      /* ... and its terms, as lpa_modularity's */
     uint64_t *changed_per_iter; /* host, cap entries, or NULL */
     float *ms_per_iter;         /* host, cap entries, or NULL */
     uint32_t cap;
@@ -114,6 +126,9 @@ lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *
 /* RAK from the unique initial labels L0(v) = v (Section 3.2).
  * labels_out: device u32[n], receives the labels after the last round.
  * tol in [0, 1]; max_iter = 0 returns the initial labels.
+ * The run works on a relabelled device copy of the CSR (vertices grouped by
+ * degree bin, high-degree vertices first) that the context allocates: about
+ * 4 bytes per arc (8 with weights) plus 25 bytes per vertex.
  * Errors: LPA_EINVAL (null pointer, tol outside [0,1] or NaN, n too large,
  * malformed row_ptr, col value >= n), LPA_EOVERFLOW, LPA_ENOMEM,
  * LPA_EDEVICE. */

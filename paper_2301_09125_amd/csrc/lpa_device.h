@@ -1,0 +1,117 @@
+// lpa_device.h -- device helpers shared by the kernel sources of the
+// label-propagation library (wavefront reductions, LDS hashtables).
+#pragma once
+
+#include "lpa_internal.h"
+
+namespace lpa {
+
+#define EMPTY_SLOT 0xFFFFFFFF00000000ull
+
+typedef unsigned long long u64;
+
+// lowbias32 integer hash (C. Wellons, "Prospecting for Hash Functions", 2018)
+__device__ __forceinline__ uint32_t hmix(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Make this wavefront's LDS writes visible to its other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a > b ? a : b; }
+
+// slot (label << 32 | tally)  ->  vote key (tally << 32 | ~label)
+__device__ __forceinline__ u64 slot_key(u64 x) { return (x << 32) | (uint32_t)~(uint32_t)(x >> 32); }
+
+__device__ __forceinline__ u64 vote_key(uint32_t lab, u64 tally) { return (tally << 32) | (uint32_t)~lab; }
+
+__device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
+    return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+__device__ __forceinline__ u64 wave_max64(u64 x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = umax64(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+// Insert (lab, wv) into an LDS table of mask+1 slots with linear probing.
+// The caller guarantees more slots than distinct labels.
+__device__ __forceinline__ void lds_insert(u64 *T, uint32_t mask, uint32_t lab, uint32_t wv) {
+    uint32_t h = hmix(lab) & mask;
+    const u64 desired = ((u64)lab << 32) | wv;
+    for (;;) {
+        u64 prev = atomicCAS(&T[h], EMPTY_SLOT, desired);
+        if (prev == EMPTY_SLOT) return;
+        if ((uint32_t)(prev >> 32) == lab) {
+            atomicAdd(&T[h], (u64)wv);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Add this thread's count c into a round's counter words: one atomic per
+// block, blocks spread over kCountSlots cache lines.  Every thread of a
+// 256-thread block calls this once.
+__device__ __forceinline__ void block_count(u64 c, u64 *slots) {
+    __shared__ u64 part[4];
+    c = wave_sum(c);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const u64 s = part[0] + part[1] + part[2] + part[3];
+        if (s) atomicAdd(&slots[(blockIdx.x % kCountSlots) * kCountStride], s);
+    }
+}
+
+// Block-wide reductions for 256 threads (4 wavefronts).
+struct BlockRed {
+    u64 mx[4];
+    u64 sum[4];
+    u64 sum2[4];
+    uint32_t orv[4];
+};
+
+__device__ __forceinline__ void block_reduce(BlockRed &R, u64 &mx, u64 &sum, u64 &sum2, uint32_t &orv) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    mx = wave_max64(mx);
+    sum = wave_sum(sum);
+    sum2 = wave_sum(sum2);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) orv |= __shfl_xor(orv, off, 64);
+    if (lane == 0) {
+        R.mx[wave] = mx;
+        R.sum[wave] = sum;
+        R.sum2[wave] = sum2;
+        R.orv[wave] = orv;
+    }
+    __syncthreads();
+    mx = umax64(umax64(R.mx[0], R.mx[1]), umax64(R.mx[2], R.mx[3]));
+    sum = R.sum[0] + R.sum[1] + R.sum[2] + R.sum[3];
+    sum2 = R.sum2[0] + R.sum2[1] + R.sum2[2] + R.sum2[3];
+    orv = R.orv[0] | R.orv[1] | R.orv[2] | R.orv[3];
+}
+
+static inline unsigned grid_for(uint64_t count, unsigned per_block, unsigned cap) {
+    uint64_t g = (count + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return (unsigned)(g < cap ? g : cap);
+}
+
+}  // namespace lpa

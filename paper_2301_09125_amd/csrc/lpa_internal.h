@@ -1,5 +1,15 @@
 // lpa_internal.h -- private declarations shared by the runtime (lpa_runtime.hip)
-// and the kernels (lpa_kernels.hip) of the label-propagation library.
+// and the kernel sources of the label-propagation library.
+//
+// Internal layout.  A run works on a relabelled copy of the caller's CSR:
+// the vertices are renumbered bin by bin -- long rows first, then wavefront
+// rows, 16-lane rows, one-lane rows and last the vertices without arcs, each
+// bin in increasing original id.  Every bin is a contiguous range of internal
+// ids, so
+// kernels walk ranges instead of index lists, and the labels of the
+// high-degree vertices, which most arcs point at, share a few hundred KB at
+// the front of the label array where the L2 cache keeps them.  Label VALUES
+// stay original vertex ids, so the lowest-label tie-break is unchanged.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,16 +25,39 @@ enum : uint32_t {
     ERR_LABEL = 8u,   // a label value >= n
 };
 
-// Degree bins (see lpa_options in lpa.h).
-enum { BIN_ZERO = 0, BIN_THREAD = 1, BIN_GROUP = 2, BIN_WAVE = 3, BIN_HUB = 4, NBINS = 5 };
+// Degree bins in internal layout order (see lpa_options in lpa.h).
+enum { BIN_HUB = 0, BIN_WIDE = 1, BIN_WAVE = 2, BIN_GROUP = 3, BIN_THREAD = 4, BIN_ZERO = 5, NBINS = 6 };
 
-constexpr int kThreadMaxCap = 8;    // register-array size of the one-lane vote
+constexpr int kThreadMaxCap = 8;     // register-array size of the one-lane vote
 constexpr int kGroupLanes = 16;
-constexpr int kGroupSlots = 64;     // LDS slots per 16-lane group (degree <= 32)
-constexpr int kWaveSlots = 512;     // LDS slots per wavefront (degree <= 256)
-constexpr int kBlockThreads = 256;
-constexpr int kChunkSlotsMax = 4096;  // LDS slots per hub block (chunk <= 2048)
-constexpr uint32_t kNoHub = 0xFFFFFFFFu;
+constexpr int kGroupSlots = 64;      // LDS slots per 16-lane group (degree <= 32)
+constexpr int kWaveArcsSmall = 128;  // wavefront rows with a small table
+constexpr int kWaveSlotsSmall = 256;
+constexpr int kWaveArcs = 512;       // arcs per wavefront work item
+constexpr int kWaveSlots = 1024;     // LDS slots per wavefront (<= 512 arcs)
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Long rows: each 512-arc segment reports its kTopK heaviest labels and a
+// bound on every label it did not report; rows of at most kMergeWaveSegs
+// segments are merged by one wavefront, rows of at most kMergeBlockSegs by
+// one block, longer rows always merge through the global slab.
+constexpr int kTopK = 4;
+constexpr int kMergeWaveSegs = 32;
+constexpr int kMergeBlockSegs = 512;
+constexpr int kMergeBlockSlots = 2 * kMergeBlockSegs * kTopK;
+
+// The changed count of one round is spread over kCountSlots u64 words
+// kCountStride words apart (one cache line each) so that blocks do not
+// serialise on a single address; the host adds them up.
+constexpr int kCountSlots = 32;
+constexpr int kCountStride = 16;
+constexpr int kCountWords = kCountSlots * kCountStride;
+
+// Per-row flags of the internal graph.
+enum : uint8_t { ROW_DISTINCT = 1 };  // the caller's row lists each neighbour once
+// Per-hub flags: HUB_OWN_SEEN and HUB_FALLBACK live for one round,
+// HUB_REPEATS and HUB_BIG for the run.
+enum : uint32_t { HUB_OWN_SEEN = 1u, HUB_REPEATS = 2u, HUB_FALLBACK = 4u, HUB_BIG = 8u };
 
 struct Graph {
     const uint64_t *rp;
@@ -34,43 +67,46 @@ struct Graph {
     uint64_t m;
 };
 
-// Arguments common to every vote kernel of one round.
+// Arguments common to every vote kernel of one round (internal graph).
 struct RoundArgs {
     Graph g;
     const uint32_t *L_old;
     uint32_t *L_new;
+    const uint8_t *rowflag;       // ROW_DISTINCT per internal row
     uint32_t sw;                  // self weight
     uint32_t check;               // nonzero: verify weighted degrees fit 32 bits
-    unsigned long long *changed;  // this round's changed counter
+    unsigned long long *changed;  // this round's kCountWords counter words
     uint32_t *err;                // error bits
 };
 
-// One block work item for high-degree rows: arcs [b0, b1) of vertex v.
-// hub == kNoHub: the row fits one chunk and the block finishes the vote;
-// otherwise hub indexes the multi-chunk state below.
+// A wavefront work item of a long row: internal row r (= hub index), arcs
+// [b0, b1) of the internal CSR, at most kWaveArcs of them.
 struct HubItem {
-    uint32_t v;
-    uint32_t hub;
+    uint32_t r;
+    uint32_t pad;
     uint64_t b0;
     uint64_t b1;
 };
 
-// State of the rows longer than one chunk (arrays of `count` entries).
+// State of the long rows (internal ids 0..H-1; arrays of H entries).
 struct HubState {
-    const uint32_t *vertex;       // vertex id
     const uint64_t *slab_off;     // offset of the row's slab (u64 slots)
     const uint32_t *slab_mask;    // slab size - 1 (power of two >= 2 * degree)
     const uint64_t *touched_off;  // offset of the row's touched-slot list (capacity = degree)
     unsigned long long *slab;     // global hashtable slots, EMPTY between rounds
-    uint32_t *touched;            // slot indices claimed this round
-    uint32_t *tcount;             // claimed slots this round (reset by hub_final)
+    uint32_t *touched;            // slot indices claimed this round (kNone = no claim)
+    uint32_t *tcount;             // touched-list entries this round (reset by hub_final)
     unsigned long long *best;     // max (weight << 32 | ~label) (reset by hub_final)
     unsigned long long *own_sum;  // weight of neighbours holding the row's own label
-    uint32_t *own_seen;           // some neighbour holds the row's own label
+    uint32_t *flags;              // HUB_* flags
     unsigned long long *rowsum;   // weighted degree (checked in round 1)
+    unsigned long long *cand;     // kTopK (label << 32 | tally) per segment, EMPTY if unused
+    uint32_t *thr;                // per segment: tally bound of its unreported labels
+    const uint32_t *item_lo;      // H + 1: first segment of each row
+    uint32_t *pending;            // nonzero: some row uses the slab this round
 };
 
-// Phase-2 item: touched-list positions [t0, t1) of multi-chunk hub `hub`.
+// Phase-2 item: touched-list positions [t0, t1) of hub `hub`.
 struct ReduceItem {
     uint32_t hub;
     uint32_t t0;
@@ -78,43 +114,76 @@ struct ReduceItem {
     uint32_t pad;
 };
 
+// Degree thresholds of the bins (see lpa_options).
+struct BinCfg {
+    uint32_t tmax, gmax, wmax, xmax;
+};
+
+// Ranges of internal ids per bin.
+struct Bins {
+    uint32_t lo[NBINS];
+    uint32_t cnt[NBINS];
+    uint64_t arcs[NBINS];
+};
+
 struct ModArgs {
-    Graph g;
-    const uint32_t *labels;
-    unsigned long long *K;         // n, summed weighted degree per community
-    unsigned long long *sums;      // [0] = 2m, [1] = Sigma_in
+    Graph g;                   // internal graph
+    const uint32_t *labels;    // internal labels (values are original ids < n_orig)
+    unsigned long long *K;     // n_orig, summed weighted degree per community
+    unsigned long long *sums;  // [0] = 2m, [1] = Sigma_in
     uint32_t *err;
 };
 
-// ---- launchers (defined in lpa_kernels.hip) ------------------------------
-hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t *b, uint32_t n, hipStream_t s);
+// ---- launchers: lpa_prep.hip ---------------------------------------------
+hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t count, hipStream_t s);
-hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t count, hipStream_t s);
 hipError_t launch_check_labels(const uint32_t *labels, uint32_t n, uint32_t *err, hipStream_t s);
+uint32_t bin_blocks(uint32_t n);
+hipError_t launch_bin_count(const Graph &g, const BinCfg &cfg, uint32_t *blk_counts, unsigned long long *blk_arcs,
+                            uint32_t nblk, uint32_t *err, hipStream_t s);
+hipError_t launch_bin_scan(uint32_t *blk_counts, unsigned long long *blk_arcs, uint32_t nblk, uint32_t *totals,
+                           unsigned long long *arc_totals, hipStream_t s);
+hipError_t launch_bin_scatter(const Graph &g, const BinCfg &cfg, const uint32_t *blk_offsets,
+                              const unsigned long long *blk_arc_offsets, uint32_t nblk, uint32_t *old_of,
+                              uint32_t *new_of, uint64_t *rp2, hipStream_t s);
+// Copy the caller's rows into the internal CSR (ids through new_of) and
+// flag rows that list each neighbour once.
+hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
+                               uint32_t *col2, uint32_t *w2, uint8_t *rowflag, uint32_t lo, uint32_t cnt,
+                               int per_wave, uint32_t *err, hipStream_t s);
+hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
+                              uint32_t *col2, uint32_t *w2, const HubItem *items, uint32_t count,
+                              uint32_t *hub_flags, uint32_t *err, hipStream_t s);
+hipError_t launch_init_labels(uint32_t *La, uint32_t *Lb, const uint32_t *old_of, const uint32_t *labels_in,
+                              uint32_t n, hipStream_t s);
+hipError_t launch_scatter_labels(uint32_t *labels_out, const uint32_t *old_of, const uint32_t *L, uint32_t n_int,
+                                 hipStream_t s);
 
-hipError_t launch_bin_count(const Graph &g, uint32_t tmax, uint32_t gmax, uint32_t wmax, uint32_t *blk_counts,
-                            unsigned long long *blk_arcs, uint32_t nblk, uint32_t *err, hipStream_t s);
-hipError_t launch_bin_scan(uint32_t *blk_counts, const unsigned long long *blk_arcs, uint32_t nblk,
-                           uint32_t *totals, unsigned long long *arc_totals, hipStream_t s);
-hipError_t launch_bin_scatter(const Graph &g, uint32_t tmax, uint32_t gmax, uint32_t wmax,
-                              const uint32_t *blk_offsets, uint32_t nblk, uint32_t *order, hipStream_t s);
-hipError_t launch_gather_rows(const uint64_t *rp, const uint32_t *verts, uint32_t count, uint64_t *out3,
+// ---- launchers: lpa_vote.hip ---------------------------------------------
+// first = 1: round 1 from the unique initial labels L0(v) = v.
+hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int grid_cap,
                               hipStream_t s);
-
-hipError_t launch_vote_thread(const RoundArgs &a, const uint32_t *list, uint32_t cnt, int grid_cap,
-                              hipStream_t s);
-hipError_t launch_vote_group(const RoundArgs &a, const uint32_t *list, uint32_t cnt, int grid_cap,
+hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int grid_cap,
                              hipStream_t s);
-hipError_t launch_vote_wave(const RoundArgs &a, const uint32_t *list, uint32_t cnt, int grid_cap,
+hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int grid_cap,
                             hipStream_t s);
-hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, uint32_t chunk,
-                           const HubState &hs, hipStream_t s);
+// Long rows, one wavefront per segment: the direct max (round 1), the top-K
+// report, or for HUB_BIG rows the slab merge; own-label tallies for all.
+hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
+                           int first, int grid_cap, hipStream_t s);
+// Merge the top-K reports of each listed row; undecided rows get HUB_FALLBACK.
+hipError_t launch_hub_merge(const RoundArgs &a, const HubState &hs, const uint32_t *rows, uint32_t count,
+                            int per_block, int first, hipStream_t s);
+// Slab merge of the segments of HUB_FALLBACK rows.
+hipError_t launch_hub_fallback(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
+                               int grid_cap, hipStream_t s);
 hipError_t launch_hub_reduce(const HubState &hs, const ReduceItem *items, uint32_t count, hipStream_t s);
-hipError_t launch_hub_final(const RoundArgs &a, const HubState &hs, uint32_t count, hipStream_t s);
+// Winner of the rows decided by best[] (direct, slab) and per-round reset.
+hipError_t launch_hub_final(const RoundArgs &a, const HubState &hs, uint32_t count, int first, hipStream_t s);
 
-hipError_t launch_mod_small(const ModArgs &a, const uint32_t *list, uint32_t cnt, hipStream_t s);
-hipError_t launch_mod_wave(const ModArgs &a, const uint32_t *list, uint32_t cnt, hipStream_t s);
+// ---- launchers: lpa_mod.hip ----------------------------------------------
+hipError_t launch_mod_rows(const ModArgs &a, uint32_t lo, uint32_t cnt, int per_wave, hipStream_t s);
 hipError_t launch_mod_hub(const ModArgs &a, const HubItem *items, uint32_t count, hipStream_t s);
 hipError_t launch_mod_sumsq(const unsigned long long *K, uint32_t n, unsigned long long *partials,
                             uint32_t nparts, hipStream_t s);

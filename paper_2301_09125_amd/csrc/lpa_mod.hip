@@ -1,0 +1,199 @@
+// lpa_mod.hip -- modularity (arXiv 2301.09125, Section 1) on the internal
+// graph:  Q = Sigma_in / 2m - sum_c K_c^2 / (2m)^2.
+//
+// Integer sums throughout: 2m and Sigma_in in u64, K_c (summed weighted
+// degree of community c, indexed by the label value) in u64, sum K_c^2 as
+// u128 block partials added on the host; only the final expression is FP64.
+// K_c contributions are first merged per block in an LDS table so that a
+// large community costs one global atomic per block, not one per vertex.
+
+#include "lpa_device.h"
+
+namespace lpa {
+
+constexpr uint32_t kModSlots = 1024;
+constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+
+struct ModTable {
+    uint32_t key[kModSlots];
+    u64 val[kModSlots];
+    BlockRed R;
+};
+
+__device__ __forceinline__ void mod_table_init(ModTable &M) {
+    for (uint32_t s = threadIdx.x; s < kModSlots; s += 256) {
+        M.key[s] = kEmpty32;
+        M.val[s] = 0;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void mod_table_add(ModTable &M, u64 *K, uint32_t lab, u64 kv) {
+    uint32_t h = hmix(lab) & (kModSlots - 1);
+    for (int p = 0; p < 16; ++p) {
+        const uint32_t prev = atomicCAS(&M.key[h], kEmpty32, lab);
+        if (prev == kEmpty32 || prev == lab) {
+            atomicAdd(&M.val[h], kv);
+            return;
+        }
+        h = (h + 1) & (kModSlots - 1);
+    }
+    atomicAdd(&K[lab], kv);  // table crowded: go straight to memory
+}
+
+// Per-wavefront peel of the first active lane's label, then the LDS table.
+__device__ __forceinline__ void add_community(ModTable &M, u64 *K, bool act, uint32_t lv, u64 kv) {
+    const u64 actmask = __ballot(act);
+    if (!actmask) return;
+    const int lead = __ffsll((long long)actmask) - 1;
+    const uint32_t ll = __shfl(lv, lead, 64);
+    const bool same = act && lv == ll;
+    const u64 part = wave_sum(same ? kv : 0ull);
+    if ((int)(threadIdx.x & 63) == lead && part) mod_table_add(M, K, ll, part);
+    if (act && !same && kv) mod_table_add(M, K, lv, kv);
+}
+
+__device__ __forceinline__ void mod_finish(const ModArgs &a, ModTable &M, u64 tw, u64 sin) {
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < kModSlots; s += 256)
+        if (M.key[s] != kEmpty32 && M.val[s]) atomicAdd(&a.K[M.key[s]], M.val[s]);
+    u64 z = 0;
+    uint32_t zo = 0;
+    block_reduce(M.R, z, tw, sin, zo);
+    if (threadIdx.x == 0) {
+        if (tw) atomicAdd(&a.sums[0], tw);
+        if (sin) atomicAdd(&a.sums[1], sin);
+    }
+}
+
+// Weighted degree and same-label weight of arcs k0 + j*STRIDE (j < A, < e).
+template <int A, int STRIDE>
+__device__ __forceinline__ void mod_arcs(const ModArgs &a, uint64_t k0, uint64_t e, uint32_t lv, u64 &kv,
+                                         u64 &sin) {
+    uint32_t u[A], wv[A];
+    uint32_t valid = 0;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = k0 + (uint64_t)j * STRIDE;
+        u[j] = 0;
+        wv[j] = 0;
+        if (k < e) {
+            valid |= 1u << j;
+            u[j] = a.g.col[k];
+            wv[j] = a.g.w ? a.g.w[k] : 1u;
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        bad |= u[j] >= a.g.n;
+        u[j] = u[j] >= a.g.n ? 0u : u[j];
+    }
+    if (bad) atomicOr(a.err, ERR_COL);
+#pragma unroll
+    for (int j = 0; j < A; ++j)
+        if (valid >> j & 1u) {
+            kv += wv[j];
+            if (a.labels[u[j]] == lv) sin += wv[j];
+        }
+}
+
+// One lane per row (rows of at most 32 arcs).
+__global__ __launch_bounds__(256) void mod_thread_k(ModArgs a, uint32_t lo, uint32_t cnt) {
+    __shared__ ModTable M;
+    mod_table_init(M);
+    u64 tw = 0, sin = 0;
+    for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < cnt; base += gridDim.x * 256) {
+        const uint32_t i = base + (threadIdx.x & 63);
+        const bool act = i < cnt;
+        u64 kv = 0;
+        uint32_t lv = 0;
+        if (act) {
+            const uint32_t v = lo + i;
+            lv = a.labels[v];
+            const uint64_t e = a.g.rp[v + 1];
+            for (uint64_t k = a.g.rp[v]; k < e; k += 8) mod_arcs<8, 1>(a, k, e, lv, kv, sin);
+        }
+        tw += kv;
+        add_community(M, a.K, act, lv, kv);
+    }
+    mod_finish(a, M, tw, sin);
+}
+
+// One wavefront per row (rows of at most 512 arcs).
+__global__ __launch_bounds__(256) void mod_wave_k(ModArgs a, uint32_t lo, uint32_t cnt) {
+    __shared__ ModTable M;
+    mod_table_init(M);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 tw = 0, sin = 0;
+    for (uint32_t i = blockIdx.x * 4 + wave; i < cnt; i += gridDim.x * 4) {
+        const uint32_t v = lo + i;
+        const uint32_t lv = a.labels[v];
+        u64 kv = 0;
+        mod_arcs<kWaveArcs / 64, 64>(a, a.g.rp[v] + lane, a.g.rp[v + 1], lv, kv, sin);
+        kv = wave_sum(kv);
+        tw += lane == 0 ? kv : 0;
+        add_community(M, a.K, lane == 0, lv, kv);
+    }
+    mod_finish(a, M, tw, sin);
+}
+
+// One wavefront per segment of a long row.
+__global__ __launch_bounds__(256) void mod_hub_k(ModArgs a, const HubItem *__restrict__ items, uint32_t count) {
+    __shared__ ModTable M;
+    mod_table_init(M);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 tw = 0, sin = 0;
+    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
+        const HubItem item = items[it];
+        const uint32_t lv = a.labels[item.r];
+        u64 kv = 0;
+        mod_arcs<kWaveArcs / 64, 64>(a, item.b0 + lane, item.b1, lv, kv, sin);
+        kv = wave_sum(kv);
+        tw += lane == 0 ? kv : 0;
+        add_community(M, a.K, lane == 0, lv, kv);
+    }
+    mod_finish(a, M, tw, sin);
+}
+
+// Per-block u128 partial sums of K_c^2, written as (lo, hi) pairs.
+__global__ __launch_bounds__(256) void mod_sumsq_k(const u64 *__restrict__ K, uint32_t n, u64 *partials) {
+    __shared__ unsigned __int128 sh[256];
+    unsigned __int128 acc = 0;
+    for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c < n; c += gridDim.x * 256) {
+        const u64 k = K[c];
+        acc += (unsigned __int128)k * k;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (uint32_t off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = (u64)sh[0];
+        partials[2 * blockIdx.x + 1] = (u64)(sh[0] >> 64);
+    }
+}
+
+hipError_t launch_mod_rows(const ModArgs &a, uint32_t lo, uint32_t cnt, int per_wave, hipStream_t s) {
+    if (cnt == 0) return hipSuccess;
+    if (per_wave)
+        mod_wave_k<<<grid_for(cnt, 4, 2048), 256, 0, s>>>(a, lo, cnt);
+    else
+        mod_thread_k<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(a, lo, cnt);
+    return hipGetLastError();
+}
+hipError_t launch_mod_hub(const ModArgs &a, const HubItem *items, uint32_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    mod_hub_k<<<grid_for(count, 4, 2048), 256, 0, s>>>(a, items, count);
+    return hipGetLastError();
+}
+hipError_t launch_mod_sumsq(const u64 *K, uint32_t n, u64 *partials, uint32_t nparts, hipStream_t s) {
+    mod_sumsq_k<<<nparts, 256, 0, s>>>(K, n, partials);
+    return hipGetLastError();
+}
+
+}  // namespace lpa

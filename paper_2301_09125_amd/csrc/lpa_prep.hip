@@ -1,0 +1,451 @@
+// lpa_prep.hip -- per-run preparation kernels: degree binning, the
+// relabelled internal CSR, label initialisation and the final scatter.
+//
+// Binning is a stable partition of the vertices by degree bin (1024
+// vertices per 256-thread block: count, one-block scan, scatter).  The
+// scatter also assigns each non-isolated vertex its internal id and the
+// start of its internal row (an exclusive prefix of degrees in internal
+// order), so the internal row_ptr comes out of the same pass.
+
+#include "lpa_device.h"
+
+namespace lpa {
+
+// ---------------------------------------------------------------- fills --
+
+__global__ void iota_k(uint32_t *a, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = i;
+}
+__global__ void fill64_k(u64 *p, u64 v, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void fill32_k(uint32_t *p, uint32_t v, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void check_labels_k(const uint32_t *labels, uint32_t n, uint32_t *err) {
+    bool bad = false;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        bad |= labels[i] >= n;
+    if (bad) atomicOr(err, ERR_LABEL);
+}
+
+hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    iota_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(a, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(u64 *p, u64 v, uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    fill64_k<<<grid_for(count, 256, 8192), 256, 0, s>>>(p, v, count);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    fill32_k<<<grid_for(count, 256, 8192), 256, 0, s>>>(p, v, count);
+    return hipGetLastError();
+}
+hipError_t launch_check_labels(const uint32_t *labels, uint32_t n, uint32_t *err, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    check_labels_k<<<grid_for(n, 256, 4096), 256, 0, s>>>(labels, n, err);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- binning --
+
+constexpr uint32_t kBinVerts = 1024;
+
+uint32_t bin_blocks(uint32_t n) { return (n + kBinVerts - 1) / kBinVerts; }
+
+__device__ __forceinline__ int bin_of(uint64_t d, const BinCfg &c) {
+    return d == 0 ? BIN_ZERO
+           : d <= c.tmax ? BIN_THREAD
+           : d <= c.gmax ? BIN_GROUP
+           : d <= c.wmax ? BIN_WAVE
+           : d <= c.xmax ? BIN_WIDE
+                         : BIN_HUB;
+}
+
+// Bin of vertex v, or -1 when its row_ptr entries are malformed.
+__device__ __forceinline__ int vertex_bin(const Graph &g, uint32_t v, const BinCfg &c, uint64_t &d, bool &bad) {
+    const uint64_t a = g.rp[v], b = g.rp[v + 1];
+    bad = (b < a) || (b > g.m) || (v == 0 && a != 0) || (v + 1 == g.n && b != g.m);
+    d = bad ? 0 : b - a;
+    return bad ? -1 : bin_of(d, c);
+}
+
+__global__ __launch_bounds__(256) void bin_count_k(Graph g, BinCfg cfg, uint32_t *blk_counts, u64 *blk_arcs,
+                                                   uint32_t nblk, uint32_t *err) {
+    __shared__ uint32_t cnt[NBINS];
+    __shared__ u64 arcs[NBINS];
+    if (threadIdx.x < NBINS) {
+        cnt[threadIdx.x] = 0;
+        arcs[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    u64 my_arcs[NBINS];
+    uint32_t my_cnt[NBINS];
+#pragma unroll
+    for (int b = 0; b < NBINS; ++b) {
+        my_arcs[b] = 0;
+        my_cnt[b] = 0;
+    }
+    bool bad_any = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t v = blockIdx.x * kBinVerts + i * 256 + threadIdx.x;
+        if (v < g.n) {
+            uint64_t d;
+            bool bad;
+            const int bin = vertex_bin(g, v, cfg, d, bad);
+            bad_any |= bad;
+#pragma unroll
+            for (int b = 0; b < NBINS; ++b)
+                if (bin == b) {
+                    my_cnt[b] += 1;
+                    my_arcs[b] += d;
+                }
+        }
+    }
+    if (bad_any) atomicOr(err, ERR_ROWPTR);
+#pragma unroll
+    for (int b = 0; b < NBINS; ++b) {
+        const uint32_t c = wave_sum(my_cnt[b]);
+        const u64 s = wave_sum(my_arcs[b]);
+        if ((threadIdx.x & 63) == 0) {
+            if (c) atomicAdd(&cnt[b], c);
+            if (s) atomicAdd(&arcs[b], s);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NBINS) {
+        blk_counts[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+        blk_arcs[threadIdx.x * nblk + blockIdx.x] = arcs[threadIdx.x];
+    }
+}
+
+// One 1024-thread block: per-block vertex and arc counts -> exclusive global
+// offsets (in place) of the internal layout, bins back to back in bin order.
+__global__ __launch_bounds__(1024) void bin_scan_k(uint32_t *blk_counts, u64 *blk_arcs, uint32_t nblk,
+                                                   uint32_t *totals, u64 *arc_totals) {
+    __shared__ uint32_t wtot[16][NBINS];
+    __shared__ u64 watot[16][NBINS];
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t per = (nblk + 1023) / 1024;
+    const uint32_t lo = min(t * per, nblk), hi = min(lo + per, nblk);
+    uint32_t s[NBINS], incl[NBINS];
+    u64 as[NBINS], aincl[NBINS];
+#pragma unroll
+    for (int b = 0; b < NBINS; ++b) {
+        s[b] = 0;
+        as[b] = 0;
+        for (uint32_t i = lo; i < hi; ++i) {
+            s[b] += blk_counts[(size_t)b * nblk + i];
+            as[b] += blk_arcs[(size_t)b * nblk + i];
+        }
+        uint32_t x = s[b];
+        u64 y = as[b];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t xs = __shfl_up(x, off, 64);
+            const u64 ys = __shfl_up(y, off, 64);
+            if ((int)lane >= off) {
+                x += xs;
+                y += ys;
+            }
+        }
+        incl[b] = x;
+        aincl[b] = y;
+        if (lane == 63) {
+            wtot[wave][b] = x;
+            watot[wave][b] = y;
+        }
+    }
+    __syncthreads();
+    uint32_t base = 0;
+    u64 abase = 0;
+#pragma unroll
+    for (int b = 0; b < NBINS; ++b) {
+        uint32_t before = 0, total = 0;
+        u64 abefore = 0, atotal = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            if (w < wave) {
+                before += wtot[w][b];
+                abefore += watot[w][b];
+            }
+            total += wtot[w][b];
+            atotal += watot[w][b];
+        }
+        uint32_t run = base + before + incl[b] - s[b];
+        u64 arun = abase + abefore + aincl[b] - as[b];
+        for (uint32_t i = lo; i < hi; ++i) {
+            const uint32_t x = blk_counts[(size_t)b * nblk + i];
+            const u64 y = blk_arcs[(size_t)b * nblk + i];
+            blk_counts[(size_t)b * nblk + i] = run;
+            blk_arcs[(size_t)b * nblk + i] = arun;
+            run += x;
+            arun += y;
+        }
+        if (t == 0) {
+            totals[b] = total;
+            arc_totals[b] = atotal;
+        }
+        base += total;
+        abase += atotal;
+    }
+}
+
+// Internal id, internal row start and the two id maps.
+__global__ __launch_bounds__(256) void bin_scatter_k(Graph g, BinCfg cfg, const uint32_t *blk_offsets,
+                                                     const u64 *blk_arc_offsets,
+                                                     uint32_t nblk, uint32_t *old_of, uint32_t *new_of,
+                                                     uint64_t *rp2) {
+    __shared__ uint32_t wcnt[4][NBINS];
+    __shared__ u64 warc[4][NBINS];
+    __shared__ uint32_t run[NBINS];
+    __shared__ u64 arun[NBINS];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < NBINS) {
+        run[threadIdx.x] = blk_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
+        arun[threadIdx.x] = blk_arc_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
+    }
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t v = blockIdx.x * kBinVerts + i * 256 + threadIdx.x;
+        int bin = -1;
+        uint64_t d = 0;
+        if (v < g.n) {
+            bool bad;
+            bin = vertex_bin(g, v, cfg, d, bad);
+        }
+        uint32_t rank = 0;
+        u64 aex = 0;
+#pragma unroll
+        for (int b = 0; b < NBINS; ++b) {
+            const u64 mask = __ballot(bin == b);
+            u64 x = bin == b ? (u64)d : 0ull;
+            const u64 x0 = x;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const u64 y = __shfl_up(x, off, 64);
+                if ((int)lane >= off) x += y;
+            }
+            if (lane == 63) warc[wave][b] = x;
+            if (lane == 0) wcnt[wave][b] = (uint32_t)__popcll(mask);
+            if (bin == b) {
+                rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+                aex = x - x0;
+            }
+        }
+        __syncthreads();
+        if (bin >= 0) {
+            uint32_t off = run[bin];
+            u64 aoff = arun[bin];
+            for (uint32_t w = 0; w < wave; ++w) {
+                off += wcnt[w][bin];
+                aoff += warc[w][bin];
+            }
+            old_of[off + rank] = v;
+            new_of[v] = off + rank;
+            rp2[off + rank] = aoff + aex;
+        }
+        __syncthreads();
+        if (threadIdx.x < NBINS) {
+            const int b = threadIdx.x;
+            run[b] += wcnt[0][b] + wcnt[1][b] + wcnt[2][b] + wcnt[3][b];
+            arun[b] += warc[0][b] + warc[1][b] + warc[2][b] + warc[3][b];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_bin_count(const Graph &g, const BinCfg &cfg, uint32_t *blk_counts, u64 *blk_arcs, uint32_t nblk,
+                            uint32_t *err, hipStream_t s) {
+    bin_count_k<<<nblk, 256, 0, s>>>(g, cfg, blk_counts, blk_arcs, nblk, err);
+    return hipGetLastError();
+}
+hipError_t launch_bin_scan(uint32_t *blk_counts, u64 *blk_arcs, uint32_t nblk, uint32_t *totals, u64 *arc_totals,
+                           hipStream_t s) {
+    bin_scan_k<<<1, 1024, 0, s>>>(blk_counts, blk_arcs, nblk, totals, arc_totals);
+    return hipGetLastError();
+}
+hipError_t launch_bin_scatter(const Graph &g, const BinCfg &cfg, const uint32_t *blk_offsets,
+                              const u64 *blk_arc_offsets, uint32_t nblk, uint32_t *old_of, uint32_t *new_of,
+                              uint64_t *rp2, hipStream_t s) {
+    bin_scatter_k<<<nblk, 256, 0, s>>>(g, cfg, blk_offsets, blk_arc_offsets, nblk, old_of, new_of, rp2);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- relabel --
+
+struct RelabelArgs {
+    Graph g;  // caller's CSR
+    const uint32_t *old_of;
+    const uint32_t *new_of;
+    const uint64_t *rp2;
+    uint32_t *col2;
+    uint32_t *w2;
+    uint32_t *err;
+};
+
+// Rows of at most 32 arcs, one lane each.
+__global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *rowflag, uint32_t lo,
+                                                        uint32_t cnt) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < cnt; i += gridDim.x * 256) {
+        const uint32_t r = lo + i;
+        const uint32_t v = a.old_of[r];
+        const uint64_t src = a.g.rp[v], e = a.g.rp[v + 1];
+        const uint64_t dst = a.rp2[r];
+        uint32_t prev = 0, distinct = 1;
+        bool bad = false;
+        for (uint64_t k = src; k < e; k += 4) {
+            uint32_t u[4], wv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                u[j] = 0;
+                wv[j] = 1;
+                if (k + j < e) {
+                    u[j] = a.g.col[k + j];
+                    if (a.g.w) wv[j] = a.g.w[k + j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                bad |= u[j] >= a.g.n;
+                u[j] = u[j] >= a.g.n ? 0u : u[j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (k + j < e) {
+                    if (k + j > src && !(prev < u[j])) distinct = 0;
+                    prev = u[j];
+                    a.col2[dst + (k + j - src)] = a.new_of[u[j]];
+                    if (a.w2) a.w2[dst + (k + j - src)] = wv[j];
+                }
+        }
+        if (bad) atomicOr(a.err, ERR_COL);
+        rowflag[r] = distinct ? ROW_DISTINCT : 0;
+    }
+}
+
+// Copy arcs [b0, b0 + len) of internal row r (one wavefront, <= 512 arcs)
+// from the caller's row of old_of[r]; returns 1 if they are strictly
+// increasing (also across the segment's first boundary inside the row).
+__device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32_t r, uint64_t b0, uint64_t len) {
+    constexpr int A = kWaveArcs / 64;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t v = a.old_of[r];
+    const uint64_t rs = a.g.rp[v];
+    const uint64_t off = b0 - a.rp2[r];  // offset of the segment inside the row
+    const uint64_t src = rs + off;
+    uint32_t u[A], pv[A], wv[A];
+    uint32_t ok = 1;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = lane + 64ull * j;
+        u[j] = 0;
+        pv[j] = 0;
+        wv[j] = 1;
+        if (k < len) {
+            u[j] = a.g.col[src + k];
+            if (src + k > rs) pv[j] = a.g.col[src + k - 1];
+            if (a.g.w) wv[j] = a.g.w[src + k];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = lane + 64ull * j;
+        if (k < len && src + k > rs && !(pv[j] < u[j])) ok = 0;
+        bad |= u[j] >= a.g.n;
+        u[j] = u[j] >= a.g.n ? 0u : u[j];
+    }
+    if (bad) atomicOr(a.err, ERR_COL);
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = lane + 64ull * j;
+        if (k < len) {
+            a.col2[b0 + k] = a.new_of[u[j]];
+            if (a.w2) a.w2[b0 + k] = wv[j];
+        }
+    }
+    return __ballot(!ok) == 0 ? 1u : 0u;
+}
+
+// Rows of 33..512 arcs, one wavefront each.
+__global__ __launch_bounds__(256) void relabel_wave_k(RelabelArgs a, uint8_t *rowflag, uint32_t lo, uint32_t cnt) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t i = blockIdx.x * 4 + wave; i < cnt; i += gridDim.x * 4) {
+        const uint32_t r = lo + i;
+        const uint64_t b0 = a.rp2[r], b1 = a.rp2[r + 1];
+        const uint32_t ok = relabel_segment(a, r, b0, b1 - b0);
+        if ((threadIdx.x & 63) == 0) rowflag[r] = ok ? ROW_DISTINCT : 0;
+    }
+}
+
+// Long rows: one wavefront per work item; a segment with a repeated or
+// decreasing id marks the row HUB_REPEATS.
+__global__ __launch_bounds__(256) void relabel_hub_k(RelabelArgs a, const HubItem *__restrict__ items,
+                                                     uint32_t count, uint32_t *hub_flags) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
+        const HubItem item = items[it];
+        const uint32_t ok = relabel_segment(a, item.r, item.b0, item.b1 - item.b0);
+        if ((threadIdx.x & 63) == 0 && !ok) atomicOr(&hub_flags[item.r], HUB_REPEATS);
+    }
+}
+
+hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
+                               uint32_t *col2, uint32_t *w2, uint8_t *rowflag, uint32_t lo, uint32_t cnt,
+                               int per_wave, uint32_t *err, hipStream_t s) {
+    if (cnt == 0) return hipSuccess;
+    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err};
+    if (per_wave)
+        relabel_wave_k<<<grid_for(cnt, 4, 8192), 256, 0, s>>>(a, rowflag, lo, cnt);
+    else
+        relabel_thread_k<<<grid_for(cnt, 256, 8192), 256, 0, s>>>(a, rowflag, lo, cnt);
+    return hipGetLastError();
+}
+hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
+                              uint32_t *col2, uint32_t *w2, const HubItem *items, uint32_t count,
+                              uint32_t *hub_flags, uint32_t *err, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err};
+    relabel_hub_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hub_flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- labels in/out --
+
+// Both label buffers: vertices without arcs are never voted and keep their
+// label in whichever buffer a round reads.
+__global__ void init_labels_k(uint32_t *La, uint32_t *Lb, const uint32_t *old_of, const uint32_t *labels_in,
+                              uint32_t n) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const uint32_t v = old_of[r];
+        const uint32_t l = labels_in ? labels_in[v] : v;
+        La[r] = l;
+        if (Lb) Lb[r] = l;
+    }
+}
+__global__ void scatter_labels_k(uint32_t *out, const uint32_t *old_of, const uint32_t *L, uint32_t n_int) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n_int; r += gridDim.x * blockDim.x)
+        out[old_of[r]] = L[r];
+}
+
+hipError_t launch_init_labels(uint32_t *La, uint32_t *Lb, const uint32_t *old_of, const uint32_t *labels_in,
+                              uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    init_labels_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(La, Lb, old_of, labels_in, n);
+    return hipGetLastError();
+}
+hipError_t launch_scatter_labels(uint32_t *out, const uint32_t *old_of, const uint32_t *L, uint32_t n_int,
+                                 hipStream_t s) {
+    if (n_int == 0) return hipSuccess;
+    scatter_labels_k<<<grid_for(n_int, 256, 8192), 256, 0, s>>>(out, old_of, L, n_int);
+    return hipGetLastError();
+}
+
+}  // namespace lpa

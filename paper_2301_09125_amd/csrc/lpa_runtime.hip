@@ -1,17 +1,18 @@
 // lpa_runtime.hip -- host side of the C ABI declared in include/lpa.h.
 //
 // lpa_run (arXiv 2301.09125, Section 3.2):
-//   1. validate arguments on the host; bin vertices by degree on the device
-//      (this pass also checks row_ptr) and lay out work for the long rows;
+//   1. validate arguments on the host; bin the vertices by degree on the
+//      device (this pass also checks row_ptr) and build the relabelled
+//      internal CSR (lpa_internal.h), which also checks every col value;
 //   2. L0(v) = v in both label buffers (or the caller's labels to resume);
-//   3. per round: the vote kernels of every non-empty bin read L_old and
-//      write L_new, each adding its changed vertices to this round's device
-//      counter; 8 bytes come back to the host, which applies the tolerance
-//      test changed_t <= floor(tol * n) (Sections 3.2 and 4) and swaps the
-//      buffers;
-//   4. the final buffer is copied to labels_out if it is not already there.
-// lpa_modularity evaluates the Section 1 quality measure with exact integer
-// sums on the device.
+//   3. per round: the vote kernel of every non-empty bin reads L_old and
+//      writes L_new, adding its changed vertices to this round's device
+//      counter words; 4 KB come back to the host, which applies the
+//      tolerance test changed_t <= floor(tol * n) (Sections 3.2 and 4) and
+//      swaps the buffers;
+//   4. the final labels are scattered back to the caller's vertex order, and
+//      optionally their modularity (Section 1) is computed on the same
+//      internal graph.
 
 #include <hip/hip_runtime.h>
 
@@ -22,7 +23,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
-#include <string>
 #include <vector>
 
 #include "lpa.h"
@@ -57,9 +57,11 @@ struct DevBuf {
     }
 };
 
-enum KernelId { K_THREAD, K_GROUP, K_WAVE, K_HUB, K_HUB_REDUCE, K_HUB_FINAL, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"vote_thread", "vote_group", "vote_wave",
-                                     "vote_hub",    "hub_reduce", "hub_final"};
+enum KernelId {
+    K_THREAD, K_GROUP, K_WAVE, K_WIDE, K_HUB, K_MERGE, K_FALLBACK, K_REDUCE, K_FINAL, K_MOD, K_COUNT
+};
+const char *kKernelNames[K_COUNT] = {"vote_thread", "vote_group", "vote_wave",  "vote_wide",  "vote_hub",
+                                     "hub_merge",   "hub_fallback", "hub_reduce", "hub_final", "modularity"};
 
 struct Pending {
     int kid;
@@ -67,14 +69,14 @@ struct Pending {
     uint64_t bytes, arcs;
 };
 
-// Degree binning and long-row layout of one CSR.
+// Bins and long-row work of one CSR.
 struct Plan {
-    uint32_t cnt[NBINS] = {0, 0, 0, 0, 0};
-    uint64_t arcs[NBINS] = {0, 0, 0, 0, 0};
-    uint32_t off[NBINS] = {0, 0, 0, 0, 0};
-    uint32_t n_items = 0;   // hub work items (single-chunk rows + chunks of long rows)
-    uint32_t n_multi = 0;   // rows longer than one chunk
+    Bins bins;
+    uint32_t H = 0;         // long rows (internal ids 0..H-1)
+    uint32_t n_items = 0;   // wavefront segments of long rows
     uint32_t n_ritems = 0;  // phase-2 items
+    uint32_t n_mwave = 0;   // rows merged by one wavefront
+    uint32_t n_mblock = 0;  // rows merged by one block
 };
 
 }  // namespace
@@ -85,11 +87,11 @@ struct lpa_ctx {
     lpa_options opt{};
     int num_cu = 256;
 
-    DevBuf labels_b, order, blk_counts, blk_arcs, small;  // small: totals + arc totals
-    DevBuf counters;                                     // u64[max_iter] + error word
-    DevBuf hub_rows, items, ritems;
-    DevBuf hub_vertex, slab_off, slab_mask, touched_off, tcount, best, own_sum, own_seen, rowsum;
-    DevBuf slab, touched;
+    DevBuf blk_counts, blk_arcs, small;
+    DevBuf old_of, new_of, rp2, col2, w2, rowflag, La, Lb;
+    DevBuf counters;  // kCountWords u64 per round, then the error word
+    DevBuf items, ritems, slab_off, slab_mask, touched_off, tcount, best, own_sum, hflags, rowsum, slab, touched;
+    DevBuf cand, thr, item_lo, mrows, slab_pending;
     DevBuf K, mod_sums, partials;
     uint64_t *pinned = nullptr;  // host pinned scratch for small read-backs
     size_t pinned_words = 0;
@@ -109,16 +111,16 @@ lpa_status dev_status(hipError_t e) {
     return LPA_EDEVICE;
 }
 
-#define HIP_TRY(expr)                                   \
-    do {                                                \
-        hipError_t _e = (expr);                         \
-        if (_e != hipSuccess) return dev_status(_e);    \
+#define HIP_TRY(expr)                                \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return dev_status(_e); \
     } while (0)
 
-#define LPA_TRY(expr)                                   \
-    do {                                                \
-        lpa_status _s = (expr);                         \
-        if (_s != LPA_OK) return _s;                    \
+#define LPA_TRY(expr)                \
+    do {                             \
+        lpa_status _s = (expr);      \
+        if (_s != LPA_OK) return _s; \
     } while (0)
 
 lpa_status err_status(uint32_t bits) {
@@ -127,17 +129,18 @@ lpa_status err_status(uint32_t bits) {
     return LPA_OK;
 }
 
-uint32_t pow2_ceil(uint64_t x) {
+uint64_t pow2_ceil(uint64_t x) {
     uint64_t p = 1;
     while (p < x) p <<= 1;
-    return (uint32_t)p;
+    return p;
 }
 
 lpa_status check_options(const lpa_options &o) {
     if (o.thread_max < 1 || o.thread_max > (uint32_t)kThreadMaxCap) return LPA_EINVAL;
     if (o.group_max < o.thread_max || o.group_max > (uint32_t)kGroupSlots / 2) return LPA_EINVAL;
-    if (o.wave_max < o.group_max || o.wave_max > (uint32_t)kWaveSlots / 2) return LPA_EINVAL;
-    if (o.chunk < 256 || o.chunk > (uint32_t)kChunkSlotsMax / 2 || (o.chunk & (o.chunk - 1))) return LPA_EINVAL;
+    if (o.wave_max < o.group_max || o.wave_max > (uint32_t)kWaveArcsSmall) return LPA_EINVAL;
+    if (o.wide_max < o.wave_max || o.wide_max > (uint32_t)kWaveArcs) return LPA_EINVAL;
+    if (o.merge_max < 1 || o.merge_max > (uint32_t)kMergeBlockSegs) return LPA_EINVAL;
     return LPA_OK;
 }
 
@@ -196,8 +199,6 @@ void collect_profile(lpa_ctx *c) {
     c->ev_used = 0;
 }
 
-Graph make_graph(const lpa_csr *g) { return Graph{g->row_ptr, g->col, g->w, g->n, g->m}; }
-
 lpa_status check_csr_args(const lpa_csr *g) {
     if (!g) return LPA_EINVAL;
     if (g->n > 0xFFFFFFFEu) return LPA_EINVAL;
@@ -207,125 +208,12 @@ lpa_status check_csr_args(const lpa_csr *g) {
     return LPA_OK;
 }
 
-// Bin the vertices, validate row_ptr, and lay out the long rows.
-lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, bool hub_state) {
-    const hipStream_t s = c->stream;
-    const Graph G = make_graph(g);
-    const uint32_t n = g->n;
-    const uint32_t nblk = (n + 255) / 256;
-    HIP_TRY(c->blk_counts.ensure((size_t)NBINS * nblk * sizeof(uint32_t)));
-    HIP_TRY(c->blk_arcs.ensure((size_t)NBINS * nblk * sizeof(u64)));
-    HIP_TRY(c->order.ensure((size_t)n * sizeof(uint32_t)));
-    HIP_TRY(c->small.ensure(NBINS * (sizeof(uint32_t) + sizeof(u64)) + 64));
-    uint32_t *totals = c->small.as<uint32_t>();
-    u64 *arc_totals = reinterpret_cast<u64 *>(c->small.as<char>() + 32);
-    const lpa_options &o = c->opt;
-    HIP_TRY(launch_bin_count(G, o.thread_max, o.group_max, o.wave_max, c->blk_counts.as<uint32_t>(),
-                             c->blk_arcs.as<u64>(), nblk, err_dev, s));
-    HIP_TRY(launch_bin_scan(c->blk_counts.as<uint32_t>(), c->blk_arcs.as<u64>(), nblk, totals, arc_totals, s));
-    HIP_TRY(launch_bin_scatter(G, o.thread_max, o.group_max, o.wave_max, c->blk_counts.as<uint32_t>(), nblk,
-                               c->order.as<uint32_t>(), s));
-    LPA_TRY(ensure_pinned(c, 16));
-    uint32_t *h32 = reinterpret_cast<uint32_t *>(c->pinned);
-    HIP_TRY(hipMemcpyAsync(c->pinned, c->small.p, 32 + NBINS * sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(c->pinned + 12, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 12)[0];
-    if (errbits) return err_status(errbits);
-    uint32_t run = 0;
-    for (int b = 0; b < NBINS; ++b) {
-        P.cnt[b] = h32[b];
-        P.arcs[b] = c->pinned[4 + b];
-        P.off[b] = run;
-        run += P.cnt[b];
-    }
-    P.n_items = P.n_multi = P.n_ritems = 0;
-    const uint32_t H = P.cnt[BIN_HUB];
-    if (H == 0) return LPA_OK;
-
-    // Long rows: fetch (vertex, row begin, row end) and build the work items.
-    HIP_TRY(c->hub_rows.ensure((size_t)H * 2 * sizeof(uint64_t)));
-    const uint32_t *hub_list = c->order.as<uint32_t>() + P.off[BIN_HUB];
-    HIP_TRY(launch_gather_rows(g->row_ptr, hub_list, H, c->hub_rows.as<uint64_t>(), s));
-    std::vector<uint32_t> verts(H);
-    std::vector<uint64_t> rows((size_t)H * 2);
-    HIP_TRY(hipMemcpyAsync(verts.data(), hub_list, (size_t)H * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(rows.data(), c->hub_rows.p, (size_t)H * 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-
-    const uint64_t C = o.chunk;
-    std::vector<HubItem> items;
-    std::vector<ReduceItem> ritems;
-    std::vector<uint32_t> hv;
-    std::vector<uint64_t> soff, toff;
-    std::vector<uint32_t> smask;
-    uint64_t slab_total = 0, touched_total = 0;
-    std::vector<HubItem> singles;
-    for (uint32_t i = 0; i < H; ++i) {
-        const uint64_t b = rows[2 * i], e = rows[2 * i + 1], d = e - b;
-        if (d <= C) {
-            singles.push_back(HubItem{verts[i], kNoHub, b, e});
-            continue;
-        }
-        const uint32_t h = (uint32_t)hv.size();
-        hv.push_back(verts[i]);
-        const uint64_t slots = pow2_ceil(2 * d);
-        soff.push_back(slab_total);
-        smask.push_back((uint32_t)(slots - 1));
-        toff.push_back(touched_total);
-        slab_total += slots;
-        touched_total += d;
-        uint32_t ci = 0;
-        for (uint64_t x = b; x < e; x += C, ++ci) {
-            items.push_back(HubItem{verts[i], h, x, std::min(e, x + C)});
-            ritems.push_back(ReduceItem{h, (uint32_t)(ci * C), (uint32_t)((ci + 1) * C), 0});
-        }
-    }
-    // long rows first: their chunks are the largest units of work
-    items.insert(items.end(), singles.begin(), singles.end());
-    P.n_items = (uint32_t)items.size();
-    P.n_multi = (uint32_t)hv.size();
-    P.n_ritems = (uint32_t)ritems.size();
-    HIP_TRY(c->items.ensure(items.size() * sizeof(HubItem)));
-    HIP_TRY(hipMemcpyAsync(c->items.p, items.data(), items.size() * sizeof(HubItem), hipMemcpyHostToDevice, s));
-    if (!hub_state || P.n_multi == 0) {
-        HIP_TRY(hipStreamSynchronize(s));
-        return LPA_OK;
-    }
-    const uint32_t M = P.n_multi;
-    HIP_TRY(c->ritems.ensure(ritems.size() * sizeof(ReduceItem)));
-    HIP_TRY(c->hub_vertex.ensure(M * sizeof(uint32_t)));
-    HIP_TRY(c->slab_off.ensure(M * sizeof(uint64_t)));
-    HIP_TRY(c->slab_mask.ensure(M * sizeof(uint32_t)));
-    HIP_TRY(c->touched_off.ensure(M * sizeof(uint64_t)));
-    HIP_TRY(c->tcount.ensure(M * sizeof(uint32_t)));
-    HIP_TRY(c->best.ensure(M * sizeof(u64)));
-    HIP_TRY(c->own_sum.ensure(M * sizeof(u64)));
-    HIP_TRY(c->own_seen.ensure(M * sizeof(uint32_t)));
-    HIP_TRY(c->rowsum.ensure(M * sizeof(u64)));
-    HIP_TRY(c->touched.ensure(touched_total * sizeof(uint32_t)));
-    const size_t old_slab = c->slab.bytes;
-    HIP_TRY(c->slab.ensure(slab_total * sizeof(u64)));
-    if (c->slab.bytes != old_slab || old_slab == 0)  // fresh allocation: every slot EMPTY
-        HIP_TRY(launch_fill_u64(c->slab.as<u64>(), 0xFFFFFFFF00000000ull, c->slab.bytes / sizeof(u64), s));
-    HIP_TRY(hipMemcpyAsync(c->ritems.p, ritems.data(), ritems.size() * sizeof(ReduceItem), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(c->hub_vertex.p, hv.data(), M * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(c->slab_off.p, soff.data(), M * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(c->slab_mask.p, smask.data(), M * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(c->touched_off.p, toff.data(), M * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_fill_u32(c->tcount.as<uint32_t>(), 0, M, s));
-    HIP_TRY(launch_fill_u64(c->best.as<u64>(), 0, M, s));
-    HIP_TRY(launch_fill_u64(c->own_sum.as<u64>(), 0, M, s));
-    HIP_TRY(launch_fill_u32(c->own_seen.as<uint32_t>(), 0, M, s));
-    HIP_TRY(launch_fill_u64(c->rowsum.as<u64>(), 0, M, s));
-    // the host vectors must outlive the asynchronous copies
-    HIP_TRY(hipStreamSynchronize(s));
-    return LPA_OK;
+Graph internal_graph(lpa_ctx *c, const lpa_csr *g) {
+    return Graph{c->rp2.as<uint64_t>(), c->col2.as<uint32_t>(), g->w ? c->w2.as<uint32_t>() : nullptr, g->n, g->m};
 }
 
 HubState hub_state(lpa_ctx *c) {
     HubState h;
-    h.vertex = c->hub_vertex.as<uint32_t>();
     h.slab_off = c->slab_off.as<uint64_t>();
     h.slab_mask = c->slab_mask.as<uint32_t>();
     h.touched_off = c->touched_off.as<uint64_t>();
@@ -334,38 +222,268 @@ HubState hub_state(lpa_ctx *c) {
     h.tcount = c->tcount.as<uint32_t>();
     h.best = c->best.as<u64>();
     h.own_sum = c->own_sum.as<u64>();
-    h.own_seen = c->own_seen.as<uint32_t>();
+    h.flags = c->hflags.as<uint32_t>();
     h.rowsum = c->rowsum.as<u64>();
+    h.cand = c->cand.as<u64>();
+    h.thr = c->thr.as<uint32_t>();
+    h.item_lo = c->item_lo.as<uint32_t>();
+    h.pending = c->slab_pending.as<uint32_t>();
     return h;
 }
 
-// Enqueue every vote kernel of one round.
-lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const HubState &hs, bool weighted) {
+// Bin the vertices, validate row_ptr, build the internal CSR and lay out the
+// long rows.  with_slab: also prepare the global slabs used by the vote.
+lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, bool with_slab) {
     const hipStream_t s = c->stream;
-    const uint32_t *order = c->order.as<uint32_t>();
-    const uint64_t ab = weighted ? 12 : 8;  // algorithmic bytes per arc: col, w, gathered label
-    const int cap = c->num_cu * 8;
-    LPA_TRY(timed(c, K_THREAD, ab * P.arcs[BIN_THREAD] + 16ull * P.cnt[BIN_THREAD], P.arcs[BIN_THREAD], [&] {
-        return launch_vote_thread(ra, order + P.off[BIN_THREAD], P.cnt[BIN_THREAD], cap, s);
-    }));
-    LPA_TRY(timed(c, K_GROUP, ab * P.arcs[BIN_GROUP] + 16ull * P.cnt[BIN_GROUP], P.arcs[BIN_GROUP], [&] {
-        return launch_vote_group(ra, order + P.off[BIN_GROUP], P.cnt[BIN_GROUP], cap, s);
-    }));
-    LPA_TRY(timed(c, K_WAVE, ab * P.arcs[BIN_WAVE] + 16ull * P.cnt[BIN_WAVE], P.arcs[BIN_WAVE], [&] {
-        return launch_vote_wave(ra, order + P.off[BIN_WAVE], P.cnt[BIN_WAVE], cap, s);
-    }));
-    if (P.n_items) {
-        LPA_TRY(timed(c, K_HUB, ab * P.arcs[BIN_HUB] + 16ull * P.cnt[BIN_HUB], P.arcs[BIN_HUB], [&] {
-            return launch_vote_hub(ra, c->items.as<HubItem>(), P.n_items, c->opt.chunk, hs, s);
-        }));
+    const Graph G{g->row_ptr, g->col, g->w, g->n, g->m};
+    const uint32_t n = g->n;
+    const uint32_t nblk = bin_blocks(n);
+    const lpa_options &o = c->opt;
+    HIP_TRY(c->blk_counts.ensure((size_t)NBINS * nblk * sizeof(uint32_t)));
+    HIP_TRY(c->blk_arcs.ensure((size_t)NBINS * nblk * sizeof(u64)));
+    HIP_TRY(c->small.ensure(128));
+    HIP_TRY(c->old_of.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(c->new_of.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(c->rp2.ensure(((size_t)n + 1) * sizeof(uint64_t)));
+    HIP_TRY(c->col2.ensure((size_t)g->m * sizeof(uint32_t)));
+    if (g->w) HIP_TRY(c->w2.ensure((size_t)g->m * sizeof(uint32_t)));
+    HIP_TRY(c->rowflag.ensure((size_t)n));
+    uint32_t *totals = c->small.as<uint32_t>();
+    u64 *arc_totals = reinterpret_cast<u64 *>(c->small.as<char>() + 32);
+    const BinCfg cfg{o.thread_max, o.group_max, o.wave_max, o.wide_max};
+    HIP_TRY(launch_bin_count(G, cfg, c->blk_counts.as<uint32_t>(), c->blk_arcs.as<u64>(), nblk, err_dev, s));
+    HIP_TRY(launch_bin_scan(c->blk_counts.as<uint32_t>(), c->blk_arcs.as<u64>(), nblk, totals, arc_totals, s));
+    HIP_TRY(launch_bin_scatter(G, cfg, c->blk_counts.as<uint32_t>(), c->blk_arcs.as<u64>(), nblk,
+                               c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(), s));
+    HIP_TRY(launch_fill_u64(reinterpret_cast<u64 *>(c->rp2.as<uint64_t>() + n), g->m, 1, s));
+    LPA_TRY(ensure_pinned(c, 16));
+    HIP_TRY(hipMemcpyAsync(c->pinned, c->small.p, 32 + NBINS * sizeof(u64), hipMemcpyDeviceToHost, s));
+    static_assert(NBINS <= 8 && 4 + NBINS <= 12, "bin totals must fit the read-back layout");
+    HIP_TRY(hipMemcpyAsync(c->pinned + 12, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 12)[0];
+    if (errbits) return err_status(errbits);
+    const uint32_t *h32 = reinterpret_cast<const uint32_t *>(c->pinned);
+    uint32_t run = 0;
+    for (int b = 0; b < NBINS; ++b) {
+        P.bins.cnt[b] = h32[b];
+        P.bins.arcs[b] = c->pinned[4 + b];
+        P.bins.lo[b] = run;
+        run += P.bins.cnt[b];
     }
-    if (P.n_multi) {
-        LPA_TRY(timed(c, K_HUB_REDUCE, 0, 0, [&] {
+    P.H = P.bins.cnt[BIN_HUB];
+    P.n_items = P.n_ritems = 0;
+
+    // long rows: wavefront segments of kWaveArcs arcs, merge lists, slabs,
+    // touched lists
+    std::vector<HubItem> items;
+    std::vector<ReduceItem> ritems;
+    std::vector<uint64_t> soff, toff;
+    std::vector<uint32_t> smask, hflags, item_lo, mrows_w, mrows_b;
+    uint64_t slab_total = 0, touched_total = 0;
+    if (P.H) {
+        std::vector<uint64_t> rows((size_t)P.H + 1);
+        HIP_TRY(hipMemcpyAsync(rows.data(), c->rp2.p, rows.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (uint32_t h = 0; h < P.H; ++h) {
+            const uint64_t b = rows[h], e = rows[h + 1], d = e - b;
+            item_lo.push_back((uint32_t)items.size());
+            for (uint64_t x = b; x < e; x += kWaveArcs)
+                items.push_back(HubItem{h, 0, x, std::min<uint64_t>(e, x + kWaveArcs)});
+            const uint64_t nseg = (d + kWaveArcs - 1) / kWaveArcs;
+            uint32_t f = 0;
+            if (nseg > (uint64_t)o.merge_max)
+                f = HUB_BIG;
+            else if (nseg <= (uint64_t)kMergeWaveSegs)
+                mrows_w.push_back(h);
+            else
+                mrows_b.push_back(h);
+            hflags.push_back(f);
+            for (uint64_t t = 0; t < d; t += 2048)
+                ritems.push_back(ReduceItem{h, (uint32_t)t, (uint32_t)std::min<uint64_t>(d, t + 2048), 0});
+            const uint64_t slots = pow2_ceil(2 * d);
+            soff.push_back(slab_total);
+            smask.push_back((uint32_t)(slots - 1));
+            toff.push_back(touched_total);
+            slab_total += slots;
+            touched_total += d;
+        }
+        item_lo.push_back((uint32_t)items.size());
+        P.n_items = (uint32_t)items.size();
+        P.n_ritems = (uint32_t)ritems.size();
+        P.n_mwave = (uint32_t)mrows_w.size();
+        P.n_mblock = (uint32_t)mrows_b.size();
+        HIP_TRY(c->items.ensure(items.size() * sizeof(HubItem)));
+        HIP_TRY(hipMemcpyAsync(c->items.p, items.data(), items.size() * sizeof(HubItem), hipMemcpyHostToDevice, s));
+        HIP_TRY(c->hflags.ensure((size_t)P.H * sizeof(uint32_t)));
+        HIP_TRY(hipMemcpyAsync(c->hflags.p, hflags.data(), (size_t)P.H * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    }
+
+    // internal CSR
+    uint32_t *w2 = g->w ? c->w2.as<uint32_t>() : nullptr;
+    const Bins &B = P.bins;
+    HIP_TRY(launch_relabel_hub(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
+                               c->col2.as<uint32_t>(), w2, c->items.as<HubItem>(), P.n_items,
+                               c->hflags.as<uint32_t>(), err_dev, s));
+    HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
+                                c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_WIDE],
+                                B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE], 1, err_dev, s));
+    HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
+                                c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_GROUP],
+                                B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD], 0, err_dev, s));
+
+    if (with_slab && P.H) {
+        const uint32_t H = P.H;
+        HIP_TRY(c->ritems.ensure(ritems.size() * sizeof(ReduceItem)));
+        HIP_TRY(c->slab_off.ensure(H * sizeof(uint64_t)));
+        HIP_TRY(c->slab_mask.ensure(H * sizeof(uint32_t)));
+        HIP_TRY(c->touched_off.ensure(H * sizeof(uint64_t)));
+        HIP_TRY(c->tcount.ensure(H * sizeof(uint32_t)));
+        HIP_TRY(c->best.ensure(H * sizeof(u64)));
+        HIP_TRY(c->own_sum.ensure(H * sizeof(u64)));
+        HIP_TRY(c->rowsum.ensure(H * sizeof(u64)));
+        HIP_TRY(c->touched.ensure(touched_total * sizeof(uint32_t)));
+        const size_t old_slab = c->slab.bytes;
+        HIP_TRY(c->slab.ensure(slab_total * sizeof(u64)));
+        if (c->slab.bytes != old_slab || old_slab == 0)  // fresh allocation: every slot EMPTY
+            HIP_TRY(launch_fill_u64(c->slab.as<u64>(), 0xFFFFFFFF00000000ull, c->slab.bytes / sizeof(u64), s));
+        HIP_TRY(hipMemcpyAsync(c->ritems.p, ritems.data(), ritems.size() * sizeof(ReduceItem),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(c->slab_off.p, soff.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(c->slab_mask.p, smask.data(), H * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(c->touched_off.p, toff.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(c->slab_pending.ensure(sizeof(uint32_t)));
+        HIP_TRY(launch_fill_u32(c->slab_pending.as<uint32_t>(), 0, 1, s));
+        HIP_TRY(c->cand.ensure((size_t)P.n_items * kTopK * sizeof(u64)));
+        HIP_TRY(c->thr.ensure((size_t)P.n_items * sizeof(uint32_t)));
+        HIP_TRY(c->item_lo.ensure(item_lo.size() * sizeof(uint32_t)));
+        HIP_TRY(c->mrows.ensure((mrows_w.size() + mrows_b.size()) * sizeof(uint32_t)));
+        HIP_TRY(hipMemcpyAsync(c->item_lo.p, item_lo.data(), item_lo.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, s));
+        if (!mrows_w.empty())
+            HIP_TRY(hipMemcpyAsync(c->mrows.p, mrows_w.data(), mrows_w.size() * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice, s));
+        if (!mrows_b.empty())
+            HIP_TRY(hipMemcpyAsync(c->mrows.as<uint32_t>() + mrows_w.size(), mrows_b.data(),
+                                   mrows_b.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_fill_u32(c->tcount.as<uint32_t>(), 0, H, s));
+        HIP_TRY(launch_fill_u64(c->best.as<u64>(), 0, H, s));
+        HIP_TRY(launch_fill_u64(c->own_sum.as<u64>(), 0, H, s));
+        HIP_TRY(launch_fill_u64(c->rowsum.as<u64>(), 0, H, s));
+    }
+    // the host vectors must outlive the asynchronous copies
+    HIP_TRY(hipStreamSynchronize(s));
+    return LPA_OK;
+}
+
+// Enqueue every vote kernel of one round.  first = round 1 from L0(v) = v.
+lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const HubState &hs, bool weighted,
+                         int first) {
+    const hipStream_t s = c->stream;
+    // algorithmic bytes: per arc col, weight, gathered label; per vertex
+    // row_ptr, own label read, new label write
+    const uint64_t ab = weighted ? 12 : 8;
+    const Bins &B = P.bins;
+    const int cap = c->num_cu * 8;
+    auto bytes = [&](int b) { return ab * B.arcs[b] + 16ull * B.cnt[b]; };
+    LPA_TRY(timed(c, K_THREAD, bytes(BIN_THREAD), B.arcs[BIN_THREAD], [&] {
+        return launch_vote_thread(ra, B.lo[BIN_THREAD], B.cnt[BIN_THREAD], first, cap, s);
+    }));
+    LPA_TRY(timed(c, K_GROUP, bytes(BIN_GROUP), B.arcs[BIN_GROUP], [&] {
+        return launch_vote_group(ra, B.lo[BIN_GROUP], B.cnt[BIN_GROUP], first, cap, s);
+    }));
+    LPA_TRY(timed(c, K_WAVE, bytes(BIN_WAVE), B.arcs[BIN_WAVE], [&] {
+        return launch_vote_wave(ra, B.lo[BIN_WAVE], B.cnt[BIN_WAVE], 0, first, cap, s);
+    }));
+    LPA_TRY(timed(c, K_WIDE, bytes(BIN_WIDE), B.arcs[BIN_WIDE], [&] {
+        return launch_vote_wave(ra, B.lo[BIN_WIDE], B.cnt[BIN_WIDE], 1, first, c->num_cu * 5, s);
+    }));
+    if (P.H) {
+        const uint32_t *mrows = c->mrows.as<uint32_t>();
+        LPA_TRY(timed(c, K_HUB, bytes(BIN_HUB), B.arcs[BIN_HUB], [&] {
+            return launch_vote_hub(ra, c->items.as<HubItem>(), P.n_items, hs, first, c->num_cu * 5, s);
+        }));
+        LPA_TRY(timed(c, K_MERGE, 0, 0, [&] {
+            hipError_t e = launch_hub_merge(ra, hs, mrows, P.n_mwave, 0, first, s);
+            if (e == hipSuccess) e = launch_hub_merge(ra, hs, mrows + P.n_mwave, P.n_mblock, 1, first, s);
+            return e;
+        }));
+        LPA_TRY(timed(c, K_FALLBACK, 0, 0, [&] {
+            return launch_hub_fallback(ra, c->items.as<HubItem>(), P.n_items, hs, c->num_cu * 5, s);
+        }));
+        LPA_TRY(timed(c, K_REDUCE, 0, 0, [&] {
             return launch_hub_reduce(hs, c->ritems.as<ReduceItem>(), P.n_ritems, s);
         }));
-        LPA_TRY(timed(c, K_HUB_FINAL, 0, 0, [&] { return launch_hub_final(ra, hs, P.n_multi, s); }));
+        LPA_TRY(timed(c, K_FINAL, 0, 0, [&] { return launch_hub_final(ra, hs, P.H, first, s); }));
     }
     return LPA_OK;
+}
+
+// Modularity of the internal labels L on the internal graph.
+lpa_status modularity_internal(lpa_ctx *c, const lpa_csr *g, const Plan &P, const uint32_t *L, uint32_t *err_dev,
+                               double *q_out, uint64_t *terms) {
+    const hipStream_t s = c->stream;
+    const uint32_t n = g->n;
+    const uint32_t nparts = 1024;
+    HIP_TRY(c->K.ensure((size_t)n * sizeof(u64)));
+    HIP_TRY(c->mod_sums.ensure(2 * sizeof(u64)));
+    HIP_TRY(c->partials.ensure(2 * nparts * sizeof(u64)));
+    const Bins &B = P.bins;
+    const uint64_t wb = g->w ? 12 : 8;
+    LPA_TRY(timed(c, K_MOD, wb * g->m + 28ull * n, g->m, [&]() -> hipError_t {
+        hipError_t e = launch_fill_u64(c->K.as<u64>(), 0, n, s);
+        if (e == hipSuccess) e = launch_fill_u64(c->mod_sums.as<u64>(), 0, 2, s);
+        ModArgs ma;
+        ma.g = internal_graph(c, g);
+        ma.labels = L;
+        ma.K = c->K.as<u64>();
+        ma.sums = c->mod_sums.as<u64>();
+        ma.err = err_dev;
+        if (e == hipSuccess)
+            e = launch_mod_rows(ma, B.lo[BIN_GROUP], B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD], 0, s);
+        if (e == hipSuccess) e = launch_mod_rows(ma, B.lo[BIN_WIDE], B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE], 1, s);
+        if (e == hipSuccess) e = launch_mod_hub(ma, c->items.as<HubItem>(), P.n_items, s);
+        if (e == hipSuccess) e = launch_mod_sumsq(c->K.as<u64>(), n, c->partials.as<u64>(), nparts, s);
+        return e;
+    }));
+    std::vector<u64> parts(2 * nparts);
+    u64 sums[2];
+    uint32_t errbits = 0;
+    HIP_TRY(hipMemcpyAsync(parts.data(), c->partials.p, 2 * nparts * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sums, c->mod_sums.p, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&errbits, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->opt.profile) collect_profile(c);
+    if (errbits) return err_status(errbits);
+    unsigned __int128 sk2 = 0;
+    for (uint32_t i = 0; i < nparts; ++i)
+        sk2 += ((unsigned __int128)parts[2 * i + 1] << 64) | (unsigned __int128)parts[2 * i];
+    const u64 two_m = sums[0], sigma_in = sums[1];
+    double q = 0.0;
+    if (two_m > 0) {
+        const double W = (double)two_m;
+        q = (double)sigma_in / W - (double)sk2 / (W * W);
+    }
+    *q_out = q;
+    if (terms) {
+        terms[0] = two_m;
+        terms[1] = sigma_in;
+        terms[2] = (u64)sk2;
+        terms[3] = (u64)(sk2 >> 64);
+    }
+    return LPA_OK;
+}
+
+void clear_stats(lpa_stats *stats) {
+    if (!stats) return;
+    stats->iterations = 0;
+    stats->converged = 0;
+    stats->changed_last = 0;
+    stats->arcs_processed = 0;
+    stats->ms_total = 0;
+    stats->ms_rounds = 0;
+    stats->modularity = 0;
+    for (int i = 0; i < 4; ++i) stats->mod_terms[i] = 0;
 }
 
 lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, uint32_t max_iter,
@@ -378,60 +496,52 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     HIP_TRY(hipSetDevice(c->device));
     const hipStream_t s = c->stream;
     const uint32_t n = g->n;
-    if (stats) {
-        stats->iterations = 0;
-        stats->converged = 0;
-        stats->changed_last = 0;
-        stats->arcs_processed = 0;
-        stats->ms_rounds = 0;
-        stats->ms_total = 0;
-    }
-    // counters: one u64 per round, then the error word
-    HIP_TRY(c->counters.ensure(((size_t)max_iter + 2) * sizeof(u64)));
-    u64 *counters = c->counters.as<u64>();
-    uint32_t *err_dev = reinterpret_cast<uint32_t *>(counters + max_iter + 1);
-    HIP_TRY(launch_fill_u64(counters, 0, (size_t)max_iter + 2, s));
-    LPA_TRY(ensure_pinned(c, 16));
+    clear_stats(stats);
+    if (n == 0) return LPA_OK;
 
-    if (resume && n) {
-        HIP_TRY(launch_check_labels(labels, n, err_dev, s));
-    }
+    const size_t cwords = (size_t)max_iter * kCountWords + 1;
+    HIP_TRY(c->counters.ensure(cwords * sizeof(u64)));
+    u64 *counters = c->counters.as<u64>();
+    uint32_t *err_dev = reinterpret_cast<uint32_t *>(counters + (size_t)max_iter * kCountWords);
+    HIP_TRY(launch_fill_u64(counters, 0, cwords, s));
+    LPA_TRY(ensure_pinned(c, kCountWords + 16));
+    if (resume) HIP_TRY(launch_check_labels(labels, n, err_dev, s));
+
     Plan P;
-    if (n) LPA_TRY(prepare(c, g, P, err_dev, true));
-    HIP_TRY(c->labels_b.ensure((size_t)n * sizeof(uint32_t)));
-    uint32_t *A = labels, *B = c->labels_b.as<uint32_t>();
-    if (resume) {
-        HIP_TRY(launch_copy_u32(B, A, n, s));
-    } else {
-        HIP_TRY(launch_fill_u32_iota(A, B, n, s));
-    }
+    LPA_TRY(prepare(c, g, P, err_dev, true));
+    HIP_TRY(c->La.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(c->Lb.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(),
+                               resume ? labels : nullptr, n, s));
+
     const uint64_t thr = (uint64_t)std::floor(tol * (double)n);
     const bool weighted = g->w != nullptr;
     const HubState hs = hub_state(c);
-    const uint64_t voted_arcs = P.arcs[BIN_THREAD] + P.arcs[BIN_GROUP] + P.arcs[BIN_WAVE] + P.arcs[BIN_HUB];
+    const Bins &B = P.bins;
+    const uint64_t voted_arcs = B.arcs[BIN_THREAD] + B.arcs[BIN_GROUP] + B.arcs[BIN_WAVE] + B.arcs[BIN_HUB];
     if (!c->round_a) HIP_TRY(hipEventCreate(&c->round_a));
     if (!c->round_b) HIP_TRY(hipEventCreate(&c->round_b));
 
-    uint32_t *L_old = A, *L_new = B;
-    lpa_status st = LPA_OK;
+    uint32_t *L_old = c->La.as<uint32_t>(), *L_new = c->Lb.as<uint32_t>();
     uint32_t it = 0;
     int converged = 0;
     u64 changed = 0;
     double ms_rounds = 0;
-    for (uint32_t t = 1; t <= max_iter && n; ++t) {
+    for (uint32_t t = 1; t <= max_iter; ++t) {
         RoundArgs ra;
-        ra.g = make_graph(g);
+        ra.g = internal_graph(c, g);
         ra.L_old = L_old;
         ra.L_new = L_new;
+        ra.rowflag = c->rowflag.as<uint8_t>();
         ra.sw = c->opt.self_weight;
         ra.check = (t == 1);
-        ra.changed = counters + (t - 1);
+        ra.changed = counters + (size_t)(t - 1) * kCountWords;
         ra.err = err_dev;
+        const int first = (t == 1 && !resume) ? 1 : 0;
         HIP_TRY(hipEventRecord(c->round_a, s));
-        st = enqueue_round(c, P, ra, hs, weighted);
-        if (st != LPA_OK) break;
+        LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first));
         HIP_TRY(hipEventRecord(c->round_b, s));
-        HIP_TRY(hipMemcpyAsync(c->pinned, counters + (t - 1), sizeof(u64), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(c->pinned + 16, ra.changed, kCountWords * sizeof(u64), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (c->opt.profile) collect_profile(c);
@@ -439,11 +549,9 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
         ms_rounds += ms;
         const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
-        if (errbits) {
-            st = err_status(errbits);
-            break;
-        }
-        changed = c->pinned[0];
+        if (errbits) return err_status(errbits);
+        changed = 0;
+        for (int k = 0; k < kCountSlots; ++k) changed += c->pinned[16 + (size_t)k * kCountStride];
         it = t;
         if (stats) {
             if (stats->changed_per_iter && t <= stats->cap) stats->changed_per_iter[t - 1] = changed;
@@ -455,15 +563,22 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
             break;
         }
     }
-    if (st != LPA_OK) return st;
-    if (L_old != labels) HIP_TRY(launch_copy_u32(labels, L_old, n, s));
+    HIP_TRY(launch_scatter_labels(labels, c->old_of.as<uint32_t>(), L_old, n, s));
+    double q = 0;
+    uint64_t terms[4] = {0, 0, 0, 0};
+    if (c->opt.modularity) LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
+    if (errbits) return err_status(errbits);
     if (stats) {
         stats->iterations = it;
         stats->converged = converged;
         stats->changed_last = changed;
         stats->arcs_processed = voted_arcs * it;
         stats->ms_rounds = ms_rounds;
+        stats->modularity = q;
+        for (int i = 0; i < 4; ++i) stats->mod_terms[i] = terms[i];
         stats->ms_total =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
@@ -479,9 +594,11 @@ void lpa_default_options(lpa_options *opt) {
     opt->self_weight = 1;
     opt->thread_max = 8;
     opt->group_max = 32;
-    opt->wave_max = 256;
-    opt->chunk = 2048;
+    opt->wave_max = 128;
+    opt->wide_max = 512;
+    opt->merge_max = 512;
     opt->profile = 0;
+    opt->modularity = 0;
 }
 
 lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *opt) {
@@ -490,13 +607,13 @@ lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *
     lpa_options o;
     lpa_default_options(&o);
     if (opt) {
+        const lpa_options d = o;
         o = *opt;
-        lpa_options d;
-        lpa_default_options(&d);
         if (!o.thread_max) o.thread_max = d.thread_max;
         if (!o.group_max) o.group_max = d.group_max;
         if (!o.wave_max) o.wave_max = d.wave_max;
-        if (!o.chunk) o.chunk = d.chunk;
+        if (!o.wide_max) o.wide_max = d.wide_max;
+        if (!o.merge_max) o.merge_max = d.merge_max;
     }
     LPA_TRY(check_options(o));
     int ndev = 0;
@@ -540,54 +657,14 @@ lpa_status lpa_modularity(lpa_ctx *c, const lpa_csr *g, const uint32_t *labels, 
     if (terms) std::memset(terms, 0, 4 * sizeof(uint64_t));
     if (n == 0) return LPA_OK;
     HIP_TRY(c->counters.ensure(4 * sizeof(u64)));
-    u64 *counters = c->counters.as<u64>();
-    uint32_t *err_dev = reinterpret_cast<uint32_t *>(counters);
-    HIP_TRY(launch_fill_u64(counters, 0, 1, s));
+    uint32_t *err_dev = reinterpret_cast<uint32_t *>(c->counters.as<u64>());
+    HIP_TRY(launch_fill_u64(c->counters.as<u64>(), 0, 1, s));
     HIP_TRY(launch_check_labels(labels, n, err_dev, s));
     Plan P;
     LPA_TRY(prepare(c, g, P, err_dev, false));
-    const uint32_t nparts = 1024;
-    HIP_TRY(c->K.ensure((size_t)n * sizeof(u64)));
-    HIP_TRY(c->mod_sums.ensure(2 * sizeof(u64)));
-    HIP_TRY(c->partials.ensure(2 * nparts * sizeof(u64)));
-    HIP_TRY(launch_fill_u64(c->K.as<u64>(), 0, n, s));
-    HIP_TRY(launch_fill_u64(c->mod_sums.as<u64>(), 0, 2, s));
-    ModArgs ma;
-    ma.g = make_graph(g);
-    ma.labels = labels;
-    ma.K = c->K.as<u64>();
-    ma.sums = c->mod_sums.as<u64>();
-    ma.err = err_dev;
-    const uint32_t *order = c->order.as<uint32_t>();
-    HIP_TRY(launch_mod_small(ma, order + P.off[BIN_THREAD], P.cnt[BIN_THREAD] + P.cnt[BIN_GROUP], s));
-    HIP_TRY(launch_mod_wave(ma, order + P.off[BIN_WAVE], P.cnt[BIN_WAVE], s));
-    HIP_TRY(launch_mod_hub(ma, c->items.as<HubItem>(), P.n_items, s));
-    HIP_TRY(launch_mod_sumsq(c->K.as<u64>(), n, c->partials.as<u64>(), nparts, s));
-    std::vector<u64> parts(2 * nparts);
-    u64 sums[2];
-    uint32_t errbits = 0;
-    HIP_TRY(hipMemcpyAsync(parts.data(), c->partials.p, 2 * nparts * sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(sums, c->mod_sums.p, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&errbits, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (errbits) return err_status(errbits);
-    unsigned __int128 sk2 = 0;
-    for (uint32_t i = 0; i < nparts; ++i)
-        sk2 += ((unsigned __int128)parts[2 * i + 1] << 64) | (unsigned __int128)parts[2 * i];
-    const u64 two_m = sums[0], sigma_in = sums[1];
-    double q = 0.0;
-    if (two_m > 0) {
-        const double W = (double)two_m;
-        q = (double)sigma_in / W - (double)sk2 / (W * W);
-    }
-    *q_out = q;
-    if (terms) {
-        terms[0] = two_m;
-        terms[1] = sigma_in;
-        terms[2] = (u64)sk2;
-        terms[3] = (u64)(sk2 >> 64);
-    }
-    return LPA_OK;
+    HIP_TRY(c->La.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), nullptr, c->old_of.as<uint32_t>(), labels, n, s));
+    return modularity_internal(c, g, P, c->La.as<uint32_t>(), err_dev, q_out, terms);
 }
 
 lpa_status lpa_profile_get(lpa_ctx *c, lpa_kernel_prof *out, uint32_t cap, uint32_t *count) {
@@ -612,10 +689,12 @@ void lpa_destroy(lpa_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    DevBuf *bufs[] = {&c->labels_b, &c->order,    &c->blk_counts, &c->blk_arcs,  &c->small,     &c->counters,
-                      &c->hub_rows, &c->items,    &c->ritems,     &c->hub_vertex, &c->slab_off, &c->slab_mask,
-                      &c->touched_off, &c->tcount, &c->best,      &c->own_sum,   &c->own_seen,  &c->rowsum,
-                      &c->slab,     &c->touched,  &c->K,          &c->mod_sums,  &c->partials};
+    DevBuf *bufs[] = {&c->blk_counts, &c->blk_arcs, &c->small,    &c->old_of,    &c->new_of,      &c->rp2,
+                      &c->col2,       &c->w2,       &c->rowflag,  &c->La,        &c->Lb,          &c->counters,
+                      &c->items,      &c->ritems,   &c->slab_off, &c->slab_mask, &c->touched_off, &c->tcount,
+                      &c->best,       &c->own_sum,  &c->hflags,   &c->rowsum,    &c->slab,        &c->touched,
+                      &c->K,          &c->mod_sums, &c->partials, &c->cand,      &c->thr,         &c->item_lo,
+                      &c->mrows,      &c->slab_pending};
     for (DevBuf *b : bufs) b->release();
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

@@ -1,0 +1,897 @@
+// lpa_vote.hip -- the per-round vote kernels on the internal graph.
+//
+// Method (arXiv 2301.09125, Section 3.2): in every round each vertex adopts
+// the label with the largest total edge weight among its neighbours (plus a
+// self weight on its own label, the Section 3.1.2 self-loop), ties going to
+// the lowest label; rounds are synchronous (read L_old, write L_new).
+//
+// A vote is the max over candidate labels of the 64-bit key
+//     (tally << 32) | ~label,
+// which orders by tally first and, among equal tallies, prefers the lowest
+// label.  Tallies are u32 (weighted degrees >= 2^32 are rejected in round
+// 1), all accumulation is integer, so the result does not depend on the
+// order in which atomics land: the labels are deterministic.
+//
+// Bins (contiguous ranges of internal ids):
+//   vote_thread_k  1 <= d <= 8     one lane, registers, pairwise tally
+//   vote_group_k   d <= 32         16-lane group, 64-slot LDS table
+//   vote_wave_k    d <= 128        one wavefront, 256-slot LDS table
+//                  d <= 512        one wavefront, 1024-slot LDS table
+//   vote_hub_k     d > 512         one wavefront per 512-arc segment, rows
+//                                  finished by the merge kernels below
+// Hashtable slots are u64 (label << 32 | tally); EMPTY has the label field all
+// ones, a value no label takes (labels < n <= 2^32 - 2).  A label is claimed
+// with one 64-bit CAS carrying its first weight, later hits add to the low
+// half, so a slot never holds a label without its weight.
+//
+// Work that would serialise on one address is avoided: every vertex's own
+// label is tallied in registers (most neighbours hold it in late rounds),
+// wavefronts pre-sum their most frequent labels before touching a table,
+// and changed counts go to per-block partials spread over cache lines.
+// Every kernel loop is wavefront-uniform and uses no block barrier, so the
+// wavefronts of a block proceed independently.
+//
+// Round 1 from the unique initial labels needs no table for a row that lists
+// each neighbour once: every label then occurs once, its tally is that arc's
+// weight, and the vote is a plain max over the row.
+
+#include "lpa_device.h"
+
+namespace lpa {
+
+// Issue the loads of arcs k0 + j*STRIDE (j < A, below e) of one lane:
+// internal ids into u, weights into wt, bit j of `valid` set for loaded
+// arcs.  Nothing here waits for the data, so the loads of the next work item
+// can be in flight while the current one is processed.
+template <int A, int STRIDE>
+__device__ __forceinline__ void issue_arcs(const RoundArgs &a, uint64_t k0, uint64_t e, uint32_t (&u)[A],
+                                           uint32_t (&wt)[A], uint32_t &valid) {
+    const uint32_t *__restrict__ col = a.g.col;
+    const uint32_t *__restrict__ w = a.g.w;
+    valid = 0;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = k0 + (uint64_t)j * STRIDE;
+        u[j] = 0;
+        if (k < e) {
+            valid |= 1u << j;
+            u[j] = col[k];
+        }
+    }
+    if (w) {
+#pragma unroll
+        for (int j = 0; j < A; ++j) wt[j] = (valid >> j & 1u) ? w[k0 + (uint64_t)j * STRIDE] : 0u;
+    } else {
+#pragma unroll
+        for (int j = 0; j < A; ++j) wt[j] = (valid >> j) & 1u;
+    }
+}
+
+// Out-of-range ids raise ERR_COL once and are read as vertex 0, so no later
+// access leaves the arrays.
+template <int A>
+__device__ __forceinline__ void check_arcs(const RoundArgs &a, uint32_t (&u)[A]) {
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        bad |= u[j] >= a.g.n;
+        u[j] = u[j] >= a.g.n ? 0u : u[j];
+    }
+    if (bad) atomicOr(a.err, ERR_COL);
+}
+
+template <int A, int STRIDE>
+__device__ __forceinline__ void load_arcs(const RoundArgs &a, uint64_t k0, uint64_t e, uint32_t (&u)[A],
+                                          uint32_t (&wt)[A], uint32_t &valid) {
+    issue_arcs<A, STRIDE>(a, k0, e, u, wt, valid);
+    check_arcs<A>(a, u);
+}
+
+template <int A>
+__device__ __forceinline__ void gather_labels(const RoundArgs &a, const uint32_t (&u)[A], uint32_t valid,
+                                              uint32_t (&lab)[A]) {
+    const uint32_t *__restrict__ L = a.L_old;
+#pragma unroll
+    for (int j = 0; j < A; ++j) lab[j] = (valid >> j & 1u) ? L[u[j]] : 0xFFFFFFFFu;
+}
+
+// Split loaded arcs into the own-label tally and the bit set `rem` of arcs
+// whose label must go through a table.
+template <int A>
+__device__ __forceinline__ void split_own(const uint32_t (&lab)[A], const uint32_t (&wt)[A], uint32_t valid,
+                                          uint32_t own, u64 &own_w, uint32_t &own_hit, uint32_t &rem, u64 &rs) {
+#pragma unroll
+    for (int j = 0; j < A; ++j)
+        if (valid >> j & 1u) {
+            rs += wt[j];
+            if (lab[j] == own) {
+                own_w += wt[j];
+                own_hit = 1;
+            } else {
+                rem |= 1u << j;
+            }
+        }
+}
+
+// Wavefront pre-aggregation: up to NPEEL times, take the first remaining
+// label of the lowest lane that has one, sum the weights of every remaining
+// arc of the wavefront with that label and insert the sum once.  All 64
+// lanes call this together.
+template <int A, int NPEEL>
+__device__ __forceinline__ void wave_peel(u64 *T, uint32_t mask, const uint32_t (&lab)[A],
+                                          const uint32_t (&wt)[A], uint32_t &rem) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < NPEEL; ++p) {
+        const u64 m = __ballot(rem != 0);
+        if (!m) return;
+        const int lead = __ffsll((long long)m) - 1;
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = A - 1; j >= 0; --j)
+            if (rem >> j & 1u) mine = lab[j];
+        const uint32_t L = __shfl(mine, lead, 64);
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < A; ++j)
+            if ((rem >> j & 1u) && lab[j] == L) {
+                s += wt[j];
+                rem &= ~(1u << j);
+            }
+        s = wave_sum(s);
+        if ((int)lane == lead) lds_insert(T, mask, L, s);
+    }
+}
+
+// ---------------------------------------------------------- one lane --
+
+__global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, uint32_t cnt) {
+    constexpr int D = kThreadMaxCap;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t stride = gridDim.x * 256;
+    u64 wchg = 0;
+    for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < cnt; base += stride) {
+        const uint32_t i = base + lane;
+        bool ch = false;
+        if (i < cnt) {
+            const uint32_t v = lo + i;
+            const uint64_t b = a.g.rp[v];
+            const uint64_t e = a.g.rp[v + 1];
+            const uint32_t own = a.L_old[v];
+            uint32_t u[D], lab[D], wt[D], tl[D];
+            uint32_t valid = 0;
+            load_arcs<D, 1>(a, b, e, u, wt, valid);
+            gather_labels<D>(a, u, valid, lab);
+            u64 rs = a.sw;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                rs += wt[j];
+                tl[j] = wt[j] + (lab[j] == own ? a.sw : 0u);
+            }
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+#pragma unroll
+                for (int k = j + 1; k < D; ++k)
+                    if (lab[j] == lab[k]) {
+                        tl[j] += wt[k];
+                        tl[k] += wt[j];
+                    }
+            u64 best = a.sw ? vote_key(own, a.sw) : 0ull;
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if (valid >> j & 1u) best = umax64(best, vote_key(lab[j], tl[j]));
+            const uint32_t nl = best ? ~(uint32_t)best : own;
+            a.L_new[v] = nl;
+            ch = nl != own;
+            if (a.check && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+        }
+        wchg += __popcll(__ballot(ch));
+    }
+    block_count(lane == 0 ? wchg : 0, a.changed);
+}
+
+// ---------------------------------------------- group / wavefront per row --
+
+// G lanes per vertex (G divides 64) with a CAP-slot LDS table per group; each
+// lane holds up to A = CAP / (2G) arcs.  A group's table is only touched by
+// lanes of its own wavefront.
+template <int G, int CAP, bool FIRST>
+__global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, uint32_t cnt) {
+    constexpr int GPB = 256 / G;  // groups per block
+    constexpr int GPW = 64 / G;   // groups per wavefront
+    constexpr int A = CAP / (2 * G);
+    __shared__ u64 table[GPB * CAP];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t gl = threadIdx.x & (G - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 *T = table + (threadIdx.x / G) * CAP;
+    for (uint32_t s = gl; s < CAP; s += G) T[s] = EMPTY_SLOT;
+    wave_sync();
+    u64 wchg = 0;
+    const uint32_t stride = gridDim.x * GPB;
+    for (uint32_t base = blockIdx.x * GPB + wave * GPW; base < cnt; base += stride) {
+        const uint32_t idx = base + lane / G;
+        const bool act = idx < cnt;
+        const uint32_t v = lo + (act ? idx : 0);
+        uint64_t b = 0, e = 0;
+        uint32_t own = 0;
+        if (act) {
+            b = a.g.rp[v];
+            e = a.g.rp[v + 1];
+            own = a.L_old[v];
+        }
+        uint32_t u[A], lab[A], wt[A];
+        uint32_t valid = 0;
+        load_arcs<A, G>(a, b + gl, e, u, wt, valid);
+        gather_labels<A>(a, u, valid, lab);
+        u64 own_w = 0, rs = 0;
+        uint32_t own_hit = 0, rem = 0;
+        split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
+        const bool direct = FIRST && act && (a.rowflag[v] & ROW_DISTINCT);
+        uint32_t S = next_pow2(2u * (uint32_t)(e - b));
+        S = S < (uint32_t)G ? (uint32_t)G : (S > (uint32_t)CAP ? (uint32_t)CAP : S);
+        const uint32_t mask = S - 1;
+        u64 best = 0;
+        if (direct) {
+#pragma unroll
+            for (int j = 0; j < A; ++j)
+                if (rem >> j & 1u) best = umax64(best, vote_key(lab[j], wt[j]));
+        } else {
+#pragma unroll
+            for (int j = 0; j < A; ++j)
+                if (rem >> j & 1u) lds_insert(T, mask, lab[j], wt[j]);
+        }
+        wave_sync();
+        if (!direct) {
+            for (uint32_t s = gl; s < S; s += G) {
+                const u64 x = T[s];
+                if (x != EMPTY_SLOT) {
+                    best = umax64(best, slot_key(x));
+                    T[s] = EMPTY_SLOT;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            best = umax64(best, __shfl_xor(best, off, 64));
+            own_w += __shfl_xor(own_w, off, 64);
+            own_hit |= __shfl_xor(own_hit, off, 64);
+            rs += __shfl_xor(rs, off, 64);
+        }
+        bool ch = false;
+        if (act && gl == 0) {
+            if (own_hit || a.sw) best = umax64(best, vote_key(own, own_w + a.sw));
+            const uint32_t nl = best ? ~(uint32_t)best : own;
+            a.L_new[v] = nl;
+            ch = nl != own;
+            if (a.check && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+        }
+        wchg += __popcll(__ballot(ch));
+        wave_sync();
+    }
+    block_count(lane == 0 ? wchg : 0, a.changed);
+}
+
+// One wavefront per row of at most A*64 arcs, A arcs per lane, SLOTS LDS
+// slots; the own label and two peeled labels are summed in registers before
+// the table.  The next row's arcs are loaded while the current one is voted.
+template <bool FIRST, int A, int SLOTS>
+__global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uint32_t cnt) {
+    __shared__ u64 table[4 * SLOTS];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 *T = table + wave * SLOTS;
+    for (uint32_t s = lane; s < (uint32_t)SLOTS; s += 64) T[s] = EMPTY_SLOT;
+    wave_sync();
+    u64 wchg = 0;
+    const uint32_t stride = gridDim.x * 4;
+    uint32_t i = blockIdx.x * 4 + wave;
+    uint64_t b = 0, e = 0;
+    uint32_t u[A], wt[A], valid = 0;
+    if (i < cnt) {
+        b = a.g.rp[lo + i];
+        e = a.g.rp[lo + i + 1];
+        issue_arcs<A, 64>(a, b + lane, e, u, wt, valid);
+    }
+    while (i < cnt) {
+        const uint32_t v = lo + i;
+        const uint32_t inext = i + stride;
+        uint64_t nb = 0, ne = 0;
+        uint32_t nu[A], nwt[A], nvalid = 0;
+        if (inext < cnt) {
+            nb = a.g.rp[lo + inext];
+            ne = a.g.rp[lo + inext + 1];
+            issue_arcs<A, 64>(a, nb + lane, ne, nu, nwt, nvalid);
+        }
+        check_arcs<A>(a, u);
+        const uint32_t own = a.L_old[v];
+        uint32_t lab[A];
+        gather_labels<A>(a, u, valid, lab);
+        u64 own_w = 0, rs = 0;
+        uint32_t own_hit = 0, rem = 0;
+        split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
+        const bool direct = FIRST && (a.rowflag[v] & ROW_DISTINCT);
+        uint32_t S = next_pow2(2u * (uint32_t)(e - b));
+        S = S < 64u ? 64u : (S > (uint32_t)SLOTS ? (uint32_t)SLOTS : S);
+        const uint32_t mask = S - 1;
+        u64 best = 0;
+        if (direct) {
+#pragma unroll
+            for (int j = 0; j < A; ++j)
+                if (rem >> j & 1u) best = umax64(best, vote_key(lab[j], wt[j]));
+        } else if (__ballot(rem != 0)) {  // some label other than the own one
+            wave_peel<A, 2>(T, mask, lab, wt, rem);
+#pragma unroll
+            for (int j = 0; j < A; ++j)
+                if (rem >> j & 1u) lds_insert(T, mask, lab[j], wt[j]);
+            wave_sync();
+            for (uint32_t s = lane; s < S; s += 64) {
+                const u64 x = T[s];
+                if (x != EMPTY_SLOT) {
+                    best = umax64(best, slot_key(x));
+                    T[s] = EMPTY_SLOT;
+                }
+            }
+        }
+        best = wave_max64(best);
+        own_w = wave_sum(own_w);
+        own_hit = __ballot(own_hit != 0) != 0;
+        if (a.check) rs = wave_sum(rs);
+        if (lane == 0) {
+            if (own_hit || a.sw) best = umax64(best, vote_key(own, own_w + a.sw));
+            const uint32_t nl = best ? ~(uint32_t)best : own;
+            a.L_new[v] = nl;
+            wchg += nl != own;
+            if (a.check && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+        }
+        wave_sync();
+        i = inext;
+        b = nb;
+        e = ne;
+        valid = nvalid;
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+            u[j] = nu[j];
+            wt[j] = nwt[j];
+        }
+    }
+    block_count(lane == 0 ? wchg : 0, a.changed);
+}
+
+hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int, int grid_cap, hipStream_t s) {
+    if (cnt == 0) return hipSuccess;
+    vote_thread_k<<<grid_for(cnt, 256, grid_cap), 256, 0, s>>>(a, lo, cnt);
+    return hipGetLastError();
+}
+hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int grid_cap,
+                             hipStream_t s) {
+    if (cnt == 0) return hipSuccess;
+    const unsigned g = grid_for(cnt, 256 / kGroupLanes, grid_cap);
+    if (first)
+        vote_group_k<kGroupLanes, kGroupSlots, true><<<g, 256, 0, s>>>(a, lo, cnt);
+    else
+        vote_group_k<kGroupLanes, kGroupSlots, false><<<g, 256, 0, s>>>(a, lo, cnt);
+    return hipGetLastError();
+}
+hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int grid_cap,
+                            hipStream_t s) {
+    if (cnt == 0) return hipSuccess;
+    const unsigned g = grid_for(cnt, 4, grid_cap);
+    constexpr int AS = kWaveArcsSmall / 64, AW = kWaveArcs / 64;
+    if (wide) {
+        if (first)
+            vote_wave_k<true, AW, kWaveSlots><<<g, 256, 0, s>>>(a, lo, cnt);
+        else
+            vote_wave_k<false, AW, kWaveSlots><<<g, 256, 0, s>>>(a, lo, cnt);
+    } else {
+        if (first)
+            vote_wave_k<true, AS, kWaveSlotsSmall><<<g, 256, 0, s>>>(a, lo, cnt);
+        else
+            vote_wave_k<false, AS, kWaveSlotsSmall><<<g, 256, 0, s>>>(a, lo, cnt);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- long rows --
+//
+// A row longer than 512 arcs is split into 512-arc segments, one wavefront
+// each.  Per round:
+//   vote_hub_k     every segment tallies its labels in an LDS table and
+//                  reports its kTopK heaviest (label, tally) pairs plus thr,
+//                  the tally of its (kTopK+1)-th label: no label it did not
+//                  report reaches more than thr in this segment.  Round 1
+//                  rows that list each neighbour once report just their max
+//                  key (every tally is one arc's weight).  HUB_BIG rows go
+//                  straight to the slab merge below.
+//   hub_merge_*    per row, lower bound LB(x) = reported tallies of x, upper
+//                  bound UB(x) = LB(x) + sum of thr over the segments that
+//                  did not report x, and any label nobody reported is below
+//                  T = sum of all thr.  The leader x* (max key over LB and the
+//                  row's exact own-label tally) is the exact winner when
+//                  every other label's best possible key is below x*'s
+//                  guaranteed key and T is below x*'s tally.  Otherwise the
+//                  row is marked HUB_FALLBACK.
+//   hub_fallback_k the segments of HUB_FALLBACK rows merge their exact
+//                  tables in the row's global slab (open addressing, 2 x
+//                  degree slots); hub_reduce_k takes the max over the slots
+//                  they claimed; hub_final_k picks the winner of every row
+//                  decided through best[] and resets the per-round state.
+
+// Merge (lab, cnt) into a row's global slab.  Returns the slot index if this
+// call claimed a new slot, else kNone.
+__device__ __forceinline__ uint32_t slab_insert(u64 *S, uint32_t mask, uint32_t lab, uint32_t cnt) {
+    uint32_t h = hmix(lab) & mask;
+    const u64 desired = ((u64)lab << 32) | cnt;
+    for (;;) {
+        const u64 prev = atomicCAS(&S[h], EMPTY_SLOT, desired);
+        if (prev == EMPTY_SLOT) return h;
+        if ((uint32_t)(prev >> 32) == lab) {
+            atomicAdd(&S[h], (u64)cnt);
+            return kNone;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Move the S-slot LDS table of one wavefront into row h's slab, recording
+// per non-empty slot the slab slot it claimed (or kNone) in the row's
+// touched list; the entries are reserved with one atomic per wavefront.
+__device__ __forceinline__ void flush_to_slab(u64 *T, uint32_t S, const HubState &hs, uint32_t h) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t ne = 0;
+    for (uint32_t s = lane; s < S; s += 64) ne += T[s] != EMPTY_SLOT;
+    uint32_t pre = ne;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(pre, off, 64);
+        if ((int)lane >= off) pre += y;
+    }
+    const uint32_t total = __shfl(pre, 63, 64);
+    pre -= ne;
+    uint32_t tbase = 0;
+    if (lane == 0 && total) tbase = atomicAdd(&hs.tcount[h], total);
+    tbase = __shfl(tbase, 0, 64);
+    u64 *slab = hs.slab + hs.slab_off[h];
+    const uint32_t smask = hs.slab_mask[h];
+    uint32_t *tl = hs.touched + hs.touched_off[h] + tbase + pre;
+    for (uint32_t s = lane; s < S; s += 64) {
+        const u64 x = T[s];
+        if (x != EMPTY_SLOT) {
+            *tl++ = slab_insert(slab, smask, (uint32_t)(x >> 32), (uint32_t)x);
+            T[s] = EMPTY_SLOT;
+        }
+    }
+}
+
+// Report the kTopK heaviest entries of the S-slot table (clearing it) to
+// cand[it * kTopK ...] and the (kTopK+1)-th tally to thr[it].  Keys are
+// unique (one slot per label), so round k takes the largest key below the
+// previous round's.
+__device__ __forceinline__ void report_topk(u64 *T, uint32_t S, const HubState &hs, uint32_t it) {
+    constexpr int J = kWaveSlots / 64;
+    const uint32_t lane = threadIdx.x & 63;
+    u64 keys[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t s = lane + 64u * j;
+        keys[j] = 0;
+        if (s < S) {
+            const u64 x = T[s];
+            if (x != EMPTY_SLOT) {
+                keys[j] = slot_key(x);
+                T[s] = EMPTY_SLOT;
+            }
+        }
+    }
+    u64 mine = 0, prev = ~0ull;
+    uint32_t thr = 0;
+#pragma unroll 1
+    for (int k = 0; k <= kTopK && S; ++k) {
+        u64 lm = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (keys[j] < prev) lm = umax64(lm, keys[j]);
+        const u64 wm = wave_max64(lm);
+        if (k == kTopK) {
+            thr = (uint32_t)(wm >> 32);
+            break;
+        }
+        if ((int)lane == k) mine = wm;
+        if (wm == 0) break;
+        prev = wm;
+    }
+    if (lane == 0) hs.thr[it] = thr;
+    if (lane < (uint32_t)kTopK)
+        hs.cand[(u64)it * kTopK + lane] = mine ? (((u64)(uint32_t)~(uint32_t)mine << 32) | (mine >> 32)) : EMPTY_SLOT;
+}
+
+// Round 1 rows that list each neighbour once: every tally is one arc's
+// weight, so a segment only needs its max key (no table, no LDS).  Rows
+// with HUB_REPEATS are left to vote_hub_k.
+__global__ __launch_bounds__(256) void vote_hub_direct_k(RoundArgs a, const HubItem *__restrict__ items,
+                                                         uint32_t count, HubState hs) {
+    constexpr int A = kWaveArcs / 64;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
+        const HubItem item = items[it];
+        const uint32_t h = item.r;
+        if (hs.flags[h] & HUB_REPEATS) continue;  // uniform over the wavefront
+        uint32_t u[A], wt[A], valid = 0, lab[A];
+        load_arcs<A, 64>(a, item.b0 + lane, item.b1, u, wt, valid);
+        gather_labels<A>(a, u, valid, lab);
+        const uint32_t own = a.L_old[h];
+        u64 own_w = 0, rs = 0;
+        uint32_t own_hit = 0, rem = 0;
+        split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
+        u64 best = 0;
+#pragma unroll
+        for (int j = 0; j < A; ++j)
+            if (rem >> j & 1u) best = umax64(best, vote_key(lab[j], wt[j]));
+        best = wave_max64(best);
+        own_w = wave_sum(own_w);
+        own_hit = __ballot(own_hit != 0) != 0;
+        rs = wave_sum(rs);
+        if (lane == 0) {
+            if (best) atomicMax(&hs.best[h], best);
+            if (own_w) atomicAdd(&hs.own_sum[h], own_w);
+            if (own_hit) atomicOr(&hs.flags[h], HUB_OWN_SEEN);
+            if (a.check) atomicAdd(&hs.rowsum[h], rs);
+        }
+    }
+}
+
+// Every other round (and round-1 rows with HUB_REPEATS): one LDS table per
+// wavefront and segment, reported as top-K, or merged into the slab for
+// HUB_BIG rows.  The next segment's arcs are loaded while the current one
+// is tallied.
+template <bool FIRST>
+__global__ __launch_bounds__(256) void vote_hub_k(RoundArgs a, const HubItem *__restrict__ items, uint32_t count,
+                                                  HubState hs) {
+    constexpr int A = kWaveArcs / 64;
+    __shared__ u64 table[4 * kWaveSlots];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 *T = table + wave * kWaveSlots;
+    for (uint32_t s = lane; s < kWaveSlots; s += 64) T[s] = EMPTY_SLOT;
+    wave_sync();
+    const uint32_t stride = gridDim.x * 4;
+    uint32_t it = blockIdx.x * 4 + wave;
+    HubItem item{0, 0, 0, 0};
+    uint32_t u[A], wt[A], valid = 0;
+    if (it < count) {
+        item = items[it];
+        issue_arcs<A, 64>(a, item.b0 + lane, item.b1, u, wt, valid);
+    }
+    while (it < count) {
+        const uint32_t nit = it + stride;
+        HubItem nitem{0, 0, 0, 0};
+        uint32_t nu[A], nwt[A], nvalid = 0;
+        if (nit < count) {
+            nitem = items[nit];
+            issue_arcs<A, 64>(a, nitem.b0 + lane, nitem.b1, nu, nwt, nvalid);
+        }
+        const uint32_t h = item.r;
+        const uint32_t flags = hs.flags[h];
+        if (!FIRST || (flags & HUB_REPEATS)) {
+            check_arcs<A>(a, u);
+            const uint32_t own = a.L_old[h];
+            uint32_t lab[A];
+            gather_labels<A>(a, u, valid, lab);
+            u64 own_w = 0, rs = 0;
+            uint32_t own_hit = 0, rem = 0;
+            split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
+            uint32_t S = next_pow2(2u * (uint32_t)(item.b1 - item.b0));
+            S = S < 64u ? 64u : (S > (uint32_t)kWaveSlots ? (uint32_t)kWaveSlots : S);
+            const uint32_t mask = S - 1;
+            const bool any = __ballot(rem != 0) != 0;
+            if (any) {
+                if (!FIRST) wave_peel<A, 2>(T, mask, lab, wt, rem);
+#pragma unroll
+                for (int j = 0; j < A; ++j)
+                    if (rem >> j & 1u) lds_insert(T, mask, lab[j], wt[j]);
+                wave_sync();
+            }
+            if (flags & HUB_BIG) {
+                if (any) {
+                    flush_to_slab(T, S, hs, h);
+                    if (lane == 0) atomicOr(hs.pending, 1u);
+                }
+            } else {
+                report_topk(T, any ? S : 0, hs, it);
+            }
+            own_w = wave_sum(own_w);
+            own_hit = __ballot(own_hit != 0) != 0;
+            if (a.check) rs = wave_sum(rs);
+            if (lane == 0) {
+                if (own_w) atomicAdd(&hs.own_sum[h], own_w);
+                if (own_hit) atomicOr(&hs.flags[h], HUB_OWN_SEEN);
+                if (a.check) atomicAdd(&hs.rowsum[h], rs);
+            }
+            wave_sync();
+        }
+        it = nit;
+        item = nitem;
+        valid = nvalid;
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+            u[j] = nu[j];
+            wt[j] = nwt[j];
+        }
+    }
+}
+
+// Second pass over the segments of rows the merge could not decide: exact
+// tables merged through the slab (own-label tallies are already counted).
+__global__ __launch_bounds__(256) void hub_fallback_k(RoundArgs a, const HubItem *__restrict__ items,
+                                                      uint32_t count, HubState hs) {
+    if (!*hs.pending) return;  // no row fell back this round
+    constexpr int A = kWaveArcs / 64;
+    __shared__ u64 table[4 * kWaveSlots];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 *T = table + wave * kWaveSlots;
+    for (uint32_t s = lane; s < kWaveSlots; s += 64) T[s] = EMPTY_SLOT;
+    wave_sync();
+    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
+        const HubItem item = items[it];
+        const uint32_t h = item.r;
+        if (!(hs.flags[h] & HUB_FALLBACK)) continue;  // uniform over the wavefront
+        const uint32_t own = a.L_old[h];
+        uint32_t u[A], lab[A], wt[A];
+        uint32_t valid = 0;
+        load_arcs<A, 64>(a, item.b0 + lane, item.b1, u, wt, valid);
+        gather_labels<A>(a, u, valid, lab);
+        u64 own_w = 0, rs = 0;
+        uint32_t own_hit = 0, rem = 0;
+        split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
+        uint32_t S = next_pow2(2u * (uint32_t)(item.b1 - item.b0));
+        S = S < 64u ? 64u : (S > (uint32_t)kWaveSlots ? (uint32_t)kWaveSlots : S);
+        const uint32_t mask = S - 1;
+        wave_peel<A, 2>(T, mask, lab, wt, rem);
+#pragma unroll
+        for (int j = 0; j < A; ++j)
+            if (rem >> j & 1u) lds_insert(T, mask, lab[j], wt[j]);
+        wave_sync();
+        flush_to_slab(T, S, hs, h);
+        wave_sync();
+    }
+}
+
+// Add one report (label, tally, its segment's thr) to a merge table of
+// mask+1 slots: keys, lower bounds LB and sums of reporting segments' thr.
+__device__ __forceinline__ void merge_insert(uint32_t *mk, uint32_t *mlb, uint32_t *mtr, uint32_t mask, uint32_t lab,
+                                             uint32_t c, uint32_t t) {
+    uint32_t h = hmix(lab) & mask;
+    for (;;) {
+        const uint32_t prev = atomicCAS(&mk[h], kNone, lab);
+        if (prev == kNone || prev == lab) {
+            atomicAdd(&mlb[h], c);
+            atomicAdd(&mtr[h], t);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// One wavefront per row of at most kMergeWaveSegs segments.
+__global__ __launch_bounds__(256) void hub_merge_wave_k(RoundArgs a, HubState hs, const uint32_t *__restrict__ rows,
+                                                        uint32_t count, int first) {
+    constexpr uint32_t MS = 2 * kMergeWaveSegs * kTopK;  // at most half full
+    __shared__ uint32_t mkey[4][MS], mlb[4][MS], mtr[4][MS];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t *mk = mkey[wave], *lb = mlb[wave], *tr = mtr[wave];
+    for (uint32_t s = lane; s < MS; s += 64) {
+        mk[s] = kNone;
+        lb[s] = 0;
+        tr[s] = 0;
+    }
+    wave_sync();
+    u64 wchg = 0;
+    for (uint32_t i = blockIdx.x * 4 + wave; i < count; i += gridDim.x * 4) {
+        const uint32_t h = rows[i];
+        const uint32_t flags = hs.flags[h];
+        if (first && !(flags & HUB_REPEATS)) continue;  // decided through best[]
+        const uint32_t lo = hs.item_lo[h], ns = hs.item_lo[h + 1] - lo;
+        const u64 T = wave_sum((u64)(lane < ns ? hs.thr[lo + lane] : 0u));
+        for (uint32_t e = lane; e < ns * kTopK; e += 64) {
+            const u64 x = hs.cand[(u64)lo * kTopK + e];
+            if (x != EMPTY_SLOT) merge_insert(mk, lb, tr, MS - 1, (uint32_t)(x >> 32), (uint32_t)x, hs.thr[lo + e / kTopK]);
+        }
+        wave_sync();
+        const uint32_t own = a.L_old[h];
+        u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(own, hs.own_sum[h] + a.sw) : 0ull;
+        for (uint32_t s = lane; s < MS; s += 64)
+            if (mk[s] != kNone) xkey = umax64(xkey, vote_key(mk[s], lb[s]));
+        xkey = wave_max64(xkey);
+        const uint32_t xs = ~(uint32_t)xkey;
+        const u64 V = xkey >> 32;
+        bool bad = false;
+        for (uint32_t s = lane; s < MS; s += 64) {
+            const uint32_t lab = mk[s];
+            if (lab != kNone) {
+                if (lab != xs && vote_key(lab, (u64)lb[s] + T - tr[s]) >= xkey) bad = true;
+                mk[s] = kNone;
+                lb[s] = 0;
+                tr[s] = 0;
+            }
+        }
+        bad |= (T > 0 && T >= V);
+        const bool decided = __ballot(bad) == 0;
+        if (lane == 0) {
+            if (decided) {
+                const uint32_t nl = xkey ? xs : own;
+                a.L_new[h] = nl;
+                wchg += nl != own;
+            } else {
+                atomicOr(&hs.flags[h], HUB_FALLBACK);
+                atomicOr(hs.pending, 1u);
+            }
+        }
+        wave_sync();
+    }
+    block_count(lane == 0 ? wchg : 0, a.changed);
+}
+
+// One 256-thread block per row of kMergeWaveSegs+1 .. kMergeBlockSegs segments.
+__global__ __launch_bounds__(256) void hub_merge_block_k(RoundArgs a, HubState hs, const uint32_t *__restrict__ rows,
+                                                         uint32_t count, int first) {
+    constexpr uint32_t MS = kMergeBlockSlots;
+    __shared__ uint32_t mk[MS], lb[MS], tr[MS];
+    __shared__ BlockRed R;
+    for (uint32_t s = threadIdx.x; s < MS; s += 256) {
+        mk[s] = kNone;
+        lb[s] = 0;
+        tr[s] = 0;
+    }
+    __syncthreads();
+    u64 bchg = 0;
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint32_t h = rows[i];
+        const uint32_t flags = hs.flags[h];
+        if (first && !(flags & HUB_REPEATS)) continue;  // uniform over the block
+        const uint32_t lo = hs.item_lo[h], ns = hs.item_lo[h + 1] - lo;
+        u64 T = 0, z1 = 0, z2 = 0;
+        uint32_t zo = 0;
+        for (uint32_t sgi = threadIdx.x; sgi < ns; sgi += 256) T += hs.thr[lo + sgi];
+        for (uint32_t e = threadIdx.x; e < ns * kTopK; e += 256) {
+            const u64 x = hs.cand[(u64)lo * kTopK + e];
+            if (x != EMPTY_SLOT) merge_insert(mk, lb, tr, MS - 1, (uint32_t)(x >> 32), (uint32_t)x, hs.thr[lo + e / kTopK]);
+        }
+        block_reduce(R, z1, T, z2, zo);  // T summed, includes a barrier
+        const uint32_t own = a.L_old[h];
+        u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(own, hs.own_sum[h] + a.sw) : 0ull;
+        for (uint32_t s = threadIdx.x; s < MS; s += 256)
+            if (mk[s] != kNone) xkey = umax64(xkey, vote_key(mk[s], lb[s]));
+        __syncthreads();
+        u64 z3 = 0, z4 = 0;
+        block_reduce(R, xkey, z3, z4, zo);
+        const uint32_t xs = ~(uint32_t)xkey;
+        const u64 V = xkey >> 32;
+        uint32_t bad = 0;
+        for (uint32_t s = threadIdx.x; s < MS; s += 256) {
+            const uint32_t lab = mk[s];
+            if (lab != kNone) {
+                if (lab != xs && vote_key(lab, (u64)lb[s] + T - tr[s]) >= xkey) bad = 1;
+                mk[s] = kNone;
+                lb[s] = 0;
+                tr[s] = 0;
+            }
+        }
+        bad |= (T > 0 && T >= V) ? 1u : 0u;
+        bad = __syncthreads_or((int)bad);
+        if (threadIdx.x == 0) {
+            if (!bad) {
+                const uint32_t nl = xkey ? xs : own;
+                a.L_new[h] = nl;
+                bchg += nl != own;
+            } else {
+                atomicOr(&hs.flags[h], HUB_FALLBACK);
+                atomicOr(hs.pending, 1u);
+            }
+        }
+        __syncthreads();
+    }
+    block_count(threadIdx.x == 0 ? bchg : 0, a.changed);
+}
+
+// Phase 2: max key over the slab slots claimed by a row, clearing them for
+// the next round.  One block per item of <= 2048 touched-list positions.
+__global__ __launch_bounds__(256) void hub_reduce_k(HubState hs, const ReduceItem *__restrict__ items,
+                                                    uint32_t count) {
+    __shared__ BlockRed R;
+    if (!*hs.pending) return;  // no slab was used this round
+    for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+        const ReduceItem r = items[it];
+        const uint32_t t1 = min(r.t1, hs.tcount[r.hub]);
+        if (r.t0 >= t1) continue;  // uniform over the block
+        u64 *slab = hs.slab + hs.slab_off[r.hub];
+        const uint32_t *tlist = hs.touched + hs.touched_off[r.hub];
+        u64 best = 0, z0 = 0, z1 = 0;
+        uint32_t z2 = 0;
+        for (uint32_t p = r.t0 + threadIdx.x; p < t1; p += 256) {
+            const uint32_t s = tlist[p];
+            if (s != kNone) {
+                best = umax64(best, slot_key(slab[s]));
+                slab[s] = EMPTY_SLOT;
+            }
+        }
+        block_reduce(R, best, z0, z1, z2);
+        if (threadIdx.x == 0 && best) atomicMax(&hs.best[r.hub], best);
+        __syncthreads();
+    }
+}
+
+// Phase 3: one lane per long row.  Rows decided through best[] (round-1
+// direct rows, HUB_BIG rows, HUB_FALLBACK rows) pick their winner here; every
+// row's per-round state is reset.
+__global__ __launch_bounds__(256) void hub_final_k(RoundArgs a, HubState hs, uint32_t count, int first) {
+    const uint32_t lane = threadIdx.x & 63;
+    u64 wchg = 0;
+    for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < count; base += gridDim.x * 256) {
+        const uint32_t i = base + lane;
+        bool ch = false;
+        if (i < count) {
+            const uint32_t f = hs.flags[i];
+            const bool via_best = (first && !(f & HUB_REPEATS)) || (f & (HUB_BIG | HUB_FALLBACK));
+            if (via_best) {
+                const uint32_t own = a.L_old[i];
+                u64 best = hs.best[i];
+                if ((f & HUB_OWN_SEEN) || a.sw) best = umax64(best, vote_key(own, hs.own_sum[i] + a.sw));
+                const uint32_t nl = best ? ~(uint32_t)best : own;
+                a.L_new[i] = nl;
+                ch = nl != own;
+            }
+            if (a.check && hs.rowsum[i] + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+            hs.best[i] = 0;
+            hs.own_sum[i] = 0;
+            hs.flags[i] = f & (HUB_REPEATS | HUB_BIG);
+            hs.tcount[i] = 0;
+            hs.rowsum[i] = 0;
+        }
+        wchg += __popcll(__ballot(ch));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *hs.pending = 0;
+    block_count(lane == 0 ? wchg : 0, a.changed);
+}
+
+hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
+                           int first, int grid_cap, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const unsigned g = grid_for(count, 4, grid_cap);
+    if (first) {
+        vote_hub_direct_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hs);
+        vote_hub_k<true><<<g, 256, 0, s>>>(a, items, count, hs);
+    } else {
+        vote_hub_k<false><<<g, 256, 0, s>>>(a, items, count, hs);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_hub_merge(const RoundArgs &a, const HubState &hs, const uint32_t *rows, uint32_t count,
+                            int per_block, int first, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    if (per_block)
+        hub_merge_block_k<<<grid_for(count, 1, 512), 256, 0, s>>>(a, hs, rows, count, first);
+    else
+        hub_merge_wave_k<<<grid_for(count, 4, 2048), 256, 0, s>>>(a, hs, rows, count, first);
+    return hipGetLastError();
+}
+hipError_t launch_hub_fallback(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
+                               int grid_cap, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hub_fallback_k<<<grid_for(count, 4, grid_cap), 256, 0, s>>>(a, items, count, hs);
+    return hipGetLastError();
+}
+hipError_t launch_hub_reduce(const HubState &hs, const ReduceItem *items, uint32_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hub_reduce_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(hs, items, count);
+    return hipGetLastError();
+}
+hipError_t launch_hub_final(const RoundArgs &a, const HubState &hs, uint32_t count, int first, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hub_final_k<<<grid_for(count, 256, 1024), 256, 0, s>>>(a, hs, count, first);
+    return hipGetLastError();
+}
+
+}  // namespace lpa

@@ -38,13 +38,15 @@ class _Csr(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("self_weight", ctypes.c_uint32), ("thread_max", ctypes.c_uint32),
                 ("group_max", ctypes.c_uint32), ("wave_max", ctypes.c_uint32),
-                ("chunk", ctypes.c_uint32), ("profile", ctypes.c_uint32)]
+                ("wide_max", ctypes.c_uint32), ("merge_max", ctypes.c_uint32), ("profile", ctypes.c_uint32),
+                ("modularity", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_uint32), ("converged", ctypes.c_int32),
                 ("changed_last", ctypes.c_uint64), ("arcs_processed", ctypes.c_uint64),
                 ("ms_total", ctypes.c_double), ("ms_rounds", ctypes.c_double),
+                ("modularity", ctypes.c_double), ("mod_terms", ctypes.c_uint64 * 4),
                 ("changed_per_iter", ctypes.POINTER(ctypes.c_uint64)),
                 ("ms_per_iter", ctypes.POINTER(ctypes.c_float)), ("cap", ctypes.c_uint32)]
 
@@ -148,6 +150,8 @@ class Stats:
     ms_rounds: float
     changed: list = field(default_factory=list)
     ms_per_iter: list = field(default_factory=list)
+    modularity: float = 0.0
+    mod_terms: dict = field(default_factory=dict)
 
 
 class Context:
@@ -205,8 +209,10 @@ class Context:
     @staticmethod
     def _pack(st, ch, ms) -> Stats:
         k = st.iterations
+        t = st.mod_terms
         return Stats(st.iterations, bool(st.converged), st.changed_last, st.arcs_processed, st.ms_total,
-                     st.ms_rounds, [int(x) for x in ch[:k]], [float(x) for x in ms[:k]])
+                     st.ms_rounds, [int(x) for x in ch[:k]], [float(x) for x in ms[:k]], st.modularity,
+                     {"two_m": int(t[0]), "sigma_in": int(t[1]), "sum_k2": int(t[2]) + (int(t[3]) << 64)})
 
     def run(self, g: DeviceGraph, tol: float = 0.05, max_iter: int = 20, labels_out=None):
         """RAK from L0(v) = v; returns (labels int32 tensor viewed as u32, Stats)."""

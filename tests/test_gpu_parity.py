@@ -131,14 +131,61 @@ def test_mid_graphs_all_bins(gg, orc, lpa, ctx, case):
     assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=30, sw=1)
 
 
-def test_long_rows_split_into_chunks(gg, orc, lpa, ctx):
-    # chunk 256 makes rows above 256 arcs go through the global slab path
+def test_long_rows_split_into_segments(gg, orc, lpa, ctx):
+    # wave_max 40 sends rows above 40 arcs to the segment path; rows above 512
+    # arcs are split over several wavefronts and merge through the slab
     g = gg.rmat(15, seed=15)
     deg = np.diff(g.row_ptr)
-    assert (deg > 256).sum() > 20 and deg.max() > 2048
+    assert (deg > 512).sum() > 20 and deg.max() > 2048
     for sw in (0, 1):
-        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=15, sw=sw, chunk=256)
-        assert_same(orc, lpa, ctx, g, tol=0.05, max_iter=15, sw=sw, chunk=2048)
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=15, sw=sw, wave_max=40, wide_max=40)
+        assert_same(orc, lpa, ctx, g, tol=0.05, max_iter=15, sw=sw)
+    gw = gg.with_weights(g, 11, 1, 6)
+    assert_same(orc, lpa, ctx, gw, tol=0.0, max_iter=15, sw=1, wave_max=33, wide_max=33)
+
+
+def test_long_rows_slab_merge(gg, orc, lpa, ctx):
+    # merge_max 1: every row of two or more segments merges its full tallies
+    # through the global slab instead of the top-K reports
+    g = gg.rmat(15, seed=19)
+    for sw in (0, 1):
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=12, sw=sw, merge_max=1)
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=12, sw=sw, merge_max=1, wave_max=40, wide_max=40)
+
+
+def test_long_rows_undecided_reports_fall_back(gg, orc, lpa, ctx):
+    # a hub whose neighbours carry labels in pairs: after round 1 every
+    # segment reports eight labels of tally 2 and a bound of 2 for the rest,
+    # so no leader can be proven and every round of the hub takes the slab
+    # fallback.  The answer must still be exact.
+    leaves = 6000
+    hub = leaves
+    edges = [(i, hub) for i in range(leaves)] + [(2 * j, 2 * j + 1) for j in range(leaves // 2)]
+    g = gg.from_edges(leaves + 1, edges, weights=(5, 1, 1))
+    for sw in (0, 1):
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=6, sw=sw)
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=6, sw=sw, group_max=8, wave_max=8, wide_max=8)
+
+
+def test_repeated_neighbours_round_one(gg, orc, lpa, ctx):
+    # rows that list a neighbour twice (multigraph arcs) may not take the
+    # round-1 direct path; their tallies must add the repeated weights
+    import graphgen
+    base = gg.rmat(12, seed=31)
+    src = np.repeat(np.arange(base.n), np.diff(base.row_ptr).astype(np.int64))
+    rng = np.random.default_rng(2)
+    dup = rng.random(base.m) < 0.05
+    s2 = np.concatenate([src, src[dup]])
+    d2 = np.concatenate([base.col.astype(np.int64), base.col[dup].astype(np.int64)])
+    order = np.lexsort((rng.random(len(s2)), s2))  # rows unsorted inside
+    s2, d2 = s2[order], d2[order]
+    rp = np.zeros(base.n + 1, np.uint64)
+    np.add.at(rp, s2 + 1, 1)
+    rp = np.cumsum(rp).astype(np.uint64)
+    g = graphgen.from_csr_arrays(base.n, rp, d2.astype(np.uint32), name="rmat12_multi")
+    for sw in (0, 1):
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=10, sw=sw)
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=10, sw=sw, wave_max=40, wide_max=40)
 
 
 def test_random_bin_thresholds_give_same_labels(gg, orc, lpa, ctx):
@@ -148,10 +195,10 @@ def test_random_bin_thresholds_give_same_labels(gg, orc, lpa, ctx):
     for _ in range(6):
         t = int(rng.integers(1, 9))
         gm = int(rng.integers(t, 33))
-        wm = int(rng.integers(gm, 257))
-        ch = int(2 ** rng.integers(8, 12))
-        lab, st = gpu_run(lpa, ctx, g, 0.0, 12, 1, thread_max=t, group_max=gm, wave_max=wm, chunk=ch)
-        assert np.array_equal(lab, ref.labels), (t, gm, wm, ch)
+        wm = int(rng.integers(gm, 129))
+        xm = int(rng.integers(wm, 513))
+        lab, st = gpu_run(lpa, ctx, g, 0.0, 12, 1, thread_max=t, group_max=gm, wave_max=wm, wide_max=xm)
+        assert np.array_equal(lab, ref.labels), (t, gm, wm, xm)
         assert st.changed == ref.changed
 
 
@@ -199,6 +246,17 @@ def test_modularity_matches_oracle(gg, orc, lpa, ctx, case):
     assert (terms["two_m"], terms["sigma_in"], terms["sum_k2"]) == (ref.two_m, ref.sigma_in, ref.sum_k2)
     assert abs(q - ref.q) <= 1e-9
     assert q == ref.q  # same exact integers, same FP64 expression
+
+
+def test_run_reports_modularity(gg, orc, lpa):
+    for g in (gg.rmat(14, seed=6), gg.road(60, 70, seed=3)):
+        ref = orc.rak(g)
+        mref = orc.modularity(g, ref.labels)
+        with lpa.Context(0, modularity=1) as c:
+            lab, st = c.run(dev(lpa, g))
+        assert np.array_equal(lpa.labels_to_numpy(lab), ref.labels)
+        assert st.mod_terms == {"two_m": mref.two_m, "sigma_in": mref.sigma_in, "sum_k2": mref.sum_k2}
+        assert st.modularity == mref.q
 
 
 # ---------------------------------------------------------- edge + errors --
@@ -253,7 +311,9 @@ def test_error_codes(gg, lpa, ctx):
     with pytest.raises(lpa.LpaError):
         lpa.Context(0, thread_max=9)
     with pytest.raises(lpa.LpaError):
-        lpa.Context(0, chunk=3000)
+        lpa.Context(0, wide_max=513)
+    with pytest.raises(lpa.LpaError):
+        lpa.Context(0, group_max=4, thread_max=8)
     # the context still works after errors
     lab, st = ctx.run(ok, tol=0.0, max_iter=2)
     assert st.iterations >= 1
