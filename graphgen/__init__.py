@@ -57,6 +57,8 @@ def _load():
         lib.gg_sbm.argtypes = [u32, u32, dbl, dbl, u64, P]
         lib.gg_from_edges.argtypes = [u32, u64, ctypes.c_void_p, ctypes.c_void_p, P]
         lib.gg_weights.argtypes = [P, u64, u32, u32]
+        lib.gg_sbm_batch.argtypes = [u32, u32, u32, dbl, dbl, u64, P, ctypes.c_void_p, ctypes.c_void_p]
+        lib.gg_sbm_batch.restype = ctypes.c_int
         lib.gg_free.argtypes = [P]
         lib.gg_version.restype = u32
         lib.gg_hash.argtypes = [u64, u64, u64]
@@ -193,3 +195,59 @@ def hash64(seed: int, stream: int, ctr: int) -> int:
 
 def version() -> int:
     return int(_load().gg_version())
+
+
+@dataclass
+class Batch:
+    """G graphs packed in one CSR: graph g owns vertices gv[g]..gv[g+1]."""
+    csr: CSR
+    gv: np.ndarray          # uint64, G+1
+    k: np.ndarray           # uint32, G: planted block count per graph
+
+    @property
+    def G(self) -> int:
+        return len(self.gv) - 1
+
+    def graph(self, g: int) -> CSR:
+        """Graph g alone, with local vertex ids."""
+        v0, v1 = int(self.gv[g]), int(self.gv[g + 1])
+        rp = self.csr.row_ptr[v0:v1 + 1]
+        a0, a1 = int(rp[0]), int(rp[-1])
+        col = (self.csr.col[a0:a1].astype(np.int64) - v0).astype(np.uint32)
+        w = None if self.csr.w is None else self.csr.w[a0:a1].copy()
+        return CSR(n=v1 - v0, row_ptr=(rp - rp[0]).astype(np.uint64), col=col, w=w, name=f"{self.csr.name}[{g}]")
+
+
+def sbm_batch(G: int = 4096, n_min: int = 200, n_max: int = 200000, deg_in: float = 12.0,
+              deg_out: float = 2.0, seed: int = 4096) -> Batch:
+    """G planted-partition graphs with n log-uniform in [n_min, n_max], 8..64
+    blocks (each >= 25 vertices), expected intra/inter degrees deg_in and
+    deg_out, packed into one CSR (unit weights)."""
+    g = _GG()
+    gv = np.zeros(G + 1, dtype=np.uint64)
+    kk = np.zeros(G, dtype=np.uint32)
+    _check(_load().gg_sbm_batch(G, n_min, n_max, deg_in, deg_out, seed, ctypes.byref(g),
+                                gv.ctypes.data, kk.ctypes.data), "sbm_batch")
+    return Batch(_take(g, f"sbmbatch{G}_{n_min}-{n_max}_s{seed}"), gv, kk)
+
+
+def pack(graphs) -> Batch:
+    """Pack CSR graphs (local ids) into one CSR; graph g gets the vertex
+    range gv[g]..gv[g+1]-1.  Weights are kept if every graph has them."""
+    graphs = list(graphs)
+    gv = np.zeros(len(graphs) + 1, dtype=np.uint64)
+    for i, g in enumerate(graphs):
+        gv[i + 1] = gv[i] + g.n
+    rps, cols, ws, base_arc = [np.zeros(1, np.uint64)], [], [], 0
+    weighted = bool(graphs) and all(g.w is not None for g in graphs)
+    for i, g in enumerate(graphs):
+        rps.append((g.row_ptr[1:].astype(np.uint64) + np.uint64(base_arc)))
+        cols.append((g.col.astype(np.int64) + int(gv[i])).astype(np.uint32))
+        if weighted:
+            ws.append(g.w.astype(np.uint32))
+        base_arc += g.m
+    rp = np.concatenate(rps)
+    col = np.concatenate(cols) if cols else np.zeros(0, np.uint32)
+    w = (np.concatenate(ws) if ws else np.zeros(0, np.uint32)) if weighted else None
+    k = np.zeros(len(graphs), dtype=np.uint32)
+    return Batch(CSR(n=int(gv[-1]), row_ptr=rp, col=col, w=w, name=f"pack{len(graphs)}"), gv, k)

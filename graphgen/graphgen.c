@@ -462,3 +462,87 @@ int gg_weights(gg_csr *g, uint64_t seed, uint32_t lo, uint32_t hi) {
     g->w = NULL;
     return assign_weights(g, seed, lo, hi);
 }
+
+/* ------------------------------------------------------- SBM batches -- */
+
+/* A batch of G planted-partition graphs packed into one CSR (vertex ranges
+ * gv[g]..gv[g+1], arcs stay inside their graph).  Graph g: n_g =
+ * round(exp(U[ln n_min, ln n_max])), k_g uniform in [8, min(64, n_g/25)]
+ * (at least 1), near-equal contiguous blocks of mean size s = n_g/k_g,
+ * p_in = deg_in/(s-1) clamped to 0.5 and p_out = deg_out/(n_g - s), so the
+ * expected intra- and inter-block degrees are deg_in and deg_out.  The
+ * per-graph seed is derived from (seed, g).  blocks_out (optional, filled
+ * when not NULL after the call) receives every vertex's planted block. */
+int gg_sbm_batch(uint32_t G, uint32_t n_min, uint32_t n_max, double deg_in, double deg_out, uint64_t seed,
+                 gg_csr *out, uint64_t *gv, uint32_t *kk) {
+    if (!out || !gv || G == 0 || n_min < 50 || n_max < n_min) return -1;
+    uint64_t key = gg_key(seed, 0x42415443ull);
+    uint32_t *ng = (uint32_t *)malloc((size_t)G * sizeof(uint32_t));
+    uint32_t *kg = (uint32_t *)malloc((size_t)G * sizeof(uint32_t));
+    gg_csr *parts = (gg_csr *)calloc((size_t)G, sizeof(gg_csr));
+    if (!ng || !kg || !parts) { free(ng); free(kg); free(parts); return -3; }
+    const double l0 = log((double)n_min), l1 = log((double)n_max);
+    uint64_t total_n = 0;
+    for (uint32_t g = 0; g < G; ++g) {
+        double r = u01(gg_draw(key, 2ull * g));
+        uint32_t n = (uint32_t)llround(exp(l0 + (l1 - l0) * r));
+        if (n < n_min) n = n_min;
+        if (n > n_max) n = n_max;
+        uint32_t kmax = n / 25;
+        if (kmax > 64) kmax = 64;
+        uint32_t kmin = 8 < kmax ? 8 : (kmax ? kmax : 1);
+        if (kmax < kmin) kmax = kmin;
+        uint32_t k = kmin + (uint32_t)(gg_draw(key, 2ull * g + 1) % (uint64_t)(kmax - kmin + 1));
+        ng[g] = n;
+        kg[g] = k;
+        total_n += n;
+    }
+    if (total_n > 0xFFFFFFFEull) { free(ng); free(kg); free(parts); return -1; }
+    int err = 0;
+    /* each graph draws from its own streams; gg_sbm parallelises inside */
+    for (uint32_t g = 0; g < G && !err; ++g) {
+        const double n = ng[g], s = n / kg[g];
+        double p_in = deg_in / (s - 1.0);
+        if (p_in > 0.5) p_in = 0.5;
+        double p_out = (n - s) > 0 ? deg_out / (n - s) : 0.0;
+        if (p_out > 1.0) p_out = 1.0;
+        int rc = gg_sbm(ng[g], kg[g], p_in, p_out, gg_draw(key, 0x100000000ull + g), &parts[g]);
+        if (rc) err = rc;
+    }
+    if (!err) {
+        uint64_t m = 0;
+        gv[0] = 0;
+        for (uint32_t g = 0; g < G; ++g) {
+            gv[g + 1] = gv[g] + ng[g];
+            m += parts[g].m;
+        }
+        uint64_t *rp = (uint64_t *)malloc(((size_t)total_n + 1) * sizeof(uint64_t));
+        uint32_t *col = (uint32_t *)malloc((size_t)(m ? m : 1) * sizeof(uint32_t));
+        if (!rp || !col) {
+            free(rp);
+            free(col);
+            err = -3;
+        } else {
+            uint64_t ao = 0;
+            for (uint32_t g = 0; g < G; ++g) {
+                const uint64_t vo = gv[g];
+                for (uint32_t v = 0; v < ng[g]; ++v) rp[vo + v] = ao + parts[g].row_ptr[v];
+                for (uint64_t e = 0; e < parts[g].m; ++e) col[ao + e] = (uint32_t)(vo + parts[g].col[e]);
+                ao += parts[g].m;
+            }
+            rp[total_n] = ao;
+            out->n = (uint32_t)total_n;
+            out->m = m;
+            out->row_ptr = rp;
+            out->col = col;
+            out->w = NULL;
+        }
+    }
+    if (kk && !err)
+        for (uint32_t g = 0; g < G; ++g) kk[g] = kg[g];
+    for (uint32_t g = 0; g < G; ++g) gg_free(&parts[g]);
+    free(parts);
+    free(ng);
+    free(kg);
+    return err;
+}

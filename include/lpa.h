@@ -49,7 +49,9 @@ typedef enum {
     LPA_EOVERFLOW = -2,    /* a vertex's weighted degree + self_weight >= 2^32 */
     LPA_ENOMEM = -3,       /* device or host allocation failed */
     LPA_EDEVICE = -4,      /* a HIP runtime call failed */
-    LPA_EUNSUPPORTED = -5  /* option or size this build does not handle */
+    LPA_EUNSUPPORTED = -5, /* option or size this build does not handle */
+    LPA_ETIMEDOUT = -6     /* a grid-wide wait of the batched kernel exceeded
+                              its limit (every block left the kernel) */
 } lpa_status;
 
 typedef struct lpa_ctx lpa_ctx;
@@ -151,6 +153,42 @@ lpa_status lpa_run_resume(lpa_ctx *ctx, const lpa_csr *g, uint32_t *labels_inout
  * {2m, Sigma_in, low 64 bits of sum K_c^2, high 64 bits}. */
 lpa_status lpa_modularity(lpa_ctx *ctx, const lpa_csr *g, const uint32_t *labels,
                           double *q_out, uint64_t *terms);
+
+/* Batched-run statistics.  The per-graph arrays are optional host arrays
+ * owned by the caller (NULL = not wanted). */
+typedef struct {
+    uint32_t graphs;            /* G */
+    uint32_t rounds;            /* rounds of the launch = max_g iterations[g] */
+    uint32_t converged_graphs;  /* graphs whose tolerance test passed */
+    uint64_t arcs_processed;    /* sum over graphs of arcs x rounds voted */
+    double ms_total;            /* host wall time of the call */
+    double ms_device;           /* device time of the captured run (HIP events) */
+    uint32_t *iterations;       /* [G] rounds executed per graph */
+    int32_t *converged;         /* [G] 1 if changed_last[g] <= floor(tol * n_g) */
+    uint64_t *changed_last;     /* [G] changed count of the graph's last round */
+    uint64_t *changed_hist;     /* [G * hist_cap]: row g holds the changed count
+                                   of rounds 1..min(iterations[g], hist_cap),
+                                   zeros after */
+    uint32_t hist_cap;
+} lpa_batch_stats;
+
+/* RAK (Section 3.2) on G independent graphs packed in one CSR: graph g owns
+ * vertices graph_vptr[g] .. graph_vptr[g+1]-1, and its arcs must stay among
+ * them.  Every graph runs exactly as lpa_run would run it alone: labels
+ * start as its local vertex ids, its tolerance test is
+ * changed_g <= floor(tol * n_g) and it stops voting on its own once that test
+ * passes or after max_iter rounds, while the others go on.  All rounds of
+ * all graphs run in one persistent kernel launch (blocks kept co-resident,
+ * grid-wide barriers between rounds); that launch and its set-up are
+ * captured once in a HIP graph per context and layout, then replayed.
+ * graph_vptr: host u64[G+1], graph_vptr[0] = 0, non-decreasing,
+ *   graph_vptr[G] = packed->n (empty graphs are allowed).
+ * labels_out: device u32[n]; vertex v of graph g receives its final label
+ *   as a local id (global label - graph_vptr[g]).
+ * Errors: those of lpa_run, LPA_EINVAL also for a malformed graph_vptr or
+ * an arc leaving its graph, and LPA_ETIMEDOUT. */
+lpa_status lpa_run_batch(lpa_ctx *ctx, const lpa_csr *packed, const uint64_t *graph_vptr, uint32_t G,
+                         uint32_t *labels_out, double tol, uint32_t max_iter, lpa_batch_stats *stats);
 
 /* Copy up to `cap` per-kernel profile records into out (host); *count gets
  * the number of records available.  lpa_profile_reset clears them. */

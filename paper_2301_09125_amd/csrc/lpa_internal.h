@@ -23,6 +23,8 @@ enum : uint32_t {
     ERR_WOVF = 2u,    // weighted degree + self weight >= 2^32
     ERR_ROWPTR = 4u,  // row_ptr not monotone / not ending at m
     ERR_LABEL = 8u,   // a label value >= n
+    ERR_TIMEOUT = 16u,  // a grid barrier of the batch kernel waited too long
+    ERR_GRAPH = 32u,  // a batch arc leaves its graph
 };
 
 // Degree bins in internal layout order (see lpa_options in lpa.h).
@@ -134,6 +136,37 @@ struct ModArgs {
     uint32_t *err;
 };
 
+// Batched run: state of the persistent kernel (lpa_batch.hip).
+struct BatchArgs {
+    Graph g;                     // internal packed graph
+    uint32_t *L0, *L1;           // label buffers; round t reads L0 if t is odd
+    const uint32_t *gid;         // internal vertex -> graph
+    const uint64_t *gv;          // graph g owns original ids gv[g] .. gv[g+1]-1
+    const uint64_t *orp;         // caller's row_ptr (arcs per graph)
+    uint32_t sw;
+    uint32_t lo[NBINS], cnt[NBINS];
+    uint32_t G, max_iter;
+    const unsigned long long *thr;  // [G] floor(tol * n_g)
+    uint32_t *active;            // [G] 1 while the graph votes
+    uint32_t *iters;             // [G] rounds executed
+    int32_t *conv;               // [G] tolerance met
+    unsigned long long *changed; // [G] changed count of the current round
+    unsigned long long *last;    // [G] changed count of the graph's last round
+    unsigned long long *hist;    // [G * hist_len] changed counts of rounds 1..hist_len
+    uint32_t hist_len;
+    unsigned long long *arcs;    // arcs voted, summed over graphs
+    uint32_t *n_active;          // graphs still voting
+    uint32_t *bar;               // [0] arrivals, [1] generation
+    uint32_t *err;
+    const uint64_t *slab_off;    // long rows: per-row global slab ...
+    const uint32_t *slab_mask;
+    const uint64_t *touched_off;
+    unsigned long long *slab;
+    uint32_t *touched;
+    uint32_t *tcount;
+    uint64_t timeout_ticks;      // wall-clock ticks one barrier may wait
+};
+
 // ---- launchers: lpa_prep.hip ---------------------------------------------
 hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t count, hipStream_t s);
@@ -185,6 +218,14 @@ hipError_t launch_hub_final(const RoundArgs &a, const HubState &hs, uint32_t cou
 // ---- launchers: lpa_mod.hip ----------------------------------------------
 hipError_t launch_mod_rows(const ModArgs &a, uint32_t lo, uint32_t cnt, int per_wave, hipStream_t s);
 hipError_t launch_mod_hub(const ModArgs &a, const HubItem *items, uint32_t count, hipStream_t s);
+hipError_t launch_batch_gid(const uint32_t *old_of, uint32_t n, const uint64_t *gv, uint32_t G, uint32_t *gid,
+                            hipStream_t s);
+hipError_t launch_batch_out(uint32_t *out, const uint32_t *old_of, const uint32_t *gid, const uint32_t *L0,
+                            const uint32_t *L1, const uint32_t *iters, const uint64_t *gv, uint32_t n,
+                            hipStream_t s);
+hipError_t launch_batch(const BatchArgs &b, uint32_t nblocks, hipStream_t s);
+int batch_blocks_per_cu();
+
 hipError_t launch_mod_sumsq(const unsigned long long *K, uint32_t n, unsigned long long *partials,
                             uint32_t nparts, hipStream_t s);
 

@@ -93,6 +93,11 @@ struct lpa_ctx {
     DevBuf items, ritems, slab_off, slab_mask, touched_off, tcount, best, own_sum, hflags, rowsum, slab, touched;
     DevBuf cand, thr, item_lo, mrows, slab_pending;
     DevBuf K, mod_sums, partials;
+    DevBuf gid, gvd, bstate;      // batched run
+    bool slab_dirty = false;      // slab may hold entries (set after a timed-out batch)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t bexec = nullptr;
+    std::vector<unsigned char> bkey;  // launch parameters the captured graph was made with
     uint64_t *pinned = nullptr;  // host pinned scratch for small read-backs
     size_t pinned_words = 0;
 
@@ -124,7 +129,8 @@ lpa_status dev_status(hipError_t e) {
     } while (0)
 
 lpa_status err_status(uint32_t bits) {
-    if (bits & (ERR_COL | ERR_ROWPTR | ERR_LABEL)) return LPA_EINVAL;
+    if (bits & (ERR_COL | ERR_ROWPTR | ERR_LABEL | ERR_GRAPH)) return LPA_EINVAL;
+    if (bits & ERR_TIMEOUT) return LPA_ETIMEDOUT;
     if (bits & ERR_WOVF) return LPA_EOVERFLOW;
     return LPA_OK;
 }
@@ -345,8 +351,10 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
         HIP_TRY(c->touched.ensure(touched_total * sizeof(uint32_t)));
         const size_t old_slab = c->slab.bytes;
         HIP_TRY(c->slab.ensure(slab_total * sizeof(u64)));
-        if (c->slab.bytes != old_slab || old_slab == 0)  // fresh allocation: every slot EMPTY
+        if (c->slab.bytes != old_slab || old_slab == 0 || c->slab_dirty) {  // every slot EMPTY
             HIP_TRY(launch_fill_u64(c->slab.as<u64>(), 0xFFFFFFFF00000000ull, c->slab.bytes / sizeof(u64), s));
+            c->slab_dirty = false;
+        }
         HIP_TRY(hipMemcpyAsync(c->ritems.p, ritems.data(), ritems.size() * sizeof(ReduceItem),
                                hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(c->slab_off.p, soff.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
@@ -585,6 +593,246 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     return LPA_OK;
 }
 
+// ------------------------------------------------------------- batched run --
+//
+// lpa_run_batch: the packed CSR is binned and relabelled once like a single
+// graph (its arcs never leave their graph, so each graph's rows only read
+// its own labels); gid maps internal vertices to graphs.  The state reset,
+// the persistent kernel that runs every round of every graph and the output
+// scatter are captured in one HIP graph, re-captured only when a launch
+// parameter changes.
+
+struct BatchLayout {
+    u64 *thr, *changed, *last, *hist, *arcs;
+    uint32_t *active, *iters, *n_active, *bar;
+    int32_t *conv;
+    size_t bytes;
+};
+
+BatchLayout batch_layout(void *base, uint32_t G, uint32_t hist_len) {
+    BatchLayout L;
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *q = p ? p + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return q;
+    };
+    L.thr = reinterpret_cast<u64 *>(take((size_t)G * 8));
+    L.changed = reinterpret_cast<u64 *>(take((size_t)G * 8));
+    L.last = reinterpret_cast<u64 *>(take((size_t)G * 8));
+    L.hist = reinterpret_cast<u64 *>(take((size_t)G * hist_len * 8));
+    L.arcs = reinterpret_cast<u64 *>(take(8));
+    L.active = reinterpret_cast<uint32_t *>(take((size_t)G * 4));
+    L.iters = reinterpret_cast<uint32_t *>(take((size_t)G * 4));
+    L.conv = reinterpret_cast<int32_t *>(take((size_t)G * 4));
+    L.n_active = reinterpret_cast<uint32_t *>(take(4));
+    L.bar = reinterpret_cast<uint32_t *>(take(8));
+    L.bytes = off;
+    return L;
+}
+
+constexpr uint32_t kBatchHistMax = 1024;  // rounds whose per-graph counts are kept
+constexpr double kBarrierTimeoutS = 10.0;
+
+void clear_batch_stats(lpa_batch_stats *st, uint32_t G) {
+    if (!st) return;
+    st->graphs = G;
+    st->rounds = 0;
+    st->converged_graphs = 0;
+    st->arcs_processed = 0;
+    st->ms_total = 0;
+    st->ms_device = 0;
+}
+
+lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint32_t G, uint32_t *labels,
+                          double tol, uint32_t max_iter, lpa_batch_stats *stats) {
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!c) return LPA_EINVAL;
+    LPA_TRY(check_csr_args(g));
+    if (!gv && G) return LPA_EINVAL;
+    if (!labels && g->n) return LPA_EINVAL;
+    if (!(tol >= 0.0 && tol <= 1.0)) return LPA_EINVAL;
+    if (G == 0) {
+        if (g->n) return LPA_EINVAL;
+        clear_batch_stats(stats, 0);
+        return LPA_OK;
+    }
+    if (gv[0] != 0 || gv[G] != g->n) return LPA_EINVAL;
+    for (uint32_t k = 0; k < G; ++k)
+        if (gv[k + 1] < gv[k]) return LPA_EINVAL;
+    HIP_TRY(hipSetDevice(c->device));
+    const hipStream_t s = c->stream;
+    const uint32_t n = g->n;
+    clear_batch_stats(stats, G);
+    const uint32_t hist_len = std::min<uint32_t>(max_iter, kBatchHistMax);
+    std::vector<uint64_t> thr_h(G);
+    for (uint32_t k = 0; k < G; ++k) thr_h[k] = (uint64_t)std::floor(tol * (double)(gv[k + 1] - gv[k]));
+
+    std::vector<uint32_t> it_h(G, 0);
+    std::vector<int32_t> conv_h(G, 0);
+    std::vector<u64> last_h(G, 0), hist_h((size_t)G * hist_len, 0);
+    u64 arcs_h = 0;
+    double ms_dev = 0;
+    if (n == 0) {
+        // every graph is empty: one round that changes nothing
+        if (max_iter > 0) {
+            std::fill(it_h.begin(), it_h.end(), 1u);
+            std::fill(conv_h.begin(), conv_h.end(), 1);
+        }
+    } else {
+        HIP_TRY(c->counters.ensure(sizeof(u64)));
+        uint32_t *err_dev = reinterpret_cast<uint32_t *>(c->counters.as<u64>());
+        HIP_TRY(launch_fill_u64(c->counters.as<u64>(), 0, 1, s));
+        LPA_TRY(ensure_pinned(c, 16));
+        Plan P;
+        LPA_TRY(prepare(c, g, P, err_dev, true));
+        HIP_TRY(c->gvd.ensure(((size_t)G + 1) * sizeof(uint64_t)));
+        HIP_TRY(hipMemcpyAsync(c->gvd.p, gv, ((size_t)G + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(c->gid.ensure((size_t)n * sizeof(uint32_t)));
+        HIP_TRY(launch_batch_gid(c->old_of.as<uint32_t>(), n, c->gvd.as<uint64_t>(), G, c->gid.as<uint32_t>(), s));
+        HIP_TRY(c->La.ensure((size_t)n * sizeof(uint32_t)));
+        HIP_TRY(c->Lb.ensure((size_t)n * sizeof(uint32_t)));
+        HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(), nullptr, n,
+                                   s));
+        HIP_TRY(c->bstate.ensure(batch_layout(nullptr, G, hist_len).bytes));
+        const BatchLayout L = batch_layout(c->bstate.p, G, hist_len);
+        HIP_TRY(hipMemcpyAsync(L.thr, thr_h.data(), (size_t)G * 8, hipMemcpyHostToDevice, s));
+
+        const Bins &B = P.bins;
+        BatchArgs b;
+        std::memset(&b, 0, sizeof(b));
+        b.g = internal_graph(c, g);
+        b.L0 = c->La.as<uint32_t>();
+        b.L1 = c->Lb.as<uint32_t>();
+        b.gid = c->gid.as<uint32_t>();
+        b.gv = c->gvd.as<uint64_t>();
+        b.orp = g->row_ptr;
+        b.sw = c->opt.self_weight;
+        for (int k = 0; k < NBINS; ++k) {
+            b.lo[k] = B.lo[k];
+            b.cnt[k] = B.cnt[k];
+        }
+        b.G = G;
+        b.max_iter = max_iter;
+        b.thr = L.thr;
+        b.active = L.active;
+        b.iters = L.iters;
+        b.conv = L.conv;
+        b.changed = L.changed;
+        b.last = L.last;
+        b.hist = L.hist;
+        b.hist_len = hist_len;
+        b.arcs = L.arcs;
+        b.n_active = L.n_active;
+        b.bar = L.bar;
+        b.err = err_dev;
+        const HubState hs = hub_state(c);
+        b.slab_off = hs.slab_off;
+        b.slab_mask = hs.slab_mask;
+        b.touched_off = hs.touched_off;
+        b.slab = hs.slab;
+        b.touched = hs.touched;
+        b.tcount = hs.tcount;
+        int rate_khz = 0;
+        HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
+        b.timeout_ticks = (uint64_t)(kBarrierTimeoutS * 1e3 * (double)(rate_khz > 0 ? rate_khz : 100000));
+        const uint64_t units = (uint64_t)B.cnt[BIN_HUB] + B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE] +
+                               (B.cnt[BIN_GROUP] + 3) / 4 + (B.cnt[BIN_THREAD] + 63) / 64;
+        const uint64_t cap_blocks = (uint64_t)batch_blocks_per_cu() * c->num_cu;
+        const uint32_t nblocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap_blocks, (units + 3) / 4));
+
+        // the captured graph depends on exactly these values
+        std::vector<unsigned char> key(sizeof(b) + sizeof(nblocks) + sizeof(labels) + sizeof(n) + sizeof(s));
+        {
+            unsigned char *k = key.data();
+            std::memcpy(k, &b, sizeof(b));
+            k += sizeof(b);
+            std::memcpy(k, &nblocks, sizeof(nblocks));
+            k += sizeof(nblocks);
+            std::memcpy(k, &labels, sizeof(labels));
+            k += sizeof(labels);
+            std::memcpy(k, &n, sizeof(n));
+            k += sizeof(n);
+            std::memcpy(k, &s, sizeof(s));
+        }
+        if (!c->bexec || key != c->bkey) {
+            if (c->bexec) {
+                (void)hipGraphExecDestroy(c->bexec);
+                c->bexec = nullptr;
+            }
+            if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            const hipStream_t cs = c->cap_stream;
+            HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            hipError_t e = launch_fill_u32(L.active, 1, G, cs);
+            if (e == hipSuccess) e = launch_fill_u32(L.iters, 0, G, cs);
+            if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(L.conv), 0, G, cs);
+            if (e == hipSuccess) e = launch_fill_u64(L.changed, 0, G, cs);
+            if (e == hipSuccess) e = launch_fill_u64(L.last, 0, G, cs);
+            if (e == hipSuccess && hist_len) e = launch_fill_u64(L.hist, 0, (uint64_t)G * hist_len, cs);
+            if (e == hipSuccess) e = launch_fill_u64(L.arcs, 0, 1, cs);
+            if (e == hipSuccess) e = launch_fill_u32(L.n_active, G, 1, cs);
+            if (e == hipSuccess) e = launch_fill_u32(L.bar, 0, 2, cs);
+            if (e == hipSuccess && max_iter) e = launch_batch(b, nblocks, cs);
+            if (e == hipSuccess)
+                e = launch_batch_out(labels, c->old_of.as<uint32_t>(), c->gid.as<uint32_t>(), b.L0, b.L1, L.iters,
+                                     b.gv, n, cs);
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&c->bexec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                c->bexec = nullptr;
+                return dev_status(e);
+            }
+            c->bkey = key;
+        }
+        if (!c->round_a) HIP_TRY(hipEventCreate(&c->round_a));
+        if (!c->round_b) HIP_TRY(hipEventCreate(&c->round_b));
+        HIP_TRY(hipEventRecord(c->round_a, s));
+        HIP_TRY(hipGraphLaunch(c->bexec, s));
+        HIP_TRY(hipEventRecord(c->round_b, s));
+        uint32_t errbits = 0;
+        HIP_TRY(hipMemcpyAsync(&errbits, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(it_h.data(), L.iters, (size_t)G * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(conv_h.data(), L.conv, (size_t)G * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(last_h.data(), L.last, (size_t)G * 8, hipMemcpyDeviceToHost, s));
+        if (stats && stats->changed_hist && hist_len)
+            HIP_TRY(hipMemcpyAsync(hist_h.data(), L.hist, hist_h.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&arcs_h, L.arcs, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
+        ms_dev = ms;
+        if (errbits & ERR_TIMEOUT) c->slab_dirty = true;
+        if (errbits) return err_status(errbits);
+    }
+    if (stats) {
+        uint32_t rounds = 0, nconv = 0;
+        for (uint32_t k = 0; k < G; ++k) {
+            rounds = std::max(rounds, it_h[k]);
+            nconv += conv_h[k] ? 1u : 0u;
+            if (stats->iterations) stats->iterations[k] = it_h[k];
+            if (stats->converged) stats->converged[k] = conv_h[k];
+            if (stats->changed_last) stats->changed_last[k] = last_h[k];
+        }
+        if (stats->changed_hist && stats->hist_cap) {
+            const uint32_t hc = stats->hist_cap;
+            for (uint32_t k = 0; k < G; ++k)
+                for (uint32_t t = 0; t < hc; ++t)
+                    stats->changed_hist[(size_t)k * hc + t] = t < hist_len ? hist_h[(size_t)k * hist_len + t] : 0;
+        }
+        stats->rounds = rounds;
+        stats->converged_graphs = nconv;
+        stats->arcs_processed = arcs_h;
+        stats->ms_device = ms_dev;
+        stats->ms_total =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return LPA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -646,6 +894,11 @@ lpa_status lpa_run_resume(lpa_ctx *ctx, const lpa_csr *g, uint32_t *labels_inout
     return run_impl(ctx, g, labels_inout, tol, max_iter, stats, true);
 }
 
+lpa_status lpa_run_batch(lpa_ctx *ctx, const lpa_csr *packed, const uint64_t *graph_vptr, uint32_t G,
+                         uint32_t *labels_out, double tol, uint32_t max_iter, lpa_batch_stats *stats) {
+    return run_batch_impl(ctx, packed, graph_vptr, G, labels_out, tol, max_iter, stats);
+}
+
 lpa_status lpa_modularity(lpa_ctx *c, const lpa_csr *g, const uint32_t *labels, double *q_out, uint64_t *terms) {
     if (!c || !q_out) return LPA_EINVAL;
     LPA_TRY(check_csr_args(g));
@@ -694,7 +947,9 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->items,      &c->ritems,   &c->slab_off, &c->slab_mask, &c->touched_off, &c->tcount,
                       &c->best,       &c->own_sum,  &c->hflags,   &c->rowsum,    &c->slab,        &c->touched,
                       &c->K,          &c->mod_sums, &c->partials, &c->cand,      &c->thr,         &c->item_lo,
-                      &c->mrows,      &c->slab_pending};
+                      &c->mrows,      &c->slab_pending, &c->gid,  &c->gvd,      &c->bstate};
+    if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) b->release();
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -711,6 +966,7 @@ const char *lpa_strerror(lpa_status s) {
         case LPA_ENOMEM: return "out of memory";
         case LPA_EDEVICE: return "HIP runtime error";
         case LPA_EUNSUPPORTED: return "unsupported option or size";
+        case LPA_ETIMEDOUT: return "a grid-wide wait of the batched kernel timed out";
     }
     return "unknown status";
 }

@@ -35,113 +35,9 @@
 // each neighbour once: every label then occurs once, its tally is that arc's
 // weight, and the vote is a plain max over the row.
 
-#include "lpa_device.h"
+#include "lpa_vote_dev.h"
 
 namespace lpa {
-
-// Issue the loads of arcs k0 + j*STRIDE (j < A, below e) of one lane:
-// internal ids into u, weights into wt, bit j of `valid` set for loaded
-// arcs.  Nothing here waits for the data, so the loads of the next work item
-// can be in flight while the current one is processed.
-template <int A, int STRIDE>
-__device__ __forceinline__ void issue_arcs(const RoundArgs &a, uint64_t k0, uint64_t e, uint32_t (&u)[A],
-                                           uint32_t (&wt)[A], uint32_t &valid) {
-    const uint32_t *__restrict__ col = a.g.col;
-    const uint32_t *__restrict__ w = a.g.w;
-    valid = 0;
-#pragma unroll
-    for (int j = 0; j < A; ++j) {
-        const uint64_t k = k0 + (uint64_t)j * STRIDE;
-        u[j] = 0;
-        if (k < e) {
-            valid |= 1u << j;
-            u[j] = col[k];
-        }
-    }
-    if (w) {
-#pragma unroll
-        for (int j = 0; j < A; ++j) wt[j] = (valid >> j & 1u) ? w[k0 + (uint64_t)j * STRIDE] : 0u;
-    } else {
-#pragma unroll
-        for (int j = 0; j < A; ++j) wt[j] = (valid >> j) & 1u;
-    }
-}
-
-// Out-of-range ids raise ERR_COL once and are read as vertex 0, so no later
-// access leaves the arrays.
-template <int A>
-__device__ __forceinline__ void check_arcs(const RoundArgs &a, uint32_t (&u)[A]) {
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < A; ++j) {
-        bad |= u[j] >= a.g.n;
-        u[j] = u[j] >= a.g.n ? 0u : u[j];
-    }
-    if (bad) atomicOr(a.err, ERR_COL);
-}
-
-template <int A, int STRIDE>
-__device__ __forceinline__ void load_arcs(const RoundArgs &a, uint64_t k0, uint64_t e, uint32_t (&u)[A],
-                                          uint32_t (&wt)[A], uint32_t &valid) {
-    issue_arcs<A, STRIDE>(a, k0, e, u, wt, valid);
-    check_arcs<A>(a, u);
-}
-
-template <int A>
-__device__ __forceinline__ void gather_labels(const RoundArgs &a, const uint32_t (&u)[A], uint32_t valid,
-                                              uint32_t (&lab)[A]) {
-    const uint32_t *__restrict__ L = a.L_old;
-#pragma unroll
-    for (int j = 0; j < A; ++j) lab[j] = (valid >> j & 1u) ? L[u[j]] : 0xFFFFFFFFu;
-}
-
-// Split loaded arcs into the own-label tally and the bit set `rem` of arcs
-// whose label must go through a table.
-template <int A>
-__device__ __forceinline__ void split_own(const uint32_t (&lab)[A], const uint32_t (&wt)[A], uint32_t valid,
-                                          uint32_t own, u64 &own_w, uint32_t &own_hit, uint32_t &rem, u64 &rs) {
-#pragma unroll
-    for (int j = 0; j < A; ++j)
-        if (valid >> j & 1u) {
-            rs += wt[j];
-            if (lab[j] == own) {
-                own_w += wt[j];
-                own_hit = 1;
-            } else {
-                rem |= 1u << j;
-            }
-        }
-}
-
-// Wavefront pre-aggregation: up to NPEEL times, take the first remaining
-// label of the lowest lane that has one, sum the weights of every remaining
-// arc of the wavefront with that label and insert the sum once.  All 64
-// lanes call this together.
-template <int A, int NPEEL>
-__device__ __forceinline__ void wave_peel(u64 *T, uint32_t mask, const uint32_t (&lab)[A],
-                                          const uint32_t (&wt)[A], uint32_t &rem) {
-    const uint32_t lane = threadIdx.x & 63;
-#pragma unroll
-    for (int p = 0; p < NPEEL; ++p) {
-        const u64 m = __ballot(rem != 0);
-        if (!m) return;
-        const int lead = __ffsll((long long)m) - 1;
-        uint32_t mine = 0;
-#pragma unroll
-        for (int j = A - 1; j >= 0; --j)
-            if (rem >> j & 1u) mine = lab[j];
-        const uint32_t L = __shfl(mine, lead, 64);
-        uint32_t s = 0;
-#pragma unroll
-        for (int j = 0; j < A; ++j)
-            if ((rem >> j & 1u) && lab[j] == L) {
-                s += wt[j];
-                rem &= ~(1u << j);
-            }
-        s = wave_sum(s);
-        if ((int)lane == lead) lds_insert(T, mask, L, s);
-    }
-}
 
 // ---------------------------------------------------------- one lane --
 
@@ -416,52 +312,6 @@ hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int w
 //                  degree slots); hub_reduce_k takes the max over the slots
 //                  they claimed; hub_final_k picks the winner of every row
 //                  decided through best[] and resets the per-round state.
-
-// Merge (lab, cnt) into a row's global slab.  Returns the slot index if this
-// call claimed a new slot, else kNone.
-__device__ __forceinline__ uint32_t slab_insert(u64 *S, uint32_t mask, uint32_t lab, uint32_t cnt) {
-    uint32_t h = hmix(lab) & mask;
-    const u64 desired = ((u64)lab << 32) | cnt;
-    for (;;) {
-        const u64 prev = atomicCAS(&S[h], EMPTY_SLOT, desired);
-        if (prev == EMPTY_SLOT) return h;
-        if ((uint32_t)(prev >> 32) == lab) {
-            atomicAdd(&S[h], (u64)cnt);
-            return kNone;
-        }
-        h = (h + 1) & mask;
-    }
-}
-
-// Move the S-slot LDS table of one wavefront into row h's slab, recording
-// per non-empty slot the slab slot it claimed (or kNone) in the row's
-// touched list; the entries are reserved with one atomic per wavefront.
-__device__ __forceinline__ void flush_to_slab(u64 *T, uint32_t S, const HubState &hs, uint32_t h) {
-    const uint32_t lane = threadIdx.x & 63;
-    uint32_t ne = 0;
-    for (uint32_t s = lane; s < S; s += 64) ne += T[s] != EMPTY_SLOT;
-    uint32_t pre = ne;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(pre, off, 64);
-        if ((int)lane >= off) pre += y;
-    }
-    const uint32_t total = __shfl(pre, 63, 64);
-    pre -= ne;
-    uint32_t tbase = 0;
-    if (lane == 0 && total) tbase = atomicAdd(&hs.tcount[h], total);
-    tbase = __shfl(tbase, 0, 64);
-    u64 *slab = hs.slab + hs.slab_off[h];
-    const uint32_t smask = hs.slab_mask[h];
-    uint32_t *tl = hs.touched + hs.touched_off[h] + tbase + pre;
-    for (uint32_t s = lane; s < S; s += 64) {
-        const u64 x = T[s];
-        if (x != EMPTY_SLOT) {
-            *tl++ = slab_insert(slab, smask, (uint32_t)(x >> 32), (uint32_t)x);
-            T[s] = EMPTY_SLOT;
-        }
-    }
-}
 
 // Report the kTopK heaviest entries of the S-slot table (clearing it) to
 // cand[it * kTopK ...] and the (kTopK+1)-th tally to thr[it].  Keys are

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblpa.so")
 
 LPA_OK, LPA_EINVAL, LPA_EOVERFLOW, LPA_ENOMEM, LPA_EDEVICE, LPA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+LPA_ETIMEDOUT = -6
 
 _lib = None
 
@@ -51,12 +52,19 @@ class _Stats(ctypes.Structure):
                 ("ms_per_iter", ctypes.POINTER(ctypes.c_float)), ("cap", ctypes.c_uint32)]
 
 
+class _BatchStats(ctypes.Structure):
+    _fields_ = [("graphs", ctypes.c_uint32), ("rounds", ctypes.c_uint32), ("converged_graphs", ctypes.c_uint32),
+                ("arcs_processed", ctypes.c_uint64), ("ms_total", ctypes.c_double), ("ms_device", ctypes.c_double),
+                ("iterations", ctypes.c_void_p), ("converged", ctypes.c_void_p), ("changed_last", ctypes.c_void_p),
+                ("changed_hist", ctypes.c_void_p), ("hist_cap", ctypes.c_uint32)]
+
+
 class _KProf(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_uint64), ("arcs", ctypes.c_uint64)]
 
 
-EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_modularity",
+EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_run_batch", "lpa_modularity",
            "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
 
 
@@ -75,6 +83,7 @@ def _load():
     lib.lpa_init.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(_Options)]
     lib.lpa_run.argtypes = [vp, ctypes.POINTER(_Csr), vp, dbl, u32, ctypes.POINTER(_Stats)]
     lib.lpa_run_resume.argtypes = [vp, ctypes.POINTER(_Csr), vp, dbl, u32, ctypes.POINTER(_Stats)]
+    lib.lpa_run_batch.argtypes = [vp, ctypes.POINTER(_Csr), vp, u32, vp, dbl, u32, ctypes.POINTER(_BatchStats)]
     lib.lpa_modularity.argtypes = [vp, ctypes.POINTER(_Csr), vp, ctypes.POINTER(dbl),
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.lpa_profile_get.argtypes = [vp, ctypes.POINTER(_KProf), u32, ctypes.POINTER(u32)]
@@ -83,7 +92,7 @@ def _load():
     lib.lpa_destroy.restype = None
     lib.lpa_strerror.argtypes = [ctypes.c_int]
     lib.lpa_strerror.restype = ctypes.c_char_p
-    for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_modularity, lib.lpa_profile_get,
+    for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_run_batch, lib.lpa_modularity, lib.lpa_profile_get,
               lib.lpa_profile_reset):
         f.restype = ctypes.c_int
     _lib = lib
@@ -152,6 +161,25 @@ class Stats:
     ms_per_iter: list = field(default_factory=list)
     modularity: float = 0.0
     mod_terms: dict = field(default_factory=dict)
+
+
+@dataclass
+class BatchStats:
+    graphs: int
+    rounds: int
+    converged_graphs: int
+    arcs_processed: int
+    ms_total: float
+    ms_device: float
+    iterations: np.ndarray      # u32[G]
+    converged: np.ndarray       # bool[G]
+    changed_last: np.ndarray    # u64[G]
+    changed_hist: np.ndarray    # u64[G, hist_cap]
+
+    def changed(self, g: int) -> list:
+        """Changed counts of graph g's rounds (up to hist_cap of them)."""
+        k = min(int(self.iterations[g]), self.changed_hist.shape[1])
+        return [int(x) for x in self.changed_hist[g, :k]]
 
 
 class Context:
@@ -236,6 +264,32 @@ class Context:
         if rc:
             raise LpaError(rc, "lpa_run_resume")
         return labels, self._pack(st, ch, ms)
+
+    def run_batch(self, g: DeviceGraph, graph_vptr, tol: float = 0.05, max_iter: int = 20, labels_out=None,
+                  hist_cap: int | None = None):
+        """RAK on the graphs packed in g (graph k owns vertices graph_vptr[k] ..
+        graph_vptr[k+1]-1); labels come back as ids local to each graph."""
+        import torch
+        gv = np.ascontiguousarray(np.asarray(graph_vptr, dtype=np.uint64))
+        G = max(len(gv) - 1, 0)
+        if labels_out is None:
+            labels_out = torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+        cap = max_iter if hist_cap is None else hist_cap
+        it = np.zeros(max(G, 1), np.uint32)
+        cv = np.zeros(max(G, 1), np.int32)
+        last = np.zeros(max(G, 1), np.uint64)
+        hist = np.zeros((max(G, 1), max(cap, 1)), np.uint64)
+        st = _BatchStats()
+        st.iterations, st.converged, st.changed_last = it.ctypes.data, cv.ctypes.data, last.ctypes.data
+        st.changed_hist, st.hist_cap = hist.ctypes.data, cap
+        c = g._c()
+        rc = _load().lpa_run_batch(self._h, ctypes.byref(c), gv.ctypes.data if len(gv) else None, G,
+                                   labels_out.data_ptr() if g.n else None, float(tol), int(max_iter),
+                                   ctypes.byref(st))
+        if rc:
+            raise LpaError(rc, "lpa_run_batch")
+        return labels_out, BatchStats(st.graphs, st.rounds, st.converged_graphs, st.arcs_processed, st.ms_total,
+                                      st.ms_device, it[:G], cv[:G].astype(bool), last[:G], hist[:G, :cap])
 
     def modularity(self, g: DeviceGraph, labels):
         """(Q, {'two_m', 'sigma_in', 'sum_k2'}) computed on the device."""

@@ -47,8 +47,9 @@ def test_ctypes_layouts_match_c():
 #include <stddef.h>
 #include "lpa.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lpa_csr), sizeof(lpa_options), sizeof(lpa_stats),
-         sizeof(lpa_kernel_prof), offsetof(lpa_stats, changed_per_iter), offsetof(lpa_kernel_prof, ms));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lpa_csr), sizeof(lpa_options), sizeof(lpa_stats),
+         sizeof(lpa_kernel_prof), offsetof(lpa_stats, changed_per_iter), offsetof(lpa_kernel_prof, ms),
+         sizeof(lpa_batch_stats), offsetof(lpa_batch_stats, iterations), offsetof(lpa_batch_stats, hist_cap));
   return 0;
 }
 '''
@@ -59,7 +60,8 @@ int main(void) {
         subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(x) for x in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(lpa._Csr), ctypes.sizeof(lpa._Options), ctypes.sizeof(lpa._Stats),
-            ctypes.sizeof(lpa._KProf), lpa._Stats.changed_per_iter.offset, lpa._KProf.ms.offset]
+            ctypes.sizeof(lpa._KProf), lpa._Stats.changed_per_iter.offset, lpa._KProf.ms.offset,
+            ctypes.sizeof(lpa._BatchStats), lpa._BatchStats.iterations.offset, lpa._BatchStats.hist_cap.offset]
     assert got == want
 
 

@@ -1,0 +1,186 @@
+"""GPU parity of the batched run (lpa_run_batch) against the CPU oracle run on
+each graph alone.
+
+Every graph of a batch must come out exactly as the oracle's RAK (arXiv
+2301.09125, Section 3.2) on that graph: the same labels as local ids, the
+same per-round changed counts, round count and convergence flag, although
+all graphs share one persistent launch and stop at different rounds.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lpa(torch_mod):
+    import paper_2301_09125_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(lpa):
+    c = lpa.Context(0)
+    yield c
+    c.close()
+
+
+def run_batch(lpa, ctx, batch, tol=0.05, max_iter=20):
+    dg = lpa.DeviceGraph.from_csr(batch.csr, "cuda")
+    lab, st = ctx.run_batch(dg, batch.gv, tol=tol, max_iter=max_iter)
+    return lpa.labels_to_numpy(lab), st
+
+
+def check_graphs(orc, batch, lab, st, which, tol, max_iter, sw=1):
+    for k in which:
+        g = batch.graph(k)
+        ref = orc.rak(g, tol=tol, max_iter=max_iter, self_weight=sw)
+        v0, v1 = int(batch.gv[k]), int(batch.gv[k + 1])
+        assert int(st.iterations[k]) == ref.iterations, (k, g.n, st.changed(k), ref.changed)
+        assert bool(st.converged[k]) == ref.converged, k
+        assert st.changed(k) == ref.changed[:st.changed_hist.shape[1]], (k, st.changed(k), ref.changed)
+        if ref.iterations:
+            assert int(st.changed_last[k]) == ref.changed[-1]
+        mism = np.flatnonzero(lab[v0:v1] != ref.labels)
+        assert mism.size == 0, f"graph {k} (n={g.n}): {mism.size} labels differ, first {mism[:8]}"
+
+
+def test_sbm_batch_matches_oracle_per_graph(gg, orc, lpa, ctx):
+    b = gg.sbm_batch(G=96, n_min=50, n_max=3000, seed=11)
+    say("[batch] sbm_batch G=96", b.csr.n, b.csr.m)
+    lab, st = run_batch(lpa, ctx, b)
+    check_graphs(orc, b, lab, st, range(b.G), 0.05, 20)
+    assert st.rounds == int(st.iterations.max())
+    assert st.converged_graphs == int(st.converged.sum())
+    rp = b.csr.row_ptr
+    arcs = sum(int(rp[b.gv[k + 1]] - rp[b.gv[k]]) * int(st.iterations[k]) for k in range(b.G))
+    assert st.arcs_processed == arcs
+
+
+def test_tolerance_zero_graphs_stop_at_different_rounds(gg, orc, lpa, ctx):
+    b = gg.sbm_batch(G=40, n_min=50, n_max=800, seed=5)
+    lab, st = run_batch(lpa, ctx, b, tol=0.0, max_iter=12)
+    check_graphs(orc, b, lab, st, range(b.G), 0.0, 12)
+    assert len(set(st.iterations.tolist())) > 1
+
+
+def mixed_graphs(gg):
+    """Graphs of every bin and the method's degenerate cases, local ids."""
+    out = []
+    out.append(gg.from_csr_arrays(0, [0], []))                      # empty graph
+    out.append(gg.from_edges(5, []))                                # isolated vertices only
+    out.append(gg.from_edges(2, [(0, 1)]))                          # K2
+    out.append(gg.from_edges(7, [(i, i + 1) for i in range(6)]))    # path
+    star = [(0, i) for i in range(1, 700)]                          # hub of degree 699
+    out.append(gg.from_edges(700, star))
+    cl = [(a + 8 * c, b + 8 * c) for c in range(3) for a in range(8) for b in range(a + 1, 8)]
+    out.append(gg.from_edges(24, cl))                               # 3 x K8
+    out.append(gg.rmat(11, 8, seed=3))                              # skewed degrees
+    out.append(gg.road(24, 30, 0.3, 0.05, 0, 0, seed=9))
+    out.append(gg.sbm(500, 5, 0.2, 0.01, seed=4))
+    # a hub whose leaves pair up so that its vote is contested
+    e = [(600, i) for i in range(600)] + [(2 * i, 2 * i + 1) for i in range(300)]
+    out.append(gg.from_edges(601, e))
+    return out
+
+
+def test_mixed_batch_all_bins(gg, orc, lpa, ctx):
+    graphs = mixed_graphs(gg)
+    b = gg.pack(graphs)
+    lab, st = run_batch(lpa, ctx, b)
+    check_graphs(orc, b, lab, st, range(b.G), 0.05, 20)
+
+
+def test_mixed_batch_small_thresholds_long_rows(gg, orc, lpa):
+    # rows above 40 arcs go through the per-row slab; many graphs then have
+    # long rows
+    graphs = mixed_graphs(gg)
+    b = gg.pack(graphs)
+    c = lpa.Context(0, thread_max=4, group_max=8, wave_max=16, wide_max=40)
+    try:
+        lab, st = run_batch(lpa, c, b)
+    finally:
+        c.close()
+    check_graphs(orc, b, lab, st, range(b.G), 0.05, 20)
+
+
+def test_weighted_batch(gg, orc, lpa, ctx):
+    graphs = [gg.with_weights(g, 17, 1, 9) for g in mixed_graphs(gg)[1:]]
+    b = gg.pack(graphs)
+    lab, st = run_batch(lpa, ctx, b, tol=0.02, max_iter=15)
+    check_graphs(orc, b, lab, st, range(b.G), 0.02, 15)
+
+
+@pytest.mark.parametrize("sw", [0, 3])
+def test_self_weight(gg, orc, lpa, sw):
+    b = gg.pack(mixed_graphs(gg))
+    c = lpa.Context(0, self_weight=sw)
+    try:
+        lab, st = run_batch(lpa, c, b, tol=0.0, max_iter=9)
+    finally:
+        c.close()
+    check_graphs(orc, b, lab, st, range(b.G), 0.0, 9, sw=sw)
+
+
+def test_max_iter_zero_and_replay(gg, orc, lpa, ctx):
+    b = gg.sbm_batch(G=20, n_min=50, n_max=400, seed=2)
+    lab, st = run_batch(lpa, ctx, b, max_iter=0)
+    local = np.concatenate([np.arange(int(b.gv[k + 1] - b.gv[k]), dtype=np.uint32) for k in range(b.G)])
+    assert np.array_equal(lab, local)
+    assert st.iterations.tolist() == [0] * b.G and not st.converged.any()
+    # the captured run replays bit-identically, also after another batch
+    lab1, st1 = run_batch(lpa, ctx, b)
+    lab2, st2 = run_batch(lpa, ctx, b)
+    other = gg.sbm_batch(G=7, n_min=50, n_max=300, seed=3)
+    run_batch(lpa, ctx, other)
+    lab3, st3 = run_batch(lpa, ctx, b)
+    for l, s in ((lab2, st2), (lab3, st3)):
+        assert np.array_equal(l, lab1)
+        assert np.array_equal(s.changed_hist, st1.changed_hist)
+    check_graphs(orc, b, lab1, st1, range(b.G), 0.05, 20)
+
+
+def test_history_cap(gg, orc, lpa, ctx):
+    b = gg.sbm_batch(G=10, n_min=50, n_max=300, seed=8)
+    dg = lpa.DeviceGraph.from_csr(b.csr, "cuda")
+    lab, st = ctx.run_batch(dg, b.gv, tol=0.0, max_iter=10, hist_cap=3)
+    lab = lpa.labels_to_numpy(lab)
+    for k in range(b.G):
+        ref = orc.rak(b.graph(k), tol=0.0, max_iter=10)
+        assert st.changed(k) == ref.changed[:3]
+        assert int(st.changed_last[k]) == ref.changed[-1]
+
+
+def test_errors(gg, lpa, ctx):
+    b = gg.pack([gg.from_edges(3, [(0, 1), (1, 2)]), gg.from_edges(3, [(0, 1)])])
+    dg = lpa.DeviceGraph.from_csr(b.csr, "cuda")
+    for gv in ([0, 3, 5], [0, 4, 3, 6], [1, 3, 6], [0, 7, 6]):
+        with pytest.raises(lpa.LpaError) as e:
+            ctx.run_batch(dg, gv)
+        assert e.value.code == lpa.lpa.LPA_EINVAL, gv
+    # an arc that leaves its graph: split the first graph's path
+    with pytest.raises(lpa.LpaError) as e:
+        ctx.run_batch(dg, [0, 2, 6])
+    assert e.value.code == lpa.lpa.LPA_EINVAL
+    # the context stays usable afterwards
+    lab, st = ctx.run_batch(dg, [0, 3, 6], tol=0.0)
+    assert lpa.labels_to_numpy(lab).tolist() == [0, 0, 0, 0, 0, 2]
+    # an empty batch
+    e0 = lpa.DeviceGraph.from_csr(gg.from_csr_arrays(0, [0], []), "cuda")
+    lab, st = ctx.run_batch(e0, [0])
+    assert st.graphs == 0 and st.rounds == 0
