@@ -5,8 +5,10 @@ one MI355X through the library's C ABI.
 A step is one whole hot-path pass over the resident graph: lpa_run from the
 unique initial labels (degree binning, init, synchronous vote rounds with the
 device changed-count until changed <= floor(0.05 n) or 20 rounds) followed by
-lpa_modularity of the result.  The graph is generated on the host (seeded,
-synthetic) and copied to HBM before the timed region.
+the modularity of the result.  The graph is generated on the host (seeded,
+synthetic) and copied to HBM before the timed region.  The batch workloads
+time lpa_run_batch instead: every graph of a packed 4096-graph batch run to
+its own tolerance in one persistent launch.
 
 value = arcs voted per second over the timed steps (GE/s; an undirected edge
 is two arcs, as in the paper's Table 1).  The JSON line also carries the
@@ -40,6 +42,12 @@ WORKLOADS = {
                  "seed 4096", lambda gg: gg.road(4096, 4096, 0.3, 0.01, 1, 8, seed=4096)),
     "sbm10k": ("planted partition, 10000 vertices, 100 blocks, p_in 0.1, p_out 0.001, seed 1",
                lambda gg: gg.sbm(10000, 100, 0.1, 0.001, seed=1)),
+    "batch50m": ("4096 planted-partition graphs, n log-uniform in [200, 6150], 8-64 blocks, mean intra degree 12, "
+                 "inter degree 2, seed 4096 (about 5e7 edges)",
+                 lambda gg: gg.sbm_batch(4096, 200, 6150, seed=4096)),
+    "batch4096": ("4096 planted-partition graphs, n log-uniform in [200, 200000], 8-64 blocks, mean intra degree "
+                  "12, inter degree 2, seed 4096 (about 8.4e8 edges)",
+                  lambda gg: gg.sbm_batch(4096, 200, 200000, seed=4096)),
 }
 
 
@@ -58,6 +66,93 @@ def cpu_baseline(g, rounds: int):
     return {"value": arcs / dt / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
             "sample": f"first {r.iterations} rounds of the sequential oracle on the same graph "
                       f"({arcs} arcs voted in {dt:.1f} s)"}
+
+
+def cpu_baseline_batch(b, budget_s: float = 15.0):
+    """The oracle on a bounded sample of a batch: whole graphs, in a seeded
+    random order, until the time budget is spent."""
+    import oracle
+    order = np.random.default_rng(1).permutation(b.G)
+    arcs, graphs, t0 = 0, 0, time.perf_counter()
+    for k in order:
+        g = b.graph(int(k))
+        r = oracle.rak(g, tol=0.05, max_iter=20, self_weight=1)
+        arcs += g.m * r.iterations
+        graphs += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": arcs / dt / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
+            "sample": f"{graphs} whole graphs of the batch (seeded order), {arcs} arcs voted in {dt:.1f} s"}
+
+
+def run_batch_bench(args, b, desc, P):
+    import torch
+    g = b.csr
+    dg = P.DeviceGraph.from_csr(g, "cuda")
+    torch.cuda.synchronize()
+    ctx = P.Context(0)
+    labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    def step():
+        _, st = ctx.run_batch(dg, b.gv, tol=args.tol, max_iter=args.max_iter, labels_out=labels)
+        return st
+
+    for i in range(args.warmup):
+        st = step()
+        log(f"[bench] warmup {i}: {st.rounds} rounds, {st.converged_graphs}/{st.graphs} converged, "
+            f"{st.ms_device:.2f} ms device, {st.ms_total:.2f} ms call")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st0 = stats[0]
+    for st in stats:
+        if not np.array_equal(st.changed_hist, st0.changed_hist):
+            raise SystemExit("non-deterministic result across steps")
+    arcs = sum(st.arcs_processed for st in stats)
+    value = arcs / elapsed / 1e9
+    ms_per_step = 1e3 * elapsed / args.steps
+    # algorithmic bytes of the persistent kernel: per graph and round, 8 B
+    # per arc (col + gathered label) and 16 B per non-isolated vertex
+    rp = g.row_ptr
+    deg = np.diff(rp)
+    nz = np.concatenate([[0], np.cumsum(deg > 0)])
+    gv = b.gv.astype(np.int64)
+    m_g = (rp[gv[1:]] - rp[gv[:-1]]).astype(np.float64)
+    nz_g = (nz[gv[1:]] - nz[gv[:-1]]).astype(np.float64)
+    it = st0.iterations.astype(np.float64)
+    wb = 12 if g.w is not None else 8
+    bytes_step = float(np.sum((wb * m_g + 16 * nz_g) * it))
+    dev_ms = float(np.mean([st.ms_device for st in stats]))
+    achieved = bytes_step / (dev_ms * 1e-3) / 1e9
+    log(f"[bench] {args.steps} steps in {elapsed:.3f}s: {ms_per_step:.3f} ms/step ({dev_ms:.3f} ms device), "
+        f"{value:.2f} GE/s, {achieved:.1f} GB/s algorithmic")
+    roofline = {"bound": "hbm", "kernel": "batch_k", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(dev_ms, 4), "bytes_per_launch": int(bytes_step)}
+    cpu = None
+    if args.cpu_rounds > 0:
+        log("[bench] cpu baseline: oracle on a sample of whole graphs ...")
+        cpu = cpu_baseline_batch(b)
+        log(f"[bench] cpu baseline {cpu['value']:.4f} GE/s")
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GE/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "graphs": b.G, "n": g.n, "m_arcs": g.m,
+                   "tol": args.tol, "max_iter": args.max_iter, "self_weight": 1, "tie_break": "lowest label",
+                   "rounds": st0.rounds, "converged_graphs": st0.converged_graphs,
+                   "hbm_gbs_effective": round(bytes_step * args.steps / elapsed / 1e9, 1),
+                   "device_ms": round(dev_ms, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def main():
@@ -87,6 +182,9 @@ def main():
     desc, gen = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     g = gen(gg)
+    if isinstance(g, gg.Batch):
+        log(f"[bench] generated {args.workload}: G={g.G} n={g.csr.n} m={g.csr.m} in {time.perf_counter() - t0:.1f}s")
+        return run_batch_bench(args, g, desc, P)
     log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
     dg = P.DeviceGraph.from_csr(g, "cuda")
     torch.cuda.synchronize()

@@ -2,34 +2,41 @@
 // graphs at once, all rounds in one persistent launch.
 //
 // The graphs are packed into one CSR whose arcs stay inside their graph and
-// relabelled like a single graph (lpa_internal.h), so every degree bin is a
-// contiguous range of internal ids across all graphs.  gid[r] names the
-// graph of internal vertex r.  Each graph keeps its own tolerance test
-// (changed_g <= floor(tol * n_g)) and its own round count: a graph that
-// converges (or reaches max_iter) stops being voted, and its labels stay in
-// the buffer its last round wrote.  The result of every graph therefore
-// equals a run of that graph alone.
+// relabelled like a single graph (lpa_internal.h).  Inside a degree bin the
+// internal ids keep the original order, so the rows of graph g in bin b form
+// one contiguous segment seg_lo[b][g] .. + seg_cnt[b][g].  Each graph keeps
+// its own tolerance test (changed_g <= floor(tol * n_g)) and round count; a
+// graph that passes it (or reaches max_iter) stops voting, and its labels stay
+// in the buffer its last round wrote, so every graph ends exactly as a run of
+// that graph alone.
 //
-// One launch, `nblocks` co-resident blocks; per round:
-//   phase A  every wavefront takes work units from a fixed interleaved list:
-//            one long row (> wide_max arcs; its 512-arc segments are merged
-//            exactly through the row's global slab by the same wavefront),
-//            one wavefront row, four 16-lane rows or 64 one-lane rows.
-//            Rows of converged graphs are skipped.  Changed counts are added
-//            per graph (one atomic per graph present in a wavefront).
+// Work units: one row (long, wide and wavefront bins), four 16-lane rows
+// (group bin) or 64 one-lane rows (thread bin), never spanning two graphs.
+// One launch of co-resident blocks; per round:
+//   phase A  for each bin, the units of the graphs still voting are split
+//            into equal contiguous ranges, one per wavefront; a wavefront
+//            walks its range segment by segment and adds its changed count
+//            to a graph's counter once per segment.
 //   barrier
-//   phase B  one lane per active graph records the round and applies its
-//            tolerance test; the number of running graphs drops as they stop.
-//   barrier  then every block leaves once no graph is running.
+//   phase B  block 0 applies every active graph's tolerance test, then
+//            prefix-sums the units of the graphs that go on (per bin) and
+//            records the segment each wavefront starts in.
+//   barrier  every block leaves once no graph is voting.
 // Barriers count arrivals with an atomic and release on a generation
-// number; a wait that exceeds a wall-clock limit raises ERR_TIMEOUT and
-// every block leaves the kernel, so the launch always ends.
+// number; a wait longer than the time limit raises ERR_TIMEOUT and every
+// block leaves the kernel, so the launch always ends.
 
 #include "lpa_vote_dev.h"
 
 namespace lpa {
 
-// Grid-wide barrier over `nblocks` blocks that are all resident.
+constexpr int kBatchThreads = 1024;
+constexpr int kBatchWaves = kBatchThreads / 64;
+
+// rows per work unit of each bin
+__device__ __forceinline__ uint32_t unit_rows(int b) { return b == BIN_THREAD ? 64u : (b == BIN_GROUP ? 4u : 1u); }
+
+// Grid-wide barrier over `nblocks` co-resident blocks.
 __device__ __forceinline__ bool grid_barrier(const BatchArgs &b, uint32_t nblocks) {
     __shared__ int failed;
     __syncthreads();
@@ -45,7 +52,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs &b, uint32_t nblock
         } else {
             const uint64_t t0 = wall_clock64();
             while (__hip_atomic_load(&b.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > b.timeout_ticks) {
                     atomicOr(b.err, ERR_TIMEOUT);
                     failed = 1;
@@ -60,21 +67,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs &b, uint32_t nblock
     return failed == 0;
 }
 
-// Add the changed flags of the wavefront's lanes to their graphs' counters:
-// one atomic per distinct graph among the changed lanes.
-__device__ __forceinline__ void count_per_graph(const BatchArgs &b, bool ch, uint32_t g) {
-    const uint32_t lane = threadIdx.x & 63;
-    u64 m = __ballot(ch);
-    while (m) {
-        const int lead = __ffsll((long long)m) - 1;
-        const uint32_t gl = __shfl(g, lead, 64);
-        const u64 same = __ballot(ch && g == gl);
-        if (lane == 0) atomicAdd(&b.changed[gl], (u64)__popcll(same));
-        m &= ~same;
-    }
-}
-
-// In round 1, arcs must stay inside their graph.
+// In round 1, every arc must stay inside its graph.
 template <int A>
 __device__ __forceinline__ void check_graph(const BatchArgs &b, const uint32_t (&u)[A], uint32_t valid,
                                             uint32_t g) {
@@ -85,60 +78,54 @@ __device__ __forceinline__ void check_graph(const BatchArgs &b, const uint32_t (
     if (bad) atomicOr(b.err, ERR_GRAPH);
 }
 
-// 64 one-lane rows (degree <= 8).
-__device__ void unit_thread(const BatchArgs &b, const RoundArgs &a, uint32_t v0, uint32_t v1, bool round1) {
+// 64 one-lane rows v0 .. v1-1 (degree <= 8) of graph g.  Returns the number
+// of changed rows (same value on every lane).
+__device__ uint32_t unit_thread(const BatchArgs &b, const RoundArgs &a, uint32_t v0, uint32_t v1, uint32_t g,
+                                bool round1) {
     constexpr int D = kThreadMaxCap;
     const uint32_t v = v0 + (threadIdx.x & 63);
     bool ch = false;
-    uint32_t g = 0;
     if (v < v1) {
-        g = b.gid[v];
-        if (b.active[g]) {
-            const uint64_t rb = a.g.rp[v], re = a.g.rp[v + 1];
-            const uint32_t own = a.L_old[v];
-            uint32_t u[D], lab[D], wt[D], tl[D], valid = 0;
-            load_arcs<D, 1>(a, rb, re, u, wt, valid);
-            if (round1) check_graph<D>(b, u, valid, g);
-            gather_labels<D>(a, u, valid, lab);
-            u64 rs = a.sw;
+        const uint64_t rb = a.g.rp[v], re = a.g.rp[v + 1];
+        const uint32_t own = a.L_old[v];
+        uint32_t u[D], lab[D], wt[D], tl[D], valid = 0;
+        load_arcs<D, 1>(a, rb, re, u, wt, valid);
+        if (round1) check_graph<D>(b, u, valid, g);
+        gather_labels<D>(a, u, valid, lab);
+        u64 rs = a.sw;
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                rs += wt[j];
-                tl[j] = wt[j] + (lab[j] == own ? a.sw : 0u);
-            }
-#pragma unroll
-            for (int j = 0; j < D; ++j)
-#pragma unroll
-                for (int k = j + 1; k < D; ++k)
-                    if (lab[j] == lab[k]) {
-                        tl[j] += wt[k];
-                        tl[k] += wt[j];
-                    }
-            u64 best = a.sw ? vote_key(own, a.sw) : 0ull;
-#pragma unroll
-            for (int j = 0; j < D; ++j)
-                if (valid >> j & 1u) best = umax64(best, vote_key(lab[j], tl[j]));
-            const uint32_t nl = best ? ~(uint32_t)best : own;
-            a.L_new[v] = nl;
-            ch = nl != own;
-            if (round1 && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+        for (int j = 0; j < D; ++j) {
+            rs += wt[j];
+            tl[j] = wt[j] + (lab[j] == own ? a.sw : 0u);
         }
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = j + 1; k < D; ++k)
+                if (lab[j] == lab[k]) {
+                    tl[j] += wt[k];
+                    tl[k] += wt[j];
+                }
+        u64 best = a.sw ? vote_key(own, a.sw) : 0ull;
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            if (valid >> j & 1u) best = umax64(best, vote_key(lab[j], tl[j]));
+        const uint32_t nl = best ? ~(uint32_t)best : own;
+        a.L_new[v] = nl;
+        ch = nl != own;
+        if (round1 && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
     }
-    count_per_graph(b, ch, g);
+    return (uint32_t)__popcll(__ballot(ch));
 }
 
-// Four 16-lane rows (degree <= 32), one 64-slot table each inside T.
-__device__ void unit_group(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32_t v0, uint32_t v1, bool round1) {
+// Four 16-lane rows v0 .. v1-1 (degree <= 32), a 64-slot table each in T.
+__device__ uint32_t unit_group(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32_t v0, uint32_t v1, uint32_t g,
+                               bool round1) {
     constexpr int G = kGroupLanes, CAP = kGroupSlots, A = CAP / (2 * G);
     const uint32_t lane = threadIdx.x & 63, gl = lane & (G - 1);
     u64 *Tg = T + (lane / G) * CAP;
     const uint32_t v = v0 + lane / G;
-    bool act = v < v1;
-    uint32_t g = 0;
-    if (act) {
-        g = b.gid[v];
-        act = b.active[g] != 0;
-    }
+    const bool act = v < v1;
     uint64_t rb = 0, re = 0;
     uint32_t own = 0;
     if (act) {
@@ -183,23 +170,23 @@ __device__ void unit_group(const BatchArgs &b, const RoundArgs &a, u64 *T, uint3
         if (round1 && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
     }
     wave_sync();
-    count_per_graph(b, ch, g);
+    return (uint32_t)__popcll(__ballot(ch));
 }
 
-// One row of at most 512 arcs, or of any length through its global slab
-// when `long_row` (h = its index among the long rows).
-__device__ void unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32_t v, uint32_t h, bool long_row,
-                          bool round1) {
-    constexpr int A = kWaveArcs / 64;
+// One row v of graph g: at most SLOTS/2 arcs through the wavefront's LDS
+// table, or, when `long_row` (h = its index among the long rows), any number
+// of arcs in SLOTS/2-arc chunks merged exactly in the row's global slab.
+template <int SLOTS>
+__device__ uint32_t unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32_t v, uint32_t h, uint32_t g,
+                              bool long_row, bool round1) {
+    constexpr int CHUNK = SLOTS / 2, A = CHUNK / 64;
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t g = b.gid[v];
-    if (!b.active[g]) return;  // uniform over the wavefront
     const uint64_t rb = a.g.rp[v], re = a.g.rp[v + 1];
     const uint32_t own = a.L_old[v];
     u64 own_w = 0, rs = 0, best = 0;
     uint32_t own_hit = 0;
-    for (uint64_t k0 = rb; k0 < re; k0 += kWaveArcs) {
-        const uint64_t k1 = re < k0 + kWaveArcs ? re : k0 + kWaveArcs;
+    for (uint64_t k0 = rb; k0 < re; k0 += CHUNK) {
+        const uint64_t k1 = re < k0 + CHUNK ? re : k0 + CHUNK;
         uint32_t u[A], lab[A], wt[A], valid = 0;
         load_arcs<A, 64>(a, k0 + lane, k1, u, wt, valid);
         if (round1) check_graph<A>(b, u, valid, g);
@@ -207,7 +194,7 @@ __device__ void unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32
         uint32_t rem = 0;
         split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
         uint32_t S = next_pow2(2u * (uint32_t)(k1 - k0));
-        S = S < 64u ? 64u : (S > (uint32_t)kWaveSlots ? (uint32_t)kWaveSlots : S);
+        S = S < 64u ? 64u : (S > (uint32_t)SLOTS ? (uint32_t)SLOTS : S);
         if (__ballot(rem != 0)) {
             wave_peel<A, 2>(T, S - 1, lab, wt, rem);
 #pragma unroll
@@ -231,7 +218,8 @@ __device__ void unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32
     }
     if (long_row) {
         // the row's slab holds its exact tallies: take the max over the
-        // claimed slots and clear them for the next round
+        // claimed slots and clear them for the next round (only this
+        // wavefront touches the row's slab)
         __threadfence();
         const uint32_t tc = __hip_atomic_load(&b.tcount[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         u64 *slab = b.slab + b.slab_off[h];
@@ -239,7 +227,8 @@ __device__ void unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32
         for (uint32_t p = lane; p < tc; p += 64) {
             const uint32_t s = tl[p];
             if (s != kNone) {
-                best = umax64(best, slot_key(__hip_atomic_load(&slab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                best = umax64(best,
+                              slot_key(__hip_atomic_load(&slab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
                 __hip_atomic_store(&slab[s], EMPTY_SLOT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -257,22 +246,148 @@ __device__ void unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32
         ch = nl != own;
         if (round1 && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
     }
-    count_per_graph(b, ch, g);
+    return (uint32_t)__popcll(__ballot(ch));
 }
 
-__global__ __launch_bounds__(256) void batch_k(BatchArgs b, uint32_t nblocks) {
-    __shared__ u64 table[4 * kWaveSlots];
+// Units of bin `bin` assigned to wavefront w this round.
+template <int SLOTS>
+__device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t w, bool round1) {
+    const uint32_t *pref = b.pref + (size_t)bin * (b.G + 1);
+    const uint32_t total = pref[b.G];
+    const uint32_t i0 = (uint32_t)((u64)w * total / b.nw);
+    const uint32_t i1 = (uint32_t)((u64)(w + 1) * total / b.nw);
+    if (i0 >= i1) return;
+    const uint32_t R = unit_rows(bin);
+    uint32_t g = b.start[(size_t)bin * b.nw + w];
+    uint32_t p0 = pref[g], p1 = pref[g + 1];
+    uint32_t lo = b.seg_lo[(size_t)bin * b.G + g], end = lo + b.seg_cnt[(size_t)bin * b.G + g];
+    uint32_t wch = 0;
+    for (uint32_t i = i0; i < i1; ++i) {
+        if (i >= p1) {  // next segment that has units this round
+            if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[g], (u64)wch);
+            wch = 0;
+            do {
+                ++g;
+                p0 = p1;
+                p1 = pref[g + 1];
+            } while (i >= p1);
+            lo = b.seg_lo[(size_t)bin * b.G + g];
+            end = lo + b.seg_cnt[(size_t)bin * b.G + g];
+        }
+        const uint32_t v0 = lo + (i - p0) * R;
+        if (bin == BIN_THREAD)
+            wch += unit_thread(b, a, v0, end, g, round1);
+        else if (bin == BIN_GROUP)
+            wch += unit_group(b, a, T, v0, end, g, round1);
+        else
+            wch += unit_wave<SLOTS>(b, a, T, v0, v0 - b.lo[BIN_HUB], g, bin == BIN_HUB, round1);
+    }
+    if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[g], (u64)wch);
+}
+
+// Phase B, run by block 0 alone: tolerance tests of round t (none for
+// t = 0), then the per-bin prefix sums of the units of the graphs that go on
+// voting and every wavefront's first segment.
+__device__ void decide(const BatchArgs &b, uint32_t t) {
+    __shared__ uint32_t wsum[kBatchWaves][kBatchBins];
+    __shared__ uint32_t carry[kBatchBins];
+    __shared__ uint32_t n_on;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) n_on = 0;
+    if (tid < kBatchBins) carry[tid] = 0;
+    __syncthreads();
+    uint32_t on = 0;
+    for (uint32_t g = tid; g < b.G; g += kBatchThreads) {
+        if (!b.active[g]) continue;
+        if (t == 0) {
+            ++on;
+            continue;
+        }
+        const u64 ch = b.changed[g];
+        b.changed[g] = 0;
+        b.last[g] = ch;
+        b.iters[g] = t;
+        if (t <= b.hist_len) b.hist[(u64)g * b.hist_len + (t - 1)] = ch;
+        const bool ok = ch <= b.thr[g];
+        if (ok || t == b.max_iter) {
+            b.conv[g] = ok ? 1 : 0;
+            b.active[g] = 0;
+            atomicAdd(b.arcs, (u64)(b.orp[b.gv[g + 1]] - b.orp[b.gv[g]]) * t);
+        } else {
+            ++on;
+        }
+    }
+    on = wave_sum(on);
+    if (lane == 0 && on) atomicAdd(&n_on, on);
+    __syncthreads();  // active[] of every graph is final
+    // exclusive prefix sums over graphs, kBatchThreads graphs per pass
+    for (uint32_t base = 0; base < b.G; base += kBatchThreads) {
+        const uint32_t g = base + tid;
+        uint32_t x[kBatchBins];
+        const bool live = g < b.G && b.active[g];
+#pragma unroll
+        for (int k = 0; k < kBatchBins; ++k) {
+            const uint32_t c = live ? b.seg_cnt[(size_t)k * b.G + g] : 0u;
+            x[k] = (c + unit_rows(k) - 1) / unit_rows(k);
+        }
+#pragma unroll
+        for (int k = 0; k < kBatchBins; ++k) {
+            uint32_t s = x[k];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(s, off, 64);
+                if ((int)lane >= off) s += y;
+            }
+            if (lane == 63) wsum[wave][k] = s;
+            x[k] = s - x[k];  // exclusive within the wavefront
+        }
+        __syncthreads();
+        if (g < b.G) {
+#pragma unroll
+            for (int k = 0; k < kBatchBins; ++k) {
+                uint32_t off = carry[k];
+                for (uint32_t q = 0; q < wave; ++q) off += wsum[q][k];
+                b.pref[(size_t)k * (b.G + 1) + g] = off + x[k];
+            }
+        }
+        __syncthreads();
+        if (tid < kBatchBins) {
+            uint32_t s = 0;
+            for (int q = 0; q < kBatchWaves; ++q) s += wsum[q][tid];
+            carry[tid] += s;
+        }
+        __syncthreads();
+    }
+    if (tid < kBatchBins) b.pref[(size_t)tid * (b.G + 1) + b.G] = carry[tid];
+    __syncthreads();
+    // wavefront w starts in the segment that holds unit floor(w * total / nw)
+    for (uint32_t g = tid; g < b.G; g += kBatchThreads) {
+#pragma unroll 1
+        for (int k = 0; k < kBatchBins; ++k) {
+            const uint32_t *pref = b.pref + (size_t)k * (b.G + 1);
+            const u64 total = carry[k];
+            const u64 p0 = pref[g], p1 = pref[g + 1];
+            if (p1 == p0) continue;
+            const u64 w0 = (p0 * b.nw + total - 1) / total;
+            const u64 w1 = (p1 * b.nw + total - 1) / total;
+            for (u64 w = w0; w < w1 && w < b.nw; ++w) b.start[(size_t)k * b.nw + w] = g;
+        }
+    }
+    if (tid == 0) *b.n_active = n_on;
+}
+
+template <int SLOTS>
+__global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t nblocks) {
+    __shared__ u64 table[kBatchWaves * SLOTS];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    u64 *T = table + wave * kWaveSlots;
-    for (uint32_t s = lane; s < kWaveSlots; s += 64) T[s] = EMPTY_SLOT;
+    u64 *T = table + wave * SLOTS;
+    for (uint32_t s = lane; s < SLOTS; s += 64) T[s] = EMPTY_SLOT;
     wave_sync();
-    const uint32_t n_long = b.cnt[BIN_HUB];
-    const uint32_t n_wave = b.cnt[BIN_WIDE] + b.cnt[BIN_WAVE];
-    const uint32_t n_group = (b.cnt[BIN_GROUP] + 3) / 4;
-    const uint32_t n_thread = (b.cnt[BIN_THREAD] + 63) / 64;
-    const uint32_t units = n_long + n_wave + n_group + n_thread;
-    const uint32_t wid = blockIdx.x * 4 + wave, nw = nblocks * 4;
+    const uint32_t w = blockIdx.x * kBatchWaves + wave;
+    // the work split of round 1: every graph votes
+    if (blockIdx.x == 0) decide(b, 0);
+    if (!grid_barrier(b, nblocks)) return;
     for (uint32_t t = 1; t <= b.max_iter; ++t) {
         RoundArgs a;
         a.g = b.g;
@@ -284,38 +399,9 @@ __global__ __launch_bounds__(256) void batch_k(BatchArgs b, uint32_t nblocks) {
         a.changed = nullptr;
         a.err = b.err;
         const bool round1 = t == 1;
-        // phase A
-        for (uint32_t u = wid; u < units; u += nw) {
-            if (u < n_long) {
-                unit_wave(b, a, T, b.lo[BIN_HUB] + u, u, true, round1);
-            } else if (u < n_long + n_wave) {
-                unit_wave(b, a, T, b.lo[BIN_WIDE] + (u - n_long), 0, false, round1);
-            } else if (u < n_long + n_wave + n_group) {
-                const uint32_t v0 = b.lo[BIN_GROUP] + 4 * (u - n_long - n_wave);
-                unit_group(b, a, T, v0, b.lo[BIN_GROUP] + b.cnt[BIN_GROUP], round1);
-            } else {
-                const uint32_t v0 = b.lo[BIN_THREAD] + 64 * (u - n_long - n_wave - n_group);
-                unit_thread(b, a, v0, b.lo[BIN_THREAD] + b.cnt[BIN_THREAD], round1);
-            }
-        }
+        for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin) run_bin<SLOTS>(b, a, T, bin, w, round1);
         if (!grid_barrier(b, nblocks)) return;
-        // phase B: tolerance test per graph
-        for (uint32_t g = blockIdx.x * 256 + threadIdx.x; g < b.G; g += nblocks * 256) {
-            if (b.active[g]) {
-                const u64 ch = b.changed[g];
-                b.changed[g] = 0;
-                b.last[g] = ch;
-                b.iters[g] = t;
-                if (t <= b.hist_len) b.hist[(u64)g * b.hist_len + (t - 1)] = ch;
-                const bool ok = ch <= b.thr[g];
-                if (ok || t == b.max_iter) {
-                    b.conv[g] = ok ? 1 : 0;
-                    b.active[g] = 0;
-                    atomicSub(b.n_active, 1u);
-                    atomicAdd(b.arcs, (u64)(b.orp[b.gv[g + 1]] - b.orp[b.gv[g]]) * t);
-                }
-            }
-        }
+        if (blockIdx.x == 0) decide(b, t);
         if (!grid_barrier(b, nblocks)) return;
         if (__hip_atomic_load(b.n_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
         if (__hip_atomic_load(b.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (ERR_COL | ERR_GRAPH)) break;
@@ -338,6 +424,33 @@ __global__ void batch_gid_k(const uint32_t *old_of, uint32_t n, const uint64_t *
     }
 }
 
+// Segment of graph g in bin k: the rows of the bin whose gid is g (gid does
+// not decrease inside a bin).
+__global__ void batch_seg_k(const uint32_t *gid, Bins bins, uint32_t G, uint32_t *seg_lo, uint32_t *seg_cnt) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint32_t)kBatchBins * G) return;
+    const uint32_t k = i / G, g = i % G;
+    const uint32_t lo = bins.lo[k], cnt = bins.cnt[k];
+    uint32_t first = 0, last = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const uint32_t key = g + pass;
+        uint32_t l = 0, h = cnt;  // first row with gid >= key
+        while (l < h) {
+            const uint32_t mid = (l + h) / 2;
+            if (gid[lo + mid] < key)
+                l = mid + 1;
+            else
+                h = mid;
+        }
+        if (pass == 0)
+            first = l;
+        else
+            last = l;
+    }
+    seg_lo[i] = lo + first;
+    seg_cnt[i] = last - first;
+}
+
 // labels_out[old_of[r]] = final label of r, as an id local to its graph.
 __global__ void batch_out_k(uint32_t *out, const uint32_t *old_of, const uint32_t *gid, const uint32_t *L0,
                             const uint32_t *L1, const uint32_t *iters, const uint64_t *gv, uint32_t n) {
@@ -354,6 +467,13 @@ hipError_t launch_batch_gid(const uint32_t *old_of, uint32_t n, const uint64_t *
     batch_gid_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(old_of, n, gv, G, gid);
     return hipGetLastError();
 }
+hipError_t launch_batch_seg(const uint32_t *gid, const Bins &bins, uint32_t G, uint32_t *seg_lo, uint32_t *seg_cnt,
+                            hipStream_t s) {
+    const uint64_t total = (uint64_t)kBatchBins * G;
+    if (total == 0) return hipSuccess;
+    batch_seg_k<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(gid, bins, G, seg_lo, seg_cnt);
+    return hipGetLastError();
+}
 hipError_t launch_batch_out(uint32_t *out, const uint32_t *old_of, const uint32_t *gid, const uint32_t *L0,
                             const uint32_t *L1, const uint32_t *iters, const uint64_t *gv, uint32_t n,
                             hipStream_t s) {
@@ -362,16 +482,27 @@ hipError_t launch_batch_out(uint32_t *out, const uint32_t *old_of, const uint32_
     return hipGetLastError();
 }
 
-int batch_blocks_per_cu() {
+int batch_slots(const Bins &bins) { return bins.cnt[BIN_WIDE] ? kWaveSlots : kWaveSlotsSmall; }
+
+int batch_blocks_per_cu(int slots) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_k, 256, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
+    const hipError_t e =
+        slots == kWaveSlots
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_k<kWaveSlots>, kBatchThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_k<kWaveSlotsSmall>, kBatchThreads, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
     return per_cu;
 }
 
-hipError_t launch_batch(const BatchArgs &b, uint32_t nblocks, hipStream_t s) {
+int batch_waves_per_block() { return kBatchWaves; }
+
+hipError_t launch_batch(const BatchArgs &b, uint32_t nblocks, int slots, hipStream_t s) {
     void *args[] = {(void *)&b, (void *)&nblocks};
-    return hipLaunchCooperativeKernel((const void *)batch_k, dim3(nblocks), dim3(256), args, 0, s);
+    if (slots == kWaveSlots)
+        return hipLaunchCooperativeKernel((const void *)batch_k<kWaveSlots>, dim3(nblocks), dim3(kBatchThreads), args,
+                                          0, s);
+    return hipLaunchCooperativeKernel((const void *)batch_k<kWaveSlotsSmall>, dim3(nblocks), dim3(kBatchThreads),
+                                      args, 0, s);
 }
 
 }  // namespace lpa

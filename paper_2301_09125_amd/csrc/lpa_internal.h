@@ -136,7 +136,11 @@ struct ModArgs {
     uint32_t *err;
 };
 
-// Batched run: state of the persistent kernel (lpa_batch.hip).
+// Batched run: state of the persistent kernel (lpa_batch.hip).  The bins
+// BIN_HUB .. BIN_THREAD vote; rows of graph g in bin k are the segment
+// seg_lo[k*G+g] .. + seg_cnt[k*G+g] of internal ids.
+constexpr int kBatchBins = 5;
+
 struct BatchArgs {
     Graph g;                     // internal packed graph
     uint32_t *L0, *L1;           // label buffers; round t reads L0 if t is odd
@@ -164,6 +168,11 @@ struct BatchArgs {
     unsigned long long *slab;
     uint32_t *touched;
     uint32_t *tcount;
+    const uint32_t *seg_lo;      // [kBatchBins * G]
+    const uint32_t *seg_cnt;     // [kBatchBins * G]
+    uint32_t *pref;              // [kBatchBins * (G+1)] units of voting graphs, prefix sums
+    uint32_t *start;             // [kBatchBins * nw] first segment of each wavefront
+    uint32_t nw;                 // wavefronts of the launch
     uint64_t timeout_ticks;      // wall-clock ticks one barrier may wait
 };
 
@@ -223,8 +232,12 @@ hipError_t launch_batch_gid(const uint32_t *old_of, uint32_t n, const uint64_t *
 hipError_t launch_batch_out(uint32_t *out, const uint32_t *old_of, const uint32_t *gid, const uint32_t *L0,
                             const uint32_t *L1, const uint32_t *iters, const uint64_t *gv, uint32_t n,
                             hipStream_t s);
-hipError_t launch_batch(const BatchArgs &b, uint32_t nblocks, hipStream_t s);
-int batch_blocks_per_cu();
+hipError_t launch_batch_seg(const uint32_t *gid, const Bins &bins, uint32_t G, uint32_t *seg_lo, uint32_t *seg_cnt,
+                            hipStream_t s);
+hipError_t launch_batch(const BatchArgs &b, uint32_t nblocks, int slots, hipStream_t s);
+int batch_slots(const Bins &bins);
+int batch_blocks_per_cu(int slots);
+int batch_waves_per_block();
 
 hipError_t launch_mod_sumsq(const unsigned long long *K, uint32_t n, unsigned long long *partials,
                             uint32_t nparts, hipStream_t s);

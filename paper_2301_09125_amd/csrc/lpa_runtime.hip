@@ -93,7 +93,7 @@ struct lpa_ctx {
     DevBuf items, ritems, slab_off, slab_mask, touched_off, tcount, best, own_sum, hflags, rowsum, slab, touched;
     DevBuf cand, thr, item_lo, mrows, slab_pending;
     DevBuf K, mod_sums, partials;
-    DevBuf gid, gvd, bstate;      // batched run
+    DevBuf gid, gvd, bstate, bseg;  // batched run
     bool slab_dirty = false;      // slab may hold entries (set after a timed-out batch)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t bexec = nullptr;
@@ -695,11 +695,25 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         HIP_TRY(c->Lb.ensure((size_t)n * sizeof(uint32_t)));
         HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(), nullptr, n,
                                    s));
+        const Bins &B = P.bins;
+        const int slots = batch_slots(B);
+        const uint64_t units = (uint64_t)B.cnt[BIN_HUB] + B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE] +
+                               (B.cnt[BIN_GROUP] + 3) / 4 + (B.cnt[BIN_THREAD] + 63) / 64;
+        const uint32_t wpb = (uint32_t)batch_waves_per_block();
+        const uint64_t cap_blocks = (uint64_t)batch_blocks_per_cu(slots) * c->num_cu;
+        const uint32_t nblocks =
+            (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap_blocks, (units + wpb - 1) / wpb));
+        const uint32_t nw = nblocks * wpb;
         HIP_TRY(c->bstate.ensure(batch_layout(nullptr, G, hist_len).bytes));
         const BatchLayout L = batch_layout(c->bstate.p, G, hist_len);
         HIP_TRY(hipMemcpyAsync(L.thr, thr_h.data(), (size_t)G * 8, hipMemcpyHostToDevice, s));
+        const size_t seg_words = (size_t)kBatchBins * G;
+        const size_t pref_words = (size_t)kBatchBins * ((size_t)G + 1);
+        HIP_TRY(c->bseg.ensure((2 * seg_words + pref_words + (size_t)kBatchBins * nw) * sizeof(uint32_t)));
+        uint32_t *seg_lo = c->bseg.as<uint32_t>(), *seg_cnt = seg_lo + seg_words;
+        uint32_t *pref = seg_cnt + seg_words, *start = pref + pref_words;
+        HIP_TRY(launch_batch_seg(c->gid.as<uint32_t>(), B, G, seg_lo, seg_cnt, s));
 
-        const Bins &B = P.bins;
         BatchArgs b;
         std::memset(&b, 0, sizeof(b));
         b.g = internal_graph(c, g);
@@ -734,16 +748,17 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         b.slab = hs.slab;
         b.touched = hs.touched;
         b.tcount = hs.tcount;
+        b.seg_lo = seg_lo;
+        b.seg_cnt = seg_cnt;
+        b.pref = pref;
+        b.start = start;
+        b.nw = nw;
         int rate_khz = 0;
         HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
         b.timeout_ticks = (uint64_t)(kBarrierTimeoutS * 1e3 * (double)(rate_khz > 0 ? rate_khz : 100000));
-        const uint64_t units = (uint64_t)B.cnt[BIN_HUB] + B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE] +
-                               (B.cnt[BIN_GROUP] + 3) / 4 + (B.cnt[BIN_THREAD] + 63) / 64;
-        const uint64_t cap_blocks = (uint64_t)batch_blocks_per_cu() * c->num_cu;
-        const uint32_t nblocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap_blocks, (units + 3) / 4));
-
         // the captured graph depends on exactly these values
-        std::vector<unsigned char> key(sizeof(b) + sizeof(nblocks) + sizeof(labels) + sizeof(n) + sizeof(s));
+        std::vector<unsigned char> key(sizeof(b) + sizeof(nblocks) + sizeof(labels) + sizeof(n) + sizeof(s) +
+                                       sizeof(slots));
         {
             unsigned char *k = key.data();
             std::memcpy(k, &b, sizeof(b));
@@ -755,6 +770,8 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
             std::memcpy(k, &n, sizeof(n));
             k += sizeof(n);
             std::memcpy(k, &s, sizeof(s));
+            k += sizeof(s);
+            std::memcpy(k, &slots, sizeof(slots));
         }
         if (!c->bexec || key != c->bkey) {
             if (c->bexec) {
@@ -773,7 +790,7 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
             if (e == hipSuccess) e = launch_fill_u64(L.arcs, 0, 1, cs);
             if (e == hipSuccess) e = launch_fill_u32(L.n_active, G, 1, cs);
             if (e == hipSuccess) e = launch_fill_u32(L.bar, 0, 2, cs);
-            if (e == hipSuccess && max_iter) e = launch_batch(b, nblocks, cs);
+            if (e == hipSuccess && max_iter) e = launch_batch(b, nblocks, slots, cs);
             if (e == hipSuccess)
                 e = launch_batch_out(labels, c->old_of.as<uint32_t>(), c->gid.as<uint32_t>(), b.L0, b.L1, L.iters,
                                      b.gv, n, cs);
@@ -947,7 +964,7 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->items,      &c->ritems,   &c->slab_off, &c->slab_mask, &c->touched_off, &c->tcount,
                       &c->best,       &c->own_sum,  &c->hflags,   &c->rowsum,    &c->slab,        &c->touched,
                       &c->K,          &c->mod_sums, &c->partials, &c->cand,      &c->thr,         &c->item_lo,
-                      &c->mrows,      &c->slab_pending, &c->gid,  &c->gvd,      &c->bstate};
+                      &c->mrows,      &c->slab_pending, &c->gid,  &c->gvd,      &c->bstate, &c->bseg};
     if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) b->release();

@@ -106,12 +106,14 @@ def test_mixed_batch_all_bins(gg, orc, lpa, ctx):
     check_graphs(orc, b, lab, st, range(b.G), 0.05, 20)
 
 
-def test_mixed_batch_small_thresholds_long_rows(gg, orc, lpa):
-    # rows above 40 arcs go through the per-row slab; many graphs then have
-    # long rows
+@pytest.mark.parametrize("wave_max", [16, 40])
+def test_mixed_batch_small_thresholds_long_rows(gg, orc, lpa, wave_max):
+    # rows above 40 arcs go through the per-row slab, so many graphs have
+    # long rows; with wave_max = 40 no row needs the 1024-slot tables and the
+    # long rows are merged in 128-arc chunks
     graphs = mixed_graphs(gg)
     b = gg.pack(graphs)
-    c = lpa.Context(0, thread_max=4, group_max=8, wave_max=16, wide_max=40)
+    c = lpa.Context(0, thread_max=4, group_max=8, wave_max=wave_max, wide_max=40)
     try:
         lab, st = run_batch(lpa, c, b)
     finally:

@@ -3,7 +3,10 @@ configuration bench.py times (default options, tol 0.05, max 20 rounds,
 self weight 1): the planted-partition SBM, R-MAT scale 22 and the
 4096 x 4096 road lattice are each run in full by the oracle and compared
 bit-exactly (labels, per-round changed counts, iterations), and the
-modularity integer terms are compared exactly.
+modularity integer terms are compared exactly.  The batched run is
+compared graph by graph: every graph of the 4096-graph batch with about
+1e8 arcs, and a sample (with the largest graphs) of the 4096-graph batch
+with about 1.7e9 arcs, plus properties checked on every graph.
 """
 import sys
 import time
@@ -71,3 +74,52 @@ def test_road4096_full(gg, orc, lpa, ctx):
     g = gg.road(4096, 4096, 0.3, 0.01, 1, 8, seed=4096)
     say(f"road generated in {time.time() - t:.1f}s: n={g.n} m={g.m}")
     full_compare(gg, orc, lpa, ctx, g)
+
+
+def batch_compare(orc, lpa, ctx, b, which):
+    t = time.time()
+    dg = lpa.DeviceGraph.from_csr(b.csr, "cuda")
+    lab, st = ctx.run_batch(dg, b.gv, tol=0.05, max_iter=20)
+    got = lpa.labels_to_numpy(lab)
+    say(f"{b.csr.name}: gpu {st.rounds} rounds, {st.converged_graphs}/{st.graphs} converged, "
+        f"{st.ms_device:.1f} ms device, {st.ms_total:.1f} ms call")
+    n_g = np.diff(b.gv).astype(np.int64)
+    # properties of every graph: round counts, tolerance test, local labels
+    assert st.iterations.max() <= 20 and st.iterations.min() >= 1
+    thr = np.floor(0.05 * n_g.astype(np.float64)).astype(np.int64)
+    conv = st.changed_last.astype(np.int64) <= thr
+    assert np.array_equal(st.converged, conv)
+    assert np.all(st.converged | (st.iterations == 20))
+    owner = np.repeat(np.arange(b.G), n_g)
+    assert np.all(got.astype(np.int64) < n_g[owner])
+    for k in which:
+        g = b.graph(k)
+        ref = orc.rak(g, tol=0.05, max_iter=20, self_weight=1)
+        v0, v1 = int(b.gv[k]), int(b.gv[k + 1])
+        assert st.changed(k) == ref.changed, (k, st.changed(k), ref.changed)
+        assert bool(st.converged[k]) == ref.converged
+        mism = np.flatnonzero(got[v0:v1] != ref.labels)
+        assert mism.size == 0, f"graph {k} (n={g.n}): {mism.size} labels differ"
+    say(f"{b.csr.name}: {len(which)} graphs checked against the oracle in {time.time() - t:.1f}s")
+
+
+@pytest.mark.timeout(900)
+def test_batch_50m_reading_every_graph(gg, orc, lpa, ctx):
+    # 4096 SBM graphs, n log-uniform in [200, 6150]: about 1e8 arcs in total
+    t = time.time()
+    b = gg.sbm_batch(4096, 200, 6150, seed=4096)
+    say(f"batch-50M generated in {time.time() - t:.1f}s: n={b.csr.n} m={b.csr.m}")
+    batch_compare(orc, lpa, ctx, b, range(b.G))
+
+
+@pytest.mark.timeout(1200)
+def test_batch_literal_sampled(gg, orc, lpa, ctx):
+    # 4096 SBM graphs, n log-uniform in [200, 200000]: about 1.7e9 arcs; the
+    # oracle re-runs a seeded sample that includes the four largest graphs
+    t = time.time()
+    b = gg.sbm_batch(4096, 200, 200000, seed=4096)
+    say(f"batch literal generated in {time.time() - t:.1f}s: n={b.csr.n} m={b.csr.m}")
+    n_g = np.diff(b.gv)
+    rng = np.random.default_rng(4096)
+    which = sorted(set(rng.choice(b.G, 24, replace=False).tolist()) | set(np.argsort(n_g)[-4:].tolist()))
+    batch_compare(orc, lpa, ctx, b, which)
