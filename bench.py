@@ -55,17 +55,63 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, rounds: int):
+def cpu_baseline(g, budget_s: float):
     """The oracle as it stands (sequential C, one core) on a bounded sample:
-    its first `rounds` rounds on the same graph."""
+    its rounds on the same graph from the unique initial labels, one at a
+    time, until the time budget is spent (at least one round)."""
     import oracle
-    t0 = time.perf_counter()
-    r = oracle.rak(g, tol=0.0, max_iter=rounds, self_weight=1)
+    labels = np.arange(g.n, dtype=np.uint32)
+    rounds, t0 = 0, time.perf_counter()
+    while rounds < 20:
+        labels, _ = oracle.rak_round(g, labels, self_weight=1)
+        rounds += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
     dt = time.perf_counter() - t0
-    arcs = g.m * r.iterations
+    arcs = g.m * rounds
     return {"value": arcs / dt / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {r.iterations} rounds of the sequential oracle on the same graph "
+            "sample": f"first {rounds} rounds of the sequential oracle on the same graph "
                       f"({arcs} arcs voted in {dt:.1f} s)"}
+
+
+def copy_calibration():
+    """A plain device copy of known size (256 MiB read, 256 MiB written),
+    run so that a hardware-counter profile of this process holds a reference
+    for its byte counters."""
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 copies of {src.numel() * 4} bytes")
+
+
+def traffic_from_profile(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` measured with hardware counters for
+    this workload, from the committed profile summary, or None when there is
+    none or when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2301_09125_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(src, f), "rb").read())
+    if kv.get("kernel_sources_sha256") != h.hexdigest()[:16]:
+        log(f"[bench] {path}: kernel sources changed since the counters were taken; traffic = null")
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline_batch(b, budget_s: float = 15.0):
@@ -132,12 +178,13 @@ def run_batch_bench(args, b, desc, P):
     log(f"[bench] {args.steps} steps in {elapsed:.3f}s: {ms_per_step:.3f} ms/step ({dev_ms:.3f} ms device), "
         f"{value:.2f} GE/s, {achieved:.1f} GB/s algorithmic")
     roofline = {"bound": "hbm", "kernel": "batch_k", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profile(args.workload, "batch_k"),
                 "avg_launch_ms": round(dev_ms, 4), "bytes_per_launch": int(bytes_step)}
     cpu = None
-    if args.cpu_rounds > 0:
+    if args.cpu_seconds > 0:
         log("[bench] cpu baseline: oracle on a sample of whole graphs ...")
-        cpu = cpu_baseline_batch(b)
+        cpu = cpu_baseline_batch(b, args.cpu_seconds)
         log(f"[bench] cpu baseline {cpu['value']:.4f} GE/s")
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GE/s", "n_gpus": 1, "steps": args.steps,
@@ -163,7 +210,10 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=0.05)
     ap.add_argument("--max-iter", type=int, default=20)
-    ap.add_argument("--cpu-rounds", type=int, default=3, help="oracle rounds for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="time budget of the oracle for cpu_baseline (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 256 MiB device copy first (reference for counter profiles)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     args = ap.parse_args()
 
@@ -180,6 +230,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     desc, gen = WORKLOADS[args.workload]
+    if args.copy_calibration:
+        copy_calibration()
     t0 = time.perf_counter()
     g = gen(gg)
     if isinstance(g, gg.Batch):
@@ -232,7 +284,7 @@ def main():
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None,
+                    "traffic": traffic_from_profile(args.workload, dom["name"]),
                     "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
                     "bytes_per_launch": dom["bytes"] // dom["launches"]}
         for p in prof:
@@ -242,9 +294,9 @@ def main():
                     f"  {gbs:8.1f} GB/s alg")
     round_ms = float(np.median([st0.ms_rounds / max(st0.iterations, 1)]))
     cpu = None
-    if args.cpu_rounds > 0:
-        log(f"[bench] cpu baseline: {args.cpu_rounds} oracle rounds ...")
-        cpu = cpu_baseline(g, args.cpu_rounds)
+    if args.cpu_seconds > 0:
+        log(f"[bench] cpu baseline: oracle rounds for about {args.cpu_seconds:.0f} s ...")
+        cpu = cpu_baseline(g, args.cpu_seconds)
         log(f"[bench] cpu baseline {cpu['value']:.4f} GE/s")
 
     out = {

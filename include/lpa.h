@@ -162,7 +162,8 @@ typedef struct {
     uint32_t converged_graphs;  /* graphs whose tolerance test passed */
     uint64_t arcs_processed;    /* sum over graphs of arcs x rounds voted */
     double ms_total;            /* host wall time of the call */
-    double ms_device;           /* device time of the captured run (HIP events) */
+    double ms_device;           /* duration of the persistent kernel (device
+                                   wall clock read at its start and end) */
     uint32_t *iterations;       /* [G] rounds executed per graph */
     int32_t *converged;         /* [G] 1 if changed_last[g] <= floor(tol * n_g) */
     uint64_t *changed_last;     /* [G] changed count of the graph's last round */

@@ -385,6 +385,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
     for (uint32_t s = lane; s < SLOTS; s += 64) T[s] = EMPTY_SLOT;
     wave_sync();
     const uint32_t w = blockIdx.x * kBatchWaves + wave;
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.clock[0] = wall_clock64();
     // the work split of round 1: every graph votes
     if (blockIdx.x == 0) decide(b, 0);
     if (!grid_barrier(b, nblocks)) return;
@@ -406,6 +407,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
         if (__hip_atomic_load(b.n_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
         if (__hip_atomic_load(b.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (ERR_COL | ERR_GRAPH)) break;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.clock[1] = wall_clock64();
 }
 
 // Graph of each internal vertex: binary search of old_of[r] in gv.

@@ -159,6 +159,7 @@ struct BatchArgs {
     unsigned long long *hist;    // [G * hist_len] changed counts of rounds 1..hist_len
     uint32_t hist_len;
     unsigned long long *arcs;    // arcs voted, summed over graphs
+    unsigned long long *clock;   // [2] wall clock at the kernel's start and end (block 0)
     uint32_t *n_active;          // graphs still voting
     uint32_t *bar;               // [0] arrivals, [1] generation
     uint32_t *err;

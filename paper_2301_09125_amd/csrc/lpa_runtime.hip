@@ -58,10 +58,12 @@ struct DevBuf {
 };
 
 enum KernelId {
-    K_THREAD, K_GROUP, K_WAVE, K_WIDE, K_HUB, K_MERGE, K_FALLBACK, K_REDUCE, K_FINAL, K_MOD, K_COUNT
+    K_THREAD, K_GROUP, K_WAVE, K_WIDE, K_HUB, K_HUB1, K_MERGE, K_FALLBACK, K_REDUCE, K_FINAL, K_MOD, K_COUNT
 };
-const char *kKernelNames[K_COUNT] = {"vote_thread", "vote_group", "vote_wave",  "vote_wide",  "vote_hub",
-                                     "hub_merge",   "hub_fallback", "hub_reduce", "hub_final", "modularity"};
+// vote_hub_first: the long-row vote of round 1 from the unique labels
+const char *kKernelNames[K_COUNT] = {"vote_thread",  "vote_group", "vote_wave",    "vote_wide",
+                                     "vote_hub",     "vote_hub_first", "hub_merge", "hub_fallback",
+                                     "hub_reduce",   "hub_final",  "modularity"};
 
 struct Pending {
     int kid;
@@ -408,7 +410,7 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
     }));
     if (P.H) {
         const uint32_t *mrows = c->mrows.as<uint32_t>();
-        LPA_TRY(timed(c, K_HUB, bytes(BIN_HUB), B.arcs[BIN_HUB], [&] {
+        LPA_TRY(timed(c, first ? K_HUB1 : K_HUB, bytes(BIN_HUB), B.arcs[BIN_HUB], [&] {
             return launch_vote_hub(ra, c->items.as<HubItem>(), P.n_items, hs, first, c->num_cu * 5, s);
         }));
         LPA_TRY(timed(c, K_MERGE, 0, 0, [&] {
@@ -603,7 +605,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
 // parameter changes.
 
 struct BatchLayout {
-    u64 *thr, *changed, *last, *hist, *arcs;
+    u64 *thr, *changed, *last, *hist, *arcs, *clock;
     uint32_t *active, *iters, *n_active, *bar;
     int32_t *conv;
     size_t bytes;
@@ -623,6 +625,7 @@ BatchLayout batch_layout(void *base, uint32_t G, uint32_t hist_len) {
     L.last = reinterpret_cast<u64 *>(take((size_t)G * 8));
     L.hist = reinterpret_cast<u64 *>(take((size_t)G * hist_len * 8));
     L.arcs = reinterpret_cast<u64 *>(take(8));
+    L.clock = reinterpret_cast<u64 *>(take(16));
     L.active = reinterpret_cast<uint32_t *>(take((size_t)G * 4));
     L.iters = reinterpret_cast<uint32_t *>(take((size_t)G * 4));
     L.conv = reinterpret_cast<int32_t *>(take((size_t)G * 4));
@@ -753,9 +756,11 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         b.pref = pref;
         b.start = start;
         b.nw = nw;
+        b.clock = L.clock;
         int rate_khz = 0;
         HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
-        b.timeout_ticks = (uint64_t)(kBarrierTimeoutS * 1e3 * (double)(rate_khz > 0 ? rate_khz : 100000));
+        if (rate_khz <= 0) rate_khz = 100000;
+        b.timeout_ticks = (uint64_t)(kBarrierTimeoutS * 1e3 * (double)rate_khz);
         // the captured graph depends on exactly these values
         std::vector<unsigned char> key(sizeof(b) + sizeof(nblocks) + sizeof(labels) + sizeof(n) + sizeof(s) +
                                        sizeof(slots));
@@ -790,6 +795,7 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
             if (e == hipSuccess) e = launch_fill_u64(L.arcs, 0, 1, cs);
             if (e == hipSuccess) e = launch_fill_u32(L.n_active, G, 1, cs);
             if (e == hipSuccess) e = launch_fill_u32(L.bar, 0, 2, cs);
+            if (e == hipSuccess) e = launch_fill_u64(L.clock, 0, 2, cs);
             if (e == hipSuccess && max_iter) e = launch_batch(b, nblocks, slots, cs);
             if (e == hipSuccess)
                 e = launch_batch_out(labels, c->old_of.as<uint32_t>(), c->gid.as<uint32_t>(), b.L0, b.L1, L.iters,
@@ -805,11 +811,7 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
             }
             c->bkey = key;
         }
-        if (!c->round_a) HIP_TRY(hipEventCreate(&c->round_a));
-        if (!c->round_b) HIP_TRY(hipEventCreate(&c->round_b));
-        HIP_TRY(hipEventRecord(c->round_a, s));
         HIP_TRY(hipGraphLaunch(c->bexec, s));
-        HIP_TRY(hipEventRecord(c->round_b, s));
         uint32_t errbits = 0;
         HIP_TRY(hipMemcpyAsync(&errbits, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(it_h.data(), L.iters, (size_t)G * 4, hipMemcpyDeviceToHost, s));
@@ -818,10 +820,10 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         if (stats && stats->changed_hist && hist_len)
             HIP_TRY(hipMemcpyAsync(hist_h.data(), L.hist, hist_h.size() * 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&arcs_h, L.arcs, 8, hipMemcpyDeviceToHost, s));
+        u64 clock_h[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(clock_h, L.clock, 16, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
-        ms_dev = ms;
+        ms_dev = clock_h[1] > clock_h[0] ? (double)(clock_h[1] - clock_h[0]) / (double)rate_khz : 0.0;
         if (errbits & ERR_TIMEOUT) c->slab_dirty = true;
         if (errbits) return err_status(errbits);
     }
