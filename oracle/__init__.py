@@ -50,6 +50,8 @@ def _load():
         lib.orc_rak.restype = ctypes.c_int
         lib.orc_rak_round.argtypes = [u32, vp, vp, vp, u32, vp, vp, vp]
         lib.orc_rak_round.restype = ctypes.c_int64
+        lib.orc_rak_round_top2.argtypes = [u32, vp, vp, vp, u32, vp, vp, vp, vp]
+        lib.orc_rak_round_top2.restype = ctypes.c_int64
         lib.orc_rak_masked.argtypes = [u32, vp, vp, vp, u32, u32, vp, vp, vp, vp]
         lib.orc_rak_masked.restype = ctypes.c_int
         lib.orc_modularity.argtypes = [u32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -111,6 +113,22 @@ def rak_round(g, labels: np.ndarray, self_weight: int = 1, active: np.ndarray | 
     if ch < 0:
         raise OracleError(int(ch))
     return new, int(ch)
+
+
+def rak_round_top2(g, labels: np.ndarray, self_weight: int = 1):
+    """One synchronous round over every vertex; returns (new_labels, changed,
+    top1, top2): the winning tally of each vertex and the largest tally of
+    any other label in its closed neighbourhood (0 if none)."""
+    rp, col, w = _arrs(g)
+    old = np.ascontiguousarray(labels, dtype=np.uint32)
+    new = np.empty_like(old)
+    t1 = np.zeros(g.n, dtype=np.uint64)
+    t2 = np.zeros(g.n, dtype=np.uint64)
+    ch = _load().orc_rak_round_top2(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight,
+                                    old.ctypes.data, new.ctypes.data, t1.ctypes.data, t2.ctypes.data)
+    if ch < 0:
+        raise OracleError(int(ch))
+    return new, int(ch), t1, t2
 
 
 def rak_masked(g, masks: np.ndarray, self_weight: int = 1, init_labels=None):

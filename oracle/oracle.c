@@ -64,9 +64,13 @@ static int check_csr(uint32_t n, const uint64_t *rp, const uint32_t *col, const 
     return 0;
 }
 
-/* The label vertex v takes from L_old.  buf must hold deg(v)+1 pairs. */
+/* The label vertex v takes from L_old.  buf must hold deg(v)+1 pairs.
+ * When top1/top2 are given they receive the winning tally and the largest
+ * tally of any other label (0 when there is none; both 0 for an empty
+ * vote). */
 static uint32_t vote(uint32_t v, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
-                     uint32_t self_weight, const uint32_t *L_old, pair_lw *buf) {
+                     uint32_t self_weight, const uint32_t *L_old, pair_lw *buf, uint64_t *top1,
+                     uint64_t *top2) {
     uint64_t k = 0;
     if (self_weight > 0) {
         buf[k].label = L_old[v];
@@ -78,10 +82,12 @@ static uint32_t vote(uint32_t v, const uint64_t *rp, const uint32_t *col, const 
         buf[k].weight = w ? w[e] : 1u;
         ++k;
     }
+    if (top1) *top1 = 0;
+    if (top2) *top2 = 0;
     if (k == 0) return L_old[v];
     qsort(buf, (size_t)k, sizeof(pair_lw), by_label);
     uint32_t best_label = 0;
-    uint64_t best_weight = 0;
+    uint64_t best_weight = 0, second_weight = 0;
     int have = 0;
     uint64_t i = 0;
     while (i < k) {
@@ -91,11 +97,16 @@ static uint32_t vote(uint32_t v, const uint64_t *rp, const uint32_t *col, const 
         /* labels arrive in increasing order, so a strictly larger sum is
          * needed to displace the current best: ties keep the lower label */
         if (!have || sum > best_weight) {
+            if (have) second_weight = best_weight;
             best_label = lab;
             best_weight = sum;
             have = 1;
+        } else if (sum > second_weight) {
+            second_weight = sum;
         }
     }
+    if (top1) *top1 = best_weight;
+    if (top2) *top2 = second_weight;
     return best_label;
 }
 
@@ -116,7 +127,29 @@ int64_t orc_rak_round(uint32_t n, const uint64_t *rp, const uint32_t *col, const
     if (!buf) return -3;
     int64_t changed = 0;
     for (uint32_t v = 0; v < n; ++v) {
-        uint32_t lab = (active && !active[v]) ? L_old[v] : vote(v, rp, col, w, self_weight, L_old, buf);
+        uint32_t lab = (active && !active[v]) ? L_old[v] : vote(v, rp, col, w, self_weight, L_old, buf, NULL, NULL);
+        L_new[v] = lab;
+        changed += (lab != L_old[v]);
+    }
+    free(buf);
+    return changed;
+}
+
+/* One synchronous round over every vertex that also reports, per vertex,
+ * the winning tally (top1) and the largest tally of any other label (top2),
+ * both including the self weight on the vertex's own label.  Returns the
+ * number of changed vertices or a negative code. */
+int64_t orc_rak_round_top2(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                           uint32_t self_weight, const uint32_t *L_old, uint32_t *L_new, uint64_t *top1,
+                           uint64_t *top2) {
+    if (!top1 || !top2) return -1;
+    int rc = check_csr(n, rp, col, w, self_weight);
+    if (rc) return rc;
+    pair_lw *buf = (pair_lw *)malloc((size_t)(max_degree(n, rp) + 1) * sizeof(pair_lw));
+    if (!buf) return -3;
+    int64_t changed = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+        uint32_t lab = vote(v, rp, col, w, self_weight, L_old, buf, &top1[v], &top2[v]);
         L_new[v] = lab;
         changed += (lab != L_old[v]);
     }
