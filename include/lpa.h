@@ -90,6 +90,14 @@ typedef struct {
     uint32_t modularity;   /* nonzero: lpa_run also reports the modularity of
                               its result in lpa_stats (same definition as
                               lpa_modularity) */
+    uint32_t frontier;     /* 0: lpa_run votes every vertex in every round;
+                              1: from round 2 on it votes only the vertices
+                              that can change -- those whose closed
+                              neighbourhood changed in the previous round
+                              (frontier-based propagation, Section 2).  A
+                              vertex outside that set sees the tally of its
+                              last vote again, so the labels, changed counts
+                              and rounds are identical to mode 0. */
 } lpa_options;
 
 /* Run statistics.  The arrays are optional and owned by the caller; when
@@ -190,6 +198,102 @@ typedef struct {
  * an arc leaving its graph, and LPA_ETIMEDOUT. */
 lpa_status lpa_run_batch(lpa_ctx *ctx, const lpa_csr *packed, const uint64_t *graph_vptr, uint32_t G,
                          uint32_t *labels_out, double tol, uint32_t max_iter, lpa_batch_stats *stats);
+
+/* ---- Learned frontier -------------------------------------------------
+ *
+ * Not part of the paper: a small network predicts, for every vertex that
+ * may change in a round (see lpa_options.frontier), whether it will; only the
+ * predicted changers are voted, the others keep their label for that round.
+ * Features of vertex v before round t, from the state after round t-1
+ * (top1 / top2 = winning and runner-up tally of v's most recent vote, both
+ * including the self weight; k = weighted degree; sw = self weight):
+ *   f1 = log2(1 + deg v)         f2 = (top1 - top2) / (k + sw)
+ *   f3 = 1 if v changed in t-1   f4 = top1 / (k + sw)
+ *   f5 = 1 if v or a neighbour changed in t-1 (1 when not tracked)
+ *   f6 = t / max_iter
+ * Network: h1 = relu(x W1 + b1); h2 = relu(bf16(h1) W2 + b2);
+ * z = h2 . w3 + b3, with x, W1, W2 and w3 rounded to bfloat16 and FP32
+ * accumulation; v is voted iff sigmoid(z) >= tau. */
+typedef struct {
+    float w1[6][32];
+    float b1[32];
+    float w2[32][32];
+    float b2[32];
+    float w3[32];
+    float b3;
+    float tau;  /* decision threshold in [0, 1]; 0 votes every candidate */
+} lpa_mlp;
+
+typedef struct {
+    uint32_t iterations;        /* rounds executed */
+    int32_t converged;          /* 1 if the run ended by a passed full check */
+    uint32_t learned_rounds;    /* rounds in which the network chose */
+    uint32_t check_round;       /* first round that voted every candidate
+                                   after the learned rounds (0: none) */
+    uint64_t changed_last;
+    uint64_t arcs_processed;    /* arcs of the rows actually voted */
+    double ms_total;
+    double ms_rounds;
+    uint64_t *changed_per_iter;    /* host, cap entries, or NULL */
+    uint64_t *voted_per_iter;      /* rows voted per round, or NULL */
+    uint64_t *candidates_per_iter; /* rows that could change per round, or NULL */
+    uint32_t cap;
+} lpa_learned_stats;
+
+/* RAK with the learned frontier.  Round 1 votes every vertex.  Each later
+ * round votes the candidates the network keeps, until a round changes at
+ * most floor(tol * n) labels; the next round then votes every candidate (a
+ * full check, equivalent to voting every vertex).  If the check passes the
+ * run has converged; otherwise rounds go on voting every candidate (plain
+ * RAK) until the tolerance test passes or max_iter rounds have run.  Rows
+ * longer than wide_max arcs are voted in every round.
+ * model: host.  masks: device u8[mask_rounds * n] or NULL; row t-1 receives
+ * 1 for every vertex voted in round t (by original id), for replaying the
+ * run.  The result approximates lpa_run's; with tau = 0 it is identical.
+ * Errors: those of lpa_run, LPA_EINVAL for tau outside [0, 1]. */
+lpa_status lpa_run_learned(lpa_ctx *ctx, const lpa_csr *g, const lpa_mlp *model, uint32_t *labels_out,
+                           double tol, uint32_t max_iter, lpa_learned_stats *stats, uint8_t *masks,
+                           uint32_t mask_rounds);
+
+/* Training samples from a plain run (every vertex voted every round, exact
+ * f5): for every round t >= 2 and every row of at most wide_max arcs with
+ * at least one arc, the features before round t (6 floats, unrounded) and
+ * y = 1 if the row changed in round t.  X: device float[cap * 6], y: device
+ * u8[cap]; *count receives the number of samples (also when above cap, in
+ * which case only cap were written).  The run stops as lpa_run does. */
+lpa_status lpa_trace(lpa_ctx *ctx, const lpa_csr *g, double tol, uint32_t max_iter, float *X, uint8_t *y,
+                     uint64_t cap, uint64_t *count);
+
+typedef struct {
+    uint32_t epochs;       /* passes over the samples */
+    uint32_t batch;        /* samples per Adam step, a multiple of 256 */
+    float lr;              /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+    float pos_weight;      /* weight of the positive class in the loss */
+    uint64_t seed;         /* sample order of each epoch */
+    const float *val_X;    /* device validation samples, or NULL */
+    const uint8_t *val_y;
+    uint64_t val_n;
+    float recall;          /* with validation samples: tau is set to the
+                              largest value that keeps at least this
+                              fraction of the positive validation samples */
+} lpa_train_options;
+
+/* Train model (host, in: initial weights, out: trained weights) on device
+ * samples X (float[N * 6]) and y (u8[N]) with the weighted binary
+ * cross-entropy of the logit, mean over each batch.  loss_per_epoch: host
+ * float[epochs] (mean training loss of each epoch) or NULL. */
+lpa_status lpa_train(lpa_ctx *ctx, const float *X, const uint8_t *y, uint64_t N, const lpa_train_options *opt,
+                     lpa_mlp *model, float *loss_per_epoch);
+
+/* Logits of N samples (device X float[N * 6] -> device z float[N]) with the
+ * inference arithmetic used by lpa_run_learned. */
+lpa_status lpa_mlp_forward(lpa_ctx *ctx, const lpa_mlp *model, const float *X, uint64_t N, float *z);
+
+/* Loss and gradient (host float[1313], in the lpa_mlp field order w1, b1,
+ * w2, b2, w3, b3) of the training loss over all N samples, as lpa_train
+ * computes them for one batch (N <= 2^31). */
+lpa_status lpa_mlp_grad(lpa_ctx *ctx, const lpa_mlp *model, const float *X, const uint8_t *y, uint64_t N,
+                        float pos_weight, float *grad, float *loss);
 
 /* Copy up to `cap` per-kernel profile records into out (host); *count gets
  * the number of records available.  lpa_profile_reset clears them. */

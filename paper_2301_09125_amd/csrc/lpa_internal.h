@@ -79,6 +79,9 @@ struct RoundArgs {
     uint32_t check;               // nonzero: verify weighted degrees fit 32 bits
     unsigned long long *changed;  // this round's kCountWords counter words
     uint32_t *err;                // error bits
+    const uint32_t *list;         // rows of the launch: list[0..min(cnt, *list_n)) (NULL: lo .. lo+cnt-1)
+    const uint32_t *list_n;       // device count of list entries
+    uint32_t *top1, *top2;        // vote kernels with FEAT: winning / runner-up tally per row
 };
 
 // A wavefront work item of a long row: internal row r (= hub index), arcs
@@ -177,6 +180,36 @@ struct BatchArgs {
     uint64_t timeout_ticks;      // wall-clock ticks one barrier may wait
 };
 
+// Learned frontier (lpa_learned.hip).  A model in the lane layouts of the
+// 32x32x8 bfloat16 MFMA: a1[l] = W1[4*(l/32)+c][l%32] for c = 0..3 (rows 6
+// and 7 zero), a2[s][l] = W2[8s+4*(l/32)+c][l%32], four bfloat16 per u64.
+struct MlpDev {
+    uint64_t a1[64];
+    uint64_t a2[4][64];
+    float b1[32], b2[32];
+    float w3[32];  // rounded to bfloat16
+    float b3;
+    float zcut;    // keep a candidate iff its logit >= zcut
+};
+
+struct FrontArgs {
+    Graph g;
+    const uint32_t *L_old;
+    uint32_t *L_new;
+    const uint32_t *top1, *top2;  // tallies of each vertex's last vote
+    const uint32_t *kw;           // weighted degree (NULL: unit weights)
+    uint32_t *lastchg;            // last round the vertex changed (0: never)
+    uint32_t *front;              // == t: the vertex or a neighbour changed in round t-1
+    uint8_t *stale;               // skipped since its last vote
+    uint8_t *mask;                // round's vote mask by original id, or NULL
+    const uint32_t *old_of;
+    unsigned long long *cand_count;  // += candidates of the round
+    unsigned long long *kept_arcs;   // += arcs of the rows kept for the vote
+    uint32_t sw, t, max_iter;
+    uint32_t all_dirty;  // every vertex counts as having a changed neighbour
+    uint32_t keep_all;   // vote every candidate (no prediction)
+};
+
 // ---- launchers: lpa_prep.hip ---------------------------------------------
 hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t count, hipStream_t s);
@@ -205,14 +238,12 @@ hipError_t launch_scatter_labels(uint32_t *labels_out, const uint32_t *old_of, c
 
 // ---- launchers: lpa_vote.hip ---------------------------------------------
 // first = 1: round 1 from the unique initial labels L0(v) = v.
-hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int grid_cap,
+hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int grid_cap,
                               hipStream_t s);
-hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int grid_cap,
+hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int grid_cap,
                              hipStream_t s);
-hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int grid_cap,
-                            hipStream_t s);
-// Long rows, one wavefront per segment: the direct max (round 1), the top-K
-// report, or for HUB_BIG rows the slab merge; own-label tallies for all.
+hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int feat,
+                            int grid_cap, hipStream_t s);
 hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
                            int first, int grid_cap, hipStream_t s);
 // Merge the top-K reports of each listed row; undecided rows get HUB_FALLBACK.
@@ -239,6 +270,22 @@ hipError_t launch_batch(const BatchArgs &b, uint32_t nblocks, int slots, hipStre
 int batch_slots(const Bins &bins);
 int batch_blocks_per_cu(int slots);
 int batch_waves_per_block();
+
+hipError_t launch_predict(const FrontArgs &p, const MlpDev *model, uint32_t lo, uint32_t cnt, uint32_t *list,
+                          uint32_t *list_count, int num_cu, hipStream_t s);
+hipError_t launch_push(const FrontArgs &p, const Bins &B, int mark, hipStream_t s);
+hipError_t launch_trace_x(const FrontArgs &p, uint32_t lo, uint32_t cnt, float *X, hipStream_t s);
+hipError_t launch_trace_y(const uint32_t *L_old, const uint32_t *L_new, uint32_t lo, uint32_t cnt, uint8_t *y,
+                          hipStream_t s);
+hipError_t launch_mlp_forward(const MlpDev *model, const float *X, uint64_t N, float *z, hipStream_t s);
+int mlp_params();
+hipError_t launch_train_step(const float *X, const uint8_t *y, uint64_t N, uint64_t mul, uint64_t add,
+                             uint64_t start, uint32_t bn, float *wm, float *m, float *v, float *part, float *grad,
+                             float pos_weight, float lr, float c1, float c2, float *loss_acc, int update,
+                             hipStream_t s);
+hipError_t launch_row_sums(const Graph &g, uint32_t *kw, hipStream_t s);
+hipError_t launch_mask_rows(uint8_t *mask, const uint32_t *old_of, uint32_t lo, uint32_t cnt, uint8_t val,
+                            hipStream_t s);
 
 hipError_t launch_mod_sumsq(const unsigned long long *K, uint32_t n, unsigned long long *partials,
                             uint32_t nparts, hipStream_t s);

@@ -96,6 +96,8 @@ struct lpa_ctx {
     DevBuf cand, thr, item_lo, mrows, slab_pending;
     DevBuf K, mod_sums, partials;
     DevBuf gid, gvd, bstate, bseg;  // batched run
+    DevBuf f_top1, f_top2, f_kw, f_last, f_front, f_stale, f_lists, f_small, f_model;  // frontier runs
+    DevBuf t_w, t_m, t_v, t_part, t_grad, t_loss, t_z;                               // training
     bool slab_dirty = false;      // slab may hold entries (set after a timed-out batch)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t bexec = nullptr;
@@ -149,6 +151,7 @@ lpa_status check_options(const lpa_options &o) {
     if (o.wave_max < o.group_max || o.wave_max > (uint32_t)kWaveArcsSmall) return LPA_EINVAL;
     if (o.wide_max < o.wave_max || o.wide_max > (uint32_t)kWaveArcs) return LPA_EINVAL;
     if (o.merge_max < 1 || o.merge_max > (uint32_t)kMergeBlockSegs) return LPA_EINVAL;
+    if (o.frontier > 1) return LPA_EINVAL;
     return LPA_OK;
 }
 
@@ -388,25 +391,34 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
 
 // Enqueue every vote kernel of one round.  first = round 1 from L0(v) = v.
 lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const HubState &hs, bool weighted,
-                         int first) {
+                         int first, int feat = 0, uint32_t *const *lists = nullptr,
+                         const uint32_t *list_n = nullptr) {
     const hipStream_t s = c->stream;
     // algorithmic bytes: per arc col, weight, gathered label; per vertex
-    // row_ptr, own label read, new label write
+    // row_ptr, own label read, new label write (rows of a list: unknown here)
     const uint64_t ab = weighted ? 12 : 8;
     const Bins &B = P.bins;
     const int cap = c->num_cu * 8;
-    auto bytes = [&](int b) { return ab * B.arcs[b] + 16ull * B.cnt[b]; };
+    auto bytes = [&](int b) { return lists ? 0ull : ab * B.arcs[b] + 16ull * B.cnt[b]; };
+    auto args = [&](int b) {
+        RoundArgs r = ra;
+        if (lists) {
+            r.list = lists[b];
+            r.list_n = list_n + b;
+        }
+        return r;
+    };
     LPA_TRY(timed(c, K_THREAD, bytes(BIN_THREAD), B.arcs[BIN_THREAD], [&] {
-        return launch_vote_thread(ra, B.lo[BIN_THREAD], B.cnt[BIN_THREAD], first, cap, s);
+        return launch_vote_thread(args(BIN_THREAD), B.lo[BIN_THREAD], B.cnt[BIN_THREAD], first, feat, cap, s);
     }));
     LPA_TRY(timed(c, K_GROUP, bytes(BIN_GROUP), B.arcs[BIN_GROUP], [&] {
-        return launch_vote_group(ra, B.lo[BIN_GROUP], B.cnt[BIN_GROUP], first, cap, s);
+        return launch_vote_group(args(BIN_GROUP), B.lo[BIN_GROUP], B.cnt[BIN_GROUP], first, feat, cap, s);
     }));
     LPA_TRY(timed(c, K_WAVE, bytes(BIN_WAVE), B.arcs[BIN_WAVE], [&] {
-        return launch_vote_wave(ra, B.lo[BIN_WAVE], B.cnt[BIN_WAVE], 0, first, cap, s);
+        return launch_vote_wave(args(BIN_WAVE), B.lo[BIN_WAVE], B.cnt[BIN_WAVE], 0, first, feat, cap, s);
     }));
     LPA_TRY(timed(c, K_WIDE, bytes(BIN_WIDE), B.arcs[BIN_WIDE], [&] {
-        return launch_vote_wave(ra, B.lo[BIN_WIDE], B.cnt[BIN_WIDE], 1, first, c->num_cu * 5, s);
+        return launch_vote_wave(args(BIN_WIDE), B.lo[BIN_WIDE], B.cnt[BIN_WIDE], 1, first, feat, c->num_cu * 5, s);
     }));
     if (P.H) {
         const uint32_t *mrows = c->mrows.as<uint32_t>();
@@ -547,6 +559,9 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         ra.check = (t == 1);
         ra.changed = counters + (size_t)(t - 1) * kCountWords;
         ra.err = err_dev;
+        ra.list = nullptr;
+        ra.list_n = nullptr;
+        ra.top1 = ra.top2 = nullptr;
         const int first = (t == 1 && !resume) ? 1 : 0;
         HIP_TRY(hipEventRecord(c->round_a, s));
         LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first));
@@ -594,6 +609,317 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     }
     return LPA_OK;
 }
+
+// -------------------------------------------------- frontier / learned --
+//
+// One engine runs three kinds of run on the relabelled graph:
+//   exact    rounds >= 2 vote only the vertices that can change (lossless);
+//   learned  rounds >= 2 vote the candidates the network keeps, then a full
+//            check round, then plain rounds if the check fails;
+//   trace    every round votes every vertex; before each round t >= 2 the
+//            features of the rows of at most wide_max arcs are written out,
+//            after it whether they changed.
+// Round 1 always votes every vertex (from the unique labels).  The vote
+// kernels record each row's winning and runner-up tally (FEAT); after every
+// round the push kernels stamp the rows that may change next.
+
+uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+float host_bf16_float(float f) {
+    const uint32_t u = (uint32_t)host_bf16(f) << 16;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+
+// Model in the MFMA lane layouts (MlpDev, lpa_internal.h).
+MlpDev make_mlp_dev(const lpa_mlp &m) {
+    MlpDev d;
+    std::memset(&d, 0, sizeof(d));
+    for (int l = 0; l < 64; ++l) {
+        uint64_t w = 0;
+        for (int c = 0; c < 4; ++c) {
+            const int k = 4 * (l / 32) + c;
+            const float x = k < 6 ? m.w1[k][l % 32] : 0.f;
+            w |= (uint64_t)host_bf16(x) << (16 * c);
+        }
+        d.a1[l] = w;
+        for (int st = 0; st < 4; ++st) {
+            uint64_t w2 = 0;
+            for (int c = 0; c < 4; ++c) w2 |= (uint64_t)host_bf16(m.w2[8 * st + 4 * (l / 32) + c][l % 32]) << (16 * c);
+            d.a2[st][l] = w2;
+        }
+    }
+    for (int j = 0; j < 32; ++j) {
+        d.b1[j] = m.b1[j];
+        d.b2[j] = m.b2[j];
+        d.w3[j] = host_bf16_float(m.w3[j]);
+    }
+    d.b3 = m.b3;
+    const double tau = m.tau;
+    d.zcut = tau <= 0.0 ? -INFINITY : (tau >= 1.0 ? INFINITY : (float)std::log(tau / (1.0 - tau)));
+    return d;
+}
+
+enum FrontMode { F_EXACT, F_LEARNED, F_TRACE };
+
+struct FrontRun {
+    FrontMode mode = F_EXACT;
+    const lpa_mlp *model = nullptr;
+    uint8_t *masks = nullptr;
+    uint32_t mask_rounds = 0;
+    float *tX = nullptr;
+    uint8_t *ty = nullptr;
+    uint64_t tcap = 0, tcount = 0;
+    // results
+    uint32_t iterations = 0;
+    int converged = 0;
+    uint32_t learned_rounds = 0, check_round = 0;
+    uint64_t changed_last = 0, arcs = 0;
+    double ms_rounds = 0;
+    std::vector<u64> changed, voted, cands;
+    std::vector<float> ms;
+    double q = 0;
+    uint64_t terms[4] = {0, 0, 0, 0};
+};
+
+lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, uint32_t max_iter,
+                         FrontRun &R) {
+    LPA_TRY(check_csr_args(g));
+    if (!labels && g->n && R.mode != F_TRACE) return LPA_EINVAL;
+    if (!(tol >= 0.0 && tol <= 1.0)) return LPA_EINVAL;
+    HIP_TRY(hipSetDevice(c->device));
+    const hipStream_t s = c->stream;
+    const uint32_t n = g->n;
+    if (n == 0) return LPA_OK;
+    const size_t cwords = (size_t)std::max<uint32_t>(max_iter, 1) * kCountWords + 1;
+    HIP_TRY(c->counters.ensure(cwords * sizeof(u64)));
+    u64 *counters = c->counters.as<u64>();
+    uint32_t *err_dev = reinterpret_cast<uint32_t *>(counters + (cwords - 1));
+    HIP_TRY(launch_fill_u64(counters, 0, cwords, s));
+    LPA_TRY(ensure_pinned(c, kCountWords + 32));
+    Plan P;
+    LPA_TRY(prepare(c, g, P, err_dev, true));
+    const Bins &B = P.bins;
+    HIP_TRY(c->La.ensure((size_t)n * 4));
+    HIP_TRY(c->Lb.ensure((size_t)n * 4));
+    HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(), nullptr, n, s));
+    for (DevBuf *b : {&c->f_top1, &c->f_top2, &c->f_last, &c->f_front}) HIP_TRY(b->ensure((size_t)n * 4));
+    HIP_TRY(c->f_stale.ensure(n));
+    HIP_TRY(c->f_lists.ensure((size_t)n * 4));
+    HIP_TRY(c->f_small.ensure(64));  // list counts [8], candidates, kept arcs
+    HIP_TRY(launch_fill_u32(c->f_last.as<uint32_t>(), 0, n, s));
+    HIP_TRY(launch_fill_u32(c->f_front.as<uint32_t>(), 0, n, s));
+    HIP_TRY(launch_fill_u32(c->f_top1.as<uint32_t>(), 0, n, s));
+    HIP_TRY(launch_fill_u32(c->f_top2.as<uint32_t>(), 0, n, s));
+    HIP_TRY(launch_fill_u64(reinterpret_cast<u64 *>(c->f_stale.p), 0, ((size_t)n + 7) / 8, s));
+    const Graph gi = internal_graph(c, g);
+    const uint32_t *kw = nullptr;
+    if (g->w) {
+        HIP_TRY(c->f_kw.ensure((size_t)n * 4));
+        HIP_TRY(launch_row_sums(gi, c->f_kw.as<uint32_t>(), s));
+        kw = c->f_kw.as<uint32_t>();
+    }
+    if (R.mode == F_LEARNED) {
+        if (!R.model) return LPA_EINVAL;
+        const MlpDev md = make_mlp_dev(*R.model);
+        HIP_TRY(c->f_model.ensure(sizeof(MlpDev)));
+        HIP_TRY(hipMemcpyAsync(c->f_model.p, &md, sizeof(MlpDev), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // md lives on this stack frame
+    }
+    // per-bin lists over the non-long bins, in one buffer
+    uint32_t *lists[NBINS] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    {
+        uint32_t off = 0;
+        for (int b = BIN_WIDE; b <= BIN_THREAD; ++b) {
+            lists[b] = c->f_lists.as<uint32_t>() + off;
+            off += B.cnt[b];
+        }
+    }
+    uint32_t *list_n = c->f_small.as<uint32_t>();                          // [NBINS]
+    u64 *cand_dev = reinterpret_cast<u64 *>(c->f_small.as<char>() + 32);  // candidates
+    const uint32_t nonhub_lo = B.lo[BIN_WIDE];
+    const uint32_t nonhub_cnt = B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE] + B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD];
+    const uint64_t nonisolated = (uint64_t)nonhub_cnt + B.cnt[BIN_HUB];
+    const uint64_t thr = (uint64_t)std::floor(tol * (double)n);
+    const bool weighted = g->w != nullptr;
+    const HubState hs = hub_state(c);
+    const uint64_t all_arcs = B.arcs[BIN_THREAD] + B.arcs[BIN_GROUP] + B.arcs[BIN_WAVE] + B.arcs[BIN_WIDE] +
+                              B.arcs[BIN_HUB];
+    // below this many changed vertices the next round's candidates are
+    // tracked exactly; above it every vertex counts as a candidate
+    const uint64_t push_limit = nonisolated / 4;
+    if (!c->round_a) HIP_TRY(hipEventCreate(&c->round_a));
+    if (!c->round_b) HIP_TRY(hipEventCreate(&c->round_b));
+
+    uint32_t *L_old = c->La.as<uint32_t>(), *L_new = c->Lb.as<uint32_t>();
+    int all_dirty = 1;
+    enum { PH_LEARN, PH_CHECK, PH_PLAIN } phase = R.mode == F_LEARNED ? PH_LEARN : PH_PLAIN;
+    for (uint32_t t = 1; t <= max_iter; ++t) {
+        RoundArgs ra;
+        ra.g = gi;
+        ra.L_old = L_old;
+        ra.L_new = L_new;
+        ra.rowflag = c->rowflag.as<uint8_t>();
+        ra.sw = c->opt.self_weight;
+        ra.check = t == 1;
+        ra.changed = counters + (size_t)(t - 1) * kCountWords;
+        ra.err = err_dev;
+        ra.list = nullptr;
+        ra.list_n = nullptr;
+        ra.top1 = c->f_top1.as<uint32_t>();
+        ra.top2 = c->f_top2.as<uint32_t>();
+        FrontArgs fa;
+        fa.g = gi;
+        fa.L_old = L_old;
+        fa.L_new = L_new;
+        fa.top1 = ra.top1;
+        fa.top2 = ra.top2;
+        fa.kw = kw;
+        fa.lastchg = c->f_last.as<uint32_t>();
+        fa.front = c->f_front.as<uint32_t>();
+        fa.stale = c->f_stale.as<uint8_t>();
+        fa.mask = (R.masks && t - 1 < R.mask_rounds) ? R.masks + (size_t)(t - 1) * n : nullptr;
+        fa.old_of = c->old_of.as<uint32_t>();
+        fa.cand_count = cand_dev;
+        fa.kept_arcs = cand_dev + 1;
+        fa.sw = c->opt.self_weight;
+        fa.t = t;
+        fa.max_iter = max_iter;
+        fa.all_dirty = all_dirty;
+        fa.keep_all = phase != PH_LEARN;
+        const bool full = t == 1 || R.mode == F_TRACE;
+        const bool learned_round = !full && phase == PH_LEARN;
+        uint64_t trace_base = R.tcount;
+        HIP_TRY(hipEventRecord(c->round_a, s));
+        if (full) {
+            if (fa.mask) HIP_TRY(launch_mask_rows(fa.mask, fa.old_of, 0, n, 1, s));
+            if (R.mode == F_TRACE && t >= 2 && R.tX && trace_base + nonhub_cnt <= R.tcap)
+                HIP_TRY(launch_trace_x(fa, nonhub_lo, nonhub_cnt, R.tX + trace_base * 6, s));
+            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, t == 1 ? 1 : 0, 1));
+        } else {
+            HIP_TRY(launch_fill_u32(list_n, 0, NBINS, s));
+            HIP_TRY(launch_fill_u64(cand_dev, 0, 2, s));
+            for (int b = BIN_WIDE; b <= BIN_THREAD; ++b)
+                HIP_TRY(launch_predict(fa, c->f_model.as<MlpDev>(), B.lo[b], B.cnt[b], lists[b], list_n + b,
+                                       c->num_cu, s));
+            if (fa.mask) {
+                HIP_TRY(launch_mask_rows(fa.mask, fa.old_of, B.lo[BIN_HUB], B.cnt[BIN_HUB], 1, s));
+                HIP_TRY(launch_mask_rows(fa.mask, fa.old_of, B.lo[BIN_ZERO], B.cnt[BIN_ZERO], 0, s));
+            }
+            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, 0, 1, lists, list_n));
+        }
+        HIP_TRY(hipEventRecord(c->round_b, s));
+        HIP_TRY(hipMemcpyAsync(c->pinned + 16, ra.changed, kCountWords * sizeof(u64), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (!full) HIP_TRY(hipMemcpyAsync(c->pinned + 2, c->f_small.p, 48, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (c->opt.profile) collect_profile(c);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
+        R.ms_rounds += ms;
+        const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
+        if (errbits) return err_status(errbits);
+        u64 changed = 0;
+        for (int k = 0; k < kCountSlots; ++k) changed += c->pinned[16 + (size_t)k * kCountStride];
+        u64 voted = nonisolated, cand = nonisolated, arcs = all_arcs;
+        if (!full) {
+            const uint32_t *ln = reinterpret_cast<const uint32_t *>(c->pinned + 2);
+            voted = B.cnt[BIN_HUB];
+            for (int b = BIN_WIDE; b <= BIN_THREAD; ++b) voted += ln[b];
+            cand = c->pinned[2 + 4] + B.cnt[BIN_HUB];
+            arcs = c->pinned[2 + 5] + B.arcs[BIN_HUB];
+        }
+        if (R.mode == F_TRACE && t >= 2) {
+            if (R.ty && trace_base + nonhub_cnt <= R.tcap)
+                HIP_TRY(launch_trace_y(L_old, L_new, nonhub_lo, nonhub_cnt, R.ty + trace_base, s));
+            R.tcount += nonhub_cnt;
+        }
+        R.changed.push_back(changed);
+        R.voted.push_back(voted);
+        R.cands.push_back(cand);
+        R.ms.push_back(ms);
+        R.arcs += arcs;
+        R.iterations = t;
+        R.changed_last = changed;
+        if (learned_round) ++R.learned_rounds;
+        // which vertices can change next round
+        const int mark = R.mode == F_TRACE || changed <= push_limit;
+        fa.t = t;
+        HIP_TRY(launch_push(fa, B, mark, s));
+        all_dirty = !mark;
+        std::swap(L_old, L_new);
+        if (full && R.mode != F_TRACE && t == 1) {
+            if (changed <= thr) {
+                R.converged = 1;
+                break;
+            }
+            continue;
+        }
+        if (R.mode == F_TRACE || phase == PH_PLAIN) {
+            if (changed <= thr) {
+                R.converged = 1;
+                break;
+            }
+        } else if (phase == PH_LEARN) {
+            if (changed <= thr) {
+                phase = PH_CHECK;
+                R.check_round = t + 1;
+            }
+        } else {  // the full check
+            if (changed <= thr) {
+                R.converged = 1;
+                break;
+            }
+            phase = PH_PLAIN;
+        }
+    }
+    if (labels) HIP_TRY(launch_scatter_labels(labels, c->old_of.as<uint32_t>(), L_old, n, s));
+    if (c->opt.modularity && labels) LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &R.q, R.terms));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
+    if (errbits) return err_status(errbits);
+    return LPA_OK;
+}
+
+// ---------------------------------------------------------------- training --
+
+constexpr int kMlpParams = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1;
+
+uint64_t splitmix(uint64_t &x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+lpa_status ensure_train_bufs(lpa_ctx *c, uint32_t max_batch, uint32_t epochs) {
+    const uint32_t nblk = (max_batch + 255) / 256;
+    HIP_TRY(c->t_w.ensure(kMlpParams * 4));
+    HIP_TRY(c->t_m.ensure(kMlpParams * 4));
+    HIP_TRY(c->t_v.ensure(kMlpParams * 4));
+    HIP_TRY(c->t_part.ensure((size_t)nblk * (kMlpParams + 1) * 4));
+    HIP_TRY(c->t_grad.ensure((kMlpParams + 1) * 4));
+    HIP_TRY(c->t_loss.ensure((size_t)std::max<uint32_t>(epochs, 1) * 4));
+    return LPA_OK;
+}
+
+}  // namespace
+
+namespace {
 
 // ------------------------------------------------------------- batched run --
 //
@@ -866,6 +1192,7 @@ void lpa_default_options(lpa_options *opt) {
     opt->merge_max = 512;
     opt->profile = 0;
     opt->modularity = 0;
+    opt->frontier = 0;
 }
 
 lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *opt) {
@@ -905,7 +1232,177 @@ lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *
 
 lpa_status lpa_run(lpa_ctx *ctx, const lpa_csr *g, uint32_t *labels_out, double tol, uint32_t max_iter,
                    lpa_stats *stats) {
-    return run_impl(ctx, g, labels_out, tol, max_iter, stats, false);
+    if (!ctx || !ctx->opt.frontier) return run_impl(ctx, g, labels_out, tol, max_iter, stats, false);
+    const auto t0 = std::chrono::steady_clock::now();
+    clear_stats(stats);
+    FrontRun R;
+    R.mode = F_EXACT;
+    LPA_TRY(frontier_impl(ctx, g, labels_out, tol, max_iter, R));
+    if (stats) {
+        stats->iterations = R.iterations;
+        stats->converged = R.converged;
+        stats->changed_last = R.changed_last;
+        stats->arcs_processed = R.arcs;
+        stats->ms_rounds = R.ms_rounds;
+        stats->modularity = R.q;
+        for (int i = 0; i < 4; ++i) stats->mod_terms[i] = R.terms[i];
+        for (uint32_t t = 0; t < R.iterations && t < stats->cap; ++t) {
+            if (stats->changed_per_iter) stats->changed_per_iter[t] = R.changed[t];
+            if (stats->ms_per_iter) stats->ms_per_iter[t] = R.ms[t];
+        }
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return LPA_OK;
+}
+
+lpa_status lpa_run_learned(lpa_ctx *ctx, const lpa_csr *g, const lpa_mlp *model, uint32_t *labels_out,
+                           double tol, uint32_t max_iter, lpa_learned_stats *stats, uint8_t *masks,
+                           uint32_t mask_rounds) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!ctx || !model) return LPA_EINVAL;
+    if (!(model->tau >= 0.f && model->tau <= 1.f)) return LPA_EINVAL;
+    if (stats) {
+        stats->iterations = 0;
+        stats->converged = 0;
+        stats->learned_rounds = 0;
+        stats->check_round = 0;
+        stats->changed_last = 0;
+        stats->arcs_processed = 0;
+        stats->ms_total = stats->ms_rounds = 0;
+    }
+    FrontRun R;
+    R.mode = F_LEARNED;
+    R.model = model;
+    R.masks = masks;
+    R.mask_rounds = masks ? mask_rounds : 0;
+    LPA_TRY(frontier_impl(ctx, g, labels_out, tol, max_iter, R));
+    if (stats) {
+        stats->iterations = R.iterations;
+        stats->converged = R.converged;
+        stats->learned_rounds = R.learned_rounds;
+        stats->check_round = R.check_round <= R.iterations ? R.check_round : 0;
+        stats->changed_last = R.changed_last;
+        stats->arcs_processed = R.arcs;
+        stats->ms_rounds = R.ms_rounds;
+        for (uint32_t t = 0; t < R.iterations && t < stats->cap; ++t) {
+            if (stats->changed_per_iter) stats->changed_per_iter[t] = R.changed[t];
+            if (stats->voted_per_iter) stats->voted_per_iter[t] = R.voted[t];
+            if (stats->candidates_per_iter) stats->candidates_per_iter[t] = R.cands[t];
+        }
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return LPA_OK;
+}
+
+lpa_status lpa_trace(lpa_ctx *ctx, const lpa_csr *g, double tol, uint32_t max_iter, float *X, uint8_t *y,
+                     uint64_t cap, uint64_t *count) {
+    if (!ctx || !count || (cap && (!X || !y))) return LPA_EINVAL;
+    *count = 0;
+    FrontRun R;
+    R.mode = F_TRACE;
+    R.tX = X;
+    R.ty = y;
+    R.tcap = cap;
+    LPA_TRY(frontier_impl(ctx, g, nullptr, tol, max_iter, R));
+    *count = R.tcount;
+    return LPA_OK;
+}
+
+lpa_status lpa_mlp_forward(lpa_ctx *ctx, const lpa_mlp *model, const float *X, uint64_t N, float *z) {
+    if (!ctx || !model || (N && (!X || !z))) return LPA_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const MlpDev md = make_mlp_dev(*model);
+    HIP_TRY(ctx->f_model.ensure(sizeof(MlpDev)));
+    HIP_TRY(hipMemcpyAsync(ctx->f_model.p, &md, sizeof(MlpDev), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(launch_mlp_forward(ctx->f_model.as<MlpDev>(), X, N, z, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return LPA_OK;
+}
+
+lpa_status lpa_mlp_grad(lpa_ctx *ctx, const lpa_mlp *model, const float *X, const uint8_t *y, uint64_t N,
+                        float pos_weight, float *grad, float *loss) {
+    if (!ctx || !model || !grad || !N || !X || !y || N > 0x80000000ull) return LPA_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const hipStream_t s = ctx->stream;
+    LPA_TRY(ensure_train_bufs(ctx, (uint32_t)N, 1));
+    HIP_TRY(hipMemcpyAsync(ctx->t_w.p, model, kMlpParams * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_train_step(X, y, N, 1, 0, 0, (uint32_t)N, ctx->t_w.as<float>(), ctx->t_m.as<float>(),
+                              ctx->t_v.as<float>(), ctx->t_part.as<float>(), ctx->t_grad.as<float>(), pos_weight,
+                              0.f, 1.f, 1.f, ctx->t_loss.as<float>(), 0, s));
+    std::vector<float> h(kMlpParams + 1);
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx->t_grad.p, (kMlpParams + 1) * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(grad, h.data(), kMlpParams * 4);
+    if (loss) *loss = h[kMlpParams] / (float)N;
+    return LPA_OK;
+}
+
+lpa_status lpa_train(lpa_ctx *ctx, const float *X, const uint8_t *y, uint64_t N, const lpa_train_options *opt,
+                     lpa_mlp *model, float *loss_per_epoch) {
+    if (!ctx || !opt || !model || !N || !X || !y) return LPA_EINVAL;
+    if (!opt->batch || (opt->batch & 255) || !(opt->lr > 0.f) || !(opt->pos_weight > 0.f)) return LPA_EINVAL;
+    if (N >= 0xFFFFFFFFull) return LPA_EINVAL;
+    if (opt->val_n && (!opt->val_X || !opt->val_y)) return LPA_EINVAL;
+    if (opt->val_n && !(opt->recall > 0.f && opt->recall <= 1.f)) return LPA_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const hipStream_t s = ctx->stream;
+    const uint32_t batch = (uint32_t)std::min<uint64_t>(opt->batch, ((N + 255) / 256) * 256);
+    LPA_TRY(ensure_train_bufs(ctx, batch, opt->epochs));
+    HIP_TRY(hipMemcpyAsync(ctx->t_w.p, model, kMlpParams * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u32(ctx->t_m.as<uint32_t>(), 0, kMlpParams, s));
+    HIP_TRY(launch_fill_u32(ctx->t_v.as<uint32_t>(), 0, kMlpParams, s));
+    HIP_TRY(launch_fill_u32(ctx->t_loss.as<uint32_t>(), 0, std::max<uint32_t>(opt->epochs, 1), s));
+    uint64_t rng = opt->seed;
+    uint64_t step = 0;
+    for (uint32_t e = 0; e < opt->epochs; ++e) {
+        // sample order of this epoch: i -> (mul * i + add) mod N, mul coprime to N
+        uint64_t mul = 1, add = 0;
+        if (N > 1) {
+            do {
+                mul = 1 + splitmix(rng) % (N - 1);
+            } while (gcd64(mul, N) != 1);
+            add = splitmix(rng) % N;
+        }
+        for (uint64_t start = 0; start < N; start += batch) {
+            const uint32_t bn = (uint32_t)std::min<uint64_t>(batch, N - start);
+            ++step;
+            const float c1 = 1.f - (float)std::pow(0.9, (double)step);
+            const float c2 = 1.f - (float)std::pow(0.999, (double)step);
+            HIP_TRY(launch_train_step(X, y, N, mul, add, start, bn, ctx->t_w.as<float>(), ctx->t_m.as<float>(),
+                                      ctx->t_v.as<float>(), ctx->t_part.as<float>(), ctx->t_grad.as<float>(),
+                                      opt->pos_weight, opt->lr, c1, c2, ctx->t_loss.as<float>() + e, 1, s));
+        }
+    }
+    std::vector<float> lossv(std::max<uint32_t>(opt->epochs, 1));
+    HIP_TRY(hipMemcpyAsync(model, ctx->t_w.p, kMlpParams * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(lossv.data(), ctx->t_loss.p, lossv.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss_per_epoch)
+        for (uint32_t e = 0; e < opt->epochs; ++e) loss_per_epoch[e] = lossv[e] / (float)N;
+    if (opt->val_n) {
+        // tau: the largest threshold keeping `recall` of the positive samples
+        HIP_TRY(ctx->t_z.ensure(opt->val_n * 4));
+        lpa_mlp m = *model;
+        m.tau = 0.f;
+        LPA_TRY(lpa_mlp_forward(ctx, &m, opt->val_X, opt->val_n, ctx->t_z.as<float>()));
+        std::vector<float> z(opt->val_n);
+        std::vector<uint8_t> yy(opt->val_n);
+        HIP_TRY(hipMemcpyAsync(z.data(), ctx->t_z.p, opt->val_n * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(yy.data(), opt->val_y, opt->val_n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::vector<float> zp;
+        for (uint64_t i = 0; i < opt->val_n; ++i)
+            if (yy[i]) zp.push_back(z[i]);
+        if (zp.empty()) {
+            model->tau = 0.5f;
+        } else {
+            std::sort(zp.begin(), zp.end());
+            const size_t k = (size_t)std::floor((1.0 - (double)opt->recall) * (double)zp.size());
+            const double thr = zp[std::min(k, zp.size() - 1)];
+            model->tau = (float)(1.0 / (1.0 + std::exp(-thr)));
+        }
+    }
+    return LPA_OK;
 }
 
 lpa_status lpa_run_resume(lpa_ctx *ctx, const lpa_csr *g, uint32_t *labels_inout, double tol, uint32_t max_iter,
@@ -966,7 +1463,10 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->items,      &c->ritems,   &c->slab_off, &c->slab_mask, &c->touched_off, &c->tcount,
                       &c->best,       &c->own_sum,  &c->hflags,   &c->rowsum,    &c->slab,        &c->touched,
                       &c->K,          &c->mod_sums, &c->partials, &c->cand,      &c->thr,         &c->item_lo,
-                      &c->mrows,      &c->slab_pending, &c->gid,  &c->gvd,      &c->bstate, &c->bseg};
+                      &c->mrows,      &c->slab_pending, &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
+                      &c->f_top1, &c->f_top2, &c->f_kw, &c->f_last, &c->f_front, &c->f_stale, &c->f_lists,
+                      &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
+                      &c->t_loss, &c->t_z};
     if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) b->release();

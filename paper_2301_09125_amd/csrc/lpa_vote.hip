@@ -41,8 +41,11 @@ namespace lpa {
 
 // ---------------------------------------------------------- one lane --
 
+// FEAT: also record the winning and the runner-up tally of every row.
+template <bool FEAT>
 __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, uint32_t cnt) {
     constexpr int D = kThreadMaxCap;
+    if (a.list) cnt = min(cnt, *a.list_n);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t stride = gridDim.x * 256;
     u64 wchg = 0;
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
         const uint32_t i = base + lane;
         bool ch = false;
         if (i < cnt) {
-            const uint32_t v = lo + i;
+            const uint32_t v = row_of(a, lo, i);
             const uint64_t b = a.g.rp[v];
             const uint64_t e = a.g.rp[v + 1];
             const uint32_t own = a.L_old[v];
@@ -73,9 +76,25 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
                         tl[k] += wt[j];
                     }
             u64 best = a.sw ? vote_key(own, a.sw) : 0ull;
+            if (FEAT) {
+                // the own label's key with its full tally (equal keys of one
+                // label collapse in top2_add)
+                u64 own_t = a.sw;
 #pragma unroll
-            for (int j = 0; j < D; ++j)
-                if (valid >> j & 1u) best = umax64(best, vote_key(lab[j], tl[j]));
+                for (int j = 0; j < D; ++j)
+                    if ((valid >> j & 1u) && lab[j] == own) own_t += wt[j];
+                u64 k2 = 0;
+                best = a.sw ? vote_key(own, own_t) : 0ull;
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    if (valid >> j & 1u) top2_add(best, k2, vote_key(lab[j], tl[j]));
+                a.top1[v] = (uint32_t)(best >> 32);
+                a.top2[v] = (uint32_t)(k2 >> 32);
+            } else {
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    if (valid >> j & 1u) best = umax64(best, vote_key(lab[j], tl[j]));
+            }
             const uint32_t nl = best ? ~(uint32_t)best : own;
             a.L_new[v] = nl;
             ch = nl != own;
@@ -91,12 +110,13 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
 // G lanes per vertex (G divides 64) with a CAP-slot LDS table per group; each
 // lane holds up to A = CAP / (2G) arcs.  A group's table is only touched by
 // lanes of its own wavefront.
-template <int G, int CAP, bool FIRST>
+template <int G, int CAP, bool FIRST, bool FEAT>
 __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, uint32_t cnt) {
     constexpr int GPB = 256 / G;  // groups per block
     constexpr int GPW = 64 / G;   // groups per wavefront
     constexpr int A = CAP / (2 * G);
     __shared__ u64 table[GPB * CAP];
+    if (a.list) cnt = min(cnt, *a.list_n);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t gl = threadIdx.x & (G - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -108,7 +128,7 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
     for (uint32_t base = blockIdx.x * GPB + wave * GPW; base < cnt; base += stride) {
         const uint32_t idx = base + lane / G;
         const bool act = idx < cnt;
-        const uint32_t v = lo + (act ? idx : 0);
+        const uint32_t v = act ? row_of(a, lo, idx) : 0u;
         uint64_t b = 0, e = 0;
         uint32_t own = 0;
         if (act) {
@@ -127,11 +147,16 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
         uint32_t S = next_pow2(2u * (uint32_t)(e - b));
         S = S < (uint32_t)G ? (uint32_t)G : (S > (uint32_t)CAP ? (uint32_t)CAP : S);
         const uint32_t mask = S - 1;
-        u64 best = 0;
+        u64 best = 0, k2 = 0;
         if (direct) {
 #pragma unroll
             for (int j = 0; j < A; ++j)
-                if (rem >> j & 1u) best = umax64(best, vote_key(lab[j], wt[j]));
+                if (rem >> j & 1u) {
+                    if (FEAT)
+                        top2_add(best, k2, vote_key(lab[j], wt[j]));
+                    else
+                        best = umax64(best, vote_key(lab[j], wt[j]));
+                }
         } else {
 #pragma unroll
             for (int j = 0; j < A; ++j)
@@ -142,21 +167,36 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
             for (uint32_t s = gl; s < S; s += G) {
                 const u64 x = T[s];
                 if (x != EMPTY_SLOT) {
-                    best = umax64(best, slot_key(x));
+                    if (FEAT)
+                        top2_add(best, k2, slot_key(x));
+                    else
+                        best = umax64(best, slot_key(x));
                     T[s] = EMPTY_SLOT;
                 }
             }
         }
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) {
-            best = umax64(best, __shfl_xor(best, off, 64));
+            if (FEAT)
+                top2_xor(best, k2, off);
+            else
+                best = umax64(best, __shfl_xor(best, off, 64));
             own_w += __shfl_xor(own_w, off, 64);
             own_hit |= __shfl_xor(own_hit, off, 64);
             rs += __shfl_xor(rs, off, 64);
         }
         bool ch = false;
         if (act && gl == 0) {
-            if (own_hit || a.sw) best = umax64(best, vote_key(own, own_w + a.sw));
+            if (own_hit || a.sw) {
+                if (FEAT)
+                    top2_add(best, k2, vote_key(own, own_w + a.sw));
+                else
+                    best = umax64(best, vote_key(own, own_w + a.sw));
+            }
+            if (FEAT) {
+                a.top1[v] = (uint32_t)(best >> 32);
+                a.top2[v] = (uint32_t)(k2 >> 32);
+            }
             const uint32_t nl = best ? ~(uint32_t)best : own;
             a.L_new[v] = nl;
             ch = nl != own;
@@ -171,9 +211,10 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
 // One wavefront per row of at most A*64 arcs, A arcs per lane, SLOTS LDS
 // slots; the own label and two peeled labels are summed in registers before
 // the table.  The next row's arcs are loaded while the current one is voted.
-template <bool FIRST, int A, int SLOTS>
+template <bool FIRST, bool FEAT, int A, int SLOTS>
 __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uint32_t cnt) {
     __shared__ u64 table[4 * SLOTS];
+    if (a.list) cnt = min(cnt, *a.list_n);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 *T = table + wave * SLOTS;
@@ -184,19 +225,21 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
     uint32_t i = blockIdx.x * 4 + wave;
     uint64_t b = 0, e = 0;
     uint32_t u[A], wt[A], valid = 0;
+    uint32_t v = 0;
     if (i < cnt) {
-        b = a.g.rp[lo + i];
-        e = a.g.rp[lo + i + 1];
+        v = row_of(a, lo, i);
+        b = a.g.rp[v];
+        e = a.g.rp[v + 1];
         issue_arcs<A, 64>(a, b + lane, e, u, wt, valid);
     }
     while (i < cnt) {
-        const uint32_t v = lo + i;
         const uint32_t inext = i + stride;
         uint64_t nb = 0, ne = 0;
-        uint32_t nu[A], nwt[A], nvalid = 0;
+        uint32_t nu[A], nwt[A], nvalid = 0, nv = 0;
         if (inext < cnt) {
-            nb = a.g.rp[lo + inext];
-            ne = a.g.rp[lo + inext + 1];
+            nv = row_of(a, lo, inext);
+            nb = a.g.rp[nv];
+            ne = a.g.rp[nv + 1];
             issue_arcs<A, 64>(a, nb + lane, ne, nu, nwt, nvalid);
         }
         check_arcs<A>(a, u);
@@ -210,11 +253,16 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
         uint32_t S = next_pow2(2u * (uint32_t)(e - b));
         S = S < 64u ? 64u : (S > (uint32_t)SLOTS ? (uint32_t)SLOTS : S);
         const uint32_t mask = S - 1;
-        u64 best = 0;
+        u64 best = 0, k2 = 0;
         if (direct) {
 #pragma unroll
             for (int j = 0; j < A; ++j)
-                if (rem >> j & 1u) best = umax64(best, vote_key(lab[j], wt[j]));
+                if (rem >> j & 1u) {
+                    if (FEAT)
+                        top2_add(best, k2, vote_key(lab[j], wt[j]));
+                    else
+                        best = umax64(best, vote_key(lab[j], wt[j]));
+                }
         } else if (__ballot(rem != 0)) {  // some label other than the own one
             wave_peel<A, 2>(T, mask, lab, wt, rem);
 #pragma unroll
@@ -224,17 +272,34 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
             for (uint32_t s = lane; s < S; s += 64) {
                 const u64 x = T[s];
                 if (x != EMPTY_SLOT) {
-                    best = umax64(best, slot_key(x));
+                    if (FEAT)
+                        top2_add(best, k2, slot_key(x));
+                    else
+                        best = umax64(best, slot_key(x));
                     T[s] = EMPTY_SLOT;
                 }
             }
         }
-        best = wave_max64(best);
+        if (FEAT) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) top2_xor(best, k2, off);
+        } else {
+            best = wave_max64(best);
+        }
         own_w = wave_sum(own_w);
         own_hit = __ballot(own_hit != 0) != 0;
         if (a.check) rs = wave_sum(rs);
         if (lane == 0) {
-            if (own_hit || a.sw) best = umax64(best, vote_key(own, own_w + a.sw));
+            if (own_hit || a.sw) {
+                if (FEAT)
+                    top2_add(best, k2, vote_key(own, own_w + a.sw));
+                else
+                    best = umax64(best, vote_key(own, own_w + a.sw));
+            }
+            if (FEAT) {
+                a.top1[v] = (uint32_t)(best >> 32);
+                a.top2[v] = (uint32_t)(k2 >> 32);
+            }
             const uint32_t nl = best ? ~(uint32_t)best : own;
             a.L_new[v] = nl;
             wchg += nl != own;
@@ -242,6 +307,7 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
         }
         wave_sync();
         i = inext;
+        v = nv;
         b = nb;
         e = ne;
         valid = nvalid;
@@ -254,37 +320,48 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
     block_count(lane == 0 ? wchg : 0, a.changed);
 }
 
-hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int, int grid_cap, hipStream_t s) {
+hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int, int feat, int grid_cap,
+                              hipStream_t s) {
     if (cnt == 0) return hipSuccess;
-    vote_thread_k<<<grid_for(cnt, 256, grid_cap), 256, 0, s>>>(a, lo, cnt);
+    const unsigned g = grid_for(cnt, 256, grid_cap);
+    if (feat)
+        vote_thread_k<true><<<g, 256, 0, s>>>(a, lo, cnt);
+    else
+        vote_thread_k<false><<<g, 256, 0, s>>>(a, lo, cnt);
     return hipGetLastError();
 }
-hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int grid_cap,
+hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int grid_cap,
                              hipStream_t s) {
     if (cnt == 0) return hipSuccess;
     const unsigned g = grid_for(cnt, 256 / kGroupLanes, grid_cap);
+    constexpr int GL = kGroupLanes, GS = kGroupSlots;
     if (first)
-        vote_group_k<kGroupLanes, kGroupSlots, true><<<g, 256, 0, s>>>(a, lo, cnt);
+        feat ? vote_group_k<GL, GS, true, true><<<g, 256, 0, s>>>(a, lo, cnt)
+             : vote_group_k<GL, GS, true, false><<<g, 256, 0, s>>>(a, lo, cnt);
     else
-        vote_group_k<kGroupLanes, kGroupSlots, false><<<g, 256, 0, s>>>(a, lo, cnt);
+        feat ? vote_group_k<GL, GS, false, true><<<g, 256, 0, s>>>(a, lo, cnt)
+             : vote_group_k<GL, GS, false, false><<<g, 256, 0, s>>>(a, lo, cnt);
     return hipGetLastError();
 }
-hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int grid_cap,
-                            hipStream_t s) {
+
+template <bool FIRST, bool FEAT>
+static void launch_wave_t(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, unsigned g, hipStream_t s) {
+    constexpr int AS = kWaveArcsSmall / 64, AW = kWaveArcs / 64;
+    if (wide)
+        vote_wave_k<FIRST, FEAT, AW, kWaveSlots><<<g, 256, 0, s>>>(a, lo, cnt);
+    else
+        vote_wave_k<FIRST, FEAT, AS, kWaveSlotsSmall><<<g, 256, 0, s>>>(a, lo, cnt);
+}
+
+hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int feat,
+                            int grid_cap, hipStream_t s) {
     if (cnt == 0) return hipSuccess;
     const unsigned g = grid_for(cnt, 4, grid_cap);
-    constexpr int AS = kWaveArcsSmall / 64, AW = kWaveArcs / 64;
-    if (wide) {
-        if (first)
-            vote_wave_k<true, AW, kWaveSlots><<<g, 256, 0, s>>>(a, lo, cnt);
-        else
-            vote_wave_k<false, AW, kWaveSlots><<<g, 256, 0, s>>>(a, lo, cnt);
-    } else {
-        if (first)
-            vote_wave_k<true, AS, kWaveSlotsSmall><<<g, 256, 0, s>>>(a, lo, cnt);
-        else
-            vote_wave_k<false, AS, kWaveSlotsSmall><<<g, 256, 0, s>>>(a, lo, cnt);
-    }
+    if (first)
+        feat ? launch_wave_t<true, true>(a, lo, cnt, wide, g, s) : launch_wave_t<true, false>(a, lo, cnt, wide, g, s);
+    else
+        feat ? launch_wave_t<false, true>(a, lo, cnt, wide, g, s)
+             : launch_wave_t<false, false>(a, lo, cnt, wide, g, s);
     return hipGetLastError();
 }
 

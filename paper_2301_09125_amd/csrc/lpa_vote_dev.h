@@ -8,6 +8,28 @@
 
 namespace lpa {
 
+// Row of work item i of a launch over [lo, lo + cnt) or over a list.
+__device__ __forceinline__ uint32_t row_of(const RoundArgs &a, uint32_t lo, uint32_t i) {
+    return a.list ? a.list[i] : lo + i;
+}
+
+// Two largest distinct vote keys seen so far (0 = none).
+__device__ __forceinline__ void top2_add(u64 &k1, u64 &k2, u64 k) {
+    if (k > k1) {
+        k2 = k1;
+        k1 = k;
+    } else if (k < k1 && k > k2) {
+        k2 = k;
+    }
+}
+
+// Merge the top-two pairs of lanes that are `off` apart (xor pattern).
+__device__ __forceinline__ void top2_xor(u64 &k1, u64 &k2, int off) {
+    const u64 o1 = __shfl_xor(k1, off, 64), o2 = __shfl_xor(k2, off, 64);
+    top2_add(k1, k2, o1);
+    top2_add(k1, k2, o2);
+}
+
 // Issue the loads of arcs k0 + j*STRIDE (j < A, below e) of one lane:
 // internal ids into u, weights into wt, bit j of `valid` set for loaded
 // arcs.  Nothing here waits for the data, so the loads of the next work item

@@ -40,7 +40,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("self_weight", ctypes.c_uint32), ("thread_max", ctypes.c_uint32),
                 ("group_max", ctypes.c_uint32), ("wave_max", ctypes.c_uint32),
                 ("wide_max", ctypes.c_uint32), ("merge_max", ctypes.c_uint32), ("profile", ctypes.c_uint32),
-                ("modularity", ctypes.c_uint32)]
+                ("modularity", ctypes.c_uint32), ("frontier", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
@@ -59,12 +59,59 @@ class _BatchStats(ctypes.Structure):
                 ("changed_hist", ctypes.c_void_p), ("hist_cap", ctypes.c_uint32)]
 
 
+_F32 = ctypes.c_float
+
+
+class _Mlp(ctypes.Structure):
+    _fields_ = [("w1", (_F32 * 32) * 6), ("b1", _F32 * 32), ("w2", (_F32 * 32) * 32), ("b2", _F32 * 32),
+                ("w3", _F32 * 32), ("b3", _F32), ("tau", _F32)]
+
+
+class _LearnedStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_uint32), ("converged", ctypes.c_int32),
+                ("learned_rounds", ctypes.c_uint32), ("check_round", ctypes.c_uint32),
+                ("changed_last", ctypes.c_uint64), ("arcs_processed", ctypes.c_uint64),
+                ("ms_total", ctypes.c_double), ("ms_rounds", ctypes.c_double),
+                ("changed_per_iter", ctypes.c_void_p), ("voted_per_iter", ctypes.c_void_p),
+                ("candidates_per_iter", ctypes.c_void_p), ("cap", ctypes.c_uint32)]
+
+
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", _F32), ("pos_weight", _F32),
+                ("seed", ctypes.c_uint64), ("val_X", ctypes.c_void_p), ("val_y", ctypes.c_void_p),
+                ("val_n", ctypes.c_uint64), ("recall", _F32)]
+
+
+MLP_FIELDS = ("w1", "b1", "w2", "b2", "w3", "b3")
+
+
+def _mlp_to_c(model: dict) -> _Mlp:
+    m = _Mlp()
+    flat = np.concatenate([np.asarray(model[k], dtype=np.float32).ravel() for k in MLP_FIELDS])
+    assert flat.size == 1313, flat.size
+    ctypes.memmove(ctypes.addressof(m), flat.ctypes.data, flat.nbytes)
+    m.tau = float(model.get("tau", 0.5))
+    return m
+
+
+def _mlp_from_c(m: _Mlp) -> dict:
+    flat = np.frombuffer(ctypes.string_at(ctypes.addressof(m), 1313 * 4), dtype=np.float32).copy()
+    out, o = {}, 0
+    for k, shape in (("w1", (6, 32)), ("b1", (32,)), ("w2", (32, 32)), ("b2", (32,)), ("w3", (32,)), ("b3", ())):
+        size = int(np.prod(shape)) if shape else 1
+        out[k] = flat[o:o + size].reshape(shape) if shape else np.float32(flat[o])
+        o += size
+    out["tau"] = float(m.tau)
+    return out
+
+
 class _KProf(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_uint64), ("arcs", ctypes.c_uint64)]
 
 
-EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_run_batch", "lpa_modularity",
+EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_run_batch", "lpa_run_learned",
+           "lpa_trace", "lpa_train", "lpa_mlp_forward", "lpa_mlp_grad", "lpa_modularity",
            "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
 
 
@@ -84,6 +131,13 @@ def _load():
     lib.lpa_run.argtypes = [vp, ctypes.POINTER(_Csr), vp, dbl, u32, ctypes.POINTER(_Stats)]
     lib.lpa_run_resume.argtypes = [vp, ctypes.POINTER(_Csr), vp, dbl, u32, ctypes.POINTER(_Stats)]
     lib.lpa_run_batch.argtypes = [vp, ctypes.POINTER(_Csr), vp, u32, vp, dbl, u32, ctypes.POINTER(_BatchStats)]
+    u64 = ctypes.c_uint64
+    lib.lpa_run_learned.argtypes = [vp, ctypes.POINTER(_Csr), ctypes.POINTER(_Mlp), vp, dbl, u32,
+                                    ctypes.POINTER(_LearnedStats), vp, u32]
+    lib.lpa_trace.argtypes = [vp, ctypes.POINTER(_Csr), dbl, u32, vp, vp, u64, ctypes.POINTER(u64)]
+    lib.lpa_train.argtypes = [vp, vp, vp, u64, ctypes.POINTER(_TrainOpts), ctypes.POINTER(_Mlp), vp]
+    lib.lpa_mlp_forward.argtypes = [vp, ctypes.POINTER(_Mlp), vp, u64, vp]
+    lib.lpa_mlp_grad.argtypes = [vp, ctypes.POINTER(_Mlp), vp, vp, u64, _F32, vp, ctypes.POINTER(_F32)]
     lib.lpa_modularity.argtypes = [vp, ctypes.POINTER(_Csr), vp, ctypes.POINTER(dbl),
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.lpa_profile_get.argtypes = [vp, ctypes.POINTER(_KProf), u32, ctypes.POINTER(u32)]
@@ -92,6 +146,8 @@ def _load():
     lib.lpa_destroy.restype = None
     lib.lpa_strerror.argtypes = [ctypes.c_int]
     lib.lpa_strerror.restype = ctypes.c_char_p
+    for f in (lib.lpa_run_learned, lib.lpa_trace, lib.lpa_train, lib.lpa_mlp_forward, lib.lpa_mlp_grad):
+        f.restype = ctypes.c_int
     for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_run_batch, lib.lpa_modularity, lib.lpa_profile_get,
               lib.lpa_profile_reset):
         f.restype = ctypes.c_int
@@ -180,6 +236,21 @@ class BatchStats:
         """Changed counts of graph g's rounds (up to hist_cap of them)."""
         k = min(int(self.iterations[g]), self.changed_hist.shape[1])
         return [int(x) for x in self.changed_hist[g, :k]]
+
+
+@dataclass
+class LearnedStats:
+    iterations: int
+    converged: bool
+    learned_rounds: int
+    check_round: int
+    changed_last: int
+    arcs_processed: int
+    ms_total: float
+    ms_rounds: float
+    changed: list
+    voted: list
+    candidates: list
 
 
 class Context:
@@ -290,6 +361,90 @@ class Context:
             raise LpaError(rc, "lpa_run_batch")
         return labels_out, BatchStats(st.graphs, st.rounds, st.converged_graphs, st.arcs_processed, st.ms_total,
                                       st.ms_device, it[:G], cv[:G].astype(bool), last[:G], hist[:G, :cap])
+
+    def run_learned(self, g: DeviceGraph, model: dict, tol: float = 0.05, max_iter: int = 20, labels_out=None,
+                    masks: bool = False):
+        """RAK with the learned frontier; returns (labels, LearnedStats, masks
+        (u8 tensor [rounds, n] by original id) or None)."""
+        import torch
+        if labels_out is None:
+            labels_out = torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+        mk = torch.zeros((max_iter, g.n), dtype=torch.uint8, device=g.row_ptr.device) if masks else None
+        cap = max(max_iter, 1)
+        ch, vo, ca = (np.zeros(cap, np.uint64) for _ in range(3))
+        st = _LearnedStats()
+        st.changed_per_iter, st.voted_per_iter, st.candidates_per_iter = ch.ctypes.data, vo.ctypes.data, ca.ctypes.data
+        st.cap = cap
+        m = _mlp_to_c(model)
+        c = g._c()
+        rc = _load().lpa_run_learned(self._h, ctypes.byref(c), ctypes.byref(m), labels_out.data_ptr() if g.n else None,
+                                     float(tol), int(max_iter), ctypes.byref(st),
+                                     mk.data_ptr() if (mk is not None and g.n) else None, max_iter if masks else 0)
+        if rc:
+            raise LpaError(rc, "lpa_run_learned")
+        k = st.iterations
+        stats = LearnedStats(k, bool(st.converged), st.learned_rounds, st.check_round, st.changed_last,
+                             st.arcs_processed, st.ms_total, st.ms_rounds, [int(x) for x in ch[:k]],
+                             [int(x) for x in vo[:k]], [int(x) for x in ca[:k]])
+        return labels_out, stats, (mk[:k] if mk is not None else None)
+
+    def trace(self, g: DeviceGraph, tol: float = 0.05, max_iter: int = 20, cap: int | None = None):
+        """Training samples of a plain run: (X float32 [count, 6], y uint8 [count]) on the device."""
+        import torch
+        if cap is None:
+            cap = g.n * max(max_iter - 1, 0)
+        X = torch.empty((max(cap, 1), 6), dtype=torch.float32, device=g.row_ptr.device)
+        y = torch.empty(max(cap, 1), dtype=torch.uint8, device=g.row_ptr.device)
+        cnt = ctypes.c_uint64(0)
+        c = g._c()
+        rc = _load().lpa_trace(self._h, ctypes.byref(c), float(tol), int(max_iter), X.data_ptr(), y.data_ptr(),
+                               cap, ctypes.byref(cnt))
+        if rc:
+            raise LpaError(rc, "lpa_trace")
+        if cnt.value > cap:
+            raise RuntimeError(f"trace holds {cnt.value} samples, more than cap={cap}")
+        return X[:cnt.value], y[:cnt.value]
+
+    def train(self, X, y, model: dict, epochs: int = 3, batch: int = 65536, lr: float = 3e-3,
+              pos_weight: float = 1.0, seed: int = 1, val=None, recall: float = 0.99):
+        """Train on device samples; returns (model dict with tau set from the
+        validation samples when given, loss per epoch)."""
+        m = _mlp_to_c(model)
+        o = _TrainOpts()
+        o.epochs, o.batch, o.lr, o.pos_weight, o.seed = epochs, batch, lr, pos_weight, seed
+        if val is not None:
+            o.val_X, o.val_y, o.val_n, o.recall = val[0].data_ptr(), val[1].data_ptr(), val[0].shape[0], recall
+        losses = np.zeros(max(epochs, 1), np.float32)
+        rc = _load().lpa_train(self._h, X.data_ptr(), y.data_ptr(), X.shape[0], ctypes.byref(o), ctypes.byref(m),
+                               losses.ctypes.data)
+        if rc:
+            raise LpaError(rc, "lpa_train")
+        return _mlp_from_c(m), [float(x) for x in losses[:epochs]]
+
+    def mlp_forward(self, model: dict, X):
+        """Logits of device samples X (float32 [N, 6]) with the inference arithmetic."""
+        import torch
+        z = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        m = _mlp_to_c(model)
+        rc = _load().lpa_mlp_forward(self._h, ctypes.byref(m), X.data_ptr(), X.shape[0], z.data_ptr())
+        if rc:
+            raise LpaError(rc, "lpa_mlp_forward")
+        return z
+
+    def mlp_grad(self, model: dict, X, y, pos_weight: float = 1.0):
+        """(loss, gradient dict) of the training loss over all samples."""
+        m = _mlp_to_c(model)
+        g = np.zeros(1313, np.float32)
+        loss = ctypes.c_float(0)
+        rc = _load().lpa_mlp_grad(self._h, ctypes.byref(m), X.data_ptr(), y.data_ptr(), X.shape[0],
+                                  float(pos_weight), g.ctypes.data, ctypes.byref(loss))
+        if rc:
+            raise LpaError(rc, "lpa_mlp_grad")
+        out = _Mlp()
+        ctypes.memmove(ctypes.addressof(out), g.ctypes.data, g.nbytes)
+        d = _mlp_from_c(out)
+        d.pop("tau")
+        return float(loss.value), d
 
     def modularity(self, g: DeviceGraph, labels):
         """(Q, {'two_m', 'sigma_in', 'sum_k2'}) computed on the device."""

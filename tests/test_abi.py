@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_and_strerror():
     from paper_2301_09125_amd import lpa
     o = lpa.default_options()
-    assert o == {"self_weight": 1, "thread_max": 8, "group_max": 32, "wave_max": 128, "wide_max": 512, "merge_max": 512,
+    assert o == {"self_weight": 1, "thread_max": 8, "group_max": 32, "wave_max": 128, "wide_max": 512, "merge_max": 512, "frontier": 0,
                  "profile": 0, "modularity": 0}
     lib = lpa.library()
     for code in (0, -1, -2, -3, -4, -5):
@@ -50,6 +50,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lpa_csr), sizeof(lpa_options), sizeof(lpa_stats),
          sizeof(lpa_kernel_prof), offsetof(lpa_stats, changed_per_iter), offsetof(lpa_kernel_prof, ms),
          sizeof(lpa_batch_stats), offsetof(lpa_batch_stats, iterations), offsetof(lpa_batch_stats, hist_cap));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lpa_mlp), offsetof(lpa_mlp, tau), sizeof(lpa_learned_stats),
+         offsetof(lpa_learned_stats, cap), sizeof(lpa_train_options), offsetof(lpa_train_options, recall));
   return 0;
 }
 '''
@@ -61,7 +63,9 @@ int main(void) {
         got = [int(x) for x in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(lpa._Csr), ctypes.sizeof(lpa._Options), ctypes.sizeof(lpa._Stats),
             ctypes.sizeof(lpa._KProf), lpa._Stats.changed_per_iter.offset, lpa._KProf.ms.offset,
-            ctypes.sizeof(lpa._BatchStats), lpa._BatchStats.iterations.offset, lpa._BatchStats.hist_cap.offset]
+            ctypes.sizeof(lpa._BatchStats), lpa._BatchStats.iterations.offset, lpa._BatchStats.hist_cap.offset,
+            ctypes.sizeof(lpa._Mlp), lpa._Mlp.tau.offset, ctypes.sizeof(lpa._LearnedStats), lpa._LearnedStats.cap.offset,
+            ctypes.sizeof(lpa._TrainOpts), lpa._TrainOpts.recall.offset]
     assert got == want
 
 
