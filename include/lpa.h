@@ -241,9 +241,11 @@ typedef struct {
 } lpa_learned_stats;
 
 /* RAK with the learned frontier.  Round 1 votes every vertex.  Each later
- * round votes the candidates the network keeps, until a round changes at
- * most floor(tol * n) labels; the next round then votes every candidate (a
- * full check, equivalent to voting every vertex).  If the check passes the
+ * round votes the candidates the network keeps (and every vertex skipped in
+ * the round before), until the round's changed count plus the predicted
+ * changes of the rows it skipped is at most floor(tol * n); the next round
+ * then votes every candidate (a full check, equivalent to voting every
+ * vertex).  If the check passes the
  * run has converged; otherwise rounds go on voting every candidate (plain
  * RAK) until the tolerance test passes or max_iter rounds have run.  Rows
  * longer than wide_max arcs are voted in every round.

@@ -205,6 +205,7 @@ struct FrontArgs {
     const uint32_t *old_of;
     unsigned long long *cand_count;  // += candidates of the round
     unsigned long long *kept_arcs;   // += arcs of the rows kept for the vote
+    unsigned long long *exp_skip;    // += 1024 x predicted change probability of skipped rows
     uint32_t sw, t, max_iter;
     uint32_t all_dirty;  // every vertex counts as having a changed neighbour
     uint32_t keep_all;   // vote every candidate (no prediction)

@@ -10,7 +10,8 @@
 //
 // Predictor.  For every dirty vertex a 6-32-32-1 network scores whether it
 // will change; only vertices scoring at least the cut are voted, the others
-// copy their label and stay stale.  Features (computed here, in FP32, then
+// copy their label and stay stale.  A vertex skipped in one round is always
+// voted in the next (its features would be a round old).  Features (computed here, in FP32, then
 // rounded to bfloat16):
 //   f1 log2(1+deg)   f2 (top1-top2)/(k+sw)   f3 changed in round t-1
 //   f4 top1/(k+sw)   f5 dirty through a neighbour   f6 t/max_iter
@@ -124,21 +125,28 @@ __global__ __launch_bounds__(256) void predict_k(FrontArgs p, const MlpDev *mode
                                                  uint32_t K, uint32_t *list, uint32_t *list_count) {
     __shared__ MlpDev M;
     __shared__ uint32_t wsum[4][2];
-    __shared__ unsigned long long warcs[4];
+    __shared__ unsigned long long warcs[4], wskip[4];
     __shared__ uint32_t base_s;
-    if (!p.keep_all) load_model(M, model);
+    __shared__ u64 mk[32][4];      // kept lanes of each chunk and wavefront
+    __shared__ uint32_t offs[32][4];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 128) (&mk[0][0])[tid] = 0;
+    if (!p.keep_all)
+        load_model(M, model);
+    else
+        __syncthreads();
     const uint64_t begin = (uint64_t)blockIdx.x * K * 256;
     uint32_t bits = 0, ncand = 0;
-    uint64_t karcs = 0;
+    uint64_t karcs = 0, eskip = 0;
     for (uint32_t k = 0; k < K; ++k) {
         const uint64_t i = begin + (uint64_t)k * 256 + tid;
         const bool in = i < cnt;
         const uint32_t v = lo + (uint32_t)(in ? i : 0);
-        bool dirty_nb = false, cand = false;
+        bool dirty_nb = false, cand = false, was_skipped = false;
         if (in) {
             dirty_nb = p.all_dirty || p.front[v] == p.t;
-            cand = dirty_nb || p.stale[v];
+            was_skipped = p.stale[v] != 0;
+            cand = dirty_nb || was_skipped;
         }
         if (!__ballot(cand)) {
             if (in && p.mask) p.mask[p.old_of[v]] = 0;
@@ -151,7 +159,10 @@ __global__ __launch_bounds__(256) void predict_k(FrontArgs p, const MlpDev *mode
             uint64_t fa, fb;
             pack_features(f, fa, fb);
             const float z = mlp_wave(M, fa, fb);
-            keep = cand && z >= M.zcut;
+            // a row skipped last round is voted now: its features are a
+            // round old, and no row stays unvoted two rounds in a row
+            keep = cand && (was_skipped || z >= M.zcut);
+            if (cand && !keep) eskip += (uint32_t)(1024.f / (1.f + expf(-z)) + 0.5f);
         }
         if (cand) {
             ++ncand;
@@ -165,42 +176,44 @@ __global__ __launch_bounds__(256) void predict_k(FrontArgs p, const MlpDev *mode
             }
         }
         if (in && p.mask) p.mask[p.old_of[v]] = keep ? 1 : 0;
+        const u64 kb = __ballot(cand && keep);
+        if (lane == 0) mk[k][wave] = kb;
     }
-    // block-wide prefix of the kept counts
-    const uint32_t mine = __popc(bits);
-    uint32_t pre = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(pre, off, 64);
-        if ((int)lane >= off) pre += y;
-    }
+    // list positions in vertex order: chunk-major, then wavefront, then lane
     const uint32_t nc = wave_sum(ncand);
     const unsigned long long ka = wave_sum((unsigned long long)karcs);
-    if (lane == 63) wsum[wave][0] = pre;
+    const unsigned long long es = wave_sum((unsigned long long)eskip);
     if (lane == 0) {
         wsum[wave][1] = nc;
         warcs[wave] = ka;
+        wskip[wave] = es;
     }
     __syncthreads();
-    uint32_t off = 0, total = 0, tc = 0;
-    unsigned long long ta = 0;
-    for (uint32_t q = 0; q < 4; ++q) {
-        if (q < wave) off += wsum[q][0];
-        total += wsum[q][0];
-        tc += wsum[q][1];
-        ta += warcs[q];
-    }
     if (tid == 0) {
-        base_s = total ? atomicAdd(list_count, total) : 0u;
+        uint32_t run = 0, tc = 0;
+        unsigned long long ta = 0, ts = 0;
+        for (uint32_t k = 0; k < K; ++k)
+            for (uint32_t q = 0; q < 4; ++q) {
+                offs[k][q] = run;
+                run += __popcll(mk[k][q]);
+            }
+        for (uint32_t q = 0; q < 4; ++q) {
+            tc += wsum[q][1];
+            ta += warcs[q];
+            ts += wskip[q];
+        }
+        base_s = run ? atomicAdd(list_count, run) : 0u;
         if (tc) atomicAdd(p.cand_count, (unsigned long long)tc);
         if (ta) atomicAdd(p.kept_arcs, ta);
+        if (ts) atomicAdd(p.exp_skip, ts);
     }
     __syncthreads();
-    uint32_t pos = base_s + off + pre - mine;
+    const u64 below = (1ull << lane) - 1;
     while (bits) {
         const uint32_t k = __ffs(bits) - 1;
         bits &= bits - 1;
-        list[pos++] = lo + (uint32_t)(begin + (uint64_t)k * 256 + tid);
+        const uint32_t pos = base_s + offs[k][wave] + __popcll(mk[k][wave] & below);
+        list[pos] = lo + (uint32_t)(begin + (uint64_t)k * 256 + tid);
     }
 }
 
@@ -476,8 +489,10 @@ hipError_t launch_mask_rows(uint8_t *mask, const uint32_t *old_of, uint32_t lo, 
 hipError_t launch_predict(const FrontArgs &p, const MlpDev *model, uint32_t lo, uint32_t cnt, uint32_t *list,
                           uint32_t *list_count, int num_cu, hipStream_t s) {
     if (cnt == 0) return hipSuccess;
+    // few blocks (each reserves its list range with one atomic on a shared
+    // counter), at most 32 chunks of 256 rows per thread
     const uint64_t chunks = (cnt + 255) / 256;
-    const uint64_t want = std::max<uint64_t>((uint64_t)num_cu * 8, (chunks + 31) / 32);
+    const uint64_t want = std::max<uint64_t>((uint64_t)num_cu * 2, (chunks + 31) / 32);
     const uint64_t grid = std::min<uint64_t>(chunks, want);
     const uint32_t K = (uint32_t)((chunks + grid - 1) / grid);
     const uint32_t g = (uint32_t)((chunks + K - 1) / K);

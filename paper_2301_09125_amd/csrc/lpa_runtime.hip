@@ -58,12 +58,14 @@ struct DevBuf {
 };
 
 enum KernelId {
-    K_THREAD, K_GROUP, K_WAVE, K_WIDE, K_HUB, K_HUB1, K_MERGE, K_FALLBACK, K_REDUCE, K_FINAL, K_MOD, K_COUNT
+    K_THREAD, K_GROUP, K_WAVE, K_WIDE, K_HUB, K_HUB1, K_MERGE, K_FALLBACK, K_REDUCE, K_FINAL, K_MOD,
+    K_PREDICT, K_PUSH, K_COUNT
 };
-// vote_hub_first: the long-row vote of round 1 from the unique labels
+// vote_hub_first: the long-row vote of round 1 from the unique labels;
+// predict / push: candidate selection and frontier stamps of frontier runs
 const char *kKernelNames[K_COUNT] = {"vote_thread",  "vote_group", "vote_wave",    "vote_wide",
                                      "vote_hub",     "vote_hub_first", "hub_merge", "hub_fallback",
-                                     "hub_reduce",   "hub_final",  "modularity"};
+                                     "hub_reduce",   "hub_final",  "modularity", "predict", "push"};
 
 struct Pending {
     int kid;
@@ -710,7 +712,7 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
     for (DevBuf *b : {&c->f_top1, &c->f_top2, &c->f_last, &c->f_front}) HIP_TRY(b->ensure((size_t)n * 4));
     HIP_TRY(c->f_stale.ensure(n));
     HIP_TRY(c->f_lists.ensure((size_t)n * 4));
-    HIP_TRY(c->f_small.ensure(64));  // list counts [8], candidates, kept arcs
+    HIP_TRY(c->f_small.ensure(64));  // list counts [8], candidates, kept arcs, expected skipped changes
     HIP_TRY(launch_fill_u32(c->f_last.as<uint32_t>(), 0, n, s));
     HIP_TRY(launch_fill_u32(c->f_front.as<uint32_t>(), 0, n, s));
     HIP_TRY(launch_fill_u32(c->f_top1.as<uint32_t>(), 0, n, s));
@@ -786,36 +788,48 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         fa.old_of = c->old_of.as<uint32_t>();
         fa.cand_count = cand_dev;
         fa.kept_arcs = cand_dev + 1;
+        fa.exp_skip = cand_dev + 2;
         fa.sw = c->opt.self_weight;
         fa.t = t;
         fa.max_iter = max_iter;
         fa.all_dirty = all_dirty;
         fa.keep_all = phase != PH_LEARN;
-        const bool full = t == 1 || R.mode == F_TRACE;
+        // full: every non-isolated row votes, no candidate lists (round 1,
+        // traces, and rounds in which every row is a candidate anyway)
+        const bool full = t == 1 || R.mode == F_TRACE || (phase != PH_LEARN && all_dirty);
         const bool learned_round = !full && phase == PH_LEARN;
+        // the tallies feed the features of the next round's prediction
+        const int feat = R.mode == F_TRACE || (R.mode == F_LEARNED && phase == PH_LEARN);
         uint64_t trace_base = R.tcount;
         HIP_TRY(hipEventRecord(c->round_a, s));
         if (full) {
             if (fa.mask) HIP_TRY(launch_mask_rows(fa.mask, fa.old_of, 0, n, 1, s));
+            if (R.mode == F_LEARNED && R.learned_rounds)
+                HIP_TRY(launch_fill_u64(reinterpret_cast<u64 *>(c->f_stale.p), 0, ((size_t)n + 7) / 8, s));
             if (R.mode == F_TRACE && t >= 2 && R.tX && trace_base + nonhub_cnt <= R.tcap)
                 HIP_TRY(launch_trace_x(fa, nonhub_lo, nonhub_cnt, R.tX + trace_base * 6, s));
-            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, t == 1 ? 1 : 0, 1));
+            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, t == 1 ? 1 : 0, feat));
         } else {
             HIP_TRY(launch_fill_u32(list_n, 0, NBINS, s));
-            HIP_TRY(launch_fill_u64(cand_dev, 0, 2, s));
-            for (int b = BIN_WIDE; b <= BIN_THREAD; ++b)
-                HIP_TRY(launch_predict(fa, c->f_model.as<MlpDev>(), B.lo[b], B.cnt[b], lists[b], list_n + b,
-                                       c->num_cu, s));
+            HIP_TRY(launch_fill_u64(cand_dev, 0, 3, s));
+            LPA_TRY(timed(c, K_PREDICT, 0, 0, [&]() -> hipError_t {
+                for (int b = BIN_WIDE; b <= BIN_THREAD; ++b) {
+                    const hipError_t e = launch_predict(fa, c->f_model.as<MlpDev>(), B.lo[b], B.cnt[b], lists[b],
+                                                        list_n + b, c->num_cu, s);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+            }));
             if (fa.mask) {
                 HIP_TRY(launch_mask_rows(fa.mask, fa.old_of, B.lo[BIN_HUB], B.cnt[BIN_HUB], 1, s));
                 HIP_TRY(launch_mask_rows(fa.mask, fa.old_of, B.lo[BIN_ZERO], B.cnt[BIN_ZERO], 0, s));
             }
-            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, 0, 1, lists, list_n));
+            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, 0, feat, lists, list_n));
         }
         HIP_TRY(hipEventRecord(c->round_b, s));
         HIP_TRY(hipMemcpyAsync(c->pinned + 16, ra.changed, kCountWords * sizeof(u64), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        if (!full) HIP_TRY(hipMemcpyAsync(c->pinned + 2, c->f_small.p, 48, hipMemcpyDeviceToHost, s));
+        if (!full) HIP_TRY(hipMemcpyAsync(c->pinned + 2, c->f_small.p, 56, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (c->opt.profile) collect_profile(c);
         float ms = 0.f;
@@ -825,13 +839,14 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         if (errbits) return err_status(errbits);
         u64 changed = 0;
         for (int k = 0; k < kCountSlots; ++k) changed += c->pinned[16 + (size_t)k * kCountStride];
-        u64 voted = nonisolated, cand = nonisolated, arcs = all_arcs;
+        u64 voted = nonisolated, cand = nonisolated, arcs = all_arcs, expected_skipped = 0;
         if (!full) {
             const uint32_t *ln = reinterpret_cast<const uint32_t *>(c->pinned + 2);
             voted = B.cnt[BIN_HUB];
             for (int b = BIN_WIDE; b <= BIN_THREAD; ++b) voted += ln[b];
             cand = c->pinned[2 + 4] + B.cnt[BIN_HUB];
             arcs = c->pinned[2 + 5] + B.arcs[BIN_HUB];
+            expected_skipped = (c->pinned[2 + 6] + 512) / 1024;
         }
         if (R.mode == F_TRACE && t >= 2) {
             if (R.ty && trace_base + nonhub_cnt <= R.tcap)
@@ -849,10 +864,10 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         // which vertices can change next round
         const int mark = R.mode == F_TRACE || changed <= push_limit;
         fa.t = t;
-        HIP_TRY(launch_push(fa, B, mark, s));
+        LPA_TRY(timed(c, K_PUSH, 0, 0, [&] { return launch_push(fa, B, mark, s); }));
         all_dirty = !mark;
         std::swap(L_old, L_new);
-        if (full && R.mode != F_TRACE && t == 1) {
+        if (t == 1 && R.mode != F_TRACE) {
             if (changed <= thr) {
                 R.converged = 1;
                 break;
@@ -865,7 +880,10 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
                 break;
             }
         } else if (phase == PH_LEARN) {
-            if (changed <= thr) {
+            // the skipped rows would have changed with the predicted
+            // probabilities: stop predicting once the expected full-round
+            // count passes the tolerance test
+            if (changed + expected_skipped <= thr) {
                 phase = PH_CHECK;
                 R.check_round = t + 1;
             }

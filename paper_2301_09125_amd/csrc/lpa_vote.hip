@@ -49,11 +49,19 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t stride = gridDim.x * 256;
     u64 wchg = 0;
+    // row of this lane's next work item, loaded one iteration ahead
+    uint32_t vnext = 0;
+    {
+        const uint32_t i0 = blockIdx.x * 256 + (threadIdx.x & ~63u) + lane;
+        if (i0 < cnt) vnext = row_of(a, lo, i0);
+    }
     for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < cnt; base += stride) {
         const uint32_t i = base + lane;
+        const uint32_t vcur = vnext;
+        if (i + stride < cnt) vnext = row_of(a, lo, i + stride);
         bool ch = false;
         if (i < cnt) {
-            const uint32_t v = row_of(a, lo, i);
+            const uint32_t v = vcur;
             const uint64_t b = a.g.rp[v];
             const uint64_t e = a.g.rp[v + 1];
             const uint32_t own = a.L_old[v];
@@ -125,10 +133,16 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
     wave_sync();
     u64 wchg = 0;
     const uint32_t stride = gridDim.x * GPB;
+    uint32_t vnext = 0;  // row of the group's next work item, loaded one iteration ahead
+    {
+        const uint32_t i0 = blockIdx.x * GPB + wave * GPW + lane / G;
+        if (i0 < cnt) vnext = row_of(a, lo, i0);
+    }
     for (uint32_t base = blockIdx.x * GPB + wave * GPW; base < cnt; base += stride) {
         const uint32_t idx = base + lane / G;
         const bool act = idx < cnt;
-        const uint32_t v = act ? row_of(a, lo, idx) : 0u;
+        const uint32_t v = act ? vnext : 0u;
+        if (idx + stride < cnt) vnext = row_of(a, lo, idx + stride);
         uint64_t b = 0, e = 0;
         uint32_t own = 0;
         if (act) {
