@@ -42,6 +42,9 @@ WORKLOADS = {
                  "seed 4096", lambda gg: gg.road(4096, 4096, 0.3, 0.01, 1, 8, seed=4096)),
     "sbm10k": ("planted partition, 10000 vertices, 100 blocks, p_in 0.1, p_out 0.001, seed 1",
                lambda gg: gg.sbm(10000, 100, 0.1, 0.001, seed=1)),
+    "learned24": ("R-MAT scale 24, edge factor 16, same (a,b,c), unit weights, seed 24; the learned-frontier run "
+                  "(model trained on R-MAT 18-20 and two 1024x1024 lattices) timed against plain RAK",
+                  lambda gg: gg.rmat(24, 16, 0.57, 0.19, 0.19, seed=24)),
     "batch50m": ("4096 planted-partition graphs, n log-uniform in [200, 6150], 8-64 blocks, mean intra degree 12, "
                  "inter degree 2, seed 4096 (about 5e7 edges)",
                  lambda gg: gg.sbm_batch(4096, 200, 6150, seed=4096)),
@@ -139,6 +142,12 @@ def run_batch_bench(args, b, desc, P):
     torch.cuda.synchronize()
     ctx = P.Context(0)
     labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    tuned = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tuned, tried = ctx.autotune(dg, b.gv)
+        log(f"[bench] autotuned bins in {time.perf_counter() - t0:.2f}s over {tried} candidates: "
+            f"{ {k: tuned[k] for k in ('thread_max', 'group_max', 'wave_max', 'wide_max')} }")
 
     def step():
         _, st = ctx.run_batch(dg, b.gv, tol=args.tol, max_iter=args.max_iter, labels_out=labels)
@@ -193,6 +202,8 @@ def run_batch_bench(args, b, desc, P):
         "config": {"workload": f"{args.workload}: {desc}", "graphs": b.G, "n": g.n, "m_arcs": g.m,
                    "tol": args.tol, "max_iter": args.max_iter, "self_weight": 1, "tie_break": "lowest label",
                    "rounds": st0.rounds, "converged_graphs": st0.converged_graphs,
+                   "bins": None if tuned is None else {k: tuned[k] for k in ("thread_max", "group_max", "wave_max",
+                                                                             "wide_max")},
                    "hbm_gbs_effective": round(bytes_step * args.steps / elapsed / 1e9, 1),
                    "device_ms": round(dev_ms, 4)},
         "roofline": roofline,
@@ -200,6 +211,105 @@ def run_batch_bench(args, b, desc, P):
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def nmi(a, b) -> float:
+    """Normalised mutual information (arithmetic mean of the entropies,
+    natural log) of two labelings."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    n = a.size
+    _, ai = np.unique(a, return_inverse=True)
+    _, bi = np.unique(b, return_inverse=True)
+    pa = np.bincount(ai) / n
+    pb = np.bincount(bi) / n
+    _, nij = np.unique(ai.astype(np.int64) * (int(bi.max()) + 1) + bi, return_counts=True)
+    keys = _
+    pij = nij / n
+    ia, ib = keys // (int(bi.max()) + 1), keys % (int(bi.max()) + 1)
+    mi = float(np.sum(pij * np.log(pij / (pa[ia] * pb[ib]))))
+    ha, hb = float(-np.sum(pa * np.log(pa))), float(-np.sum(pb * np.log(pb)))
+    return 1.0 if ha + hb == 0 else 2.0 * mi / (ha + hb)
+
+
+def run_learned_bench(args, g, desc, P):
+    """Learned-frontier RAK against plain RAK on the same graph: the timed
+    steps are learned runs (lpa_run_learned + modularity); plain runs are
+    timed the same way for the comparison in `config`."""
+    import torch
+    from paper_2301_09125_amd import train_frontier as TF
+    model = TF.load_model()
+    dg = P.DeviceGraph.from_csr(g, "cuda")
+    labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    plain = P.Context(0, modularity=1)
+    lctx = P.Context(0, profile=0 if args.no_profile else 1, modularity=1)
+
+    def plain_step():
+        _, st = plain.run(dg, tol=args.tol, max_iter=args.max_iter, labels_out=labels)
+        return st, st.modularity
+
+    def learned_step():
+        _, st, _ = lctx.run_learned(dg, model, tol=args.tol, max_iter=args.max_iter, labels_out=labels)
+        return st, st.modularity
+
+    for _ in range(args.warmup):
+        plain_step()
+        learned_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pst, pq = plain_step()
+    torch.cuda.synchronize()
+    plain_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    plain_labels = P.labels_to_numpy(labels)
+    lctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    arcs = 0
+    for _ in range(args.steps):
+        lst, lq = learned_step()
+        arcs += lst.arcs_processed
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    learned_labels = P.labels_to_numpy(labels)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = arcs / elapsed / 1e9
+    agree = nmi(learned_labels, plain_labels)
+    log(f"[bench] plain {plain_ms:.3f} ms/step ({pst.iterations} rounds, Q {pq:.6f}); learned {ms_per_step:.3f} ms/step "
+        f"({lst.iterations} rounds, {lst.learned_rounds} learned, Q {lq:.6f}, NMI vs plain {agree:.4f})")
+    roofline = None
+    prof = [] if args.no_profile else lctx.profile()
+    votes = [p for p in prof if p["launches"] and p["bytes"]]
+    if votes:
+        dom = max(votes, key=lambda p: p["ms"])
+        achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic_from_profile(args.workload, dom["name"]),
+                    "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
+                    "bytes_per_launch": dom["bytes"] // dom["launches"]}
+    cpu = None
+    if args.cpu_seconds > 0:
+        log(f"[bench] cpu baseline: oracle rounds for about {args.cpu_seconds:.0f} s ...")
+        cpu = cpu_baseline(g, args.cpu_seconds)
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GE/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n": g.n, "m_arcs": g.m, "tol": args.tol,
+                   "max_iter": args.max_iter, "self_weight": 1, "tau": model["tau"],
+                   "plain_ms_per_step": round(plain_ms, 4), "learned_ms_per_step": round(ms_per_step, 4),
+                   "speedup_vs_plain": round(plain_ms / ms_per_step, 4),
+                   "plain_rounds": pst.iterations, "learned_rounds": lst.iterations,
+                   "learned_phase_rounds": lst.learned_rounds, "voted_per_round": lst.voted,
+                   "modularity_plain": pq, "modularity_learned": lq, "modularity_delta": lq - pq,
+                   "nmi_vs_plain": round(agree, 6)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plain.close()
+    lctx.close()
 
 
 def main():
@@ -215,6 +325,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for counter profiles)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    ap.add_argument("--no-autotune", action="store_true", help="batch workloads: keep the default bins")
+    ap.add_argument("--autotune", action="store_true", help="single-graph workloads: autotune the bins first")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -238,10 +350,16 @@ def main():
         log(f"[bench] generated {args.workload}: G={g.G} n={g.csr.n} m={g.csr.m} in {time.perf_counter() - t0:.1f}s")
         return run_batch_bench(args, g, desc, P)
     log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
+    if args.workload.startswith("learned"):
+        return run_learned_bench(args, g, desc, P)
     dg = P.DeviceGraph.from_csr(g, "cuda")
     torch.cuda.synchronize()
     ctx = P.Context(0, profile=0 if args.no_profile else 1, modularity=1)
     labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuned, tried = ctx.autotune(dg)
+        log(f"[bench] autotuned bins in {time.perf_counter() - t0:.2f}s over {tried} candidates: {tuned}")
 
     def step():
         # one call: binning + relabelled CSR, rounds to tolerance, modularity

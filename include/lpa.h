@@ -234,6 +234,8 @@ typedef struct {
     uint64_t arcs_processed;    /* arcs of the rows actually voted */
     double ms_total;
     double ms_rounds;
+    double modularity;          /* with options.modularity: Q of the result */
+    uint64_t mod_terms[4];      /* ... and its terms, as lpa_modularity's */
     uint64_t *changed_per_iter;    /* host, cap entries, or NULL */
     uint64_t *voted_per_iter;      /* rows voted per round, or NULL */
     uint64_t *candidates_per_iter; /* rows that could change per round, or NULL */
@@ -296,6 +298,19 @@ lpa_status lpa_mlp_forward(lpa_ctx *ctx, const lpa_mlp *model, const float *X, u
  * computes them for one batch (N <= 2^31). */
 lpa_status lpa_mlp_grad(lpa_ctx *ctx, const lpa_mlp *model, const float *X, const uint8_t *y, uint64_t N,
                         float pos_weight, float *grad, float *loss);
+
+/* Autotuner of the degree bins: times `rounds` rounds (0 = 2) of lpa_run --
+ * or of lpa_run_batch when graph_vptr is given -- under every combination of
+ * thread_max {4, 8}, group_max {16, 32}, wave_max {64, 128} and wide_max
+ * {256, 512}, and makes the fastest the context's thresholds.  The choice is
+ * cached in the context under the graph's degree signature (share of rows
+ * and of arcs per power-of-two row length, in 1/32 steps, with the orders of
+ * magnitude of n and m); a graph with a cached signature is not timed again.
+ * chosen: host, receives the context's options afterwards (may be NULL);
+ * measured: host, the number of candidates timed (0 on a cache hit; may be
+ * NULL).  Labels never depend on the thresholds, only the speed does. */
+lpa_status lpa_autotune(lpa_ctx *ctx, const lpa_csr *g, const uint64_t *graph_vptr, uint32_t G, uint32_t rounds,
+                        lpa_options *chosen, uint32_t *measured);
 
 /* Copy up to `cap` per-kernel profile records into out (host); *count gets
  * the number of records available.  lpa_profile_reset clears them. */

@@ -38,6 +38,7 @@ constexpr int kWaveSlotsSmall = 256;
 constexpr int kWaveArcs = 512;       // arcs per wavefront work item
 constexpr int kWaveSlots = 1024;     // LDS slots per wavefront (<= 512 arcs)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kDegBuckets = 24;  // row-length histogram of the autotuner
 
 // Long rows: each 512-arc segment reports its kTopK heaviest labels and a
 // bound on every label it did not report; rows of at most kMergeWaveSegs
@@ -214,6 +215,7 @@ struct FrontArgs {
 // ---- launchers: lpa_prep.hip ---------------------------------------------
 hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t count, hipStream_t s);
+hipError_t launch_degree_hist(const uint64_t *rp, uint32_t n, unsigned long long *hist, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t count, hipStream_t s);
 hipError_t launch_check_labels(const uint32_t *labels, uint32_t n, uint32_t *err, hipStream_t s);
 uint32_t bin_blocks(uint32_t n);

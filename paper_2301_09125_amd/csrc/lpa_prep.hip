@@ -38,6 +38,30 @@ hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t n, hipStream_t s) {
     iota_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(a, n);
     return hipGetLastError();
 }
+// Histogram of row lengths in buckets 0, 1, 2..3, 4..7, ... (bucket b > 0
+// holds lengths in [2^(b-1), 2^b)); kDegBuckets u64 counters, arcs per
+// bucket in the next kDegBuckets.
+__global__ void degree_hist_k(const uint64_t *rp, uint32_t n, u64 *hist) {
+    __shared__ u64 h[2 * kDegBuckets];
+    for (uint32_t i = threadIdx.x; i < 2 * kDegBuckets; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint64_t d = rp[v + 1] - rp[v];
+        const int b = d == 0 ? 0 : min(kDegBuckets - 1, 64 - __clzll((long long)d));
+        atomicAdd(&h[b], 1ull);
+        atomicAdd(&h[kDegBuckets + b], (u64)d);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 2 * kDegBuckets; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+hipError_t launch_degree_hist(const uint64_t *rp, uint32_t n, u64 *hist, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    degree_hist_k<<<grid_for(n, 256, 1024), 256, 0, s>>>(rp, n, hist);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(u64 *p, u64 v, uint64_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
     fill64_k<<<grid_for(count, 256, 8192), 256, 0, s>>>(p, v, count);

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -59,13 +60,15 @@ struct DevBuf {
 
 enum KernelId {
     K_THREAD, K_GROUP, K_WAVE, K_WIDE, K_HUB, K_HUB1, K_MERGE, K_FALLBACK, K_REDUCE, K_FINAL, K_MOD,
-    K_PREDICT, K_PUSH, K_COUNT
+    K_PREDICT, K_PUSH, K_LISTED, K_COUNT
 };
 // vote_hub_first: the long-row vote of round 1 from the unique labels;
-// predict / push: candidate selection and frontier stamps of frontier runs
+// predict / push: candidate selection and frontier stamps of frontier runs;
+// vote_listed: the short-row votes of a round driven by candidate lists
 const char *kKernelNames[K_COUNT] = {"vote_thread",  "vote_group", "vote_wave",    "vote_wide",
                                      "vote_hub",     "vote_hub_first", "hub_merge", "hub_fallback",
-                                     "hub_reduce",   "hub_final",  "modularity", "predict", "push"};
+                                     "hub_reduce",   "hub_final",  "modularity", "predict", "push",
+                                     "vote_listed"};
 
 struct Pending {
     int kid;
@@ -100,6 +103,8 @@ struct lpa_ctx {
     DevBuf gid, gvd, bstate, bseg;  // batched run
     DevBuf f_top1, f_top2, f_kw, f_last, f_front, f_stale, f_lists, f_small, f_model;  // frontier runs
     DevBuf t_w, t_m, t_v, t_part, t_grad, t_loss, t_z;                               // training
+    DevBuf tune_labels, tune_hist;                                                    // autotuner
+    std::map<std::vector<int>, lpa_options> tune_cache;
     bool slab_dirty = false;      // slab may hold entries (set after a timed-out batch)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t bexec = nullptr;
@@ -410,16 +415,17 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
         }
         return r;
     };
-    LPA_TRY(timed(c, K_THREAD, bytes(BIN_THREAD), B.arcs[BIN_THREAD], [&] {
+    auto kid = [&](int k) { return lists ? (int)K_LISTED : k; };
+    LPA_TRY(timed(c, kid(K_THREAD), bytes(BIN_THREAD), B.arcs[BIN_THREAD], [&] {
         return launch_vote_thread(args(BIN_THREAD), B.lo[BIN_THREAD], B.cnt[BIN_THREAD], first, feat, cap, s);
     }));
-    LPA_TRY(timed(c, K_GROUP, bytes(BIN_GROUP), B.arcs[BIN_GROUP], [&] {
+    LPA_TRY(timed(c, kid(K_GROUP), bytes(BIN_GROUP), B.arcs[BIN_GROUP], [&] {
         return launch_vote_group(args(BIN_GROUP), B.lo[BIN_GROUP], B.cnt[BIN_GROUP], first, feat, cap, s);
     }));
-    LPA_TRY(timed(c, K_WAVE, bytes(BIN_WAVE), B.arcs[BIN_WAVE], [&] {
+    LPA_TRY(timed(c, kid(K_WAVE), bytes(BIN_WAVE), B.arcs[BIN_WAVE], [&] {
         return launch_vote_wave(args(BIN_WAVE), B.lo[BIN_WAVE], B.cnt[BIN_WAVE], 0, first, feat, cap, s);
     }));
-    LPA_TRY(timed(c, K_WIDE, bytes(BIN_WIDE), B.arcs[BIN_WIDE], [&] {
+    LPA_TRY(timed(c, kid(K_WIDE), bytes(BIN_WIDE), B.arcs[BIN_WIDE], [&] {
         return launch_vote_wave(args(BIN_WIDE), B.lo[BIN_WIDE], B.cnt[BIN_WIDE], 1, first, feat, c->num_cu * 5, s);
     }));
     if (P.H) {
@@ -1287,6 +1293,8 @@ lpa_status lpa_run_learned(lpa_ctx *ctx, const lpa_csr *g, const lpa_mlp *model,
         stats->changed_last = 0;
         stats->arcs_processed = 0;
         stats->ms_total = stats->ms_rounds = 0;
+        stats->modularity = 0;
+        for (int i = 0; i < 4; ++i) stats->mod_terms[i] = 0;
     }
     FrontRun R;
     R.mode = F_LEARNED;
@@ -1302,6 +1310,8 @@ lpa_status lpa_run_learned(lpa_ctx *ctx, const lpa_csr *g, const lpa_mlp *model,
         stats->changed_last = R.changed_last;
         stats->arcs_processed = R.arcs;
         stats->ms_rounds = R.ms_rounds;
+        stats->modularity = R.q;
+        for (int i = 0; i < 4; ++i) stats->mod_terms[i] = R.terms[i];
         for (uint32_t t = 0; t < R.iterations && t < stats->cap; ++t) {
             if (stats->changed_per_iter) stats->changed_per_iter[t] = R.changed[t];
             if (stats->voted_per_iter) stats->voted_per_iter[t] = R.voted[t];
@@ -1433,6 +1443,98 @@ lpa_status lpa_run_batch(lpa_ctx *ctx, const lpa_csr *packed, const uint64_t *gr
     return run_batch_impl(ctx, packed, graph_vptr, G, labels_out, tol, max_iter, stats);
 }
 
+lpa_status lpa_autotune(lpa_ctx *c, const lpa_csr *g, const uint64_t *graph_vptr, uint32_t G, uint32_t rounds,
+                        lpa_options *chosen, uint32_t *measured) {
+    if (!c) return LPA_EINVAL;
+    LPA_TRY(check_csr_args(g));
+    if (measured) *measured = 0;
+    if (rounds == 0) rounds = 2;
+    HIP_TRY(hipSetDevice(c->device));
+    const hipStream_t s = c->stream;
+    // degree signature: fractions of rows and arcs per power-of-two length
+    // bucket, in 1/32 steps, plus the magnitudes of n and m
+    std::vector<int> key;
+    key.push_back(graph_vptr ? 1 : 0);
+    key.push_back(g->w ? 1 : 0);
+    key.push_back(g->n ? 31 - __builtin_clz(g->n) : -1);
+    key.push_back(g->m ? 63 - __builtin_clzll(g->m) : -1);
+    if (g->n) {
+        HIP_TRY(c->tune_hist.ensure(2 * kDegBuckets * sizeof(u64)));
+        HIP_TRY(launch_fill_u64(c->tune_hist.as<u64>(), 0, 2 * kDegBuckets, s));
+        HIP_TRY(launch_degree_hist(g->row_ptr, g->n, c->tune_hist.as<u64>(), s));
+        std::vector<u64> h(2 * kDegBuckets);
+        HIP_TRY(hipMemcpyAsync(h.data(), c->tune_hist.p, h.size() * sizeof(u64), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int b = 0; b < kDegBuckets; ++b) {
+            key.push_back((int)std::lround(32.0 * (double)h[b] / (double)g->n));
+            key.push_back(g->m ? (int)std::lround(32.0 * (double)h[kDegBuckets + b] / (double)g->m) : 0);
+        }
+    }
+    auto it = c->tune_cache.find(key);
+    if (it == c->tune_cache.end()) {
+        const lpa_options saved = c->opt;
+        lpa_options best = saved;
+        double best_ms = 1e300;
+        uint32_t tried = 0;
+        if (g->n) {
+            HIP_TRY(c->tune_labels.ensure((size_t)g->n * sizeof(uint32_t)));
+            const uint32_t tms[] = {4, 8}, gms[] = {16, 32}, wms[] = {64, 128}, xms[] = {256, 512};
+            for (uint32_t tm : tms)
+                for (uint32_t gm : gms)
+                    for (uint32_t wm : wms)
+                        for (uint32_t xm : xms) {
+                            c->opt.thread_max = tm;
+                            c->opt.group_max = gm;
+                            c->opt.wave_max = wm;
+                            c->opt.wide_max = xm;
+                            c->opt.profile = 0;
+                            c->opt.modularity = 0;
+                            c->opt.frontier = 0;
+                            double ms = 1e300;
+                            for (int rep = 0; rep < 2; ++rep) {
+                                double t = 0;
+                                lpa_status st;
+                                if (graph_vptr) {
+                                    lpa_batch_stats bs;
+                                    std::memset(&bs, 0, sizeof(bs));
+                                    st = run_batch_impl(c, g, graph_vptr, G, c->tune_labels.as<uint32_t>(), 0.0,
+                                                        rounds, &bs);
+                                    t = bs.ms_device;
+                                } else {
+                                    lpa_stats rs;
+                                    std::memset(&rs, 0, sizeof(rs));
+                                    st = run_impl(c, g, c->tune_labels.as<uint32_t>(), 0.0, rounds, &rs, false);
+                                    t = rs.ms_rounds;
+                                }
+                                if (st != LPA_OK) {
+                                    c->opt = saved;
+                                    return st;
+                                }
+                                ms = std::min(ms, t);
+                            }
+                            ++tried;
+                            if (ms < best_ms) {
+                                best_ms = ms;
+                                best = saved;
+                                best.thread_max = tm;
+                                best.group_max = gm;
+                                best.wave_max = wm;
+                                best.wide_max = xm;
+                            }
+                        }
+        }
+        c->opt = saved;
+        it = c->tune_cache.emplace(key, best).first;
+        if (measured) *measured = tried;
+    }
+    c->opt.thread_max = it->second.thread_max;
+    c->opt.group_max = it->second.group_max;
+    c->opt.wave_max = it->second.wave_max;
+    c->opt.wide_max = it->second.wide_max;
+    if (chosen) *chosen = c->opt;
+    return LPA_OK;
+}
+
 lpa_status lpa_modularity(lpa_ctx *c, const lpa_csr *g, const uint32_t *labels, double *q_out, uint64_t *terms) {
     if (!c || !q_out) return LPA_EINVAL;
     LPA_TRY(check_csr_args(g));
@@ -1484,7 +1586,7 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->mrows,      &c->slab_pending, &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
                       &c->f_top1, &c->f_top2, &c->f_kw, &c->f_last, &c->f_front, &c->f_stale, &c->f_lists,
                       &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
-                      &c->t_loss, &c->t_z};
+                      &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist};
     if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) b->release();

@@ -72,6 +72,7 @@ class _LearnedStats(ctypes.Structure):
                 ("learned_rounds", ctypes.c_uint32), ("check_round", ctypes.c_uint32),
                 ("changed_last", ctypes.c_uint64), ("arcs_processed", ctypes.c_uint64),
                 ("ms_total", ctypes.c_double), ("ms_rounds", ctypes.c_double),
+                ("modularity", ctypes.c_double), ("mod_terms", ctypes.c_uint64 * 4),
                 ("changed_per_iter", ctypes.c_void_p), ("voted_per_iter", ctypes.c_void_p),
                 ("candidates_per_iter", ctypes.c_void_p), ("cap", ctypes.c_uint32)]
 
@@ -111,7 +112,7 @@ class _KProf(ctypes.Structure):
 
 
 EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_run_batch", "lpa_run_learned",
-           "lpa_trace", "lpa_train", "lpa_mlp_forward", "lpa_mlp_grad", "lpa_modularity",
+           "lpa_trace", "lpa_train", "lpa_mlp_forward", "lpa_mlp_grad", "lpa_autotune", "lpa_modularity",
            "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
 
 
@@ -138,6 +139,8 @@ def _load():
     lib.lpa_train.argtypes = [vp, vp, vp, u64, ctypes.POINTER(_TrainOpts), ctypes.POINTER(_Mlp), vp]
     lib.lpa_mlp_forward.argtypes = [vp, ctypes.POINTER(_Mlp), vp, u64, vp]
     lib.lpa_mlp_grad.argtypes = [vp, ctypes.POINTER(_Mlp), vp, vp, u64, _F32, vp, ctypes.POINTER(_F32)]
+    lib.lpa_autotune.argtypes = [vp, ctypes.POINTER(_Csr), vp, u32, u32, ctypes.POINTER(_Options),
+                                 ctypes.POINTER(u32)]
     lib.lpa_modularity.argtypes = [vp, ctypes.POINTER(_Csr), vp, ctypes.POINTER(dbl),
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.lpa_profile_get.argtypes = [vp, ctypes.POINTER(_KProf), u32, ctypes.POINTER(u32)]
@@ -146,7 +149,8 @@ def _load():
     lib.lpa_destroy.restype = None
     lib.lpa_strerror.argtypes = [ctypes.c_int]
     lib.lpa_strerror.restype = ctypes.c_char_p
-    for f in (lib.lpa_run_learned, lib.lpa_trace, lib.lpa_train, lib.lpa_mlp_forward, lib.lpa_mlp_grad):
+    for f in (lib.lpa_run_learned, lib.lpa_trace, lib.lpa_train, lib.lpa_mlp_forward, lib.lpa_mlp_grad,
+              lib.lpa_autotune):
         f.restype = ctypes.c_int
     for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_run_batch, lib.lpa_modularity, lib.lpa_profile_get,
               lib.lpa_profile_reset):
@@ -251,6 +255,7 @@ class LearnedStats:
     changed: list
     voted: list
     candidates: list
+    modularity: float = 0.0
 
 
 class Context:
@@ -385,7 +390,7 @@ class Context:
         k = st.iterations
         stats = LearnedStats(k, bool(st.converged), st.learned_rounds, st.check_round, st.changed_last,
                              st.arcs_processed, st.ms_total, st.ms_rounds, [int(x) for x in ch[:k]],
-                             [int(x) for x in vo[:k]], [int(x) for x in ca[:k]])
+                             [int(x) for x in vo[:k]], [int(x) for x in ca[:k]], st.modularity)
         return labels_out, stats, (mk[:k] if mk is not None else None)
 
     def trace(self, g: DeviceGraph, tol: float = 0.05, max_iter: int = 20, cap: int | None = None):
@@ -445,6 +450,20 @@ class Context:
         d = _mlp_from_c(out)
         d.pop("tau")
         return float(loss.value), d
+
+    def autotune(self, g: DeviceGraph, graph_vptr=None, rounds: int = 2):
+        """Pick the fastest degree-bin thresholds for g (batched when
+        graph_vptr is given); returns (options dict, candidates timed)."""
+        o = _Options()
+        n = ctypes.c_uint32(0)
+        gv = None if graph_vptr is None else np.ascontiguousarray(np.asarray(graph_vptr, dtype=np.uint64))
+        c = g._c()
+        rc = _load().lpa_autotune(self._h, ctypes.byref(c), gv.ctypes.data if gv is not None else None,
+                                  0 if gv is None else len(gv) - 1, rounds, ctypes.byref(o), ctypes.byref(n))
+        if rc:
+            raise LpaError(rc, "lpa_autotune")
+        self.options = {k: getattr(o, k) for k, _ in _Options._fields_}
+        return dict(self.options), int(n.value)
 
     def modularity(self, g: DeviceGraph, labels):
         """(Q, {'two_m', 'sigma_in', 'sum_k2'}) computed on the device."""
