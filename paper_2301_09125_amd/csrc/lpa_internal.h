@@ -83,6 +83,7 @@ struct RoundArgs {
     const uint32_t *list;         // rows of the launch: list[0..min(cnt, *list_n)) (NULL: lo .. lo+cnt-1)
     const uint32_t *list_n;       // device count of list entries
     uint32_t *top1, *top2;        // vote kernels with FEAT: winning / runner-up tally per row
+    uint32_t skip_distinct;       // round 1: rows flagged ROW_DISTINCT were voted by the relabel pass
 };
 
 // A wavefront work item of a long row: internal row r (= hub index), arcs
@@ -212,10 +213,25 @@ struct FrontArgs {
     uint32_t keep_all;   // vote every candidate (no prediction)
 };
 
+// Round 1 from the unique labels computed by the relabel pass (rows that
+// list each neighbour once); see RelabelArgs in lpa_prep.hip.
+struct Round1Fuse {
+    uint32_t *L1;                 // round-1 label buffer (internal index)
+    unsigned long long *changed;  // round-1 counter words
+    uint32_t sw;
+};
+
 // ---- launchers: lpa_prep.hip ---------------------------------------------
 hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t count, hipStream_t s);
 hipError_t launch_degree_hist(const uint64_t *rp, uint32_t n, unsigned long long *hist, hipStream_t s);
+hipError_t launch_hub_plan(const uint64_t *rp2, uint32_t H, uint32_t merge_max, uint32_t *item_lo,
+                           uint64_t *slab_off, uint64_t *touched_off, uint32_t *ritem_lo, uint32_t *mw_pos,
+                           uint32_t *mb_pos, unsigned long long *out, hipStream_t s);
+hipError_t launch_hub_items(const uint64_t *rp2, uint32_t H, uint32_t merge_max, const uint32_t *item_lo,
+                            const uint32_t *ritem_lo, const uint32_t *mw_pos, const uint32_t *mb_pos,
+                            uint32_t n_mwave, HubItem *items, ReduceItem *ritems, uint32_t *hflags,
+                            uint32_t *slab_mask, uint32_t *mrows, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t count, hipStream_t s);
 hipError_t launch_check_labels(const uint32_t *labels, uint32_t n, uint32_t *err, hipStream_t s);
 uint32_t bin_blocks(uint32_t n);
@@ -230,10 +246,11 @@ hipError_t launch_bin_scatter(const Graph &g, const BinCfg &cfg, const uint32_t 
 // flag rows that list each neighbour once.
 hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                                uint32_t *col2, uint32_t *w2, uint8_t *rowflag, uint32_t lo, uint32_t cnt,
-                               int per_wave, uint32_t *err, hipStream_t s);
+                               int per_wave, uint32_t *err, const Round1Fuse *f, hipStream_t s);
 hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                               uint32_t *col2, uint32_t *w2, const HubItem *items, uint32_t count,
-                              uint32_t *hub_flags, uint32_t *err, hipStream_t s);
+                              uint32_t *hub_flags, uint32_t *err, const Round1Fuse *f, const HubState *hs,
+                              uint32_t H, hipStream_t s);
 hipError_t launch_init_labels(uint32_t *La, uint32_t *Lb, const uint32_t *old_of, const uint32_t *labels_in,
                               uint32_t n, hipStream_t s);
 hipError_t launch_scatter_labels(uint32_t *labels_out, const uint32_t *old_of, const uint32_t *L, uint32_t n_int,
@@ -248,7 +265,7 @@ hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int 
 hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int feat,
                             int grid_cap, hipStream_t s);
 hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
-                           int first, int grid_cap, hipStream_t s);
+                           int first, int fused, int grid_cap, hipStream_t s);
 // Merge the top-K reports of each listed row; undecided rows get HUB_FALLBACK.
 hipError_t launch_hub_merge(const RoundArgs &a, const HubState &hs, const uint32_t *rows, uint32_t count,
                             int per_block, int first, hipStream_t s);

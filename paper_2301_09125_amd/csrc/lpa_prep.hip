@@ -302,6 +302,123 @@ hipError_t launch_bin_scatter(const Graph &g, const BinCfg &cfg, const uint32_t 
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------- long rows --
+//
+// Work layout of the long rows (internal ids 0..H-1), planned on the device:
+// per row d arcs, ceil(d/512) wavefront segments (HubItem), a slab of
+// pow2(2d) slots, a touched list of d entries, ceil(d/2048) reduce items,
+// and a merge class (one wavefront for <= kMergeWaveSegs segments, one block
+// up to merge_max, else HUB_BIG: always through the slab).
+
+// Exclusive scan of one value per thread of a 1024-thread block; returns
+// the prefix and adds the block total to *carry (all threads see it).
+__device__ __forceinline__ u64 block_scan_1024(u64 x, u64 *wtot, u64 &carry) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    u64 inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const u64 y = __shfl_up(inc, off, 64);
+        if ((int)lane >= off) inc += y;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    u64 before = 0, total = 0;
+    for (uint32_t q = 0; q < 16; ++q) {
+        if (q < wave) before += wtot[q];
+        total += wtot[q];
+    }
+    const u64 res = carry + before + inc - x;
+    __syncthreads();
+    carry += total;
+    return res;
+}
+
+__global__ __launch_bounds__(1024) void hub_plan_k(const uint64_t *rp2, uint32_t H, uint32_t merge_max,
+                                                   uint32_t *item_lo, uint64_t *slab_off, uint64_t *touched_off,
+                                                   uint32_t *ritem_lo, uint32_t *mw_pos, uint32_t *mb_pos,
+                                                   u64 *out) {
+    __shared__ u64 wtot[16];
+    u64 c_items = 0, c_slab = 0, c_touch = 0, c_red = 0, c_mw = 0, c_mb = 0;
+    for (uint32_t base = 0; base < H; base += 1024) {
+        const uint32_t h = base + threadIdx.x;
+        u64 d = 0, nseg = 0, slots = 0, red = 0, mw = 0, mb = 0;
+        if (h < H) {
+            d = rp2[h + 1] - rp2[h];
+            nseg = (d + kWaveArcs - 1) / kWaveArcs;
+            slots = 1;
+            while (slots < 2 * d) slots <<= 1;
+            red = (d + 2047) / 2048;
+            const bool big = nseg > merge_max;
+            mw = !big && nseg <= (u64)kMergeWaveSegs;
+            mb = !big && !mw;
+        }
+        const u64 pi = block_scan_1024(nseg, wtot, c_items);
+        const u64 ps = block_scan_1024(slots, wtot, c_slab);
+        const u64 pt = block_scan_1024(d, wtot, c_touch);
+        const u64 pr = block_scan_1024(red, wtot, c_red);
+        const u64 pw = block_scan_1024(mw, wtot, c_mw);
+        const u64 pb = block_scan_1024(mb, wtot, c_mb);
+        if (h < H) {
+            item_lo[h] = (uint32_t)pi;
+            slab_off[h] = ps;
+            touched_off[h] = pt;
+            ritem_lo[h] = (uint32_t)pr;
+            mw_pos[h] = (uint32_t)pw;
+            mb_pos[h] = (uint32_t)pb;
+        }
+    }
+    if (threadIdx.x == 0) {
+        item_lo[H] = (uint32_t)c_items;
+        out[0] = c_items;
+        out[1] = c_red;
+        out[2] = c_slab;
+        out[3] = c_touch;
+        out[4] = c_mw;
+        out[5] = c_mb;
+    }
+}
+
+__global__ void hub_items_k(const uint64_t *rp2, uint32_t H, uint32_t merge_max, const uint32_t *item_lo,
+                            const uint32_t *ritem_lo, const uint32_t *mw_pos, const uint32_t *mb_pos,
+                            uint32_t n_mwave, HubItem *items, ReduceItem *ritems, uint32_t *hflags,
+                            uint32_t *slab_mask, uint32_t *mrows) {
+    for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
+        const uint64_t b = rp2[h], e = rp2[h + 1], d = e - b;
+        const uint64_t nseg = (d + kWaveArcs - 1) / kWaveArcs;
+        uint64_t slots = 1;
+        while (slots < 2 * d) slots <<= 1;
+        const bool big = nseg > merge_max;
+        const bool mw = !big && nseg <= (uint64_t)kMergeWaveSegs;
+        hflags[h] = big ? HUB_BIG : 0u;
+        slab_mask[h] = (uint32_t)(slots - 1);
+        uint32_t k = item_lo[h];
+        for (uint64_t x = b; x < e; x += kWaveArcs) items[k++] = HubItem{h, 0, x, min(e, x + (uint64_t)kWaveArcs)};
+        uint32_t q = ritem_lo[h];
+        for (uint64_t t = 0; t < d; t += 2048) ritems[q++] = ReduceItem{h, (uint32_t)t, (uint32_t)min(d, t + 2048), 0};
+        if (mw)
+            mrows[mw_pos[h]] = h;
+        else if (!big)
+            mrows[n_mwave + mb_pos[h]] = h;
+    }
+}
+
+hipError_t launch_hub_plan(const uint64_t *rp2, uint32_t H, uint32_t merge_max, uint32_t *item_lo,
+                           uint64_t *slab_off, uint64_t *touched_off, uint32_t *ritem_lo, uint32_t *mw_pos,
+                           uint32_t *mb_pos, u64 *out, hipStream_t s) {
+    hub_plan_k<<<1, 1024, 0, s>>>(rp2, H, merge_max, item_lo, slab_off, touched_off, ritem_lo, mw_pos, mb_pos, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hub_items(const uint64_t *rp2, uint32_t H, uint32_t merge_max, const uint32_t *item_lo,
+                            const uint32_t *ritem_lo, const uint32_t *mw_pos, const uint32_t *mb_pos,
+                            uint32_t n_mwave, HubItem *items, ReduceItem *ritems, uint32_t *hflags,
+                            uint32_t *slab_mask, uint32_t *mrows, hipStream_t s) {
+    if (H == 0) return hipSuccess;
+    hub_items_k<<<grid_for(H, 256, 4096), 256, 0, s>>>(rp2, H, merge_max, item_lo, ritem_lo, mw_pos, mb_pos,
+                                                         n_mwave, items, ritems, hflags, slab_mask, mrows);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- relabel --
 
 struct RelabelArgs {
@@ -312,11 +429,37 @@ struct RelabelArgs {
     uint32_t *col2;
     uint32_t *w2;
     uint32_t *err;
+    // round 1 from the unique labels, done while the rows are copied: a
+    // row that lists each neighbour once sees every label (= the
+    // neighbour's id) once, so its vote is the max of (weight, -id) over the
+    // row and its own id with the self weight; NULL L1 = not done here
+    uint32_t *L1;       // round-1 labels (internal index)
+    u64 *changed;       // round-1 changed counter words
+    uint32_t sw;
+    HubState hs;        // long rows: best / own_sum / flags / rowsum
 };
+
+// Round-1 key of the arcs a lane holds (labels = original ids).
+template <int A>
+__device__ __forceinline__ void round1_keys(const uint32_t (&u)[A], const uint32_t (&wv)[A], uint32_t nvalid_mask,
+                                            uint32_t v, u64 &best, u64 &own_w, uint32_t &own_hit, u64 &rs) {
+#pragma unroll
+    for (int j = 0; j < A; ++j)
+        if (nvalid_mask >> j & 1u) {
+            rs += wv[j];
+            if (u[j] == v) {
+                own_w += wv[j];
+                own_hit = 1;
+            } else {
+                best = umax64(best, vote_key(u[j], wv[j]));
+            }
+        }
+}
 
 // Rows of at most 32 arcs, one lane each.
 __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *rowflag, uint32_t lo,
                                                         uint32_t cnt) {
+    u64 chg = 0;
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < cnt; i += gridDim.x * 256) {
         const uint32_t r = lo + i;
         const uint32_t v = a.old_of[r];
@@ -324,6 +467,8 @@ __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *
         const uint64_t dst = a.rp2[r];
         uint32_t prev = 0, distinct = 1;
         bool bad = false;
+        u64 best = 0, own_w = 0, rs = 0;
+        uint32_t own_hit = 0;
         for (uint64_t k = src; k < e; k += 4) {
             uint32_t u[4], wv[4];
 #pragma unroll
@@ -348,16 +493,31 @@ __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *
                     a.col2[dst + (k + j - src)] = a.new_of[u[j]];
                     if (a.w2) a.w2[dst + (k + j - src)] = wv[j];
                 }
+            if (a.L1) {
+                uint32_t m = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) m |= (k + j < e ? 1u : 0u) << j;
+                round1_keys<4>(u, wv, m, v, best, own_w, own_hit, rs);
+            }
         }
         if (bad) atomicOr(a.err, ERR_COL);
         rowflag[r] = distinct ? ROW_DISTINCT : 0;
+        if (a.L1 && distinct) {
+            if (own_hit || a.sw) best = umax64(best, vote_key(v, own_w + a.sw));
+            const uint32_t nl = best ? ~(uint32_t)best : v;
+            a.L1[r] = nl;
+            chg += nl != v;
+            if (rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+        }
     }
+    if (a.L1) block_count(chg, a.changed);
 }
 
 // Copy arcs [b0, b0 + len) of internal row r (one wavefront, <= 512 arcs)
 // from the caller's row of old_of[r]; returns 1 if they are strictly
 // increasing (also across the segment's first boundary inside the row).
-__device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32_t r, uint64_t b0, uint64_t len) {
+__device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32_t r, uint64_t b0, uint64_t len,
+                                                    u64 &best, u64 &own_w, uint32_t &own_hit, u64 &wsum) {
     constexpr int A = kWaveArcs / 64;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t v = a.old_of[r];
@@ -387,13 +547,22 @@ __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32
         u[j] = u[j] >= a.g.n ? 0u : u[j];
     }
     if (bad) atomicOr(a.err, ERR_COL);
+    uint32_t m = 0;
 #pragma unroll
     for (int j = 0; j < A; ++j) {
         const uint64_t k = lane + 64ull * j;
         if (k < len) {
+            m |= 1u << j;
             a.col2[b0 + k] = a.new_of[u[j]];
             if (a.w2) a.w2[b0 + k] = wv[j];
         }
+    }
+    if (a.L1) {
+        round1_keys<A>(u, wv, m, v, best, own_w, own_hit, wsum);
+        best = wave_max64(best);
+        own_w = wave_sum(own_w);
+        own_hit = __ballot(own_hit != 0) != 0;
+        wsum = wave_sum(wsum);
     }
     return __ballot(!ok) == 0 ? 1u : 0u;
 }
@@ -401,12 +570,26 @@ __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32
 // Rows of 33..512 arcs, one wavefront each.
 __global__ __launch_bounds__(256) void relabel_wave_k(RelabelArgs a, uint8_t *rowflag, uint32_t lo, uint32_t cnt) {
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 chg = 0;
     for (uint32_t i = blockIdx.x * 4 + wave; i < cnt; i += gridDim.x * 4) {
         const uint32_t r = lo + i;
         const uint64_t b0 = a.rp2[r], b1 = a.rp2[r + 1];
-        const uint32_t ok = relabel_segment(a, r, b0, b1 - b0);
-        if ((threadIdx.x & 63) == 0) rowflag[r] = ok ? ROW_DISTINCT : 0;
+        u64 best = 0, own_w = 0, rs = 0;
+        uint32_t own_hit = 0;
+        const uint32_t ok = relabel_segment(a, r, b0, b1 - b0, best, own_w, own_hit, rs);
+        if ((threadIdx.x & 63) == 0) {
+            rowflag[r] = ok ? ROW_DISTINCT : 0;
+            if (a.L1 && ok) {
+                const uint32_t v = a.old_of[r];
+                if (own_hit || a.sw) best = umax64(best, vote_key(v, own_w + a.sw));
+                const uint32_t nl = best ? ~(uint32_t)best : v;
+                a.L1[r] = nl;
+                chg += nl != v;
+                if (rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+            }
+        }
     }
+    if (a.L1) block_count(chg, a.changed);
 }
 
 // Long rows: one wavefront per work item; a segment with a repeated or
@@ -416,16 +599,46 @@ __global__ __launch_bounds__(256) void relabel_hub_k(RelabelArgs a, const HubIte
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
         const HubItem item = items[it];
-        const uint32_t ok = relabel_segment(a, item.r, item.b0, item.b1 - item.b0);
-        if ((threadIdx.x & 63) == 0 && !ok) atomicOr(&hub_flags[item.r], HUB_REPEATS);
+        u64 best = 0, own_w = 0, rs = 0;
+        uint32_t own_hit = 0;
+        const uint32_t ok = relabel_segment(a, item.r, item.b0, item.b1 - item.b0, best, own_w, own_hit, rs);
+        if ((threadIdx.x & 63) == 0) {
+            if (!ok) atomicOr(&hub_flags[item.r], HUB_REPEATS);
+            if (a.L1) {  // the row's round-1 partials, as the direct long-row vote gathers them
+                const uint32_t h = item.r;
+                if (best) atomicMax(&a.hs.best[h], best);
+                if (own_w) atomicAdd(&a.hs.own_sum[h], own_w);
+                if (own_hit) atomicOr(&a.hs.flags[h], HUB_OWN_SEEN);
+                atomicAdd(&a.hs.rowsum[h], rs);
+            }
+        }
+    }
+}
+
+// Rows whose segments turned out not to list each neighbour once are voted
+// by the regular round-1 kernels: drop the partials the copy gathered.
+__global__ void hub_unfuse_k(HubState hs, uint32_t H) {
+    for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
+        const uint32_t f = hs.flags[h];
+        if (f & HUB_REPEATS) {
+            hs.best[h] = 0;
+            hs.own_sum[h] = 0;
+            hs.rowsum[h] = 0;
+            hs.flags[h] = f & ~HUB_OWN_SEEN;
+        }
     }
 }
 
 hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                                uint32_t *col2, uint32_t *w2, uint8_t *rowflag, uint32_t lo, uint32_t cnt,
-                               int per_wave, uint32_t *err, hipStream_t s) {
+                               int per_wave, uint32_t *err, const Round1Fuse *f, hipStream_t s) {
     if (cnt == 0) return hipSuccess;
-    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err};
+    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err, nullptr, nullptr, 0, HubState{}};
+    if (f) {
+        a.L1 = f->L1;
+        a.changed = f->changed;
+        a.sw = f->sw;
+    }
     if (per_wave)
         relabel_wave_k<<<grid_for(cnt, 4, 8192), 256, 0, s>>>(a, rowflag, lo, cnt);
     else
@@ -434,10 +647,18 @@ hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uin
 }
 hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                               uint32_t *col2, uint32_t *w2, const HubItem *items, uint32_t count,
-                              uint32_t *hub_flags, uint32_t *err, hipStream_t s) {
+                              uint32_t *hub_flags, uint32_t *err, const Round1Fuse *f, const HubState *hs,
+                              uint32_t H, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err};
+    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err, nullptr, nullptr, 0, HubState{}};
+    if (f) {
+        a.L1 = f->L1;
+        a.changed = f->changed;
+        a.sw = f->sw;
+        a.hs = *hs;
+    }
     relabel_hub_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hub_flags);
+    if (f && H) hub_unfuse_k<<<grid_for(H, 256, 1024), 256, 0, s>>>(a.hs, H);
     return hipGetLastError();
 }
 

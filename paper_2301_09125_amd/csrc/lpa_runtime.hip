@@ -98,7 +98,7 @@ struct lpa_ctx {
     DevBuf old_of, new_of, rp2, col2, w2, rowflag, La, Lb;
     DevBuf counters;  // kCountWords u64 per round, then the error word
     DevBuf items, ritems, slab_off, slab_mask, touched_off, tcount, best, own_sum, hflags, rowsum, slab, touched;
-    DevBuf cand, thr, item_lo, mrows, slab_pending;
+    DevBuf cand, thr, item_lo, mrows, slab_pending, hub_tmp;
     DevBuf K, mod_sums, partials;
     DevBuf gid, gvd, bstate, bseg;  // batched run
     DevBuf f_top1, f_top2, f_kw, f_last, f_front, f_stale, f_lists, f_small, f_model;  // frontier runs
@@ -144,12 +144,6 @@ lpa_status err_status(uint32_t bits) {
     if (bits & ERR_TIMEOUT) return LPA_ETIMEDOUT;
     if (bits & ERR_WOVF) return LPA_EOVERFLOW;
     return LPA_OK;
-}
-
-uint64_t pow2_ceil(uint64_t x) {
-    uint64_t p = 1;
-    while (p < x) p <<= 1;
-    return p;
 }
 
 lpa_status check_options(const lpa_options &o) {
@@ -251,7 +245,11 @@ HubState hub_state(lpa_ctx *c) {
 
 // Bin the vertices, validate row_ptr, build the internal CSR and lay out the
 // long rows.  with_slab: also prepare the global slabs used by the vote.
-lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, bool with_slab) {
+// fuse: also run round 1 from the unique labels inside the relabel pass
+// (rows that list each neighbour once); La/fuse->L1 then get their initial
+// labels here.
+lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, bool with_slab,
+                   const Round1Fuse *fuse = nullptr, uint32_t *La = nullptr) {
     const hipStream_t s = c->stream;
     const Graph G{g->row_ptr, g->col, g->w, g->n, g->m};
     const uint32_t n = g->n;
@@ -291,71 +289,42 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
     }
     P.H = P.bins.cnt[BIN_HUB];
     P.n_items = P.n_ritems = 0;
-
-    // long rows: wavefront segments of kWaveArcs arcs, merge lists, slabs,
-    // touched lists
-    std::vector<HubItem> items;
-    std::vector<ReduceItem> ritems;
-    std::vector<uint64_t> soff, toff;
-    std::vector<uint32_t> smask, hflags, item_lo, mrows_w, mrows_b;
     uint64_t slab_total = 0, touched_total = 0;
-    if (P.H) {
-        std::vector<uint64_t> rows((size_t)P.H + 1);
-        HIP_TRY(hipMemcpyAsync(rows.data(), c->rp2.p, rows.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        for (uint32_t h = 0; h < P.H; ++h) {
-            const uint64_t b = rows[h], e = rows[h + 1], d = e - b;
-            item_lo.push_back((uint32_t)items.size());
-            for (uint64_t x = b; x < e; x += kWaveArcs)
-                items.push_back(HubItem{h, 0, x, std::min<uint64_t>(e, x + kWaveArcs)});
-            const uint64_t nseg = (d + kWaveArcs - 1) / kWaveArcs;
-            uint32_t f = 0;
-            if (nseg > (uint64_t)o.merge_max)
-                f = HUB_BIG;
-            else if (nseg <= (uint64_t)kMergeWaveSegs)
-                mrows_w.push_back(h);
-            else
-                mrows_b.push_back(h);
-            hflags.push_back(f);
-            for (uint64_t t = 0; t < d; t += 2048)
-                ritems.push_back(ReduceItem{h, (uint32_t)t, (uint32_t)std::min<uint64_t>(d, t + 2048), 0});
-            const uint64_t slots = pow2_ceil(2 * d);
-            soff.push_back(slab_total);
-            smask.push_back((uint32_t)(slots - 1));
-            toff.push_back(touched_total);
-            slab_total += slots;
-            touched_total += d;
-        }
-        item_lo.push_back((uint32_t)items.size());
-        P.n_items = (uint32_t)items.size();
-        P.n_ritems = (uint32_t)ritems.size();
-        P.n_mwave = (uint32_t)mrows_w.size();
-        P.n_mblock = (uint32_t)mrows_b.size();
-        HIP_TRY(c->items.ensure(items.size() * sizeof(HubItem)));
-        HIP_TRY(hipMemcpyAsync(c->items.p, items.data(), items.size() * sizeof(HubItem), hipMemcpyHostToDevice, s));
-        HIP_TRY(c->hflags.ensure((size_t)P.H * sizeof(uint32_t)));
-        HIP_TRY(hipMemcpyAsync(c->hflags.p, hflags.data(), (size_t)P.H * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    }
 
-    // internal CSR
-    uint32_t *w2 = g->w ? c->w2.as<uint32_t>() : nullptr;
-    const Bins &B = P.bins;
-    HIP_TRY(launch_relabel_hub(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
-                               c->col2.as<uint32_t>(), w2, c->items.as<HubItem>(), P.n_items,
-                               c->hflags.as<uint32_t>(), err_dev, s));
-    HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
-                                c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_WIDE],
-                                B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE], 1, err_dev, s));
-    HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
-                                c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_GROUP],
-                                B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD], 0, err_dev, s));
+    // long rows: wavefront segments, merge lists, slab and touched-list
+    // offsets, planned on the device
+    if (P.H) {
+        const uint32_t H = P.H;
+        HIP_TRY(c->item_lo.ensure(((size_t)H + 1) * sizeof(uint32_t)));
+        HIP_TRY(c->slab_off.ensure(H * sizeof(uint64_t)));
+        HIP_TRY(c->touched_off.ensure(H * sizeof(uint64_t)));
+        HIP_TRY(c->slab_mask.ensure(H * sizeof(uint32_t)));
+        HIP_TRY(c->hflags.ensure(H * sizeof(uint32_t)));
+        HIP_TRY(c->hub_tmp.ensure(3 * (size_t)H * sizeof(uint32_t) + 64));
+        uint32_t *ritem_lo = c->hub_tmp.as<uint32_t>(), *mw_pos = ritem_lo + H, *mb_pos = mw_pos + H;
+        u64 *plan = reinterpret_cast<u64 *>(c->hub_tmp.as<char>() + ((3 * (size_t)H * 4 + 7) & ~(size_t)7));
+        HIP_TRY(launch_hub_plan(c->rp2.as<uint64_t>(), H, o.merge_max, c->item_lo.as<uint32_t>(),
+                                c->slab_off.as<uint64_t>(), c->touched_off.as<uint64_t>(), ritem_lo, mw_pos, mb_pos,
+                                plan, s));
+        HIP_TRY(hipMemcpyAsync(c->pinned, plan, 6 * sizeof(u64), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        P.n_items = (uint32_t)c->pinned[0];
+        P.n_ritems = (uint32_t)c->pinned[1];
+        slab_total = c->pinned[2];
+        touched_total = c->pinned[3];
+        P.n_mwave = (uint32_t)c->pinned[4];
+        P.n_mblock = (uint32_t)c->pinned[5];
+        HIP_TRY(c->items.ensure((size_t)P.n_items * sizeof(HubItem)));
+        HIP_TRY(c->ritems.ensure((size_t)P.n_ritems * sizeof(ReduceItem)));
+        HIP_TRY(c->mrows.ensure(((size_t)P.n_mwave + P.n_mblock) * sizeof(uint32_t)));
+        HIP_TRY(launch_hub_items(c->rp2.as<uint64_t>(), H, o.merge_max, c->item_lo.as<uint32_t>(), ritem_lo, mw_pos,
+                                 mb_pos, P.n_mwave, c->items.as<HubItem>(), c->ritems.as<ReduceItem>(),
+                                 c->hflags.as<uint32_t>(), c->slab_mask.as<uint32_t>(), c->mrows.as<uint32_t>(),
+                                 s));
+    }
 
     if (with_slab && P.H) {
         const uint32_t H = P.H;
-        HIP_TRY(c->ritems.ensure(ritems.size() * sizeof(ReduceItem)));
-        HIP_TRY(c->slab_off.ensure(H * sizeof(uint64_t)));
-        HIP_TRY(c->slab_mask.ensure(H * sizeof(uint32_t)));
-        HIP_TRY(c->touched_off.ensure(H * sizeof(uint64_t)));
         HIP_TRY(c->tcount.ensure(H * sizeof(uint32_t)));
         HIP_TRY(c->best.ensure(H * sizeof(u64)));
         HIP_TRY(c->own_sum.ensure(H * sizeof(u64)));
@@ -367,32 +336,32 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
             HIP_TRY(launch_fill_u64(c->slab.as<u64>(), 0xFFFFFFFF00000000ull, c->slab.bytes / sizeof(u64), s));
             c->slab_dirty = false;
         }
-        HIP_TRY(hipMemcpyAsync(c->ritems.p, ritems.data(), ritems.size() * sizeof(ReduceItem),
-                               hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(c->slab_off.p, soff.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(c->slab_mask.p, smask.data(), H * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(c->touched_off.p, toff.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
         HIP_TRY(c->slab_pending.ensure(sizeof(uint32_t)));
         HIP_TRY(launch_fill_u32(c->slab_pending.as<uint32_t>(), 0, 1, s));
         HIP_TRY(c->cand.ensure((size_t)P.n_items * kTopK * sizeof(u64)));
         HIP_TRY(c->thr.ensure((size_t)P.n_items * sizeof(uint32_t)));
-        HIP_TRY(c->item_lo.ensure(item_lo.size() * sizeof(uint32_t)));
-        HIP_TRY(c->mrows.ensure((mrows_w.size() + mrows_b.size()) * sizeof(uint32_t)));
-        HIP_TRY(hipMemcpyAsync(c->item_lo.p, item_lo.data(), item_lo.size() * sizeof(uint32_t),
-                               hipMemcpyHostToDevice, s));
-        if (!mrows_w.empty())
-            HIP_TRY(hipMemcpyAsync(c->mrows.p, mrows_w.data(), mrows_w.size() * sizeof(uint32_t),
-                                   hipMemcpyHostToDevice, s));
-        if (!mrows_b.empty())
-            HIP_TRY(hipMemcpyAsync(c->mrows.as<uint32_t>() + mrows_w.size(), mrows_b.data(),
-                                   mrows_b.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
         HIP_TRY(launch_fill_u32(c->tcount.as<uint32_t>(), 0, H, s));
         HIP_TRY(launch_fill_u64(c->best.as<u64>(), 0, H, s));
         HIP_TRY(launch_fill_u64(c->own_sum.as<u64>(), 0, H, s));
         HIP_TRY(launch_fill_u64(c->rowsum.as<u64>(), 0, H, s));
     }
-    // the host vectors must outlive the asynchronous copies
-    HIP_TRY(hipStreamSynchronize(s));
+
+    // internal CSR
+    uint32_t *w2 = g->w ? c->w2.as<uint32_t>() : nullptr;
+    const Bins &B = P.bins;
+    if (fuse) HIP_TRY(launch_init_labels(La, fuse->L1, c->old_of.as<uint32_t>(), nullptr, n, s));
+    const HubState hs = hub_state(c);
+    HIP_TRY(launch_relabel_hub(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
+                               c->col2.as<uint32_t>(), w2, c->items.as<HubItem>(), P.n_items,
+                               c->hflags.as<uint32_t>(), err_dev, (fuse && with_slab) ? fuse : nullptr, &hs, P.H,
+                               s));
+    HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
+                                c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_WIDE],
+                                B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE], 1, err_dev, fuse, s));
+    HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
+                                c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_GROUP],
+                                B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD], 0, err_dev, fuse, s));
+
     return LPA_OK;
 }
 
@@ -431,7 +400,8 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
     if (P.H) {
         const uint32_t *mrows = c->mrows.as<uint32_t>();
         LPA_TRY(timed(c, first ? K_HUB1 : K_HUB, bytes(BIN_HUB), B.arcs[BIN_HUB], [&] {
-            return launch_vote_hub(ra, c->items.as<HubItem>(), P.n_items, hs, first, c->num_cu * 5, s);
+            return launch_vote_hub(ra, c->items.as<HubItem>(), P.n_items, hs, first, ra.skip_distinct ? 1 : 0,
+                                   c->num_cu * 5, s);
         }));
         LPA_TRY(timed(c, K_MERGE, 0, 0, [&] {
             hipError_t e = launch_hub_merge(ra, hs, mrows, P.n_mwave, 0, first, s);
@@ -538,11 +508,16 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     if (resume) HIP_TRY(launch_check_labels(labels, n, err_dev, s));
 
     Plan P;
-    LPA_TRY(prepare(c, g, P, err_dev, true));
     HIP_TRY(c->La.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->Lb.ensure((size_t)n * sizeof(uint32_t)));
-    HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(),
-                               resume ? labels : nullptr, n, s));
+    // from the unique labels, round 1 of the rows that list each neighbour
+    // once is done while the internal CSR is built
+    const bool fused = !resume && max_iter > 0;
+    const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight};
+    LPA_TRY(prepare(c, g, P, err_dev, true, fused ? &fz : nullptr, c->La.as<uint32_t>()));
+    if (!fused)
+        HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(),
+                                   resume ? labels : nullptr, n, s));
 
     const uint64_t thr = (uint64_t)std::floor(tol * (double)n);
     const bool weighted = g->w != nullptr;
@@ -571,6 +546,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         ra.list_n = nullptr;
         ra.top1 = ra.top2 = nullptr;
         const int first = (t == 1 && !resume) ? 1 : 0;
+        ra.skip_distinct = (first && fused) ? 1 : 0;
         HIP_TRY(hipEventRecord(c->round_a, s));
         LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first));
         HIP_TRY(hipEventRecord(c->round_b, s));
@@ -778,6 +754,7 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         ra.err = err_dev;
         ra.list = nullptr;
         ra.list_n = nullptr;
+        ra.skip_distinct = 0;
         ra.top1 = c->f_top1.as<uint32_t>();
         ra.top2 = c->f_top2.as<uint32_t>();
         FrontArgs fa;
@@ -1583,7 +1560,7 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->items,      &c->ritems,   &c->slab_off, &c->slab_mask, &c->touched_off, &c->tcount,
                       &c->best,       &c->own_sum,  &c->hflags,   &c->rowsum,    &c->slab,        &c->touched,
                       &c->K,          &c->mod_sums, &c->partials, &c->cand,      &c->thr,         &c->item_lo,
-                      &c->mrows,      &c->slab_pending, &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
+                      &c->mrows,      &c->slab_pending, &c->hub_tmp, &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
                       &c->f_top1, &c->f_top2, &c->f_kw, &c->f_last, &c->f_front, &c->f_stale, &c->f_lists,
                       &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
                       &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist};

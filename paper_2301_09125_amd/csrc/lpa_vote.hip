@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
         const uint32_t vcur = vnext;
         if (i + stride < cnt) vnext = row_of(a, lo, i + stride);
         bool ch = false;
-        if (i < cnt) {
+        if (i < cnt && !(a.skip_distinct && (a.rowflag[vcur] & ROW_DISTINCT))) {
             const uint32_t v = vcur;
             const uint64_t b = a.g.rp[v];
             const uint64_t e = a.g.rp[v + 1];
@@ -140,9 +140,10 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
     }
     for (uint32_t base = blockIdx.x * GPB + wave * GPW; base < cnt; base += stride) {
         const uint32_t idx = base + lane / G;
-        const bool act = idx < cnt;
+        bool act = idx < cnt;
         const uint32_t v = act ? vnext : 0u;
         if (idx + stride < cnt) vnext = row_of(a, lo, idx + stride);
+        if (FIRST && act && a.skip_distinct && (a.rowflag[v] & ROW_DISTINCT)) act = false;
         uint64_t b = 0, e = 0;
         uint32_t own = 0;
         if (act) {
@@ -240,22 +241,37 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
     uint64_t b = 0, e = 0;
     uint32_t u[A], wt[A], valid = 0;
     uint32_t v = 0;
+    // round 1: rows the relabel pass already voted are skipped (no loads)
+    auto skipped = [&](uint32_t row) { return FIRST && a.skip_distinct && (a.rowflag[row] & ROW_DISTINCT); };
+    bool skip = false;
     if (i < cnt) {
         v = row_of(a, lo, i);
-        b = a.g.rp[v];
-        e = a.g.rp[v + 1];
-        issue_arcs<A, 64>(a, b + lane, e, u, wt, valid);
+        skip = skipped(v);
+        if (!skip) {
+            b = a.g.rp[v];
+            e = a.g.rp[v + 1];
+            issue_arcs<A, 64>(a, b + lane, e, u, wt, valid);
+        }
     }
     while (i < cnt) {
         const uint32_t inext = i + stride;
         uint64_t nb = 0, ne = 0;
         uint32_t nu[A], nwt[A], nvalid = 0, nv = 0;
+        bool nskip = false;
         if (inext < cnt) {
             nv = row_of(a, lo, inext);
-            nb = a.g.rp[nv];
-            ne = a.g.rp[nv + 1];
-            issue_arcs<A, 64>(a, nb + lane, ne, nu, nwt, nvalid);
+            nskip = skipped(nv);
+            if (!nskip) {
+                nb = a.g.rp[nv];
+                ne = a.g.rp[nv + 1];
+                issue_arcs<A, 64>(a, nb + lane, ne, nu, nwt, nvalid);
+            }
         }
+        if (nskip || inext >= cnt) {
+#pragma unroll
+            for (int j = 0; j < A; ++j) nu[j] = nwt[j] = 0;
+        }
+        if (!skip) {
         check_arcs<A>(a, u);
         const uint32_t own = a.L_old[v];
         uint32_t lab[A];
@@ -320,8 +336,10 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
             if (a.check && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
         }
         wave_sync();
+        }
         i = inext;
         v = nv;
+        skip = nskip;
         b = nb;
         e = ne;
         valid = nvalid;
@@ -798,11 +816,12 @@ __global__ __launch_bounds__(256) void hub_final_k(RoundArgs a, HubState hs, uin
 }
 
 hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
-                           int first, int grid_cap, hipStream_t s) {
+                           int first, int fused, int grid_cap, hipStream_t s) {
     if (count == 0) return hipSuccess;
     const unsigned g = grid_for(count, 4, grid_cap);
     if (first) {
-        vote_hub_direct_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hs);
+        // fused: the relabel pass already gathered the direct rows' partials
+        if (!fused) vote_hub_direct_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hs);
         vote_hub_k<true><<<g, 256, 0, s>>>(a, items, count, hs);
     } else {
         vote_hub_k<false><<<g, 256, 0, s>>>(a, items, count, hs);
