@@ -225,13 +225,12 @@ struct Round1Fuse {
 hipError_t launch_fill_u32_iota(uint32_t *a, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t count, hipStream_t s);
 hipError_t launch_degree_hist(const uint64_t *rp, uint32_t n, unsigned long long *hist, hipStream_t s);
-hipError_t launch_hub_plan(const uint64_t *rp2, uint32_t H, uint32_t merge_max, uint32_t *item_lo,
-                           uint64_t *slab_off, uint64_t *touched_off, uint32_t *ritem_lo, uint32_t *mw_pos,
-                           uint32_t *mb_pos, unsigned long long *out, hipStream_t s);
-hipError_t launch_hub_items(const uint64_t *rp2, uint32_t H, uint32_t merge_max, const uint32_t *item_lo,
-                            const uint32_t *ritem_lo, const uint32_t *mw_pos, const uint32_t *mb_pos,
-                            uint32_t n_mwave, HubItem *items, ReduceItem *ritems, uint32_t *hflags,
-                            uint32_t *slab_mask, uint32_t *mrows, hipStream_t s);
+hipError_t launch_hub_plan(const uint64_t *rp2, uint32_t H, uint32_t merge_max, unsigned long long *blk,
+                           unsigned long long *out, hipStream_t s);
+hipError_t launch_hub_fill(const uint64_t *rp2, uint32_t H, uint32_t merge_max, const unsigned long long *blk,
+                           const unsigned long long *out, uint32_t *item_lo, uint64_t *slab_off,
+                           uint64_t *touched_off, HubItem *items, ReduceItem *ritems, uint32_t *hflags,
+                           uint32_t *slab_mask, uint32_t *mrows, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t count, hipStream_t s);
 hipError_t launch_check_labels(const uint32_t *labels, uint32_t n, uint32_t *err, hipStream_t s);
 uint32_t bin_blocks(uint32_t n);

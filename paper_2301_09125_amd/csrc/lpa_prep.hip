@@ -333,89 +333,109 @@ __device__ __forceinline__ u64 block_scan_1024(u64 x, u64 *wtot, u64 &carry) {
     return res;
 }
 
-__global__ __launch_bounds__(1024) void hub_plan_k(const uint64_t *rp2, uint32_t H, uint32_t merge_max,
-                                                   uint32_t *item_lo, uint64_t *slab_off, uint64_t *touched_off,
-                                                   uint32_t *ritem_lo, uint32_t *mw_pos, uint32_t *mb_pos,
-                                                   u64 *out) {
+// Per long row h: arcs d, segments, slab slots, reduce items, merge class.
+struct HubRow {
+    u64 d, nseg, slots, red, mw, mb;
+};
+__device__ __forceinline__ HubRow hub_row(const uint64_t *rp2, uint32_t h, uint32_t merge_max) {
+    HubRow r;
+    r.d = rp2[h + 1] - rp2[h];
+    r.nseg = (r.d + kWaveArcs - 1) / kWaveArcs;
+    r.slots = 1;
+    while (r.slots < 2 * r.d) r.slots <<= 1;
+    r.red = (r.d + 2047) / 2048;
+    const bool big = r.nseg > merge_max;
+    r.mw = !big && r.nseg <= (u64)kMergeWaveSegs;
+    r.mb = !big && !r.mw;
+    return r;
+}
+
+// Block sums of the six per-row quantities (1024 rows per block).
+__global__ __launch_bounds__(1024) void hub_count_k(const uint64_t *rp2, uint32_t H, uint32_t merge_max,
+                                                    u64 *blk) {
+    __shared__ u64 wt[16][6];
+    const uint32_t h = blockIdx.x * 1024 + threadIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    HubRow r{0, 0, 0, 0, 0, 0};
+    if (h < H) r = hub_row(rp2, h, merge_max);
+    u64 x[6] = {r.nseg, r.slots, r.d, r.red, r.mw, r.mb};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        x[k] = wave_sum(x[k]);
+        if (lane == 0) wt[wave][k] = x[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        u64 s = 0;
+        for (int q = 0; q < 16; ++q) s += wt[q][threadIdx.x];
+        blk[(size_t)blockIdx.x * 6 + threadIdx.x] = s;
+    }
+}
+
+// Exclusive scan of the block sums (in place) and the totals.
+__global__ __launch_bounds__(1024) void hub_scan_k(u64 *blk, uint32_t nb, u64 *out) {
     __shared__ u64 wtot[16];
-    u64 c_items = 0, c_slab = 0, c_touch = 0, c_red = 0, c_mw = 0, c_mb = 0;
-    for (uint32_t base = 0; base < H; base += 1024) {
-        const uint32_t h = base + threadIdx.x;
-        u64 d = 0, nseg = 0, slots = 0, red = 0, mw = 0, mb = 0;
-        if (h < H) {
-            d = rp2[h + 1] - rp2[h];
-            nseg = (d + kWaveArcs - 1) / kWaveArcs;
-            slots = 1;
-            while (slots < 2 * d) slots <<= 1;
-            red = (d + 2047) / 2048;
-            const bool big = nseg > merge_max;
-            mw = !big && nseg <= (u64)kMergeWaveSegs;
-            mb = !big && !mw;
+    for (int k = 0; k < 6; ++k) {
+        u64 carry = 0;
+        for (uint32_t base = 0; base < nb; base += 1024) {
+            const uint32_t b = base + threadIdx.x;
+            const u64 x = b < nb ? blk[(size_t)b * 6 + k] : 0;
+            const u64 p = block_scan_1024(x, wtot, carry);
+            if (b < nb) blk[(size_t)b * 6 + k] = p;
         }
-        const u64 pi = block_scan_1024(nseg, wtot, c_items);
-        const u64 ps = block_scan_1024(slots, wtot, c_slab);
-        const u64 pt = block_scan_1024(d, wtot, c_touch);
-        const u64 pr = block_scan_1024(red, wtot, c_red);
-        const u64 pw = block_scan_1024(mw, wtot, c_mw);
-        const u64 pb = block_scan_1024(mb, wtot, c_mb);
-        if (h < H) {
-            item_lo[h] = (uint32_t)pi;
-            slab_off[h] = ps;
-            touched_off[h] = pt;
-            ritem_lo[h] = (uint32_t)pr;
-            mw_pos[h] = (uint32_t)pw;
-            mb_pos[h] = (uint32_t)pb;
-        }
-    }
-    if (threadIdx.x == 0) {
-        item_lo[H] = (uint32_t)c_items;
-        out[0] = c_items;
-        out[1] = c_red;
-        out[2] = c_slab;
-        out[3] = c_touch;
-        out[4] = c_mw;
-        out[5] = c_mb;
+        if (threadIdx.x == 0) out[k] = carry;
     }
 }
 
-__global__ void hub_items_k(const uint64_t *rp2, uint32_t H, uint32_t merge_max, const uint32_t *item_lo,
-                            const uint32_t *ritem_lo, const uint32_t *mw_pos, const uint32_t *mb_pos,
-                            uint32_t n_mwave, HubItem *items, ReduceItem *ritems, uint32_t *hflags,
-                            uint32_t *slab_mask, uint32_t *mrows) {
-    for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < H; h += gridDim.x * blockDim.x) {
-        const uint64_t b = rp2[h], e = rp2[h + 1], d = e - b;
-        const uint64_t nseg = (d + kWaveArcs - 1) / kWaveArcs;
-        uint64_t slots = 1;
-        while (slots < 2 * d) slots <<= 1;
-        const bool big = nseg > merge_max;
-        const bool mw = !big && nseg <= (uint64_t)kMergeWaveSegs;
-        hflags[h] = big ? HUB_BIG : 0u;
-        slab_mask[h] = (uint32_t)(slots - 1);
-        uint32_t k = item_lo[h];
-        for (uint64_t x = b; x < e; x += kWaveArcs) items[k++] = HubItem{h, 0, x, min(e, x + (uint64_t)kWaveArcs)};
-        uint32_t q = ritem_lo[h];
-        for (uint64_t t = 0; t < d; t += 2048) ritems[q++] = ReduceItem{h, (uint32_t)t, (uint32_t)min(d, t + 2048), 0};
-        if (mw)
-            mrows[mw_pos[h]] = h;
-        else if (!big)
-            mrows[n_mwave + mb_pos[h]] = h;
-    }
+// Offsets, segments, reduce items, flags, slab masks and merge lists of
+// every long row.
+__global__ __launch_bounds__(1024) void hub_fill_k(const uint64_t *rp2, uint32_t H, uint32_t merge_max,
+                                                   const u64 *blk, const u64 *tot, uint32_t *item_lo,
+                                                   uint64_t *slab_off, uint64_t *touched_off, HubItem *items,
+                                                   ReduceItem *ritems, uint32_t *hflags, uint32_t *slab_mask,
+                                                   uint32_t *mrows) {
+    __shared__ u64 wtot[16];
+    const uint32_t h = blockIdx.x * 1024 + threadIdx.x;
+    HubRow r{0, 0, 0, 0, 0, 0};
+    if (h < H) r = hub_row(rp2, h, merge_max);
+    u64 c0 = blk[(size_t)blockIdx.x * 6 + 0], c1 = blk[(size_t)blockIdx.x * 6 + 1], c2 = blk[(size_t)blockIdx.x * 6 + 2];
+    u64 c3 = blk[(size_t)blockIdx.x * 6 + 3], c4 = blk[(size_t)blockIdx.x * 6 + 4], c5 = blk[(size_t)blockIdx.x * 6 + 5];
+    const u64 pi = block_scan_1024(r.nseg, wtot, c0);
+    const u64 ps = block_scan_1024(r.slots, wtot, c1);
+    const u64 pt = block_scan_1024(r.d, wtot, c2);
+    const u64 pr = block_scan_1024(r.red, wtot, c3);
+    const u64 pw = block_scan_1024(r.mw, wtot, c4);
+    const u64 pb = block_scan_1024(r.mb, wtot, c5);
+    if (h >= H) return;
+    item_lo[h] = (uint32_t)pi;
+    if (h == H - 1) item_lo[H] = (uint32_t)tot[0];
+    slab_off[h] = ps;
+    touched_off[h] = pt;
+    hflags[h] = (!r.mw && !r.mb) ? HUB_BIG : 0u;
+    slab_mask[h] = (uint32_t)(r.slots - 1);
+    const uint64_t b = rp2[h], e = rp2[h + 1];
+    uint32_t k = (uint32_t)pi;
+    for (uint64_t x = b; x < e; x += kWaveArcs) items[k++] = HubItem{h, 0, x, min(e, x + (uint64_t)kWaveArcs)};
+    uint32_t q = (uint32_t)pr;
+    for (uint64_t t = 0; t < r.d; t += 2048) ritems[q++] = ReduceItem{h, (uint32_t)t, (uint32_t)min(r.d, t + 2048), 0};
+    if (r.mw)
+        mrows[pw] = h;
+    else if (r.mb)
+        mrows[tot[4] + pb] = h;
 }
 
-hipError_t launch_hub_plan(const uint64_t *rp2, uint32_t H, uint32_t merge_max, uint32_t *item_lo,
-                           uint64_t *slab_off, uint64_t *touched_off, uint32_t *ritem_lo, uint32_t *mw_pos,
-                           uint32_t *mb_pos, u64 *out, hipStream_t s) {
-    hub_plan_k<<<1, 1024, 0, s>>>(rp2, H, merge_max, item_lo, slab_off, touched_off, ritem_lo, mw_pos, mb_pos, out);
+hipError_t launch_hub_plan(const uint64_t *rp2, uint32_t H, uint32_t merge_max, u64 *blk, u64 *out, hipStream_t s) {
+    const uint32_t nb = (H + 1023) / 1024;
+    hub_count_k<<<nb, 1024, 0, s>>>(rp2, H, merge_max, blk);
+    hub_scan_k<<<1, 1024, 0, s>>>(blk, nb, out);
     return hipGetLastError();
 }
 
-hipError_t launch_hub_items(const uint64_t *rp2, uint32_t H, uint32_t merge_max, const uint32_t *item_lo,
-                            const uint32_t *ritem_lo, const uint32_t *mw_pos, const uint32_t *mb_pos,
-                            uint32_t n_mwave, HubItem *items, ReduceItem *ritems, uint32_t *hflags,
-                            uint32_t *slab_mask, uint32_t *mrows, hipStream_t s) {
+hipError_t launch_hub_fill(const uint64_t *rp2, uint32_t H, uint32_t merge_max, const u64 *blk, const u64 *out,
+                           uint32_t *item_lo, uint64_t *slab_off, uint64_t *touched_off, HubItem *items,
+                           ReduceItem *ritems, uint32_t *hflags, uint32_t *slab_mask, uint32_t *mrows, hipStream_t s) {
     if (H == 0) return hipSuccess;
-    hub_items_k<<<grid_for(H, 256, 4096), 256, 0, s>>>(rp2, H, merge_max, item_lo, ritem_lo, mw_pos, mb_pos,
-                                                         n_mwave, items, ritems, hflags, slab_mask, mrows);
+    hub_fill_k<<<(H + 1023) / 1024, 1024, 0, s>>>(rp2, H, merge_max, blk, out, item_lo, slab_off, touched_off, items,
+                                                   ritems, hflags, slab_mask, mrows);
     return hipGetLastError();
 }
 

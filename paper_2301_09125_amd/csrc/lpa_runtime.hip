@@ -295,32 +295,30 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
     // offsets, planned on the device
     if (P.H) {
         const uint32_t H = P.H;
+        const uint32_t nb = (H + 1023) / 1024;
         HIP_TRY(c->item_lo.ensure(((size_t)H + 1) * sizeof(uint32_t)));
         HIP_TRY(c->slab_off.ensure(H * sizeof(uint64_t)));
         HIP_TRY(c->touched_off.ensure(H * sizeof(uint64_t)));
         HIP_TRY(c->slab_mask.ensure(H * sizeof(uint32_t)));
         HIP_TRY(c->hflags.ensure(H * sizeof(uint32_t)));
-        HIP_TRY(c->hub_tmp.ensure(3 * (size_t)H * sizeof(uint32_t) + 64));
-        uint32_t *ritem_lo = c->hub_tmp.as<uint32_t>(), *mw_pos = ritem_lo + H, *mb_pos = mw_pos + H;
-        u64 *plan = reinterpret_cast<u64 *>(c->hub_tmp.as<char>() + ((3 * (size_t)H * 4 + 7) & ~(size_t)7));
-        HIP_TRY(launch_hub_plan(c->rp2.as<uint64_t>(), H, o.merge_max, c->item_lo.as<uint32_t>(),
-                                c->slab_off.as<uint64_t>(), c->touched_off.as<uint64_t>(), ritem_lo, mw_pos, mb_pos,
-                                plan, s));
+        HIP_TRY(c->hub_tmp.ensure(((size_t)nb * 6 + 8) * sizeof(u64)));
+        u64 *blk = c->hub_tmp.as<u64>(), *plan = blk + (size_t)nb * 6;
+        HIP_TRY(launch_hub_plan(c->rp2.as<uint64_t>(), H, o.merge_max, blk, plan, s));
         HIP_TRY(hipMemcpyAsync(c->pinned, plan, 6 * sizeof(u64), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         P.n_items = (uint32_t)c->pinned[0];
-        P.n_ritems = (uint32_t)c->pinned[1];
-        slab_total = c->pinned[2];
-        touched_total = c->pinned[3];
+        slab_total = c->pinned[1];
+        touched_total = c->pinned[2];
+        P.n_ritems = (uint32_t)c->pinned[3];
         P.n_mwave = (uint32_t)c->pinned[4];
         P.n_mblock = (uint32_t)c->pinned[5];
         HIP_TRY(c->items.ensure((size_t)P.n_items * sizeof(HubItem)));
         HIP_TRY(c->ritems.ensure((size_t)P.n_ritems * sizeof(ReduceItem)));
         HIP_TRY(c->mrows.ensure(((size_t)P.n_mwave + P.n_mblock) * sizeof(uint32_t)));
-        HIP_TRY(launch_hub_items(c->rp2.as<uint64_t>(), H, o.merge_max, c->item_lo.as<uint32_t>(), ritem_lo, mw_pos,
-                                 mb_pos, P.n_mwave, c->items.as<HubItem>(), c->ritems.as<ReduceItem>(),
-                                 c->hflags.as<uint32_t>(), c->slab_mask.as<uint32_t>(), c->mrows.as<uint32_t>(),
-                                 s));
+        HIP_TRY(launch_hub_fill(c->rp2.as<uint64_t>(), H, o.merge_max, blk, plan, c->item_lo.as<uint32_t>(),
+                                c->slab_off.as<uint64_t>(), c->touched_off.as<uint64_t>(), c->items.as<HubItem>(),
+                                c->ritems.as<ReduceItem>(), c->hflags.as<uint32_t>(), c->slab_mask.as<uint32_t>(),
+                                c->mrows.as<uint32_t>(), s));
     }
 
     if (with_slab && P.H) {
