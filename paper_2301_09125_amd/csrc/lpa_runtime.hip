@@ -62,11 +62,12 @@ enum KernelId {
     K_THREAD, K_GROUP, K_WAVE, K_WIDE, K_HUB, K_HUB1, K_MERGE, K_FALLBACK, K_REDUCE, K_FINAL, K_MOD,
     K_PREDICT, K_PUSH, K_LISTED, K_COUNT
 };
-// vote_hub_first: the long-row vote of round 1 from the unique labels;
+// vote_round1_rest: round-1 votes of the rows the relabel pass could not
+// decide (repeated neighbours), no algorithmic bytes counted;
 // predict / push: candidate selection and frontier stamps of frontier runs;
 // vote_listed: the short-row votes of a round driven by candidate lists
 const char *kKernelNames[K_COUNT] = {"vote_thread",  "vote_group", "vote_wave",    "vote_wide",
-                                     "vote_hub",     "vote_hub_first", "hub_merge", "hub_fallback",
+                                     "vote_hub",     "vote_round1_rest", "hub_merge", "hub_fallback",
                                      "hub_reduce",   "hub_final",  "modularity", "predict", "push",
                                      "vote_listed"};
 
@@ -373,7 +374,8 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
     const uint64_t ab = weighted ? 12 : 8;
     const Bins &B = P.bins;
     const int cap = c->num_cu * 8;
-    auto bytes = [&](int b) { return lists ? 0ull : ab * B.arcs[b] + 16ull * B.cnt[b]; };
+    const bool rest = ra.skip_distinct != 0;  // round 1 after the relabel pass voted the distinct rows
+    auto bytes = [&](int b) { return (lists || rest) ? 0ull : ab * B.arcs[b] + 16ull * B.cnt[b]; };
     auto args = [&](int b) {
         RoundArgs r = ra;
         if (lists) {
@@ -382,7 +384,7 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
         }
         return r;
     };
-    auto kid = [&](int k) { return lists ? (int)K_LISTED : k; };
+    auto kid = [&](int k) { return lists ? (int)K_LISTED : (rest ? (int)K_HUB1 : k); };
     LPA_TRY(timed(c, kid(K_THREAD), bytes(BIN_THREAD), B.arcs[BIN_THREAD], [&] {
         return launch_vote_thread(args(BIN_THREAD), B.lo[BIN_THREAD], B.cnt[BIN_THREAD], first, feat, cap, s);
     }));
@@ -397,7 +399,7 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
     }));
     if (P.H) {
         const uint32_t *mrows = c->mrows.as<uint32_t>();
-        LPA_TRY(timed(c, first ? K_HUB1 : K_HUB, bytes(BIN_HUB), B.arcs[BIN_HUB], [&] {
+        LPA_TRY(timed(c, (first && rest) ? K_HUB1 : K_HUB, bytes(BIN_HUB), B.arcs[BIN_HUB], [&] {
             return launch_vote_hub(ra, c->items.as<HubItem>(), P.n_items, hs, first, ra.skip_distinct ? 1 : 0,
                                    c->num_cu * 5, s);
         }));
