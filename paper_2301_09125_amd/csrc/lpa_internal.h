@@ -37,6 +37,14 @@ constexpr int kWaveArcsSmall = 128;  // wavefront rows with a small table
 constexpr int kWaveSlotsSmall = 256;
 constexpr int kWaveArcs = 512;       // arcs per wavefront work item
 constexpr int kWaveSlots = 1024;     // LDS slots per wavefront (<= 512 arcs)
+// LDS slots of a long-row segment's table.  A segment with more than
+// kHubSpill distinct labels would hand its row to the exact slab merge; with
+// 1024 slots and at most 512 arcs per segment that cannot happen, and a
+// smaller table (more wavefronts per CU) lost more to probing and to rows
+// sent to the slab than it won.
+constexpr int kHubSlots = 1024;
+constexpr uint32_t kHubSpill = 900;
+static_assert(kHubSpill + 64 < (uint32_t)kHubSlots, "a capped table must never fill up");
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kDegBuckets = 24;  // row-length histogram of the autotuner
 

@@ -489,36 +489,45 @@ __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *
         bool bad = false;
         u64 best = 0, own_w = 0, rs = 0;
         uint32_t own_hit = 0;
-        for (uint64_t k = src; k < e; k += 4) {
-            uint32_t u[4], wv[4];
+        // 8 arcs at a time, every load issued unconditionally (arcs past the
+        // row read the row's first arc and are masked) so the id lookups of
+        // a chunk are in flight together
+        for (uint64_t k = src; k < e; k += 8) {
+            uint32_t u[8], wv[8], mk = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                u[j] = 0;
-                wv[j] = 1;
-                if (k + j < e) {
-                    u[j] = a.g.col[k + j];
-                    if (a.g.w) wv[j] = a.g.w[k + j];
+            for (int j = 0; j < 8; ++j) {
+                const bool in = k + j < e;
+                mk |= (uint32_t)in << j;
+                const uint32_t x = a.g.col[in ? k + j : src];
+                u[j] = in ? x : 0u;
+            }
+            if (a.g.w) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint32_t x = a.g.w[(mk >> j & 1u) ? k + j : src];
+                    wv[j] = (mk >> j & 1u) ? x : 0u;
                 }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) wv[j] = mk >> j & 1u;
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 8; ++j) {
                 bad |= u[j] >= a.g.n;
+                if ((mk >> j & 1u) && k + j > src && !(prev < u[j])) distinct = 0;
+                if (mk >> j & 1u) prev = u[j];
                 u[j] = u[j] >= a.g.n ? 0u : u[j];
             }
+            uint32_t nid[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (k + j < e) {
-                    if (k + j > src && !(prev < u[j])) distinct = 0;
-                    prev = u[j];
-                    a.col2[dst + (k + j - src)] = a.new_of[u[j]];
+            for (int j = 0; j < 8; ++j) nid[j] = a.new_of[u[j]];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (mk >> j & 1u) {
+                    a.col2[dst + (k + j - src)] = nid[j];
                     if (a.w2) a.w2[dst + (k + j - src)] = wv[j];
                 }
-            if (a.L1) {
-                uint32_t m = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) m |= (k + j < e ? 1u : 0u) << j;
-                round1_keys<4>(u, wv, m, v, best, own_w, own_hit, rs);
-            }
+            if (a.L1) round1_keys<8>(u, wv, mk, v, best, own_w, own_hit, rs);
         }
         if (bad) atomicOr(a.err, ERR_COL);
         rowflag[r] = distinct ? ROW_DISTINCT : 0;
@@ -533,9 +542,12 @@ __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *
     if (a.L1) block_count(chg, a.changed);
 }
 
-// Copy arcs [b0, b0 + len) of internal row r (one wavefront, <= 512 arcs)
-// from the caller's row of old_of[r]; returns 1 if they are strictly
+// Copy arcs [b0, b0 + len) of internal row r (one wavefront, 1 <= len <= 512
+// arcs) from the caller's row of old_of[r]; returns 1 if they are strictly
 // increasing (also across the segment's first boundary inside the row).
+// Every load is issued by every lane (lanes past the segment read its first
+// arc and are masked), so the 8 id lookups per lane are in flight together
+// instead of one after the other.
 __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32_t r, uint64_t b0, uint64_t len,
                                                     u64 &best, u64 &own_w, uint32_t &own_hit, u64 &wsum) {
     constexpr int A = kWaveArcs / 64;
@@ -544,36 +556,55 @@ __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32
     const uint64_t rs = a.g.rp[v];
     const uint64_t off = b0 - a.rp2[r];  // offset of the segment inside the row
     const uint64_t src = rs + off;
-    uint32_t u[A], pv[A], wv[A];
-    uint32_t ok = 1;
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < A; ++j) {
-        const uint64_t k = lane + 64ull * j;
-        u[j] = 0;
-        pv[j] = 0;
-        wv[j] = 1;
-        if (k < len) {
-            u[j] = a.g.col[src + k];
-            if (src + k > rs) pv[j] = a.g.col[src + k - 1];
-            if (a.g.w) wv[j] = a.g.w[src + k];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < A; ++j) {
-        const uint64_t k = lane + 64ull * j;
-        if (k < len && src + k > rs && !(pv[j] < u[j])) ok = 0;
-        bad |= u[j] >= a.g.n;
-        u[j] = u[j] >= a.g.n ? 0u : u[j];
-    }
-    if (bad) atomicOr(a.err, ERR_COL);
+    uint32_t u[A], wv[A];
     uint32_t m = 0;
 #pragma unroll
     for (int j = 0; j < A; ++j) {
         const uint64_t k = lane + 64ull * j;
-        if (k < len) {
-            m |= 1u << j;
-            a.col2[b0 + k] = a.new_of[u[j]];
+        const bool in = k < len;
+        m |= (uint32_t)in << j;
+        const uint32_t x = a.g.col[src + (in ? k : 0)];
+        u[j] = in ? x : 0u;
+    }
+    if (a.g.w) {
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+            const uint64_t k = lane + 64ull * j;
+            const uint32_t x = a.g.w[src + ((m >> j & 1u) ? k : 0)];
+            wv[j] = (m >> j & 1u) ? x : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < A; ++j) wv[j] = m >> j & 1u;
+    }
+    // the arc before the segment (the row's previous segment), for the order test
+    const uint32_t before = a.g.col[src > rs ? src - 1 : src];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < A; ++j) bad |= (m >> j & 1u) && u[j] >= a.g.n;
+    if (bad) atomicOr(a.err, ERR_COL);
+    // strictly increasing: compare each arc with the one before it (the lane
+    // below, or lane 63 of the previous column, or the arc before the segment)
+    uint32_t ok = 1;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint32_t up = __shfl_up(u[j], 1, 64);
+        const uint32_t wrap = j ? __shfl(u[j ? j - 1 : 0], 63, 64) : before;
+        const uint32_t pv = lane ? up : wrap;
+        const uint64_t k = lane + 64ull * j;
+        const bool has_prev = k > 0 || src > rs;
+        if ((m >> j & 1u) && has_prev && !(pv < u[j])) ok = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) u[j] = u[j] >= a.g.n ? 0u : u[j];
+    uint32_t nid[A];
+#pragma unroll
+    for (int j = 0; j < A; ++j) nid[j] = a.new_of[u[j]];
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = lane + 64ull * j;
+        if (m >> j & 1u) {
+            a.col2[b0 + k] = nid[j];
             if (a.w2) a.w2[b0 + k] = wv[j];
         }
     }

@@ -422,30 +422,16 @@ hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int w
 //                  they claimed; hub_final_k picks the winner of every row
 //                  decided through best[] and resets the per-round state.
 
-// Report the kTopK heaviest entries of the S-slot table (clearing it) to
-// cand[it * kTopK ...] and the (kTopK+1)-th tally to thr[it].  Keys are
+// Report the kTopK heaviest entries of a segment's listed table (clearing
+// it) to cand[it * kTopK ...] and the (kTopK+1)-th tally to thr[it].  Keys are
 // unique (one slot per label), so round k takes the largest key below the
-// previous round's.
-__device__ __forceinline__ void report_topk(u64 *T, uint32_t S, const HubState &hs, uint32_t it) {
-    constexpr int J = kWaveSlots / 64;
+// previous round's.  J = key columns per lane in use.
+template <int J>
+__device__ __forceinline__ void select_topk(const u64 (&keys)[kWaveArcs / 64], u64 &mine, uint32_t &thr) {
     const uint32_t lane = threadIdx.x & 63;
-    u64 keys[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t s = lane + 64u * j;
-        keys[j] = 0;
-        if (s < S) {
-            const u64 x = T[s];
-            if (x != EMPTY_SLOT) {
-                keys[j] = slot_key(x);
-                T[s] = EMPTY_SLOT;
-            }
-        }
-    }
-    u64 mine = 0, prev = ~0ull;
-    uint32_t thr = 0;
+    u64 prev = ~0ull;
 #pragma unroll 1
-    for (int k = 0; k <= kTopK && S; ++k) {
+    for (int k = 0; k <= kTopK; ++k) {
         u64 lm = 0;
 #pragma unroll
         for (int j = 0; j < J; ++j)
@@ -459,6 +445,22 @@ __device__ __forceinline__ void report_topk(u64 *T, uint32_t S, const HubState &
         if (wm == 0) break;
         prev = wm;
     }
+}
+
+__device__ __forceinline__ void report_topk(ListedTable &t, const HubState &hs, uint32_t it) {
+    const uint32_t lane = threadIdx.x & 63;
+    u64 keys[kWaveArcs / 64];
+    const uint32_t J = listed_take(t, keys);
+    u64 mine = 0;
+    uint32_t thr = 0;
+    if (J == 1)
+        select_topk<1>(keys, mine, thr);
+    else if (J == 2)
+        select_topk<2>(keys, mine, thr);
+    else if (J != 0 && J <= 4)
+        select_topk<4>(keys, mine, thr);
+    else if (J != 0)
+        select_topk<kWaveArcs / 64>(keys, mine, thr);
     if (lane == 0) hs.thr[it] = thr;
     if (lane < (uint32_t)kTopK)
         hs.cand[(u64)it * kTopK + lane] = mine ? (((u64)(uint32_t)~(uint32_t)mine << 32) | (mine >> 32)) : EMPTY_SLOT;
@@ -502,62 +504,131 @@ __global__ __launch_bounds__(256) void vote_hub_direct_k(RoundArgs a, const HubI
 
 // Every other round (and round-1 rows with HUB_REPEATS): one LDS table per
 // wavefront and segment, reported as top-K, or merged into the slab for
-// HUB_BIG rows.  The next segment's arcs are loaded while the current one
-// is tallied.
-template <bool FIRST>
+// HUB_BIG rows.  A segment whose table would pass kHubSpill distinct labels
+// marks its row HUB_FALLBACK (the merge then skips the row and the slab pass
+// counts it exactly); HUB_BIG rows flush a full table and go on.  Three
+// segments are in flight per wavefront: the arcs of the one after next load
+// and the labels of the next one are gathered while the current one is
+// tallied.
+// Arc loads of one lane of a long-row segment: columns, and weights only
+// for weighted graphs (W); unit weights are the `valid` bits.
+template <int A, bool W>
+__device__ __forceinline__ void issue_hub_arcs(const RoundArgs &a, uint64_t k0, uint64_t e, uint32_t (&u)[A],
+                                               uint32_t (&wt)[W ? A : 1], uint32_t &valid) {
+    valid = 0;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = k0 + (uint64_t)j * 64;
+        const bool in = k < e;
+        valid |= (uint32_t)in << j;
+        const uint32_t x = a.g.col[in ? k : 0];  // branch-free, as issue_arcs
+        u[j] = in ? x : 0u;
+    }
+    if (W) {
+#pragma unroll
+        for (int j = 0; j < (W ? A : 1); ++j) {
+            const uint64_t k = k0 + (uint64_t)j * 64;
+            const uint32_t x = a.g.w[(valid >> j & 1u) ? k : 0];
+            wt[j] = (valid >> j & 1u) ? x : 0u;
+        }
+    } else {
+        wt[0] = 0;
+    }
+}
+
+template <bool FIRST, bool W>
 __global__ __launch_bounds__(256) void vote_hub_k(RoundArgs a, const HubItem *__restrict__ items, uint32_t count,
                                                   HubState hs) {
     constexpr int A = kWaveArcs / 64;
-    __shared__ u64 table[4 * kWaveSlots];
+    __shared__ u64 table[4 * kHubSlots];
+    __shared__ uint16_t lists[4 * kHubSlots];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    u64 *T = table + wave * kWaveSlots;
-    for (uint32_t s = lane; s < kWaveSlots; s += 64) T[s] = EMPTY_SLOT;
+    ListedTable t{table + wave * kHubSlots, lists + wave * kHubSlots, 0, 0};
+    for (uint32_t s = lane; s < (uint32_t)kHubSlots; s += 64) t.T[s] = EMPTY_SLOT;
     wave_sync();
     const uint32_t stride = gridDim.x * 4;
-    uint32_t it = blockIdx.x * 4 + wave;
-    HubItem item{0, 0, 0, 0};
-    uint32_t u[A], wt[A], valid = 0;
-    if (it < count) {
-        item = items[it];
-        issue_arcs<A, 64>(a, item.b0 + lane, item.b1, u, wt, valid);
-    }
-    while (it < count) {
-        const uint32_t nit = it + stride;
-        HubItem nitem{0, 0, 0, 0};
-        uint32_t nu[A], nwt[A], nvalid = 0;
-        if (nit < count) {
-            nitem = items[nit];
-            issue_arcs<A, 64>(a, nitem.b0 + lane, nitem.b1, nu, nwt, nvalid);
+    // stage 0: the current segment (labels in flight); stage 1: the next
+    // segment (arcs in flight)
+    // Every stage issues its loads unconditionally (an item past the end or
+    // skipped in round 1 is an empty segment of row 0), so the compiler can
+    // wait for exactly the stage it needs.
+    // The row's flags travel in the item's spare word, read when the item is
+    // fetched, so no load of the current stage is issued behind the others.
+    auto fetch = [&](uint32_t k, bool &act_k) {
+        HubItem x{0, 0, 0, 0};
+        act_k = false;
+        if (k < count) {
+            x = items[k];
+            x.pad = hs.flags[x.r];
+            act_k = !FIRST || (x.pad & HUB_REPEATS);
+            if (!act_k) x = HubItem{0, 0, 0, 0};
         }
-        const uint32_t h = item.r;
-        const uint32_t flags = hs.flags[h];
-        if (!FIRST || (flags & HUB_REPEATS)) {
-            check_arcs<A>(a, u);
-            const uint32_t own = a.L_old[h];
-            uint32_t lab[A];
-            gather_labels<A>(a, u, valid, lab);
+        return x;
+    };
+    uint32_t it = blockIdx.x * 4 + wave;
+    bool act, nact;
+    HubItem item = fetch(it, act), nitem = fetch(it + stride, nact);
+    uint32_t lab[A], wt[W ? A : 1], valid = 0, own = 0;
+    uint32_t nu[A], nwt[W ? A : 1], nvalid = 0;
+    issue_hub_arcs<A, W>(a, item.b0 + lane, item.b1, lab, wt, valid);
+    check_arcs<A>(a, lab);
+    gather_labels<A>(a, lab, valid, lab);
+    own = a.L_old[item.r];
+    issue_hub_arcs<A, W>(a, nitem.b0 + lane, nitem.b1, nu, nwt, nvalid);
+    while (it < count) {
+        // stage 2: arcs of the segment after next
+        bool act2;
+        const HubItem item2 = fetch(it + 2 * stride, act2);
+        uint32_t u2[A], wt2[W ? A : 1], valid2 = 0;
+        issue_hub_arcs<A, W>(a, item2.b0 + lane, item2.b1, u2, wt2, valid2);
+        // stage 1 -> labels of the next segment
+        check_arcs<A>(a, nu);
+        gather_labels<A>(a, nu, nvalid, nu);
+        const uint32_t nown = a.L_old[nitem.r];
+        if (act) {
+            const uint32_t h = item.r;
+            const uint32_t flags = item.pad;
+            uint32_t w[A];
+#pragma unroll
+            for (int j = 0; j < A; ++j) w[j] = W ? wt[j < (W ? A : 1) ? j : 0] : (valid >> j & 1u);
             u64 own_w = 0, rs = 0;
             uint32_t own_hit = 0, rem = 0;
-            split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
+            split_own<A>(lab, w, valid, own, own_w, own_hit, rem, rs);
             uint32_t S = next_pow2(2u * (uint32_t)(item.b1 - item.b0));
-            S = S < 64u ? 64u : (S > (uint32_t)kWaveSlots ? (uint32_t)kWaveSlots : S);
-            const uint32_t mask = S - 1;
-            const bool any = __ballot(rem != 0) != 0;
-            if (any) {
-                if (!FIRST) wave_peel<A, 2>(T, mask, lab, wt, rem);
-#pragma unroll
-                for (int j = 0; j < A; ++j)
-                    if (rem >> j & 1u) lds_insert(T, mask, lab[j], wt[j]);
-                wave_sync();
-            }
+            S = S < 64u ? 64u : (S > (uint32_t)kHubSlots ? (uint32_t)kHubSlots : S);
+            t.mask = S - 1;
             if (flags & HUB_BIG) {
-                if (any) {
-                    flush_to_slab(T, S, hs, h);
-                    if (lane == 0) atomicOr(hs.pending, 1u);
+                bool flushed = false;
+                rem = listed_tally<A, FIRST ? 0 : 2>(t, lab, w, rem, kHubSpill);
+                for (;;) {
+                    wave_sync();
+                    if (t.n) {
+                        flush_listed_to_slab(t, hs, h);
+                        flushed = true;
+                        wave_sync();
+                    }
+                    if (!__ballot(rem != 0)) break;
+                    rem = listed_tally<A, 0>(t, lab, w, rem, kHubSpill);
                 }
+                if (lane == 0 && flushed) atomicOr(hs.pending, 1u);
             } else {
-                report_topk(T, any ? S : 0, hs, it);
+                const bool any = __ballot(rem != 0) != 0;
+                bool spilled = false;
+                if (any) {
+                    rem = listed_tally<A, FIRST ? 0 : 2>(t, lab, w, rem, kHubSpill);
+                    spilled = __ballot(rem != 0) != 0;
+                    wave_sync();
+                }
+                if (spilled) {
+                    listed_clear(t);
+                    if (lane == 0) {
+                        atomicOr(&hs.flags[h], HUB_FALLBACK);
+                        atomicOr(hs.pending, 1u);
+                    }
+                } else {
+                    report_topk(t, hs, it);
+                }
             }
             own_w = wave_sum(own_w);
             own_hit = __ballot(own_hit != 0) != 0;
@@ -569,13 +640,23 @@ __global__ __launch_bounds__(256) void vote_hub_k(RoundArgs a, const HubItem *__
             }
             wave_sync();
         }
-        it = nit;
+        it += stride;
         item = nitem;
+        act = nact;
+        own = nown;
         valid = nvalid;
+        nitem = item2;
+        nact = act2;
+        nvalid = valid2;
 #pragma unroll
         for (int j = 0; j < A; ++j) {
-            u[j] = nu[j];
+            lab[j] = nu[j];
+            nu[j] = u2[j];
+        }
+#pragma unroll
+        for (int j = 0; j < (W ? A : 1); ++j) {
             wt[j] = nwt[j];
+            nwt[j] = wt2[j];
         }
     }
 }
@@ -587,10 +668,11 @@ __global__ __launch_bounds__(256) void hub_fallback_k(RoundArgs a, const HubItem
     if (!*hs.pending) return;  // no row fell back this round
     constexpr int A = kWaveArcs / 64;
     __shared__ u64 table[4 * kWaveSlots];
+    __shared__ uint16_t lists[4 * kWaveArcs];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    u64 *T = table + wave * kWaveSlots;
-    for (uint32_t s = lane; s < kWaveSlots; s += 64) T[s] = EMPTY_SLOT;
+    ListedTable t{table + wave * kWaveSlots, lists + wave * kWaveArcs, 0, 0};
+    for (uint32_t s = lane; s < kWaveSlots; s += 64) t.T[s] = EMPTY_SLOT;
     wave_sync();
     for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
         const HubItem item = items[it];
@@ -606,13 +688,10 @@ __global__ __launch_bounds__(256) void hub_fallback_k(RoundArgs a, const HubItem
         split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
         uint32_t S = next_pow2(2u * (uint32_t)(item.b1 - item.b0));
         S = S < 64u ? 64u : (S > (uint32_t)kWaveSlots ? (uint32_t)kWaveSlots : S);
-        const uint32_t mask = S - 1;
-        wave_peel<A, 2>(T, mask, lab, wt, rem);
-#pragma unroll
-        for (int j = 0; j < A; ++j)
-            if (rem >> j & 1u) lds_insert(T, mask, lab[j], wt[j]);
+        t.mask = S - 1;
+        listed_tally<A, 2>(t, lab, wt, rem);
         wave_sync();
-        flush_to_slab(T, S, hs, h);
+        flush_listed_to_slab(t, hs, h);
         wave_sync();
     }
 }
@@ -652,6 +731,7 @@ __global__ __launch_bounds__(256) void hub_merge_wave_k(RoundArgs a, HubState hs
         const uint32_t h = rows[i];
         const uint32_t flags = hs.flags[h];
         if (first && !(flags & HUB_REPEATS)) continue;  // decided through best[]
+        if (flags & HUB_FALLBACK) continue;              // a segment spilled: slab pass
         const uint32_t lo = hs.item_lo[h], ns = hs.item_lo[h + 1] - lo;
         const u64 T = wave_sum((u64)(lane < ns ? hs.thr[lo + lane] : 0u));
         for (uint32_t e = lane; e < ns * kTopK; e += 64) {
@@ -710,6 +790,7 @@ __global__ __launch_bounds__(256) void hub_merge_block_k(RoundArgs a, HubState h
         const uint32_t h = rows[i];
         const uint32_t flags = hs.flags[h];
         if (first && !(flags & HUB_REPEATS)) continue;  // uniform over the block
+        if (flags & HUB_FALLBACK) continue;              // a segment spilled: slab pass
         const uint32_t lo = hs.item_lo[h], ns = hs.item_lo[h + 1] - lo;
         u64 T = 0, z1 = 0, z2 = 0;
         uint32_t zo = 0;
@@ -822,9 +903,15 @@ hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t co
     if (first) {
         // fused: the relabel pass already gathered the direct rows' partials
         if (!fused) vote_hub_direct_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hs);
-        vote_hub_k<true><<<g, 256, 0, s>>>(a, items, count, hs);
+        if (a.g.w)
+            vote_hub_k<true, true><<<g, 256, 0, s>>>(a, items, count, hs);
+        else
+            vote_hub_k<true, false><<<g, 256, 0, s>>>(a, items, count, hs);
     } else {
-        vote_hub_k<false><<<g, 256, 0, s>>>(a, items, count, hs);
+        if (a.g.w)
+            vote_hub_k<false, true><<<g, 256, 0, s>>>(a, items, count, hs);
+        else
+            vote_hub_k<false, false><<<g, 256, 0, s>>>(a, items, count, hs);
     }
     return hipGetLastError();
 }

@@ -33,7 +33,11 @@ __device__ __forceinline__ void top2_xor(u64 &k1, u64 &k2, int off) {
 // Issue the loads of arcs k0 + j*STRIDE (j < A, below e) of one lane:
 // internal ids into u, weights into wt, bit j of `valid` set for loaded
 // arcs.  Nothing here waits for the data, so the loads of the next work item
-// can be in flight while the current one is processed.
+// can be in flight while the current one is processed.  Every lane issues
+// every load (arcs past the row read arc 0, which exists whenever a vote
+// kernel runs, and are masked through `valid`): loads behind per-lane
+// branches leave the compiler unable to count the loads in flight, and it
+// then waits for all of them, prefetches included.
 template <int A, int STRIDE>
 __device__ __forceinline__ void issue_arcs(const RoundArgs &a, uint64_t k0, uint64_t e, uint32_t (&u)[A],
                                            uint32_t (&wt)[A], uint32_t &valid) {
@@ -43,15 +47,18 @@ __device__ __forceinline__ void issue_arcs(const RoundArgs &a, uint64_t k0, uint
 #pragma unroll
     for (int j = 0; j < A; ++j) {
         const uint64_t k = k0 + (uint64_t)j * STRIDE;
-        u[j] = 0;
-        if (k < e) {
-            valid |= 1u << j;
-            u[j] = col[k];
-        }
+        const bool in = k < e;
+        valid |= (uint32_t)in << j;
+        const uint32_t x = col[in ? k : 0];
+        u[j] = in ? x : 0u;
     }
     if (w) {
 #pragma unroll
-        for (int j = 0; j < A; ++j) wt[j] = (valid >> j & 1u) ? w[k0 + (uint64_t)j * STRIDE] : 0u;
+        for (int j = 0; j < A; ++j) {
+            const uint64_t k = k0 + (uint64_t)j * STRIDE;
+            const uint32_t x = w[(valid >> j & 1u) ? k : 0];
+            wt[j] = (valid >> j & 1u) ? x : 0u;
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < A; ++j) wt[j] = (valid >> j) & 1u;
@@ -83,7 +90,10 @@ __device__ __forceinline__ void gather_labels(const RoundArgs &a, const uint32_t
                                               uint32_t (&lab)[A]) {
     const uint32_t *__restrict__ L = a.L_old;
 #pragma unroll
-    for (int j = 0; j < A; ++j) lab[j] = (valid >> j & 1u) ? L[u[j]] : 0xFFFFFFFFu;
+    for (int j = 0; j < A; ++j) {
+        const uint32_t x = L[u[j]];  // u = 0 past the row: no branch (see issue_arcs)
+        lab[j] = (valid >> j & 1u) ? x : 0xFFFFFFFFu;
+    }
 }
 
 // Split loaded arcs into the own-label tally and the bit set `rem` of arcs
@@ -134,6 +144,113 @@ __device__ __forceinline__ void wave_peel(u64 *T, uint32_t mask, const uint32_t 
     }
 }
 
+// Number of lanes below this one whose bit is set in m.
+__device__ __forceinline__ uint32_t lanes_below(u64 m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// A wavefront's LDS hashtable together with the list of the slots it has
+// claimed, in claim order, so that reading and clearing the table costs the
+// number of distinct labels in it instead of its number of slots.  `n` holds
+// the same value in every lane.
+struct ListedTable {
+    u64 *T;
+    uint16_t *lst;
+    uint32_t mask;
+    uint32_t n;
+};
+
+// Insert (lab, wv) for every lane whose `go` is set.  All 64 lanes call this
+// together: the probe loop runs until no lane has a pair left, so the claim
+// count advances in step in every lane.  The caller guarantees more slots
+// than distinct labels.
+__device__ __forceinline__ void listed_insert(ListedTable &t, bool go, uint32_t lab, uint32_t wv) {
+    uint32_t h = hmix(lab) & t.mask;
+    const u64 desired = ((u64)lab << 32) | wv;
+    while (__ballot(go)) {
+        bool claimed = false;
+        if (go) {
+            const u64 prev = atomicCAS(&t.T[h], EMPTY_SLOT, desired);
+            if (prev == EMPTY_SLOT) {
+                claimed = true;
+                go = false;
+            } else if ((uint32_t)(prev >> 32) == lab) {
+                atomicAdd(&t.T[h], (u64)wv);
+                go = false;
+            } else {
+                h = (h + 1) & t.mask;
+            }
+        }
+        const u64 m = __ballot(claimed);
+        if (claimed) t.lst[t.n + lanes_below(m)] = (uint16_t)h;
+        t.n += (uint32_t)__popcll(m);
+    }
+}
+
+// wave_peel for a listed table, then the insertion of the arcs left, one
+// column j at a time, stopping once the table holds more than `cap` labels.
+// Returns the bits of `rem` not inserted (0 when everything went in).  Each
+// step claims at most 64 slots, so a table of at least cap + 65 slots never
+// fills up.
+template <int A, int NPEEL>
+__device__ __forceinline__ uint32_t listed_tally(ListedTable &t, const uint32_t (&lab)[A], const uint32_t (&wt)[A],
+                                                 uint32_t rem, uint32_t cap = 0xFFFFFFFFu) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < NPEEL; ++p) {
+        const u64 m = __ballot(rem != 0);
+        if (!m) return 0;
+        const int lead = __ffsll((long long)m) - 1;
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = A - 1; j >= 0; --j)
+            if (rem >> j & 1u) mine = lab[j];
+        const uint32_t L = __shfl(mine, lead, 64);
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < A; ++j)
+            if ((rem >> j & 1u) && lab[j] == L) {
+                s += wt[j];
+                rem &= ~(1u << j);
+            }
+        s = wave_sum(s);
+        listed_insert(t, (int)lane == lead, L, s);
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        if (t.n > cap) return rem;
+        listed_insert(t, rem >> j & 1u, lab[j], wt[j]);
+        rem &= ~(1u << j);
+    }
+    return rem;
+}
+
+// Clear the listed slots without reading them.
+__device__ __forceinline__ void listed_clear(ListedTable &t) {
+    for (uint32_t e = threadIdx.x & 63; e < t.n; e += 64) t.T[t.lst[e]] = EMPTY_SLOT;
+    t.n = 0;
+}
+
+// Read and clear the listed entries: entry lane + 64 j becomes keys[j] as a
+// vote key (0 where there is none).  Returns how many key columns are used.
+template <int J>
+__device__ __forceinline__ uint32_t listed_take(ListedTable &t, u64 (&keys)[J]) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t D = t.n;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        keys[j] = 0;
+        const uint32_t e = lane + 64u * j;
+        if (e < D) {
+            const uint32_t s = t.lst[e];
+            keys[j] = slot_key(t.T[s]);
+            t.T[s] = EMPTY_SLOT;
+        }
+    }
+    t.n = 0;
+    return (D + 63) >> 6;
+}
+
 // Merge (lab, cnt) into a row's global slab.  Returns the slot index if this
 // call claimed a new slot, else kNone.
 __device__ __forceinline__ uint32_t slab_insert(u64 *S, uint32_t mask, uint32_t lab, uint32_t cnt) {
@@ -182,6 +299,27 @@ __device__ __forceinline__ void flush_table(u64 *T, uint32_t S, u64 *slab, uint3
 
 __device__ __forceinline__ void flush_to_slab(u64 *T, uint32_t S, const HubState &hs, uint32_t h) {
     flush_table(T, S, hs.slab + hs.slab_off[h], hs.slab_mask[h], hs.touched + hs.touched_off[h], &hs.tcount[h]);
+}
+
+// flush_table for a listed table: only the claimed slots are visited.
+__device__ __forceinline__ void flush_listed(ListedTable &t, u64 *slab, uint32_t smask, uint32_t *touched,
+                                             uint32_t *tcount) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t D = t.n;
+    uint32_t tbase = 0;
+    if (lane == 0 && D) tbase = atomicAdd(tcount, D);
+    tbase = __shfl(tbase, 0, 64);
+    for (uint32_t e = lane; e < D; e += 64) {
+        const uint32_t s = t.lst[e];
+        const u64 x = t.T[s];
+        touched[tbase + e] = slab_insert(slab, smask, (uint32_t)(x >> 32), (uint32_t)x);
+        t.T[s] = EMPTY_SLOT;
+    }
+    t.n = 0;
+}
+
+__device__ __forceinline__ void flush_listed_to_slab(ListedTable &t, const HubState &hs, uint32_t h) {
+    flush_listed(t, hs.slab + hs.slab_off[h], hs.slab_mask[h], hs.touched + hs.touched_off[h], &hs.tcount[h]);
 }
 
 }  // namespace lpa
