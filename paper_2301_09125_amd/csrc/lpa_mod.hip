@@ -67,21 +67,33 @@ __device__ __forceinline__ void mod_finish(const ModArgs &a, ModTable &M, u64 tw
 }
 
 // Weighted degree and same-label weight of arcs k0 + j*STRIDE (j < A, < e).
+// Every lane issues every load (arcs past the row read arc k0 and are
+// masked), so the label gathers are in flight together: loads behind
+// per-lane branches are waited for one at a time.  k0 < e for lane 0.
 template <int A, int STRIDE>
 __device__ __forceinline__ void mod_arcs(const ModArgs &a, uint64_t k0, uint64_t e, uint32_t lv, u64 &kv,
                                          u64 &sin) {
     uint32_t u[A], wv[A];
     uint32_t valid = 0;
+    const uint64_t k_first = k0 - (threadIdx.x & 63) * (STRIDE == 1 ? 0 : 1);  // an arc of the row
 #pragma unroll
     for (int j = 0; j < A; ++j) {
         const uint64_t k = k0 + (uint64_t)j * STRIDE;
-        u[j] = 0;
-        wv[j] = 0;
-        if (k < e) {
-            valid |= 1u << j;
-            u[j] = a.g.col[k];
-            wv[j] = a.g.w ? a.g.w[k] : 1u;
+        const bool in = k < e;
+        valid |= (uint32_t)in << j;
+        const uint32_t x = a.g.col[in ? k : k_first];
+        u[j] = in ? x : 0u;
+    }
+    if (a.g.w) {
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+            const uint64_t k = k0 + (uint64_t)j * STRIDE;
+            const uint32_t x = a.g.w[(valid >> j & 1u) ? k : k_first];
+            wv[j] = (valid >> j & 1u) ? x : 0u;
         }
+    } else {
+#pragma unroll
+        for (int j = 0; j < A; ++j) wv[j] = valid >> j & 1u;
     }
     bool bad = false;
 #pragma unroll
@@ -90,12 +102,14 @@ __device__ __forceinline__ void mod_arcs(const ModArgs &a, uint64_t k0, uint64_t
         u[j] = u[j] >= a.g.n ? 0u : u[j];
     }
     if (bad) atomicOr(a.err, ERR_COL);
+    uint32_t lab[A];
 #pragma unroll
-    for (int j = 0; j < A; ++j)
-        if (valid >> j & 1u) {
-            kv += wv[j];
-            if (a.labels[u[j]] == lv) sin += wv[j];
-        }
+    for (int j = 0; j < A; ++j) lab[j] = a.labels[u[j]];
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        kv += wv[j];
+        if ((valid >> j & 1u) && lab[j] == lv) sin += wv[j];
+    }
 }
 
 // One lane per row (rows of at most 32 arcs).
