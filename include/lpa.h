@@ -89,7 +89,11 @@ typedef struct {
     uint32_t profile;      /* nonzero: time every kernel launch with HIP events */
     uint32_t modularity;   /* nonzero: lpa_run also reports the modularity of
                               its result in lpa_stats (same definition as
-                              lpa_modularity) */
+                              lpa_modularity).  After two or more rounds it is
+                              built from the last round's own-label weight
+                              sums plus the arcs of the vertices that changed
+                              in that round, which equals the full definition
+                              for the symmetric graphs this library requires */
     uint32_t frontier;     /* 0: lpa_run votes every vertex in every round;
                               1: from round 2 on it votes only the vertices
                               that can change -- those whose closed

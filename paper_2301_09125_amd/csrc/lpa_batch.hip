@@ -403,6 +403,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
         a.list_n = nullptr;
         a.top1 = a.top2 = nullptr;
         a.skip_distinct = 0;
+        a.insum = nullptr;
         const bool round1 = t == 1;
         for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin) run_bin<SLOTS>(b, a, T, bin, w, round1);
         if (!grid_barrier(b, nblocks)) return;

@@ -80,6 +80,34 @@ __device__ __forceinline__ void block_count(u64 c, u64 *slots) {
     }
 }
 
+// block_count for two counts into two sets of counter words (one barrier).
+__device__ __forceinline__ void block_count2(u64 c1, u64 *slots1, u64 c2, u64 *slots2) {
+    __shared__ u64 part[2][4];
+    c1 = wave_sum(c1);
+    c2 = wave_sum(c2);
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = c1;
+        part[1][threadIdx.x >> 6] = c2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const u64 s1 = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        const u64 s2 = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        const uint32_t w = (blockIdx.x % kCountSlots) * kCountStride;
+        if (s1) atomicAdd(&slots1[w], s1);
+        if (s2) atomicAdd(&slots2[w], s2);
+    }
+}
+
+// The changed count of a vote kernel and, when the round asks for it, its
+// own-label weight sum.  Every thread of a 256-thread block calls this once.
+__device__ __forceinline__ void block_counts(u64 chg, u64 ins, u64 *changed, u64 *insum) {
+    if (insum)
+        block_count2(chg, changed, ins, insum);
+    else
+        block_count(chg, changed);
+}
+
 // Block-wide reductions for 256 threads (4 wavefronts).
 struct BlockRed {
     u64 mx[4];

@@ -92,6 +92,10 @@ struct RoundArgs {
     const uint32_t *list_n;       // device count of list entries
     uint32_t *top1, *top2;        // vote kernels with FEAT: winning / runner-up tally per row
     uint32_t skip_distinct;       // round 1: rows flagged ROW_DISTINCT were voted by the relabel pass
+    // non-NULL: kCountWords counter words that receive the sum over the
+    // voted rows of the weight of arcs whose neighbour holds the row's own
+    // label (Sigma_in of L_old when every row is voted)
+    unsigned long long *insum;
 };
 
 // A wavefront work item of a long row: internal row r (= hub index), arcs
@@ -145,8 +149,12 @@ struct ModArgs {
     Graph g;                   // internal graph
     const uint32_t *labels;    // internal labels (values are original ids < n_orig)
     unsigned long long *K;     // n_orig, summed weighted degree per community
-    unsigned long long *sums;  // [0] = 2m, [1] = Sigma_in
+    unsigned long long *sums;  // [0] = 2m, [1] = Sigma_in (incremental: the change of Sigma_in, mod 2^64)
     uint32_t *err;
+    // incremental form: the labels of the round before the last one.  Only
+    // rows whose label changed in the last round read their arcs' labels
+    // (see launch_mod_rows).
+    const uint32_t *labels_prev;
 };
 
 // Batched run: state of the persistent kernel (lpa_batch.hip).  The bins

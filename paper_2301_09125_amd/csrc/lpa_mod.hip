@@ -6,6 +6,16 @@
 // u128 block partials added on the host; only the final expression is FP64.
 // K_c contributions are first merged per block in an LDS table so that a
 // large community costs one global atomic per block, not one per vertex.
+//
+// Incremental form (labels_prev set): the last round of a plain run already
+// summed, over every row, the weight of the arcs whose neighbour held the
+// row's own label, i.e. Sigma_in of the labels L' of the round before.  Only
+// arcs with an endpoint that changed label in the last round can change
+// their term, so the kernels below read the arcs of the changed rows only
+// and add, per such arc (v, u, w), w * ([L(v) = L(u)] - [L'(v) = L'(u)]),
+// once if u changed too and twice if it did not (the reverse arc (u, v) of
+// a symmetric graph carries the same term and is not visited).  K_c still
+// takes every vertex, and for unit weights its degree needs no arc at all.
 
 #include "lpa_device.h"
 
@@ -112,6 +122,130 @@ __device__ __forceinline__ void mod_arcs(const ModArgs &a, uint64_t k0, uint64_t
     }
 }
 
+// Incremental form: weighted degree of arcs k0 + j*STRIDE (j < A, < e) and,
+// for a changed row (lv = its label now, pv = before), the change of its
+// arcs' Sigma_in terms, added to d modulo 2^64.
+template <int A, int STRIDE>
+__device__ __forceinline__ void mod_delta_arcs(const ModArgs &a, uint64_t k0, uint64_t e, bool changed, uint32_t lv,
+                                               uint32_t pv, u64 &kv, u64 &d) {
+    uint32_t u[A], wv[A];
+    uint32_t valid = 0;
+    const uint64_t k_first = k0 - (threadIdx.x & 63) * (STRIDE == 1 ? 0 : 1);  // an arc of the row
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = k0 + (uint64_t)j * STRIDE;
+        valid |= (uint32_t)(k < e) << j;
+    }
+    if (a.g.w) {
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+            const uint64_t k = k0 + (uint64_t)j * STRIDE;
+            const uint32_t x = a.g.w[(valid >> j & 1u) ? k : k_first];
+            wv[j] = (valid >> j & 1u) ? x : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < A; ++j) wv[j] = valid >> j & 1u;
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) kv += wv[j];
+    if (!changed) return;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const uint64_t k = k0 + (uint64_t)j * STRIDE;
+        const uint32_t x = a.g.col[(valid >> j & 1u) ? k : k_first];
+        u[j] = (valid >> j & 1u) && x < a.g.n ? x : 0u;
+    }
+    uint32_t ln[A], lp[A];
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        ln[j] = a.labels[u[j]];
+        lp[j] = a.labels_prev[u[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const bool now = ln[j] == lv, before = lp[j] == pv;
+        if ((valid >> j & 1u) && now != before) {
+            const u64 t = (u64)wv[j] * (ln[j] != lp[j] ? 1u : 2u);
+            d += now ? t : (u64)0 - t;
+        }
+    }
+}
+
+// Incremental form, one lane per row (rows of at most 32 arcs).
+__global__ __launch_bounds__(256) void mod_delta_thread_k(ModArgs a, uint32_t lo, uint32_t cnt) {
+    __shared__ ModTable M;
+    mod_table_init(M);
+    u64 tw = 0, d = 0;
+    for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < cnt; base += gridDim.x * 256) {
+        const uint32_t i = base + (threadIdx.x & 63);
+        const bool act = i < cnt;
+        u64 kv = 0;
+        uint32_t lv = 0;
+        if (act) {
+            const uint32_t v = lo + i;
+            lv = a.labels[v];
+            const uint32_t pv = a.labels_prev[v];
+            const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
+            if (lv == pv && !a.g.w)
+                kv = e - b;  // unit weights, label kept: no arc to read
+            else
+                for (uint64_t k = b; k < e; k += 8) mod_delta_arcs<8, 1>(a, k, e, lv != pv, lv, pv, kv, d);
+        }
+        tw += kv;
+        add_community(M, a.K, act, lv, kv);
+    }
+    mod_finish(a, M, tw, d);
+}
+
+// Incremental form, one wavefront per row (rows of at most 512 arcs).
+__global__ __launch_bounds__(256) void mod_delta_wave_k(ModArgs a, uint32_t lo, uint32_t cnt) {
+    __shared__ ModTable M;
+    mod_table_init(M);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 tw = 0, d = 0;
+    for (uint32_t i = blockIdx.x * 4 + wave; i < cnt; i += gridDim.x * 4) {
+        const uint32_t v = lo + i;
+        const uint32_t lv = a.labels[v], pv = a.labels_prev[v];
+        const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
+        u64 kv = 0;
+        if (lv == pv && !a.g.w) {
+            kv = lane == 0 ? e - b : 0;  // uniform over the wavefront
+        } else {
+            mod_delta_arcs<kWaveArcs / 64, 64>(a, b + lane, e, lv != pv, lv, pv, kv, d);
+        }
+        kv = wave_sum(kv);
+        tw += lane == 0 ? kv : 0;
+        add_community(M, a.K, lane == 0, lv, kv);
+    }
+    mod_finish(a, M, tw, d);
+}
+
+// Incremental form, one wavefront per segment of a long row.
+__global__ __launch_bounds__(256) void mod_delta_hub_k(ModArgs a, const HubItem *__restrict__ items,
+                                                       uint32_t count) {
+    __shared__ ModTable M;
+    mod_table_init(M);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 tw = 0, d = 0;
+    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
+        const HubItem item = items[it];
+        const uint32_t lv = a.labels[item.r], pv = a.labels_prev[item.r];
+        u64 kv = 0;
+        if (lv == pv && !a.g.w) {
+            kv = lane == 0 ? item.b1 - item.b0 : 0;
+        } else {
+            mod_delta_arcs<kWaveArcs / 64, 64>(a, item.b0 + lane, item.b1, lv != pv, lv, pv, kv, d);
+        }
+        kv = wave_sum(kv);
+        tw += lane == 0 ? kv : 0;
+        add_community(M, a.K, lane == 0, lv, kv);
+    }
+    mod_finish(a, M, tw, d);
+}
+
 // One lane per row (rows of at most 32 arcs).
 __global__ __launch_bounds__(256) void mod_thread_k(ModArgs a, uint32_t lo, uint32_t cnt) {
     __shared__ ModTable M;
@@ -194,15 +328,24 @@ __global__ __launch_bounds__(256) void mod_sumsq_k(const u64 *__restrict__ K, ui
 
 hipError_t launch_mod_rows(const ModArgs &a, uint32_t lo, uint32_t cnt, int per_wave, hipStream_t s) {
     if (cnt == 0) return hipSuccess;
-    if (per_wave)
+    if (a.labels_prev) {
+        if (per_wave)
+            mod_delta_wave_k<<<grid_for(cnt, 4, 2048), 256, 0, s>>>(a, lo, cnt);
+        else
+            mod_delta_thread_k<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(a, lo, cnt);
+    } else if (per_wave) {
         mod_wave_k<<<grid_for(cnt, 4, 2048), 256, 0, s>>>(a, lo, cnt);
-    else
+    } else {
         mod_thread_k<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(a, lo, cnt);
+    }
     return hipGetLastError();
 }
 hipError_t launch_mod_hub(const ModArgs &a, const HubItem *items, uint32_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    mod_hub_k<<<grid_for(count, 4, 2048), 256, 0, s>>>(a, items, count);
+    if (a.labels_prev)
+        mod_delta_hub_k<<<grid_for(count, 4, 2048), 256, 0, s>>>(a, items, count);
+    else
+        mod_hub_k<<<grid_for(count, 4, 2048), 256, 0, s>>>(a, items, count);
     return hipGetLastError();
 }
 hipError_t launch_mod_sumsq(const u64 *K, uint32_t n, u64 *partials, uint32_t nparts, hipStream_t s) {

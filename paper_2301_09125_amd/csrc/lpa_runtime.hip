@@ -419,9 +419,13 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
     return LPA_OK;
 }
 
-// Modularity of the internal labels L on the internal graph.
+// Modularity of the internal labels L on the internal graph.  With L_prev
+// (the labels before the last round of a plain run, every row voted in it)
+// and insum (that round's own-label weight sum = Sigma_in of L_prev), only the
+// arcs of rows whose label changed in the last round are read.
 lpa_status modularity_internal(lpa_ctx *c, const lpa_csr *g, const Plan &P, const uint32_t *L, uint32_t *err_dev,
-                               double *q_out, uint64_t *terms) {
+                               double *q_out, uint64_t *terms, const uint32_t *L_prev = nullptr,
+                               u64 insum = 0) {
     const hipStream_t s = c->stream;
     const uint32_t n = g->n;
     const uint32_t nparts = 1024;
@@ -430,7 +434,7 @@ lpa_status modularity_internal(lpa_ctx *c, const lpa_csr *g, const Plan &P, cons
     HIP_TRY(c->partials.ensure(2 * nparts * sizeof(u64)));
     const Bins &B = P.bins;
     const uint64_t wb = g->w ? 12 : 8;
-    LPA_TRY(timed(c, K_MOD, wb * g->m + 28ull * n, g->m, [&]() -> hipError_t {
+    LPA_TRY(timed(c, K_MOD, L_prev ? 0ull : wb * g->m + 28ull * n, L_prev ? 0ull : g->m, [&]() -> hipError_t {
         hipError_t e = launch_fill_u64(c->K.as<u64>(), 0, n, s);
         if (e == hipSuccess) e = launch_fill_u64(c->mod_sums.as<u64>(), 0, 2, s);
         ModArgs ma;
@@ -439,6 +443,7 @@ lpa_status modularity_internal(lpa_ctx *c, const lpa_csr *g, const Plan &P, cons
         ma.K = c->K.as<u64>();
         ma.sums = c->mod_sums.as<u64>();
         ma.err = err_dev;
+        ma.labels_prev = L_prev;
         if (e == hipSuccess)
             e = launch_mod_rows(ma, B.lo[BIN_GROUP], B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD], 0, s);
         if (e == hipSuccess) e = launch_mod_rows(ma, B.lo[BIN_WIDE], B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE], 1, s);
@@ -458,7 +463,7 @@ lpa_status modularity_internal(lpa_ctx *c, const lpa_csr *g, const Plan &P, cons
     unsigned __int128 sk2 = 0;
     for (uint32_t i = 0; i < nparts; ++i)
         sk2 += ((unsigned __int128)parts[2 * i + 1] << 64) | (unsigned __int128)parts[2 * i];
-    const u64 two_m = sums[0], sigma_in = sums[1];
+    const u64 two_m = sums[0], sigma_in = L_prev ? insum + sums[1] : sums[1];  // mod 2^64: the change may be negative
     double q = 0.0;
     if (two_m > 0) {
         const double W = (double)two_m;
@@ -499,10 +504,15 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     clear_stats(stats);
     if (n == 0) return LPA_OK;
 
-    const size_t cwords = (size_t)max_iter * kCountWords + 1;
+    // per round: changed counter words, then (with modularity) own-label
+    // weight sums; one word of error bits after them
+    const bool want_insum = c->opt.modularity != 0;
+    const size_t rwords = (size_t)max_iter * kCountWords;
+    const size_t cwords = rwords * (want_insum ? 2 : 1) + 1;
     HIP_TRY(c->counters.ensure(cwords * sizeof(u64)));
     u64 *counters = c->counters.as<u64>();
-    uint32_t *err_dev = reinterpret_cast<uint32_t *>(counters + (size_t)max_iter * kCountWords);
+    u64 *insums = want_insum ? counters + rwords : nullptr;
+    uint32_t *err_dev = reinterpret_cast<uint32_t *>(counters + cwords - 1);
     HIP_TRY(launch_fill_u64(counters, 0, cwords, s));
     LPA_TRY(ensure_pinned(c, kCountWords + 16));
     if (resume) HIP_TRY(launch_check_labels(labels, n, err_dev, s));
@@ -547,6 +557,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         ra.top1 = ra.top2 = nullptr;
         const int first = (t == 1 && !resume) ? 1 : 0;
         ra.skip_distinct = (first && fused) ? 1 : 0;
+        ra.insum = insums ? insums + (size_t)(t - 1) * kCountWords : nullptr;
         HIP_TRY(hipEventRecord(c->round_a, s));
         LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first));
         HIP_TRY(hipEventRecord(c->round_b, s));
@@ -575,7 +586,20 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     HIP_TRY(launch_scatter_labels(labels, c->old_of.as<uint32_t>(), L_old, n, s));
     double q = 0;
     uint64_t terms[4] = {0, 0, 0, 0};
-    if (c->opt.modularity) LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms));
+    if (c->opt.modularity) {
+        if (it >= 2) {
+            // every row voted in round it (round 1 may have been voted by the
+            // relabel pass, which does not sum own-label weights)
+            HIP_TRY(hipMemcpyAsync(c->pinned + 16, insums + (size_t)(it - 1) * kCountWords,
+                                   kCountWords * sizeof(u64), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            u64 ins = 0;
+            for (int k = 0; k < kCountSlots; ++k) ins += c->pinned[16 + (size_t)k * kCountStride];
+            LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms, L_new, ins));
+        } else {
+            LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms));
+        }
+    }
     HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
@@ -755,6 +779,7 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         ra.list = nullptr;
         ra.list_n = nullptr;
         ra.skip_distinct = 0;
+        ra.insum = nullptr;
         ra.top1 = c->f_top1.as<uint32_t>();
         ra.top2 = c->f_top2.as<uint32_t>();
         FrontArgs fa;

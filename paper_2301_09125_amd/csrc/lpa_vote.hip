@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
     if (a.list) cnt = min(cnt, *a.list_n);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t stride = gridDim.x * 256;
-    u64 wchg = 0;
+    u64 wchg = 0, ins = 0;
     // row of this lane's next work item, loaded one iteration ahead
     uint32_t vnext = 0;
     {
@@ -74,6 +74,7 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
             for (int j = 0; j < D; ++j) {
                 rs += wt[j];
                 tl[j] = wt[j] + (lab[j] == own ? a.sw : 0u);
+                ins += (lab[j] == own) ? wt[j] : 0u;  // wt = 0 past the row
             }
 #pragma unroll
             for (int j = 0; j < D; ++j)
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
         }
         wchg += __popcll(__ballot(ch));
     }
-    block_count(lane == 0 ? wchg : 0, a.changed);
+    block_counts(lane == 0 ? wchg : 0, ins, a.changed, a.insum);
 }
 
 // ---------------------------------------------- group / wavefront per row --
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
     u64 *T = table + (threadIdx.x / G) * CAP;
     for (uint32_t s = gl; s < CAP; s += G) T[s] = EMPTY_SLOT;
     wave_sync();
-    u64 wchg = 0;
+    u64 wchg = 0, ins = 0;
     const uint32_t stride = gridDim.x * GPB;
     uint32_t vnext = 0;  // row of the group's next work item, loaded one iteration ahead
     {
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
         }
         bool ch = false;
         if (act && gl == 0) {
+            ins += own_w;
             if (own_hit || a.sw) {
                 if (FEAT)
                     top2_add(best, k2, vote_key(own, own_w + a.sw));
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
         wchg += __popcll(__ballot(ch));
         wave_sync();
     }
-    block_count(lane == 0 ? wchg : 0, a.changed);
+    block_counts(lane == 0 ? wchg : 0, ins, a.changed, a.insum);
 }
 
 // One wavefront per row of at most A*64 arcs, A arcs per lane, SLOTS LDS
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
     u64 *T = table + wave * SLOTS;
     for (uint32_t s = lane; s < (uint32_t)SLOTS; s += 64) T[s] = EMPTY_SLOT;
     wave_sync();
-    u64 wchg = 0;
+    u64 wchg = 0, ins = 0;
     const uint32_t stride = gridDim.x * 4;
     uint32_t i = blockIdx.x * 4 + wave;
     uint64_t b = 0, e = 0;
@@ -320,6 +322,7 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
         own_hit = __ballot(own_hit != 0) != 0;
         if (a.check) rs = wave_sum(rs);
         if (lane == 0) {
+            ins += own_w;
             if (own_hit || a.sw) {
                 if (FEAT)
                     top2_add(best, k2, vote_key(own, own_w + a.sw));
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
             wt[j] = nwt[j];
         }
     }
-    block_count(lane == 0 ? wchg : 0, a.changed);
+    block_counts(lane == 0 ? wchg : 0, ins, a.changed, a.insum);
 }
 
 hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int, int feat, int grid_cap,
@@ -868,12 +871,13 @@ __global__ __launch_bounds__(256) void hub_reduce_k(HubState hs, const ReduceIte
 // row's per-round state is reset.
 __global__ __launch_bounds__(256) void hub_final_k(RoundArgs a, HubState hs, uint32_t count, int first) {
     const uint32_t lane = threadIdx.x & 63;
-    u64 wchg = 0;
+    u64 wchg = 0, ins = 0;
     for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < count; base += gridDim.x * 256) {
         const uint32_t i = base + lane;
         bool ch = false;
         if (i < count) {
             const uint32_t f = hs.flags[i];
+            ins += hs.own_sum[i];
             const bool via_best = (first && !(f & HUB_REPEATS)) || (f & (HUB_BIG | HUB_FALLBACK));
             if (via_best) {
                 const uint32_t own = a.L_old[i];
@@ -893,7 +897,7 @@ __global__ __launch_bounds__(256) void hub_final_k(RoundArgs a, HubState hs, uin
         wchg += __popcll(__ballot(ch));
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *hs.pending = 0;
-    block_count(lane == 0 ? wchg : 0, a.changed);
+    block_counts(lane == 0 ? wchg : 0, ins, a.changed, a.insum);
 }
 
 hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,

@@ -248,15 +248,27 @@ def test_modularity_matches_oracle(gg, orc, lpa, ctx, case):
     assert q == ref.q  # same exact integers, same FP64 expression
 
 
-def test_run_reports_modularity(gg, orc, lpa):
-    for g in (gg.rmat(14, seed=6), gg.road(60, 70, seed=3)):
-        ref = orc.rak(g)
-        mref = orc.modularity(g, ref.labels)
-        with lpa.Context(0, modularity=1) as c:
-            lab, st = c.run(dev(lpa, g))
-        assert np.array_equal(lpa.labels_to_numpy(lab), ref.labels)
-        assert st.mod_terms == {"two_m": mref.two_m, "sigma_in": mref.sigma_in, "sum_k2": mref.sum_k2}
-        assert st.modularity == mref.q
+SMALL_BINS = {"thread_max": 2, "group_max": 6, "wave_max": 20, "wide_max": 40, "merge_max": 1}
+
+
+@pytest.mark.parametrize("opts", [{}, {"self_weight": 0}, SMALL_BINS], ids=["default", "sw0", "small_bins"])
+@pytest.mark.parametrize("max_iter,tol", [(1, 0.05), (2, 0.05), (3, 0.0), (20, 0.05), (30, 0.0)])
+def test_run_reports_modularity(gg, orc, lpa, opts, max_iter, tol):
+    # a run with modularity=1 reports Q of its result; after round 1 it is
+    # computed from the last round's own-label sums and the arcs of the rows
+    # that changed in it, which must give the full definition exactly
+    star = [(0, i) for i in range(1, 700)] + [(i, i + 1) for i in range(1, 699, 3)]
+    graphs = (gg.rmat(14, seed=6), gg.road(60, 70, seed=3),
+              gg.with_weights(gg.sbm(2000, 20, 0.05, 0.003, seed=5), 9, 1, 7), gg.from_edges(700, star))
+    sw = opts.get("self_weight", 1)
+    with lpa.Context(0, modularity=1, **opts) as c:
+        for g in graphs:
+            ref = orc.rak(g, tol=tol, max_iter=max_iter, self_weight=sw)
+            mref = orc.modularity(g, ref.labels)
+            lab, st = c.run(dev(lpa, g), tol=tol, max_iter=max_iter)
+            assert np.array_equal(lpa.labels_to_numpy(lab), ref.labels), g.name
+            assert st.mod_terms == {"two_m": mref.two_m, "sigma_in": mref.sigma_in, "sum_k2": mref.sum_k2}, g.name
+            assert st.modularity == mref.q
 
 
 # ---------------------------------------------------------- edge + errors --
