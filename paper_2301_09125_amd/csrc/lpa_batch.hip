@@ -71,10 +71,12 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs &b, uint32_t nblock
 template <int A>
 __device__ __forceinline__ void check_graph(const BatchArgs &b, const uint32_t (&u)[A], uint32_t valid,
                                             uint32_t g) {
+    uint32_t gj[A];
+#pragma unroll
+    for (int j = 0; j < A; ++j) gj[j] = b.gid[u[j]];  // u = 0 past the row: every lookup in flight at once
     bool bad = false;
 #pragma unroll
-    for (int j = 0; j < A; ++j)
-        if (valid >> j & 1u) bad |= b.gid[u[j]] != g;
+    for (int j = 0; j < A; ++j) bad |= (valid >> j & 1u) && gj[j] != g;
     if (bad) atomicOr(b.err, ERR_GRAPH);
 }
 
