@@ -249,9 +249,9 @@ typedef struct {
 /* RAK with the learned frontier.  Round 1 votes every vertex.  Each later
  * round votes the candidates the network keeps (and every vertex skipped in
  * the round before), until the round's changed count plus the predicted
- * changes of the rows it skipped is at most floor(tol * n); the next round
- * then votes every candidate (a full check, equivalent to voting every
- * vertex).  If the check passes the
+ * changes of the rows it skipped is at most floor(tol * n), or the network
+ * kept at least 4/5 of the candidates; the next round then votes every
+ * candidate (a full check, equivalent to voting every vertex).  If the check passes the
  * run has converged; otherwise rounds go on voting every candidate (plain
  * RAK) until the tolerance test passes or max_iter rounds have run.  Rows
  * longer than wide_max arcs are voted in every round.

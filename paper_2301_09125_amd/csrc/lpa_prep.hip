@@ -166,9 +166,22 @@ __global__ __launch_bounds__(1024) void bin_scan_k(uint32_t *blk_counts, u64 *bl
     for (int b = 0; b < NBINS; ++b) {
         s[b] = 0;
         as[b] = 0;
-        for (uint32_t i = lo; i < hi; ++i) {
-            s[b] += blk_counts[(size_t)b * nblk + i];
-            as[b] += blk_arcs[(size_t)b * nblk + i];
+        // 16 loads in flight at a time (a plain loop waits for each one)
+        for (uint32_t i0 = lo; i0 < hi; i0 += 16) {
+            uint32_t xs[16];
+            u64 ys[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t i = i0 + j < hi ? i0 + j : lo;
+                xs[j] = blk_counts[(size_t)b * nblk + i];
+                ys[j] = blk_arcs[(size_t)b * nblk + i];
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (i0 + j < hi) {
+                    s[b] += xs[j];
+                    as[b] += ys[j];
+                }
         }
         uint32_t x = s[b];
         u64 y = as[b];
@@ -205,13 +218,23 @@ __global__ __launch_bounds__(1024) void bin_scan_k(uint32_t *blk_counts, u64 *bl
         }
         uint32_t run = base + before + incl[b] - s[b];
         u64 arun = abase + abefore + aincl[b] - as[b];
-        for (uint32_t i = lo; i < hi; ++i) {
-            const uint32_t x = blk_counts[(size_t)b * nblk + i];
-            const u64 y = blk_arcs[(size_t)b * nblk + i];
-            blk_counts[(size_t)b * nblk + i] = run;
-            blk_arcs[(size_t)b * nblk + i] = arun;
-            run += x;
-            arun += y;
+        for (uint32_t i0 = lo; i0 < hi; i0 += 16) {
+            uint32_t xs[16];
+            u64 ys[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t i = i0 + j < hi ? i0 + j : lo;
+                xs[j] = blk_counts[(size_t)b * nblk + i];
+                ys[j] = blk_arcs[(size_t)b * nblk + i];
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (i0 + j < hi) {
+                    blk_counts[(size_t)b * nblk + i0 + j] = run;
+                    blk_arcs[(size_t)b * nblk + i0 + j] = arun;
+                    run += xs[j];
+                    arun += ys[j];
+                }
         }
         if (t == 0) {
             totals[b] = total;

@@ -710,11 +710,20 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
     HIP_TRY(launch_fill_u64(counters, 0, cwords, s));
     LPA_TRY(ensure_pinned(c, kCountWords + 32));
     Plan P;
-    LPA_TRY(prepare(c, g, P, err_dev, true));
-    const Bins &B = P.bins;
     HIP_TRY(c->La.ensure((size_t)n * 4));
     HIP_TRY(c->Lb.ensure((size_t)n * 4));
-    HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(), nullptr, n, s));
+    // round 1 of the rows that list each neighbour once is voted while the
+    // internal CSR is built, as in lpa_run; it leaves no top-two tallies,
+    // so round 2 votes every vertex (it changes nearly every label anyway)
+    // and the first prediction uses round 2's tallies.  Traces keep round 1
+    // in the vote kernels for the features of round 2.
+    const bool fused = R.mode != F_TRACE && max_iter > 0;
+    const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight};
+    LPA_TRY(prepare(c, g, P, err_dev, true, fused ? &fz : nullptr, c->La.as<uint32_t>()));
+    const Bins &B = P.bins;
+    if (!fused)
+        HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(), nullptr, n,
+                                   s));
     for (DevBuf *b : {&c->f_top1, &c->f_top2, &c->f_last, &c->f_front}) HIP_TRY(b->ensure((size_t)n * 4));
     HIP_TRY(c->f_stale.ensure(n));
     HIP_TRY(c->f_lists.ensure((size_t)n * 4));
@@ -778,7 +787,7 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         ra.err = err_dev;
         ra.list = nullptr;
         ra.list_n = nullptr;
-        ra.skip_distinct = 0;
+        ra.skip_distinct = (t == 1 && fused) ? 1 : 0;
         ra.insum = nullptr;
         ra.top1 = c->f_top1.as<uint32_t>();
         ra.top2 = c->f_top2.as<uint32_t>();
@@ -804,10 +813,10 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         fa.keep_all = phase != PH_LEARN;
         // full: every non-isolated row votes, no candidate lists (round 1,
         // traces, and rounds in which every row is a candidate anyway)
-        const bool full = t == 1 || R.mode == F_TRACE || (phase != PH_LEARN && all_dirty);
+        const bool full = t == 1 || (t == 2 && fused) || R.mode == F_TRACE || (phase != PH_LEARN && all_dirty);
         const bool learned_round = !full && phase == PH_LEARN;
         // the tallies feed the features of the next round's prediction
-        const int feat = R.mode == F_TRACE || (R.mode == F_LEARNED && phase == PH_LEARN);
+        const int feat = (R.mode == F_TRACE || (R.mode == F_LEARNED && phase == PH_LEARN)) && !(t == 1 && fused);
         uint64_t trace_base = R.tcount;
         HIP_TRY(hipEventRecord(c->round_a, s));
         if (full) {
@@ -890,8 +899,10 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         } else if (phase == PH_LEARN) {
             // the skipped rows would have changed with the predicted
             // probabilities: stop predicting once the expected full-round
-            // count passes the tolerance test
-            if (changed + expected_skipped <= thr) {
+            // count passes the tolerance test.  Stop too when the predictor
+            // kept nearly every candidate: the next round then votes the
+            // whole frontier anyway, so it might as well be the check.
+            if (changed + expected_skipped <= thr || (learned_round && 5 * voted >= 4 * cand)) {
                 phase = PH_CHECK;
                 R.check_round = t + 1;
             }

@@ -13,14 +13,14 @@ __device__ __forceinline__ uint32_t row_of(const RoundArgs &a, uint32_t lo, uint
     return a.list ? a.list[i] : lo + i;
 }
 
-// Two largest distinct vote keys seen so far (0 = none).
+// Two largest distinct vote keys seen so far (0 = none).  Selects only: a
+// branchy form gets the pair spilled to scratch memory and indexed.
 __device__ __forceinline__ void top2_add(u64 &k1, u64 &k2, u64 k) {
-    if (k > k1) {
-        k2 = k1;
-        k1 = k;
-    } else if (k < k1 && k > k2) {
-        k2 = k;
-    }
+    const bool above = k > k1;
+    const bool between = k < k1 && k > k2;
+    const u64 n2 = above ? k1 : (between ? k : k2);
+    k1 = above ? k : k1;
+    k2 = n2;
 }
 
 // Merge the top-two pairs of lanes that are `off` apart (xor pattern).
