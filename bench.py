@@ -90,6 +90,71 @@ def copy_calibration():
     log(f"[bench] copy calibration: 3 copies of {src.numel() * 4} bytes")
 
 
+def gather_ceiling(args, g, P):
+    """The rate of a vote's one random access, 4-byte gathers through a
+    streamed index (lpa_gather_rate), over (a) synthetic streams on tables of
+    4..256 MB, uniform and skewed (hot ids first, density ~ (id+1)^-0.8, as
+    the internal layout puts high-degree vertices first), and (b) the exact
+    label-gather streams of this workload's internal layout: every arc, and
+    the arcs of the long rows (the stream the dominant kernel reads)."""
+    import torch
+    ctx = P.Context(0)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    m = 1 << 28
+    rows = []
+    for mb in (4, 16, 64, 256):
+        n = mb * (1 << 20) // 4
+        table = torch.zeros(n, dtype=torch.int32, device="cuda")
+        for dist in ("uniform", "skewed"):
+            if dist == "uniform":
+                idx = torch.randint(0, n, (m,), device="cuda", generator=gen, dtype=torch.int64).to(torch.int32)
+            else:
+                r = torch.rand(m, device="cuda", generator=gen, dtype=torch.float64)
+                a = 0.2  # inverse CDF of a density ~ x^-0.8 on [1, n + 1]
+                idx = ((r * ((n + 1) ** a - 1) + 1) ** (1 / a) - 1).clamp(0, n - 1).to(torch.int32)
+            rate = ctx.gather_rate(idx, table)
+            rows.append((f"{mb} MB table, {dist}", m, rate))
+            log(f"[gather] {mb:4d} MB table {dist:8s}: {rate / 1e9:7.1f} G gathers/s")
+            del idx
+        del table
+    # the workload's own streams: internal ids in the library's layout (bins
+    # by degree, long rows first, original order inside a bin)
+    rp = torch.from_numpy(np.asarray(g.row_ptr, dtype=np.int64)).cuda()
+    col = torch.from_numpy(np.asarray(g.col, dtype=np.uint32).view(np.int32)).cuda()
+    n = g.n
+    deg = rp[1:] - rp[:-1]
+    o = P.default_options()
+    binno = torch.full((n,), 5, dtype=torch.int64, device="cuda")
+    for b, (lo, hi) in enumerate(((o["wide_max"] + 1, 1 << 62), (o["wave_max"] + 1, o["wide_max"]),
+                                  (o["group_max"] + 1, o["wave_max"]), (o["thread_max"] + 1, o["group_max"]),
+                                  (1, o["thread_max"]))):
+        binno[(deg >= lo) & (deg <= hi)] = b
+    order = torch.argsort(binno * n + torch.arange(n, device="cuda"))
+    new_of = torch.empty(n, dtype=torch.int32, device="cuda")
+    new_of[order] = torch.arange(n, dtype=torch.int32, device="cuda")
+    table = torch.zeros(n, dtype=torch.int32, device="cuda")
+    # every arc, rows in internal order
+    lens = deg[order]
+    starts = rp[:-1][order]
+    arc_pos = torch.repeat_interleave(starts - torch.cumsum(lens, 0) + lens, lens) + torch.arange(
+        int(lens.sum()), device="cuda")
+    stream = new_of[col[arc_pos].long()]
+    del arc_pos
+    rate = ctx.gather_rate(stream, table)
+    rows.append((f"{args.workload}: every arc", stream.numel(), rate))
+    log(f"[gather] {args.workload} every arc ({stream.numel()} gathers, {4 * n >> 20} MB labels): "
+        f"{rate / 1e9:7.1f} G gathers/s")
+    hub_arcs = int(lens[: int((binno == 0).sum())].sum())
+    hub = stream[:hub_arcs].contiguous()
+    rate_h = ctx.gather_rate(hub, table) if hub_arcs else 0.0
+    rows.append((f"{args.workload}: long rows", hub_arcs, rate_h))
+    log(f"[gather] {args.workload} long-row arcs ({hub_arcs} gathers): {rate_h / 1e9:7.1f} G gathers/s")
+    ctx.close()
+    print(json.dumps({"gather_ceiling": [{"stream": r[0], "gathers": r[1], "gathers_per_s": r[2]} for r in rows],
+                      "workload": args.workload}), flush=True)
+
+
 def traffic_from_profile(workload: str, kernel: str):
     """HBM bytes per launch of `kernel` measured with hardware counters for
     this workload, from the committed profile summary, or None when there is
@@ -325,12 +390,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for counter profiles)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    ap.add_argument("--gather-ceiling", action="store_true",
+                    help="measure the random-gather rate the vote kernels are bound by, then exit")
     ap.add_argument("--no-autotune", action="store_true", help="batch workloads: keep the default bins")
     ap.add_argument("--autotune", action="store_true", help="single-graph workloads: autotune the bins first")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
@@ -350,6 +417,8 @@ def main():
         log(f"[bench] generated {args.workload}: G={g.G} n={g.csr.n} m={g.csr.m} in {time.perf_counter() - t0:.1f}s")
         return run_batch_bench(args, g, desc, P)
     log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
+    if args.gather_ceiling:
+        return gather_ceiling(args, g, P)
     if args.workload.startswith("learned"):
         return run_learned_bench(args, g, desc, P)
     dg = P.DeviceGraph.from_csr(g, "cuda")

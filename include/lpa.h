@@ -316,6 +316,16 @@ lpa_status lpa_mlp_grad(lpa_ctx *ctx, const lpa_mlp *model, const float *X, cons
 lpa_status lpa_autotune(lpa_ctx *ctx, const lpa_csr *g, const uint64_t *graph_vptr, uint32_t G, uint32_t rounds,
                         lpa_options *chosen, uint32_t *measured);
 
+/* Calibration of the vote's roofline: the rate of the one access a vote
+ * makes per arc, a 4-byte gather whose address comes from a streamed index.
+ * Runs `reps` (>= 1) timed passes of table[idx[k]], k < m, on the context's
+ * stream (one untimed pass first) and returns gathers per second in
+ * *gathers_per_s (host).  idx: device u32[m]; table: device u32[table_n]
+ * (indices at or above table_n read the last entry).  Errors: LPA_EINVAL for
+ * NULL pointers, m = 0, table_n = 0 or reps = 0; LPA_EDEVICE. */
+lpa_status lpa_gather_rate(lpa_ctx *ctx, const uint32_t *idx, uint64_t m, const uint32_t *table,
+                           uint32_t table_n, uint32_t reps, double *gathers_per_s);
+
 /* Copy up to `cap` per-kernel profile records into out (host); *count gets
  * the number of records available.  lpa_profile_reset clears them. */
 lpa_status lpa_profile_get(lpa_ctx *ctx, lpa_kernel_prof *out, uint32_t cap, uint32_t *count);

@@ -1576,6 +1576,31 @@ lpa_status lpa_profile_get(lpa_ctx *c, lpa_kernel_prof *out, uint32_t cap, uint3
     return LPA_OK;
 }
 
+lpa_status lpa_gather_rate(lpa_ctx *c, const uint32_t *idx, uint64_t m, const uint32_t *table, uint32_t table_n,
+                           uint32_t reps, double *gathers_per_s) {
+    if (!c || !idx || !table || !gathers_per_s || m == 0 || reps == 0 || table_n == 0) return LPA_EINVAL;
+    HIP_TRY(hipSetDevice(c->device));
+    const hipStream_t s = c->stream;
+    const uint32_t grid = (uint32_t)std::max(1, c->num_cu) * 16;
+    HIP_TRY(c->hub_tmp.ensure((size_t)grid * 256 * sizeof(uint32_t)));
+    uint32_t *out = c->hub_tmp.as<uint32_t>();
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t e = launch_gather_probe(idx, m, table, table_n, out, grid, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_gather_probe(idx, m, table, table_n, out, grid, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(e);
+    *gathers_per_s = ms > 0.f ? (double)m * reps / ((double)ms * 1e-3) : 0.0;
+    return LPA_OK;
+}
+
 lpa_status lpa_profile_reset(lpa_ctx *c) {
     if (!c) return LPA_EINVAL;
     for (int k = 0; k < K_COUNT; ++k) {

@@ -113,7 +113,7 @@ class _KProf(ctypes.Structure):
 
 EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_run_batch", "lpa_run_learned",
            "lpa_trace", "lpa_train", "lpa_mlp_forward", "lpa_mlp_grad", "lpa_autotune", "lpa_modularity",
-           "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
+           "lpa_gather_rate", "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
 
 
 def _load():
@@ -143,6 +143,7 @@ def _load():
                                  ctypes.POINTER(u32)]
     lib.lpa_modularity.argtypes = [vp, ctypes.POINTER(_Csr), vp, ctypes.POINTER(dbl),
                                    ctypes.POINTER(ctypes.c_uint64)]
+    lib.lpa_gather_rate.argtypes = [vp, vp, u64, vp, u32, u32, ctypes.POINTER(dbl)]
     lib.lpa_profile_get.argtypes = [vp, ctypes.POINTER(_KProf), u32, ctypes.POINTER(u32)]
     lib.lpa_profile_reset.argtypes = [vp]
     lib.lpa_destroy.argtypes = [vp]
@@ -153,7 +154,7 @@ def _load():
               lib.lpa_autotune):
         f.restype = ctypes.c_int
     for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_run_batch, lib.lpa_modularity, lib.lpa_profile_get,
-              lib.lpa_profile_reset):
+              lib.lpa_profile_reset, lib.lpa_gather_rate):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -485,6 +486,20 @@ class Context:
             raise LpaError(rc, "lpa_profile_get")
         return [{"name": recs[i].name.decode(), "launches": recs[i].launches, "ms": recs[i].ms,
                  "bytes": recs[i].bytes, "arcs": recs[i].arcs} for i in range(min(cnt.value, 16))]
+
+    def gather_rate(self, idx, table, reps: int = 5) -> float:
+        """Gathers per second of table[idx[k]] (lpa_gather_rate); idx and
+        table are u32/int32 device tensors."""
+        import torch
+        for t, nm in ((idx, "idx"), (table, "table")):
+            if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+                raise ValueError(f"{nm}: a contiguous int32 device tensor is required")
+        out = ctypes.c_double(0.0)
+        rc = _load().lpa_gather_rate(self._h, idx.data_ptr(), idx.numel(), table.data_ptr(), table.numel(), reps,
+                                     ctypes.byref(out))
+        if rc:
+            raise LpaError(rc, "lpa_gather_rate")
+        return out.value
 
     def profile_reset(self):
         rc = _load().lpa_profile_reset(self._h)

@@ -329,3 +329,14 @@ def test_error_codes(gg, lpa, ctx):
     # the context still works after errors
     lab, st = ctx.run(ok, tol=0.0, max_iter=2)
     assert st.iterations >= 1
+
+
+def test_gather_rate_probe(lpa, ctx):
+    # the roofline calibration: a positive rate, indices clamped into the
+    # table, and argument errors reported as LPA_EINVAL
+    import torch
+    idx = torch.randint(0, 1 << 20, (1 << 20,), dtype=torch.int32, device="cuda")
+    table = torch.zeros(1 << 16, dtype=torch.int32, device="cuda")  # most indices past the end: clamped
+    assert ctx.gather_rate(idx, table, reps=2) > 0
+    with pytest.raises(lpa.LpaError):
+        ctx.gather_rate(idx[:0], table)
