@@ -703,9 +703,14 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
     const hipStream_t s = c->stream;
     const uint32_t n = g->n;
     if (n == 0) return LPA_OK;
-    const size_t cwords = (size_t)std::max<uint32_t>(max_iter, 1) * kCountWords + 1;
+    // per round: changed counter words, then (with modularity) own-label
+    // weight sums of the rounds that vote every row; the error word last
+    const bool want_insum = c->opt.modularity && labels;
+    const size_t rwords = (size_t)std::max<uint32_t>(max_iter, 1) * kCountWords;
+    const size_t cwords = rwords * (want_insum ? 2 : 1) + 1;
     HIP_TRY(c->counters.ensure(cwords * sizeof(u64)));
     u64 *counters = c->counters.as<u64>();
+    u64 *insums = want_insum ? counters + rwords : nullptr;
     uint32_t *err_dev = reinterpret_cast<uint32_t *>(counters + (cwords - 1));
     HIP_TRY(launch_fill_u64(counters, 0, cwords, s));
     LPA_TRY(ensure_pinned(c, kCountWords + 32));
@@ -774,6 +779,7 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
 
     uint32_t *L_old = c->La.as<uint32_t>(), *L_new = c->Lb.as<uint32_t>();
     int all_dirty = 1;
+    bool last_full = false;  // the last round voted every row (incremental modularity applies)
     enum { PH_LEARN, PH_CHECK, PH_PLAIN } phase = R.mode == F_LEARNED ? PH_LEARN : PH_PLAIN;
     for (uint32_t t = 1; t <= max_iter; ++t) {
         RoundArgs ra;
@@ -817,6 +823,8 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         const bool learned_round = !full && phase == PH_LEARN;
         // the tallies feed the features of the next round's prediction
         const int feat = (R.mode == F_TRACE || (R.mode == F_LEARNED && phase == PH_LEARN)) && !(t == 1 && fused);
+        ra.insum = (full && insums) ? insums + (size_t)(t - 1) * kCountWords : nullptr;
+        last_full = full;
         uint64_t trace_base = R.tcount;
         HIP_TRY(hipEventRecord(c->round_a, s));
         if (full) {
@@ -915,7 +923,18 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         }
     }
     if (labels) HIP_TRY(launch_scatter_labels(labels, c->old_of.as<uint32_t>(), L_old, n, s));
-    if (c->opt.modularity && labels) LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &R.q, R.terms));
+    if (want_insum) {
+        if (last_full && R.iterations >= 2) {
+            HIP_TRY(hipMemcpyAsync(c->pinned + 16, insums + (size_t)(R.iterations - 1) * kCountWords,
+                                   kCountWords * sizeof(u64), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            u64 ins = 0;
+            for (int k = 0; k < kCountSlots; ++k) ins += c->pinned[16 + (size_t)k * kCountStride];
+            LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &R.q, R.terms, L_new, ins));
+        } else {
+            LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &R.q, R.terms));
+        }
+    }
     HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];

@@ -257,6 +257,7 @@ class LearnedStats:
     voted: list
     candidates: list
     modularity: float = 0.0
+    mod_terms: dict = field(default_factory=dict)
 
 
 class Context:
@@ -391,7 +392,9 @@ class Context:
         k = st.iterations
         stats = LearnedStats(k, bool(st.converged), st.learned_rounds, st.check_round, st.changed_last,
                              st.arcs_processed, st.ms_total, st.ms_rounds, [int(x) for x in ch[:k]],
-                             [int(x) for x in vo[:k]], [int(x) for x in ca[:k]], st.modularity)
+                             [int(x) for x in vo[:k]], [int(x) for x in ca[:k]], st.modularity,
+                             {"two_m": int(st.mod_terms[0]), "sigma_in": int(st.mod_terms[1]),
+                              "sum_k2": int(st.mod_terms[2]) | (int(st.mod_terms[3]) << 64)})
         return labels_out, stats, (mk[:k] if mk is not None else None)
 
     def trace(self, g: DeviceGraph, tol: float = 0.05, max_iter: int = 20, cap: int | None = None):

@@ -237,3 +237,18 @@ def test_learned_run_replays_in_the_oracle(torch_mod, gg, orc, lrn, lpa, tau):
                 assert np.array_equal(got, ref.labels) and st.changed == ref.changed[:st.iterations]
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.6])
+def test_frontier_runs_report_modularity(torch_mod, gg, orc, lrn, lpa, tau):
+    # frontier and learned runs report Q of their own result: incrementally
+    # when the last round voted every row, else by the full pass
+    m = rand_model(lrn, 13)
+    m["tau"] = tau
+    with lpa.Context(0, modularity=1) as c, lpa.Context(0, modularity=1, frontier=1) as ce:
+        for g in corpus(gg)[:3] + [gg.rmat(14, 16, seed=3)]:
+            dg = lpa.DeviceGraph.from_csr(g, "cuda")
+            for lab, st in (c.run_learned(dg, m, tol=0.02, max_iter=20)[:2], ce.run(dg, tol=0.02, max_iter=20)):
+                ref = orc.modularity(g, lpa.labels_to_numpy(lab))
+                assert st.mod_terms == {"two_m": ref.two_m, "sigma_in": ref.sigma_in, "sum_k2": ref.sum_k2}, g.name
+                assert st.modularity == ref.q
