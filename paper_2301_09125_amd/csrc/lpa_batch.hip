@@ -156,13 +156,11 @@ __device__ uint32_t unit_group(const BatchArgs &b, const RoundArgs &a, u64 *T, u
             Tg[s] = EMPTY_SLOT;
         }
     }
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
-        best = umax64(best, __shfl_xor(best, off, 64));
-        own_w += __shfl_xor(own_w, off, 64);
-        own_hit |= __shfl_xor(own_hit, off, 64);
-        rs += __shfl_xor(rs, off, 64);
-    }
+    static_assert(G == 16, "a group is one DPP row");
+    best = row_max64(best);
+    own_w = row_sum64(own_w);
+    own_hit = row_sum32(own_hit);
+    rs = row_sum64(rs);
     bool ch = false;
     if (act && gl == 0) {
         if (own_hit || a.sw) best = umax64(best, vote_key(own, own_w + a.sw));

@@ -38,16 +38,92 @@ __device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
     return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+// Wavefront reductions on DPP lane moves (no LDS crossbar): swaps inside
+// quads, then half-row and row mirrors leave every lane of a 16-lane row
+// with the row's result; the row broadcasts 15 and 31 carry rows 0-2 into
+// row 3, and lane 63 holds the wavefront's result.  Lanes a move does not
+// write receive 0, the identity of both max and sum.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ u64 dpp64(u64 x) {
+    return (u64)dpp32<CTRL, ROWS>((uint32_t)x) | ((u64)dpp32<CTRL, ROWS>((uint32_t)(x >> 32)) << 32);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror
+constexpr int kDppMirror = 0x140;      // row_mirror
+constexpr int kDppBcast15 = 0x142;     // row_bcast:15 (rows 1 and 3)
+constexpr int kDppBcast31 = 0x143;     // row_bcast:31 (rows 2 and 3)
+
+// Sum / max over each 16-lane row, returned to every lane of the row.
+__device__ __forceinline__ uint32_t row_sum32(uint32_t x) {
+    x += dpp32<kDppXor1>(x);
+    x += dpp32<kDppXor2>(x);
+    x += dpp32<kDppHalfMirror>(x);
+    x += dpp32<kDppMirror>(x);
     return x;
 }
-__device__ __forceinline__ u64 wave_max64(u64 x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = umax64(x, __shfl_xor(x, off, 64));
+__device__ __forceinline__ u64 row_sum64(u64 x) {
+    x += dpp64<kDppXor1>(x);
+    x += dpp64<kDppXor2>(x);
+    x += dpp64<kDppHalfMirror>(x);
+    x += dpp64<kDppMirror>(x);
     return x;
+}
+__device__ __forceinline__ u64 row_max64(u64 x) {
+    x = umax64(x, dpp64<kDppXor1>(x));
+    x = umax64(x, dpp64<kDppXor2>(x));
+    x = umax64(x, dpp64<kDppHalfMirror>(x));
+    x = umax64(x, dpp64<kDppMirror>(x));
+    return x;
+}
+
+__device__ __forceinline__ uint32_t lane63_32(uint32_t x) { return (uint32_t)__builtin_amdgcn_readlane((int)x, 63); }
+__device__ __forceinline__ u64 lane63_64(u64 x) {
+    return (u64)lane63_32((uint32_t)x) | ((u64)lane63_32((uint32_t)(x >> 32)) << 32);
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
+    x = row_sum32(x);
+    x += dpp32<kDppBcast15, 0xA>(x);
+    x += dpp32<kDppBcast31, 0xC>(x);
+    return lane63_32(x);
+}
+__device__ __forceinline__ u64 wave_sum64(u64 x) {
+    x = row_sum64(x);
+    x += dpp64<kDppBcast15, 0xA>(x);
+    x += dpp64<kDppBcast31, 0xC>(x);
+    return lane63_64(x);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dppf(float x) {
+    return __uint_as_float(dpp32<CTRL, ROWS>(__float_as_uint(x)));
+}
+__device__ __forceinline__ float wave_sum(float x) {
+    x += dppf<kDppXor1>(x);
+    x += dppf<kDppXor2>(x);
+    x += dppf<kDppHalfMirror>(x);
+    x += dppf<kDppMirror>(x);
+    x += dppf<kDppBcast15, 0xA>(x);  // lanes not written get +0.0f
+    x += dppf<kDppBcast31, 0xC>(x);
+    return __uint_as_float(lane63_32(__float_as_uint(x)));
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "wave_sum: 32- or 64-bit integers");
+    if constexpr (sizeof(T) == 4)
+        return (T)wave_sum32((uint32_t)x);
+    else
+        return (T)wave_sum64((u64)x);
+}
+__device__ __forceinline__ u64 wave_max64(u64 x) {
+    x = row_max64(x);
+    x = umax64(x, dpp64<kDppBcast15, 0xA>(x));
+    x = umax64(x, dpp64<kDppBcast31, 0xC>(x));
+    return lane63_64(x);
 }
 
 // Insert (lab, wv) into an LDS table of mask+1 slots with linear probing.

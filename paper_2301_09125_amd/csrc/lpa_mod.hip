@@ -56,7 +56,7 @@ __device__ __forceinline__ void add_community(ModTable &M, u64 *K, bool act, uin
     const u64 actmask = __ballot(act);
     if (!actmask) return;
     const int lead = __ffsll((long long)actmask) - 1;
-    const uint32_t ll = __shfl(lv, lead, 64);
+    const uint32_t ll = (uint32_t)__builtin_amdgcn_readlane((int)lv, lead);
     const bool same = act && lv == ll;
     const u64 part = wave_sum(same ? kv : 0ull);
     if ((int)(threadIdx.x & 63) == lead && part) mod_table_add(M, K, ll, part);

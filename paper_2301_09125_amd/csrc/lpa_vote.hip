@@ -191,15 +191,23 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
                 }
             }
         }
+        if (FEAT) {
 #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-            if (FEAT)
-                top2_xor(best, k2, off);
-            else
-                best = umax64(best, __shfl_xor(best, off, 64));
-            own_w += __shfl_xor(own_w, off, 64);
-            own_hit |= __shfl_xor(own_hit, off, 64);
-            rs += __shfl_xor(rs, off, 64);
+            for (int off = G / 2; off > 0; off >>= 1) top2_xor(best, k2, off);
+        }
+        if (G == 16) {  // a group is one DPP row
+            if (!FEAT) best = row_max64(best);
+            own_w = row_sum64(own_w);
+            own_hit = row_sum32(own_hit);
+            rs = row_sum64(rs);
+        } else {
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                if (!FEAT) best = umax64(best, __shfl_xor(best, off, 64));
+                own_w += __shfl_xor(own_w, off, 64);
+                own_hit |= __shfl_xor(own_hit, off, 64);
+                rs += __shfl_xor(rs, off, 64);
+            }
         }
         bool ch = false;
         if (act && gl == 0) {

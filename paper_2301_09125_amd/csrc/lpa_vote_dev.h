@@ -131,7 +131,7 @@ __device__ __forceinline__ void wave_peel(u64 *T, uint32_t mask, const uint32_t 
 #pragma unroll
         for (int j = A - 1; j >= 0; --j)
             if (rem >> j & 1u) mine = lab[j];
-        const uint32_t L = __shfl(mine, lead, 64);
+        const uint32_t L = (uint32_t)__builtin_amdgcn_readlane((int)mine, lead);
         uint32_t s = 0;
 #pragma unroll
         for (int j = 0; j < A; ++j)
@@ -205,7 +205,7 @@ __device__ __forceinline__ uint32_t listed_tally(ListedTable &t, const uint32_t 
 #pragma unroll
         for (int j = A - 1; j >= 0; --j)
             if (rem >> j & 1u) mine = lab[j];
-        const uint32_t L = __shfl(mine, lead, 64);
+        const uint32_t L = (uint32_t)__builtin_amdgcn_readlane((int)mine, lead);
         uint32_t s = 0;
 #pragma unroll
         for (int j = 0; j < A; ++j)
