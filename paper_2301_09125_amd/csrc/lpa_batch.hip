@@ -80,99 +80,6 @@ __device__ __forceinline__ void check_graph(const BatchArgs &b, const uint32_t (
     if (bad) atomicOr(b.err, ERR_GRAPH);
 }
 
-// 64 one-lane rows v0 .. v1-1 (degree <= 8) of graph g.  Returns the number
-// of changed rows (same value on every lane).
-__device__ uint32_t unit_thread(const BatchArgs &b, const RoundArgs &a, uint32_t v0, uint32_t v1, uint32_t g,
-                                bool round1) {
-    constexpr int D = kThreadMaxCap;
-    const uint32_t v = v0 + (threadIdx.x & 63);
-    bool ch = false;
-    if (v < v1) {
-        const uint64_t rb = a.g.rp[v], re = a.g.rp[v + 1];
-        const uint32_t own = a.L_old[v];
-        uint32_t u[D], lab[D], wt[D], tl[D], valid = 0;
-        load_arcs<D, 1>(a, rb, re, u, wt, valid);
-        if (round1) check_graph<D>(b, u, valid, g);
-        gather_labels<D>(a, u, valid, lab);
-        u64 rs = a.sw;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            rs += wt[j];
-            tl[j] = wt[j] + (lab[j] == own ? a.sw : 0u);
-        }
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-#pragma unroll
-            for (int k = j + 1; k < D; ++k)
-                if (lab[j] == lab[k]) {
-                    tl[j] += wt[k];
-                    tl[k] += wt[j];
-                }
-        u64 best = a.sw ? vote_key(own, a.sw) : 0ull;
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-            if (valid >> j & 1u) best = umax64(best, vote_key(lab[j], tl[j]));
-        const uint32_t nl = best ? ~(uint32_t)best : own;
-        a.L_new[v] = nl;
-        ch = nl != own;
-        if (round1 && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
-    }
-    return (uint32_t)__popcll(__ballot(ch));
-}
-
-// Four 16-lane rows v0 .. v1-1 (degree <= 32), a 64-slot table each in T.
-__device__ uint32_t unit_group(const BatchArgs &b, const RoundArgs &a, u64 *T, uint32_t v0, uint32_t v1, uint32_t g,
-                               bool round1) {
-    constexpr int G = kGroupLanes, CAP = kGroupSlots, A = CAP / (2 * G);
-    const uint32_t lane = threadIdx.x & 63, gl = lane & (G - 1);
-    u64 *Tg = T + (lane / G) * CAP;
-    const uint32_t v = v0 + lane / G;
-    const bool act = v < v1;
-    uint64_t rb = 0, re = 0;
-    uint32_t own = 0;
-    if (act) {
-        rb = a.g.rp[v];
-        re = a.g.rp[v + 1];
-        own = a.L_old[v];
-    }
-    uint32_t u[A], lab[A], wt[A], valid = 0;
-    load_arcs<A, G>(a, rb + gl, re, u, wt, valid);
-    if (round1) check_graph<A>(b, u, valid, g);
-    gather_labels<A>(a, u, valid, lab);
-    u64 own_w = 0, rs = 0;
-    uint32_t own_hit = 0, rem = 0;
-    split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
-    uint32_t S = next_pow2(2u * (uint32_t)(re - rb));
-    S = S < (uint32_t)G ? (uint32_t)G : (S > (uint32_t)CAP ? (uint32_t)CAP : S);
-#pragma unroll
-    for (int j = 0; j < A; ++j)
-        if (rem >> j & 1u) lds_insert(Tg, S - 1, lab[j], wt[j]);
-    wave_sync();
-    u64 best = 0;
-    for (uint32_t s = gl; s < S; s += G) {
-        const u64 x = Tg[s];
-        if (x != EMPTY_SLOT) {
-            best = umax64(best, slot_key(x));
-            Tg[s] = EMPTY_SLOT;
-        }
-    }
-    static_assert(G == 16, "a group is one DPP row");
-    best = row_max64(best);
-    own_w = row_sum64(own_w);
-    own_hit = row_sum32(own_hit);
-    rs = row_sum64(rs);
-    bool ch = false;
-    if (act && gl == 0) {
-        if (own_hit || a.sw) best = umax64(best, vote_key(own, own_w + a.sw));
-        const uint32_t nl = best ? ~(uint32_t)best : own;
-        a.L_new[v] = nl;
-        ch = nl != own;
-        if (round1 && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
-    }
-    wave_sync();
-    return (uint32_t)__popcll(__ballot(ch));
-}
-
 // One row v of graph g: at most SLOTS/2 arcs through the wavefront's LDS
 // table, or, when `long_row` (h = its index among the long rows), any number
 // of arcs in SLOTS/2-arc chunks merged exactly in the row's global slab.
@@ -249,6 +156,141 @@ __device__ uint32_t unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, ui
     return (uint32_t)__popcll(__ballot(ch));
 }
 
+// Position of one work unit: its graph and its rows v0 .. min(v0 + R, end) - 1.
+struct UnitPos {
+    uint32_t g, v0, end;
+};
+
+// Row bounds and own label of row v (v < end), or an empty row: loads are
+// issued unconditionally (row 0 stands in) so that the loads of several
+// units are in flight together.
+__device__ __forceinline__ void row_head(const RoundArgs &a, uint32_t v, bool act, uint64_t &rb, uint64_t &re,
+                                         uint32_t &own) {
+    const uint32_t x = act ? v : 0u;
+    const uint64_t b0 = a.g.rp[x], b1 = a.g.rp[x + 1];
+    own = a.L_old[x];
+    rb = b0;
+    re = act ? b1 : b0;
+}
+
+// NU thread units (64 one-lane rows each) at once: every load of every unit
+// is issued before any unit waits for one.  ch[k] = rows of unit k changed.
+template <int NU>
+__device__ void units_thread(const BatchArgs &b, const RoundArgs &a, const UnitPos (&up)[NU], bool round1,
+                             uint32_t (&ch)[NU]) {
+    constexpr int D = kThreadMaxCap;
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t v[NU], own[NU], u[NU][D], lab[NU][D], wt[NU][D], valid[NU];
+    uint64_t rb[NU], re[NU];
+    bool act[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        v[k] = up[k].v0 + lane;
+        act[k] = v[k] < up[k].end;
+        row_head(a, v[k], act[k], rb[k], re[k], own[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NU; ++k) load_arcs<D, 1>(a, rb[k], re[k], u[k], wt[k], valid[k]);
+    if (round1) {
+#pragma unroll
+        for (int k = 0; k < NU; ++k) check_graph<D>(b, u[k], valid[k], up[k].g);
+    }
+#pragma unroll
+    for (int k = 0; k < NU; ++k) gather_labels<D>(a, u[k], valid[k], lab[k]);
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        u64 rs = a.sw;
+        uint32_t tl[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            rs += wt[k][j];
+            tl[j] = wt[k][j] + (lab[k][j] == own[k] ? a.sw : 0u);
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int i = j + 1; i < D; ++i)
+                if (lab[k][j] == lab[k][i]) {
+                    tl[j] += wt[k][i];
+                    tl[i] += wt[k][j];
+                }
+        u64 best = a.sw ? vote_key(own[k], a.sw) : 0ull;
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            if (valid[k] >> j & 1u) best = umax64(best, vote_key(lab[k][j], tl[j]));
+        bool c = false;
+        if (act[k]) {
+            const uint32_t nl = best ? ~(uint32_t)best : own[k];
+            a.L_new[v[k]] = nl;
+            c = nl != own[k];
+            if (round1 && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+        }
+        ch[k] = (uint32_t)__popcll(__ballot(c));
+    }
+}
+
+// NU group units (four 16-lane rows each) at once: the loads of every unit
+// are in flight together, then each unit tallies in the groups' tables T.
+template <int NU>
+__device__ void units_group(const BatchArgs &b, const RoundArgs &a, u64 *T, const UnitPos (&up)[NU], bool round1,
+                            uint32_t (&ch)[NU]) {
+    constexpr int G = kGroupLanes, CAP = kGroupSlots, A = CAP / (2 * G);
+    static_assert(G == 16, "a group is one DPP row");
+    const uint32_t lane = threadIdx.x & 63, gl = lane & (G - 1);
+    u64 *Tg = T + (lane / G) * CAP;
+    uint32_t v[NU], own[NU], u[NU][A], lab[NU][A], wt[NU][A], valid[NU];
+    uint64_t rb[NU], re[NU];
+    bool act[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        v[k] = up[k].v0 + lane / G;
+        act[k] = v[k] < up[k].end;
+        row_head(a, v[k], act[k], rb[k], re[k], own[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NU; ++k) load_arcs<A, G>(a, rb[k] + gl, re[k], u[k], wt[k], valid[k]);
+    if (round1) {
+#pragma unroll
+        for (int k = 0; k < NU; ++k) check_graph<A>(b, u[k], valid[k], up[k].g);
+    }
+#pragma unroll
+    for (int k = 0; k < NU; ++k) gather_labels<A>(a, u[k], valid[k], lab[k]);
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        u64 own_w = 0, rs = 0;
+        uint32_t own_hit = 0, rem = 0;
+        split_own<A>(lab[k], wt[k], valid[k], own[k], own_w, own_hit, rem, rs);
+        uint32_t S = next_pow2(2u * (uint32_t)(re[k] - rb[k]));
+        S = S < (uint32_t)G ? (uint32_t)G : (S > (uint32_t)CAP ? (uint32_t)CAP : S);
+#pragma unroll
+        for (int j = 0; j < A; ++j)
+            if (rem >> j & 1u) lds_insert(Tg, S - 1, lab[k][j], wt[k][j]);
+        wave_sync();
+        u64 best = 0;
+        for (uint32_t s = gl; s < S; s += G) {
+            const u64 x = Tg[s];
+            if (x != EMPTY_SLOT) {
+                best = umax64(best, slot_key(x));
+                Tg[s] = EMPTY_SLOT;
+            }
+        }
+        best = row_max64(best);
+        own_w = row_sum64(own_w);
+        own_hit = row_sum32(own_hit);
+        rs = row_sum64(rs);
+        bool c = false;
+        if (act[k] && gl == 0) {
+            if (own_hit || a.sw) best = umax64(best, vote_key(own[k], own_w + a.sw));
+            const uint32_t nl = best ? ~(uint32_t)best : own[k];
+            a.L_new[v[k]] = nl;
+            c = nl != own[k];
+            if (round1 && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+        }
+        wave_sync();
+        ch[k] = (uint32_t)__popcll(__ballot(c));
+    }
+}
+
 // Units of bin `bin` assigned to wavefront w this round.
 template <int SLOTS>
 __device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t w, bool round1) {
@@ -261,6 +303,48 @@ __device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin,
     uint32_t g = b.start[(size_t)bin * b.nw + w];
     uint32_t p0 = pref[g], p1 = pref[g + 1];
     uint32_t lo = b.seg_lo[(size_t)bin * b.G + g], end = lo + b.seg_cnt[(size_t)bin * b.G + g];
+    if (bin == BIN_THREAD || bin == BIN_GROUP) {
+        // two units at a time (a unit past i1 is empty); changed counts go
+        // to each unit's graph, one atomic per graph run
+        constexpr int NU = 2;
+        uint32_t gacc = g, wch = 0;
+        for (uint32_t i = i0; i < i1; i += NU) {
+            UnitPos up[NU];
+#pragma unroll
+            for (int k = 0; k < NU; ++k) {
+                const uint32_t ik = i + k;
+                if (ik < i1) {
+                    while (ik >= p1) {  // next segment that has units this round
+                        ++g;
+                        p0 = p1;
+                        p1 = pref[g + 1];
+                        lo = b.seg_lo[(size_t)bin * b.G + g];
+                        end = lo + b.seg_cnt[(size_t)bin * b.G + g];
+                    }
+                    up[k] = UnitPos{g, lo + (ik - p0) * R, end};
+                } else {
+                    up[k] = UnitPos{g, 0u, 0u};
+                }
+            }
+            uint32_t ch[NU];
+            if (bin == BIN_THREAD)
+                units_thread<NU>(b, a, up, round1, ch);
+            else
+                units_group<NU>(b, a, T, up, round1, ch);
+#pragma unroll
+            for (int k = 0; k < NU; ++k) {
+                if (i + k >= i1) break;
+                if (up[k].g != gacc) {
+                    if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
+                    wch = 0;
+                    gacc = up[k].g;
+                }
+                wch += ch[k];
+            }
+        }
+        if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
+        return;
+    }
     uint32_t wch = 0;
     for (uint32_t i = i0; i < i1; ++i) {
         if (i >= p1) {  // next segment that has units this round
@@ -275,12 +359,7 @@ __device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin,
             end = lo + b.seg_cnt[(size_t)bin * b.G + g];
         }
         const uint32_t v0 = lo + (i - p0) * R;
-        if (bin == BIN_THREAD)
-            wch += unit_thread(b, a, v0, end, g, round1);
-        else if (bin == BIN_GROUP)
-            wch += unit_group(b, a, T, v0, end, g, round1);
-        else
-            wch += unit_wave<SLOTS>(b, a, T, v0, v0 - b.lo[BIN_HUB], g, bin == BIN_HUB, round1);
+        wch += unit_wave<SLOTS>(b, a, T, v0, v0 - b.lo[BIN_HUB], g, bin == BIN_HUB, round1);
     }
     if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[g], (u64)wch);
 }
