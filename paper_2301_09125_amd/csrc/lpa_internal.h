@@ -123,6 +123,7 @@ struct HubState {
     uint32_t *thr;                // per segment: tally bound of its unreported labels
     const uint32_t *item_lo;      // H + 1: first segment of each row
     uint32_t *pending;            // nonzero: some row uses the slab this round
+    uint32_t *repeats;            // relabel pass: rows flagged HUB_REPEATS (0: round 1 needs no table)
 };
 
 // Phase-2 item: touched-list positions [t0, t1) of hub `hub`.
@@ -235,6 +236,11 @@ struct Round1Fuse {
     uint32_t *L1;                 // round-1 label buffer (internal index)
     unsigned long long *changed;  // round-1 counter words
     uint32_t sw;
+    // rows of at most wide_max arcs the pass could not vote (a neighbour
+    // listed twice or out of order), per bin b: rest_list[lo[b] ..
+    // lo[b] + rest_n[b]) (internal rows); round 1 votes just these
+    uint32_t *rest_list;
+    uint32_t *rest_n;
 };
 
 // ---- launchers: lpa_prep.hip ---------------------------------------------
@@ -259,9 +265,11 @@ hipError_t launch_bin_scatter(const Graph &g, const BinCfg &cfg, const uint32_t 
                               uint32_t *new_of, uint64_t *rp2, hipStream_t s);
 // Copy the caller's rows into the internal CSR (ids through new_of) and
 // flag rows that list each neighbour once.
+// Rows [lo, lo + cnt) are bin bin_a below `split` and bin_b from it on.
 hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                                uint32_t *col2, uint32_t *w2, uint8_t *rowflag, uint32_t lo, uint32_t cnt,
-                               int per_wave, uint32_t *err, const Round1Fuse *f, hipStream_t s);
+                               uint32_t split, int bin_a, int bin_b, int per_wave, uint32_t *err,
+                               const Round1Fuse *f, hipStream_t s);
 hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                               uint32_t *col2, uint32_t *w2, const HubItem *items, uint32_t count,
                               uint32_t *hub_flags, uint32_t *err, const Round1Fuse *f, const HubState *hs,

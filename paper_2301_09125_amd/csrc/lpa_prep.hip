@@ -480,7 +480,19 @@ struct RelabelArgs {
     u64 *changed;       // round-1 changed counter words
     uint32_t sw;
     HubState hs;        // long rows: best / own_sum / flags / rowsum
+    // rows this pass does not vote go to the round-1 lists (Round1Fuse)
+    uint32_t *rest_list, *rest_n;
+    uint32_t lo, split;
+    int bin_a, bin_b;
 };
+
+// Queue internal row r, which the pass could not vote, for round 1.
+__device__ __forceinline__ void queue_rest(const RelabelArgs &a, uint32_t r) {
+    if (!a.rest_list) return;
+    const bool first = r < a.split;
+    const uint32_t k = atomicAdd(&a.rest_n[first ? a.bin_a : a.bin_b], 1u);
+    a.rest_list[(first ? a.lo : a.split) + k] = r;
+}
 
 // Round-1 key of the arcs a lane holds (labels = original ids).
 template <int A>
@@ -560,6 +572,8 @@ __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *
             a.L1[r] = nl;
             chg += nl != v;
             if (rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+        } else if (a.L1) {
+            queue_rest(a, r);
         }
     }
     if (a.L1) block_count(chg, a.changed);
@@ -660,6 +674,8 @@ __global__ __launch_bounds__(256) void relabel_wave_k(RelabelArgs a, uint8_t *ro
                 a.L1[r] = nl;
                 chg += nl != v;
                 if (rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+            } else if (a.L1) {
+                queue_rest(a, r);
             }
         }
     }
@@ -677,7 +693,10 @@ __global__ __launch_bounds__(256) void relabel_hub_k(RelabelArgs a, const HubIte
         uint32_t own_hit = 0;
         const uint32_t ok = relabel_segment(a, item.r, item.b0, item.b1 - item.b0, best, own_w, own_hit, rs);
         if ((threadIdx.x & 63) == 0) {
-            if (!ok) atomicOr(&hub_flags[item.r], HUB_REPEATS);
+            if (!ok) {
+                atomicOr(&hub_flags[item.r], HUB_REPEATS);
+                if (a.L1) atomicAdd(a.hs.repeats, 1u);
+            }
             if (a.L1) {  // the row's round-1 partials, as the direct long-row vote gathers them
                 const uint32_t h = item.r;
                 if (best) atomicMax(&a.hs.best[h], best);
@@ -705,13 +724,17 @@ __global__ void hub_unfuse_k(HubState hs, uint32_t H) {
 
 hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                                uint32_t *col2, uint32_t *w2, uint8_t *rowflag, uint32_t lo, uint32_t cnt,
-                               int per_wave, uint32_t *err, const Round1Fuse *f, hipStream_t s) {
+                               uint32_t split, int bin_a, int bin_b, int per_wave, uint32_t *err,
+                               const Round1Fuse *f, hipStream_t s) {
     if (cnt == 0) return hipSuccess;
-    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err, nullptr, nullptr, 0, HubState{}};
+    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err, nullptr, nullptr, 0, HubState{},
+                  nullptr, nullptr, lo, split, bin_a, bin_b};
     if (f) {
         a.L1 = f->L1;
         a.changed = f->changed;
         a.sw = f->sw;
+        a.rest_list = f->rest_list;
+        a.rest_n = f->rest_n;
     }
     if (per_wave)
         relabel_wave_k<<<grid_for(cnt, 4, 8192), 256, 0, s>>>(a, rowflag, lo, cnt);
@@ -724,7 +747,8 @@ hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint
                               uint32_t *hub_flags, uint32_t *err, const Round1Fuse *f, const HubState *hs,
                               uint32_t H, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err, nullptr, nullptr, 0, HubState{}};
+    RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err, nullptr, nullptr, 0, HubState{},
+                  nullptr, nullptr, 0, 0, 0, 0};
     if (f) {
         a.L1 = f->L1;
         a.changed = f->changed;

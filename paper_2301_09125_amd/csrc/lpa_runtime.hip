@@ -99,7 +99,7 @@ struct lpa_ctx {
     DevBuf old_of, new_of, rp2, col2, w2, rowflag, La, Lb;
     DevBuf counters;  // kCountWords u64 per round, then the error word
     DevBuf items, ritems, slab_off, slab_mask, touched_off, tcount, best, own_sum, hflags, rowsum, slab, touched;
-    DevBuf cand, thr, item_lo, mrows, slab_pending, hub_tmp;
+    DevBuf cand, thr, item_lo, mrows, slab_pending, hub_tmp, r1_rows, r1_cnt;
     DevBuf K, mod_sums, partials;
     DevBuf gid, gvd, bstate, bseg;  // batched run
     DevBuf f_top1, f_top2, f_kw, f_last, f_front, f_stale, f_lists, f_small, f_model;  // frontier runs
@@ -241,6 +241,7 @@ HubState hub_state(lpa_ctx *c) {
     h.thr = c->thr.as<uint32_t>();
     h.item_lo = c->item_lo.as<uint32_t>();
     h.pending = c->slab_pending.as<uint32_t>();
+    h.repeats = h.pending ? h.pending + 1 : nullptr;
     return h;
 }
 
@@ -335,8 +336,8 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
             HIP_TRY(launch_fill_u64(c->slab.as<u64>(), 0xFFFFFFFF00000000ull, c->slab.bytes / sizeof(u64), s));
             c->slab_dirty = false;
         }
-        HIP_TRY(c->slab_pending.ensure(sizeof(uint32_t)));
-        HIP_TRY(launch_fill_u32(c->slab_pending.as<uint32_t>(), 0, 1, s));
+        HIP_TRY(c->slab_pending.ensure(2 * sizeof(uint32_t)));  // pending, repeats
+        HIP_TRY(launch_fill_u32(c->slab_pending.as<uint32_t>(), 0, 2, s));
         HIP_TRY(c->cand.ensure((size_t)P.n_items * kTopK * sizeof(u64)));
         HIP_TRY(c->thr.ensure((size_t)P.n_items * sizeof(uint32_t)));
         HIP_TRY(launch_fill_u32(c->tcount.as<uint32_t>(), 0, H, s));
@@ -349,6 +350,7 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
     uint32_t *w2 = g->w ? c->w2.as<uint32_t>() : nullptr;
     const Bins &B = P.bins;
     if (fuse) HIP_TRY(launch_init_labels(La, fuse->L1, c->old_of.as<uint32_t>(), nullptr, n, s));
+    if (fuse && fuse->rest_n) HIP_TRY(launch_fill_u32(fuse->rest_n, 0, NBINS, s));
     const HubState hs = hub_state(c);
     HIP_TRY(launch_relabel_hub(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
                                c->col2.as<uint32_t>(), w2, c->items.as<HubItem>(), P.n_items,
@@ -356,10 +358,12 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
                                s));
     HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
                                 c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_WIDE],
-                                B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE], 1, err_dev, fuse, s));
+                                B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE], B.lo[BIN_WAVE], BIN_WIDE, BIN_WAVE, 1, err_dev,
+                                fuse, s));
     HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
                                 c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_GROUP],
-                                B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD], 0, err_dev, fuse, s));
+                                B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD], B.lo[BIN_THREAD], BIN_GROUP, BIN_THREAD, 0,
+                                err_dev, fuse, s));
 
     return LPA_OK;
 }
@@ -384,7 +388,7 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
         }
         return r;
     };
-    auto kid = [&](int k) { return lists ? (int)K_LISTED : (rest ? (int)K_HUB1 : k); };
+    auto kid = [&](int k) { return rest ? (int)K_HUB1 : (lists ? (int)K_LISTED : k); };
     LPA_TRY(timed(c, kid(K_THREAD), bytes(BIN_THREAD), B.arcs[BIN_THREAD], [&] {
         return launch_vote_thread(args(BIN_THREAD), B.lo[BIN_THREAD], B.cnt[BIN_THREAD], first, feat, cap, s);
     }));
@@ -523,7 +527,10 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     // from the unique labels, round 1 of the rows that list each neighbour
     // once is done while the internal CSR is built
     const bool fused = !resume && max_iter > 0;
-    const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight};
+    HIP_TRY(c->r1_rows.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(c->r1_cnt.ensure(NBINS * sizeof(uint32_t)));
+    const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight, c->r1_rows.as<uint32_t>(),
+                        c->r1_cnt.as<uint32_t>()};
     LPA_TRY(prepare(c, g, P, err_dev, true, fused ? &fz : nullptr, c->La.as<uint32_t>()));
     if (!fused)
         HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(),
@@ -559,7 +566,13 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         ra.skip_distinct = (first && fused) ? 1 : 0;
         ra.insum = insums ? insums + (size_t)(t - 1) * kCountWords : nullptr;
         HIP_TRY(hipEventRecord(c->round_a, s));
-        LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first));
+        if (first && fused) {  // just the rows the relabel pass queued
+            uint32_t *r1l[NBINS];
+            for (int b = 0; b < NBINS; ++b) r1l[b] = c->r1_rows.as<uint32_t>() + B.lo[b];
+            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first, 0, r1l, c->r1_cnt.as<uint32_t>()));
+        } else {
+            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first));
+        }
         HIP_TRY(hipEventRecord(c->round_b, s));
         HIP_TRY(hipMemcpyAsync(c->pinned + 16, ra.changed, kCountWords * sizeof(u64), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -723,7 +736,10 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
     // and the first prediction uses round 2's tallies.  Traces keep round 1
     // in the vote kernels for the features of round 2.
     const bool fused = R.mode != F_TRACE && max_iter > 0;
-    const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight};
+    HIP_TRY(c->r1_rows.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(c->r1_cnt.ensure(NBINS * sizeof(uint32_t)));
+    const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight, c->r1_rows.as<uint32_t>(),
+                        c->r1_cnt.as<uint32_t>()};
     LPA_TRY(prepare(c, g, P, err_dev, true, fused ? &fz : nullptr, c->La.as<uint32_t>()));
     const Bins &B = P.bins;
     if (!fused)
@@ -833,7 +849,13 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
                 HIP_TRY(launch_fill_u64(reinterpret_cast<u64 *>(c->f_stale.p), 0, ((size_t)n + 7) / 8, s));
             if (R.mode == F_TRACE && t >= 2 && R.tX && trace_base + nonhub_cnt <= R.tcap)
                 HIP_TRY(launch_trace_x(fa, nonhub_lo, nonhub_cnt, R.tX + trace_base * 6, s));
-            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, t == 1 ? 1 : 0, feat));
+            if (t == 1 && fused) {  // just the rows the relabel pass queued
+                uint32_t *r1l[NBINS];
+                for (int b = 0; b < NBINS; ++b) r1l[b] = c->r1_rows.as<uint32_t>() + B.lo[b];
+                LPA_TRY(enqueue_round(c, P, ra, hs, weighted, 1, feat, r1l, c->r1_cnt.as<uint32_t>()));
+            } else {
+                LPA_TRY(enqueue_round(c, P, ra, hs, weighted, t == 1 ? 1 : 0, feat));
+            }
         } else {
             HIP_TRY(launch_fill_u32(list_n, 0, NBINS, s));
             HIP_TRY(launch_fill_u64(cand_dev, 0, 3, s));
@@ -1640,7 +1662,7 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->items,      &c->ritems,   &c->slab_off, &c->slab_mask, &c->touched_off, &c->tcount,
                       &c->best,       &c->own_sum,  &c->hflags,   &c->rowsum,    &c->slab,        &c->touched,
                       &c->K,          &c->mod_sums, &c->partials, &c->cand,      &c->thr,         &c->item_lo,
-                      &c->mrows,      &c->slab_pending, &c->hub_tmp, &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
+                      &c->mrows,      &c->slab_pending, &c->hub_tmp, &c->r1_rows, &c->r1_cnt, &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
                       &c->f_top1, &c->f_top2, &c->f_kw, &c->f_last, &c->f_front, &c->f_stale, &c->f_lists,
                       &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
                       &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist};

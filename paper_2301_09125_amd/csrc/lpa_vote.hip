@@ -565,6 +565,10 @@ template <bool FIRST, bool W>
 __global__ __launch_bounds__(256) void vote_hub_k(RoundArgs a, const HubItem *__restrict__ items, uint32_t count,
                                                   HubState hs) {
     constexpr int A = kWaveArcs / 64;
+    // round 1 after the relabel pass: only rows flagged HUB_REPEATS need a
+    // table, and usually there are none
+    if (FIRST && a.skip_distinct && __hip_atomic_load(hs.repeats, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return;
     __shared__ u64 table[4 * kHubSlots];
     __shared__ uint16_t lists[4 * kHubSlots];
     const uint32_t lane = threadIdx.x & 63;

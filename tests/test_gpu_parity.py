@@ -186,6 +186,8 @@ def test_repeated_neighbours_round_one(gg, orc, lpa, ctx):
     for sw in (0, 1):
         assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=10, sw=sw)
         assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=10, sw=sw, wave_max=40, wide_max=40)
+        # the frontier engine votes the same queued rows in round 1
+        assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=10, sw=sw, frontier=1, wave_max=40, wide_max=40)
 
 
 def test_random_bin_thresholds_give_same_labels(gg, orc, lpa, ctx):
