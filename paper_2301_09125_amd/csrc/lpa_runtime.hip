@@ -518,7 +518,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     u64 *insums = want_insum ? counters + rwords : nullptr;
     uint32_t *err_dev = reinterpret_cast<uint32_t *>(counters + cwords - 1);
     HIP_TRY(launch_fill_u64(counters, 0, cwords, s));
-    LPA_TRY(ensure_pinned(c, kCountWords + 16));
+    LPA_TRY(ensure_pinned(c, 2 * kCountWords + 16));  // round counts and own-label sums
     if (resume) HIP_TRY(launch_check_labels(labels, n, err_dev, s));
 
     Plan P;
@@ -547,7 +547,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     uint32_t *L_old = c->La.as<uint32_t>(), *L_new = c->Lb.as<uint32_t>();
     uint32_t it = 0;
     int converged = 0;
-    u64 changed = 0;
+    u64 changed = 0, insum_last = 0;
     double ms_rounds = 0;
     for (uint32_t t = 1; t <= max_iter; ++t) {
         RoundArgs ra;
@@ -575,6 +575,9 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         }
         HIP_TRY(hipEventRecord(c->round_b, s));
         HIP_TRY(hipMemcpyAsync(c->pinned + 16, ra.changed, kCountWords * sizeof(u64), hipMemcpyDeviceToHost, s));
+        if (ra.insum)  // read with the round's counts: no extra round trip after the last round
+            HIP_TRY(hipMemcpyAsync(c->pinned + 16 + kCountWords, ra.insum, kCountWords * sizeof(u64),
+                                   hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (c->opt.profile) collect_profile(c);
@@ -584,7 +587,11 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
         if (errbits) return err_status(errbits);
         changed = 0;
-        for (int k = 0; k < kCountSlots; ++k) changed += c->pinned[16 + (size_t)k * kCountStride];
+        insum_last = 0;
+        for (int k = 0; k < kCountSlots; ++k) {
+            changed += c->pinned[16 + (size_t)k * kCountStride];
+            if (ra.insum) insum_last += c->pinned[16 + kCountWords + (size_t)k * kCountStride];
+        }
         it = t;
         if (stats) {
             if (stats->changed_per_iter && t <= stats->cap) stats->changed_per_iter[t - 1] = changed;
@@ -600,23 +607,19 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     double q = 0;
     uint64_t terms[4] = {0, 0, 0, 0};
     if (c->opt.modularity) {
-        if (it >= 2) {
-            // every row voted in round it (round 1 may have been voted by the
-            // relabel pass, which does not sum own-label weights)
-            HIP_TRY(hipMemcpyAsync(c->pinned + 16, insums + (size_t)(it - 1) * kCountWords,
-                                   kCountWords * sizeof(u64), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            u64 ins = 0;
-            for (int k = 0; k < kCountSlots; ++k) ins += c->pinned[16 + (size_t)k * kCountStride];
-            LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms, L_new, ins));
-        } else {
+        // after round 1 every row voted in round it (round 1 may have been
+        // voted by the relabel pass, which does not sum own-label weights);
+        // modularity_internal ends with a synchronisation and an error check
+        if (it >= 2)
+            LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms, L_new, insum_last));
+        else
             LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms));
-        }
+    } else {
+        HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
+        if (errbits) return err_status(errbits);
     }
-    HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
-    if (errbits) return err_status(errbits);
     if (stats) {
         stats->iterations = it;
         stats->converged = converged;
