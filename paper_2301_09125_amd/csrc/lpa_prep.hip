@@ -585,9 +585,9 @@ __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *
 // Every load is issued by every lane (lanes past the segment read its first
 // arc and are masked), so the 8 id lookups per lane are in flight together
 // instead of one after the other.
+template <int A = kWaveArcs / 64>
 __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32_t r, uint64_t b0, uint64_t len,
                                                     u64 &best, u64 &own_w, uint32_t &own_hit, u64 &wsum) {
-    constexpr int A = kWaveArcs / 64;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t v = a.old_of[r];
     const uint64_t rs = a.g.rp[v];
@@ -656,6 +656,9 @@ __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32
 }
 
 // Rows of 33..512 arcs, one wavefront each.
+// A arcs per lane: 8 for rows of up to 512 arcs, 2 for rows of up to 128
+// (every lane issues all A loads, so a small A keeps short rows cheap).
+template <int A>
 __global__ __launch_bounds__(256) void relabel_wave_k(RelabelArgs a, uint8_t *rowflag, uint32_t lo, uint32_t cnt) {
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 chg = 0;
@@ -664,7 +667,7 @@ __global__ __launch_bounds__(256) void relabel_wave_k(RelabelArgs a, uint8_t *ro
         const uint64_t b0 = a.rp2[r], b1 = a.rp2[r + 1];
         u64 best = 0, own_w = 0, rs = 0;
         uint32_t own_hit = 0;
-        const uint32_t ok = relabel_segment(a, r, b0, b1 - b0, best, own_w, own_hit, rs);
+        const uint32_t ok = relabel_segment<A>(a, r, b0, b1 - b0, best, own_w, own_hit, rs);
         if ((threadIdx.x & 63) == 0) {
             rowflag[r] = ok ? ROW_DISTINCT : 0;
             if (a.L1 && ok) {
@@ -736,10 +739,14 @@ hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uin
         a.rest_list = f->rest_list;
         a.rest_n = f->rest_n;
     }
-    if (per_wave)
-        relabel_wave_k<<<grid_for(cnt, 4, 8192), 256, 0, s>>>(a, rowflag, lo, cnt);
-    else
+    if (per_wave) {
+        // rows [lo, split) have at most 512 arcs, rows [split, lo + cnt) at most 128
+        const uint32_t c1 = split - lo, c2 = lo + cnt - split;
+        if (c1) relabel_wave_k<kWaveArcs / 64><<<grid_for(c1, 4, 8192), 256, 0, s>>>(a, rowflag, lo, c1);
+        if (c2) relabel_wave_k<kWaveArcsSmall / 64><<<grid_for(c2, 4, 8192), 256, 0, s>>>(a, rowflag, split, c2);
+    } else {
         relabel_thread_k<<<grid_for(cnt, 256, 8192), 256, 0, s>>>(a, rowflag, lo, cnt);
+    }
     return hipGetLastError();
 }
 hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
