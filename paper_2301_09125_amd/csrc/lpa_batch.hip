@@ -291,6 +291,52 @@ __device__ void units_group(const BatchArgs &b, const RoundArgs &a, u64 *T, cons
     }
 }
 
+// Units i0 .. i1-1 of the thread (GROUP = false) or group bin, NU at a time
+// (a unit past i1 is empty); changed counts go to each unit's graph, one
+// atomic per run of units of one graph.  (g, p0, p1, lo, end): the segment
+// of unit i0, as run_bin found it.
+template <int NU, bool GROUP>
+__device__ void run_units(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, const uint32_t *pref, uint32_t i0,
+                          uint32_t i1, uint32_t g, uint32_t p0, uint32_t p1, uint32_t lo, uint32_t end, bool round1) {
+    const uint32_t R = unit_rows(bin);
+    uint32_t gacc = g, wch = 0;
+    for (uint32_t i = i0; i < i1; i += NU) {
+        UnitPos up[NU];
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            const uint32_t ik = i + k;
+            if (ik < i1) {
+                while (ik >= p1) {  // next segment that has units this round
+                    ++g;
+                    p0 = p1;
+                    p1 = pref[g + 1];
+                    lo = b.seg_lo[(size_t)bin * b.G + g];
+                    end = lo + b.seg_cnt[(size_t)bin * b.G + g];
+                }
+                up[k] = UnitPos{g, lo + (ik - p0) * R, end};
+            } else {
+                up[k] = UnitPos{g, 0u, 0u};
+            }
+        }
+        uint32_t ch[NU];
+        if (GROUP)
+            units_group<NU>(b, a, T, up, round1, ch);
+        else
+            units_thread<NU>(b, a, up, round1, ch);
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            if (i + k >= i1) break;
+            if (up[k].g != gacc) {
+                if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
+                wch = 0;
+                gacc = up[k].g;
+            }
+            wch += ch[k];
+        }
+    }
+    if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
+}
+
 // Units of bin `bin` assigned to wavefront w this round.
 template <int SLOTS>
 __device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t w, bool round1) {
@@ -303,46 +349,13 @@ __device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin,
     uint32_t g = b.start[(size_t)bin * b.nw + w];
     uint32_t p0 = pref[g], p1 = pref[g + 1];
     uint32_t lo = b.seg_lo[(size_t)bin * b.G + g], end = lo + b.seg_cnt[(size_t)bin * b.G + g];
-    if (bin == BIN_THREAD || bin == BIN_GROUP) {
-        // two units at a time (a unit past i1 is empty); changed counts go
-        // to each unit's graph, one atomic per graph run
-        constexpr int NU = 2;
-        uint32_t gacc = g, wch = 0;
-        for (uint32_t i = i0; i < i1; i += NU) {
-            UnitPos up[NU];
-#pragma unroll
-            for (int k = 0; k < NU; ++k) {
-                const uint32_t ik = i + k;
-                if (ik < i1) {
-                    while (ik >= p1) {  // next segment that has units this round
-                        ++g;
-                        p0 = p1;
-                        p1 = pref[g + 1];
-                        lo = b.seg_lo[(size_t)bin * b.G + g];
-                        end = lo + b.seg_cnt[(size_t)bin * b.G + g];
-                    }
-                    up[k] = UnitPos{g, lo + (ik - p0) * R, end};
-                } else {
-                    up[k] = UnitPos{g, 0u, 0u};
-                }
-            }
-            uint32_t ch[NU];
-            if (bin == BIN_THREAD)
-                units_thread<NU>(b, a, up, round1, ch);
-            else
-                units_group<NU>(b, a, T, up, round1, ch);
-#pragma unroll
-            for (int k = 0; k < NU; ++k) {
-                if (i + k >= i1) break;
-                if (up[k].g != gacc) {
-                    if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
-                    wch = 0;
-                    gacc = up[k].g;
-                }
-                wch += ch[k];
-            }
-        }
-        if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
+    // one-lane and 16-lane rows: several units in flight per wavefront
+    if (bin == BIN_THREAD) {
+        run_units<1, false>(b, a, T, bin, pref, i0, i1, g, p0, p1, lo, end, round1);
+        return;
+    }
+    if (bin == BIN_GROUP) {
+        run_units<4, true>(b, a, T, bin, pref, i0, i1, g, p0, p1, lo, end, round1);
         return;
     }
     uint32_t wch = 0;
