@@ -246,12 +246,16 @@ typedef struct {
     uint32_t cap;
 } lpa_learned_stats;
 
-/* RAK with the learned frontier.  Round 1 votes every vertex.  Each later
- * round votes the candidates the network keeps (and every vertex skipped in
- * the round before), until the round's changed count plus the predicted
+/* RAK with the learned frontier.  Round 1 votes every vertex.  The network
+ * is consulted for a round only when the round before recorded top-two
+ * tallies and changed fewer than half of the non-isolated vertices (tallies
+ * are recorded after a round that changed fewer than half); other rounds
+ * vote every vertex and end the run when they pass the tolerance test.  A
+ * consulted round votes the candidates the network keeps (and every vertex
+ * skipped in the round before); once its changed count plus the predicted
  * changes of the rows it skipped is at most floor(tol * n), or the network
- * kept at least 4/5 of the candidates; the next round then votes every
- * candidate (a full check, equivalent to voting every vertex).  If the check passes the
+ * kept at least 4/5 of the candidates, the next round votes every candidate
+ * (a full check, equivalent to voting every vertex).  If the check passes the
  * run has converged; otherwise rounds go on voting every candidate (plain
  * RAK) until the tolerance test passes or max_iter rounds have run.  Rows
  * longer than wide_max arcs are voted in every round.

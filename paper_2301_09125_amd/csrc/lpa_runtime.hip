@@ -799,6 +799,12 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
     uint32_t *L_old = c->La.as<uint32_t>(), *L_new = c->Lb.as<uint32_t>();
     int all_dirty = 1;
     bool last_full = false;  // the last round voted every row (incremental modularity applies)
+    // learned runs predict only after a round that recorded top-two tallies
+    // and changed fewer than half of the non-isolated vertices; while more
+    // change, the network would keep nearly every candidate and a full round
+    // (plain RAK) is cheaper
+    bool feat_prev = false;
+    bool quiet = false;  // the last round changed fewer than half of the non-isolated vertices
     enum { PH_LEARN, PH_CHECK, PH_PLAIN } phase = R.mode == F_LEARNED ? PH_LEARN : PH_PLAIN;
     for (uint32_t t = 1; t <= max_iter; ++t) {
         RoundArgs ra;
@@ -838,10 +844,11 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         fa.keep_all = phase != PH_LEARN;
         // full: every non-isolated row votes, no candidate lists (round 1,
         // traces, and rounds in which every row is a candidate anyway)
-        const bool full = t == 1 || (t == 2 && fused) || R.mode == F_TRACE || (phase != PH_LEARN && all_dirty);
-        const bool learned_round = !full && phase == PH_LEARN;
+        const bool learn = R.mode == F_LEARNED && phase == PH_LEARN;
+        const bool full = t == 1 || R.mode == F_TRACE || (learn ? !(feat_prev && quiet) : all_dirty != 0);
+        const bool learned_round = learn && !full;
         // the tallies feed the features of the next round's prediction
-        const int feat = (R.mode == F_TRACE || (R.mode == F_LEARNED && phase == PH_LEARN)) && !(t == 1 && fused);
+        const int feat = R.mode == F_TRACE || (learn && quiet && !(t == 1 && fused));
         ra.insum = (full && insums) ? insums + (size_t)(t - 1) * kCountWords : nullptr;
         last_full = full;
         uint64_t trace_base = R.tcount;
@@ -911,11 +918,20 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         R.iterations = t;
         R.changed_last = changed;
         if (learned_round) ++R.learned_rounds;
-        // which vertices can change next round
-        const int mark = R.mode == F_TRACE || changed <= push_limit;
-        fa.t = t;
-        LPA_TRY(timed(c, K_PUSH, 0, 0, [&] { return launch_push(fa, B, mark, s); }));
-        all_dirty = !mark;
+        quiet = 2 * changed < nonisolated;
+        feat_prev = feat != 0;
+        // which vertices can change next round (not needed when the next
+        // round votes every row anyway: a learned-phase round after a full
+        // one without a prediction to feed)
+        const bool next_full = learn && full && !(feat_prev && quiet);
+        if (!next_full || R.mode != F_LEARNED) {
+            const int mark = R.mode == F_TRACE || changed <= push_limit;
+            fa.t = t;
+            LPA_TRY(timed(c, K_PUSH, 0, 0, [&] { return launch_push(fa, B, mark, s); }));
+            all_dirty = !mark;
+        } else {
+            all_dirty = 1;
+        }
         std::swap(L_old, L_new);
         if (t == 1 && R.mode != F_TRACE) {
             if (changed <= thr) {
@@ -925,6 +941,12 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
             continue;
         }
         if (R.mode == F_TRACE || phase == PH_PLAIN) {
+            if (changed <= thr) {
+                R.converged = 1;
+                break;
+            }
+        } else if (phase == PH_LEARN && full) {
+            // a full round is a full sweep: its count is the tolerance test
             if (changed <= thr) {
                 R.converged = 1;
                 break;
