@@ -96,7 +96,8 @@ def gather_ceiling(args, g, P):
     4..256 MB, uniform and skewed (hot ids first, density ~ (id+1)^-0.8, as
     the internal layout puts high-degree vertices first), and (b) the exact
     label-gather streams of this workload's internal layout: every arc, and
-    the arcs of the long rows (the stream the dominant kernel reads)."""
+    the arcs of the long rows (the stream the dominant kernel reads), and the
+    same arcs by the caller's ids (the stream the relabel pass reads)."""
     import torch
     ctx = P.Context(0)
     gen = torch.Generator(device="cuda")
@@ -139,7 +140,8 @@ def gather_ceiling(args, g, P):
     starts = rp[:-1][order]
     arc_pos = torch.repeat_interleave(starts - torch.cumsum(lens, 0) + lens, lens) + torch.arange(
         int(lens.sum()), device="cuda")
-    stream = new_of[col[arc_pos].long()]
+    caller = col[arc_pos]
+    stream = new_of[caller.long()]
     del arc_pos
     rate = ctx.gather_rate(stream, table)
     rows.append((f"{args.workload}: every arc", stream.numel(), rate))
@@ -150,6 +152,13 @@ def gather_ceiling(args, g, P):
     rate_h = ctx.gather_rate(hub, table) if hub_arcs else 0.0
     rows.append((f"{args.workload}: long rows", hub_arcs, rate_h))
     log(f"[gather] {args.workload} long-row arcs ({hub_arcs} gathers): {rate_h / 1e9:7.1f} G gathers/s")
+    # the relabel pass's stream: the caller's ids of the long-row arcs into
+    # the n-entry id map (no locality: the caller's numbering is arbitrary)
+    hub_c = caller[:hub_arcs].contiguous()
+    del caller
+    rate_c = ctx.gather_rate(hub_c, table) if hub_arcs else 0.0
+    rows.append((f"{args.workload}: long rows, caller ids", hub_arcs, rate_c))
+    log(f"[gather] {args.workload} long-row arcs, caller ids: {rate_c / 1e9:7.1f} G gathers/s")
     ctx.close()
     print(json.dumps({"gather_ceiling": [{"stream": r[0], "gathers": r[1], "gathers_per_s": r[2]} for r in rows],
                       "workload": args.workload}), flush=True)

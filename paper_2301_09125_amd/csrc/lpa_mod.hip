@@ -21,6 +21,10 @@
 
 namespace lpa {
 
+// Grid cap of the row and item loops (grid stride): 16 blocks per CU on a
+// 256-CU chip, whole rounds of blocks at the 7 to 8 that fit per CU.
+constexpr unsigned kModGrid = 4096;
+
 constexpr uint32_t kModSlots = 1024;
 constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
 
@@ -330,22 +334,22 @@ hipError_t launch_mod_rows(const ModArgs &a, uint32_t lo, uint32_t cnt, int per_
     if (cnt == 0) return hipSuccess;
     if (a.labels_prev) {
         if (per_wave)
-            mod_delta_wave_k<<<grid_for(cnt, 4, 2048), 256, 0, s>>>(a, lo, cnt);
+            mod_delta_wave_k<<<grid_for(cnt, 4, kModGrid), 256, 0, s>>>(a, lo, cnt);
         else
-            mod_delta_thread_k<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(a, lo, cnt);
+            mod_delta_thread_k<<<grid_for(cnt, 256, kModGrid), 256, 0, s>>>(a, lo, cnt);
     } else if (per_wave) {
-        mod_wave_k<<<grid_for(cnt, 4, 2048), 256, 0, s>>>(a, lo, cnt);
+        mod_wave_k<<<grid_for(cnt, 4, kModGrid), 256, 0, s>>>(a, lo, cnt);
     } else {
-        mod_thread_k<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(a, lo, cnt);
+        mod_thread_k<<<grid_for(cnt, 256, kModGrid), 256, 0, s>>>(a, lo, cnt);
     }
     return hipGetLastError();
 }
 hipError_t launch_mod_hub(const ModArgs &a, const HubItem *items, uint32_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
     if (a.labels_prev)
-        mod_delta_hub_k<<<grid_for(count, 4, 2048), 256, 0, s>>>(a, items, count);
+        mod_delta_hub_k<<<grid_for(count, 4, kModGrid), 256, 0, s>>>(a, items, count);
     else
-        mod_hub_k<<<grid_for(count, 4, 2048), 256, 0, s>>>(a, items, count);
+        mod_hub_k<<<grid_for(count, 4, kModGrid), 256, 0, s>>>(a, items, count);
     return hipGetLastError();
 }
 hipError_t launch_mod_sumsq(const u64 *K, uint32_t n, u64 *partials, uint32_t nparts, hipStream_t s) {

@@ -377,7 +377,12 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
     // row_ptr, own label read, new label write (rows of a list: unknown here)
     const uint64_t ab = weighted ? 12 : 8;
     const Bins &B = P.bins;
-    const int cap = c->num_cu * 8;
+    // The vote kernels loop over their rows or items with a grid stride, so
+    // each block gets the same share of the work.  A grid of a few times the
+    // blocks that fit at once (4 to 8 per CU here, by LDS and registers)
+    // finishes in whole rounds of blocks; a grid just above one round (5 per
+    // CU where 4 fit) leaves most of the chip idle while the last blocks run.
+    const int cap = c->num_cu * 16;
     const bool rest = ra.skip_distinct != 0;  // round 1 after the relabel pass voted the distinct rows
     auto bytes = [&](int b) { return (lists || rest) ? 0ull : ab * B.arcs[b] + 16ull * B.cnt[b]; };
     auto args = [&](int b) {
@@ -399,13 +404,13 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
         return launch_vote_wave(args(BIN_WAVE), B.lo[BIN_WAVE], B.cnt[BIN_WAVE], 0, first, feat, cap, s);
     }));
     LPA_TRY(timed(c, kid(K_WIDE), bytes(BIN_WIDE), B.arcs[BIN_WIDE], [&] {
-        return launch_vote_wave(args(BIN_WIDE), B.lo[BIN_WIDE], B.cnt[BIN_WIDE], 1, first, feat, c->num_cu * 5, s);
+        return launch_vote_wave(args(BIN_WIDE), B.lo[BIN_WIDE], B.cnt[BIN_WIDE], 1, first, feat, cap, s);
     }));
     if (P.H) {
         const uint32_t *mrows = c->mrows.as<uint32_t>();
         LPA_TRY(timed(c, (first && rest) ? K_HUB1 : K_HUB, bytes(BIN_HUB), B.arcs[BIN_HUB], [&] {
             return launch_vote_hub(ra, c->items.as<HubItem>(), P.n_items, hs, first, ra.skip_distinct ? 1 : 0,
-                                   c->num_cu * 5, s);
+                                   cap, s);
         }));
         LPA_TRY(timed(c, K_MERGE, 0, 0, [&] {
             hipError_t e = launch_hub_merge(ra, hs, mrows, P.n_mwave, 0, first, s);
@@ -413,7 +418,7 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
             return e;
         }));
         LPA_TRY(timed(c, K_FALLBACK, 0, 0, [&] {
-            return launch_hub_fallback(ra, c->items.as<HubItem>(), P.n_items, hs, c->num_cu * 5, s);
+            return launch_hub_fallback(ra, c->items.as<HubItem>(), P.n_items, hs, cap, s);
         }));
         LPA_TRY(timed(c, K_REDUCE, 0, 0, [&] {
             return launch_hub_reduce(hs, c->ritems.as<ReduceItem>(), P.n_ritems, s);
