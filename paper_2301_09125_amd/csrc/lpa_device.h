@@ -184,6 +184,29 @@ __device__ __forceinline__ void block_counts(u64 chg, u64 ins, u64 *changed, u64
         block_count(chg, changed);
 }
 
+// block_counts with the per-wavefront partials in LDS the caller provides:
+// `mine` is this wavefront's own slice of a table it no longer uses (the
+// slices of wavefronts 0..3 lie `stride` words apart, wavefront 0's first),
+// so no barrier is needed before the write.
+__device__ __forceinline__ void block_counts_at(u64 *mine, uint32_t stride, u64 chg, u64 ins, u64 *changed,
+                                                u64 *insum) {
+    chg = wave_sum(chg);
+    if (insum) ins = wave_sum(ins);
+    if ((threadIdx.x & 63) == 0) {
+        mine[0] = chg;
+        mine[1] = ins;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const u64 *p = mine;  // thread 0 is in wavefront 0
+        const u64 s1 = p[0] + p[stride] + p[2 * stride] + p[3 * stride];
+        const u64 s2 = p[1] + p[stride + 1] + p[2 * stride + 1] + p[3 * stride + 1];
+        const uint32_t k = (blockIdx.x % kCountSlots) * kCountStride;
+        if (s1) atomicAdd(&changed[k], s1);
+        if (insum && s2) atomicAdd(&insum[k], s2);
+    }
+}
+
 // Block-wide reductions for 256 threads (4 wavefronts).
 struct BlockRed {
     u64 mx[4];

@@ -280,21 +280,23 @@ hipError_t launch_scatter_labels(uint32_t *labels_out, const uint32_t *old_of, c
                                  hipStream_t s);
 
 // ---- launchers: lpa_vote.hip ---------------------------------------------
-// first = 1: round 1 from the unique initial labels L0(v) = v.
-hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int grid_cap,
+// first = 1: round 1 from the unique initial labels L0(v) = v.  num_cu: the
+// device's compute units; grid-stride kernels get whole rounds of the blocks
+// that fit on them at once.
+hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int num_cu,
                               hipStream_t s);
-hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int grid_cap,
+hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int num_cu,
                              hipStream_t s);
 hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int feat,
-                            int grid_cap, hipStream_t s);
+                            int num_cu, hipStream_t s);
 hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
-                           int first, int fused, int grid_cap, hipStream_t s);
+                           int first, int fused, int num_cu, hipStream_t s);
 // Merge the top-K reports of each listed row; undecided rows get HUB_FALLBACK.
 hipError_t launch_hub_merge(const RoundArgs &a, const HubState &hs, const uint32_t *rows, uint32_t count,
                             int per_block, int first, hipStream_t s);
 // Slab merge of the segments of HUB_FALLBACK rows.
 hipError_t launch_hub_fallback(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
-                               int grid_cap, hipStream_t s);
+                               int num_cu, hipStream_t s);
 hipError_t launch_hub_reduce(const HubState &hs, const ReduceItem *items, uint32_t count, hipStream_t s);
 // Winner of the rows decided by best[] (direct, slab) and per-round reset.
 hipError_t launch_hub_final(const RoundArgs &a, const HubState &hs, uint32_t count, int first, hipStream_t s);

@@ -377,12 +377,7 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
     // row_ptr, own label read, new label write (rows of a list: unknown here)
     const uint64_t ab = weighted ? 12 : 8;
     const Bins &B = P.bins;
-    // The vote kernels loop over their rows or items with a grid stride, so
-    // each block gets the same share of the work.  A grid of a few times the
-    // blocks that fit at once (4 to 8 per CU here, by LDS and registers)
-    // finishes in whole rounds of blocks; a grid just above one round (5 per
-    // CU where 4 fit) leaves most of the chip idle while the last blocks run.
-    const int cap = c->num_cu * 16;
+    const int cap = c->num_cu;  // the launchers size grids from it
     const bool rest = ra.skip_distinct != 0;  // round 1 after the relabel pass voted the distinct rows
     auto bytes = [&](int b) { return (lists || rest) ? 0ull : ab * B.arcs[b] + 16ull * B.cnt[b]; };
     auto args = [&](int b) {

@@ -366,30 +366,60 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
             wt[j] = nwt[j];
         }
     }
-    block_counts(lane == 0 ? wchg : 0, ins, a.changed, a.insum);
+    // the partials go through this wavefront's own table (no longer in use):
+    // a separate LDS array would push a 1024-slot block past the 32 KB that
+    // lets five blocks share a CU
+    block_counts_at(T, SLOTS, lane == 0 ? wchg : 0, ins, a.changed, a.insum);
 }
 
-hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int, int feat, int grid_cap,
+// Blocks of 256 threads of kernel K that one CU holds at once, as its
+// registers and LDS allow (queried once per kernel).
+template <auto K>
+static unsigned resident_per_cu() {
+    static const unsigned nb = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, K, 256, 0) != hipSuccess || n < 1) n = 1;
+        return (unsigned)n;
+    }();
+    return nb;
+}
+
+// Grid of a grid-stride launch of K over `units` work units, `per_block` per
+// block: at most kStrideRounds whole rounds of the blocks that fit at once.
+// Every block gets the same share, so a grid just above one round (5 blocks
+// per CU where 4 fit) would leave most of the chip idle while its last
+// blocks run.
+constexpr unsigned kStrideRounds = 4;
+template <auto K>
+static unsigned stride_grid(uint64_t units, unsigned per_block, int num_cu) {
+    return grid_for(units, per_block, resident_per_cu<K>() * (unsigned)(num_cu > 0 ? num_cu : 1) * kStrideRounds);
+}
+
+template <bool FEAT>
+static void launch_thread_t(const RoundArgs &a, uint32_t lo, uint32_t cnt, int num_cu, hipStream_t s) {
+    constexpr auto K = vote_thread_k<FEAT>;
+    K<<<stride_grid<K>(cnt, 256, num_cu), 256, 0, s>>>(a, lo, cnt);
+}
+hipError_t launch_vote_thread(const RoundArgs &a, uint32_t lo, uint32_t cnt, int, int feat, int num_cu,
                               hipStream_t s) {
     if (cnt == 0) return hipSuccess;
-    const unsigned g = grid_for(cnt, 256, grid_cap);
-    if (feat)
-        vote_thread_k<true><<<g, 256, 0, s>>>(a, lo, cnt);
-    else
-        vote_thread_k<false><<<g, 256, 0, s>>>(a, lo, cnt);
+    feat ? launch_thread_t<true>(a, lo, cnt, num_cu, s) : launch_thread_t<false>(a, lo, cnt, num_cu, s);
     return hipGetLastError();
 }
-hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int grid_cap,
+template <bool FIRST, bool FEAT>
+static void launch_group_t(const RoundArgs &a, uint32_t lo, uint32_t cnt, int num_cu, hipStream_t s) {
+    constexpr int GL = kGroupLanes, GS = kGroupSlots;
+    constexpr auto K = vote_group_k<GL, GS, FIRST, FEAT>;
+    K<<<stride_grid<K>(cnt, 256 / GL, num_cu), 256, 0, s>>>(a, lo, cnt);
+}
+hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int first, int feat, int num_cu,
                              hipStream_t s) {
     if (cnt == 0) return hipSuccess;
-    const unsigned g = grid_for(cnt, 256 / kGroupLanes, grid_cap);
-    constexpr int GL = kGroupLanes, GS = kGroupSlots;
     if (first)
-        feat ? vote_group_k<GL, GS, true, true><<<g, 256, 0, s>>>(a, lo, cnt)
-             : vote_group_k<GL, GS, true, false><<<g, 256, 0, s>>>(a, lo, cnt);
+        feat ? launch_group_t<true, true>(a, lo, cnt, num_cu, s) : launch_group_t<true, false>(a, lo, cnt, num_cu, s);
     else
-        feat ? vote_group_k<GL, GS, false, true><<<g, 256, 0, s>>>(a, lo, cnt)
-             : vote_group_k<GL, GS, false, false><<<g, 256, 0, s>>>(a, lo, cnt);
+        feat ? launch_group_t<false, true>(a, lo, cnt, num_cu, s)
+             : launch_group_t<false, false>(a, lo, cnt, num_cu, s);
     return hipGetLastError();
 }
 
@@ -399,26 +429,29 @@ hipError_t launch_vote_group(const RoundArgs &a, uint32_t lo, uint32_t cnt, int 
 // round 1 keeps the wavefront kernel, which skips the rows the relabel pass
 // already voted without loading them.
 template <bool FIRST, bool FEAT>
-static void launch_wave_t(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, unsigned g, hipStream_t s) {
+static void launch_wave_t(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int num_cu, hipStream_t s) {
     constexpr int AS = kWaveArcsSmall / 64, AW = kWaveArcs / 64;
     static_assert(kWaveSlotsSmall / (2 * 32) * 32 == kWaveArcsSmall, "32-lane groups hold a whole row");
+    constexpr auto KW = vote_wave_k<FIRST, FEAT, AW, kWaveSlots>;
+    constexpr auto KS = vote_wave_k<FIRST, FEAT, AS, kWaveSlotsSmall>;
+    constexpr auto KG = vote_group_k<32, kWaveSlotsSmall, FIRST, FEAT>;
     if (wide)
-        vote_wave_k<FIRST, FEAT, AW, kWaveSlots><<<g, 256, 0, s>>>(a, lo, cnt);
+        KW<<<stride_grid<KW>(cnt, 4, num_cu), 256, 0, s>>>(a, lo, cnt);
     else if (FIRST)
-        vote_wave_k<FIRST, FEAT, AS, kWaveSlotsSmall><<<g, 256, 0, s>>>(a, lo, cnt);
+        KS<<<stride_grid<KS>(cnt, 4, num_cu), 256, 0, s>>>(a, lo, cnt);
     else
-        vote_group_k<32, kWaveSlotsSmall, FIRST, FEAT><<<(g + 1) / 2, 256, 0, s>>>(a, lo, cnt);
+        KG<<<stride_grid<KG>(cnt, 8, num_cu), 256, 0, s>>>(a, lo, cnt);
 }
 
 hipError_t launch_vote_wave(const RoundArgs &a, uint32_t lo, uint32_t cnt, int wide, int first, int feat,
-                            int grid_cap, hipStream_t s) {
+                            int num_cu, hipStream_t s) {
     if (cnt == 0) return hipSuccess;
-    const unsigned g = grid_for(cnt, 4, grid_cap);
     if (first)
-        feat ? launch_wave_t<true, true>(a, lo, cnt, wide, g, s) : launch_wave_t<true, false>(a, lo, cnt, wide, g, s);
+        feat ? launch_wave_t<true, true>(a, lo, cnt, wide, num_cu, s)
+             : launch_wave_t<true, false>(a, lo, cnt, wide, num_cu, s);
     else
-        feat ? launch_wave_t<false, true>(a, lo, cnt, wide, g, s)
-             : launch_wave_t<false, false>(a, lo, cnt, wide, g, s);
+        feat ? launch_wave_t<false, true>(a, lo, cnt, wide, num_cu, s)
+             : launch_wave_t<false, false>(a, lo, cnt, wide, num_cu, s);
     return hipGetLastError();
 }
 
@@ -926,22 +959,25 @@ __global__ __launch_bounds__(256) void hub_final_k(RoundArgs a, HubState hs, uin
     block_counts(lane == 0 ? wchg : 0, ins, a.changed, a.insum);
 }
 
+template <bool FIRST, bool W>
+static void launch_hub_t(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs, int num_cu,
+                         hipStream_t s) {
+    constexpr auto K = vote_hub_k<FIRST, W>;
+    K<<<stride_grid<K>(count, 4, num_cu), 256, 0, s>>>(a, items, count, hs);
+}
 hipError_t launch_vote_hub(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
-                           int first, int fused, int grid_cap, hipStream_t s) {
+                           int first, int fused, int num_cu, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    const unsigned g = grid_for(count, 4, grid_cap);
+    const bool w = a.g.w != nullptr;
     if (first) {
         // fused: the relabel pass already gathered the direct rows' partials
-        if (!fused) vote_hub_direct_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hs);
-        if (a.g.w)
-            vote_hub_k<true, true><<<g, 256, 0, s>>>(a, items, count, hs);
-        else
-            vote_hub_k<true, false><<<g, 256, 0, s>>>(a, items, count, hs);
+        if (!fused)
+            vote_hub_direct_k<<<stride_grid<vote_hub_direct_k>(count, 4, num_cu), 256, 0, s>>>(a, items, count, hs);
+        w ? launch_hub_t<true, true>(a, items, count, hs, num_cu, s)
+          : launch_hub_t<true, false>(a, items, count, hs, num_cu, s);
     } else {
-        if (a.g.w)
-            vote_hub_k<false, true><<<g, 256, 0, s>>>(a, items, count, hs);
-        else
-            vote_hub_k<false, false><<<g, 256, 0, s>>>(a, items, count, hs);
+        w ? launch_hub_t<false, true>(a, items, count, hs, num_cu, s)
+          : launch_hub_t<false, false>(a, items, count, hs, num_cu, s);
     }
     return hipGetLastError();
 }
@@ -955,9 +991,9 @@ hipError_t launch_hub_merge(const RoundArgs &a, const HubState &hs, const uint32
     return hipGetLastError();
 }
 hipError_t launch_hub_fallback(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
-                               int grid_cap, hipStream_t s) {
+                               int num_cu, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    hub_fallback_k<<<grid_for(count, 4, grid_cap), 256, 0, s>>>(a, items, count, hs);
+    hub_fallback_k<<<stride_grid<hub_fallback_k>(count, 4, num_cu), 256, 0, s>>>(a, items, count, hs);
     return hipGetLastError();
 }
 hipError_t launch_hub_reduce(const HubState &hs, const ReduceItem *items, uint32_t count, hipStream_t s) {
