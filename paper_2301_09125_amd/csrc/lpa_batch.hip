@@ -36,13 +36,17 @@ constexpr int kBatchWaves = kBatchThreads / 64;
 // rows per work unit of each bin
 __device__ __forceinline__ uint32_t unit_rows(int b) { return b == BIN_THREAD ? 64u : (b == BIN_GROUP ? 4u : 1u); }
 
-// Grid-wide barrier over `nblocks` co-resident blocks.
+// Grid-wide barrier over `nblocks` co-resident blocks.  The waiting blocks
+// poll the generation word with relaxed loads and acquire once, after it
+// moved: an acquiring load at device scope also invalidates the L2 of the
+// CU's die, so polling with it would keep evicting the labels of the blocks
+// that are still voting.
 __device__ __forceinline__ bool grid_barrier(const BatchArgs &b, uint32_t nblocks) {
     __shared__ int failed;
     __syncthreads();
     if (threadIdx.x == 0) {
         failed = 0;
-        const uint32_t gen = __hip_atomic_load(&b.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t gen = __hip_atomic_load(&b.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         const uint32_t arrived = atomicAdd(&b.bar[0], 1u) + 1;
         if (arrived == nblocks) {
@@ -51,7 +55,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs &b, uint32_t nblock
             __hip_atomic_fetch_add(&b.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&b.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(&b.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > b.timeout_ticks) {
                     atomicOr(b.err, ERR_TIMEOUT);
@@ -337,16 +341,32 @@ __device__ void run_units(const BatchArgs &b, const RoundArgs &a, u64 *T, int bi
     if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
 }
 
-// Units of bin `bin` assigned to wavefront w this round.
+// The segment (graph) that holds unit i of a bin: the largest g with
+// pref[g] <= i, for non-decreasing pref with pref[0] = 0 <= i < pref[G].
+__device__ __forceinline__ uint32_t segment_of_unit(const uint32_t *pref, uint32_t G, uint32_t i) {
+    uint32_t lo = 0, hi = G;  // pref[lo] <= i < pref[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (pref[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Units of bin `bin` assigned to wavefront w this round; g0 is the segment
+// that holds the first of them.
 template <int SLOTS>
-__device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t w, bool round1) {
+__device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t w, uint32_t g0,
+                        bool round1) {
     const uint32_t *pref = b.pref + (size_t)bin * (b.G + 1);
     const uint32_t total = pref[b.G];
     const uint32_t i0 = (uint32_t)((u64)w * total / b.nw);
     const uint32_t i1 = (uint32_t)((u64)(w + 1) * total / b.nw);
     if (i0 >= i1) return;
     const uint32_t R = unit_rows(bin);
-    uint32_t g = b.start[(size_t)bin * b.nw + w];
+    uint32_t g = g0;
     uint32_t p0 = pref[g], p1 = pref[g + 1];
     uint32_t lo = b.seg_lo[(size_t)bin * b.G + g], end = lo + b.seg_cnt[(size_t)bin * b.G + g];
     // one-lane and 16-lane rows: several units in flight per wavefront
@@ -379,67 +399,121 @@ __device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin,
 
 // Phase B, run by block 0 alone: tolerance tests of round t (none for
 // t = 0), then the per-bin prefix sums of the units of the graphs that go on
-// voting and every wavefront's first segment.
+// voting.  Each thread takes kDecideJ graphs per pass and issues all their
+// loads before it uses any (the data was written by other blocks, so every
+// load goes past this CU's caches).
+constexpr int kDecideJ = 4;
 __device__ void decide(const BatchArgs &b, uint32_t t) {
+    constexpr int J = kDecideJ;
     __shared__ uint32_t wsum[kBatchWaves][kBatchBins];
     __shared__ uint32_t carry[kBatchBins];
     __shared__ uint32_t n_on;
+    __shared__ u64 arcs_sum;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) n_on = 0;
+    const uint32_t G = b.G;
+    if (tid == 0) {
+        n_on = 0;
+        arcs_sum = 0;
+    }
     if (tid < kBatchBins) carry[tid] = 0;
     __syncthreads();
     uint32_t on = 0;
-    for (uint32_t g = tid; g < b.G; g += kBatchThreads) {
-        if (!b.active[g]) continue;
-        if (t == 0) {
-            ++on;
-            continue;
+    u64 arcs = 0;
+    for (uint32_t base = 0; base < G; base += J * kBatchThreads) {
+        uint32_t gg[J], act[J];
+        u64 ch[J], th[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            gg[j] = base + (uint32_t)j * kBatchThreads + tid;
+            const uint32_t gc = gg[j] < G ? gg[j] : 0u;  // index 0 exists: G >= 1
+            const uint32_t av = b.active[gc];
+            act[j] = gg[j] < G ? av : 0u;
+            ch[j] = b.changed[gc];
+            th[j] = b.thr[gc];
         }
-        const u64 ch = b.changed[g];
-        b.changed[g] = 0;
-        b.last[g] = ch;
-        b.iters[g] = t;
-        if (t <= b.hist_len) b.hist[(u64)g * b.hist_len + (t - 1)] = ch;
-        const bool ok = ch <= b.thr[g];
-        if (ok || t == b.max_iter) {
-            b.conv[g] = ok ? 1 : 0;
-            b.active[g] = 0;
-            atomicAdd(b.arcs, (u64)(b.orp[b.gv[g + 1]] - b.orp[b.gv[g]]) * t);
-        } else {
-            ++on;
+        uint32_t stop = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (!act[j]) continue;
+            if (t == 0) {
+                ++on;
+                continue;
+            }
+            const uint32_t g = gg[j];
+            b.changed[g] = 0;
+            b.last[g] = ch[j];
+            b.iters[g] = t;
+            if (t <= b.hist_len) b.hist[(u64)g * b.hist_len + (t - 1)] = ch[j];
+            const bool ok = ch[j] <= th[j];
+            if (ok || t == b.max_iter) {
+                b.conv[g] = ok ? 1 : 0;
+                b.active[g] = 0;
+                stop |= 1u << j;
+            } else {
+                ++on;
+            }
+        }
+        // arcs voted by the graphs that stopped: t rounds each
+        uint64_t v0[J], v1[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t gc = (stop >> j & 1u) ? gg[j] : 0u;
+            v0[j] = b.gv[gc];
+            v1[j] = b.gv[gc + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint64_t r0 = b.orp[v0[j]], r1 = b.orp[v1[j]];
+            if (stop >> j & 1u) arcs += (u64)(r1 - r0) * t;
         }
     }
     on = wave_sum(on);
+    arcs = wave_sum(arcs);
     if (lane == 0 && on) atomicAdd(&n_on, on);
+    if (lane == 0 && arcs) atomicAdd(&arcs_sum, arcs);
     __syncthreads();  // active[] of every graph is final
-    // exclusive prefix sums over graphs, kBatchThreads graphs per pass
-    for (uint32_t base = 0; base < b.G; base += kBatchThreads) {
-        const uint32_t g = base + tid;
-        uint32_t x[kBatchBins];
-        const bool live = g < b.G && b.active[g];
+    if (tid == 0 && arcs_sum) atomicAdd(b.arcs, arcs_sum);
+    // exclusive prefix sums over graphs: J consecutive graphs per thread,
+    // J * kBatchThreads per pass
+    for (uint32_t base = 0; base < G; base += J * kBatchThreads) {
+        const uint32_t g0 = base + tid * J;
+        uint32_t x[J][kBatchBins];
 #pragma unroll
-        for (int k = 0; k < kBatchBins; ++k) {
-            const uint32_t c = live ? b.seg_cnt[(size_t)k * b.G + g] : 0u;
-            x[k] = (c + unit_rows(k) - 1) / unit_rows(k);
+        for (int j = 0; j < J; ++j) {
+            const uint32_t g = g0 + j;
+            const uint32_t gc = g < G ? g : 0u;
+            const uint32_t av = b.active[gc];
+            const bool live = g < G && av;
+#pragma unroll
+            for (int k = 0; k < kBatchBins; ++k) {
+                const uint32_t c = b.seg_cnt[(size_t)k * G + gc];
+                x[j][k] = live ? (c + unit_rows(k) - 1) / unit_rows(k) : 0u;
+            }
         }
+        uint32_t ex[kBatchBins];
 #pragma unroll
         for (int k = 0; k < kBatchBins; ++k) {
-            uint32_t s = x[k];
+            uint32_t tot = 0;
+#pragma unroll
+            for (int j = 0; j < J; ++j) tot += x[j][k];
+            uint32_t s = tot;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 const uint32_t y = __shfl_up(s, off, 64);
                 if ((int)lane >= off) s += y;
             }
             if (lane == 63) wsum[wave][k] = s;
-            x[k] = s - x[k];  // exclusive within the wavefront
+            ex[k] = s - tot;  // exclusive within the wavefront
         }
         __syncthreads();
-        if (g < b.G) {
 #pragma unroll
-            for (int k = 0; k < kBatchBins; ++k) {
-                uint32_t off = carry[k];
-                for (uint32_t q = 0; q < wave; ++q) off += wsum[q][k];
-                b.pref[(size_t)k * (b.G + 1) + g] = off + x[k];
+        for (int k = 0; k < kBatchBins; ++k) {
+            uint32_t off = carry[k] + ex[k];
+            for (uint32_t q = 0; q < wave; ++q) off += wsum[q][k];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                if (g0 + j < G) b.pref[(size_t)k * (G + 1) + g0 + j] = off;
+                off += x[j][k];
             }
         }
         __syncthreads();
@@ -450,21 +524,7 @@ __device__ void decide(const BatchArgs &b, uint32_t t) {
         }
         __syncthreads();
     }
-    if (tid < kBatchBins) b.pref[(size_t)tid * (b.G + 1) + b.G] = carry[tid];
-    __syncthreads();
-    // wavefront w starts in the segment that holds unit floor(w * total / nw)
-    for (uint32_t g = tid; g < b.G; g += kBatchThreads) {
-#pragma unroll 1
-        for (int k = 0; k < kBatchBins; ++k) {
-            const uint32_t *pref = b.pref + (size_t)k * (b.G + 1);
-            const u64 total = carry[k];
-            const u64 p0 = pref[g], p1 = pref[g + 1];
-            if (p1 == p0) continue;
-            const u64 w0 = (p0 * b.nw + total - 1) / total;
-            const u64 w1 = (p1 * b.nw + total - 1) / total;
-            for (u64 w = w0; w < w1 && w < b.nw; ++w) b.start[(size_t)k * b.nw + w] = g;
-        }
-    }
+    if (tid < kBatchBins) b.pref[(size_t)tid * (G + 1) + G] = carry[tid];
     if (tid == 0) *b.n_active = n_on;
 }
 
@@ -497,7 +557,17 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
         a.skip_distinct = 0;
         a.insum = nullptr;
         const bool round1 = t == 1;
-        for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin) run_bin<SLOTS>(b, a, T, bin, w, round1);
+        // the segment of each bin's first unit of this wavefront: lane k
+        // searches bin k's prefix sums, all bins at once
+        uint32_t seg = 0;
+        if (lane < (uint32_t)kBatchBins) {
+            const uint32_t *pref = b.pref + (size_t)lane * (b.G + 1);
+            const uint32_t total = pref[b.G];
+            const uint32_t i0 = (uint32_t)((u64)w * total / b.nw);
+            if (i0 < total) seg = segment_of_unit(pref, b.G, i0);
+        }
+        for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin)
+            run_bin<SLOTS>(b, a, T, bin, w, (uint32_t)__builtin_amdgcn_readlane((int)seg, bin), round1);
         if (!grid_barrier(b, nblocks)) return;
         if (blockIdx.x == 0) decide(b, t);
         if (!grid_barrier(b, nblocks)) return;

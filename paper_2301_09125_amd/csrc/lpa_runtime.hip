@@ -1141,9 +1141,9 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         HIP_TRY(hipMemcpyAsync(L.thr, thr_h.data(), (size_t)G * 8, hipMemcpyHostToDevice, s));
         const size_t seg_words = (size_t)kBatchBins * G;
         const size_t pref_words = (size_t)kBatchBins * ((size_t)G + 1);
-        HIP_TRY(c->bseg.ensure((2 * seg_words + pref_words + (size_t)kBatchBins * nw) * sizeof(uint32_t)));
+        HIP_TRY(c->bseg.ensure((2 * seg_words + pref_words) * sizeof(uint32_t)));
         uint32_t *seg_lo = c->bseg.as<uint32_t>(), *seg_cnt = seg_lo + seg_words;
-        uint32_t *pref = seg_cnt + seg_words, *start = pref + pref_words;
+        uint32_t *pref = seg_cnt + seg_words;
         HIP_TRY(launch_batch_seg(c->gid.as<uint32_t>(), B, G, seg_lo, seg_cnt, s));
 
         BatchArgs b;
@@ -1183,7 +1183,6 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         b.seg_lo = seg_lo;
         b.seg_cnt = seg_cnt;
         b.pref = pref;
-        b.start = start;
         b.nw = nw;
         b.clock = L.clock;
         int rate_khz = 0;
