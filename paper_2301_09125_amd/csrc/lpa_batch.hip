@@ -355,16 +355,11 @@ __device__ __forceinline__ uint32_t segment_of_unit(const uint32_t *pref, uint32
     return lo;
 }
 
-// Units of bin `bin` assigned to wavefront w this round; g0 is the segment
-// that holds the first of them.
+// Units [i0, i1) of bin `bin`; g0 is the segment that holds unit i0.
 template <int SLOTS>
-__device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t w, uint32_t g0,
-                        bool round1) {
+__device__ void run_range(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t i0, uint32_t i1,
+                          uint32_t g0, bool round1) {
     const uint32_t *pref = b.pref + (size_t)bin * (b.G + 1);
-    const uint32_t total = pref[b.G];
-    const uint32_t i0 = (uint32_t)((u64)w * total / b.nw);
-    const uint32_t i1 = (uint32_t)((u64)(w + 1) * total / b.nw);
-    if (i0 >= i1) return;
     const uint32_t R = unit_rows(bin);
     uint32_t g = g0;
     uint32_t p0 = pref[g], p1 = pref[g + 1];
@@ -395,6 +390,32 @@ __device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin,
         wch += unit_wave<SLOTS>(b, a, T, v0, v0 - b.lo[BIN_HUB], g, bin == BIN_HUB, round1);
     }
     if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[g], (u64)wch);
+}
+
+// Units a wavefront takes at a time from its block's share of a bin: about
+// the same work per chunk (a one-lane unit is 64 rows, a group unit 4).
+__device__ __forceinline__ uint32_t chunk_units(int bin) {
+    return bin == BIN_GROUP ? 16u : (bin == BIN_WAVE ? 4u : (bin == BIN_WIDE ? 2u : 1u));
+}
+
+// The block's units of bin `bin` below `hi`, handed to its wavefronts a
+// chunk at a time from the LDS counter *next, so that the wavefronts the
+// SIMDs issue less often (the younger ones) do less of the work instead of
+// finishing last; g is the segment of the block's first unit.
+template <int SLOTS>
+__device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t hi, uint32_t g,
+                        uint32_t *next, bool round1) {
+    const uint32_t *pref = b.pref + (size_t)bin * (b.G + 1);
+    const uint32_t CH = chunk_units(bin);
+    for (;;) {
+        uint32_t i0 = 0;
+        if ((threadIdx.x & 63) == 0) i0 = atomicAdd(next, CH);
+        i0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)i0, 0, 64));
+        if (i0 >= hi) break;
+        const uint32_t i1 = i0 + CH < hi ? i0 + CH : hi;
+        while (pref[g + 1] <= i0) ++g;  // a wavefront's chunks only move forward
+        run_range<SLOTS>(b, a, T, bin, i0, i1, g, round1);
+    }
 }
 
 // Phase B, run by block 0 alone: tolerance tests of round t (none for
@@ -531,12 +552,12 @@ __device__ void decide(const BatchArgs &b, uint32_t t) {
 template <int SLOTS>
 __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t nblocks) {
     __shared__ u64 table[kBatchWaves * SLOTS];
+    __shared__ uint32_t next_unit[kBatchBins];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 *T = table + wave * SLOTS;
     for (uint32_t s = lane; s < SLOTS; s += 64) T[s] = EMPTY_SLOT;
     wave_sync();
-    const uint32_t w = blockIdx.x * kBatchWaves + wave;
     if (blockIdx.x == 0 && threadIdx.x == 0) b.clock[0] = wall_clock64();
     // the work split of round 1: every graph votes
     if (blockIdx.x == 0) decide(b, 0);
@@ -557,17 +578,21 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
         a.skip_distinct = 0;
         a.insum = nullptr;
         const bool round1 = t == 1;
-        // the segment of each bin's first unit of this wavefront: lane k
-        // searches bin k's prefix sums, all bins at once
-        uint32_t seg = 0;
+        // this block's share of every bin, [lo, hi), and the segment of its
+        // first unit: lane k of each wavefront works out bin k
+        uint32_t seg = 0, lo = 0, hi = 0;
         if (lane < (uint32_t)kBatchBins) {
             const uint32_t *pref = b.pref + (size_t)lane * (b.G + 1);
             const uint32_t total = pref[b.G];
-            const uint32_t i0 = (uint32_t)((u64)w * total / b.nw);
-            if (i0 < total) seg = segment_of_unit(pref, b.G, i0);
+            lo = (uint32_t)((u64)blockIdx.x * total / nblocks);
+            hi = (uint32_t)((u64)(blockIdx.x + 1) * total / nblocks);
+            if (lo < hi) seg = segment_of_unit(pref, b.G, lo);
         }
+        if (wave == 0 && lane < (uint32_t)kBatchBins) next_unit[lane] = lo;
+        __syncthreads();
         for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin)
-            run_bin<SLOTS>(b, a, T, bin, w, (uint32_t)__builtin_amdgcn_readlane((int)seg, bin), round1);
+            run_bin<SLOTS>(b, a, T, bin, (uint32_t)__builtin_amdgcn_readlane((int)hi, bin),
+                           (uint32_t)__builtin_amdgcn_readlane((int)seg, bin), &next_unit[bin], round1);
         if (!grid_barrier(b, nblocks)) return;
         if (blockIdx.x == 0) decide(b, t);
         if (!grid_barrier(b, nblocks)) return;
