@@ -151,52 +151,48 @@ __global__ __launch_bounds__(256) void bin_count_k(Graph g, BinCfg cfg, uint32_t
     }
 }
 
-// One 1024-thread block: per-block vertex and arc counts -> exclusive global
-// offsets (in place) of the internal layout, bins back to back in bin order.
+// Exclusive prefix sums of the per-block bin counts and arc counts, bin-major
+// (every block of bin 0, then bin 1, ...), in one block of 1024 threads.
+// Wavefront w owns a contiguous run of whole 64-entry chunks and reads it
+// coalesced, kScanJ chunks per step with their loads issued together (the
+// counts were written by other CUs, so each load goes to the memory side);
+// pass 1 sums each wavefront's run, pass 2 scans it chunk by chunk from the
+// wavefront's offset.
+constexpr int kScanJ = 8;
 __global__ __launch_bounds__(1024) void bin_scan_k(uint32_t *blk_counts, u64 *blk_arcs, uint32_t nblk,
                                                    uint32_t *totals, u64 *arc_totals) {
     __shared__ uint32_t wtot[16][NBINS];
     __shared__ u64 watot[16][NBINS];
     const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const uint32_t per = (nblk + 1023) / 1024;
-    const uint32_t lo = min(t * per, nblk), hi = min(lo + per, nblk);
-    uint32_t s[NBINS], incl[NBINS];
-    u64 as[NBINS], aincl[NBINS];
-#pragma unroll
+    const uint32_t chunks = (nblk + 63) / 64;
+    const uint32_t cpw = (chunks + 15) / 16;
+    const uint32_t lo = min(wave * cpw * 64, nblk), hi = min(lo + cpw * 64, nblk);
+#pragma unroll 1
     for (int b = 0; b < NBINS; ++b) {
-        s[b] = 0;
-        as[b] = 0;
-        // 16 loads in flight at a time (a plain loop waits for each one)
-        for (uint32_t i0 = lo; i0 < hi; i0 += 16) {
-            uint32_t xs[16];
-            u64 ys[16];
+        const uint32_t *cnt = blk_counts + (size_t)b * nblk;
+        const u64 *arc = blk_arcs + (size_t)b * nblk;
+        uint32_t x = 0;
+        u64 y = 0;
+        for (uint32_t i0 = lo; i0 < hi; i0 += 64 * kScanJ) {
+            uint32_t xs[kScanJ];
+            u64 ys[kScanJ];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const uint32_t i = i0 + j < hi ? i0 + j : lo;
-                xs[j] = blk_counts[(size_t)b * nblk + i];
-                ys[j] = blk_arcs[(size_t)b * nblk + i];
+            for (int j = 0; j < kScanJ; ++j) {
+                const uint32_t i = i0 + 64u * j + lane;
+                const uint32_t ic = i < hi ? i : lo;  // lo < hi here: an entry of this run
+                xs[j] = cnt[ic];
+                ys[j] = arc[ic];
             }
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (i0 + j < hi) {
-                    s[b] += xs[j];
-                    as[b] += ys[j];
+            for (int j = 0; j < kScanJ; ++j)
+                if (i0 + 64u * j + lane < hi) {
+                    x += xs[j];
+                    y += ys[j];
                 }
         }
-        uint32_t x = s[b];
-        u64 y = as[b];
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t xs = __shfl_up(x, off, 64);
-            const u64 ys = __shfl_up(y, off, 64);
-            if ((int)lane >= off) {
-                x += xs;
-                y += ys;
-            }
-        }
-        incl[b] = x;
-        aincl[b] = y;
-        if (lane == 63) {
+        x = wave_sum(x);
+        y = wave_sum(y);
+        if (lane == 0) {
             wtot[wave][b] = x;
             watot[wave][b] = y;
         }
@@ -204,37 +200,53 @@ __global__ __launch_bounds__(1024) void bin_scan_k(uint32_t *blk_counts, u64 *bl
     __syncthreads();
     uint32_t base = 0;
     u64 abase = 0;
-#pragma unroll
+#pragma unroll 1
     for (int b = 0; b < NBINS; ++b) {
-        uint32_t before = 0, total = 0;
-        u64 abefore = 0, atotal = 0;
+        uint32_t run = base, total = 0;
+        u64 arun = abase, atotal = 0;
         for (uint32_t w = 0; w < 16; ++w) {
             if (w < wave) {
-                before += wtot[w][b];
-                abefore += watot[w][b];
+                run += wtot[w][b];
+                arun += watot[w][b];
             }
             total += wtot[w][b];
             atotal += watot[w][b];
         }
-        uint32_t run = base + before + incl[b] - s[b];
-        u64 arun = abase + abefore + aincl[b] - as[b];
-        for (uint32_t i0 = lo; i0 < hi; i0 += 16) {
-            uint32_t xs[16];
-            u64 ys[16];
+        uint32_t *cnt = blk_counts + (size_t)b * nblk;
+        u64 *arc = blk_arcs + (size_t)b * nblk;
+        for (uint32_t i0 = lo; i0 < hi; i0 += 64 * kScanJ) {
+            uint32_t xs[kScanJ];
+            u64 ys[kScanJ];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const uint32_t i = i0 + j < hi ? i0 + j : lo;
-                xs[j] = blk_counts[(size_t)b * nblk + i];
-                ys[j] = blk_arcs[(size_t)b * nblk + i];
+            for (int j = 0; j < kScanJ; ++j) {
+                const uint32_t i = i0 + 64u * j + lane;
+                const uint32_t ic = i < hi ? i : lo;
+                const uint32_t xv = cnt[ic];
+                const u64 yv = arc[ic];
+                xs[j] = i < hi ? xv : 0u;
+                ys[j] = i < hi ? yv : 0ull;
             }
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (i0 + j < hi) {
-                    blk_counts[(size_t)b * nblk + i0 + j] = run;
-                    blk_arcs[(size_t)b * nblk + i0 + j] = arun;
-                    run += xs[j];
-                    arun += ys[j];
+            for (int j = 0; j < kScanJ; ++j) {
+                uint32_t xi = xs[j];
+                u64 yi = ys[j];
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t xu = __shfl_up(xi, off, 64);
+                    const u64 yu = __shfl_up(yi, off, 64);
+                    if ((int)lane >= off) {
+                        xi += xu;
+                        yi += yu;
+                    }
                 }
+                const uint32_t i = i0 + 64u * j + lane;
+                if (i < hi) {
+                    cnt[i] = run + xi - xs[j];
+                    arc[i] = arun + yi - ys[j];
+                }
+                run += (uint32_t)__shfl((int)xi, 63, 64);
+                arun += __shfl(yi, 63, 64);
+            }
         }
         if (t == 0) {
             totals[b] = total;

@@ -79,6 +79,18 @@ def test_tolerance_zero_graphs_stop_at_different_rounds(gg, orc, lpa, ctx):
     assert len(set(st.iterations.tolist())) > 1
 
 
+def test_many_small_graphs_per_block(gg, orc, lpa, ctx):
+    # more graphs than blocks: a block's share of a bin spans many graphs, and
+    # its wavefronts' chunks start and end inside them
+    b = gg.sbm_batch(G=2500, n_min=50, n_max=120, seed=21)
+    say("[batch] sbm_batch G=2500", b.csr.n, b.csr.m)
+    lab, st = run_batch(lpa, ctx, b)
+    check_graphs(orc, b, lab, st, range(b.G), 0.05, 20)
+    rp = b.csr.row_ptr
+    arcs = sum(int(rp[b.gv[k + 1]] - rp[b.gv[k]]) * int(st.iterations[k]) for k in range(b.G))
+    assert st.arcs_processed == arcs
+
+
 def mixed_graphs(gg):
     """Graphs of every bin and the method's degenerate cases, local ids."""
     out = []
