@@ -202,31 +202,44 @@ __global__ __launch_bounds__(256) void mod_delta_thread_k(ModArgs a, uint32_t lo
     mod_finish(a, M, tw, d);
 }
 
-// Incremental form, one wavefront per row (rows of at most 512 arcs).
+// Incremental form, rows of at most 512 arcs, 64 rows per wavefront step:
+// a row whose label stayed (unit weights) only adds its degree, one lane
+// each; the other rows' arcs are read by the whole wavefront, one row after
+// another.
 __global__ __launch_bounds__(256) void mod_delta_wave_k(ModArgs a, uint32_t lo, uint32_t cnt) {
     __shared__ ModTable M;
     mod_table_init(M);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 tw = 0, d = 0;
-    for (uint32_t i = blockIdx.x * 4 + wave; i < cnt; i += gridDim.x * 4) {
-        const uint32_t v = lo + i;
+    for (uint32_t base = (blockIdx.x * 4 + wave) * 64; base < cnt; base += gridDim.x * 4 * 64) {
+        const uint32_t i = base + lane;
+        const bool act = i < cnt;
+        const uint32_t v = lo + (act ? i : 0u);  // row lo exists: cnt > 0
         const uint32_t lv = a.labels[v], pv = a.labels_prev[v];
         const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
-        u64 kv = 0;
-        if (lv == pv && !a.g.w) {
-            kv = lane == 0 ? e - b : 0;  // uniform over the wavefront
-        } else {
-            mod_delta_arcs<kWaveArcs / 64, 64>(a, b + lane, e, lv != pv, lv, pv, kv, d);
+        const bool quick = act && lv == pv && !a.g.w;
+        const u64 kq = quick ? (u64)(e - b) : 0ull;
+        tw += kq;
+        add_community(M, a.K, quick, lv, kq);
+        u64 slow = __ballot(act && !quick);
+        while (slow) {
+            const int j = __ffsll((long long)slow) - 1;
+            slow &= slow - 1;
+            const uint32_t lj = (uint32_t)__shfl((int)lv, j, 64), pj = (uint32_t)__shfl((int)pv, j, 64);
+            const uint64_t bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
+            u64 kv = 0;
+            mod_delta_arcs<kWaveArcs / 64, 64>(a, bj + lane, ej, lj != pj, lj, pj, kv, d);
+            kv = wave_sum(kv);
+            tw += lane == 0 ? kv : 0;
+            add_community(M, a.K, lane == 0, lj, kv);
         }
-        kv = wave_sum(kv);
-        tw += lane == 0 ? kv : 0;
-        add_community(M, a.K, lane == 0, lv, kv);
     }
     mod_finish(a, M, tw, d);
 }
 
-// Incremental form, one wavefront per segment of a long row.
+// Incremental form, segments of long rows, 64 segments per wavefront step
+// as above.
 __global__ __launch_bounds__(256) void mod_delta_hub_k(ModArgs a, const HubItem *__restrict__ items,
                                                        uint32_t count) {
     __shared__ ModTable M;
@@ -234,18 +247,27 @@ __global__ __launch_bounds__(256) void mod_delta_hub_k(ModArgs a, const HubItem 
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 tw = 0, d = 0;
-    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
-        const HubItem item = items[it];
+    for (uint32_t base = (blockIdx.x * 4 + wave) * 64; base < count; base += gridDim.x * 4 * 64) {
+        const uint32_t it = base + lane;
+        const bool act = it < count;
+        const HubItem item = items[act ? it : 0u];  // item 0 exists: count > 0
         const uint32_t lv = a.labels[item.r], pv = a.labels_prev[item.r];
-        u64 kv = 0;
-        if (lv == pv && !a.g.w) {
-            kv = lane == 0 ? item.b1 - item.b0 : 0;
-        } else {
-            mod_delta_arcs<kWaveArcs / 64, 64>(a, item.b0 + lane, item.b1, lv != pv, lv, pv, kv, d);
+        const bool quick = act && lv == pv && !a.g.w;
+        const u64 kq = quick ? (u64)(item.b1 - item.b0) : 0ull;
+        tw += kq;
+        add_community(M, a.K, quick, lv, kq);
+        u64 slow = __ballot(act && !quick);
+        while (slow) {
+            const int j = __ffsll((long long)slow) - 1;
+            slow &= slow - 1;
+            const uint32_t lj = (uint32_t)__shfl((int)lv, j, 64), pj = (uint32_t)__shfl((int)pv, j, 64);
+            const uint64_t bj = __shfl(item.b0, j, 64), ej = __shfl(item.b1, j, 64);
+            u64 kv = 0;
+            mod_delta_arcs<kWaveArcs / 64, 64>(a, bj + lane, ej, lj != pj, lj, pj, kv, d);
+            kv = wave_sum(kv);
+            tw += lane == 0 ? kv : 0;
+            add_community(M, a.K, lane == 0, lj, kv);
         }
-        kv = wave_sum(kv);
-        tw += lane == 0 ? kv : 0;
-        add_community(M, a.K, lane == 0, lv, kv);
     }
     mod_finish(a, M, tw, d);
 }
@@ -334,7 +356,7 @@ hipError_t launch_mod_rows(const ModArgs &a, uint32_t lo, uint32_t cnt, int per_
     if (cnt == 0) return hipSuccess;
     if (a.labels_prev) {
         if (per_wave)
-            mod_delta_wave_k<<<grid_for(cnt, 4, kModGrid), 256, 0, s>>>(a, lo, cnt);
+            mod_delta_wave_k<<<grid_for(cnt, 256, kModGrid), 256, 0, s>>>(a, lo, cnt);
         else
             mod_delta_thread_k<<<grid_for(cnt, 256, kModGrid), 256, 0, s>>>(a, lo, cnt);
     } else if (per_wave) {
@@ -347,7 +369,7 @@ hipError_t launch_mod_rows(const ModArgs &a, uint32_t lo, uint32_t cnt, int per_
 hipError_t launch_mod_hub(const ModArgs &a, const HubItem *items, uint32_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
     if (a.labels_prev)
-        mod_delta_hub_k<<<grid_for(count, 4, kModGrid), 256, 0, s>>>(a, items, count);
+        mod_delta_hub_k<<<grid_for(count, 256, kModGrid), 256, 0, s>>>(a, items, count);
     else
         mod_hub_k<<<grid_for(count, 4, kModGrid), 256, 0, s>>>(a, items, count);
     return hipGetLastError();
