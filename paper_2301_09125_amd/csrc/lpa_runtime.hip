@@ -455,14 +455,17 @@ lpa_status modularity_internal(lpa_ctx *c, const lpa_csr *g, const Plan &P, cons
         if (e == hipSuccess) e = launch_mod_sumsq(c->K.as<u64>(), n, c->partials.as<u64>(), nparts, s);
         return e;
     }));
-    std::vector<u64> parts(2 * nparts);
-    u64 sums[2];
-    uint32_t errbits = 0;
-    HIP_TRY(hipMemcpyAsync(parts.data(), c->partials.p, 2 * nparts * sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(sums, c->mod_sums.p, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&errbits, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // read back into pinned memory (no staging copy): the block partials,
+    // the two sums, the error word
+    LPA_TRY(ensure_pinned(c, 16 + 2 * (size_t)nparts + 2));
+    const uint64_t *parts = c->pinned + 16;
+    const uint64_t *sums = parts + 2 * nparts;
+    HIP_TRY(hipMemcpyAsync(c->pinned + 16, c->partials.p, 2 * nparts * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 16 + 2 * nparts, c->mod_sums.p, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (c->opt.profile) collect_profile(c);
+    const uint32_t errbits = reinterpret_cast<const uint32_t *>(c->pinned + 1)[0];
     if (errbits) return err_status(errbits);
     unsigned __int128 sk2 = 0;
     for (uint32_t i = 0; i < nparts; ++i)
@@ -580,7 +583,8 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
                                    hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (c->opt.profile) collect_profile(c);
+        // (per-kernel timings are folded in after the run: between rounds
+        // the device waits for the host)
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
         ms_rounds += ms;
@@ -617,6 +621,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     } else {
         HIP_TRY(hipMemcpyAsync(c->pinned + 1, err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (c->opt.profile) collect_profile(c);
         const uint32_t errbits = reinterpret_cast<uint32_t *>(c->pinned + 1)[0];
         if (errbits) return err_status(errbits);
     }
