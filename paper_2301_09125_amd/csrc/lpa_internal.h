@@ -194,7 +194,6 @@ struct BatchArgs {
     const uint32_t *seg_lo;      // [kBatchBins * G]
     const uint32_t *seg_cnt;     // [kBatchBins * G]
     uint32_t *pref;              // [kBatchBins * (G+1)] units of voting graphs, prefix sums
-    uint32_t nw;                 // wavefronts of the launch
     uint64_t timeout_ticks;      // wall-clock ticks one barrier may wait
 };
 

@@ -1140,7 +1140,6 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         const uint64_t cap_blocks = (uint64_t)batch_blocks_per_cu(slots) * c->num_cu;
         const uint32_t nblocks =
             (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap_blocks, (units + wpb - 1) / wpb));
-        const uint32_t nw = nblocks * wpb;
         HIP_TRY(c->bstate.ensure(batch_layout(nullptr, G, hist_len).bytes));
         const BatchLayout L = batch_layout(c->bstate.p, G, hist_len);
         HIP_TRY(hipMemcpyAsync(L.thr, thr_h.data(), (size_t)G * 8, hipMemcpyHostToDevice, s));
@@ -1188,7 +1187,6 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         b.seg_lo = seg_lo;
         b.seg_cnt = seg_cnt;
         b.pref = pref;
-        b.nw = nw;
         b.clock = L.clock;
         int rate_khz = 0;
         HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
