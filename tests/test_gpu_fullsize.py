@@ -1,6 +1,6 @@
 """GPU parity at the full sizes of the benchmark workloads, in the launch
 configuration bench.py times (default options, tol 0.05, max 20 rounds,
-self weight 1): the planted-partition SBM, R-MAT scale 22 and the
+self weight 1): the planted-partition SBM, R-MAT scales 22 and 24 and the
 4096 x 4096 road lattice are each run in full by the oracle and compared
 bit-exactly (labels, per-round changed counts, iterations), and the
 modularity integer terms are compared exactly.  The batched run is
@@ -65,6 +65,16 @@ def test_rmat22_full(gg, orc, lpa, ctx):
     t = time.time()
     g = gg.rmat(22, 16, 0.57, 0.19, 0.19, seed=22)
     say(f"rmat22 generated in {time.time() - t:.1f}s: n={g.n} m={g.m}")
+    full_compare(gg, orc, lpa, ctx, g)
+
+
+@pytest.mark.timeout(1500)
+def test_rmat24_full(gg, orc, lpa, ctx):
+    # the scale-24 R-MAT graph of the learned-frontier comparison and of the
+    # bandwidth target: 16.8 M vertices, about 5.2e8 arcs
+    t = time.time()
+    g = gg.rmat(24, 16, 0.57, 0.19, 0.19, seed=24)
+    say(f"rmat24 generated in {time.time() - t:.1f}s: n={g.n} m={g.m}")
     full_compare(gg, orc, lpa, ctx, g)
 
 
