@@ -46,6 +46,10 @@ constexpr int kHubSlots = 1024;
 constexpr uint32_t kHubSpill = 900;
 static_assert(kHubSpill + 64 < (uint32_t)kHubSlots, "a capped table must never fill up");
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// Long rows relabelled by slices of the caller's id space (lpa_prep.hip).
+constexpr uint32_t kSliceShift = 20;     // 2^20 ids (4 MB of the id map) per slice
+constexpr uint32_t kSliceMin = 8;        // below 8 slices (32 MB) the direct gather is as fast
+constexpr uint16_t kSliceNone = 0xFFFF;  // bnd[0] of a segment that is not sorted
 constexpr int kDegBuckets = 24;  // row-length histogram of the autotuner
 
 // Long rows: each 512-arc segment reports its kTopK heaviest labels and a
@@ -268,10 +272,14 @@ hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uin
                                uint32_t *col2, uint32_t *w2, uint8_t *rowflag, uint32_t lo, uint32_t cnt,
                                uint32_t split, int bin_a, int bin_b, int per_wave, uint32_t *err,
                                const Round1Fuse *f, hipStream_t s);
+// Long rows are relabelled slice by slice of the caller's id space when
+// relabel_slices(n) > 0 (n large enough for the id map to outgrow L2): bnd
+// then holds count * (S + 1) u16 and isrc count u64 of scratch.
+uint32_t relabel_slices(uint32_t n);
 hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                               uint32_t *col2, uint32_t *w2, const HubItem *items, uint32_t count,
                               uint32_t *hub_flags, uint32_t *err, const Round1Fuse *f, const HubState *hs,
-                              uint32_t H, hipStream_t s);
+                              uint32_t H, uint16_t *bnd, uint64_t *isrc, hipStream_t s);
 hipError_t launch_init_labels(uint32_t *La, uint32_t *Lb, const uint32_t *old_of, const uint32_t *labels_in,
                               uint32_t n, hipStream_t s);
 hipError_t launch_scatter_labels(uint32_t *labels_out, const uint32_t *old_of, const uint32_t *L, uint32_t n_int,

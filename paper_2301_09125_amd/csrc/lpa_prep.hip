@@ -597,9 +597,16 @@ __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *
 // Every load is issued by every lane (lanes past the segment read its first
 // arc and are masked), so the 8 id lookups per lane are in flight together
 // instead of one after the other.
-template <int A = kWaveArcs / 64>
+//
+// SCAN (long rows copied slice by slice): the ids are not looked up here;
+// instead bnd[0..S] receive where each slice of the caller's id space starts
+// in the segment (bnd[S] = len), or bnd[0] = kSliceNone when the segment is
+// not sorted, and *src_out the segment's first arc in the caller's CSR.
+template <int A = kWaveArcs / 64, bool SCAN = false>
 __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32_t r, uint64_t b0, uint64_t len,
-                                                    u64 &best, u64 &own_w, uint32_t &own_hit, u64 &wsum) {
+                                                    u64 &best, u64 &own_w, uint32_t &own_hit, u64 &wsum,
+                                                    uint16_t *bnd = nullptr, uint32_t S = 0,
+                                                    uint64_t *src_out = nullptr) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t v = a.old_of[r];
     const uint64_t rs = a.g.rp[v];
@@ -634,7 +641,8 @@ __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32
     if (bad) atomicOr(a.err, ERR_COL);
     // strictly increasing: compare each arc with the one before it (the lane
     // below, or lane 63 of the previous column, or the arc before the segment)
-    uint32_t ok = 1;
+    uint32_t ok = 1, sorted_in = 1;
+    uint32_t prev[A];  // the arc before each one inside the segment (SCAN)
 #pragma unroll
     for (int j = 0; j < A; ++j) {
         const uint32_t up = __shfl_up(u[j], 1, 64);
@@ -643,18 +651,46 @@ __device__ __forceinline__ uint32_t relabel_segment(const RelabelArgs &a, uint32
         const uint64_t k = lane + 64ull * j;
         const bool has_prev = k > 0 || src > rs;
         if ((m >> j & 1u) && has_prev && !(pv < u[j])) ok = 0;
+        if ((m >> j & 1u) && k > 0 && pv > u[j]) sorted_in = 0;
+        prev[j] = pv;
     }
 #pragma unroll
     for (int j = 0; j < A; ++j) u[j] = u[j] >= a.g.n ? 0u : u[j];
-    uint32_t nid[A];
+    if (!SCAN) {
+        uint32_t nid[A];
 #pragma unroll
-    for (int j = 0; j < A; ++j) nid[j] = a.new_of[u[j]];
+        for (int j = 0; j < A; ++j) nid[j] = a.new_of[u[j]];
 #pragma unroll
-    for (int j = 0; j < A; ++j) {
-        const uint64_t k = lane + 64ull * j;
-        if (m >> j & 1u) {
-            a.col2[b0 + k] = nid[j];
-            if (a.w2) a.w2[b0 + k] = wv[j];
+        for (int j = 0; j < A; ++j) {
+            const uint64_t k = lane + 64ull * j;
+            if (m >> j & 1u) {
+                a.col2[b0 + k] = nid[j];
+                if (a.w2) a.w2[b0 + k] = wv[j];
+            }
+        }
+    } else {
+        if (a.w2) {
+#pragma unroll
+            for (int j = 0; j < A; ++j)
+                if (m >> j & 1u) a.w2[b0 + lane + 64ull * j] = wv[j];
+        }
+        if (lane == 0) *src_out = src;
+        if (__ballot(!sorted_in) == 0) {
+            // each slice's first arc: arc k opens the slices after its
+            // predecessor's up to its own; the last arc closes the rest
+#pragma unroll
+            for (int j = 0; j < A; ++j) {
+                const uint32_t k = lane + 64u * j;
+                if (!(m >> j & 1u)) continue;
+                const uint32_t sl = u[j] >> kSliceShift;
+                const uint32_t p = prev[j] < a.g.n ? prev[j] : 0u;
+                const uint32_t s0 = k ? (p >> kSliceShift) + 1 : 0u;
+                for (uint32_t s = s0; s <= sl && s <= S; ++s) bnd[s] = (uint16_t)k;
+                if (k + 1 == len)
+                    for (uint32_t s = sl + 1; s <= S; ++s) bnd[s] = (uint16_t)len;
+            }
+        } else if (lane == 0) {
+            bnd[0] = kSliceNone;
         }
     }
     if (a.L1) {
@@ -723,6 +759,124 @@ __global__ __launch_bounds__(256) void relabel_hub_k(RelabelArgs a, const HubIte
     }
 }
 
+// ---------------------------------------------- long rows, slice by slice --
+//
+// The long rows hold most arcs, and their relabel is a random 4-byte gather
+// into the n-entry id map (64 MB at 2^24 vertices), which runs at the memory
+// system's random-request rate.  Taken slice by slice of the caller's id
+// space (4 MB of the map per slice) the same gathers mostly hit L2: the scan pass
+// (relabel_segment in SCAN mode, one wavefront per 512-arc segment) checks
+// the segment, votes round 1 (whose labels are the caller's ids themselves)
+// and records where each slice starts in it, as the segment is sorted; then
+// one launch ordered slice-major copies each segment's arcs of one slice
+// (16 lanes per segment), and the blocks after the last slice copy the
+// segments that are not sorted the direct way.
+__global__ __launch_bounds__(256) void relabel_hub_scan_k(RelabelArgs a, const HubItem *__restrict__ items,
+                                                          uint32_t count, uint32_t *hub_flags, uint32_t S,
+                                                          uint16_t *bnd, uint64_t *isrc) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
+        const HubItem item = items[it];
+        u64 best = 0, own_w = 0, rs = 0;
+        uint32_t own_hit = 0;
+        const uint32_t ok = relabel_segment<kWaveArcs / 64, true>(a, item.r, item.b0, item.b1 - item.b0, best, own_w,
+                                                                  own_hit, rs, bnd + (size_t)it * (S + 1), S,
+                                                                  isrc + it);
+        if ((threadIdx.x & 63) == 0) {
+            if (!ok) {
+                atomicOr(&hub_flags[item.r], HUB_REPEATS);
+                if (a.L1) atomicAdd(a.hs.repeats, 1u);
+            }
+            if (a.L1) {
+                const uint32_t h = item.r;
+                if (best) atomicMax(&a.hs.best[h], best);
+                if (own_w) atomicAdd(&a.hs.own_sum[h], own_w);
+                if (own_hit) atomicOr(&a.hs.flags[h], HUB_OWN_SEEN);
+                atomicAdd(&a.hs.rowsum[h], rs);
+            }
+        }
+    }
+}
+
+// The copy: one wavefront per 64 segments and one slice.  Lane l takes
+// segment l's arcs of the slice; the wavefront then copies the 64 ranges as
+// one flattened list (an exclusive scan of their lengths), 4 x 64 arcs per
+// step with all their loads in flight, each lane finding the range of its
+// arc by a binary search over the lanes' offsets.
+constexpr uint32_t kSliceItems = 256;  // segments per block (4 wavefronts x 64)
+__global__ __launch_bounds__(256) void relabel_hub_slices_k(RelabelArgs a, const HubItem *__restrict__ items,
+                                                            uint32_t count, uint32_t S,
+                                                            const uint16_t *__restrict__ bnd,
+                                                            const uint64_t *__restrict__ isrc) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t per_slice = (count + kSliceItems - 1) / kSliceItems;
+    const uint32_t s = blockIdx.x / per_slice;  // slice-major: blocks start in order
+    const uint32_t it = (blockIdx.x - s * per_slice) * kSliceItems + wave * 64 + lane;
+    uint32_t k0 = 0, k1 = 0;
+    uint64_t src = 0, dst = 0;
+    if (it < count) {
+        const uint16_t *bi = bnd + (size_t)it * (S + 1);
+        const HubItem item = items[it];
+        const uint32_t len = (uint32_t)(item.b1 - item.b0);
+        const bool unsorted = bi[0] == kSliceNone;
+        if (s < S) {  // this slice's arcs of a sorted segment
+            if (!unsorted) {
+                // clamped: with an id out of range (reported by the scan)
+                // the boundaries need not be consistent
+                k1 = bi[s + 1] < len ? bi[s + 1] : len;
+                k0 = bi[s] < k1 ? bi[s] : k1;
+            }
+        } else if (unsorted) {  // after the last slice: whole unsorted segments
+            k1 = len;
+        }
+        src = isrc[it] + k0;
+        dst = item.b0 + k0;
+    }
+    const uint32_t c = k1 - k0;
+    uint32_t incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if ((int)lane >= off) incl += y;
+    }
+    const uint32_t excl = incl - c;
+    const uint32_t T = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const uint32_t *__restrict__ col = a.g.col;
+    const uint32_t *__restrict__ nmap = a.new_of;
+    uint32_t *__restrict__ out = a.col2;
+    for (uint32_t t0 = 0; t0 < T; t0 += 256) {
+        uint64_t from[4], to[4];
+        bool in[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t t = t0 + 64u * q + lane;
+            in[q] = t < T;
+            const uint32_t tc = in[q] ? t : 0u;  // T > 0: arc 0 exists
+            uint32_t lo = 0, hi = 64;            // the last lane whose range starts at or before tc
+#pragma unroll
+            for (int step = 0; step < 6; ++step) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if ((uint32_t)__shfl((int)excl, (int)mid, 64) <= tc)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const uint32_t d = tc - (uint32_t)__shfl((int)excl, (int)lo, 64);
+            from[q] = __shfl(src, (int)lo, 64) + d;
+            to[q] = __shfl(dst, (int)lo, 64) + d;
+        }
+        uint32_t x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = col[from[q]];
+        uint32_t y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[q] = nmap[x[q] < a.g.n ? x[q] : 0u];  // a bad id was reported by the scan
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (in[q]) out[to[q]] = y[q];
+    }
+}
+
 // Rows whose segments turned out not to list each neighbour once are voted
 // by the regular round-1 kernels: drop the partials the copy gathered.
 __global__ void hub_unfuse_k(HubState hs, uint32_t H) {
@@ -761,10 +915,15 @@ hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uin
     }
     return hipGetLastError();
 }
+uint32_t relabel_slices(uint32_t n) {
+    const uint32_t S = (uint32_t)(((uint64_t)n + (1u << kSliceShift) - 1) >> kSliceShift);
+    return S >= kSliceMin ? S : 0u;
+}
+
 hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
                               uint32_t *col2, uint32_t *w2, const HubItem *items, uint32_t count,
                               uint32_t *hub_flags, uint32_t *err, const Round1Fuse *f, const HubState *hs,
-                              uint32_t H, hipStream_t s) {
+                              uint32_t H, uint16_t *bnd, uint64_t *isrc, hipStream_t s) {
     if (count == 0) return hipSuccess;
     RelabelArgs a{g, old_of, new_of, rp2, col2, w2, err, nullptr, nullptr, 0, HubState{},
                   nullptr, nullptr, 0, 0, 0, 0};
@@ -774,7 +933,14 @@ hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint
         a.sw = f->sw;
         a.hs = *hs;
     }
-    relabel_hub_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hub_flags);
+    const uint32_t S = relabel_slices(g.n);
+    if (S && bnd && isrc) {
+        relabel_hub_scan_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hub_flags, S, bnd, isrc);
+        const uint64_t per_slice = (count + kSliceItems - 1) / kSliceItems;
+        relabel_hub_slices_k<<<(unsigned)(per_slice * (S + 1)), 256, 0, s>>>(a, items, count, S, bnd, isrc);
+    } else {
+        relabel_hub_k<<<grid_for(count, 4, 8192), 256, 0, s>>>(a, items, count, hub_flags);
+    }
     if (f && H) hub_unfuse_k<<<grid_for(H, 256, 1024), 256, 0, s>>>(a.hs, H);
     return hipGetLastError();
 }

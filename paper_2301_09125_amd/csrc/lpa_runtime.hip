@@ -100,6 +100,7 @@ struct lpa_ctx {
     DevBuf counters;  // kCountWords u64 per round, then the error word
     DevBuf items, ritems, slab_off, slab_mask, touched_off, tcount, best, own_sum, hflags, rowsum, slab, touched;
     DevBuf cand, thr, item_lo, mrows, slab_pending, hub_tmp, r1_rows, r1_cnt;
+    DevBuf hub_bnd, hub_src;  // long-row relabel by slices: slice starts per segment, segment sources
     DevBuf K, mod_sums, partials;
     DevBuf gid, gvd, bstate, bseg;  // batched run
     DevBuf f_top1, f_top2, f_kw, f_last, f_front, f_stale, f_lists, f_small, f_model;  // frontier runs
@@ -352,10 +353,18 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
     if (fuse) HIP_TRY(launch_init_labels(La, fuse->L1, c->old_of.as<uint32_t>(), nullptr, n, s));
     if (fuse && fuse->rest_n) HIP_TRY(launch_fill_u32(fuse->rest_n, 0, NBINS, s));
     const HubState hs = hub_state(c);
+    uint16_t *bnd = nullptr;
+    uint64_t *isrc = nullptr;
+    if (const uint32_t S = relabel_slices(n); S && P.n_items) {
+        HIP_TRY(c->hub_bnd.ensure((size_t)P.n_items * (S + 1) * sizeof(uint16_t)));
+        HIP_TRY(c->hub_src.ensure((size_t)P.n_items * sizeof(uint64_t)));
+        bnd = c->hub_bnd.as<uint16_t>();
+        isrc = c->hub_src.as<uint64_t>();
+    }
     HIP_TRY(launch_relabel_hub(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
                                c->col2.as<uint32_t>(), w2, c->items.as<HubItem>(), P.n_items,
                                c->hflags.as<uint32_t>(), err_dev, (fuse && with_slab) ? fuse : nullptr, &hs, P.H,
-                               s));
+                               bnd, isrc, s));
     HIP_TRY(launch_relabel_rows(G, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(),
                                 c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_WIDE],
                                 B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE], B.lo[BIN_WAVE], BIN_WIDE, BIN_WAVE, 1, err_dev,
@@ -1689,7 +1698,8 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->items,      &c->ritems,   &c->slab_off, &c->slab_mask, &c->touched_off, &c->tcount,
                       &c->best,       &c->own_sum,  &c->hflags,   &c->rowsum,    &c->slab,        &c->touched,
                       &c->K,          &c->mod_sums, &c->partials, &c->cand,      &c->thr,         &c->item_lo,
-                      &c->mrows,      &c->slab_pending, &c->hub_tmp, &c->r1_rows, &c->r1_cnt, &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
+                      &c->mrows,      &c->slab_pending, &c->hub_tmp, &c->r1_rows, &c->r1_cnt, &c->hub_bnd,
+                      &c->hub_src,    &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
                       &c->f_top1, &c->f_top2, &c->f_kw, &c->f_last, &c->f_front, &c->f_stale, &c->f_lists,
                       &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
                       &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist};

@@ -190,6 +190,50 @@ def test_repeated_neighbours_round_one(gg, orc, lpa, ctx):
         assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=10, sw=sw, frontier=1, wave_max=40, wide_max=40)
 
 
+def test_long_rows_relabelled_by_slices(gg, orc, lpa, ctx):
+    # the vertices of a weighted R-MAT graph spread over 9 M ids, so that the
+    # long rows are relabelled slice by slice of the id space (at least 8
+    # slices): most rows sorted, one reversed, one shuffled, one listing 40
+    # neighbours twice (sorted, with repeats)
+    import graphgen
+    base = gg.with_weights(gg.rmat(14, 16, seed=14), 7, 1, 8)
+    n = 9_000_000
+    rng = np.random.default_rng(5)
+    ids = rng.choice(n, base.n, replace=False).astype(np.int64)
+    deg = np.diff(base.row_ptr).astype(np.int64)
+    src = np.repeat(ids, deg)
+    dst = ids[base.col.astype(np.int64)]
+    wts = np.asarray(base.w, dtype=np.uint32)
+    order = np.lexsort((dst, src))
+    src, dst, wts = src[order], dst[order], wts[order]
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, src + 1, 1)
+    rp = np.cumsum(rp)
+    longs = ids[np.flatnonzero(deg > 512)]
+    assert len(longs) >= 3
+    a0, a1 = rp[longs[0]], rp[longs[0] + 1]
+    dst[a0:a1], wts[a0:a1] = dst[a0:a1][::-1].copy(), wts[a0:a1][::-1].copy()
+    b0, b1 = rp[longs[1]], rp[longs[1] + 1]
+    p = rng.permutation(b1 - b0)
+    dst[b0:b1], wts[b0:b1] = dst[b0:b1][p], wts[b0:b1][p]
+    r = longs[2]
+    c0, c1 = rp[r], rp[r + 1]
+    rc = np.concatenate([dst[c0:c1], dst[c0:c0 + 40]])
+    rw = np.concatenate([wts[c0:c1], wts[c0:c0 + 40]])
+    o = np.argsort(rc, kind="stable")
+    dst = np.concatenate([dst[:c0], rc[o], dst[c1:]])
+    wts = np.concatenate([wts[:c0], rw[o], wts[c1:]])
+    rp[r + 1:] += 40
+    g = graphgen.from_csr_arrays(n, rp.astype(np.uint64), dst.astype(np.uint32), wts, name="rmat14_spread9m")
+    say("[slices]", g.n, g.m, "long rows", len(longs))
+    for sw in (1, 0):
+        ref, lab, st = assert_same(orc, lpa, ctx, g, tol=0.0, max_iter=6, sw=sw)
+    ref, lab, st = assert_same(orc, lpa, ctx, g)
+    q, terms = ctx.modularity(dev(lpa, g), _t(lab))
+    mref = orc.modularity(g, ref.labels)
+    assert (terms["two_m"], terms["sigma_in"], terms["sum_k2"]) == (mref.two_m, mref.sigma_in, mref.sum_k2)
+
+
 def test_random_bin_thresholds_give_same_labels(gg, orc, lpa, ctx):
     g = gg.with_weights(gg.rmat(13, seed=21), 3, 1, 5)
     ref = orc.rak(g, tol=0.0, max_iter=12, self_weight=1)
