@@ -49,6 +49,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 // Long rows relabelled by slices of the caller's id space (lpa_prep.hip).
 constexpr uint32_t kSliceShift = 20;     // 2^20 ids (4 MB of the id map) per slice
 constexpr uint32_t kSliceMin = 8;        // below 8 slices (32 MB) the direct gather is as fast
+constexpr uint32_t kSliceMax = 32;       // beyond, a 512-arc segment holds too few arcs per slice
 constexpr uint16_t kSliceNone = 0xFFFF;  // bnd[0] of a segment that is not sorted
 constexpr int kDegBuckets = 24;  // row-length histogram of the autotuner
 

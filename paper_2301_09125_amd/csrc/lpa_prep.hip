@@ -917,7 +917,7 @@ hipError_t launch_relabel_rows(const Graph &g, const uint32_t *old_of, const uin
 }
 uint32_t relabel_slices(uint32_t n) {
     const uint32_t S = (uint32_t)(((uint64_t)n + (1u << kSliceShift) - 1) >> kSliceShift);
-    return S >= kSliceMin ? S : 0u;
+    return (S >= kSliceMin && S <= kSliceMax) ? S : 0u;
 }
 
 hipError_t launch_relabel_hub(const Graph &g, const uint32_t *old_of, const uint32_t *new_of, const uint64_t *rp2,
