@@ -142,7 +142,10 @@ lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *
  * tol in [0, 1]; max_iter = 0 returns the initial labels.
  * The run works on a relabelled device copy of the CSR (vertices grouped by
  * degree bin, high-degree vertices first) that the context allocates: about
- * 4 bytes per arc (8 with weights) plus 25 bytes per vertex.
+ * 4 bytes per arc (8 with weights) plus 25 bytes per vertex, and between
+ * 2^23 and 2^25 vertices about 0.15 bytes per arc of the rows of more than
+ * wide_max arcs (where each slice of the vertex ids starts in them: those
+ * rows are relabelled slice by slice).
  * Errors: LPA_EINVAL (null pointer, tol outside [0,1] or NaN, n too large,
  * malformed row_ptr, col value >= n), LPA_EOVERFLOW, LPA_ENOMEM,
  * LPA_EDEVICE. */
