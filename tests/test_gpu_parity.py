@@ -232,6 +232,14 @@ def test_long_rows_relabelled_by_slices(gg, orc, lpa, ctx):
     q, terms = ctx.modularity(dev(lpa, g), _t(lab))
     mref = orc.modularity(g, ref.labels)
     assert (terms["two_m"], terms["sigma_in"], terms["sum_k2"]) == (mref.two_m, mref.sigma_in, mref.sum_k2)
+    # a resumed run relabels without voting round 1 in the same pass
+    dg = dev(lpa, g)
+    part, st1 = ctx.run(dg, tol=0.0, max_iter=2)
+    start = lpa.labels_to_numpy(part).copy()  # resume overwrites the labels in place
+    rest, st2 = ctx.run_resume(dg, part, tol=0.0, max_iter=4)
+    ref2 = orc.rak(g, tol=0.0, max_iter=4, init_labels=start)
+    assert st2.changed == ref2.changed
+    assert np.array_equal(lpa.labels_to_numpy(rest), ref2.labels)
 
 
 def test_random_bin_thresholds_give_same_labels(gg, orc, lpa, ctx):
@@ -263,10 +271,12 @@ def test_resume_equals_uninterrupted(gg, orc, lpa, ctx):
     dg = dev(lpa, g)
     full, stf = ctx.run(dg, tol=0.0, max_iter=8)
     part, st1 = ctx.run(dg, tol=0.0, max_iter=3)
+    start = lpa.labels_to_numpy(part).copy()  # resume overwrites the labels in place
     rest, st2 = ctx.run_resume(dg, part, tol=0.0, max_iter=5)
     assert np.array_equal(lpa.labels_to_numpy(rest), lpa.labels_to_numpy(full))
     assert st1.changed + st2.changed == stf.changed
-    ref = orc.rak(g, tol=0.0, max_iter=5, init_labels=lpa.labels_to_numpy(part))
+    ref = orc.rak(g, tol=0.0, max_iter=5, init_labels=start)
+    assert ref.changed == st2.changed
     assert np.array_equal(lpa.labels_to_numpy(rest), ref.labels)
 
 
