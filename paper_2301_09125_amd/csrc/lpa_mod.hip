@@ -22,7 +22,8 @@
 namespace lpa {
 
 // Grid cap of the row and item loops (grid stride): 16 blocks per CU on a
-// 256-CU chip, whole rounds of blocks at the 7 to 8 that fit per CU.
+// 256-CU chip, two or more rounds of the 7 to 8 blocks that fit per CU, so a
+// partly filled last round is a small share of the launch.
 constexpr unsigned kModGrid = 4096;
 
 constexpr uint32_t kModSlots = 1024;

@@ -768,8 +768,8 @@ __global__ __launch_bounds__(256) void relabel_hub_k(RelabelArgs a, const HubIte
 // (relabel_segment in SCAN mode, one wavefront per 512-arc segment) checks
 // the segment, votes round 1 (whose labels are the caller's ids themselves)
 // and records where each slice starts in it, as the segment is sorted; then
-// one launch ordered slice-major copies each segment's arcs of one slice
-// (16 lanes per segment), and the blocks after the last slice copy the
+// one launch ordered slice-major copies the segments' arcs of one slice at a
+// time (relabel_hub_slices_k), and the blocks after the last slice copy the
 // segments that are not sorted the direct way.
 __global__ __launch_bounds__(256) void relabel_hub_scan_k(RelabelArgs a, const HubItem *__restrict__ items,
                                                           uint32_t count, uint32_t *hub_flags, uint32_t S,
