@@ -32,3 +32,28 @@ def test_help_lists_the_contract_flags():
     assert r.returncode == 0
     for flag in ("--gpus", "--steps", "--warmup", "--workload"):
         assert flag in r.stdout
+
+
+def test_traffic_is_null_once_the_kernel_sources_change(tmp_path, monkeypatch):
+    # a counter summary carries a hash of the kernel sources it was taken
+    # with; once a source changes, bench.py reports traffic as null
+    import hashlib
+    import shutil
+    sys.path.insert(0, ROOT)
+    import bench
+    csrc = tmp_path / "paper_2301_09125_amd" / "csrc"
+    shutil.copytree(os.path.join(ROOT, "paper_2301_09125_amd", "csrc"), csrc)
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update((csrc / f).read_bytes())
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic_vote_hub_toy.txt").write_text(
+        "# toy summary\nkernel: vote_hub\ntraffic_bytes_per_launch: 12345\n"
+        f"kernel_sources_sha256: {h.hexdigest()[:16]}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_from_profile("toy", "vote_hub") == 12345
+    assert bench.traffic_from_profile("other", "vote_hub") is None  # no summary
+    with open(csrc / "lpa_vote.hip", "a") as f:
+        f.write("\n// changed\n")
+    assert bench.traffic_from_profile("toy", "vote_hub") is None
