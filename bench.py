@@ -58,23 +58,60 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, budget_s: float):
-    """The oracle as it stands (sequential C, one core) on a bounded sample:
-    its rounds on the same graph from the unique initial labels, one at a
-    time, until the time budget is spent (at least one round)."""
+def host_cpu():
+    """(logical CPUs this process may use, CPU model name) of the host."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), model
+
+
+def _oracle_rounds(g, budget_s: float, parallel: bool):
+    """Rounds of the oracle on g from the unique initial labels, one at a
+    time, until the time budget is spent (at least one round): (rounds,
+    seconds, labels)."""
     import oracle
     labels = np.arange(g.n, dtype=np.uint32)
     rounds, t0 = 0, time.perf_counter()
     while rounds < 20:
-        labels, _ = oracle.rak_round(g, labels, self_weight=1)
+        labels, _ = oracle.rak_round(g, labels, self_weight=1, parallel=parallel)
         rounds += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    arcs = g.m * rounds
-    return {"value": arcs / dt / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {rounds} rounds of the sequential oracle on the same graph "
-                      f"({arcs} arcs voted in {dt:.1f} s)"}
+    return rounds, time.perf_counter() - t0, labels
+
+
+def cpu_baseline(g, budget_s: float):
+    """The oracle as it stands on a bounded sample of the same workload: its
+    rounds on the same graph from the unique initial labels until the time
+    budget is spent, once built with OpenMP on every host core (the paper's
+    OpenMP RAK, Section 3.2: vertices shared among threads, a vote buffer
+    per thread) and once sequential on one core.  The OpenMP labels must
+    equal the sequential ones round for round."""
+    import oracle
+    nproc, model = host_cpu()
+    threads = oracle.threads(True)
+    r_par, dt_par, lab_par = _oracle_rounds(g, budget_s, True)
+    r_seq, dt_seq, lab_seq = _oracle_rounds(g, budget_s, False)
+    k = min(r_par, r_seq)
+    if k == r_par and k == r_seq and not np.array_equal(lab_par, lab_seq):
+        raise SystemExit("the OpenMP oracle disagrees with the sequential oracle")
+    par = g.m * r_par / dt_par / 1e9
+    seq = g.m * r_seq / dt_seq / 1e9
+    return {"value": par, "unit": "GE/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {r_par} rounds of the oracle built with OpenMP ({threads} threads) on the same graph "
+                      f"({g.m * r_par} arcs voted in {dt_par:.1f} s)",
+            "host": {"logical_cpus": nproc, "model": model},
+            "single_core": {"value": seq, "unit": "GE/s", "cores": 1, "kind": "oracle",
+                            "sample": f"first {r_seq} rounds of the sequential oracle ({g.m * r_seq} arcs voted in "
+                                      f"{dt_seq:.1f} s)"},
+            "paper": "6.75x: the paper's OpenMP strict RAK on 12 threads over its sequential non-strict RAK at "
+                     "tolerance 0.05, 2x Intel Xeon Silver 4116 (Section 3.2; system in Section 3.1.1)"}
 
 
 def copy_calibration():
@@ -90,16 +127,45 @@ def copy_calibration():
     log(f"[bench] copy calibration: 3 copies of {src.numel() * 4} bytes")
 
 
+class GatherProbe:
+    """The bench-only random-gather probe (bench_gather_probe.hip, built into
+    libgather_probe.so next to this file; not part of liblpa.so)."""
+
+    def __init__(self):
+        import ctypes
+        from paper_2301_09125_amd import build as B
+        if not os.path.exists(B.PROBE_LIB):
+            B.build_probe()
+        self.lib = ctypes.CDLL(B.PROBE_LIB)
+        vp = ctypes.c_void_p
+        self.lib.gather_probe_rate.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint32, ctypes.c_uint32, vp,
+                                               ctypes.POINTER(ctypes.c_double)]
+        self.lib.gather_probe_rate.restype = ctypes.c_int
+
+    def rate(self, idx, table, reps: int = 5) -> float:
+        import ctypes
+        import torch
+        for t, nm in ((idx, "idx"), (table, "table")):
+            if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+                raise ValueError(f"{nm}: a contiguous int32 device tensor is required")
+        out = ctypes.c_double(0.0)
+        rc = self.lib.gather_probe_rate(idx.data_ptr(), idx.numel(), table.data_ptr(), table.numel(), reps,
+                                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(out))
+        if rc:
+            raise RuntimeError(f"gather_probe_rate failed ({rc})")
+        return out.value
+
+
 def gather_ceiling(args, g, P):
     """The rate of a vote's one random access, 4-byte gathers through a
-    streamed index (lpa_gather_rate), over (a) synthetic streams on tables of
+    streamed index (GatherProbe), over (a) synthetic streams on tables of
     4..256 MB, uniform and skewed (hot ids first, density ~ (id+1)^-0.8, as
     the internal layout puts high-degree vertices first), and (b) the exact
     label-gather streams of this workload's internal layout: every arc, and
     the arcs of the long rows (the stream the dominant kernel reads), and the
     same arcs by the caller's ids (the stream the relabel pass reads)."""
     import torch
-    ctx = P.Context(0)
+    probe = GatherProbe()
     gen = torch.Generator(device="cuda")
     gen.manual_seed(1)
     m = 1 << 28
@@ -114,7 +180,7 @@ def gather_ceiling(args, g, P):
                 r = torch.rand(m, device="cuda", generator=gen, dtype=torch.float64)
                 a = 0.2  # inverse CDF of a density ~ x^-0.8 on [1, n + 1]
                 idx = ((r * ((n + 1) ** a - 1) + 1) ** (1 / a) - 1).clamp(0, n - 1).to(torch.int32)
-            rate = ctx.gather_rate(idx, table)
+            rate = probe.rate(idx, table)
             rows.append((f"{mb} MB table, {dist}", m, rate))
             log(f"[gather] {mb:4d} MB table {dist:8s}: {rate / 1e9:7.1f} G gathers/s")
             del idx
@@ -143,23 +209,22 @@ def gather_ceiling(args, g, P):
     caller = col[arc_pos]
     stream = new_of[caller.long()]
     del arc_pos
-    rate = ctx.gather_rate(stream, table)
+    rate = probe.rate(stream, table)
     rows.append((f"{args.workload}: every arc", stream.numel(), rate))
     log(f"[gather] {args.workload} every arc ({stream.numel()} gathers, {4 * n >> 20} MB labels): "
         f"{rate / 1e9:7.1f} G gathers/s")
     hub_arcs = int(lens[: int((binno == 0).sum())].sum())
     hub = stream[:hub_arcs].contiguous()
-    rate_h = ctx.gather_rate(hub, table) if hub_arcs else 0.0
+    rate_h = probe.rate(hub, table) if hub_arcs else 0.0
     rows.append((f"{args.workload}: long rows", hub_arcs, rate_h))
     log(f"[gather] {args.workload} long-row arcs ({hub_arcs} gathers): {rate_h / 1e9:7.1f} G gathers/s")
     # the relabel pass's stream: the caller's ids of the long-row arcs into
     # the n-entry id map (no locality: the caller's numbering is arbitrary)
     hub_c = caller[:hub_arcs].contiguous()
     del caller
-    rate_c = ctx.gather_rate(hub_c, table) if hub_arcs else 0.0
+    rate_c = probe.rate(hub_c, table) if hub_arcs else 0.0
     rows.append((f"{args.workload}: long rows, caller ids", hub_arcs, rate_c))
     log(f"[gather] {args.workload} long-row arcs, caller ids: {rate_c / 1e9:7.1f} G gathers/s")
-    ctx.close()
     print(json.dumps({"gather_ceiling": [{"stream": r[0], "gathers": r[1], "gathers_per_s": r[2]} for r in rows],
                       "workload": args.workload}), flush=True)
 
@@ -193,20 +258,32 @@ def traffic_from_profile(workload: str, kernel: str):
 
 def cpu_baseline_batch(b, budget_s: float = 15.0):
     """The oracle on a bounded sample of a batch: whole graphs, in a seeded
-    random order, until the time budget is spent."""
+    random order, until the time budget is spent; once with the OpenMP build
+    on every host core, once sequential on one core."""
     import oracle
     order = np.random.default_rng(1).permutation(b.G)
-    arcs, graphs, t0 = 0, 0, time.perf_counter()
-    for k in order:
-        g = b.graph(int(k))
-        r = oracle.rak(g, tol=0.05, max_iter=20, self_weight=1)
-        arcs += g.m * r.iterations
-        graphs += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": arcs / dt / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
-            "sample": f"{graphs} whole graphs of the batch (seeded order), {arcs} arcs voted in {dt:.1f} s"}
+
+    def leg(parallel):
+        arcs, graphs, t0 = 0, 0, time.perf_counter()
+        for k in order:
+            g = b.graph(int(k))
+            r = oracle.rak(g, tol=0.05, max_iter=20, self_weight=1, parallel=parallel)
+            arcs += g.m * r.iterations
+            graphs += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        return arcs, graphs, time.perf_counter() - t0
+
+    nproc, model = host_cpu()
+    threads = oracle.threads(True)
+    a_p, g_p, dt_p = leg(True)
+    a_s, g_s, dt_s = leg(False)
+    return {"value": a_p / dt_p / 1e9, "unit": "GE/s", "cores": threads, "kind": "oracle",
+            "sample": f"{g_p} whole graphs of the batch (seeded order) with the OpenMP oracle ({threads} threads), "
+                      f"{a_p} arcs voted in {dt_p:.1f} s",
+            "host": {"logical_cpus": nproc, "model": model},
+            "single_core": {"value": a_s / dt_s / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
+                            "sample": f"{g_s} whole graphs, sequential oracle, {a_s} arcs voted in {dt_s:.1f} s"}}
 
 
 def run_batch_bench(args, b, desc, P):
@@ -391,11 +468,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=0.05)
     ap.add_argument("--max-iter", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="time budget of the oracle for cpu_baseline (0 = skip)")
+                    help="time budget of each oracle leg (OpenMP, one core) for cpu_baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for counter profiles)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
@@ -488,12 +565,17 @@ def main():
                 gbs = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
                 log(f"[bench]   {p['name']:12s} launches {p['launches']:5d}  avg {p['ms'] / p['launches']:.4f} ms"
                     f"  {gbs:8.1f} GB/s alg")
-    round_ms = float(np.median([st0.ms_rounds / max(st0.iterations, 1)]))
+    # rounds 2..T each vote every row in their own launches; most of round 1
+    # is voted inside the relabel pass (ms_prepare) and is reported with it
+    later = st0.ms_per_iter[1:]
+    round_ms = float(np.mean(later)) if later else None
+    prep_ms = float(np.mean([st.ms_prepare for st, _ in stats]))
     cpu = None
     if args.cpu_seconds > 0:
-        log(f"[bench] cpu baseline: oracle rounds for about {args.cpu_seconds:.0f} s ...")
+        log(f"[bench] cpu baseline: oracle rounds for about {args.cpu_seconds:.0f} s per leg ...")
         cpu = cpu_baseline(g, args.cpu_seconds)
-        log(f"[bench] cpu baseline {cpu['value']:.4f} GE/s")
+        log(f"[bench] cpu baseline {cpu['value']:.4f} GE/s on {cpu['cores']} threads, "
+            f"{cpu['single_core']['value']:.4f} GE/s on one core")
 
     out = {
         "metric": METRIC,
@@ -512,7 +594,10 @@ def main():
                    "max_iter": args.max_iter, "self_weight": 1, "tie_break": "lowest label",
                    "rounds": st0.iterations, "changed": st0.changed, "modularity": q0,
                    "hbm_gbs_effective": round(bytes_alg / elapsed / 1e9, 1),
-                   "round_ms_device": round(round_ms, 4)},
+                   "round_ms_device_rounds_2_to_T": None if round_ms is None else round(round_ms, 4),
+                   "round_ms_device_per_round": [round(x, 4) for x in st0.ms_per_iter],
+                   "prepare_ms_device_incl_round1_share": round(prep_ms, 4),
+                   "arcs_voted_per_step": st0.arcs_processed},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

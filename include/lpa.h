@@ -102,6 +102,10 @@ typedef struct {
                               vertex outside that set sees the tally of its
                               last vote again, so the labels, changed counts
                               and rounds are identical to mode 0. */
+    uint32_t barrier_timeout_us; /* lpa_run_batch: the longest a block waits at
+                                    a grid-wide barrier of the persistent
+                                    kernel before the launch gives up with
+                                    LPA_ETIMEDOUT (0 = the default, 10 s) */
 } lpa_options;
 
 /* Run statistics.  The arrays are optional and owned by the caller; when
@@ -112,11 +116,22 @@ typedef struct {
     uint64_t changed_last;      /* vertices changed in the last round */
     uint64_t arcs_processed;    /* sum over rounds of the arcs voted */
     double ms_total;            /* host wall time of the call */
-    double ms_rounds;           /* device time of the rounds (HIP events) */
+    double ms_rounds;           /* device time of the vote launches of every
+                                   round (HIP events around each round's
+                                   launches).  From the unique initial labels,
+                                   round 1 of the rows that list each
+                                   neighbour once is voted by the pass that
+                                   builds the relabelled CSR: that share of
+                                   round 1 is in ms_prepare, not here */
+    double ms_prepare;          /* device time from the first to the last
+                                   launch of the binning and relabel passes
+                                   (including round 1's share above and the
+                                   device's waits for the host between them) */
     double modularity;          /* with options.modularity: Q of the result */
     uint64_t mod_terms[4];      /* ... and its terms, as lpa_modularity's */
     uint64_t *changed_per_iter; /* host, cap entries, or NULL */
-    float *ms_per_iter;         /* host, cap entries, or NULL */
+    float *ms_per_iter;         /* host, cap entries, or NULL: device time of
+                                   each round's launches, as ms_rounds */
     uint32_t cap;
 } lpa_stats;
 
@@ -322,16 +337,6 @@ lpa_status lpa_mlp_grad(lpa_ctx *ctx, const lpa_mlp *model, const float *X, cons
  * NULL).  Labels never depend on the thresholds, only the speed does. */
 lpa_status lpa_autotune(lpa_ctx *ctx, const lpa_csr *g, const uint64_t *graph_vptr, uint32_t G, uint32_t rounds,
                         lpa_options *chosen, uint32_t *measured);
-
-/* Calibration of the vote's roofline: the rate of the one access a vote
- * makes per arc, a 4-byte gather whose address comes from a streamed index.
- * Runs `reps` (>= 1) timed passes of table[idx[k]], k < m, on the context's
- * stream (one untimed pass first) and returns gathers per second in
- * *gathers_per_s (host).  idx: device u32[m]; table: device u32[table_n]
- * (indices at or above table_n read the last entry).  Errors: LPA_EINVAL for
- * NULL pointers, m = 0, table_n = 0 or reps = 0; LPA_EDEVICE. */
-lpa_status lpa_gather_rate(lpa_ctx *ctx, const uint32_t *idx, uint64_t m, const uint32_t *table,
-                           uint32_t table_n, uint32_t reps, double *gathers_per_s);
 
 /* Copy up to `cap` per-kernel profile records into out (host); *count gets
  * the number of records available.  lpa_profile_reset clears them. */

@@ -26,25 +26,35 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
+_libs = {}
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so (gcc -O2, no OpenMP: the oracle is sequential)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-std=c11", "-o", tmp,
-                               os.path.join(_HERE, "oracle.c"), "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    """Compile liboracle.so (gcc -O2, sequential) and, from the same source,
+    liboracle_omp.so (gcc -O2 -fopenmp: a round's vertices shared among
+    threads, the paper's OpenMP form of RAK, Section 3.2)."""
+    for path, extra in ((_LIB_PATH, []), (_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", *extra, "-shared", "-fPIC", "-std=c11", "-o", tmp,
+                                   os.path.join(_HERE, "oracle.c"), "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+def threads(parallel: bool = True) -> int:
+    """Threads a round of the (parallel) oracle uses."""
+    return int(_load(parallel).orc_threads())
+
+
+def _load(parallel: bool = False):
+    lib = _libs.get(parallel)
+    if lib is None:
+        path = _OMP_PATH if parallel else _LIB_PATH
+        if not os.path.exists(path):
             build(force=False)
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(path)
         vp, u32, u64, dbl = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
         lib.orc_rak.argtypes = [u32, vp, vp, vp, u32, dbl, u32, vp, vp, vp, vp, vp]
         lib.orc_rak.restype = ctypes.c_int
@@ -56,8 +66,10 @@ def _load():
         lib.orc_rak_masked.restype = ctypes.c_int
         lib.orc_modularity.argtypes = [u32, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.orc_modularity.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
+        _libs[parallel] = lib
+    return lib
 
 
 class OracleError(RuntimeError):
@@ -87,28 +99,30 @@ class RakResult:
 
 
 def rak(g, tol: float = 0.05, max_iter: int = 20, self_weight: int = 1,
-        init_labels: np.ndarray | None = None) -> RakResult:
-    """Synchronous RAK (Section 3.2) with the lowest-label tie-break."""
+        init_labels: np.ndarray | None = None, parallel: bool = False) -> RakResult:
+    """Synchronous RAK (Section 3.2) with the lowest-label tie-break
+    (parallel: the OpenMP build of the same source)."""
     rp, col, w = _arrs(g)
     out = np.empty(g.n, dtype=np.uint32)
     ch = np.zeros(max(max_iter, 1), dtype=np.uint64)
     it = ctypes.c_uint32(0)
     cv = ctypes.c_int32(0)
     init = None if init_labels is None else np.ascontiguousarray(init_labels, dtype=np.uint32)
-    rc = _load().orc_rak(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight, float(tol), max_iter,
+    rc = _load(parallel).orc_rak(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight, float(tol), max_iter,
                          _p(init), out.ctypes.data, ch.ctypes.data, ctypes.byref(it), ctypes.byref(cv))
     if rc:
         raise OracleError(rc)
     return RakResult(out, int(it.value), bool(cv.value), [int(x) for x in ch[: it.value]])
 
 
-def rak_round(g, labels: np.ndarray, self_weight: int = 1, active: np.ndarray | None = None):
+def rak_round(g, labels: np.ndarray, self_weight: int = 1, active: np.ndarray | None = None,
+              parallel: bool = False):
     """One synchronous round from `labels`; returns (new_labels, changed)."""
     rp, col, w = _arrs(g)
     old = np.ascontiguousarray(labels, dtype=np.uint32)
     new = np.empty_like(old)
     act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
-    ch = _load().orc_rak_round(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight,
+    ch = _load(parallel).orc_rak_round(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight,
                                old.ctypes.data, new.ctypes.data, _p(act))
     if ch < 0:
         raise OracleError(int(ch))

@@ -1,6 +1,8 @@
 /*
- * oracle.c -- plain, sequential, deliberately slow CPU reference for the RAK
- * label propagation method and the modularity measure.
+ * oracle.c -- plain, deliberately slow CPU reference for the RAK label
+ * propagation method and the modularity measure.  Built without OpenMP
+ * (liboracle.so) it is sequential; built with it (liboracle_omp.so) the
+ * vertices of a round are shared among threads with the same arithmetic.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
  * benchmark's CPU-baseline leg may load this code.  It shares nothing with
@@ -38,6 +40,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct { uint32_t label; uint32_t weight; } pair_lw;
 
@@ -119,20 +124,46 @@ static uint64_t max_degree(uint32_t n, const uint64_t *rp) {
 
 /* One synchronous round over the vertices with active[v] != 0 (all if
  * active == NULL); inactive vertices copy their label.  Returns the number
- * of vertices whose label changed, or a negative code. */
+ * of vertices whose label changed, or a negative code.
+ *
+ * Built with OpenMP (liboracle_omp.so) the vertices are shared among the
+ * threads, each with a vote buffer of its own -- the paper's OpenMP RAK gives
+ * every thread a separately allocated hashtable (Section 3.2).  A round only
+ * reads L_old and each vertex writes only its own L_new entry, so the result
+ * does not depend on the number of threads. */
 int64_t orc_rak_round(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
                       uint32_t self_weight, const uint32_t *L_old, uint32_t *L_new,
                       const uint8_t *active) {
-    pair_lw *buf = (pair_lw *)malloc((size_t)(max_degree(n, rp) + 1) * sizeof(pair_lw));
-    if (!buf) return -3;
+    const size_t cap = (size_t)(max_degree(n, rp) + 1);
     int64_t changed = 0;
-    for (uint32_t v = 0; v < n; ++v) {
-        uint32_t lab = (active && !active[v]) ? L_old[v] : vote(v, rp, col, w, self_weight, L_old, buf, NULL, NULL);
-        L_new[v] = lab;
-        changed += (lab != L_old[v]);
+    int failed = 0;
+#pragma omp parallel reduction(+ : changed) reduction(| : failed)
+    {
+        pair_lw *buf = (pair_lw *)malloc(cap * sizeof(pair_lw));
+        if (!buf) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1024)
+            for (int64_t i = 0; i < (int64_t)n; ++i) {
+                uint32_t v = (uint32_t)i;
+                uint32_t lab = (active && !active[v]) ? L_old[v]
+                                                      : vote(v, rp, col, w, self_weight, L_old, buf, NULL, NULL);
+                L_new[v] = lab;
+                changed += (lab != L_old[v]);
+            }
+            free(buf);
+        }
     }
-    free(buf);
-    return changed;
+    return failed ? -3 : changed;
+}
+
+/* Threads a round of orc_rak_round may use (1 without OpenMP). */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* One synchronous round over every vertex that also reports, per vertex,

@@ -55,9 +55,13 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs &b, uint32_t nblock
             __hip_atomic_fetch_add(&b.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const uint64_t t0 = wall_clock64();
+            // a block that gave up never arrives again: the others leave as
+            // soon as they see its error bit instead of running into their
+            // own limits
             while (__hip_atomic_load(&b.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(1);
-                if (wall_clock64() - t0 > b.timeout_ticks) {
+                if (wall_clock64() - t0 > b.timeout_ticks ||
+                    (__hip_atomic_load(b.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TIMEOUT)) {
                     atomicOr(b.err, ERR_TIMEOUT);
                     failed = 1;
                     break;

@@ -339,10 +339,6 @@ hipError_t launch_row_sums(const Graph &g, uint32_t *kw, hipStream_t s);
 hipError_t launch_mask_rows(uint8_t *mask, const uint32_t *old_of, uint32_t lo, uint32_t cnt, uint8_t val,
                             hipStream_t s);
 
-// Gathers table[min(idx[k], table_n - 1)] for k < m (lpa_probe.hip); out:
-// grid * 256 words.
-hipError_t launch_gather_probe(const uint32_t *idx, uint64_t m, const uint32_t *table, uint32_t table_n,
-                               uint32_t *out, uint32_t grid, hipStream_t s);
 hipError_t launch_mod_sumsq(const unsigned long long *K, uint32_t n, unsigned long long *partials,
                             uint32_t nparts, hipStream_t s);
 

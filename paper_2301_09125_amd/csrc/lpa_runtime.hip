@@ -114,7 +114,7 @@ struct lpa_ctx {
     uint64_t *pinned = nullptr;  // host pinned scratch for small read-backs
     size_t pinned_words = 0;
 
-    hipEvent_t round_a = nullptr, round_b = nullptr;
+    hipEvent_t round_a = nullptr, round_b = nullptr, prep_a = nullptr, prep_b = nullptr;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<Pending> pending;
@@ -503,6 +503,7 @@ void clear_stats(lpa_stats *stats) {
     stats->arcs_processed = 0;
     stats->ms_total = 0;
     stats->ms_rounds = 0;
+    stats->ms_prepare = 0;
     stats->modularity = 0;
     for (int i = 0; i < 4; ++i) stats->mod_terms[i] = 0;
 }
@@ -543,18 +544,23 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     HIP_TRY(c->r1_cnt.ensure(NBINS * sizeof(uint32_t)));
     const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight, c->r1_rows.as<uint32_t>(),
                         c->r1_cnt.as<uint32_t>()};
+    if (!c->round_a) HIP_TRY(hipEventCreate(&c->round_a));
+    if (!c->round_b) HIP_TRY(hipEventCreate(&c->round_b));
+    if (!c->prep_a) HIP_TRY(hipEventCreate(&c->prep_a));
+    if (!c->prep_b) HIP_TRY(hipEventCreate(&c->prep_b));
+    HIP_TRY(hipEventRecord(c->prep_a, s));
     LPA_TRY(prepare(c, g, P, err_dev, true, fused ? &fz : nullptr, c->La.as<uint32_t>()));
     if (!fused)
         HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(),
                                    resume ? labels : nullptr, n, s));
+    HIP_TRY(hipEventRecord(c->prep_b, s));  // read once the first round has synchronised
 
     const uint64_t thr = (uint64_t)std::floor(tol * (double)n);
     const bool weighted = g->w != nullptr;
     const HubState hs = hub_state(c);
     const Bins &B = P.bins;
-    const uint64_t voted_arcs = B.arcs[BIN_THREAD] + B.arcs[BIN_GROUP] + B.arcs[BIN_WAVE] + B.arcs[BIN_HUB];
-    if (!c->round_a) HIP_TRY(hipEventCreate(&c->round_a));
-    if (!c->round_b) HIP_TRY(hipEventCreate(&c->round_b));
+    const uint64_t voted_arcs =
+        B.arcs[BIN_THREAD] + B.arcs[BIN_GROUP] + B.arcs[BIN_WAVE] + B.arcs[BIN_WIDE] + B.arcs[BIN_HUB];
 
     uint32_t *L_old = c->La.as<uint32_t>(), *L_new = c->Lb.as<uint32_t>();
     uint32_t it = 0;
@@ -640,6 +646,9 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         stats->changed_last = changed;
         stats->arcs_processed = voted_arcs * it;
         stats->ms_rounds = ms_rounds;
+        float ms_prep = 0.f;
+        (void)hipEventElapsedTime(&ms_prep, c->prep_a, c->prep_b);
+        stats->ms_prepare = ms_prep;
         stats->modularity = q;
         for (int i = 0; i < 4; ++i) stats->mod_terms[i] = terms[i];
         stats->ms_total =
@@ -1200,7 +1209,9 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         int rate_khz = 0;
         HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
         if (rate_khz <= 0) rate_khz = 100000;
-        b.timeout_ticks = (uint64_t)(kBarrierTimeoutS * 1e3 * (double)rate_khz);
+        const double limit_ms =
+            c->opt.barrier_timeout_us ? 1e-3 * (double)c->opt.barrier_timeout_us : kBarrierTimeoutS * 1e3;
+        b.timeout_ticks = (uint64_t)(limit_ms * (double)rate_khz);
         // the captured graph depends on exactly these values
         std::vector<unsigned char> key(sizeof(b) + sizeof(nblocks) + sizeof(labels) + sizeof(n) + sizeof(s) +
                                        sizeof(slots));
@@ -1307,6 +1318,7 @@ void lpa_default_options(lpa_options *opt) {
     opt->profile = 0;
     opt->modularity = 0;
     opt->frontier = 0;
+    opt->barrier_timeout_us = 0;
 }
 
 lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *opt) {
@@ -1653,31 +1665,6 @@ lpa_status lpa_profile_get(lpa_ctx *c, lpa_kernel_prof *out, uint32_t cap, uint3
     return LPA_OK;
 }
 
-lpa_status lpa_gather_rate(lpa_ctx *c, const uint32_t *idx, uint64_t m, const uint32_t *table, uint32_t table_n,
-                           uint32_t reps, double *gathers_per_s) {
-    if (!c || !idx || !table || !gathers_per_s || m == 0 || reps == 0 || table_n == 0) return LPA_EINVAL;
-    HIP_TRY(hipSetDevice(c->device));
-    const hipStream_t s = c->stream;
-    const uint32_t grid = (uint32_t)std::max(1, c->num_cu) * 16;
-    HIP_TRY(c->hub_tmp.ensure((size_t)grid * 256 * sizeof(uint32_t)));
-    uint32_t *out = c->hub_tmp.as<uint32_t>();
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    hipError_t e = launch_gather_probe(idx, m, table, table_n, out, grid, s);
-    if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_gather_probe(idx, m, table, table_n, out, grid, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    HIP_TRY(e);
-    *gathers_per_s = ms > 0.f ? (double)m * reps / ((double)ms * 1e-3) : 0.0;
-    return LPA_OK;
-}
-
 lpa_status lpa_profile_reset(lpa_ctx *c) {
     if (!c) return LPA_EINVAL;
     for (int k = 0; k < K_COUNT; ++k) {
@@ -1710,6 +1697,8 @@ void lpa_destroy(lpa_ctx *c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->round_a) (void)hipEventDestroy(c->round_a);
     if (c->round_b) (void)hipEventDestroy(c->round_b);
+    if (c->prep_a) (void)hipEventDestroy(c->prep_a);
+    if (c->prep_b) (void)hipEventDestroy(c->prep_b);
     delete c;
 }
 

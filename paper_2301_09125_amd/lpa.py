@@ -40,13 +40,14 @@ class _Options(ctypes.Structure):
     _fields_ = [("self_weight", ctypes.c_uint32), ("thread_max", ctypes.c_uint32),
                 ("group_max", ctypes.c_uint32), ("wave_max", ctypes.c_uint32),
                 ("wide_max", ctypes.c_uint32), ("merge_max", ctypes.c_uint32), ("profile", ctypes.c_uint32),
-                ("modularity", ctypes.c_uint32), ("frontier", ctypes.c_uint32)]
+                ("modularity", ctypes.c_uint32), ("frontier", ctypes.c_uint32),
+                ("barrier_timeout_us", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_uint32), ("converged", ctypes.c_int32),
                 ("changed_last", ctypes.c_uint64), ("arcs_processed", ctypes.c_uint64),
-                ("ms_total", ctypes.c_double), ("ms_rounds", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("ms_rounds", ctypes.c_double), ("ms_prepare", ctypes.c_double),
                 ("modularity", ctypes.c_double), ("mod_terms", ctypes.c_uint64 * 4),
                 ("changed_per_iter", ctypes.POINTER(ctypes.c_uint64)),
                 ("ms_per_iter", ctypes.POINTER(ctypes.c_float)), ("cap", ctypes.c_uint32)]
@@ -113,7 +114,7 @@ class _KProf(ctypes.Structure):
 
 EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_run_batch", "lpa_run_learned",
            "lpa_trace", "lpa_train", "lpa_mlp_forward", "lpa_mlp_grad", "lpa_autotune", "lpa_modularity",
-           "lpa_gather_rate", "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
+           "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
 
 
 def _load():
@@ -143,7 +144,6 @@ def _load():
                                  ctypes.POINTER(u32)]
     lib.lpa_modularity.argtypes = [vp, ctypes.POINTER(_Csr), vp, ctypes.POINTER(dbl),
                                    ctypes.POINTER(ctypes.c_uint64)]
-    lib.lpa_gather_rate.argtypes = [vp, vp, u64, vp, u32, u32, ctypes.POINTER(dbl)]
     lib.lpa_profile_get.argtypes = [vp, ctypes.POINTER(_KProf), u32, ctypes.POINTER(u32)]
     lib.lpa_profile_reset.argtypes = [vp]
     lib.lpa_destroy.argtypes = [vp]
@@ -154,7 +154,7 @@ def _load():
               lib.lpa_autotune):
         f.restype = ctypes.c_int
     for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_run_batch, lib.lpa_modularity, lib.lpa_profile_get,
-              lib.lpa_profile_reset, lib.lpa_gather_rate):
+              lib.lpa_profile_reset):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -222,6 +222,7 @@ class Stats:
     ms_per_iter: list = field(default_factory=list)
     modularity: float = 0.0
     mod_terms: dict = field(default_factory=dict)
+    ms_prepare: float = 0.0
 
 
 @dataclass
@@ -318,7 +319,8 @@ class Context:
         t = st.mod_terms
         return Stats(st.iterations, bool(st.converged), st.changed_last, st.arcs_processed, st.ms_total,
                      st.ms_rounds, [int(x) for x in ch[:k]], [float(x) for x in ms[:k]], st.modularity,
-                     {"two_m": int(t[0]), "sigma_in": int(t[1]), "sum_k2": int(t[2]) + (int(t[3]) << 64)})
+                     {"two_m": int(t[0]), "sigma_in": int(t[1]), "sum_k2": int(t[2]) + (int(t[3]) << 64)},
+                     st.ms_prepare)
 
     def run(self, g: DeviceGraph, tol: float = 0.05, max_iter: int = 20, labels_out=None):
         """RAK from L0(v) = v; returns (labels int32 tensor viewed as u32, Stats)."""
@@ -489,20 +491,6 @@ class Context:
             raise LpaError(rc, "lpa_profile_get")
         return [{"name": recs[i].name.decode(), "launches": recs[i].launches, "ms": recs[i].ms,
                  "bytes": recs[i].bytes, "arcs": recs[i].arcs} for i in range(min(cnt.value, 16))]
-
-    def gather_rate(self, idx, table, reps: int = 5) -> float:
-        """Gathers per second of table[idx[k]] (lpa_gather_rate); idx and
-        table are u32/int32 device tensors."""
-        import torch
-        for t, nm in ((idx, "idx"), (table, "table")):
-            if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
-                raise ValueError(f"{nm}: a contiguous int32 device tensor is required")
-        out = ctypes.c_double(0.0)
-        rc = _load().lpa_gather_rate(self._h, idx.data_ptr(), idx.numel(), table.data_ptr(), table.numel(), reps,
-                                     ctypes.byref(out))
-        if rc:
-            raise LpaError(rc, "lpa_gather_rate")
-        return out.value
 
     def profile_reset(self):
         rc = _load().lpa_profile_reset(self._h)

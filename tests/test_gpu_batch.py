@@ -198,3 +198,23 @@ def test_errors(gg, lpa, ctx):
     e0 = lpa.DeviceGraph.from_csr(gg.from_csr_arrays(0, [0], []), "cuda")
     lab, st = ctx.run_batch(e0, [0])
     assert st.graphs == 0 and st.rounds == 0
+
+
+def test_barrier_timeout_every_block_leaves(gg, orc, lpa, ctx):
+    """A grid-wide wait of the persistent kernel that passes its limit ends
+    the launch with LPA_ETIMEDOUT: a 1 us limit, set from the host, is far
+    shorter than block 0's set-up of round 1 for 4096 graphs, so the other
+    blocks give up at the first barrier; every block leaves (the call
+    returns), and a later run on the same data is exact again."""
+    b = gg.sbm_batch(G=4096, n_min=50, n_max=400, seed=21)
+    say("[batch] timeout test G=4096", b.csr.n, b.csr.m)
+    dg = lpa.DeviceGraph.from_csr(b.csr, "cuda")
+    with lpa.Context(0, barrier_timeout_us=1) as short:
+        with pytest.raises(lpa.LpaError) as ei:
+            short.run_batch(dg, b.gv)
+        assert ei.value.code == lpa.LPA_ETIMEDOUT
+        with pytest.raises(lpa.LpaError) as ei:  # the captured graph replays the same way
+            short.run_batch(dg, b.gv)
+        assert ei.value.code == lpa.LPA_ETIMEDOUT
+    lab, st = run_batch(lpa, ctx, b)
+    check_graphs(orc, b, lab, st, range(0, b.G, 97), 0.05, 20)

@@ -60,6 +60,8 @@ def assert_same(orc, lpa, ctx, g, tol=0.05, max_iter=20, sw=1, **opts):
     assert st.converged == ref.converged
     mism = np.flatnonzero(lab != ref.labels)
     assert mism.size == 0, f"{g.name}: {mism.size} labels differ, first {mism[:8]}"
+    if not opts.get("frontier"):  # every round votes every arc
+        assert st.arcs_processed == g.m * st.iterations, (g.name, st.arcs_processed, g.m, st.iterations)
     return ref, lab, st
 
 

@@ -417,3 +417,30 @@ def test_oracle_rejects_bad_input(gg, orc):
     assert ok.labels.tolist() == [1, 0]
     with pytest.raises(orc.OracleError):
         orc.rak(gg.from_edges(3, [(0, 1)]), tol=1.5)
+
+
+# ------------------------------------------------ OpenMP build of the oracle --
+
+@pytest.mark.parametrize("make", [
+    lambda gg: gg.rmat(14, seed=14),
+    lambda gg: gg.with_weights(gg.rmat(13, seed=5), 9, 1, 6),
+    lambda gg: gg.road(256, 256, 0.3, 0.01, 1, 8, seed=7),
+    lambda gg: gg.sbm(2000, 20, 0.1, 0.005, seed=3),
+])
+def test_parallel_oracle_equals_sequential(make):
+    """The OpenMP build of the same source (the paper's OpenMP RAK, Section
+    3.2: a round's vertices shared among threads, a vote buffer per thread)
+    gives the sequential labels and changed counts bit for bit: synchronous
+    rounds only read the previous round's labels."""
+    import graphgen as gg
+    import oracle
+    g = make(gg)
+    for sw in (0, 1):
+        seq = oracle.rak(g, tol=0.0, max_iter=12, self_weight=sw)
+        par = oracle.rak(g, tol=0.0, max_iter=12, self_weight=sw, parallel=True)
+        assert np.array_equal(seq.labels, par.labels)
+        assert seq.changed == par.changed and seq.iterations == par.iterations
+        lab, ch = oracle.rak_round(g, seq.labels, self_weight=sw, parallel=True)
+        lab2, ch2 = oracle.rak_round(g, seq.labels, self_weight=sw)
+        assert ch == ch2 and np.array_equal(lab, lab2)
+    assert oracle.threads(True) >= 1 and oracle.threads(False) == 1
