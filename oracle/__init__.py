@@ -66,6 +66,17 @@ def _load(parallel: bool = False):
         lib.orc_rak_masked.restype = ctypes.c_int
         lib.orc_modularity.argtypes = [u32, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.orc_modularity.restype = ctypes.c_int
+        lib.orc_rak_ext.argtypes = [u32, vp, vp, vp, u32, dbl, u32, vp, ctypes.c_int, ctypes.c_int, u64, vp, vp,
+                                    vp, vp, vp]
+        lib.orc_rak_ext.restype = ctypes.c_int
+        lib.orc_splitmix64_at.argtypes = [u64, u64]
+        lib.orc_splitmix64_at.restype = u64
+        lib.orc_lowbias32.argtypes = [u32]
+        lib.orc_lowbias32.restype = u32
+        lib.orc_half_of.argtypes = [u64, u32, u32]
+        lib.orc_half_of.restype = ctypes.c_int
+        lib.orc_tie_key.argtypes = [u64, u32, u32]
+        lib.orc_tie_key.restype = u32
         lib.orc_threads.argtypes = []
         lib.orc_threads.restype = ctypes.c_int
         _libs[parallel] = lib
@@ -113,6 +124,52 @@ def rak(g, tol: float = 0.05, max_iter: int = 20, self_weight: int = 1,
     if rc:
         raise OracleError(rc)
     return RakResult(out, int(it.value), bool(cv.value), [int(x) for x in ch[: it.value]])
+
+
+def rak_ext(g, tol: float = 0.05, max_iter: int = 20, self_weight: int = 1, order: str = "sync",
+            tie: str = "lowest", seed: int = 0, halves: np.ndarray | None = None,
+            init_labels: np.ndarray | None = None, parallel: bool = False) -> RakResult:
+    """RAK (Section 3.2) with a choice of update order -- "sync" (round t
+    reads round t-1) or "semisync" (two half-rounds per round over the
+    vertices of each half, drawn from `seed` every round, or the split
+    `halves` in every round) -- and of
+    tie-break -- "lowest" (strict) or "hash" (non-strict, reproducible from
+    `seed`)."""
+    if order not in ("sync", "semisync") or tie not in ("lowest", "hash"):
+        raise ValueError("order: sync|semisync, tie: lowest|hash")
+    rp, col, w = _arrs(g)
+    out = np.empty(g.n, dtype=np.uint32)
+    ch = np.zeros(max(max_iter, 1), dtype=np.uint64)
+    it = ctypes.c_uint32(0)
+    cv = ctypes.c_int32(0)
+    init = None if init_labels is None else np.ascontiguousarray(init_labels, dtype=np.uint32)
+    hv = None if halves is None else np.ascontiguousarray(halves, dtype=np.uint8)
+    rc = _load(parallel).orc_rak_ext(g.n, rp.ctypes.data, col.ctypes.data, _p(w), self_weight, float(tol),
+                                     max_iter, _p(init), 1 if order == "semisync" else 0, 1 if tie == "hash" else 0,
+                                     int(seed) & ((1 << 64) - 1), _p(hv), out.ctypes.data, ch.ctypes.data,
+                                     ctypes.byref(it), ctypes.byref(cv))
+    if rc:
+        raise OracleError(rc)
+    return RakResult(out, int(it.value), bool(cv.value), [int(x) for x in ch[: it.value]])
+
+
+def splitmix64_at(seed: int, c: int) -> int:
+    """Output number c+1 of SplitMix64 started from state `seed`."""
+    return int(_load().orc_splitmix64_at(seed & ((1 << 64) - 1), c & ((1 << 64) - 1)))
+
+
+def lowbias32(x: int) -> int:
+    return int(_load().orc_lowbias32(x & 0xFFFFFFFF))
+
+
+def half_of(seed: int, t: int, v: int) -> int:
+    """Half (0/1) of vertex v in round t of a semi-synchronous run."""
+    return int(_load().orc_half_of(seed & ((1 << 64) - 1), t, v))
+
+
+def tie_key(seed: int, t: int, v: int) -> int:
+    """Tie key of vertex v in round t (non-strict votes)."""
+    return int(_load().orc_tie_key(seed & ((1 << 64) - 1), t, v))
 
 
 def rak_round(g, labels: np.ndarray, self_weight: int = 1, active: np.ndarray | None = None,

@@ -35,6 +35,23 @@
  * The vote is the textbook definition: gather (label, weight) pairs of the
  * closed neighbourhood, sort them by label, add up equal labels, keep the
  * heaviest (lowest label on ties).
+ *
+ * Two further forms (orc_rak_ext):
+ *  - non-strict tie-break (Section 3.2: a random one of the tied labels),
+ *    made reproducible: every label gets the priority lowbias32(label ^ k),
+ *    k drawn per (seed, round t, vertex v) from SplitMix64, and the tied
+ *    label of highest priority wins.  lowbias32 is a bijection of 32-bit
+ *    words, so distinct labels never share a priority;
+ *  - semi-synchronous rounds, a deterministic stand-in for the paper's
+ *    in-place OpenMP updates and COPRA's asynchronous order (Sections 3.2,
+ *    3.3): each round is two half-rounds; half h votes the vertices of half
+ *    h (the top bit of a SplitMix64 draw per vertex and round, or a given
+ *    split kept for every round) reading the labels left by the half before,
+ *    the other vertices keep theirs.  A vertex votes once per round, so
+ *    changed_t still counts the vertices whose label differs from round t-1.
+ *    The split is drawn again every round: two neighbours that are each
+ *    other's heaviest neighbour swap labels while they share a half, and a
+ *    fixed split would keep such pairs swapping forever.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -69,13 +86,50 @@ static int check_csr(uint32_t n, const uint64_t *rp, const uint32_t *col, const 
     return 0;
 }
 
+/* SplitMix64 (G. Steele, D. Lea, C. Flood, "Fast splittable pseudorandom
+ * number generators", OOPSLA 2014): output number c + 1 (c >= 0) of the
+ * generator started from state `seed`, i.e. the mix of seed + (c+1)*gamma. */
+uint64_t orc_splitmix64_at(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (c + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* lowbias32 (C. Wellons, "Prospecting for Hash Functions", 2018): a
+ * bijection of 32-bit words. */
+uint32_t orc_lowbias32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+/* The draws of vertex v in round t >= 1 are SplitMix64 outputs number
+ * 2c + 1 and 2c + 2 for c = t * 2^32 + v: the first decides the half of a
+ * semi-synchronous round (its top bit), the second gives the tie key. */
+int orc_half_of(uint64_t seed, uint32_t t, uint32_t v) {
+    return (int)(orc_splitmix64_at(seed, ((((uint64_t)t << 32) | v) << 1)) >> 63);
+}
+
+/* Tie key k of vertex v in round t >= 1 (non-strict votes). */
+uint32_t orc_tie_key(uint64_t seed, uint32_t t, uint32_t v) {
+    return (uint32_t)orc_splitmix64_at(seed, ((((uint64_t)t << 32) | v) << 1) | 1u);
+}
+
+/* How a vote breaks ties: strict (the lowest tied label) or hashed (the
+ * tied label of highest priority lowbias32(label ^ k)). */
+typedef struct { int hashed; uint32_t k; } tie_rule;
+
 /* The label vertex v takes from L_old.  buf must hold deg(v)+1 pairs.
  * When top1/top2 are given they receive the winning tally and the largest
  * tally of any other label (0 when there is none; both 0 for an empty
  * vote). */
-static uint32_t vote(uint32_t v, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
-                     uint32_t self_weight, const uint32_t *L_old, pair_lw *buf, uint64_t *top1,
-                     uint64_t *top2) {
+static uint32_t vote_tie(uint32_t v, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                         uint32_t self_weight, const uint32_t *L_old, pair_lw *buf, uint64_t *top1,
+                         uint64_t *top2, tie_rule tie) {
     uint64_t k = 0;
     if (self_weight > 0) {
         buf[k].label = L_old[v];
@@ -99,9 +153,15 @@ static uint32_t vote(uint32_t v, const uint64_t *rp, const uint32_t *col, const 
         uint32_t lab = buf[i].label;
         uint64_t sum = 0;
         while (i < k && buf[i].label == lab) sum += buf[i++].weight;
-        /* labels arrive in increasing order, so a strictly larger sum is
-         * needed to displace the current best: ties keep the lower label */
-        if (!have || sum > best_weight) {
+        /* labels arrive in increasing order, so under the strict rule a
+         * strictly larger sum is needed to displace the current best: ties
+         * keep the lower label.  The hashed rule lets a tied label with a
+         * higher priority take over. */
+        int wins = !have || sum > best_weight;
+        if (have && sum == best_weight && tie.hashed &&
+            orc_lowbias32(lab ^ tie.k) > orc_lowbias32(best_label ^ tie.k))
+            wins = 1;
+        if (wins) {
             if (have) second_weight = best_weight;
             best_label = lab;
             best_weight = sum;
@@ -113,6 +173,13 @@ static uint32_t vote(uint32_t v, const uint64_t *rp, const uint32_t *col, const 
     if (top1) *top1 = best_weight;
     if (top2) *top2 = second_weight;
     return best_label;
+}
+
+static uint32_t vote(uint32_t v, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                     uint32_t self_weight, const uint32_t *L_old, pair_lw *buf, uint64_t *top1,
+                     uint64_t *top2) {
+    tie_rule strict = {0, 0};
+    return vote_tie(v, rp, col, w, self_weight, L_old, buf, top1, top2, strict);
 }
 
 static uint64_t max_degree(uint32_t n, const uint64_t *rp) {
@@ -131,9 +198,9 @@ static uint64_t max_degree(uint32_t n, const uint64_t *rp) {
  * every thread a separately allocated hashtable (Section 3.2).  A round only
  * reads L_old and each vertex writes only its own L_new entry, so the result
  * does not depend on the number of threads. */
-int64_t orc_rak_round(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
-                      uint32_t self_weight, const uint32_t *L_old, uint32_t *L_new,
-                      const uint8_t *active) {
+static int64_t round_tie(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                         uint32_t self_weight, const uint32_t *L_old, uint32_t *L_new, const uint8_t *active,
+                         int hashed, uint64_t seed, uint32_t t) {
     const size_t cap = (size_t)(max_degree(n, rp) + 1);
     int64_t changed = 0;
     int failed = 0;
@@ -146,8 +213,10 @@ int64_t orc_rak_round(uint32_t n, const uint64_t *rp, const uint32_t *col, const
 #pragma omp for schedule(dynamic, 1024)
             for (int64_t i = 0; i < (int64_t)n; ++i) {
                 uint32_t v = (uint32_t)i;
-                uint32_t lab = (active && !active[v]) ? L_old[v]
-                                                      : vote(v, rp, col, w, self_weight, L_old, buf, NULL, NULL);
+                tie_rule tie = {hashed, hashed ? orc_tie_key(seed, t, v) : 0u};
+                uint32_t lab = (active && !active[v])
+                                   ? L_old[v]
+                                   : vote_tie(v, rp, col, w, self_weight, L_old, buf, NULL, NULL, tie);
                 L_new[v] = lab;
                 changed += (lab != L_old[v]);
             }
@@ -155,6 +224,12 @@ int64_t orc_rak_round(uint32_t n, const uint64_t *rp, const uint32_t *col, const
         }
     }
     return failed ? -3 : changed;
+}
+
+int64_t orc_rak_round(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                      uint32_t self_weight, const uint32_t *L_old, uint32_t *L_new,
+                      const uint8_t *active) {
+    return round_tie(n, rp, col, w, self_weight, L_old, L_new, active, 0, 0, 0);
 }
 
 /* Threads a round of orc_rak_round may use (1 without OpenMP). */
@@ -224,6 +299,62 @@ int orc_rak(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t 
     memcpy(labels_out, a, (size_t)n * sizeof(uint32_t));
     free(a);
     free(b);
+    return 0;
+}
+
+/* RAK with a choice of update order and tie-break (see the header).
+ *   order: 0 synchronous rounds, 1 semi-synchronous rounds;
+ *   hashed: 0 strict (lowest tied label), 1 hashed priorities (non-strict);
+ *   seed: draws of both; halves: NULL, or n entries in {0, 1}: a split used
+ *   in every round instead of the drawn ones.
+ * Other arguments and the return value as orc_rak. */
+int orc_rak_ext(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                uint32_t self_weight, double tol, uint32_t max_iter, const uint32_t *init_labels,
+                int order, int hashed, uint64_t seed, const uint8_t *halves, uint32_t *labels_out,
+                uint64_t *changed_per_iter, uint32_t *iterations, int32_t *converged) {
+    if (!(tol >= 0.0 && tol <= 1.0) || !labels_out || !iterations || !converged) return -1;
+    if (n > 0xFFFFFFFEu || order < 0 || order > 1) return -1;
+    int rc = check_csr(n, rp, col, w, self_weight);
+    if (rc) return rc;
+    if (init_labels)
+        for (uint32_t v = 0; v < n; ++v)
+            if (init_labels[v] >= n) return -1;
+    const uint64_t thr = (uint64_t)floor(tol * (double)n);
+    uint32_t *a = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    uint32_t *b = (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    uint8_t *m0 = (uint8_t *)malloc((size_t)(n ? n : 1));
+    uint8_t *m1 = (uint8_t *)malloc((size_t)(n ? n : 1));
+    if (!a || !b || !m0 || !m1) { free(a); free(b); free(m0); free(m1); return -3; }
+    for (uint32_t v = 0; v < n; ++v) a[v] = init_labels ? init_labels[v] : v;
+    *iterations = 0;
+    *converged = 0;
+    for (uint32_t t = 1; t <= max_iter; ++t) {
+        int64_t ch;
+        if (order == 1)
+            for (uint32_t v = 0; v < n; ++v) {
+                int h = halves ? (halves[v] != 0) : orc_half_of(seed, t, v);
+                m0[v] = (uint8_t)(h == 0);
+                m1[v] = (uint8_t)(h == 1);
+            }
+        if (order == 0) {
+            ch = round_tie(n, rp, col, w, self_weight, a, b, NULL, hashed, seed, t);
+            if (ch >= 0) { uint32_t *s = a; a = b; b = s; }
+        } else {
+            ch = round_tie(n, rp, col, w, self_weight, a, b, m0, hashed, seed, t);
+            if (ch >= 0) {
+                uint32_t *s = a; a = b; b = s;
+                int64_t ch1 = round_tie(n, rp, col, w, self_weight, a, b, m1, hashed, seed, t);
+                if (ch1 < 0) ch = ch1;
+                else { s = a; a = b; b = s; ch += ch1; }
+            }
+        }
+        if (ch < 0) { free(a); free(b); free(m0); free(m1); return (int)ch; }
+        if (changed_per_iter) changed_per_iter[t - 1] = (uint64_t)ch;
+        *iterations = t;
+        if ((uint64_t)ch <= thr) { *converged = 1; break; }
+    }
+    memcpy(labels_out, a, (size_t)n * sizeof(uint32_t));
+    free(a); free(b); free(m0); free(m1);
     return 0;
 }
 

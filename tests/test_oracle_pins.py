@@ -444,3 +444,221 @@ def test_parallel_oracle_equals_sequential(make):
         lab2, ch2 = oracle.rak_round(g, seq.labels, self_weight=sw)
         assert ch == ch2 and np.array_equal(lab, lab2)
     assert oracle.threads(True) >= 1 and oracle.threads(False) == 1
+
+
+# ------------------------- non-strict (hashed) ties and semi-synchronous rounds --
+
+def brute_round_ext(E, A, L, sw, active=None, prio=None):
+    """Definition-level vote over every label value 0..n-1 (dense), for the
+    vertices with active[v] (all when None); the heaviest label present wins,
+    ties going to the highest prio(v, label) (None: the lowest label)."""
+    n = len(L)
+    new = list(L)
+    for v in range(n):
+        if active is not None and not active[v]:
+            continue
+        best, best_key = None, None
+        for lab in range(n):
+            present = sw > 0 and L[v] == lab
+            tally = sw if present else 0
+            for u in range(n):
+                if E[v, u] and L[u] == lab:
+                    present = True
+                    tally += A[v, u]
+            if not present:
+                continue
+            key = (tally, -lab if prio is None else prio(v, lab))
+            if best_key is None or key > best_key:
+                best, best_key = lab, key
+        new[v] = L[v] if best is None else best
+    return new
+
+
+def brute_run_ext(E, A, sw, tol, max_iter, halves_t=None, prio_t=None):
+    """Rounds of brute_round_ext; halves_t(t) gives round t's split (None:
+    synchronous rounds), prio_t(t, v, label) the tie priorities."""
+    n = E.shape[0]
+    L = list(range(n))
+    thr = math.floor(tol * n)
+    changed = []
+    for t in range(1, max_iter + 1):
+        prio = None if prio_t is None else (lambda v, lab, t=t: prio_t(t, v, lab))
+        if halves_t is None:
+            N = brute_round_ext(E, A, L, sw, None, prio)
+        else:
+            halves = halves_t(t)
+            M = brute_round_ext(E, A, L, sw, [h == 0 for h in halves], prio)
+            N = brute_round_ext(E, A, M, sw, [h == 1 for h in halves], prio)
+        ch = sum(1 for a, b in zip(L, N) if a != b)
+        changed.append(ch)
+        L = N
+        if ch <= thr:
+            return L, changed, True
+    return L, changed, False
+
+
+def test_splitmix64_known_answers(orc):
+    # the first outputs of SplitMix64 started from state 0, as published with
+    # the generator's reference code
+    assert [orc.splitmix64_at(0, c) for c in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                          0x06C45D188009454F]
+
+
+def test_lowbias32_inverts_with_published_inverse(orc):
+    # the inverse published with lowbias32 recovers every input: a bijection,
+    # so two labels never share a tie priority
+    M = 0xFFFFFFFF
+
+    def inv(x):
+        x ^= x >> 16
+        x = x * 0x43021123 & M
+        x ^= (x >> 15) ^ (x >> 30)
+        x = x * 0x1D69E2A5 & M
+        x ^= x >> 16
+        return x
+
+    xs = [0, 1, 2, M, 0x80000000] + [int(x) for x in np.random.default_rng(1).integers(0, 1 << 32, 3000)]
+    assert all(inv(orc.lowbias32(x)) == x for x in xs)
+    assert len({orc.lowbias32(x) for x in range(1 << 12)}) == 1 << 12
+
+
+def hashed_prio(orc, seed):
+    return lambda t, v, lab: orc.lowbias32(lab ^ orc.tie_key(seed, t, v))
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_hashed_tie_brute_force_small_graphs(gg, orc, n):
+    """Every graph on n <= 5 vertices: the oracle's non-strict votes equal the
+    dense voter that breaks ties by the highest priority."""
+    rng = np.random.default_rng(n)
+    for edges in all_graphs(n):
+        g = gg.from_edges(n, edges)
+        E, A = dense(g)
+        for sw in (0, 1):
+            seed = int(rng.integers(0, 1 << 63))
+            L, ch, conv = brute_run_ext(E, A, sw, 0.0, 6, None, hashed_prio(orc, seed))
+            r = orc.rak_ext(g, tol=0.0, max_iter=6, self_weight=sw, tie="hash", seed=seed)
+            assert r.labels.tolist() == L and r.changed == ch and r.converged == conv, (edges, sw)
+
+
+def test_hashed_tie_picks_uniformly(gg, orc):
+    """Non-strict mode picks a random one of the tied labels (Section 3.2):
+    the centre of a star K_{1,5} with self weight 0 sees five labels of
+    tally 1; over 3000 seeds each wins about a fifth of the time (chi-square,
+    4 degrees of freedom, 0.1 % level 18.5), and the strict mode always takes
+    the lowest."""
+    g = gg.from_edges(6, [(0, i) for i in range(1, 6)])
+    wins = np.zeros(6, int)
+    for seed in range(3000):
+        lab, _ = orc.rak_ext(g, tol=1.0, max_iter=1, self_weight=0, tie="hash", seed=seed).labels, 0
+        wins[int(lab[0])] += 1
+    assert wins[0] == 0 and wins.sum() == 3000
+    exp = 3000 / 5
+    chi2 = float(((wins[1:] - exp) ** 2 / exp).sum())
+    assert chi2 < 18.5, wins
+    assert orc.rak_ext(g, tol=1.0, max_iter=1, self_weight=0).labels[0] == 1
+
+
+def test_hashed_equals_strict_without_ties(gg, orc):
+    """With self weight 0 and distinct powers of two as edge weights no two
+    labels ever tie, so the non-strict and strict modes agree."""
+    rng = np.random.default_rng(3)
+    for trial in range(40):
+        n = int(rng.integers(4, 12))
+        pairs = [p for p in itertools.combinations(range(n), 2) if rng.random() < 0.4][:30]
+        if not pairs:
+            continue
+        g = gg.from_edges(n, pairs)
+        wmap = {}
+        for i, (a, b) in enumerate(pairs):
+            wmap[(a, b)] = wmap[(b, a)] = 1 << i
+        src = np.repeat(np.arange(n), np.diff(g.row_ptr).astype(np.int64))
+        g.w = np.array([wmap[(int(s), int(d))] for s, d in zip(src, g.col)], dtype=np.uint32)
+        a = orc.rak_ext(g, tol=0.0, max_iter=8, self_weight=0, tie="hash", seed=trial)
+        b = orc.rak(g, tol=0.0, max_iter=8, self_weight=0)
+        assert np.array_equal(a.labels, b.labels) and a.changed == b.changed
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_semisync_brute_force_small_graphs(gg, orc, n):
+    """Every graph on n <= 5 vertices, under a random split kept for every
+    round and under the splits drawn per round: the oracle's semi-synchronous
+    rounds equal two dense half-rounds per round, the second reading the
+    labels the first left."""
+    rng = np.random.default_rng(10 + n)
+    for edges in all_graphs(n):
+        g = gg.from_edges(n, edges)
+        E, A = dense(g)
+        for sw in (0, 1):
+            halves = rng.integers(0, 2, n).astype(np.uint8)
+            L, ch, conv = brute_run_ext(E, A, sw, 0.0, 6, lambda t: halves.tolist())
+            r = orc.rak_ext(g, tol=0.0, max_iter=6, self_weight=sw, order="semisync", halves=halves)
+            assert r.labels.tolist() == L and r.changed == ch and r.converged == conv, (edges, sw, halves)
+            seed = int(rng.integers(0, 1 << 63))  # halves drawn every round, and hashed ties
+            L, ch, conv = brute_run_ext(E, A, sw, 0.0, 6, lambda t: [orc.half_of(seed, t, v) for v in range(n)],
+                                        hashed_prio(orc, seed))
+            r = orc.rak_ext(g, tol=0.0, max_iter=6, self_weight=sw, order="semisync", tie="hash", seed=seed)
+            assert r.labels.tolist() == L and r.changed == ch, (edges, sw, seed)
+
+
+def test_semisync_closed_forms(gg, orc):
+    # K2, self weight 0: in different halves the first mover takes the other's
+    # label and the pair agrees; in the same half they swap forever
+    g = gg.from_edges(2, [(0, 1)])
+    r = orc.rak_ext(g, tol=0.0, max_iter=6, self_weight=0, order="semisync", halves=np.array([0, 1], np.uint8))
+    assert r.labels.tolist() == [1, 1] and r.changed == [1, 0] and r.converged
+    r = orc.rak_ext(g, tol=0.0, max_iter=6, self_weight=0, order="semisync", halves=np.array([1, 1], np.uint8))
+    assert r.changed == [2] * 6 and not r.converged
+    # path P_n, self weight 1, even vertices in the first half: even i >= 2
+    # takes i-1, odd vertices keep theirs except an odd last vertex, which
+    # ties and takes its neighbour's new label; stable from round 2
+    for n in range(2, 12):
+        g = gg.from_edges(n, [(i, i + 1) for i in range(n - 1)])
+        halves = np.array([i % 2 for i in range(n)], np.uint8)
+        want = [i - 1 if (i % 2 == 0 and i >= 2) else i for i in range(n)]
+        if (n - 1) % 2 == 1:
+            want[n - 1] = want[n - 2]
+        r = orc.rak_ext(g, tol=0.0, max_iter=10, self_weight=1, order="semisync", halves=halves)
+        ch1 = sum(1 for i in range(n) if want[i] != i)
+        assert r.labels.tolist() == want and r.changed == [ch1, 0], n
+
+
+def test_semisync_with_one_half_is_synchronous(gg, orc):
+    """If every vertex is in the first half the second half-round is empty
+    and a semi-synchronous round is a synchronous one."""
+    for g in (gg.rmat(11, seed=2), gg.with_weights(gg.road(40, 40, 0.3, 0.01, 1, 8, seed=3), 1, 1, 8)):
+        for tie in ("lowest", "hash"):
+            a = orc.rak_ext(g, tol=0.0, max_iter=10, order="semisync", tie=tie, seed=9,
+                            halves=np.zeros(g.n, np.uint8))
+            b = orc.rak_ext(g, tol=0.0, max_iter=10, tie=tie, seed=9)
+            assert np.array_equal(a.labels, b.labels) and a.changed == b.changed
+
+
+def test_semisync_converges_on_road_lattice(gg, orc):
+    """The motivation for the semi-synchronous order: on a road-like lattice
+    synchronous rounds keep swapping labels (nearly every vertex changes in
+    every round), while two half-rounds per round settle; the drawn halves
+    split the vertices about evenly, independently from round to round.  A
+    split kept fixed leaves the pairs of mutually heaviest neighbours that
+    share a half swapping forever."""
+    g = gg.road(128, 128, 0.3, 0.01, 1, 8, seed=11)
+    s = orc.rak_ext(g, tol=0.05, max_iter=20)
+    h = orc.rak_ext(g, tol=0.05, max_iter=20, order="semisync", seed=11)
+    assert not s.converged and min(s.changed) > 0.5 * g.n
+    assert h.converged and h.iterations <= 8
+    assert orc.modularity(g, h.labels).q > 0.6
+    h1 = np.array([orc.half_of(11, 1, v) for v in range(g.n)])
+    h2 = np.array([orc.half_of(11, 2, v) for v in range(g.n)])
+    assert abs(int(h1.sum()) - g.n / 2) < 4 * math.sqrt(g.n)
+    assert abs(int((h1 == h2).sum()) - g.n / 2) < 4 * math.sqrt(g.n)
+    fixed = orc.rak_ext(g, tol=0.05, max_iter=20, order="semisync", halves=h1.astype(np.uint8))
+    assert not fixed.converged
+
+
+def test_parallel_oracle_ext_equals_sequential(gg, orc):
+    g = gg.with_weights(gg.rmat(13, seed=8), 2, 1, 4)
+    for order in ("sync", "semisync"):
+        for tie in ("lowest", "hash"):
+            a = orc.rak_ext(g, tol=0.0, max_iter=8, order=order, tie=tie, seed=77)
+            b = orc.rak_ext(g, tol=0.0, max_iter=8, order=order, tie=tie, seed=77, parallel=True)
+            assert np.array_equal(a.labels, b.labels) and a.changed == b.changed
