@@ -106,7 +106,31 @@ typedef struct {
                                     a grid-wide barrier of the persistent
                                     kernel before the launch gives up with
                                     LPA_ETIMEDOUT (0 = the default, 10 s) */
+    uint32_t order;        /* LPA_ORDER_SYNC (default): round t reads only
+                              round t-1's labels.  LPA_ORDER_SEMISYNC: each
+                              round is two half-rounds; a vertex's half is the
+                              top bit of SplitMix64 output number 2c + 1 from
+                              state `seed`, c = t * 2^32 + v, drawn again every
+                              round; the first half's vertices vote, then the
+                              second half's vertices vote reading the labels
+                              the first left, and every vertex keeps its label
+                              in the other half.  A deterministic stand-in for
+                              the paper's in-place OpenMP updates and COPRA's
+                              asynchronous order (Sections 3.2, 3.3); it
+                              settles where synchronous rounds swap labels
+                              back and forth (nearly bipartite graphs) */
+    uint32_t tie;          /* LPA_TIE_LOWEST (default): the strict mode of
+                              Section 3.2, "the first" tied label read as the
+                              lowest label.  LPA_TIE_HASH: the non-strict mode
+                              (a random tied label) made reproducible: label
+                              x scores lowbias32(x ^ k), k = the low 32 bits
+                              of SplitMix64 output number 2c + 2 (c as above),
+                              and the tied label of highest score wins */
+    uint64_t seed;         /* draws of order and tie (any value) */
 } lpa_options;
+
+enum { LPA_ORDER_SYNC = 0, LPA_ORDER_SEMISYNC = 1 };
+enum { LPA_TIE_LOWEST = 0, LPA_TIE_HASH = 1 };
 
 /* Run statistics.  The arrays are optional and owned by the caller; when
  * given they receive min(iterations, cap) entries. */
@@ -152,7 +176,10 @@ void lpa_default_options(lpa_options *opt);
  * defaults.  Invalid option values give LPA_EINVAL. */
 lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *opt);
 
-/* RAK from the unique initial labels L0(v) = v (Section 3.2).
+/* RAK from the unique initial labels L0(v) = v (Section 3.2), in the
+ * context's update order and tie-break (lpa_options.order, .tie); a context
+ * with order or tie set and frontier = 1 gives LPA_EUNSUPPORTED (as do
+ * lpa_run_batch, lpa_run_learned and lpa_trace on such a context).
  * labels_out: device u32[n], receives the labels after the last round.
  * tol in [0, 1]; max_iter = 0 returns the initial labels.
  * The run works on a relabelled device copy of the CSR (vertices grouped by

@@ -123,7 +123,7 @@ __device__ uint32_t unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, ui
                 for (uint32_t s = lane; s < S; s += 64) {
                     const u64 x = T[s];
                     if (x != EMPTY_SLOT) {
-                        best = umax64(best, slot_key(x));
+                        best = umax64(best, slot_key(kStrict, x));
                         T[s] = EMPTY_SLOT;
                     }
                 }
@@ -143,7 +143,7 @@ __device__ uint32_t unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, ui
             const uint32_t s = tl[p];
             if (s != kNone) {
                 best = umax64(best,
-                              slot_key(__hip_atomic_load(&slab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                              slot_key(kStrict, __hip_atomic_load(&slab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
                 __hip_atomic_store(&slab[s], EMPTY_SLOT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -155,8 +155,8 @@ __device__ uint32_t unit_wave(const BatchArgs &b, const RoundArgs &a, u64 *T, ui
     rs = wave_sum(rs);
     bool ch = false;
     if (lane == 0) {
-        if (own_hit || a.sw) best = umax64(best, vote_key(own, own_w + a.sw));
-        const uint32_t nl = best ? ~(uint32_t)best : own;
+        if (own_hit || a.sw) best = umax64(best, vote_key(kStrict, own, own_w + a.sw));
+        const uint32_t nl = best ? key_label(kStrict, best) : own;
         a.L_new[v] = nl;
         ch = nl != own;
         if (round1 && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
@@ -222,13 +222,13 @@ __device__ void units_thread(const BatchArgs &b, const RoundArgs &a, const UnitP
                     tl[j] += wt[k][i];
                     tl[i] += wt[k][j];
                 }
-        u64 best = a.sw ? vote_key(own[k], a.sw) : 0ull;
+        u64 best = a.sw ? vote_key(kStrict, own[k], a.sw) : 0ull;
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            if (valid[k] >> j & 1u) best = umax64(best, vote_key(lab[k][j], tl[j]));
+            if (valid[k] >> j & 1u) best = umax64(best, vote_key(kStrict, lab[k][j], tl[j]));
         bool c = false;
         if (act[k]) {
-            const uint32_t nl = best ? ~(uint32_t)best : own[k];
+            const uint32_t nl = best ? key_label(kStrict, best) : own[k];
             a.L_new[v[k]] = nl;
             c = nl != own[k];
             if (round1 && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
@@ -278,7 +278,7 @@ __device__ void units_group(const BatchArgs &b, const RoundArgs &a, u64 *T, cons
         for (uint32_t s = gl; s < S; s += G) {
             const u64 x = Tg[s];
             if (x != EMPTY_SLOT) {
-                best = umax64(best, slot_key(x));
+                best = umax64(best, slot_key(kStrict, x));
                 Tg[s] = EMPTY_SLOT;
             }
         }
@@ -288,8 +288,8 @@ __device__ void units_group(const BatchArgs &b, const RoundArgs &a, u64 *T, cons
         rs = row_sum64(rs);
         bool c = false;
         if (act[k] && gl == 0) {
-            if (own_hit || a.sw) best = umax64(best, vote_key(own[k], own_w + a.sw));
-            const uint32_t nl = best ? ~(uint32_t)best : own[k];
+            if (own_hit || a.sw) best = umax64(best, vote_key(kStrict, own[k], own_w + a.sw));
+            const uint32_t nl = best ? key_label(kStrict, best) : own[k];
             a.L_new[v[k]] = nl;
             c = nl != own[k];
             if (round1 && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
@@ -581,6 +581,11 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
         a.top1 = a.top2 = nullptr;
         a.skip_distinct = 0;
         a.insum = nullptr;
+        a.half = 0;  // synchronous rounds, strict ties
+        a.tie = 0;
+        a.t = t;
+        a.seed = 0;
+        a.orig = nullptr;
         const bool round1 = t == 1;
         // this block's share of every bin, [lo, hi), and the segment of its
         // first unit: lane k of each wavefront works out bin k

@@ -20,6 +20,41 @@ __device__ __forceinline__ uint32_t hmix(uint32_t x) {
     return x;
 }
 
+// Inverse of hmix (published with lowbias32).
+__device__ __forceinline__ uint32_t hmix_inv(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x43021123u;
+    x ^= (x >> 15) ^ (x >> 30);
+    x *= 0x1d69e2a5u;
+    x ^= x >> 16;
+    return x;
+}
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output number c + 1 of the
+// generator started from state `seed`.
+__device__ __forceinline__ unsigned long long splitmix64_at(unsigned long long seed, unsigned long long c) {
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (c + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Vote keys.  A candidate label is scored (tally << 32) | code(label), so one
+// unsigned max picks the heaviest label and, among equal tallies, the one
+// with the largest code.  Strict ties (Section 3.2, "the first" tied label,
+// read as the lowest): code = ~label.  Hashed ties (the non-strict mode made
+// reproducible): code = lowbias32(label ^ k) with a key k per vertex and
+// round; lowbias32 is a bijection, so codes never collide and decode back.
+// `hashed` comes from a kernel argument (uniform), `k` is per row.
+struct Tie {
+    uint32_t hashed;
+    uint32_t k;
+};
+__device__ __forceinline__ uint32_t tie_code(Tie t, uint32_t lab) { return t.hashed ? hmix(lab ^ t.k) : ~lab; }
+__device__ __forceinline__ uint32_t tie_label(Tie t, uint32_t code) {
+    return t.hashed ? hmix_inv(code) ^ t.k : ~code;
+}
+
 // Make this wavefront's LDS writes visible to its other lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -29,10 +64,15 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a > b ? a : b; }
 
-// slot (label << 32 | tally)  ->  vote key (tally << 32 | ~label)
-__device__ __forceinline__ u64 slot_key(u64 x) { return (x << 32) | (uint32_t)~(uint32_t)(x >> 32); }
+// slot (label << 32 | tally)  ->  vote key (tally << 32 | code(label))
+__device__ __forceinline__ u64 slot_key(Tie t, u64 x) { return (x << 32) | tie_code(t, (uint32_t)(x >> 32)); }
 
-__device__ __forceinline__ u64 vote_key(uint32_t lab, u64 tally) { return (tally << 32) | (uint32_t)~lab; }
+__device__ __forceinline__ u64 vote_key(Tie t, uint32_t lab, u64 tally) { return (tally << 32) | tie_code(t, lab); }
+
+// The label a vote key stands for.
+__device__ __forceinline__ uint32_t key_label(Tie t, u64 key) { return tie_label(t, (uint32_t)key); }
+
+constexpr Tie kStrict{0u, 0u};
 
 __device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
     return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));

@@ -101,6 +101,17 @@ struct RoundArgs {
     // voted rows of the weight of arcs whose neighbour holds the row's own
     // label (Sigma_in of L_old when every row is voted)
     unsigned long long *insum;
+    // Update order and tie-break (see row_mode in lpa_vote_dev.h):
+    // half 0: every row votes; 1 / 2: only the rows whose draw for round t
+    // puts them in the first / second half vote, the others copy their label
+    // from L_old to L_new.  tie 0: strict (lowest label); 1: hashed.  The
+    // draws use seed, t and the row's original id orig[row] (NULL when
+    // half = tie = 0).
+    uint32_t half;
+    uint32_t tie;
+    uint32_t t;
+    unsigned long long seed;
+    const uint32_t *orig;
 };
 
 // A wavefront work item of a long row: internal row r (= hub index), arcs
@@ -304,7 +315,8 @@ hipError_t launch_hub_merge(const RoundArgs &a, const HubState &hs, const uint32
 // Slab merge of the segments of HUB_FALLBACK rows.
 hipError_t launch_hub_fallback(const RoundArgs &a, const HubItem *items, uint32_t count, const HubState &hs,
                                int num_cu, hipStream_t s);
-hipError_t launch_hub_reduce(const HubState &hs, const ReduceItem *items, uint32_t count, hipStream_t s);
+hipError_t launch_hub_reduce(const RoundArgs &a, const HubState &hs, const ReduceItem *items, uint32_t count,
+                             hipStream_t s);
 // Winner of the rows decided by best[] (direct, slab) and per-round reset.
 hipError_t launch_hub_final(const RoundArgs &a, const HubState &hs, uint32_t count, int first, hipStream_t s);
 

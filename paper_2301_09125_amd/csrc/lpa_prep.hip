@@ -518,7 +518,7 @@ __device__ __forceinline__ void round1_keys(const uint32_t (&u)[A], const uint32
                 own_w += wv[j];
                 own_hit = 1;
             } else {
-                best = umax64(best, vote_key(u[j], wv[j]));
+                best = umax64(best, vote_key(kStrict, u[j], wv[j]));
             }
         }
 }
@@ -579,8 +579,8 @@ __global__ __launch_bounds__(256) void relabel_thread_k(RelabelArgs a, uint8_t *
         if (bad) atomicOr(a.err, ERR_COL);
         rowflag[r] = distinct ? ROW_DISTINCT : 0;
         if (a.L1 && distinct) {
-            if (own_hit || a.sw) best = umax64(best, vote_key(v, own_w + a.sw));
-            const uint32_t nl = best ? ~(uint32_t)best : v;
+            if (own_hit || a.sw) best = umax64(best, vote_key(kStrict, v, own_w + a.sw));
+            const uint32_t nl = best ? key_label(kStrict, best) : v;
             a.L1[r] = nl;
             chg += nl != v;
             if (rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
@@ -720,8 +720,8 @@ __global__ __launch_bounds__(256) void relabel_wave_k(RelabelArgs a, uint8_t *ro
             rowflag[r] = ok ? ROW_DISTINCT : 0;
             if (a.L1 && ok) {
                 const uint32_t v = a.old_of[r];
-                if (own_hit || a.sw) best = umax64(best, vote_key(v, own_w + a.sw));
-                const uint32_t nl = best ? ~(uint32_t)best : v;
+                if (own_hit || a.sw) best = umax64(best, vote_key(kStrict, v, own_w + a.sw));
+                const uint32_t nl = best ? key_label(kStrict, best) : v;
                 a.L1[r] = nl;
                 chg += nl != v;
                 if (rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);

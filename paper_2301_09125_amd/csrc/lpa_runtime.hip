@@ -155,6 +155,8 @@ lpa_status check_options(const lpa_options &o) {
     if (o.wide_max < o.wave_max || o.wide_max > (uint32_t)kWaveArcs) return LPA_EINVAL;
     if (o.merge_max < 1 || o.merge_max > (uint32_t)kMergeBlockSegs) return LPA_EINVAL;
     if (o.frontier > 1) return LPA_EINVAL;
+    if (o.order > LPA_ORDER_SEMISYNC || o.tie > LPA_TIE_HASH) return LPA_EINVAL;
+    if (o.frontier && (o.order || o.tie)) return LPA_EUNSUPPORTED;
     return LPA_OK;
 }
 
@@ -425,7 +427,7 @@ lpa_status enqueue_round(lpa_ctx *c, const Plan &P, const RoundArgs &ra, const H
             return launch_hub_fallback(ra, c->items.as<HubItem>(), P.n_items, hs, cap, s);
         }));
         LPA_TRY(timed(c, K_REDUCE, 0, 0, [&] {
-            return launch_hub_reduce(hs, c->ritems.as<ReduceItem>(), P.n_ritems, s);
+            return launch_hub_reduce(ra, hs, c->ritems.as<ReduceItem>(), P.n_ritems, s);
         }));
         LPA_TRY(timed(c, K_FINAL, 0, 0, [&] { return launch_hub_final(ra, hs, P.H, first, s); }));
     }
@@ -521,9 +523,15 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     clear_stats(stats);
     if (n == 0) return LPA_OK;
 
+    // semi-synchronous rounds and hashed ties: every row is voted by the
+    // round kernels (no round 1 in the relabel pass, which votes strictly
+    // from the unique labels) and, for semi-synchronous rounds, modularity
+    // by the full pass (a round's own-label sums mix two labelings)
+    const bool semi = c->opt.order == LPA_ORDER_SEMISYNC;
+    const bool plain_order = !semi && c->opt.tie == LPA_TIE_LOWEST;
     // per round: changed counter words, then (with modularity) own-label
     // weight sums; one word of error bits after them
-    const bool want_insum = c->opt.modularity != 0;
+    const bool want_insum = c->opt.modularity != 0 && !semi;
     const size_t rwords = (size_t)max_iter * kCountWords;
     const size_t cwords = rwords * (want_insum ? 2 : 1) + 1;
     HIP_TRY(c->counters.ensure(cwords * sizeof(u64)));
@@ -539,7 +547,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     HIP_TRY(c->Lb.ensure((size_t)n * sizeof(uint32_t)));
     // from the unique labels, round 1 of the rows that list each neighbour
     // once is done while the internal CSR is built
-    const bool fused = !resume && max_iter > 0;
+    const bool fused = !resume && max_iter > 0 && plain_order;
     HIP_TRY(c->r1_rows.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->r1_cnt.ensure(NBINS * sizeof(uint32_t)));
     const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight, c->r1_rows.as<uint32_t>(),
@@ -580,14 +588,32 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         ra.list = nullptr;
         ra.list_n = nullptr;
         ra.top1 = ra.top2 = nullptr;
-        const int first = (t == 1 && !resume) ? 1 : 0;
+        // round 1 from the unique labels (its single-occurrence shortcuts);
+        // the second half of a semi-synchronous round 1 reads labels the
+        // first half changed, so those rounds take the general path
+        const int first = (t == 1 && !resume && plain_order) ? 1 : 0;
         ra.skip_distinct = (first && fused) ? 1 : 0;
         ra.insum = insums ? insums + (size_t)(t - 1) * kCountWords : nullptr;
+        ra.half = 0;
+        ra.tie = c->opt.tie;
+        ra.t = t;
+        ra.seed = c->opt.seed;
+        ra.orig = c->old_of.as<uint32_t>();
         HIP_TRY(hipEventRecord(c->round_a, s));
         if (first && fused) {  // just the rows the relabel pass queued
             uint32_t *r1l[NBINS];
             for (int b = 0; b < NBINS; ++b) r1l[b] = c->r1_rows.as<uint32_t>() + B.lo[b];
             LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first, 0, r1l, c->r1_cnt.as<uint32_t>()));
+        } else if (semi) {
+            // half 1 writes every row of L_new (its rows voted, the others
+            // copied), half 2 reads that and writes every row of L_old; a
+            // vertex votes in one half only, so both add to the same counts
+            ra.half = 1;
+            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, 0));
+            ra.half = 2;
+            ra.L_old = L_new;
+            ra.L_new = L_old;
+            LPA_TRY(enqueue_round(c, P, ra, hs, weighted, 0));
         } else {
             LPA_TRY(enqueue_round(c, P, ra, hs, weighted, first));
         }
@@ -616,7 +642,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
             if (stats->changed_per_iter && t <= stats->cap) stats->changed_per_iter[t - 1] = changed;
             if (stats->ms_per_iter && t <= stats->cap) stats->ms_per_iter[t - 1] = ms;
         }
-        std::swap(L_old, L_new);
+        if (!semi) std::swap(L_old, L_new);  // a semi-synchronous round ends in L_old
         if (changed <= thr) {
             converged = 1;
             break;
@@ -629,7 +655,7 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
         // after round 1 every row voted in round it (round 1 may have been
         // voted by the relabel pass, which does not sum own-label weights);
         // modularity_internal ends with a synchronisation and an error check
-        if (it >= 2)
+        if (it >= 2 && !semi)
             LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms, L_new, insum_last));
         else
             LPA_TRY(modularity_internal(c, g, P, L_old, err_dev, &q, terms));
@@ -735,6 +761,7 @@ struct FrontRun {
 
 lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, uint32_t max_iter,
                          FrontRun &R) {
+    if (c->opt.order != LPA_ORDER_SYNC || c->opt.tie != LPA_TIE_LOWEST) return LPA_EUNSUPPORTED;
     LPA_TRY(check_csr_args(g));
     if (!labels && g->n && R.mode != F_TRACE) return LPA_EINVAL;
     if (!(tol >= 0.0 && tol <= 1.0)) return LPA_EINVAL;
@@ -843,6 +870,11 @@ lpa_status frontier_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double 
         ra.list_n = nullptr;
         ra.skip_distinct = (t == 1 && fused) ? 1 : 0;
         ra.insum = nullptr;
+        ra.half = 0;  // synchronous rounds, strict ties
+        ra.tie = 0;
+        ra.t = t;
+        ra.seed = 0;
+        ra.orig = nullptr;
         ra.top1 = c->f_top1.as<uint32_t>();
         ra.top2 = c->f_top2.as<uint32_t>();
         FrontArgs fa;
@@ -1104,6 +1136,7 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
                           double tol, uint32_t max_iter, lpa_batch_stats *stats) {
     const auto t_start = std::chrono::steady_clock::now();
     if (!c) return LPA_EINVAL;
+    if (c->opt.order != LPA_ORDER_SYNC || c->opt.tie != LPA_TIE_LOWEST) return LPA_EUNSUPPORTED;
     LPA_TRY(check_csr_args(g));
     if (!gv && G) return LPA_EINVAL;
     if (!labels && g->n) return LPA_EINVAL;
@@ -1319,6 +1352,9 @@ void lpa_default_options(lpa_options *opt) {
     opt->modularity = 0;
     opt->frontier = 0;
     opt->barrier_timeout_us = 0;
+    opt->order = LPA_ORDER_SYNC;
+    opt->tie = LPA_TIE_LOWEST;
+    opt->seed = 0;
 }
 
 lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *opt) {

@@ -60,8 +60,12 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
         const uint32_t vcur = vnext;
         if (i + stride < cnt) vnext = row_of(a, lo, i + stride);
         bool ch = false;
-        if (i < cnt && !(a.skip_distinct && (a.rowflag[vcur] & ROW_DISTINCT))) {
+        const RowMode rm = row_mode(a, vcur);  // vcur is a row of the launch (or row lo)
+        if (i < cnt && !rm.on) {
+            a.L_new[vcur] = a.L_old[vcur];  // the other half of a semi-synchronous round
+        } else if (i < cnt && !(a.skip_distinct && (a.rowflag[vcur] & ROW_DISTINCT))) {
             const uint32_t v = vcur;
+            const Tie tie = rm.tie;
             const uint64_t b = a.g.rp[v];
             const uint64_t e = a.g.rp[v + 1];
             const uint32_t own = a.L_old[v];
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
                         tl[j] += wt[k];
                         tl[k] += wt[j];
                     }
-            u64 best = a.sw ? vote_key(own, a.sw) : 0ull;
+            u64 best = a.sw ? vote_key(tie, own, a.sw) : 0ull;
             if (FEAT) {
                 // the own label's key with its full tally (equal keys of one
                 // label collapse in top2_add)
@@ -93,18 +97,18 @@ __global__ __launch_bounds__(256) void vote_thread_k(RoundArgs a, uint32_t lo, u
                 for (int j = 0; j < D; ++j)
                     if ((valid >> j & 1u) && lab[j] == own) own_t += wt[j];
                 u64 k2 = 0;
-                best = a.sw ? vote_key(own, own_t) : 0ull;
+                best = a.sw ? vote_key(tie, own, own_t) : 0ull;
 #pragma unroll
                 for (int j = 0; j < D; ++j)
-                    if (valid >> j & 1u) top2_add(best, k2, vote_key(lab[j], tl[j]));
+                    if (valid >> j & 1u) top2_add(best, k2, vote_key(tie, lab[j], tl[j]));
                 a.top1[v] = (uint32_t)(best >> 32);
                 a.top2[v] = (uint32_t)(k2 >> 32);
             } else {
 #pragma unroll
                 for (int j = 0; j < D; ++j)
-                    if (valid >> j & 1u) best = umax64(best, vote_key(lab[j], tl[j]));
+                    if (valid >> j & 1u) best = umax64(best, vote_key(tie, lab[j], tl[j]));
             }
-            const uint32_t nl = best ? ~(uint32_t)best : own;
+            const uint32_t nl = best ? key_label(tie, best) : own;
             a.L_new[v] = nl;
             ch = nl != own;
             if (a.check && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
@@ -145,6 +149,10 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
         const uint32_t v = act ? vnext : 0u;
         if (idx + stride < cnt) vnext = row_of(a, lo, idx + stride);
         if (FIRST && act && a.skip_distinct && (a.rowflag[v] & ROW_DISTINCT)) act = false;
+        const RowMode rm = row_mode(a, v);
+        const Tie tie = rm.tie;  // the same in every lane of the group
+        const bool keep = act && !rm.on;  // the other half of a semi-synchronous round
+        act = act && rm.on;
         uint64_t b = 0, e = 0;
         uint32_t own = 0;
         if (act) {
@@ -169,9 +177,9 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
             for (int j = 0; j < A; ++j)
                 if (rem >> j & 1u) {
                     if (FEAT)
-                        top2_add(best, k2, vote_key(lab[j], wt[j]));
+                        top2_add(best, k2, vote_key(tie, lab[j], wt[j]));
                     else
-                        best = umax64(best, vote_key(lab[j], wt[j]));
+                        best = umax64(best, vote_key(tie, lab[j], wt[j]));
                 }
         } else {
 #pragma unroll
@@ -184,9 +192,9 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
                 const u64 x = T[s];
                 if (x != EMPTY_SLOT) {
                     if (FEAT)
-                        top2_add(best, k2, slot_key(x));
+                        top2_add(best, k2, slot_key(tie, x));
                     else
-                        best = umax64(best, slot_key(x));
+                        best = umax64(best, slot_key(tie, x));
                     T[s] = EMPTY_SLOT;
                 }
             }
@@ -220,19 +228,20 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
             ins += own_w;
             if (own_hit || a.sw) {
                 if (FEAT)
-                    top2_add(best, k2, vote_key(own, own_w + a.sw));
+                    top2_add(best, k2, vote_key(tie, own, own_w + a.sw));
                 else
-                    best = umax64(best, vote_key(own, own_w + a.sw));
+                    best = umax64(best, vote_key(tie, own, own_w + a.sw));
             }
             if (FEAT) {
                 a.top1[v] = (uint32_t)(best >> 32);
                 a.top2[v] = (uint32_t)(k2 >> 32);
             }
-            const uint32_t nl = best ? ~(uint32_t)best : own;
+            const uint32_t nl = best ? key_label(tie, best) : own;
             a.L_new[v] = nl;
             ch = nl != own;
             if (a.check && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
         }
+        if (keep && gl == 0) a.L_new[v] = a.L_old[v];
         wchg += __popcll(__ballot(ch));
         wave_sync();
     }
@@ -257,12 +266,16 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
     uint64_t b = 0, e = 0;
     uint32_t u[A], wt[A], valid = 0;
     uint32_t v = 0;
-    // round 1: rows the relabel pass already voted are skipped (no loads)
+    // rows this launch does not vote are skipped (no loads): in round 1 the
+    // rows the relabel pass already voted, in a half of a semi-synchronous
+    // round the rows of the other half (`keep`: they copy their label)
     auto skipped = [&](uint32_t row) { return FIRST && a.skip_distinct && (a.rowflag[row] & ROW_DISTINCT); };
-    bool skip = false;
+    auto other_half = [&](uint32_t row) { return a.half != 0 && !row_mode(a, row).on; };
+    bool skip = false, keep = false;
     if (i < cnt) {
         v = row_of(a, lo, i);
-        skip = skipped(v);
+        keep = other_half(v);
+        skip = keep || skipped(v);
         if (!skip) {
             b = a.g.rp[v];
             e = a.g.rp[v + 1];
@@ -273,10 +286,11 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
         const uint32_t inext = i + stride;
         uint64_t nb = 0, ne = 0;
         uint32_t nu[A], nwt[A], nvalid = 0, nv = 0;
-        bool nskip = false;
+        bool nskip = false, nkeep = false;
         if (inext < cnt) {
             nv = row_of(a, lo, inext);
-            nskip = skipped(nv);
+            nkeep = other_half(nv);
+            nskip = nkeep || skipped(nv);
             if (!nskip) {
                 nb = a.g.rp[nv];
                 ne = a.g.rp[nv + 1];
@@ -287,8 +301,10 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
 #pragma unroll
             for (int j = 0; j < A; ++j) nu[j] = nwt[j] = 0;
         }
+        if (keep && lane == 0) a.L_new[v] = a.L_old[v];
         if (!skip) {
         check_arcs<A>(a, u);
+        const Tie tie = row_mode(a, v).tie;
         const uint32_t own = a.L_old[v];
         uint32_t lab[A];
         gather_labels<A>(a, u, valid, lab);
@@ -305,9 +321,9 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
             for (int j = 0; j < A; ++j)
                 if (rem >> j & 1u) {
                     if (FEAT)
-                        top2_add(best, k2, vote_key(lab[j], wt[j]));
+                        top2_add(best, k2, vote_key(tie, lab[j], wt[j]));
                     else
-                        best = umax64(best, vote_key(lab[j], wt[j]));
+                        best = umax64(best, vote_key(tie, lab[j], wt[j]));
                 }
         } else if (__ballot(rem != 0)) {  // some label other than the own one
             wave_peel<A, 2>(T, mask, lab, wt, rem);
@@ -319,9 +335,9 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
                 const u64 x = T[s];
                 if (x != EMPTY_SLOT) {
                     if (FEAT)
-                        top2_add(best, k2, slot_key(x));
+                        top2_add(best, k2, slot_key(tie, x));
                     else
-                        best = umax64(best, slot_key(x));
+                        best = umax64(best, slot_key(tie, x));
                     T[s] = EMPTY_SLOT;
                 }
             }
@@ -339,15 +355,15 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
             ins += own_w;
             if (own_hit || a.sw) {
                 if (FEAT)
-                    top2_add(best, k2, vote_key(own, own_w + a.sw));
+                    top2_add(best, k2, vote_key(tie, own, own_w + a.sw));
                 else
-                    best = umax64(best, vote_key(own, own_w + a.sw));
+                    best = umax64(best, vote_key(tie, own, own_w + a.sw));
             }
             if (FEAT) {
                 a.top1[v] = (uint32_t)(best >> 32);
                 a.top2[v] = (uint32_t)(k2 >> 32);
             }
-            const uint32_t nl = best ? ~(uint32_t)best : own;
+            const uint32_t nl = best ? key_label(tie, best) : own;
             a.L_new[v] = nl;
             wchg += nl != own;
             if (a.check && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
@@ -357,6 +373,7 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
         i = inext;
         v = nv;
         skip = nskip;
+        keep = nkeep;
         b = nb;
         e = ne;
         valid = nvalid;
@@ -505,10 +522,10 @@ __device__ __forceinline__ void select_topk(const u64 (&keys)[kWaveArcs / 64], u
     }
 }
 
-__device__ __forceinline__ void report_topk(ListedTable &t, const HubState &hs, uint32_t it) {
+__device__ __forceinline__ void report_topk(ListedTable &t, Tie tie, const HubState &hs, uint32_t it) {
     const uint32_t lane = threadIdx.x & 63;
     u64 keys[kWaveArcs / 64];
-    const uint32_t J = listed_take(t, keys);
+    const uint32_t J = listed_take(t, tie, keys);
     u64 mine = 0;
     uint32_t thr = 0;
     if (J == 1)
@@ -521,7 +538,7 @@ __device__ __forceinline__ void report_topk(ListedTable &t, const HubState &hs, 
         select_topk<kWaveArcs / 64>(keys, mine, thr);
     if (lane == 0) hs.thr[it] = thr;
     if (lane < (uint32_t)kTopK)
-        hs.cand[(u64)it * kTopK + lane] = mine ? (((u64)(uint32_t)~(uint32_t)mine << 32) | (mine >> 32)) : EMPTY_SLOT;
+        hs.cand[(u64)it * kTopK + lane] = mine ? (((u64)key_label(tie, mine) << 32) | (mine >> 32)) : EMPTY_SLOT;
 }
 
 // Round 1 rows that list each neighbour once: every tally is one arc's
@@ -536,6 +553,8 @@ __global__ __launch_bounds__(256) void vote_hub_direct_k(RoundArgs a, const HubI
         const HubItem item = items[it];
         const uint32_t h = item.r;
         if (hs.flags[h] & HUB_REPEATS) continue;  // uniform over the wavefront
+        const RowMode rm = row_mode(a, h);
+        if (!rm.on) continue;  // the other half: hub_final_k copies its label
         uint32_t u[A], wt[A], valid = 0, lab[A];
         load_arcs<A, 64>(a, item.b0 + lane, item.b1, u, wt, valid);
         gather_labels<A>(a, u, valid, lab);
@@ -546,7 +565,7 @@ __global__ __launch_bounds__(256) void vote_hub_direct_k(RoundArgs a, const HubI
         u64 best = 0;
 #pragma unroll
         for (int j = 0; j < A; ++j)
-            if (rem >> j & 1u) best = umax64(best, vote_key(lab[j], wt[j]));
+            if (rem >> j & 1u) best = umax64(best, vote_key(rm.tie, lab[j], wt[j]));
         best = wave_max64(best);
         own_w = wave_sum(own_w);
         own_hit = __ballot(own_hit != 0) != 0;
@@ -624,6 +643,8 @@ __global__ __launch_bounds__(256) void vote_hub_k(RoundArgs a, const HubItem *__
             x = items[k];
             x.pad = hs.flags[x.r];
             act_k = !FIRST || (x.pad & HUB_REPEATS);
+            // the other half of a semi-synchronous round: hub_final_k copies
+            if (act_k && a.half && !row_mode(a, x.r).on) act_k = false;
             if (!act_k) x = HubItem{0, 0, 0, 0};
         }
         return x;
@@ -689,7 +710,7 @@ __global__ __launch_bounds__(256) void vote_hub_k(RoundArgs a, const HubItem *__
                         atomicOr(hs.pending, 1u);
                     }
                 } else {
-                    report_topk(t, hs, it);
+                    report_topk(t, row_mode(a, h).tie, hs, it);
                 }
             }
             own_w = wave_sum(own_w);
@@ -794,6 +815,9 @@ __global__ __launch_bounds__(256) void hub_merge_wave_k(RoundArgs a, HubState hs
         const uint32_t flags = hs.flags[h];
         if (first && !(flags & HUB_REPEATS)) continue;  // decided through best[]
         if (flags & HUB_FALLBACK) continue;              // a segment spilled: slab pass
+        const RowMode rm = row_mode(a, h);
+        if (!rm.on) continue;  // the other half: hub_final_k copies its label
+        const Tie tie = rm.tie;
         const uint32_t lo = hs.item_lo[h], ns = hs.item_lo[h + 1] - lo;
         const u64 T = wave_sum((u64)(lane < ns ? hs.thr[lo + lane] : 0u));
         for (uint32_t e = lane; e < ns * kTopK; e += 64) {
@@ -802,17 +826,17 @@ __global__ __launch_bounds__(256) void hub_merge_wave_k(RoundArgs a, HubState hs
         }
         wave_sync();
         const uint32_t own = a.L_old[h];
-        u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(own, hs.own_sum[h] + a.sw) : 0ull;
+        u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(tie, own, hs.own_sum[h] + a.sw) : 0ull;
         for (uint32_t s = lane; s < MS; s += 64)
-            if (mk[s] != kNone) xkey = umax64(xkey, vote_key(mk[s], lb[s]));
+            if (mk[s] != kNone) xkey = umax64(xkey, vote_key(tie, mk[s], lb[s]));
         xkey = wave_max64(xkey);
-        const uint32_t xs = ~(uint32_t)xkey;
+        const uint32_t xs = key_label(tie, xkey);
         const u64 V = xkey >> 32;
         bool bad = false;
         for (uint32_t s = lane; s < MS; s += 64) {
             const uint32_t lab = mk[s];
             if (lab != kNone) {
-                if (lab != xs && vote_key(lab, (u64)lb[s] + T - tr[s]) >= xkey) bad = true;
+                if (lab != xs && vote_key(tie, lab, (u64)lb[s] + T - tr[s]) >= xkey) bad = true;
                 mk[s] = kNone;
                 lb[s] = 0;
                 tr[s] = 0;
@@ -853,6 +877,9 @@ __global__ __launch_bounds__(256) void hub_merge_block_k(RoundArgs a, HubState h
         const uint32_t flags = hs.flags[h];
         if (first && !(flags & HUB_REPEATS)) continue;  // uniform over the block
         if (flags & HUB_FALLBACK) continue;              // a segment spilled: slab pass
+        const RowMode rm = row_mode(a, h);
+        if (!rm.on) continue;  // the other half: hub_final_k copies its label
+        const Tie tie = rm.tie;
         const uint32_t lo = hs.item_lo[h], ns = hs.item_lo[h + 1] - lo;
         u64 T = 0, z1 = 0, z2 = 0;
         uint32_t zo = 0;
@@ -863,19 +890,19 @@ __global__ __launch_bounds__(256) void hub_merge_block_k(RoundArgs a, HubState h
         }
         block_reduce(R, z1, T, z2, zo);  // T summed, includes a barrier
         const uint32_t own = a.L_old[h];
-        u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(own, hs.own_sum[h] + a.sw) : 0ull;
+        u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(tie, own, hs.own_sum[h] + a.sw) : 0ull;
         for (uint32_t s = threadIdx.x; s < MS; s += 256)
-            if (mk[s] != kNone) xkey = umax64(xkey, vote_key(mk[s], lb[s]));
+            if (mk[s] != kNone) xkey = umax64(xkey, vote_key(tie, mk[s], lb[s]));
         __syncthreads();
         u64 z3 = 0, z4 = 0;
         block_reduce(R, xkey, z3, z4, zo);
-        const uint32_t xs = ~(uint32_t)xkey;
+        const uint32_t xs = key_label(tie, xkey);
         const u64 V = xkey >> 32;
         uint32_t bad = 0;
         for (uint32_t s = threadIdx.x; s < MS; s += 256) {
             const uint32_t lab = mk[s];
             if (lab != kNone) {
-                if (lab != xs && vote_key(lab, (u64)lb[s] + T - tr[s]) >= xkey) bad = 1;
+                if (lab != xs && vote_key(tie, lab, (u64)lb[s] + T - tr[s]) >= xkey) bad = 1;
                 mk[s] = kNone;
                 lb[s] = 0;
                 tr[s] = 0;
@@ -900,7 +927,7 @@ __global__ __launch_bounds__(256) void hub_merge_block_k(RoundArgs a, HubState h
 
 // Phase 2: max key over the slab slots claimed by a row, clearing them for
 // the next round.  One block per item of <= 2048 touched-list positions.
-__global__ __launch_bounds__(256) void hub_reduce_k(HubState hs, const ReduceItem *__restrict__ items,
+__global__ __launch_bounds__(256) void hub_reduce_k(RoundArgs a, HubState hs, const ReduceItem *__restrict__ items,
                                                     uint32_t count) {
     __shared__ BlockRed R;
     if (!*hs.pending) return;  // no slab was used this round
@@ -910,12 +937,13 @@ __global__ __launch_bounds__(256) void hub_reduce_k(HubState hs, const ReduceIte
         if (r.t0 >= t1) continue;  // uniform over the block
         u64 *slab = hs.slab + hs.slab_off[r.hub];
         const uint32_t *tlist = hs.touched + hs.touched_off[r.hub];
+        const Tie tie = row_mode(a, r.hub).tie;  // rows of the other half claimed no slot
         u64 best = 0, z0 = 0, z1 = 0;
         uint32_t z2 = 0;
         for (uint32_t p = r.t0 + threadIdx.x; p < t1; p += 256) {
             const uint32_t s = tlist[p];
             if (s != kNone) {
-                best = umax64(best, slot_key(slab[s]));
+                best = umax64(best, slot_key(tie, slab[s]));
                 slab[s] = EMPTY_SLOT;
             }
         }
@@ -937,12 +965,15 @@ __global__ __launch_bounds__(256) void hub_final_k(RoundArgs a, HubState hs, uin
         if (i < count) {
             const uint32_t f = hs.flags[i];
             ins += hs.own_sum[i];
+            const RowMode rm = row_mode(a, i);
             const bool via_best = (first && !(f & HUB_REPEATS)) || (f & (HUB_BIG | HUB_FALLBACK));
-            if (via_best) {
+            if (!rm.on) {
+                a.L_new[i] = a.L_old[i];  // the other half of a semi-synchronous round
+            } else if (via_best) {
                 const uint32_t own = a.L_old[i];
                 u64 best = hs.best[i];
-                if ((f & HUB_OWN_SEEN) || a.sw) best = umax64(best, vote_key(own, hs.own_sum[i] + a.sw));
-                const uint32_t nl = best ? ~(uint32_t)best : own;
+                if ((f & HUB_OWN_SEEN) || a.sw) best = umax64(best, vote_key(rm.tie, own, hs.own_sum[i] + a.sw));
+                const uint32_t nl = best ? key_label(rm.tie, best) : own;
                 a.L_new[i] = nl;
                 ch = nl != own;
             }
@@ -996,9 +1027,10 @@ hipError_t launch_hub_fallback(const RoundArgs &a, const HubItem *items, uint32_
     hub_fallback_k<<<stride_grid<hub_fallback_k>(count, 4, num_cu), 256, 0, s>>>(a, items, count, hs);
     return hipGetLastError();
 }
-hipError_t launch_hub_reduce(const HubState &hs, const ReduceItem *items, uint32_t count, hipStream_t s) {
+hipError_t launch_hub_reduce(const RoundArgs &a, const HubState &hs, const ReduceItem *items, uint32_t count,
+                             hipStream_t s) {
     if (count == 0) return hipSuccess;
-    hub_reduce_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(hs, items, count);
+    hub_reduce_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(a, hs, items, count);
     return hipGetLastError();
 }
 hipError_t launch_hub_final(const RoundArgs &a, const HubState &hs, uint32_t count, int first, hipStream_t s) {

@@ -13,6 +13,24 @@ __device__ __forceinline__ uint32_t row_of(const RoundArgs &a, uint32_t lo, uint
     return a.list ? a.list[i] : lo + i;
 }
 
+// Whether internal row v votes in this launch, and its tie rule.  The draws
+// of a vertex in round t are SplitMix64 outputs number 2c + 1 (the top bit
+// gives its half of a semi-synchronous round) and 2c + 2 (its tie key) for
+// c = t * 2^32 + (original id of v).
+struct RowMode {
+    bool on;
+    Tie tie;
+};
+__device__ __forceinline__ RowMode row_mode(const RoundArgs &a, uint32_t v) {
+    RowMode m{true, Tie{a.tie, 0u}};
+    if (a.half | a.tie) {
+        const u64 c = (((u64)a.t << 32) | a.orig[v]) << 1;
+        if (a.half) m.on = (uint32_t)(splitmix64_at(a.seed, c) >> 63) == a.half - 1;
+        if (a.tie) m.tie.k = (uint32_t)splitmix64_at(a.seed, c | 1u);
+    }
+    return m;
+}
+
 // Two largest distinct vote keys seen so far (0 = none).  Selects only: a
 // branchy form gets the pair spilled to scratch memory and indexed.
 __device__ __forceinline__ void top2_add(u64 &k1, u64 &k2, u64 k) {
@@ -234,7 +252,7 @@ __device__ __forceinline__ void listed_clear(ListedTable &t) {
 // Read and clear the listed entries: entry lane + 64 j becomes keys[j] as a
 // vote key (0 where there is none).  Returns how many key columns are used.
 template <int J>
-__device__ __forceinline__ uint32_t listed_take(ListedTable &t, u64 (&keys)[J]) {
+__device__ __forceinline__ uint32_t listed_take(ListedTable &t, Tie tie, u64 (&keys)[J]) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t D = t.n;
 #pragma unroll
@@ -243,7 +261,7 @@ __device__ __forceinline__ uint32_t listed_take(ListedTable &t, u64 (&keys)[J]) 
         const uint32_t e = lane + 64u * j;
         if (e < D) {
             const uint32_t s = t.lst[e];
-            keys[j] = slot_key(t.T[s]);
+            keys[j] = slot_key(tie, t.T[s]);
             t.T[s] = EMPTY_SLOT;
         }
     }

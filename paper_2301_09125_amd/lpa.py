@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "liblpa.so")
 
 LPA_OK, LPA_EINVAL, LPA_EOVERFLOW, LPA_ENOMEM, LPA_EDEVICE, LPA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LPA_ETIMEDOUT = -6
+LPA_ORDER_SYNC, LPA_ORDER_SEMISYNC = 0, 1
+LPA_TIE_LOWEST, LPA_TIE_HASH = 0, 1
 
 _lib = None
 
@@ -41,7 +43,8 @@ class _Options(ctypes.Structure):
                 ("group_max", ctypes.c_uint32), ("wave_max", ctypes.c_uint32),
                 ("wide_max", ctypes.c_uint32), ("merge_max", ctypes.c_uint32), ("profile", ctypes.c_uint32),
                 ("modularity", ctypes.c_uint32), ("frontier", ctypes.c_uint32),
-                ("barrier_timeout_us", ctypes.c_uint32)]
+                ("barrier_timeout_us", ctypes.c_uint32), ("order", ctypes.c_uint32), ("tie", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
 
 
 class _Stats(ctypes.Structure):

@@ -4,6 +4,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -57,3 +59,20 @@ def test_traffic_is_null_once_the_kernel_sources_change(tmp_path, monkeypatch):
     with open(csrc / "lpa_vote.hip", "a") as f:
         f.write("\n// changed\n")
     assert bench.traffic_from_profile("toy", "vote_hub") is None
+
+
+@pytest.mark.gpu
+def test_bench_gather_probe():
+    """The bench-only random-gather probe (bench_gather_probe.hip, not part of
+    liblpa.so): a positive rate, indices past the table clamped into it, and
+    an empty index stream rejected."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import bench
+    probe = bench.GatherProbe()
+    idx = torch.randint(0, 1 << 20, (1 << 20,), dtype=torch.int32, device="cuda")
+    table = torch.zeros(1 << 16, dtype=torch.int32, device="cuda")  # most indices past the end: clamped
+    assert probe.rate(idx, table, reps=2) > 0
+    with pytest.raises(RuntimeError):
+        probe.rate(idx[:0], table)
