@@ -77,6 +77,9 @@ def _load(parallel: bool = False):
         lib.orc_half_of.restype = ctypes.c_int
         lib.orc_tie_key.argtypes = [u64, u32, u32]
         lib.orc_tie_key.restype = u32
+        lib.orc_copra.argtypes = [u32, vp, vp, vp, u32, ctypes.c_int, ctypes.c_int, u64, dbl, u32, vp, vp, vp, vp,
+                                  vp, vp, vp]
+        lib.orc_copra.restype = ctypes.c_int
         lib.orc_threads.argtypes = []
         lib.orc_threads.restype = ctypes.c_int
         _libs[parallel] = lib
@@ -215,6 +218,46 @@ def rak_masked(g, masks: np.ndarray, self_weight: int = 1, init_labels=None):
     if rc:
         raise OracleError(rc)
     return out, [int(x) for x in ch[:rounds]]
+
+
+COPRA_ONE = 1 << 16  # belonging coefficient 1 in the oracle's fixed point
+
+
+@dataclass
+class CopraResult:
+    labels: np.ndarray      # best label of every vertex
+    iterations: int
+    converged: bool
+    changed: list
+    state: list             # per vertex: sorted [(label, coefficient * 2^16), ...]
+
+
+def copra(g, max_labels: int = 4, tol: float = 0.01, max_iter: int = 20, order: str = "sync", tie: str = "lowest",
+          seed: int = 0) -> CopraResult:
+    """COPRA (Section 3.3) with fixed-point belonging coefficients, in
+    synchronous or semi-synchronous rounds; the best label's ties go to the
+    lowest label or, with tie="hash", to the highest priority as in rak_ext.
+    See the C source for the readings taken."""
+    if order not in ("sync", "semisync") or tie not in ("lowest", "hash"):
+        raise ValueError("order: sync|semisync, tie: lowest|hash")
+    rp, col, w = _arrs(g)
+    V = int(max_labels)
+    best = np.empty(g.n, dtype=np.uint32)
+    sl = np.zeros(max(g.n * V, 1), dtype=np.uint32)
+    sc = np.zeros(max(g.n * V, 1), dtype=np.uint32)
+    sn = np.zeros(max(g.n, 1), dtype=np.uint32)
+    ch = np.zeros(max(max_iter, 1), dtype=np.uint64)
+    it = ctypes.c_uint32(0)
+    cv = ctypes.c_int32(0)
+    rc = _load().orc_copra(g.n, rp.ctypes.data, col.ctypes.data, _p(w), V, 1 if order == "semisync" else 0,
+                           1 if tie == "hash" else 0,
+                           int(seed) & ((1 << 64) - 1), float(tol), max_iter, best.ctypes.data,
+                           sl.ctypes.data, sc.ctypes.data, sn.ctypes.data, ch.ctypes.data, ctypes.byref(it),
+                           ctypes.byref(cv))
+    if rc:
+        raise OracleError(rc)
+    state = [sorted(zip(sl[v * V:v * V + sn[v]].tolist(), sc[v * V:v * V + sn[v]].tolist())) for v in range(g.n)]
+    return CopraResult(best, int(it.value), bool(cv.value), [int(x) for x in ch[: it.value]], state)
 
 
 @dataclass

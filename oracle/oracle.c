@@ -425,3 +425,196 @@ int orc_modularity(uint32_t n, const uint64_t *rp, const uint32_t *col, const ui
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ COPRA --
+ *
+ * COPRA (Section 3.3): every vertex holds a set of (label, belonging
+ * coefficient) pairs whose coefficients sum to 1; it starts as its own
+ * community with belonging 1.  In each iteration a vertex collects the
+ * labels of its neighbourhood (not its own), each neighbour's coefficients
+ * scaled by the connecting edge weight; it keeps the labels whose share of
+ * the collected weight reaches the threshold 1/max_labels; if none does, it
+ * keeps only the best label; a vertex with nothing to collect joins its own
+ * community; the kept labels are normalised to sum to 1.  Convergence is
+ * counted as in RAK, on the vertices whose best label changed, and the
+ * result is each vertex's best label.
+ *
+ * Readings taken here (the paper leaves them open):
+ *   - synchronous rounds, as for RAK here, or, standing in for the paper's
+ *     asynchronous COPRA, semi-synchronous rounds (two half-rounds over the
+ *     halves orc_half_of draws, a vertex of the other half keeping its
+ *     state), as orc_rak_ext;
+ *   - coefficients are fixed point, integer multiples of 2^-16 (COPRA_ONE =
+ *     2^16 stands for 1), so every sum is an exact integer: the collected
+ *     tally of label c at v is sum over arcs (v,u,w) of w * b_u(c), and the
+ *     total is weighted_degree(v) * 2^16;
+ *   - a label is kept iff tally > 0 and tally * max_labels >= total
+ *     (Gregory's original rule drops coefficients below 1/max_labels; a
+ *     vertex whose arcs all weigh 0 collects nothing to share and keeps its
+ *     best label alone);
+ *   - the best label is the one of largest tally; ties go to the lowest
+ *     label (strict, as RAK) or, for "a random best label" (the paper's
+ *     wording), to the tied label of highest priority lowbias32(label ^ k),
+ *     k = orc_tie_key(seed, t, v), as the non-strict RAK; if nothing reaches
+ *     the threshold the best label is kept alone with coefficient 1;
+ *   - normalisation: b(c) = floor(tally(c) * 2^16 / sum of kept tallies),
+ *     and what the floors leave out of 2^16 goes to the best label, so the
+ *     coefficients sum to exactly 2^16.
+ * With max_labels = 1 a label is kept only when it is the only one, so the
+ * vertex takes its best label: RAK with self weight 0. */
+
+#define COPRA_ONE 65536u
+
+typedef struct { uint32_t label; uint64_t tally; } pair_lt;
+
+static int by_label_lt(const void *a, const void *b) {
+    uint32_t x = ((const pair_lt *)a)->label, y = ((const pair_lt *)b)->label;
+    return (x > y) - (x < y);
+}
+
+/* One round for vertex v: reads the state (lab, coef, cnt) of the previous
+ * round (V slots per vertex), writes v's new state and returns its best
+ * label.  buf holds deg(v) * V pairs. */
+static uint32_t copra_vertex(uint32_t v, const uint64_t *rp, const uint32_t *col, const uint32_t *w, uint32_t V,
+                             const uint32_t *lab, const uint32_t *coef, const uint32_t *cnt, pair_lt *buf,
+                             uint32_t *nlab, uint32_t *ncoef, uint32_t *ncnt, tie_rule tie) {
+    uint64_t k = 0, total = 0;
+    for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) {
+        uint32_t u = col[e];
+        uint64_t we = w ? w[e] : 1u;
+        total += we * COPRA_ONE;
+        for (uint32_t i = 0; i < cnt[u]; ++i) {
+            buf[k].label = lab[(size_t)u * V + i];
+            buf[k].tally = we * coef[(size_t)u * V + i];
+            ++k;
+        }
+    }
+    uint32_t *ol = nlab + (size_t)v * V, *oc = ncoef + (size_t)v * V;
+    if (k == 0) {  /* nothing collected: its own community */
+        ol[0] = v;
+        oc[0] = COPRA_ONE;
+        *ncnt = 1;
+        return v;
+    }
+    qsort(buf, (size_t)k, sizeof(pair_lt), by_label_lt);
+    /* sum runs of equal labels in place: buf[0..d) = distinct labels */
+    uint64_t d = 0;
+    for (uint64_t i = 0; i < k;) {
+        uint32_t l = buf[i].label;
+        uint64_t s = 0;
+        while (i < k && buf[i].label == l) s += buf[i++].tally;
+        buf[d].label = l;
+        buf[d].tally = s;
+        ++d;
+    }
+    uint64_t bi = 0;  /* labels ascend: a strictly larger tally is needed to win */
+    for (uint64_t i = 1; i < d; ++i)
+        if (buf[i].tally > buf[bi].tally ||
+            (tie.hashed && buf[i].tally == buf[bi].tally &&
+             orc_lowbias32(buf[i].label ^ tie.k) > orc_lowbias32(buf[bi].label ^ tie.k)))
+            bi = i;
+    uint64_t kept_sum = 0;
+    uint32_t kept = 0;
+    for (uint64_t i = 0; i < d; ++i)
+        if (buf[i].tally > 0 && buf[i].tally * V >= total) {
+            kept_sum += buf[i].tally;
+            ++kept;
+        }
+    if (kept == 0) {
+        ol[0] = buf[bi].label;
+        oc[0] = COPRA_ONE;
+        *ncnt = 1;
+        return buf[bi].label;
+    }
+    uint32_t j = 0, given = 0, best_slot = 0;
+    for (uint64_t i = 0; i < d; ++i)
+        if (buf[i].tally > 0 && buf[i].tally * V >= total) {
+            uint32_t c = (uint32_t)(buf[i].tally * COPRA_ONE / kept_sum);
+            if (i == bi) best_slot = j;
+            ol[j] = buf[i].label;
+            oc[j] = c;
+            given += c;
+            ++j;
+        }
+    oc[best_slot] += COPRA_ONE - given;
+    *ncnt = kept;
+    return buf[bi].label;
+}
+
+/* COPRA run (see above).  max_labels in 1..64; order (0 synchronous, 1
+ * semi-synchronous), hashed, seed: as orc_rak_ext.
+ *   best_out:  n best labels after the last executed round;
+ *   state_lab, state_coef (n * max_labels) and state_cnt (n): the final
+ *              state, or NULL;
+ *   changed_per_iter: max_iter entries (may be NULL): vertices whose best
+ *              label changed in each round.
+ * Returns 0, -1 (invalid input), -2 (weight overflow), -3 (out of memory). */
+int orc_copra(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w, uint32_t max_labels,
+              int order, int hashed, uint64_t seed, double tol, uint32_t max_iter, uint32_t *best_out,
+              uint32_t *state_lab,
+              uint32_t *state_coef, uint32_t *state_cnt, uint64_t *changed_per_iter, uint32_t *iterations,
+              int32_t *converged) {
+    if (!(tol >= 0.0 && tol <= 1.0) || !best_out || !iterations || !converged) return -1;
+    if (n > 0xFFFFFFFEu || max_labels < 1 || max_labels > 64 || order < 0 || order > 1) return -1;
+    int rc = check_csr(n, rp, col, w, 0);
+    if (rc) return rc;
+    const uint32_t V = max_labels;
+    const size_t nv = (size_t)(n ? n : 1);
+    const uint64_t thr = (uint64_t)floor(tol * (double)n);
+    uint32_t *lab[2], *coef[2], *cnt[2], *best[2];
+    int fail = 0;
+    for (int s = 0; s < 2; ++s) {
+        lab[s] = (uint32_t *)malloc(nv * V * sizeof(uint32_t));
+        coef[s] = (uint32_t *)malloc(nv * V * sizeof(uint32_t));
+        cnt[s] = (uint32_t *)malloc(nv * sizeof(uint32_t));
+        best[s] = (uint32_t *)malloc(nv * sizeof(uint32_t));
+        fail |= !lab[s] || !coef[s] || !cnt[s] || !best[s];
+    }
+    pair_lt *buf = (pair_lt *)malloc((size_t)(max_degree(n, rp) * V + 1) * sizeof(pair_lt));
+    if (fail || !buf) {
+        for (int s = 0; s < 2; ++s) { free(lab[s]); free(coef[s]); free(cnt[s]); free(best[s]); }
+        free(buf);
+        return -3;
+    }
+    for (uint32_t v = 0; v < n; ++v) {  /* every vertex its own community */
+        lab[0][(size_t)v * V] = v;
+        coef[0][(size_t)v * V] = COPRA_ONE;
+        cnt[0][v] = 1;
+        best[0][v] = v;
+    }
+    int cur = 0;
+    *iterations = 0;
+    *converged = 0;
+    for (uint32_t t = 1; t <= max_iter; ++t) {
+        uint64_t ch = 0;
+        for (int h = 0; h <= order; ++h) {  /* one pass, or the two halves */
+            const int nx = cur ^ 1;
+            for (uint32_t v = 0; v < n; ++v) {
+                if (order && orc_half_of(seed, t, v) != h) {  /* the other half keeps its state */
+                    memcpy(lab[nx] + (size_t)v * V, lab[cur] + (size_t)v * V, V * sizeof(uint32_t));
+                    memcpy(coef[nx] + (size_t)v * V, coef[cur] + (size_t)v * V, V * sizeof(uint32_t));
+                    cnt[nx][v] = cnt[cur][v];
+                    best[nx][v] = best[cur][v];
+                    continue;
+                }
+                tie_rule tie = {hashed, hashed ? orc_tie_key(seed, t, v) : 0u};
+                best[nx][v] = copra_vertex(v, rp, col, w, V, lab[cur], coef[cur], cnt[cur], buf, lab[nx], coef[nx],
+                                           &cnt[nx][v], tie);
+                ch += best[nx][v] != best[cur][v];
+            }
+            cur = nx;
+        }
+        if (changed_per_iter) changed_per_iter[t - 1] = ch;
+        *iterations = t;
+        if (ch <= thr) { *converged = 1; break; }
+    }
+    memcpy(best_out, best[cur], (size_t)n * sizeof(uint32_t));
+    if (state_lab && state_coef && state_cnt) {
+        memcpy(state_lab, lab[cur], (size_t)n * V * sizeof(uint32_t));
+        memcpy(state_coef, coef[cur], (size_t)n * V * sizeof(uint32_t));
+        memcpy(state_cnt, cnt[cur], (size_t)n * sizeof(uint32_t));
+    }
+    for (int s = 0; s < 2; ++s) { free(lab[s]); free(coef[s]); free(cnt[s]); free(best[s]); }
+    free(buf);
+    return 0;
+}

@@ -662,3 +662,150 @@ def test_parallel_oracle_ext_equals_sequential(gg, orc):
             a = orc.rak_ext(g, tol=0.0, max_iter=8, order=order, tie=tie, seed=77)
             b = orc.rak_ext(g, tol=0.0, max_iter=8, order=order, tie=tie, seed=77, parallel=True)
             assert np.array_equal(a.labels, b.labels) and a.changed == b.changed
+
+
+# ------------------------------------------------------------------ COPRA --
+
+ONE = 1 << 16  # the oracle's fixed-point belonging coefficient 1
+
+
+def brute_copra(E, A, V, tol, max_iter, order="sync", prio_t=None, halves_t=None):
+    """COPRA (Section 3.3) by its definition on a dense state matrix B[v][c]
+    (coefficients in units of 2^-16): collect sum_u A[v,u] B[u][c] for every
+    label value c, keep c iff tally * V >= total, keep only the best label
+    when nothing passes, normalise with floors and give the remainder to the
+    best label; a vertex with no arcs is its own community.  Returns the
+    best labels, the changed counts and the final state as sorted pairs."""
+    n = E.shape[0]
+    B = [[ONE if c == v else 0 for c in range(n)] for v in range(n)]
+    best = list(range(n))
+    thr = math.floor(tol * n)
+    changed = []
+
+    def vote(v, Bs, t):
+        total = int(A[v].sum()) * ONE
+        tally = [sum(int(A[v, u]) * Bs[u][c] for u in range(n)) for c in range(n)]
+        present = [c for c in range(n) if any(E[v, u] and Bs[u][c] for u in range(n))]
+        if not present:
+            return [ONE if c == v else 0 for c in range(n)], v
+        key = (lambda c: (tally[c], -c)) if prio_t is None else (lambda c: (tally[c], prio_t(t, v, c)))
+        b = max(present, key=key)
+        kept = [c for c in present if tally[c] > 0 and tally[c] * V >= total]
+        row = [0] * n
+        if not kept:
+            row[b] = ONE
+            return row, b
+        s = sum(tally[c] for c in kept)
+        for c in kept:
+            row[c] = tally[c] * ONE // s
+        row[b] += ONE - sum(row)
+        return row, b
+
+    for t in range(1, max_iter + 1):
+        nb = list(best)
+        passes = [None] if order == "sync" else [0, 1]
+        for h in passes:
+            NB = [list(r) for r in B]
+            for v in range(n):
+                if h is not None and halves_t(t)[v] != h:
+                    continue
+                NB[v], nb[v] = vote(v, B, t)
+            B = NB
+        ch = sum(1 for a, b in zip(best, nb) if a != b)
+        changed.append(ch)
+        best = nb
+        if ch <= thr:
+            break
+    state = [sorted((c, x) for c, x in enumerate(B[v]) if x) for v in range(n)]
+    return best, changed, state
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_copra_brute_force_small_graphs(gg, orc, n):
+    """Every graph on n <= 5 vertices, unit and random weights, max_labels 1
+    to 3, synchronous and semi-synchronous, strict and hashed ties: the
+    oracle's best labels, changed counts and final states equal the dense
+    definition."""
+    rng = np.random.default_rng(20 + n)
+    for edges in all_graphs(n):
+        if not edges:
+            continue
+        g = gg.from_edges(n, edges)
+        if rng.random() < 0.5:
+            wmap = {}
+            for a, b in edges:
+                wmap[(a, b)] = wmap[(b, a)] = int(rng.integers(1, 5))
+            src = np.repeat(np.arange(n), np.diff(g.row_ptr).astype(np.int64))
+            g.w = np.array([wmap[(int(s), int(d))] for s, d in zip(src, g.col)], dtype=np.uint32)
+        E, A = dense(g)
+        V = int(rng.integers(1, 4))
+        order = "semisync" if rng.random() < 0.5 else "sync"
+        tie = "hash" if rng.random() < 0.5 else "lowest"
+        seed = int(rng.integers(0, 1 << 63))
+        best, ch, state = brute_copra(E, A, V, 0.0, 5, order, hashed_prio(orc, seed) if tie == "hash" else None,
+                                      lambda t: [orc.half_of(seed, t, v) for v in range(n)])
+        r = orc.copra(g, max_labels=V, tol=0.0, max_iter=5, order=order, tie=tie, seed=seed)
+        assert r.labels.tolist() == best and r.changed == ch, (edges, V, order, tie)
+        assert r.state == state, (edges, V, order, tie)
+
+
+def test_copra_one_label_is_rak_without_self_loop(gg, orc):
+    """With max_labels 1 a label is kept only when it is the only one, so a
+    vertex takes its best label: COPRA is RAK with self weight 0 (labels and
+    changed counts), in every order and tie rule."""
+    for g in (gg.rmat(12, seed=3), gg.with_weights(gg.road(48, 48, 0.3, 0.01, 1, 8, seed=4), 2, 1, 8),
+              gg.with_weights(gg.sbm(800, 8, 0.1, 0.01, seed=5), 7, 1, 3)):
+        for order in ("sync", "semisync"):
+            for tie in ("lowest", "hash"):
+                c = orc.copra(g, max_labels=1, tol=0.0, max_iter=8, order=order, tie=tie, seed=11)
+                r = orc.rak_ext(g, tol=0.0, max_iter=8, self_weight=0, order=order, tie=tie, seed=11)
+                assert np.array_equal(c.labels, r.labels) and c.changed == r.changed, (g.name, order, tie)
+                assert all(len(s) == 1 and s[0][1] == ONE for s in c.state)
+
+
+def test_copra_state_invariants(gg, orc):
+    """Every vertex holds 1..max_labels labels whose coefficients sum to 1,
+    its best label among them with the largest coefficient."""
+    g = gg.with_weights(gg.rmat(11, seed=6), 3, 1, 6)
+    for V in (2, 4, 8):
+        r = orc.copra(g, max_labels=V, tol=0.0, max_iter=6, tie="hash", seed=V)
+        for v, st in enumerate(r.state):
+            assert 1 <= len(st) <= V
+            assert sum(x for _, x in st) == ONE
+            d = dict(st)
+            assert int(r.labels[v]) in d and d[int(r.labels[v])] == max(d.values())
+
+
+def test_copra_closed_forms(gg, orc):
+    # star K_{1,s}, max_labels >= s, one round: the centre keeps every leaf's
+    # label with floor(1/s) and the remainder on label 1 (lowest of the tied
+    # best); each leaf keeps the centre's label alone
+    for s in (3, 4, 5):
+        g = gg.from_edges(s + 1, [(0, i) for i in range(1, s + 1)])
+        r = orc.copra(g, max_labels=s, tol=0.0, max_iter=1)
+        q = ONE // s
+        assert r.state[0] == [(1, q + ONE - s * q)] + [(i, q) for i in range(2, s + 1)]
+        assert all(r.state[i] == [(0, ONE)] for i in range(1, s + 1))
+        assert r.labels.tolist() == [1] + [0] * s and r.changed == [s + 1]
+        # below the threshold: max_labels < s keeps only the best label
+        r = orc.copra(g, max_labels=s - 1, tol=0.0, max_iter=1)
+        assert r.state[0] == [(1, ONE)]
+    # clique K_s, max_labels >= s-1: round 1 every vertex keeps the s-1 other
+    # labels with equal shares, the remainder on the lowest other label
+    for s in (3, 4, 6):
+        g = gg.from_edges(s, itertools.combinations(range(s), 2))
+        r = orc.copra(g, max_labels=s - 1, tol=0.0, max_iter=1)
+        q = ONE // (s - 1)
+        for v in range(s):
+            others = [u for u in range(s) if u != v]
+            want = [(u, q + (ONE - (s - 1) * q if u == others[0] else 0)) for u in others]
+            assert r.state[v] == want
+    # isolated vertices stay their own community
+    g = gg.from_edges(4, [(0, 1)])
+    r = orc.copra(g, max_labels=2, tol=0.0, max_iter=3)
+    assert r.state[2] == [(2, ONE)] and r.state[3] == [(3, ONE)]
+    # arcs of weight 0 bring labels but no weight: the best (lowest) label alone
+    g = gg.from_edges(3, [(0, 1), (0, 2)])
+    g.w = np.zeros(g.m, np.uint32)
+    r = orc.copra(g, max_labels=4, tol=0.0, max_iter=1)
+    assert r.state[0] == [(1, ONE)] and r.state[1] == [(0, ONE)] and r.state[2] == [(0, ONE)]
