@@ -5,11 +5,16 @@ self weight 1): the planted-partition SBM, R-MAT scales 22 and 24 and the
 bit-exactly (labels, per-round changed counts, iterations), and the
 modularity integer terms are compared exactly.  The batched run is
 compared graph by graph: every graph of the 4096-graph batch with about
-1e8 arcs, and a sample (with the largest graphs) of the 4096-graph batch
-with about 1.7e9 arcs, plus properties checked on every graph.
+1e8 arcs and every graph of the 4096-graph batch with about 1.7e9 arcs,
+plus properties checked on every graph.  The semi-synchronous order and the
+hashed tie-break are compared at full size on the graphs that motivate them:
+the road lattice (synchronous rounds oscillate on it) and R-MAT 22 and the
+SBM (strict ties collapse them).
 """
+import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -86,11 +91,67 @@ def test_road4096_full(gg, orc, lpa, ctx):
     full_compare(gg, orc, lpa, ctx, g)
 
 
+def mode_compare(orc, lpa, g, order, tie, seed):
+    """A run in the given update order and tie rule against the oracle's
+    orc_rak_ext, bit for bit, with the quality it reaches."""
+    t = time.time()
+    dg = lpa.DeviceGraph.from_csr(g, "cuda")
+    with lpa.Context(0, order={"sync": 0, "semisync": 1}[order], tie={"lowest": 0, "hash": 1}[tie],
+                     seed=seed, modularity=1) as c:
+        lab, st = c.run(dg, tol=0.05, max_iter=20)
+    got = lpa.labels_to_numpy(lab)
+    say(f"{g.name} {order}/{tie}: gpu {st.iterations} rounds {st.changed} in {st.ms_total:.1f} ms, "
+        f"Q={st.modularity:.4f}")
+    ref = orc.rak_ext(g, tol=0.05, max_iter=20, self_weight=1, order=order, tie=tie, seed=seed, parallel=True)
+    say(f"{g.name} {order}/{tie}: oracle done in {time.time() - t:.1f}s")
+    assert st.changed == ref.changed and st.iterations == ref.iterations and st.converged == ref.converged
+    mism = np.flatnonzero(got != ref.labels)
+    assert mism.size == 0, f"{mism.size} labels differ, first {mism[:8]}"
+    assert st.arcs_processed == g.m * st.iterations
+    m = orc.modularity(g, ref.labels)
+    assert st.mod_terms == {"two_m": m.two_m, "sigma_in": m.sigma_in, "sum_k2": m.sum_k2}
+    return st
+
+
+@pytest.mark.timeout(900)
+def test_road4096_semisync_full(gg, orc, lpa):
+    # synchronous rounds oscillate on the lattice (97% of the vertices change
+    # every round); the semi-synchronous order converges
+    g = gg.road(4096, 4096, 0.3, 0.01, 1, 8, seed=4096)
+    for tie in ("lowest", "hash"):
+        st = mode_compare(orc, lpa, g, "semisync", tie, 1)
+        assert st.converged and st.modularity > 0.5
+
+
+@pytest.mark.timeout(900)
+def test_rmat22_hash_full(gg, orc, lpa):
+    g = gg.rmat(22, 16, 0.57, 0.19, 0.19, seed=22)
+    mode_compare(orc, lpa, g, "sync", "hash", 1)
+
+
+@pytest.mark.timeout(600)
+def test_sbm_config_modes_full(gg, orc, lpa):
+    # strict lowest-label ties collapse the planted partition (Q near 0);
+    # the hashed tie-break recovers it
+    g = gg.sbm(10000, 100, 0.1, 0.001, seed=1)
+    q = {}
+    for order in ("sync", "semisync"):
+        for tie in ("lowest", "hash"):
+            q[order, tie] = mode_compare(orc, lpa, g, order, tie, 1).modularity
+    assert q["sync", "hash"] > 0.4 and q["sync", "lowest"] < 0.1
+
+
+def _oracle_graph(orc, b, k):
+    g = b.graph(k)
+    return k, orc.rak(g, tol=0.05, max_iter=20, self_weight=1)
+
+
 def batch_compare(orc, lpa, ctx, b, which):
     t = time.time()
     dg = lpa.DeviceGraph.from_csr(b.csr, "cuda")
     lab, st = ctx.run_batch(dg, b.gv, tol=0.05, max_iter=20)
     got = lpa.labels_to_numpy(lab)
+    del dg
     say(f"{b.csr.name}: gpu {st.rounds} rounds, {st.converged_graphs}/{st.graphs} converged, "
         f"{st.ms_device:.1f} ms device, {st.ms_total:.1f} ms call")
     n_g = np.diff(b.gv).astype(np.int64)
@@ -102,15 +163,23 @@ def batch_compare(orc, lpa, ctx, b, which):
     assert np.all(st.converged | (st.iterations == 20))
     owner = np.repeat(np.arange(b.G), n_g)
     assert np.all(got.astype(np.int64) < n_g[owner])
-    for k in which:
-        g = b.graph(k)
-        ref = orc.rak(g, tol=0.05, max_iter=20, self_weight=1)
-        v0, v1 = int(b.gv[k]), int(b.gv[k + 1])
-        assert st.changed(k) == ref.changed, (k, st.changed(k), ref.changed)
-        assert bool(st.converged[k]) == ref.converged
-        mism = np.flatnonzero(got[v0:v1] != ref.labels)
-        assert mism.size == 0, f"graph {k} (n={g.n}): {mism.size} labels differ"
-    say(f"{b.csr.name}: {len(which)} graphs checked against the oracle in {time.time() - t:.1f}s")
+    # the sequential oracle per graph, graphs spread over host threads (the
+    # oracle's C call releases the interpreter lock); largest graphs first
+    which = sorted(which, key=lambda k: -int(n_g[k]))
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    done = 0
+    with ThreadPoolExecutor(workers) as ex:
+        for k, ref in ex.map(lambda k: _oracle_graph(orc, b, k), which):
+            v0, v1 = int(b.gv[k]), int(b.gv[k + 1])
+            assert st.changed(k) == ref.changed, (k, st.changed(k), ref.changed)
+            assert bool(st.converged[k]) == ref.converged
+            mism = np.flatnonzero(got[v0:v1] != ref.labels)
+            assert mism.size == 0, f"graph {k} (n={v1 - v0}): {mism.size} labels differ"
+            done += 1
+            if done % 512 == 0:
+                say(f"{b.csr.name}: {done}/{len(which)} graphs equal the oracle ({time.time() - t:.1f}s)")
+    say(f"{b.csr.name}: {len(which)} graphs checked against the oracle on {workers} threads "
+        f"in {time.time() - t:.1f}s")
 
 
 @pytest.mark.timeout(900)
@@ -123,13 +192,10 @@ def test_batch_50m_reading_every_graph(gg, orc, lpa, ctx):
 
 
 @pytest.mark.timeout(1200)
-def test_batch_literal_sampled(gg, orc, lpa, ctx):
+def test_batch_literal_every_graph(gg, orc, lpa, ctx):
     # 4096 SBM graphs, n log-uniform in [200, 200000]: about 1.7e9 arcs; the
-    # oracle re-runs a seeded sample that includes the four largest graphs
+    # sequential oracle re-runs every graph
     t = time.time()
     b = gg.sbm_batch(4096, 200, 200000, seed=4096)
     say(f"batch literal generated in {time.time() - t:.1f}s: n={b.csr.n} m={b.csr.m}")
-    n_g = np.diff(b.gv)
-    rng = np.random.default_rng(4096)
-    which = sorted(set(rng.choice(b.G, 24, replace=False).tolist()) | set(np.argsort(n_g)[-4:].tolist()))
-    batch_compare(orc, lpa, ctx, b, which)
+    batch_compare(orc, lpa, ctx, b, range(b.G))
