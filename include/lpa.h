@@ -50,8 +50,10 @@ typedef enum {
     LPA_ENOMEM = -3,       /* device or host allocation failed */
     LPA_EDEVICE = -4,      /* a HIP runtime call failed */
     LPA_EUNSUPPORTED = -5, /* option or size this build does not handle */
-    LPA_ETIMEDOUT = -6     /* a grid-wide wait of the batched kernel exceeded
+    LPA_ETIMEDOUT = -6,    /* a grid-wide wait of the batched kernel exceeded
                               its limit (every block left the kernel) */
+    LPA_ETOOLARGE = -7     /* the input exceeds the fixed scratch of
+                              lpa_modularity_noalloc */
 } lpa_status;
 
 typedef struct lpa_ctx lpa_ctx;
@@ -210,6 +212,22 @@ lpa_status lpa_run_resume(lpa_ctx *ctx, const lpa_csr *g, uint32_t *labels_inout
  * {2m, Sigma_in, low 64 bits of sum K_c^2, high 64 bits}. */
 lpa_status lpa_modularity(lpa_ctx *ctx, const lpa_csr *g, const uint32_t *labels,
                           double *q_out, uint64_t *terms);
+
+/* lpa_modularity for callers that cannot allocate (code between HIP graph
+ * captures, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result and terms as lpa_modularity, computed without any device, pinned
+ * or host allocation.  Its scratch is one fixed device array of
+ * LPA_NOALLOC_MAX_N + 2064 u64 words (about 32 MiB) per GPU, held until the
+ * process ends, whose address lpa_init looks up.  The CSR is read as stored
+ * (no relabelled copy); ctx supplies only the device and the stream.
+ * Every call on a GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (other streams, other threads, other contexts) race and must be
+ * serialised by the caller.  Returns when q_out and terms are final.
+ * Errors: LPA_ETOOLARGE when n > LPA_NOALLOC_MAX_N; LPA_EINVAL for a null
+ * pointer, a malformed row_ptr, a col value or a label >= n; LPA_EDEVICE. */
+#define LPA_NOALLOC_MAX_N (1u << 22)
+lpa_status lpa_modularity_noalloc(lpa_ctx *ctx, const lpa_csr *g, const uint32_t *labels,
+                                  double *q_out, uint64_t *terms);
 
 /* Batched-run statistics.  The per-graph arrays are optional host arrays
  * owned by the caller (NULL = not wanted). */

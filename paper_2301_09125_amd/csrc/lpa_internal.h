@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+typedef struct lpa_ctx lpa_ctx;
+
 namespace lpa {
 
 // Error bits raised by kernels into a device word.
@@ -351,6 +353,18 @@ hipError_t launch_row_sums(const Graph &g, uint32_t *kw, hipStream_t s);
 hipError_t launch_mask_rows(uint8_t *mask, const uint32_t *old_of, uint32_t lo, uint32_t cnt, uint8_t val,
                             hipStream_t s);
 
+// Modularity sums of a CSR as the caller stores it (any row length, row
+// bounds and labels checked in the kernel), and the final u128 reduction of
+// mod_sumsq_k's partials (lpa_mod.hip).
+hipError_t launch_mod_any(const ModArgs &a, hipStream_t s);
+hipError_t launch_mod_final(const unsigned long long *partials, uint32_t nparts, const unsigned long long *sums,
+                            const uint32_t *err, unsigned long long *out, hipStream_t s);
+// Fixed scratch of lpa_modularity_noalloc: look up its address on `device`
+// (current) once; called by lpa_init (lpa_noalloc.hip).
+hipError_t noalloc_attach(int device);
+// The device and stream a context was made with (lpa_runtime.hip).
+int ctx_device(const lpa_ctx *c);
+hipStream_t ctx_stream(const lpa_ctx *c);
 hipError_t launch_mod_sumsq(const unsigned long long *K, uint32_t n, unsigned long long *partials,
                             uint32_t nparts, hipStream_t s);
 

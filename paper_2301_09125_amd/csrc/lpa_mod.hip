@@ -333,6 +333,80 @@ __global__ __launch_bounds__(256) void mod_hub_k(ModArgs a, const HubItem *__res
     mod_finish(a, M, tw, sin);
 }
 
+// Any row length, on a CSR as the caller stores it (no binning): each
+// wavefront takes 64 rows; rows of at most 32 arcs are summed one lane
+// each, longer rows by the whole wavefront in 512-arc steps, one row after
+// another.  The row bounds and labels are checked here (a bad row is
+// skipped and flagged, a bad label counts as label 0 and is flagged), so no
+// access leaves the arrays whatever the input.
+__global__ __launch_bounds__(256) void mod_any_k(ModArgs a) {
+    __shared__ ModTable M;
+    mod_table_init(M);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t n = a.g.n;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (a.g.rp[0] != 0 || a.g.rp[n] != a.g.m)) atomicOr(a.err, ERR_ROWPTR);
+    u64 tw = 0, sin = 0;
+    for (uint32_t base = (blockIdx.x * 4 + wave) * 64; base < n; base += gridDim.x * 4 * 64) {
+        const uint32_t i = base + lane;
+        const bool act = i < n;
+        const uint32_t v = act ? i : 0u;
+        const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
+        uint32_t lv = a.labels[v];
+        const bool badrow = act && (b > e || e > a.g.m);
+        const bool badlab = act && lv >= n;
+        if (badrow) atomicOr(a.err, ERR_ROWPTR);
+        if (badlab) atomicOr(a.err, ERR_LABEL);
+        lv = badlab ? 0u : lv;
+        const bool ok = act && !badrow;
+        const bool one = ok && e - b <= 32;
+        u64 kv = 0;
+        if (one)
+            for (uint64_t k = b; k < e; k += 8) mod_arcs<8, 1>(a, k, e, lv, kv, sin);
+        tw += kv;
+        add_community(M, a.K, one, lv, kv);
+        u64 longm = __ballot(ok && !one);
+        while (longm) {
+            const int j = __ffsll((long long)longm) - 1;
+            longm &= longm - 1;
+            const uint32_t lj = (uint32_t)__shfl((int)lv, j, 64);
+            const uint64_t bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
+            u64 kw = 0;
+            for (uint64_t k0 = bj; k0 < ej; k0 += kWaveArcs)
+                mod_arcs<kWaveArcs / 64, 64>(a, k0 + lane, ej, lj, kw, sin);
+            kw = wave_sum(kw);
+            tw += lane == 0 ? kw : 0;
+            add_community(M, a.K, lane == 0, lj, kw);
+        }
+    }
+    mod_finish(a, M, tw, sin);
+}
+
+// One block: the u128 sum of the partials of mod_sumsq_k, with the two sums
+// and the error word, into out[0..4] = {sum K^2 low, high, 2m, Sigma_in,
+// error bits}.
+__global__ __launch_bounds__(256) void mod_final_k(const u64 *__restrict__ partials, uint32_t nparts,
+                                                   const u64 *__restrict__ sums, const uint32_t *__restrict__ err,
+                                                   u64 *out) {
+    __shared__ unsigned __int128 sh[256];
+    unsigned __int128 acc = 0;
+    for (uint32_t i = threadIdx.x; i < nparts; i += 256)
+        acc += ((unsigned __int128)partials[2 * i + 1] << 64) | (unsigned __int128)partials[2 * i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (uint32_t off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = (u64)sh[0];
+        out[1] = (u64)(sh[0] >> 64);
+        out[2] = sums[0];
+        out[3] = sums[1];
+        out[4] = *err;
+    }
+}
+
 // Per-block u128 partial sums of K_c^2, written as (lo, hi) pairs.
 __global__ __launch_bounds__(256) void mod_sumsq_k(const u64 *__restrict__ K, uint32_t n, u64 *partials) {
     __shared__ unsigned __int128 sh[256];
@@ -373,6 +447,16 @@ hipError_t launch_mod_hub(const ModArgs &a, const HubItem *items, uint32_t count
         mod_delta_hub_k<<<grid_for(count, 256, kModGrid), 256, 0, s>>>(a, items, count);
     else
         mod_hub_k<<<grid_for(count, 4, kModGrid), 256, 0, s>>>(a, items, count);
+    return hipGetLastError();
+}
+hipError_t launch_mod_any(const ModArgs &a, hipStream_t s) {
+    if (a.g.n == 0) return hipSuccess;
+    mod_any_k<<<grid_for(a.g.n, 256, kModGrid), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+hipError_t launch_mod_final(const u64 *partials, uint32_t nparts, const u64 *sums, const uint32_t *err, u64 *out,
+                            hipStream_t s) {
+    mod_final_k<<<1, 256, 0, s>>>(partials, nparts, sums, err, out);
     return hipGetLastError();
 }
 hipError_t launch_mod_sumsq(const u64 *K, uint32_t n, u64 *partials, uint32_t nparts, hipStream_t s) {

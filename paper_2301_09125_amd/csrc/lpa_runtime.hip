@@ -121,6 +121,11 @@ struct lpa_ctx {
     lpa_kernel_prof prof[K_COUNT];
 };
 
+namespace lpa {
+int ctx_device(const lpa_ctx *c) { return c->device; }
+hipStream_t ctx_stream(const lpa_ctx *c) { return c->stream; }
+}  // namespace lpa
+
 namespace {
 
 lpa_status dev_status(hipError_t e) {
@@ -1384,6 +1389,9 @@ lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *
     c->stream = static_cast<hipStream_t>(stream);
     c->opt = o;
     c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    // address of lpa_modularity_noalloc's fixed scratch on this device; a
+    // failed lookup is retried (and reported) by that entry point
+    (void)noalloc_attach(device);
     for (int k = 0; k < K_COUNT; ++k) {
         std::memset(&c->prof[k], 0, sizeof(lpa_kernel_prof));
         std::snprintf(c->prof[k].name, sizeof(c->prof[k].name), "%s", kKernelNames[k]);
@@ -1747,6 +1755,7 @@ const char *lpa_strerror(lpa_status s) {
         case LPA_EDEVICE: return "HIP runtime error";
         case LPA_EUNSUPPORTED: return "unsupported option or size";
         case LPA_ETIMEDOUT: return "a grid-wide wait of the batched kernel timed out";
+        case LPA_ETOOLARGE: return "the input exceeds the fixed scratch of the allocation-free entry point";
     }
     return "unknown status";
 }

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "liblpa.so")
 
 LPA_OK, LPA_EINVAL, LPA_EOVERFLOW, LPA_ENOMEM, LPA_EDEVICE, LPA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LPA_ETIMEDOUT = -6
+LPA_ETOOLARGE = -7
+LPA_NOALLOC_MAX_N = 1 << 22
 LPA_ORDER_SYNC, LPA_ORDER_SEMISYNC = 0, 1
 LPA_TIE_LOWEST, LPA_TIE_HASH = 0, 1
 
@@ -117,6 +119,7 @@ class _KProf(ctypes.Structure):
 
 EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_run_batch", "lpa_run_learned",
            "lpa_trace", "lpa_train", "lpa_mlp_forward", "lpa_mlp_grad", "lpa_autotune", "lpa_modularity",
+           "lpa_modularity_noalloc",
            "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
 
 
@@ -147,6 +150,8 @@ def _load():
                                  ctypes.POINTER(u32)]
     lib.lpa_modularity.argtypes = [vp, ctypes.POINTER(_Csr), vp, ctypes.POINTER(dbl),
                                    ctypes.POINTER(ctypes.c_uint64)]
+    lib.lpa_modularity_noalloc.argtypes = [vp, ctypes.POINTER(_Csr), vp, ctypes.POINTER(dbl),
+                                           ctypes.POINTER(ctypes.c_uint64)]
     lib.lpa_profile_get.argtypes = [vp, ctypes.POINTER(_KProf), u32, ctypes.POINTER(u32)]
     lib.lpa_profile_reset.argtypes = [vp]
     lib.lpa_destroy.argtypes = [vp]
@@ -156,7 +161,8 @@ def _load():
     for f in (lib.lpa_run_learned, lib.lpa_trace, lib.lpa_train, lib.lpa_mlp_forward, lib.lpa_mlp_grad,
               lib.lpa_autotune):
         f.restype = ctypes.c_int
-    for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_run_batch, lib.lpa_modularity, lib.lpa_profile_get,
+    for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_run_batch, lib.lpa_modularity, lib.lpa_modularity_noalloc,
+              lib.lpa_profile_get,
               lib.lpa_profile_reset):
         f.restype = ctypes.c_int
     _lib = lib
@@ -483,6 +489,19 @@ class Context:
                                     ctypes.byref(q), terms)
         if rc:
             raise LpaError(rc, "lpa_modularity")
+        return q.value, {"two_m": int(terms[0]), "sigma_in": int(terms[1]),
+                         "sum_k2": int(terms[2]) + (int(terms[3]) << 64)}
+
+    def modularity_noalloc(self, g: DeviceGraph, labels):
+        """As modularity(), through lpa_modularity_noalloc (fixed scratch,
+        no allocation; n <= LPA_NOALLOC_MAX_N)."""
+        q = ctypes.c_double(0)
+        terms = (ctypes.c_uint64 * 4)()
+        c = g._c()
+        rc = _load().lpa_modularity_noalloc(self._h, ctypes.byref(c), labels.data_ptr() if g.n else None,
+                                            ctypes.byref(q), terms)
+        if rc:
+            raise LpaError(rc, "lpa_modularity_noalloc")
         return q.value, {"two_m": int(terms[0]), "sigma_in": int(terms[1]),
                          "sum_k2": int(terms[2]) + (int(terms[3]) << 64)}
 
