@@ -213,6 +213,39 @@ lpa_status lpa_run_resume(lpa_ctx *ctx, const lpa_csr *g, uint32_t *labels_inout
 lpa_status lpa_modularity(lpa_ctx *ctx, const lpa_csr *g, const uint32_t *labels,
                           double *q_out, uint64_t *terms);
 
+/* COPRA (Section 3.3): label propagation in which every vertex holds up to
+ * max_labels (1..64) pairs (label, belonging coefficient), coefficients
+ * summing to 1.  From every vertex alone with belonging 1, each round a
+ * vertex collects its neighbours' pairs, each coefficient multiplied by the
+ * connecting edge weight (its own pairs are not collected); it keeps the
+ * labels whose collected weight is positive and at least 1/max_labels of
+ * the total, or, if none is, its best label alone; and it normalises what
+ * it kept.  The best label is the heaviest collected one, ties broken as
+ * options.tie says (lowest label, or the hashed priority of non-strict
+ * RAK); a vertex without arcs is its own community.  Rounds follow
+ * options.order (synchronous, or the semi-synchronous halves of RAK, the
+ * deterministic stand-in for the paper's asynchronous COPRA) and stop after
+ * round t iff at most floor(tol * n) best labels changed in it, or after
+ * max_iter rounds (the paper settles on tol = 0.01 for COPRA).
+ * Coefficients are exact fixed point: integers in units of 2^-16 (65536 =
+ * 1); a kept label gets floor(tally * 65536 / kept_sum) and the best label
+ * also what the floors leave out of 65536.  options.self_weight does not
+ * apply; options.frontier must be 0 (LPA_EUNSUPPORTED otherwise).
+ * labels_out: device u32[n], the best label of every vertex (the disjoint
+ * result).  state_labels / state_coefs: device u32[n * max_labels] or NULL:
+ * vertex v's kept pairs in slots v * max_labels + i, i < state_count[v],
+ * labels increasing; state_count: device u32[n] or NULL.  The CSR is read
+ * as stored (no relabelled copy); the context holds about
+ * 16 * max_labels + 20 bytes per vertex of state, and tables in device
+ * memory for rows whose distinct labels outgrow the on-chip table (at most
+ * 24 * deg * max_labels bytes for such a row).  stats: as lpa_run (changed
+ * counts are best-label changes; arcs_processed = m per round; with
+ * options.modularity the modularity of labels_out).  Errors: as lpa_run,
+ * LPA_EINVAL also for max_labels outside 1..64. */
+lpa_status lpa_run_copra(lpa_ctx *ctx, const lpa_csr *g, uint32_t max_labels, uint32_t *labels_out,
+                         uint32_t *state_labels, uint32_t *state_coefs, uint32_t *state_count, double tol,
+                         uint32_t max_iter, lpa_stats *stats);
+
 /* lpa_modularity for callers that cannot allocate (code between HIP graph
  * captures, tight serving loops, harnesses that forbid hipMalloc): the same
  * result and terms as lpa_modularity, computed without any device, pinned

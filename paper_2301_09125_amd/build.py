@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "liblpa.so")
 SOURCES = ["csrc/lpa_prep.hip", "csrc/lpa_vote.hip", "csrc/lpa_mod.hip", "csrc/lpa_batch.hip", "csrc/lpa_learned.hip",
-           "csrc/lpa_runtime.hip", "csrc/lpa_noalloc.hip"]
+           "csrc/lpa_runtime.hip", "csrc/lpa_noalloc.hip",
+           "csrc/lpa_copra.hip"]
 ARCH = os.environ.get("LPA_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1,0 +1,473 @@
+// lpa_copra.hip -- COPRA (arXiv 2301.09125, Section 3.3): label propagation
+// where every vertex holds up to max_labels (label, belonging coefficient)
+// pairs.  Each round a vertex collects its neighbours' pairs, each scaled by
+// the connecting edge weight, keeps the labels whose share of the collected
+// weight reaches 1/max_labels (or, if none does, its best label alone) and
+// normalises what it kept.  The run stops as RAK does, on the vertices whose
+// best label changed.
+//
+// Exact arithmetic: coefficients are integers in units of 2^-16 (65536 =
+// belonging 1).  The tally of label c at v is sum over arcs (v,u,w) of
+// w * b_u(c), below 2^48 because weighted degrees stay below 2^32; the
+// collected total is weighted_degree(v) * 2^16.  Label c is kept iff its
+// tally is positive and tally * max_labels >= total.  New coefficients are
+// floor(tally * 2^16 / kept_sum), and what the floors leave out of 2^16 goes
+// to the best label (largest tally; ties to the lowest label, or to the
+// highest lowbias32(label ^ k) with the hashed rule).  A vertex that
+// collects nothing (no arcs) is its own community.  Kept labels are stored
+// in increasing label order.
+//
+// State: lab / coef u32[n * V] (slot i of vertex v at v * V + i, the first
+// cnt[v] slots valid), cnt u32[n], best u32[n], double-buffered.  The rounds
+// read the caller's CSR directly (original ids, no relabelled copy):
+//   copra_wave_k   rows with deg * V <= 512: one wavefront per row, an LDS
+//                  table of next_pow2(2 * deg * V) slots (<= 1024);
+//   copra_block_k  the other rows: one block per row, a 4096-slot LDS
+//                  table; a row whose distinct labels would fill more than
+//                  3/4 of it is listed for
+//   copra_global_k one block per listed row, a table in device memory of
+//                  next_pow2(2 * min(deg * V, n)) slots (at least twice the
+//                  row's distinct labels).
+// Semi-synchronous rounds: two half-rounds, a vertex votes in the half its
+// SplitMix64 draw for the round names and copies its state in the other.
+
+#include "lpa_device.h"
+
+namespace lpa {
+
+constexpr uint32_t kOne = 65536u;
+constexpr uint32_t kCopraWaveSlots = 1024;
+constexpr uint32_t kCopraBlockSlots = 4096;
+constexpr uint32_t kCopraBlockFill = 3072;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+
+__device__ __forceinline__ bool copra_votes(const CopraArgs &a, uint32_t v) {
+    if (!a.half) return true;
+    const u64 c = (((u64)a.t << 32) | v) << 1;
+    return (uint32_t)(splitmix64_at(a.seed, c) >> 63) == a.half - 1;
+}
+
+__device__ __forceinline__ Tie copra_tie(const CopraArgs &a, uint32_t v) {
+    Tie t{a.tie, 0u};
+    if (a.tie) t.k = (uint32_t)splitmix64_at(a.seed, ((((u64)a.t << 32) | v) << 1) | 1u);
+    return t;
+}
+
+// Insert (lab, x) into a table of mask+1 slots (LDS or device memory) with
+// linear probing, giving up after mask+1 probes: 1 = claimed a new slot,
+// 0 = added to the label's slot, -1 = no free slot (nothing added).
+__device__ __forceinline__ int copra_insert_bounded(uint32_t *key, u64 *tal, uint32_t mask, uint32_t lab, u64 x) {
+    uint32_t h = hmix(lab) & mask;
+    for (uint32_t p = 0; p <= mask; ++p) {
+        const uint32_t prev = atomicCAS(&key[h], kEmptyKey, lab);
+        if (prev == kEmptyKey || prev == lab) {
+            atomicAdd(&tal[h], x);
+            return prev == kEmptyKey ? 1 : 0;
+        }
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+// Copy vertex v's state unchanged (the other half of a semi-synchronous round).
+__device__ __forceinline__ void copra_copy(const CopraArgs &a, uint32_t v, uint32_t lane, uint32_t lanes) {
+    for (uint32_t i = lane; i < a.V; i += lanes) {
+        a.lab_out[(u64)v * a.V + i] = a.lab_in[(u64)v * a.V + i];
+        a.coef_out[(u64)v * a.V + i] = a.coef_in[(u64)v * a.V + i];
+    }
+    if (lane == 0) {
+        a.cnt_out[v] = a.cnt_in[v];
+        a.best_out[v] = a.best_in[v];
+    }
+}
+
+// A vertex with nothing to collect: its own community.
+__device__ __forceinline__ void copra_alone(const CopraArgs &a, uint32_t v, uint32_t lab) {
+    a.lab_out[(u64)v * a.V] = lab;
+    a.coef_out[(u64)v * a.V] = kOne;
+    a.cnt_out[v] = 1;
+    a.best_out[v] = lab;
+}
+
+// Write the kept labels klab[0..kn) (coefficients before the remainder in
+// kcoef) in increasing label order, the remainder to `best`.  Lanes 0..63 of
+// one wavefront call this; kn <= V <= 64.
+__device__ __forceinline__ void copra_store(const CopraArgs &a, uint32_t v, uint32_t lane, const uint32_t *klab,
+                                            const uint32_t *kcoef, uint32_t kn, uint32_t best) {
+    const bool mine = lane < kn;
+    const uint32_t l = mine ? klab[lane] : 0u;
+    uint32_t c = mine ? kcoef[lane] : 0u;
+    const uint32_t given = wave_sum(c);
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < kn; ++j) rank += klab[j] < l;
+    if (mine && l == best) c += kOne - given;
+    if (mine) {
+        a.lab_out[(u64)v * a.V + rank] = l;
+        a.coef_out[(u64)v * a.V + rank] = c;
+    }
+    if (lane == 0) {
+        a.cnt_out[v] = kn;
+        a.best_out[v] = best;
+    }
+}
+
+// One wavefront per row, rows with deg * V <= 512.
+__global__ __launch_bounds__(256) void copra_wave_k(CopraArgs a) {
+    __shared__ uint32_t skey[4][kCopraWaveSlots];
+    __shared__ u64 stal[4][kCopraWaveSlots];
+    __shared__ uint32_t sklab[4][64], skcoef[4][64], skn[4];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t *key = skey[wave];
+    u64 *tal = stal[wave];
+    const uint32_t V = a.V;
+    u64 chg = 0;
+    for (uint32_t v = blockIdx.x * 4 + wave; v < a.g.n; v += gridDim.x * 4) {
+        const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
+        const uint64_t deg = e - b;
+        if (deg * V > 512) continue;  // copra_block_k
+        if (!copra_votes(a, v)) {
+            copra_copy(a, v, lane, 64);
+            continue;
+        }
+        const uint32_t old_best = a.best_in[v];
+        if (deg == 0) {
+            if (lane == 0) {
+                copra_alone(a, v, v);
+                chg += old_best != v;
+            }
+            continue;
+        }
+        const Tie tie = copra_tie(a, v);
+        const uint32_t S = next_pow2((uint32_t)(2 * deg * V));
+        for (uint32_t s = lane; s < S; s += 64) {
+            key[s] = kEmptyKey;
+            tal[s] = 0;
+        }
+        if (lane == 0) skn[wave] = 0;
+        wave_sync();
+        u64 tw = 0;
+        for (uint64_t k0 = b; k0 < e; k0 += 64) {
+            const uint64_t k = k0 + lane;
+            const bool in = k < e;
+            const uint32_t u = in ? a.g.col[k] : 0u;
+            const uint32_t we = in ? (a.g.w ? a.g.w[k] : 1u) : 0u;
+            const uint32_t c = in ? a.cnt_in[u] : 0u;
+            tw += we;
+            for (uint32_t i = 0; i < c; ++i)
+                if (copra_insert_bounded(key, tal, S - 1, a.lab_in[(u64)u * V + i],
+                                         (u64)we * a.coef_in[(u64)u * V + i]) < 0)
+                    atomicOr(a.err, ERR_TABLE);  // cannot happen: distinct labels <= deg * V <= S / 2
+        }
+        wave_sync();
+        const u64 total = wave_sum(tw) * kOne;
+        u64 m1 = 0;  // largest tally + 1 over the occupied slots
+        for (uint32_t s = lane; s < S; s += 64)
+            if (key[s] != kEmptyKey) m1 = umax64(m1, tal[s] + 1);
+        m1 = wave_max64(m1);
+        u64 bc = 0;  // largest tie code among the heaviest labels
+        u64 ksum = 0, kcnt = 0;
+        for (uint32_t s = lane; s < S; s += 64) {
+            const uint32_t l = key[s];
+            if (l == kEmptyKey) continue;
+            const u64 t = tal[s];
+            if (t + 1 == m1) bc = umax64(bc, tie_code(tie, l));
+            if (t > 0 && t * V >= total) {
+                ksum += t;
+                ++kcnt;
+            }
+        }
+        bc = wave_max64(bc);
+        ksum = wave_sum(ksum);
+        kcnt = wave_sum(kcnt);
+        const uint32_t best = tie_label(tie, (uint32_t)bc);
+        if (kcnt == 0) {
+            if (lane == 0) copra_alone(a, v, best);
+        } else {
+            for (uint32_t s = lane; s < S; s += 64) {
+                const uint32_t l = key[s];
+                if (l == kEmptyKey) continue;
+                const u64 t = tal[s];
+                if (t > 0 && t * V >= total) {
+                    const uint32_t j = atomicAdd(&skn[wave], 1u);
+                    sklab[wave][j] = l;
+                    skcoef[wave][j] = (uint32_t)(t * kOne / ksum);
+                }
+            }
+            wave_sync();
+            copra_store(a, v, lane, sklab[wave], skcoef[wave], (uint32_t)kcnt, best);
+        }
+        if (lane == 0) chg += old_best != best;
+        wave_sync();  // the table is cleared for the next row
+    }
+    block_count(chg, a.changed);
+}
+
+// A table entry: from LDS, or from device memory past the L1 cache (the
+// entries were written by device-scope atomics).
+template <bool GLOBAL, typename T>
+__device__ __forceinline__ T tload(const T *p) {
+    if constexpr (GLOBAL)
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+
+// The vote of row v from a filled table of S slots (LDS, or device memory
+// when GLOBAL), by a 256-thread block; reductions and kept lists in LDS.
+template <bool GLOBAL>
+__device__ __forceinline__ uint32_t copra_finish_block(const CopraArgs &a, uint32_t v, Tie tie, const uint32_t *key,
+                                                       const u64 *tal, uint32_t S, u64 total, BlockRed *red,
+                                                       uint32_t *klab, uint32_t *kcoef, uint32_t *kn) {
+    const uint32_t V = a.V;
+    u64 m1 = 0, z1 = 0, z2 = 0;
+    uint32_t zo = 0;
+    for (uint32_t s = threadIdx.x; s < S; s += 256)
+        if (tload<GLOBAL>(&key[s]) != kEmptyKey) m1 = umax64(m1, tload<GLOBAL>(&tal[s]) + 1);
+    block_reduce(red[0], m1, z1, z2, zo);
+    u64 bc = 0, ksum = 0, kcnt = 0;
+    for (uint32_t s = threadIdx.x; s < S; s += 256) {
+        const uint32_t l = tload<GLOBAL>(&key[s]);
+        if (l == kEmptyKey) continue;
+        const u64 t = tload<GLOBAL>(&tal[s]);
+        if (t + 1 == m1) bc = umax64(bc, tie_code(tie, l));
+        if (t > 0 && t * V >= total) {
+            ksum += t;
+            ++kcnt;
+        }
+    }
+    zo = 0;
+    block_reduce(red[1], bc, ksum, kcnt, zo);
+    const uint32_t best = tie_label(tie, (uint32_t)bc);
+    if (kcnt == 0) {
+        if (threadIdx.x == 0) copra_alone(a, v, best);
+        return best;
+    }
+    for (uint32_t s = threadIdx.x; s < S; s += 256) {
+        const uint32_t l = tload<GLOBAL>(&key[s]);
+        if (l == kEmptyKey) continue;
+        const u64 t = tload<GLOBAL>(&tal[s]);
+        if (t > 0 && t * V >= total) {
+            const uint32_t j = atomicAdd(kn, 1u);
+            klab[j] = l;
+            kcoef[j] = (uint32_t)(t * kOne / ksum);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) copra_store(a, v, threadIdx.x, klab, kcoef, (uint32_t)kcnt, best);
+    return best;
+}
+
+// One block per row of deg * V > 512 (rows listed in `rows`), a 4096-slot
+// LDS table; rows with too many distinct labels are listed for the global
+// table.
+__global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count) {
+    __shared__ uint32_t key[kCopraBlockSlots];
+    __shared__ u64 tal[kCopraBlockSlots];
+    __shared__ BlockRed red[3];
+    __shared__ uint32_t klab[64], kcoef[64], kn, claimed, full;
+    const uint32_t V = a.V;
+    u64 chg = 0;
+    for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+        const uint32_t v = rows[it];
+        if (!copra_votes(a, v)) {
+            copra_copy(a, v, threadIdx.x, 256);
+            continue;
+        }
+        const Tie tie = copra_tie(a, v);
+        for (uint32_t s = threadIdx.x; s < kCopraBlockSlots; s += 256) {
+            key[s] = kEmptyKey;
+            tal[s] = 0;
+        }
+        if (threadIdx.x == 0) {
+            kn = 0;
+            claimed = 0;
+            full = 0;
+        }
+        __syncthreads();
+        const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
+        u64 tw = 0;
+        for (uint64_t k = b + threadIdx.x; k < e; k += 256) {
+            const uint32_t we = a.g.w ? a.g.w[k] : 1u;
+            tw += we;
+            if (__atomic_load_n(&full, __ATOMIC_RELAXED)) continue;
+            const uint32_t u = a.g.col[k];
+            const uint32_t c = a.cnt_in[u];
+            for (uint32_t i = 0; i < c; ++i) {
+                // the table is given up once 3/4 of it is claimed (or a probe
+                // finds no slot): the row then goes to the device-memory table
+                if (__atomic_load_n(&full, __ATOMIC_RELAXED)) break;
+                const int r = copra_insert_bounded(key, tal, kCopraBlockSlots - 1, a.lab_in[(u64)u * V + i],
+                                                   (u64)we * a.coef_in[(u64)u * V + i]);
+                if (r < 0 || (r > 0 && atomicAdd(&claimed, 1u) + 1 >= kCopraBlockFill)) {
+                    __atomic_store_n(&full, 1u, __ATOMIC_RELAXED);
+                    break;
+                }
+            }
+        }
+        u64 z1 = 0, z2 = 0;
+        uint32_t zo = 0;
+        block_reduce(red[2], z1, tw, z2, zo);
+        if (full) {
+            if (threadIdx.x == 0) a.ovf_rows[atomicAdd(a.ovf_count, 1u)] = v;
+            __syncthreads();
+            continue;
+        }
+        const uint32_t best = copra_finish_block<false>(a, v, tie, key, tal, kCopraBlockSlots, tw * kOne, red, klab, kcoef,
+                                                 &kn);
+        if (threadIdx.x == 0) chg += a.best_in[v] != best;
+        __syncthreads();  // tables and reductions are reused by the next row
+    }
+    block_count(chg, a.changed);
+}
+
+// One block per listed row, its table at slab + off[i] (off[count] = end),
+// filled with empty keys and zero tallies beforehand.
+__global__ __launch_bounds__(256) void copra_global_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count,
+                                                      const u64 *__restrict__ off, uint32_t *slab_key,
+                                                      u64 *slab_tal) {
+    __shared__ BlockRed red[3];
+    __shared__ uint32_t klab[64], kcoef[64], kn;
+    const uint32_t V = a.V;
+    u64 chg = 0;
+    for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+        const uint32_t v = rows[it];
+        const Tie tie = copra_tie(a, v);
+        const u64 o = off[it];
+        const uint32_t S = (uint32_t)(off[it + 1] - o);
+        uint32_t *key = slab_key + o;
+        u64 *tal = slab_tal + o;
+        if (threadIdx.x == 0) kn = 0;
+        const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
+        u64 tw = 0;
+        for (uint64_t k = b + threadIdx.x; k < e; k += 256) {
+            const uint32_t we = a.g.w ? a.g.w[k] : 1u;
+            tw += we;
+            const uint32_t u = a.g.col[k];
+            const uint32_t c = a.cnt_in[u];
+            for (uint32_t i = 0; i < c; ++i)
+                if (copra_insert_bounded(key, tal, S - 1, a.lab_in[(u64)u * V + i],
+                                         (u64)we * a.coef_in[(u64)u * V + i]) < 0)
+                    atomicOr(a.err, ERR_TABLE);  // cannot happen: S >= 2 * distinct labels
+        }
+        u64 z1 = 0, z2 = 0;
+        uint32_t zo = 0;
+        block_reduce(red[2], z1, tw, z2, zo);  // every insertion of the row is done after its barrier
+        const uint32_t best = copra_finish_block<true>(a, v, tie, key, tal, S, tw * kOne, red, klab, kcoef, &kn);
+        if (threadIdx.x == 0) chg += a.best_in[v] != best;
+        __syncthreads();
+    }
+    block_count(chg, a.changed);
+}
+
+// Every vertex its own community with belonging 1.
+__global__ void copra_init_k(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        lab[(u64)v * V] = v;
+        coef[(u64)v * V] = kOne;
+        cnt[v] = 1;
+        best[v] = v;
+    }
+}
+
+// Rows of deg * V > 512, appended in any order (the result does not depend
+// on it).
+__global__ void copra_list_k(Graph g, uint32_t V, uint32_t *rows, uint32_t *count) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x)
+        if ((g.rp[v + 1] - g.rp[v]) * V > 512) rows[atomicAdd(count, 1u)] = v;
+}
+
+// Table sizes of the listed rows: next_pow2(2 * min(deg * V, n)).
+__global__ void copra_sizes_k(Graph g, uint32_t V, const uint32_t *rows, uint32_t count, u64 *size) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const uint32_t v = rows[i];
+        u64 d = (g.rp[v + 1] - g.rp[v]) * V;
+        d = d < g.n ? d : g.n;
+        u64 s = 1;
+        while (s < 2 * d && s < (1ull << 31)) s <<= 1;  // 2^31 slots: more than any row's labels here
+        size[i] = s;
+    }
+}
+
+// The caller's CSR, checked before any round reads it: row_ptr starts at 0,
+// never decreases and ends at m; every col < n; every weighted degree below
+// 2^32.  One wavefront per 64 rows, long rows summed by the whole wavefront.
+__global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (g.rp[0] != 0 || g.rp[g.n] != g.m)) atomicOr(err, ERR_ROWPTR);
+    uint32_t bits = 0;
+    for (uint32_t base = (blockIdx.x * 4 + wave) * 64; base < g.n; base += gridDim.x * 4 * 64) {
+        const uint32_t i = base + lane;
+        const bool act = i < g.n;
+        const uint32_t v = act ? i : 0u;
+        const uint64_t b = g.rp[v], e = g.rp[v + 1];
+        const bool bad = act && (b > e || e > g.m);
+        bits |= bad ? ERR_ROWPTR : 0u;
+        const bool ok = act && !bad;
+        const bool one = ok && e - b <= 32;
+        if (one) {
+            u64 tw = 0;
+            for (uint64_t k = b; k < e; ++k) {
+                bits |= g.col[k] >= g.n ? ERR_COL : 0u;
+                tw += g.w ? g.w[k] : 1u;
+            }
+            bits |= tw > 0xFFFFFFFFull ? ERR_WOVF : 0u;
+        }
+        u64 longm = __ballot(ok && !one);
+        while (longm) {
+            const int j = __ffsll((long long)longm) - 1;
+            longm &= longm - 1;
+            const uint64_t bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
+            u64 tw = 0;
+            for (uint64_t k = bj + lane; k < ej; k += 64) {
+                bits |= g.col[k] >= g.n ? ERR_COL : 0u;
+                tw += g.w ? g.w[k] : 1u;
+            }
+            tw = wave_sum(tw);
+            bits |= tw > 0xFFFFFFFFull ? ERR_WOVF : 0u;
+        }
+    }
+    if (bits) atomicOr(err, bits);
+}
+
+hipError_t launch_csr_check(const Graph &g, uint32_t *err, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    csr_check_k<<<grid_for(g.n, 256, 4096), 256, 0, s>>>(g, err);
+    return hipGetLastError();
+}
+hipError_t launch_copra_init(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best,
+                             hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    copra_init_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, V, lab, coef, cnt, best);
+    return hipGetLastError();
+}
+hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows, uint32_t *count, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    copra_list_k<<<grid_for(g.n, 256, 8192), 256, 0, s>>>(g, V, rows, count);
+    return hipGetLastError();
+}
+hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count, u64 *size,
+                              hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    copra_sizes_k<<<grid_for(count, 256, 4096), 256, 0, s>>>(g, V, rows, count, size);
+    return hipGetLastError();
+}
+hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *big_rows, uint32_t n_big, hipStream_t s) {
+    if (a.g.n == 0) return hipSuccess;
+    copra_wave_k<<<grid_for(a.g.n, 4, 8192), 256, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && n_big) {
+        copra_block_k<<<grid_for(n_big, 1, 4096), 256, 0, s>>>(a, big_rows, n_big);
+        e = hipGetLastError();
+    }
+    return e;
+}
+hipError_t launch_copra_global(const CopraArgs &a, const uint32_t *rows, uint32_t count, const u64 *off,
+                               uint32_t *slab_key, u64 *slab_tal, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    copra_global_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(a, rows, count, off, slab_key, slab_tal);
+    return hipGetLastError();
+}
+
+}  // namespace lpa

@@ -27,6 +27,7 @@ enum : uint32_t {
     ERR_LABEL = 8u,   // a label value >= n
     ERR_TIMEOUT = 16u,  // a grid barrier of the batch kernel waited too long
     ERR_GRAPH = 32u,  // a batch arc leaves its graph
+    ERR_TABLE = 64u,  // a COPRA hashtable had no free slot (a size bound was broken)
 };
 
 // Degree bins in internal layout order (see lpa_options in lpa.h).
@@ -174,6 +175,23 @@ struct ModArgs {
     // rows whose label changed in the last round read their arcs' labels
     // (see launch_mod_rows).
     const uint32_t *labels_prev;
+};
+
+// One COPRA half-round (lpa_copra.hip) on the caller's CSR: the state of
+// the round before (lab/coef: V slots per vertex, cnt valid slots, best
+// label) and the state written.  half 0 = every vertex votes; 1 / 2 = only
+// the vertices whose draw names that half, the others copy their state.
+struct CopraArgs {
+    Graph g;
+    uint32_t V;  // max_labels, 1..64
+    const uint32_t *lab_in, *coef_in, *cnt_in, *best_in;
+    uint32_t *lab_out, *coef_out, *cnt_out, *best_out;
+    uint32_t t, half, tie;
+    unsigned long long seed;
+    unsigned long long *changed;  // kCountWords counter words: best labels changed
+    uint32_t *ovf_rows;           // rows left to the device-memory table ...
+    uint32_t *ovf_count;          // ... and their number
+    uint32_t *err;                // ERR_TABLE if a table had no free slot
 };
 
 // Batched run: state of the persistent kernel (lpa_batch.hip).  The bins
@@ -353,6 +371,19 @@ hipError_t launch_row_sums(const Graph &g, uint32_t *kw, hipStream_t s);
 hipError_t launch_mask_rows(uint8_t *mask, const uint32_t *old_of, uint32_t lo, uint32_t cnt, uint8_t val,
                             hipStream_t s);
 
+// ---- launchers: lpa_copra.hip --------------------------------------------
+// Check a caller's CSR (row_ptr, col < n, weighted degrees < 2^32) into err.
+hipError_t launch_csr_check(const Graph &g, uint32_t *err, hipStream_t s);
+hipError_t launch_copra_init(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best,
+                             hipStream_t s);
+// Rows of deg * V > 512 into rows[0..*count) (count zeroed by the caller).
+hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows, uint32_t *count, hipStream_t s);
+hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count,
+                              unsigned long long *size, hipStream_t s);
+hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *big_rows, uint32_t n_big, hipStream_t s);
+hipError_t launch_copra_global(const CopraArgs &a, const uint32_t *rows, uint32_t count,
+                               const unsigned long long *off, uint32_t *slab_key, unsigned long long *slab_tal,
+                               hipStream_t s);
 // Modularity sums of a CSR as the caller stores it (any row length, row
 // bounds and labels checked in the kernel), and the final u128 reduction of
 // mod_sumsq_k's partials (lpa_mod.hip).

@@ -60,7 +60,7 @@ struct DevBuf {
 
 enum KernelId {
     K_THREAD, K_GROUP, K_WAVE, K_WIDE, K_HUB, K_HUB1, K_MERGE, K_FALLBACK, K_REDUCE, K_FINAL, K_MOD,
-    K_PREDICT, K_PUSH, K_LISTED, K_COUNT
+    K_PREDICT, K_PUSH, K_LISTED, K_COPRA, K_COPRA_GLOBAL, K_COUNT
 };
 // vote_round1_rest: round-1 votes of the rows the relabel pass could not
 // decide (repeated neighbours), no algorithmic bytes counted;
@@ -69,7 +69,7 @@ enum KernelId {
 const char *kKernelNames[K_COUNT] = {"vote_thread",  "vote_group", "vote_wave",    "vote_wide",
                                      "vote_hub",     "vote_round1_rest", "hub_merge", "hub_fallback",
                                      "hub_reduce",   "hub_final",  "modularity", "predict", "push",
-                                     "vote_listed"};
+                                     "vote_listed", "copra", "copra_global"};
 
 struct Pending {
     int kid;
@@ -106,6 +106,7 @@ struct lpa_ctx {
     DevBuf f_top1, f_top2, f_kw, f_last, f_front, f_stale, f_lists, f_small, f_model;  // frontier runs
     DevBuf t_w, t_m, t_v, t_part, t_grad, t_loss, t_z;                               // training
     DevBuf tune_labels, tune_hist;                                                    // autotuner
+    DevBuf cp_lab[2], cp_coef[2], cp_cnt[2], cp_best[2], cp_rows, cp_ovf, cp_off, cp_key, cp_tal;  // COPRA
     std::map<std::vector<int>, lpa_options> tune_cache;
     bool slab_dirty = false;      // slab may hold entries (set after a timed-out batch)
     hipStream_t cap_stream = nullptr;
@@ -150,6 +151,7 @@ lpa_status err_status(uint32_t bits) {
     if (bits & (ERR_COL | ERR_ROWPTR | ERR_LABEL | ERR_GRAPH)) return LPA_EINVAL;
     if (bits & ERR_TIMEOUT) return LPA_ETIMEDOUT;
     if (bits & ERR_WOVF) return LPA_EOVERFLOW;
+    if (bits & ERR_TABLE) return LPA_EDEVICE;
     return LPA_OK;
 }
 
@@ -1341,6 +1343,179 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
     return LPA_OK;
 }
 
+// ------------------------------------------------------------------ COPRA --
+//
+// Rounds of COPRA (lpa_copra.hip) on the caller's CSR.  Per half-round: the
+// wavefront and block kernels, one read-back of the changed count and of the
+// number of rows whose distinct labels outgrew the block's LDS table; those
+// rows (if any) are then voted with tables in device memory sized from their
+// degrees, and their changes are read back too.
+lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_out, uint32_t *state_lab,
+                      uint32_t *state_coef, uint32_t *state_cnt, double tol, uint32_t max_iter, lpa_stats *stats) {
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!c) return LPA_EINVAL;
+    LPA_TRY(check_csr_args(g));
+    if (!best_out && g->n) return LPA_EINVAL;
+    if (!(tol >= 0.0 && tol <= 1.0)) return LPA_EINVAL;
+    if (V < 1 || V > 64) return LPA_EINVAL;
+    if (c->opt.frontier) return LPA_EUNSUPPORTED;
+    HIP_TRY(hipSetDevice(c->device));
+    const hipStream_t s = c->stream;
+    const uint32_t n = g->n;
+    clear_stats(stats);
+    if (n == 0) return LPA_OK;
+    const Graph G{g->row_ptr, g->col, g->w, n, g->m};
+    // counters: kCountWords changed words, then the overflow count, the
+    // big-row count and the error word
+    HIP_TRY(c->counters.ensure((kCountWords + 8) * sizeof(u64)));
+    u64 *cw = c->counters.as<u64>();
+    uint32_t *ovf_count = reinterpret_cast<uint32_t *>(cw + kCountWords);
+    uint32_t *big_count = ovf_count + 2;
+    uint32_t *err = ovf_count + 4;
+    LPA_TRY(ensure_pinned(c, kCountWords + 32));
+    HIP_TRY(launch_fill_u64(cw, 0, kCountWords + 8, s));
+    HIP_TRY(launch_csr_check(G, err, s));
+    HIP_TRY(hipMemcpyAsync(c->pinned, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (const uint32_t bits = reinterpret_cast<uint32_t *>(c->pinned)[0]) return err_status(bits);
+
+    const size_t slots = (size_t)n * V;
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(c->cp_lab[b].ensure(slots * sizeof(uint32_t)));
+        HIP_TRY(c->cp_coef[b].ensure(slots * sizeof(uint32_t)));
+        HIP_TRY(c->cp_cnt[b].ensure((size_t)n * sizeof(uint32_t)));
+        HIP_TRY(c->cp_best[b].ensure((size_t)n * sizeof(uint32_t)));
+    }
+    HIP_TRY(c->cp_rows.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(launch_copra_init(n, V, c->cp_lab[0].as<uint32_t>(), c->cp_coef[0].as<uint32_t>(),
+                              c->cp_cnt[0].as<uint32_t>(), c->cp_best[0].as<uint32_t>(), s));
+    HIP_TRY(launch_copra_list(G, V, c->cp_rows.as<uint32_t>(), big_count, s));
+    HIP_TRY(hipMemcpyAsync(c->pinned, big_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t n_big = reinterpret_cast<uint32_t *>(c->pinned)[0];
+    HIP_TRY(c->cp_ovf.ensure((size_t)(n_big ? n_big : 1) * sizeof(uint32_t)));
+
+    const uint64_t thr = (uint64_t)std::floor(tol * (double)n);
+    const bool semi = c->opt.order == LPA_ORDER_SEMISYNC;
+    const uint64_t wb = g->w ? 20 : 16;  // per arc: col (+ weight), count and first slot of the neighbour
+    int cur = 0;
+    uint32_t it = 0;
+    int32_t converged = 0;
+    uint64_t changed = 0;
+    double ms_rounds = 0;
+    if (!c->round_a) HIP_TRY(hipEventCreate(&c->round_a));
+    if (!c->round_b) HIP_TRY(hipEventCreate(&c->round_b));
+    for (uint32_t t = 1; t <= max_iter; ++t) {
+        changed = 0;
+        float ms_t = 0.f;
+        for (uint32_t h = 0; h <= (semi ? 1u : 0u); ++h) {
+            const int nx = cur ^ 1;
+            CopraArgs a;
+            a.g = G;
+            a.V = V;
+            a.lab_in = c->cp_lab[cur].as<uint32_t>();
+            a.coef_in = c->cp_coef[cur].as<uint32_t>();
+            a.cnt_in = c->cp_cnt[cur].as<uint32_t>();
+            a.best_in = c->cp_best[cur].as<uint32_t>();
+            a.lab_out = c->cp_lab[nx].as<uint32_t>();
+            a.coef_out = c->cp_coef[nx].as<uint32_t>();
+            a.cnt_out = c->cp_cnt[nx].as<uint32_t>();
+            a.best_out = c->cp_best[nx].as<uint32_t>();
+            a.t = t;
+            a.half = semi ? h + 1 : 0;
+            a.tie = c->opt.tie;
+            a.seed = c->opt.seed;
+            a.changed = cw;
+            a.ovf_rows = c->cp_ovf.as<uint32_t>();
+            a.ovf_count = ovf_count;
+            a.err = err;
+            HIP_TRY(launch_fill_u64(cw, 0, kCountWords + 1, s));  // changed words and the overflow count
+            HIP_TRY(hipEventRecord(c->round_a, s));
+            // a half-round votes about half of the arcs; the whole round's
+            // bytes are charged to its first launch
+            const uint64_t bytes = h ? 0 : wb * g->m + 28ull * n;
+            LPA_TRY(timed(c, K_COPRA, bytes, h ? 0 : g->m,
+                          [&] { return launch_copra_round(a, c->cp_rows.as<uint32_t>(), n_big, s); }));
+            HIP_TRY(hipEventRecord(c->round_b, s));
+            // changed words, overflow count, error word
+            HIP_TRY(hipMemcpyAsync(c->pinned, cw, (kCountWords + 3) * sizeof(u64), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
+            ms_t += ms;
+            const uint32_t n_ovf = reinterpret_cast<uint32_t *>(c->pinned + kCountWords)[0];
+            if (n_ovf) {
+                // tables in device memory for the rows the LDS could not hold
+                HIP_TRY(c->cp_off.ensure(((size_t)n_ovf + 1) * sizeof(u64)));
+                HIP_TRY(launch_copra_sizes(G, V, a.ovf_rows, n_ovf, c->cp_off.as<u64>(), s));
+                std::vector<u64> off((size_t)n_ovf + 1);
+                HIP_TRY(hipMemcpyAsync(off.data(), c->cp_off.p, (size_t)n_ovf * sizeof(u64), hipMemcpyDeviceToHost,
+                                       s));
+                HIP_TRY(hipStreamSynchronize(s));
+                u64 total = 0;
+                for (uint32_t i = 0; i < n_ovf; ++i) {
+                    const u64 sz = off[i];
+                    off[i] = total;
+                    total += sz;
+                }
+                off[n_ovf] = total;
+                HIP_TRY(hipMemcpyAsync(c->cp_off.p, off.data(), off.size() * sizeof(u64), hipMemcpyHostToDevice, s));
+                HIP_TRY(c->cp_key.ensure((size_t)total * sizeof(uint32_t)));
+                HIP_TRY(c->cp_tal.ensure((size_t)total * sizeof(u64)));
+                HIP_TRY(launch_fill_u32(c->cp_key.as<uint32_t>(), 0xFFFFFFFFu, total, s));
+                HIP_TRY(launch_fill_u64(c->cp_tal.as<u64>(), 0, total, s));
+                HIP_TRY(hipEventRecord(c->round_a, s));
+                LPA_TRY(timed(c, K_COPRA_GLOBAL, 0, 0, [&] {
+                    return launch_copra_global(a, a.ovf_rows, n_ovf, c->cp_off.as<u64>(), c->cp_key.as<uint32_t>(),
+                                               c->cp_tal.as<u64>(), s);
+                }));
+                HIP_TRY(hipEventRecord(c->round_b, s));
+                HIP_TRY(hipMemcpyAsync(c->pinned, cw, (kCountWords + 3) * sizeof(u64), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
+                ms_t += ms;
+            }
+            for (int k = 0; k < kCountSlots; ++k) changed += c->pinned[(size_t)k * kCountStride];
+            cur = nx;
+            if (const uint32_t bits = reinterpret_cast<uint32_t *>(c->pinned + kCountWords)[4]) return err_status(bits);
+        }
+        ms_rounds += ms_t;
+        it = t;
+        if (stats) {
+            if (stats->changed_per_iter && t <= stats->cap) stats->changed_per_iter[t - 1] = changed;
+            if (stats->ms_per_iter && t <= stats->cap) stats->ms_per_iter[t - 1] = ms_t;
+        }
+        if (changed <= thr) {
+            converged = 1;
+            break;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(best_out, c->cp_best[cur].p, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (state_lab)
+        HIP_TRY(hipMemcpyAsync(state_lab, c->cp_lab[cur].p, slots * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (state_coef)
+        HIP_TRY(hipMemcpyAsync(state_coef, c->cp_coef[cur].p, slots * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (state_cnt)
+        HIP_TRY(hipMemcpyAsync(state_cnt, c->cp_cnt[cur].p, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->opt.profile) collect_profile(c);
+    double q = 0;
+    uint64_t terms[4] = {0, 0, 0, 0};
+    if (c->opt.modularity) LPA_TRY(lpa_modularity(c, g, best_out, &q, terms));
+    if (stats) {
+        stats->iterations = it;
+        stats->converged = converged;
+        stats->changed_last = changed;
+        stats->arcs_processed = g->m * it;
+        stats->ms_rounds = ms_rounds;
+        stats->modularity = q;
+        for (int i = 0; i < 4; ++i) stats->mod_terms[i] = terms[i];
+        stats->ms_total =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return LPA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1702,6 +1877,12 @@ lpa_status lpa_modularity(lpa_ctx *c, const lpa_csr *g, const uint32_t *labels, 
     return modularity_internal(c, g, P, c->La.as<uint32_t>(), err_dev, q_out, terms);
 }
 
+lpa_status lpa_run_copra(lpa_ctx *c, const lpa_csr *g, uint32_t max_labels, uint32_t *labels_out,
+                         uint32_t *state_labels, uint32_t *state_coefs, uint32_t *state_count, double tol,
+                         uint32_t max_iter, lpa_stats *stats) {
+    return copra_impl(c, g, max_labels, labels_out, state_labels, state_coefs, state_count, tol, max_iter, stats);
+}
+
 lpa_status lpa_profile_get(lpa_ctx *c, lpa_kernel_prof *out, uint32_t cap, uint32_t *count) {
     if (!c || !count || (cap && !out)) return LPA_EINVAL;
     *count = K_COUNT;
@@ -1733,7 +1914,9 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->hub_src,    &c->gid,  &c->gvd,      &c->bstate, &c->bseg,
                       &c->f_top1, &c->f_top2, &c->f_kw, &c->f_last, &c->f_front, &c->f_stale, &c->f_lists,
                       &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
-                      &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist};
+                      &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist,
+                      &c->cp_lab[0], &c->cp_lab[1], &c->cp_coef[0], &c->cp_coef[1], &c->cp_cnt[0], &c->cp_cnt[1],
+                      &c->cp_best[0], &c->cp_best[1], &c->cp_rows, &c->cp_ovf, &c->cp_off, &c->cp_key, &c->cp_tal};
     if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) b->release();

@@ -119,7 +119,7 @@ class _KProf(ctypes.Structure):
 
 EXPORTS = ("lpa_default_options", "lpa_init", "lpa_run", "lpa_run_resume", "lpa_run_batch", "lpa_run_learned",
            "lpa_trace", "lpa_train", "lpa_mlp_forward", "lpa_mlp_grad", "lpa_autotune", "lpa_modularity",
-           "lpa_modularity_noalloc",
+           "lpa_modularity_noalloc", "lpa_run_copra",
            "lpa_profile_get", "lpa_profile_reset", "lpa_destroy", "lpa_strerror")
 
 
@@ -152,6 +152,7 @@ def _load():
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.lpa_modularity_noalloc.argtypes = [vp, ctypes.POINTER(_Csr), vp, ctypes.POINTER(dbl),
                                            ctypes.POINTER(ctypes.c_uint64)]
+    lib.lpa_run_copra.argtypes = [vp, ctypes.POINTER(_Csr), u32, vp, vp, vp, vp, dbl, u32, ctypes.POINTER(_Stats)]
     lib.lpa_profile_get.argtypes = [vp, ctypes.POINTER(_KProf), u32, ctypes.POINTER(u32)]
     lib.lpa_profile_reset.argtypes = [vp]
     lib.lpa_destroy.argtypes = [vp]
@@ -162,7 +163,7 @@ def _load():
               lib.lpa_autotune):
         f.restype = ctypes.c_int
     for f in (lib.lpa_init, lib.lpa_run, lib.lpa_run_resume, lib.lpa_run_batch, lib.lpa_modularity, lib.lpa_modularity_noalloc,
-              lib.lpa_profile_get,
+              lib.lpa_run_copra, lib.lpa_profile_get,
               lib.lpa_profile_reset):
         f.restype = ctypes.c_int
     _lib = lib
@@ -343,6 +344,31 @@ class Context:
         if rc:
             raise LpaError(rc, "lpa_run")
         return labels_out, self._pack(st, ch, ms)
+
+    def run_copra(self, g: DeviceGraph, max_labels: int = 4, tol: float = 0.01, max_iter: int = 20,
+                  state: bool = False, labels_out=None):
+        """COPRA (lpa_run_copra); returns (best labels int32 tensor viewed as
+        u32, Stats) or, with state, (best, Stats, (labels [n, V], coefs
+        [n, V], count [n]) int32 tensors)."""
+        import torch
+        dev = g.row_ptr.device
+        if labels_out is None:
+            labels_out = torch.empty(g.n, dtype=torch.int32, device=dev)
+        V = int(max_labels)
+        sl = sc = sn = None
+        if state:
+            sl = torch.zeros((g.n, V), dtype=torch.int32, device=dev)
+            sc = torch.zeros((g.n, V), dtype=torch.int32, device=dev)
+            sn = torch.zeros(g.n, dtype=torch.int32, device=dev)
+        st, ch, ms = self._stats(max_iter)
+        c = g._c()
+        p = (lambda t: t.data_ptr() if (t is not None and g.n) else None)
+        rc = _load().lpa_run_copra(self._h, ctypes.byref(c), V, p(labels_out), p(sl), p(sc), p(sn), float(tol),
+                                   int(max_iter), ctypes.byref(st))
+        if rc:
+            raise LpaError(rc, "lpa_run_copra")
+        out = (labels_out, self._pack(st, ch, ms))
+        return out + ((sl, sc, sn),) if state else out
 
     def run_resume(self, g: DeviceGraph, labels, tol: float = 0.05, max_iter: int = 20):
         """RAK from the labels in `labels` (updated in place)."""
