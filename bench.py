@@ -45,6 +45,9 @@ WORKLOADS = {
     "learned24": ("R-MAT scale 24, edge factor 16, same (a,b,c), unit weights, seed 24; the learned-frontier run "
                   "(model trained on R-MAT 18-20 and two 1024x1024 lattices) timed against plain RAK",
                   lambda gg: gg.rmat(24, 16, 0.57, 0.19, 0.19, seed=24)),
+    "copra22": ("COPRA (Section 3.3), max_labels 4, tol 0.01 (the paper's COPRA tolerance), synchronous rounds, "
+                "lowest-label ties, on R-MAT scale 22, edge factor 16, (a,b,c)=(0.57,0.19,0.19), unit weights, seed 22",
+                lambda gg: gg.rmat(22, 16, 0.57, 0.19, 0.19, seed=22)),
     "batch50m": ("4096 planted-partition graphs, n log-uniform in [200, 6150], 8-64 blocks, mean intra degree 12, "
                  "inter degree 2, seed 4096 (about 5e7 edges)",
                  lambda gg: gg.sbm_batch(4096, 200, 6150, seed=4096)),
@@ -229,11 +232,29 @@ def gather_ceiling(args, g, P):
                       "workload": args.workload}), flush=True)
 
 
+# The sources each kernel is compiled from: a counter profile stays valid
+# while they are unchanged.
+_COMMON_SRC = ["lpa_device.h", "lpa_internal.h"]
+KERNEL_SOURCES = {
+    "batch_k": ["lpa_batch.hip", "lpa_vote_dev.h"] + _COMMON_SRC,
+    "copra": ["lpa_copra.hip"] + _COMMON_SRC,
+}
+VOTE_SOURCES = ["lpa_vote.hip", "lpa_vote_dev.h"] + _COMMON_SRC
+
+
+def kernel_sources_hash(kernel: str) -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_2301_09125_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(KERNEL_SOURCES.get(kernel, VOTE_SOURCES)):
+        h.update(open(os.path.join(src, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profile(workload: str, kernel: str):
     """HBM bytes per launch of `kernel` measured with hardware counters for
     this workload, from the committed profile summary, or None when there is
-    none or when the kernel sources changed since it was taken."""
-    import hashlib
+    none or when the kernel's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -242,12 +263,7 @@ def traffic_from_profile(workload: str, kernel: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2301_09125_amd", "csrc")
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(src, f), "rb").read())
-    if kv.get("kernel_sources_sha256") != h.hexdigest()[:16]:
+    if kv.get("kernel_sources_sha256") != kernel_sources_hash(kernel):
         log(f"[bench] {path}: kernel sources changed since the counters were taken; traffic = null")
         return None
     try:
@@ -357,6 +373,117 @@ def run_batch_bench(args, b, desc, P):
                                                                              "wide_max")},
                    "hbm_gbs_effective": round(bytes_step * args.steps / elapsed / 1e9, 1),
                    "device_ms": round(dev_ms, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def sweep(args, P):
+    """The paper's two RAK experiments on the synthetic classes (Section 3.2):
+    strict (lowest-label) against non-strict (hashed, reproducible) ties,
+    in synchronous and semi-synchronous rounds, over tolerances 0.1 down to
+    0.0001.  One JSON object per run on stdout: rounds, whether the test
+    passed, device time of the rounds, modularity and, where the graph has
+    a planted partition, NMI against it."""
+    import torch
+    import graphgen as gg
+    graphs = [("sbm10k", gg.sbm(10000, 100, 0.1, 0.001, seed=1), np.arange(10000) // 100),
+              ("road4096", gg.road(4096, 4096, 0.3, 0.01, 1, 8, seed=4096), None),
+              ("rmat22", gg.rmat(22, 16, 0.57, 0.19, 0.19, seed=22), None)]
+    for name, g, planted in graphs:
+        dg = P.DeviceGraph.from_csr(g, "cuda")
+        torch.cuda.synchronize()
+        for order in (0, 1):
+            for tie in (0, 1):
+                ctx = P.Context(0, order=order, tie=tie, seed=1, modularity=1)
+                for tol in (0.1, 0.05, 0.01, 0.001, 0.0001):
+                    lab, st = ctx.run(dg, tol=tol, max_iter=args.max_iter)
+                    rec = {"graph": name, "order": ["sync", "semisync"][order], "tie": ["lowest", "hash"][tie],
+                           "tol": tol, "rounds": st.iterations, "converged": st.converged,
+                           "ms_rounds": round(st.ms_rounds, 3), "ms_total": round(st.ms_total, 3),
+                           "modularity": round(st.modularity, 5)}
+                    if planted is not None:
+                        rec["nmi_planted"] = round(nmi(P.labels_to_numpy(lab), planted), 5)
+                    print(json.dumps(rec), flush=True)
+                ctx.close()
+        del dg
+
+
+COPRA_MAX_LABELS = 4
+COPRA_TOL = 0.01
+
+
+def run_copra_bench(args, g, desc, P):
+    """COPRA steps (lpa_run_copra from every vertex alone, rounds to
+    tolerance 0.01, modularity of the best labels)."""
+    import torch
+    import oracle
+    dg = P.DeviceGraph.from_csr(g, "cuda")
+    torch.cuda.synchronize()
+    ctx = P.Context(0, profile=0 if args.no_profile else 1, modularity=1)
+    labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    def step():
+        _, st = ctx.run_copra(dg, max_labels=COPRA_MAX_LABELS, tol=COPRA_TOL, max_iter=args.max_iter,
+                              labels_out=labels)
+        return st
+
+    for i in range(args.warmup):
+        st = step()
+        log(f"[bench] warmup {i}: {st.iterations} rounds, changed {st.changed}, Q={st.modularity:.6f}, "
+            f"{st.ms_total:.2f} ms")
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st0 = stats[0]
+    if any(st.changed != st0.changed or st.modularity != st0.modularity for st in stats):
+        raise SystemExit("non-deterministic result across steps")
+    arcs = sum(st.arcs_processed for st in stats)
+    value = arcs / elapsed / 1e9
+    ms_per_step = 1e3 * elapsed / args.steps
+    log(f"[bench] {args.steps} steps in {elapsed:.3f}s: {ms_per_step:.3f} ms/step, {value:.2f} GE/s, "
+        f"rounds {st0.iterations}, Q {st0.modularity:.6f}")
+    roofline = None
+    prof = [] if args.no_profile else ctx.profile()
+    cp = [p for p in prof if p["name"] == "copra" and p["launches"]]
+    if cp:
+        p = cp[0]
+        # per round: col (+ weight), the neighbour's count and first slot per
+        # arc, 28 B per vertex -- a lower bound (further kept slots add 8 B)
+        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "copra", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic_from_profile(args.workload, "copra"),
+                    "avg_launch_ms": round(p["ms"] / p["launches"], 4),
+                    "bytes_per_launch": p["bytes"] // p["launches"]}
+        for q in prof:
+            if q["launches"]:
+                log(f"[bench]   {q['name']:12s} launches {q['launches']:5d}  avg {q['ms'] / q['launches']:.4f} ms")
+    cpu = None
+    if args.cpu_seconds > 0:
+        # the sequential oracle's first round (every vertex alone -> one
+        # round of collecting), on the same graph
+        t0 = time.perf_counter()
+        r = oracle.copra(g, max_labels=COPRA_MAX_LABELS, tol=COPRA_TOL, max_iter=1)
+        dt = time.perf_counter() - t0
+        ncpu, model = host_cpu()
+        cpu = {"value": g.m * r.iterations / dt / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first round of the sequential oracle orc_copra on the same graph "
+                         f"({g.m} arcs in {dt:.1f} s)", "host": {"logical_cpus": ncpu, "model": model}}
+        log(f"[bench] cpu baseline {cpu['value']:.4f} GE/s on one core")
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GE/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n": g.n, "m_arcs": g.m, "max_labels": COPRA_MAX_LABELS,
+                   "tol": COPRA_TOL, "max_iter": args.max_iter, "order": "synchronous", "tie_break": "lowest label",
+                   "rounds": st0.iterations, "changed": st0.changed, "modularity": st0.modularity,
+                   "round_ms_device_per_round": [round(x, 4) for x in st0.ms_per_iter]},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -480,6 +607,9 @@ def main():
                     help="measure the random-gather rate the vote kernels are bound by, then exit")
     ap.add_argument("--no-autotune", action="store_true", help="batch workloads: keep the default bins")
     ap.add_argument("--autotune", action="store_true", help="single-graph workloads: autotune the bins first")
+    ap.add_argument("--sweep", action="store_true",
+                    help="strict vs non-strict ties, synchronous vs semi-synchronous rounds, tolerances 0.1..0.0001 "
+                         "on the SBM, road and R-MAT 22 graphs (one JSON object per run), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -494,6 +624,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        return sweep(args, P)
     desc, gen = WORKLOADS[args.workload]
     if args.copy_calibration:
         copy_calibration()
@@ -507,6 +639,8 @@ def main():
         return gather_ceiling(args, g, P)
     if args.workload.startswith("learned"):
         return run_learned_bench(args, g, desc, P)
+    if args.workload.startswith("copra"):
+        return run_copra_bench(args, g, desc, P)
     dg = P.DeviceGraph.from_csr(g, "cuda")
     torch.cuda.synchronize()
     ctx = P.Context(0, profile=0 if args.no_profile else 1, modularity=1)

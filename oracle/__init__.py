@@ -229,11 +229,12 @@ class CopraResult:
     iterations: int
     converged: bool
     changed: list
-    state: list             # per vertex: sorted [(label, coefficient * 2^16), ...]
+    state: list             # per vertex: sorted [(label, coefficient * 2^16), ...] (None when raw)
+    state_arrays: tuple = None  # raw: (labels [n, V], coefficients [n, V], counts [n]), uint32
 
 
 def copra(g, max_labels: int = 4, tol: float = 0.01, max_iter: int = 20, order: str = "sync", tie: str = "lowest",
-          seed: int = 0) -> CopraResult:
+          seed: int = 0, raw: bool = False) -> CopraResult:
     """COPRA (Section 3.3) with fixed-point belonging coefficients, in
     synchronous or semi-synchronous rounds; the best label's ties go to the
     lowest label or, with tie="hash", to the highest priority as in rak_ext.
@@ -256,8 +257,12 @@ def copra(g, max_labels: int = 4, tol: float = 0.01, max_iter: int = 20, order: 
                            ctypes.byref(cv))
     if rc:
         raise OracleError(rc)
+    changed = [int(x) for x in ch[: it.value]]
+    if raw:
+        return CopraResult(best, int(it.value), bool(cv.value), changed, None,
+                           (sl[: g.n * V].reshape(g.n, V), sc[: g.n * V].reshape(g.n, V), sn[: g.n]))
     state = [sorted(zip(sl[v * V:v * V + sn[v]].tolist(), sc[v * V:v * V + sn[v]].tolist())) for v in range(g.n)]
-    return CopraResult(best, int(it.value), bool(cv.value), [int(x) for x in ch[: it.value]], state)
+    return CopraResult(best, int(it.value), bool(cv.value), changed, state)
 
 
 @dataclass

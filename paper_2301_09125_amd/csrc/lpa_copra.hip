@@ -20,16 +20,22 @@
 // State: lab / coef u32[n * V] (slot i of vertex v at v * V + i, the first
 // cnt[v] slots valid), cnt u32[n], best u32[n], double-buffered.  The rounds
 // read the caller's CSR directly (original ids, no relabelled copy):
+//   copra_group_k  rows with deg * V <= 32: 16 lanes per row, a 64-slot
+//                  LDS table;
 //   copra_wave_k   rows with deg * V <= 512: one wavefront per row, an LDS
 //                  table of next_pow2(2 * deg * V) slots (<= 1024);
 //   copra_block_k  the other rows: one block per row, a 4096-slot LDS
 //                  table; a row whose distinct labels would fill more than
 //                  3/4 of it is listed for
-//   copra_global_k one block per listed row, a table in device memory of
-//                  next_pow2(2 * min(deg * V, n)) slots (at least twice the
-//                  row's distinct labels).
-// Semi-synchronous rounds: two half-rounds, a vertex votes in the half its
-// SplitMix64 draw for the round names and copies its state in the other.
+//   copra_gpiece_k / copra_gfinal_k  the listed rows, with a table in
+//                  device memory of next_pow2(2 * min(deg * V, n)) slots (at
+//                  least twice the row's distinct labels) each: pieces of
+//                  the row pre-sum their entries in LDS and add them to it,
+//                  then one block per row decides.
+// Rows without arcs are in no list: they stay alone, and both buffers hold
+// that state from the start.  Semi-synchronous rounds: two half-rounds, a
+// vertex votes in the half its SplitMix64 draw for the round names and
+// copies its state in the other.
 
 #include "lpa_device.h"
 
@@ -111,8 +117,111 @@ __device__ __forceinline__ void copra_store(const CopraArgs &a, uint32_t v, uint
     }
 }
 
-// One wavefront per row, rows with deg * V <= 512.
-__global__ __launch_bounds__(256) void copra_wave_k(CopraArgs a) {
+// 16 lanes per row, four rows per wavefront, rows with deg * V <= 32 (listed
+// in `rows`): a 64-slot LDS table per row, reductions over each 16-lane row
+// of the wavefront.
+constexpr uint32_t kCopraGroupSlots = 64;
+__global__ __launch_bounds__(256) void copra_group_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count) {
+    __shared__ uint32_t skey[16][kCopraGroupSlots];
+    __shared__ u64 stal[16][kCopraGroupSlots];
+    __shared__ uint32_t sklab[16][32], skcoef[16][32], skn[16];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t gl = lane & 15;
+    const uint32_t grp = threadIdx.x >> 4;  // 0..15 in the block
+    uint32_t *key = skey[grp];
+    u64 *tal = stal[grp];
+    const uint32_t V = a.V;
+    u64 chg = 0;
+    // every lane of a wavefront runs the same number of steps (the bound is
+    // per wavefront), so the wavefront-wide LDS syncs line up
+    for (uint32_t base = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4; base < count; base += gridDim.x * 16) {
+        const uint32_t idx = base + (lane >> 4);
+        const bool act = idx < count;
+        const uint32_t v = act ? rows[idx] : 0u;
+        const bool on = act && copra_votes(a, v);
+        if (act && !on) copra_copy(a, v, gl, 16);
+        const uint64_t b = on ? a.g.rp[v] : 0, e = on ? a.g.rp[v + 1] : 0;
+        const Tie tie = copra_tie(a, v);
+        for (uint32_t s = gl; s < kCopraGroupSlots; s += 16) {
+            key[s] = kEmptyKey;
+            tal[s] = 0;
+        }
+        if (gl == 0) skn[grp] = 0;
+        wave_sync();
+        u64 tw = 0;
+        for (uint32_t j = 0; j < 2; ++j) {  // deg <= 32
+            const uint64_t k = b + gl + 16 * j;
+            const bool in = k < e;
+            const uint32_t u = in ? a.g.col[k] : 0u;
+            const uint32_t we = in ? (a.g.w ? a.g.w[k] : 1u) : 0u;
+            const uint32_t c = in ? a.cnt_in[u] : 0u;
+            tw += we;
+            for (uint32_t i = 0; i < c; ++i)
+                if (copra_insert_bounded(key, tal, kCopraGroupSlots - 1, a.lab_in[(u64)u * V + i],
+                                         (u64)we * a.coef_in[(u64)u * V + i]) < 0)
+                    atomicOr(a.err, ERR_TABLE);  // cannot happen: at most 32 entries
+        }
+        wave_sync();
+        const u64 total = row_sum64(tw) * kOne;
+        u64 m1 = 0;
+        for (uint32_t s = gl; s < kCopraGroupSlots; s += 16)
+            if (key[s] != kEmptyKey) m1 = umax64(m1, tal[s] + 1);
+        m1 = row_max64(m1);
+        u64 bc = 0, ksum = 0, kcnt = 0;
+        for (uint32_t s = gl; s < kCopraGroupSlots; s += 16) {
+            const uint32_t l = key[s];
+            if (l == kEmptyKey) continue;
+            const u64 t = tal[s];
+            if (t + 1 == m1) bc = umax64(bc, tie_code(tie, l));
+            if (t > 0 && t * V >= total) {
+                ksum += t;
+                ++kcnt;
+            }
+        }
+        bc = row_max64(bc);
+        ksum = row_sum64(ksum);
+        kcnt = row_sum64(kcnt);
+        const uint32_t best = tie_label(tie, (uint32_t)bc);
+        for (uint32_t s = gl; s < kCopraGroupSlots; s += 16) {
+            const uint32_t l = key[s];
+            if (l == kEmptyKey) continue;
+            const u64 t = tal[s];
+            if (on && t > 0 && t * V >= total) {
+                const uint32_t j = atomicAdd(&skn[grp], 1u);
+                sklab[grp][j] = l;
+                skcoef[grp][j] = (uint32_t)(t * kOne / ksum);
+            }
+        }
+        wave_sync();
+        // kept labels (at most 32) in increasing order, the remainder to best
+        const uint32_t kn = (uint32_t)kcnt;
+        uint32_t given = 0;
+        for (uint32_t j = gl; j < kn; j += 16) given += skcoef[grp][j];
+        given = row_sum32(given);
+        if (on && kn == 0 && gl == 0) copra_alone(a, v, best);
+        if (on && kn > 0) {
+            for (uint32_t j = gl; j < kn; j += 16) {
+                const uint32_t l = sklab[grp][j];
+                uint32_t c = skcoef[grp][j];
+                uint32_t rank = 0;
+                for (uint32_t q = 0; q < kn; ++q) rank += sklab[grp][q] < l;
+                if (l == best) c += kOne - given;
+                a.lab_out[(u64)v * V + rank] = l;
+                a.coef_out[(u64)v * V + rank] = c;
+            }
+            if (gl == 0) {
+                a.cnt_out[v] = kn;
+                a.best_out[v] = best;
+            }
+        }
+        if (on && gl == 0) chg += a.best_in[v] != best;
+        wave_sync();  // the tables are cleared for the next rows
+    }
+    block_count(chg, a.changed);
+}
+
+// One wavefront per row, rows with 32 < deg * V <= 512 (listed in `rows`).
+__global__ __launch_bounds__(256) void copra_wave_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count) {
     __shared__ uint32_t skey[4][kCopraWaveSlots];
     __shared__ u64 stal[4][kCopraWaveSlots];
     __shared__ uint32_t sklab[4][64], skcoef[4][64], skn[4];
@@ -122,22 +231,15 @@ __global__ __launch_bounds__(256) void copra_wave_k(CopraArgs a) {
     u64 *tal = stal[wave];
     const uint32_t V = a.V;
     u64 chg = 0;
-    for (uint32_t v = blockIdx.x * 4 + wave; v < a.g.n; v += gridDim.x * 4) {
+    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
+        const uint32_t v = rows[it];
         const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
         const uint64_t deg = e - b;
-        if (deg * V > 512) continue;  // copra_block_k
         if (!copra_votes(a, v)) {
             copra_copy(a, v, lane, 64);
             continue;
         }
         const uint32_t old_best = a.best_in[v];
-        if (deg == 0) {
-            if (lane == 0) {
-                copra_alone(a, v, v);
-                chg += old_best != v;
-            }
-            continue;
-        }
         const Tie tie = copra_tie(a, v);
         const uint32_t S = next_pow2((uint32_t)(2 * deg * V));
         for (uint32_t s = lane; s < S; s += 64) {
@@ -258,6 +360,50 @@ __device__ __forceinline__ uint32_t copra_finish_block(const CopraArgs &a, uint3
     return best;
 }
 
+// The first vote of row v while every vertex is still alone with belonging
+// 1 and v lists each neighbour once: tally(u) = w(v,u) * 2^16.  A
+// 256-thread block; kn zeroed by the caller.
+__device__ __forceinline__ uint32_t copra_first_block(const CopraArgs &a, uint32_t v, Tie tie, BlockRed *red,
+                                                      uint32_t *klab, uint32_t *kcoef, uint32_t *kn) {
+    const uint32_t V = a.V;
+    const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
+    u64 bk = 0, tw = 0, z = 0;
+    uint32_t zo = 0;
+    for (uint64_t k = b + threadIdx.x; k < e; k += 256) {
+        const uint32_t we = a.g.w ? a.g.w[k] : 1u;
+        tw += we;
+        bk = umax64(bk, ((u64)we << 32) | tie_code(tie, a.g.col[k]));
+    }
+    block_reduce(red[0], bk, tw, z, zo);
+    const uint32_t best = tie_label(tie, (uint32_t)bk);
+    u64 ksum = 0, kcnt = 0;
+    for (uint64_t k = b + threadIdx.x; k < e; k += 256) {
+        const uint32_t we = a.g.w ? a.g.w[k] : 1u;
+        if (we > 0 && (u64)we * V >= tw) {
+            ksum += (u64)we * kOne;
+            ++kcnt;
+        }
+    }
+    u64 z2 = 0;
+    zo = 0;
+    block_reduce(red[1], z2, ksum, kcnt, zo);
+    if (kcnt == 0) {
+        if (threadIdx.x == 0) copra_alone(a, v, best);
+        return best;
+    }
+    for (uint64_t k = b + threadIdx.x; k < e; k += 256) {
+        const uint32_t we = a.g.w ? a.g.w[k] : 1u;
+        if (we > 0 && (u64)we * V >= tw) {
+            const uint32_t j = atomicAdd(kn, 1u);
+            klab[j] = a.g.col[k];
+            kcoef[j] = (uint32_t)(((u64)we << 32) / ksum);  // (w * 2^16) * 2^16 / kept_sum
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) copra_store(a, v, threadIdx.x, klab, kcoef, (uint32_t)kcnt, best);
+    return best;
+}
+
 // One block per row of deg * V > 512 (rows listed in `rows`), a 4096-slot
 // LDS table; rows with too many distinct labels are listed for the global
 // table.
@@ -275,6 +421,15 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
             continue;
         }
         const Tie tie = copra_tie(a, v);
+        if (a.first && a.distinct[v]) {
+            // every neighbour still alone and listed once: label u's tally is
+            // w(v,u) * 2^16, so the row is decided without a table
+            if (threadIdx.x == 0) kn = 0;
+            const uint32_t best = copra_first_block(a, v, tie, red, klab, kcoef, &kn);
+            if (threadIdx.x == 0) chg += a.best_in[v] != best;
+            __syncthreads();
+            continue;
+        }
         for (uint32_t s = threadIdx.x; s < kCopraBlockSlots; s += 256) {
             key[s] = kEmptyKey;
             tal[s] = 0;
@@ -321,43 +476,90 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
     block_count(chg, a.changed);
 }
 
-// One block per listed row, its table at slab + off[i] (off[count] = end),
-// filled with empty keys and zero tallies beforehand.
-__global__ __launch_bounds__(256) void copra_global_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count,
-                                                      const u64 *__restrict__ off, uint32_t *slab_key,
-                                                      u64 *slab_tal) {
-    __shared__ BlockRed red[3];
-    __shared__ uint32_t klab[64], kcoef[64], kn;
+// Rows left to device-memory tables, in pieces: each block takes a piece
+// (row index i of the list, arcs [b0, b1), at most 2048 / V arcs, so at
+// most 2048 entries), sums them in a 4096-slot LDS table, then adds each of
+// its distinct labels once to row i's table at slab + off[i] (of off[i+1] -
+// off[i] slots, empty beforehand) and its weights to total[i].  A hot
+// label costs one device atomic per piece, and a long row is spread over
+// many blocks.
+__global__ __launch_bounds__(256) void copra_gpiece_k(CopraArgs a, const CopraPiece *__restrict__ pieces,
+                                                      uint32_t count, const u64 *__restrict__ off, uint32_t *slab_key,
+                                                      u64 *slab_tal, u64 *total) {
+    __shared__ uint32_t key[kCopraBlockSlots];
+    __shared__ u64 tal[kCopraBlockSlots];
     const uint32_t V = a.V;
+    for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+        const CopraPiece pc = pieces[it];
+        for (uint32_t s = threadIdx.x; s < kCopraBlockSlots; s += 256) {
+            key[s] = kEmptyKey;
+            tal[s] = 0;
+        }
+        __syncthreads();
+        const u64 o = off[pc.i];
+        const uint32_t S = (uint32_t)(off[pc.i + 1] - o);
+        u64 tw = 0;
+        for (uint64_t k = pc.b0 + threadIdx.x; k < pc.b1; k += 256) {
+            const uint32_t we = a.g.w ? a.g.w[k] : 1u;
+            tw += we;
+            const uint32_t u = a.g.col[k];
+            const uint32_t c = a.cnt_in[u];
+            for (uint32_t i = 0; i < c; ++i) {
+                const uint32_t l = a.lab_in[(u64)u * V + i];
+                const u64 x = (u64)we * a.coef_in[(u64)u * V + i];
+                // a piece has at most 2048 entries: the LDS table never fills
+                if (copra_insert_bounded(key, tal, kCopraBlockSlots - 1, l, x) < 0 &&
+                    copra_insert_bounded(slab_key + o, slab_tal + o, S - 1, l, x) < 0)
+                    atomicOr(a.err, ERR_TABLE);
+            }
+        }
+        if (tw) atomicAdd(&total[pc.i], tw);
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < kCopraBlockSlots; s += 256) {
+            const uint32_t l = key[s];
+            if (l != kEmptyKey && copra_insert_bounded(slab_key + o, slab_tal + o, S - 1, l, tal[s]) < 0)
+                atomicOr(a.err, ERR_TABLE);  // cannot happen: S >= 2 * distinct labels
+        }
+        __syncthreads();  // the LDS table is cleared for the next piece
+    }
+}
+
+// One block per listed row: the vote from its filled device-memory table.
+__global__ __launch_bounds__(256) void copra_gfinal_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count,
+                                                      const u64 *__restrict__ off, const uint32_t *slab_key,
+                                                      const u64 *slab_tal, const u64 *__restrict__ total) {
+    __shared__ BlockRed red[2];
+    __shared__ uint32_t klab[64], kcoef[64], kn;
     u64 chg = 0;
     for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
         const uint32_t v = rows[it];
         const Tie tie = copra_tie(a, v);
         const u64 o = off[it];
         const uint32_t S = (uint32_t)(off[it + 1] - o);
-        uint32_t *key = slab_key + o;
-        u64 *tal = slab_tal + o;
         if (threadIdx.x == 0) kn = 0;
-        const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
-        u64 tw = 0;
-        for (uint64_t k = b + threadIdx.x; k < e; k += 256) {
-            const uint32_t we = a.g.w ? a.g.w[k] : 1u;
-            tw += we;
-            const uint32_t u = a.g.col[k];
-            const uint32_t c = a.cnt_in[u];
-            for (uint32_t i = 0; i < c; ++i)
-                if (copra_insert_bounded(key, tal, S - 1, a.lab_in[(u64)u * V + i],
-                                         (u64)we * a.coef_in[(u64)u * V + i]) < 0)
-                    atomicOr(a.err, ERR_TABLE);  // cannot happen: S >= 2 * distinct labels
-        }
-        u64 z1 = 0, z2 = 0;
-        uint32_t zo = 0;
-        block_reduce(red[2], z1, tw, z2, zo);  // every insertion of the row is done after its barrier
-        const uint32_t best = copra_finish_block<true>(a, v, tie, key, tal, S, tw * kOne, red, klab, kcoef, &kn);
+        __syncthreads();
+        const uint32_t best = copra_finish_block<true>(a, v, tie, slab_key + o, slab_tal + o, S, total[it] * kOne,
+                                                       red, klab, kcoef, &kn);
         if (threadIdx.x == 0) chg += a.best_in[v] != best;
         __syncthreads();
     }
     block_count(chg, a.changed);
+}
+
+// Pieces of the listed rows: row i gets ceil(deg / per) pieces starting at
+// first[i] (an exclusive prefix sum), each of at most `per` arcs.
+__global__ void copra_pieces_k(Graph g, const uint32_t *rows, uint32_t count, const u64 *first, uint32_t per,
+                               CopraPiece *pieces) {
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint32_t v = rows[i];
+        const uint64_t b = g.rp[v], e = g.rp[v + 1];
+        const u64 p0 = first[i];
+        const u64 np = (e - b + per - 1) / per;
+        for (u64 j = threadIdx.x; j < np; j += blockDim.x) {
+            const uint64_t b0 = b + j * per;
+            pieces[p0 + j] = CopraPiece{i, 0u, b0, b0 + per < e ? b0 + per : e};
+        }
+    }
 }
 
 // Every vertex its own community with belonging 1.
@@ -370,18 +572,42 @@ __global__ void copra_init_k(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *co
     }
 }
 
-// Rows of deg * V > 512, appended in any order (the result does not depend
-// on it).
-__global__ void copra_list_k(Graph g, uint32_t V, uint32_t *rows, uint32_t *count) {
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x)
-        if ((g.rp[v + 1] - g.rp[v]) * V > 512) rows[atomicAdd(count, 1u)] = v;
+// Rows by class, appended in any order (the result does not depend on it):
+// class 0 deg * V <= 32, class 1 <= 512, class 2 larger; rows without arcs
+// are in no list (their state never changes: both buffers hold it).
+// One atomic per wavefront and class.
+__global__ void copra_list_k(Graph g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,
+                             uint32_t *count) {
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t base = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u; base < g.n;
+         base += gridDim.x * blockDim.x) {
+        const uint32_t v = base + lane;
+        const uint64_t d = v < g.n ? (g.rp[v + 1] - g.rp[v]) * V : 0;
+        const int cls = v >= g.n || d == 0 ? -1 : d <= 32 ? 0 : d <= 512 ? 1 : 2;
+        uint32_t *dst[3] = {rows0, rows1, rows2};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const u64 m = __ballot(cls == c);
+            if (!m) continue;
+            const int lead = __ffsll((long long)m) - 1;
+            uint32_t at = 0;
+            if ((int)lane == lead) at = atomicAdd(&count[c], (uint32_t)__popcll(m));
+            at = (uint32_t)__shfl((int)at, lead, 64);
+            if (cls == c) dst[c][at + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = v;
+        }
+    }
 }
 
-// Table sizes of the listed rows: next_pow2(2 * min(deg * V, n)).
-__global__ void copra_sizes_k(Graph g, uint32_t V, const uint32_t *rows, uint32_t count, u64 *size) {
+// Table sizes of the listed rows, next_pow2(2 * min(deg * V, n)), and their
+// numbers of pieces of at most `per` arcs.
+__global__ void copra_sizes_k(Graph g, uint32_t V, const uint32_t *rows, uint32_t count, uint32_t per, u64 *size,
+                              u64 *npieces) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
         const uint32_t v = rows[i];
-        u64 d = (g.rp[v + 1] - g.rp[v]) * V;
+        const u64 deg = g.rp[v + 1] - g.rp[v];
+        npieces[i] = (deg + per - 1) / per;
+        u64 d = deg * V;
         d = d < g.n ? d : g.n;
         u64 s = 1;
         while (s < 2 * d && s < (1ull << 31)) s <<= 1;  // 2^31 slots: more than any row's labels here
@@ -391,8 +617,10 @@ __global__ void copra_sizes_k(Graph g, uint32_t V, const uint32_t *rows, uint32_
 
 // The caller's CSR, checked before any round reads it: row_ptr starts at 0,
 // never decreases and ends at m; every col < n; every weighted degree below
-// 2^32.  One wavefront per 64 rows, long rows summed by the whole wavefront.
-__global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err) {
+// 2^32.  With `distinct`, also whether each row's neighbours are strictly
+// increasing (each listed once).  One wavefront per 64 rows: rows of at most 8 arcs one lane each,
+// longer rows by the whole wavefront.
+__global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err, uint8_t *distinct) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (blockIdx.x == 0 && threadIdx.x == 0 && (g.rp[0] != 0 || g.rp[g.n] != g.m)) atomicOr(err, ERR_ROWPTR);
@@ -405,14 +633,22 @@ __global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err) {
         const bool bad = act && (b > e || e > g.m);
         bits |= bad ? ERR_ROWPTR : 0u;
         const bool ok = act && !bad;
-        const bool one = ok && e - b <= 32;
+        const bool one = ok && e - b <= 8;
         if (one) {
             u64 tw = 0;
+            bool inc = true;  // neighbours strictly increasing: each listed once
+            uint32_t prev = 0;
             for (uint64_t k = b; k < e; ++k) {
-                bits |= g.col[k] >= g.n ? ERR_COL : 0u;
+                const uint32_t u = g.col[k];
+                bits |= u >= g.n ? ERR_COL : 0u;
+                inc &= k == b || u > prev;
+                prev = u;
                 tw += g.w ? g.w[k] : 1u;
             }
             bits |= tw > 0xFFFFFFFFull ? ERR_WOVF : 0u;
+            if (distinct) distinct[v] = inc;
+        } else if (act && distinct) {
+            distinct[v] = 0;
         }
         u64 longm = __ballot(ok && !one);
         while (longm) {
@@ -420,20 +656,25 @@ __global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err) {
             longm &= longm - 1;
             const uint64_t bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
             u64 tw = 0;
+            bool inc = true;
             for (uint64_t k = bj + lane; k < ej; k += 64) {
-                bits |= g.col[k] >= g.n ? ERR_COL : 0u;
+                const uint32_t u = g.col[k];
+                bits |= u >= g.n ? ERR_COL : 0u;
+                inc &= k + 1 >= ej || u < g.col[k + 1];
                 tw += g.w ? g.w[k] : 1u;
             }
             tw = wave_sum(tw);
             bits |= tw > 0xFFFFFFFFull ? ERR_WOVF : 0u;
+            const bool all_inc = __ballot(!inc) == 0;
+            if (distinct && lane == 0) distinct[base + j] = all_inc;
         }
     }
     if (bits) atomicOr(err, bits);
 }
 
-hipError_t launch_csr_check(const Graph &g, uint32_t *err, hipStream_t s) {
+hipError_t launch_csr_check(const Graph &g, uint32_t *err, uint8_t *distinct, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    csr_check_k<<<grid_for(g.n, 256, 4096), 256, 0, s>>>(g, err);
+    csr_check_k<<<grid_for(g.n, 256, 4096), 256, 0, s>>>(g, err, distinct);
     return hipGetLastError();
 }
 hipError_t launch_copra_init(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best,
@@ -442,32 +683,51 @@ hipError_t launch_copra_init(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *co
     copra_init_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, V, lab, coef, cnt, best);
     return hipGetLastError();
 }
-hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows, uint32_t *count, hipStream_t s) {
+hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,
+                             uint32_t *count, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    copra_list_k<<<grid_for(g.n, 256, 8192), 256, 0, s>>>(g, V, rows, count);
+    copra_list_k<<<grid_for(g.n, 256, 8192), 256, 0, s>>>(g, V, rows0, rows1, rows2, count);
     return hipGetLastError();
 }
-hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count, u64 *size,
-                              hipStream_t s) {
+hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count, uint32_t per,
+                              u64 *size, u64 *npieces, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    copra_sizes_k<<<grid_for(count, 256, 4096), 256, 0, s>>>(g, V, rows, count, size);
+    copra_sizes_k<<<grid_for(count, 256, 4096), 256, 0, s>>>(g, V, rows, count, per, size, npieces);
     return hipGetLastError();
 }
-hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *big_rows, uint32_t n_big, hipStream_t s) {
-    if (a.g.n == 0) return hipSuccess;
-    copra_wave_k<<<grid_for(a.g.n, 4, 8192), 256, 0, s>>>(a);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && n_big) {
-        copra_block_k<<<grid_for(n_big, 1, 4096), 256, 0, s>>>(a, big_rows, n_big);
+hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *const *rows, const uint32_t *count,
+                              hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (count[0]) {
+        copra_group_k<<<grid_for(count[0], 16, 8192), 256, 0, s>>>(a, rows[0], count[0]);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && count[1]) {
+        copra_wave_k<<<grid_for(count[1], 4, 8192), 256, 0, s>>>(a, rows[1], count[1]);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && count[2]) {
+        copra_block_k<<<grid_for(count[2], 1, 4096), 256, 0, s>>>(a, rows[2], count[2]);
         e = hipGetLastError();
     }
     return e;
 }
-hipError_t launch_copra_global(const CopraArgs &a, const uint32_t *rows, uint32_t count, const u64 *off,
-                               uint32_t *slab_key, u64 *slab_tal, hipStream_t s) {
+hipError_t launch_copra_global(const CopraArgs &a, const uint32_t *rows, uint32_t count, const u64 *first,
+                               uint32_t per, CopraPiece *pieces, uint64_t npieces, const u64 *off, uint32_t *slab_key,
+                               u64 *slab_tal, u64 *total, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    copra_global_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(a, rows, count, off, slab_key, slab_tal);
-    return hipGetLastError();
+    copra_pieces_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(a.g, rows, count, first, per, pieces);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        copra_gpiece_k<<<grid_for(npieces, 1, 8192), 256, 0, s>>>(a, pieces, (uint32_t)npieces, off, slab_key,
+                                                                  slab_tal, total);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        copra_gfinal_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(a, rows, count, off, slab_key, slab_tal, total);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 }  // namespace lpa

@@ -192,6 +192,8 @@ struct CopraArgs {
     uint32_t *ovf_rows;           // rows left to the device-memory table ...
     uint32_t *ovf_count;          // ... and their number
     uint32_t *err;                // ERR_TABLE if a table had no free slot
+    uint32_t first;               // every vertex is still alone (round 1, first half)
+    const uint8_t *distinct;      // per row: its neighbours are listed once
 };
 
 // Batched run: state of the persistent kernel (lpa_batch.hip).  The bins
@@ -371,25 +373,50 @@ hipError_t launch_row_sums(const Graph &g, uint32_t *kw, hipStream_t s);
 hipError_t launch_mask_rows(uint8_t *mask, const uint32_t *old_of, uint32_t lo, uint32_t cnt, uint8_t val,
                             hipStream_t s);
 
+// A piece of a COPRA row voted through a device-memory table: arcs
+// [b0, b1) of row rows[i].
+struct CopraPiece {
+    uint32_t i;
+    uint32_t pad;
+    uint64_t b0, b1;
+};
+
 // ---- launchers: lpa_copra.hip --------------------------------------------
-// Check a caller's CSR (row_ptr, col < n, weighted degrees < 2^32) into err.
-hipError_t launch_csr_check(const Graph &g, uint32_t *err, hipStream_t s);
+// Check a caller's CSR (row_ptr, col < n, weighted degrees < 2^32) into
+// err; distinct (u8[n] or NULL) receives whether each row's neighbours are
+// strictly increasing.
+hipError_t launch_csr_check(const Graph &g, uint32_t *err, uint8_t *distinct, hipStream_t s);
 hipError_t launch_copra_init(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best,
                              hipStream_t s);
-// Rows of deg * V > 512 into rows[0..*count) (count zeroed by the caller).
-hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows, uint32_t *count, hipStream_t s);
-hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count,
-                              unsigned long long *size, hipStream_t s);
-hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *big_rows, uint32_t n_big, hipStream_t s);
+// Rows with arcs by class into rows0 (deg * V <= 32), rows1 (<= 512) and
+// rows2 (larger), count[0..3) (zeroed by the caller).
+hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,
+                             uint32_t *count, hipStream_t s);
+// Table sizes (next_pow2(2 * min(deg * V, n))) and piece counts (pieces of
+// at most `per` arcs) of the listed rows.
+hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count, uint32_t per,
+                              unsigned long long *size, unsigned long long *npieces, hipStream_t s);
+// One half-round over the three row lists (count: host copy of their sizes).
+hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *const *rows, const uint32_t *count,
+                              hipStream_t s);
+// The listed rows through device-memory tables (off: table offsets, count + 1
+// entries; first: first piece of each row; tables and totals zeroed).
 hipError_t launch_copra_global(const CopraArgs &a, const uint32_t *rows, uint32_t count,
+                               const unsigned long long *first, uint32_t per, CopraPiece *pieces, uint64_t npieces,
                                const unsigned long long *off, uint32_t *slab_key, unsigned long long *slab_tal,
-                               hipStream_t s);
+                               unsigned long long *total, hipStream_t s);
 // Modularity sums of a CSR as the caller stores it (any row length, row
 // bounds and labels checked in the kernel), and the final u128 reduction of
 // mod_sumsq_k's partials (lpa_mod.hip).
 hipError_t launch_mod_any(const ModArgs &a, hipStream_t s);
 hipError_t launch_mod_final(const unsigned long long *partials, uint32_t nparts, const unsigned long long *sums,
                             const uint32_t *err, unsigned long long *out, hipStream_t s);
+// The whole modularity of `labels` on a CSR as the caller stores it: clears
+// K[0..n) and sums[0..3) (two totals, then the error word that `err` points
+// into), then fills out[0..5) = {sum K^2 low, high, 2m, Sigma_in, error bits}.
+hipError_t launch_modularity_any(const Graph &g, const uint32_t *labels, unsigned long long *K,
+                                 unsigned long long *sums, uint32_t *err, unsigned long long *partials,
+                                 uint32_t nparts, unsigned long long *out, hipStream_t s);
 // Fixed scratch of lpa_modularity_noalloc: look up its address on `device`
 // (current) once; called by lpa_init (lpa_noalloc.hip).
 hipError_t noalloc_attach(int device);

@@ -459,6 +459,22 @@ hipError_t launch_mod_final(const u64 *partials, uint32_t nparts, const u64 *sum
     mod_final_k<<<1, 256, 0, s>>>(partials, nparts, sums, err, out);
     return hipGetLastError();
 }
+hipError_t launch_modularity_any(const Graph &g, const uint32_t *labels, u64 *K, u64 *sums, uint32_t *err,
+                                 u64 *partials, uint32_t nparts, u64 *out, hipStream_t s) {
+    hipError_t e = launch_fill_u64(K, 0, g.n, s);
+    if (e == hipSuccess) e = launch_fill_u64(sums, 0, 3, s);  // the two totals and the error word
+    ModArgs ma;
+    ma.g = g;
+    ma.labels = labels;
+    ma.K = K;
+    ma.sums = sums;
+    ma.err = err;
+    ma.labels_prev = nullptr;
+    if (e == hipSuccess) e = launch_mod_any(ma, s);
+    if (e == hipSuccess) e = launch_mod_sumsq(K, g.n, partials, nparts, s);
+    if (e == hipSuccess) e = launch_mod_final(partials, nparts, sums, err, out, s);
+    return e;
+}
 hipError_t launch_mod_sumsq(const u64 *K, uint32_t n, u64 *partials, uint32_t nparts, hipStream_t s) {
     mod_sumsq_k<<<nparts, 256, 0, s>>>(K, n, partials);
     return hipGetLastError();

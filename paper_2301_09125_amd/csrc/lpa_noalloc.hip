@@ -91,18 +91,8 @@ extern "C" lpa_status lpa_modularity_noalloc(lpa_ctx *c, const lpa_csr *g, const
     const uint32_t n = g->n;
     u64 *K = S, *sums = S + kOffSums, *out = S + kOffOut, *parts = S + kOffParts;
     uint32_t *err = reinterpret_cast<uint32_t *>(S + kOffErr);
-    NA_TRY(launch_fill_u64(K, 0, n, s));
-    NA_TRY(launch_fill_u64(sums, 0, 3, s));  // the two totals and the error word
-    ModArgs ma;
-    ma.g = Graph{g->row_ptr, g->col, g->w, n, g->m};
-    ma.labels = labels;
-    ma.K = K;
-    ma.sums = sums;
-    ma.err = err;
-    ma.labels_prev = nullptr;
-    NA_TRY(launch_mod_any(ma, s));
-    NA_TRY(launch_mod_sumsq(K, n, parts, kNoAllocParts, s));
-    NA_TRY(launch_mod_final(parts, kNoAllocParts, sums, err, out, s));
+    NA_TRY(launch_modularity_any(Graph{g->row_ptr, g->col, g->w, n, g->m}, labels, K, sums, err, parts,
+                                 kNoAllocParts, out, s));
     u64 res[5];
     NA_TRY(hipMemcpyAsync(res, out, sizeof(res), hipMemcpyDeviceToHost, s));
     NA_TRY(hipStreamSynchronize(s));

@@ -107,6 +107,7 @@ struct lpa_ctx {
     DevBuf t_w, t_m, t_v, t_part, t_grad, t_loss, t_z;                               // training
     DevBuf tune_labels, tune_hist;                                                    // autotuner
     DevBuf cp_lab[2], cp_coef[2], cp_cnt[2], cp_best[2], cp_rows, cp_ovf, cp_off, cp_key, cp_tal;  // COPRA
+    DevBuf cp_first, cp_pieces, cp_total, cp_rows1, cp_rows2, cp_distinct;
     std::map<std::vector<int>, lpa_options> tune_cache;
     bool slab_dirty = false;      // slab may hold entries (set after a timed-out batch)
     hipStream_t cap_stream = nullptr;
@@ -1343,6 +1344,43 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
     return LPA_OK;
 }
 
+// Modularity (as lpa_modularity) of labels on the caller's CSR as stored,
+// without the binning and relabelled copy: the kernels of
+// lpa_modularity_noalloc with the context's buffers.
+lpa_status modularity_direct(lpa_ctx *c, const Graph &G, const uint32_t *labels, double *q_out, uint64_t *terms) {
+    const hipStream_t s = c->stream;
+    const uint32_t nparts = 1024;
+    HIP_TRY(c->K.ensure((size_t)G.n * sizeof(u64)));
+    HIP_TRY(c->mod_sums.ensure(8 * sizeof(u64)));
+    HIP_TRY(c->partials.ensure(2 * nparts * sizeof(u64)));
+    u64 *sums = c->mod_sums.as<u64>();
+    LPA_TRY(timed(c, K_MOD, 0, 0, [&] {
+        return launch_modularity_any(G, labels, c->K.as<u64>(), sums, reinterpret_cast<uint32_t *>(sums + 2),
+                                     c->partials.as<u64>(), nparts, sums + 3, s);
+    }));
+    LPA_TRY(ensure_pinned(c, 8));
+    HIP_TRY(hipMemcpyAsync(c->pinned, sums + 3, 5 * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->opt.profile) collect_profile(c);
+    const uint64_t *res = c->pinned;
+    if (res[4]) return err_status((uint32_t)res[4]);
+    const unsigned __int128 sk2 = ((unsigned __int128)res[1] << 64) | (unsigned __int128)res[0];
+    const u64 two_m = res[2], sigma_in = res[3];
+    double q = 0.0;
+    if (two_m > 0) {
+        const double W = (double)two_m;
+        q = (double)sigma_in / W - (double)sk2 / (W * W);
+    }
+    *q_out = q;
+    if (terms) {
+        terms[0] = two_m;
+        terms[1] = sigma_in;
+        terms[2] = (u64)sk2;
+        terms[3] = (u64)(sk2 >> 64);
+    }
+    return LPA_OK;
+}
+
 // ------------------------------------------------------------------ COPRA --
 //
 // Rounds of COPRA (lpa_copra.hip) on the caller's CSR.  Per half-round: the
@@ -1365,16 +1403,18 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
     clear_stats(stats);
     if (n == 0) return LPA_OK;
     const Graph G{g->row_ptr, g->col, g->w, n, g->m};
-    // counters: kCountWords changed words, then the overflow count, the
-    // big-row count and the error word
+    // counters: kCountWords changed words, then the overflow count (word
+    // kCountWords), the error word (kCountWords + 1) and the three row-list
+    // sizes (kCountWords + 2 ..)
     HIP_TRY(c->counters.ensure((kCountWords + 8) * sizeof(u64)));
     u64 *cw = c->counters.as<u64>();
     uint32_t *ovf_count = reinterpret_cast<uint32_t *>(cw + kCountWords);
-    uint32_t *big_count = ovf_count + 2;
-    uint32_t *err = ovf_count + 4;
+    uint32_t *err = reinterpret_cast<uint32_t *>(cw + kCountWords + 1);
+    uint32_t *list_count = reinterpret_cast<uint32_t *>(cw + kCountWords + 2);
     LPA_TRY(ensure_pinned(c, kCountWords + 32));
     HIP_TRY(launch_fill_u64(cw, 0, kCountWords + 8, s));
-    HIP_TRY(launch_csr_check(G, err, s));
+    HIP_TRY(c->cp_distinct.ensure(n));
+    HIP_TRY(launch_csr_check(G, err, c->cp_distinct.as<uint8_t>(), s));
     HIP_TRY(hipMemcpyAsync(c->pinned, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (const uint32_t bits = reinterpret_cast<uint32_t *>(c->pinned)[0]) return err_status(bits);
@@ -1387,12 +1427,20 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
         HIP_TRY(c->cp_best[b].ensure((size_t)n * sizeof(uint32_t)));
     }
     HIP_TRY(c->cp_rows.ensure((size_t)n * sizeof(uint32_t)));
-    HIP_TRY(launch_copra_init(n, V, c->cp_lab[0].as<uint32_t>(), c->cp_coef[0].as<uint32_t>(),
-                              c->cp_cnt[0].as<uint32_t>(), c->cp_best[0].as<uint32_t>(), s));
-    HIP_TRY(launch_copra_list(G, V, c->cp_rows.as<uint32_t>(), big_count, s));
-    HIP_TRY(hipMemcpyAsync(c->pinned, big_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c->cp_rows1.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(c->cp_rows2.ensure((size_t)n * sizeof(uint32_t)));
+    // both buffers start alone: rows without arcs are never voted again
+    for (int b = 0; b < 2; ++b)
+        HIP_TRY(launch_copra_init(n, V, c->cp_lab[b].as<uint32_t>(), c->cp_coef[b].as<uint32_t>(),
+                                  c->cp_cnt[b].as<uint32_t>(), c->cp_best[b].as<uint32_t>(), s));
+    HIP_TRY(launch_copra_list(G, V, c->cp_rows.as<uint32_t>(), c->cp_rows1.as<uint32_t>(),
+                              c->cp_rows2.as<uint32_t>(), list_count, s));
+    HIP_TRY(hipMemcpyAsync(c->pinned, list_count, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const uint32_t n_big = reinterpret_cast<uint32_t *>(c->pinned)[0];
+    uint32_t n_list[3];
+    std::memcpy(n_list, c->pinned, sizeof(n_list));
+    const uint32_t *lists[3] = {c->cp_rows.as<uint32_t>(), c->cp_rows1.as<uint32_t>(), c->cp_rows2.as<uint32_t>()};
+    const uint32_t n_big = n_list[2];
     HIP_TRY(c->cp_ovf.ensure((size_t)(n_big ? n_big : 1) * sizeof(uint32_t)));
 
     const uint64_t thr = (uint64_t)std::floor(tol * (double)n);
@@ -1429,55 +1477,73 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
             a.ovf_rows = c->cp_ovf.as<uint32_t>();
             a.ovf_count = ovf_count;
             a.err = err;
+            a.first = t == 1 && h == 0;  // before any vertex voted
+            a.distinct = c->cp_distinct.as<uint8_t>();
             HIP_TRY(launch_fill_u64(cw, 0, kCountWords + 1, s));  // changed words and the overflow count
             HIP_TRY(hipEventRecord(c->round_a, s));
             // a half-round votes about half of the arcs; the whole round's
             // bytes are charged to its first launch
             const uint64_t bytes = h ? 0 : wb * g->m + 28ull * n;
             LPA_TRY(timed(c, K_COPRA, bytes, h ? 0 : g->m,
-                          [&] { return launch_copra_round(a, c->cp_rows.as<uint32_t>(), n_big, s); }));
+                          [&] { return launch_copra_round(a, lists, n_list, s); }));
             HIP_TRY(hipEventRecord(c->round_b, s));
             // changed words, overflow count, error word
-            HIP_TRY(hipMemcpyAsync(c->pinned, cw, (kCountWords + 3) * sizeof(u64), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(c->pinned, cw, (kCountWords + 2) * sizeof(u64), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
             ms_t += ms;
             const uint32_t n_ovf = reinterpret_cast<uint32_t *>(c->pinned + kCountWords)[0];
             if (n_ovf) {
-                // tables in device memory for the rows the LDS could not hold
+                // tables in device memory for the rows the LDS could not
+                // hold, filled by pieces of at most 2048 / V arcs
+                const uint32_t per = 2048u / V;
                 HIP_TRY(c->cp_off.ensure(((size_t)n_ovf + 1) * sizeof(u64)));
-                HIP_TRY(launch_copra_sizes(G, V, a.ovf_rows, n_ovf, c->cp_off.as<u64>(), s));
-                std::vector<u64> off((size_t)n_ovf + 1);
+                HIP_TRY(c->cp_first.ensure((size_t)n_ovf * sizeof(u64)));
+                HIP_TRY(launch_copra_sizes(G, V, a.ovf_rows, n_ovf, per, c->cp_off.as<u64>(), c->cp_first.as<u64>(),
+                                           s));
+                std::vector<u64> off((size_t)n_ovf + 1), first((size_t)n_ovf);
                 HIP_TRY(hipMemcpyAsync(off.data(), c->cp_off.p, (size_t)n_ovf * sizeof(u64), hipMemcpyDeviceToHost,
                                        s));
+                HIP_TRY(hipMemcpyAsync(first.data(), c->cp_first.p, (size_t)n_ovf * sizeof(u64),
+                                       hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipStreamSynchronize(s));
-                u64 total = 0;
+                u64 total = 0, npieces = 0;
                 for (uint32_t i = 0; i < n_ovf; ++i) {
-                    const u64 sz = off[i];
+                    const u64 sz = off[i], np = first[i];
                     off[i] = total;
+                    first[i] = npieces;
                     total += sz;
+                    npieces += np;
                 }
                 off[n_ovf] = total;
                 HIP_TRY(hipMemcpyAsync(c->cp_off.p, off.data(), off.size() * sizeof(u64), hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync(c->cp_first.p, first.data(), first.size() * sizeof(u64), hipMemcpyHostToDevice,
+                                       s));
                 HIP_TRY(c->cp_key.ensure((size_t)total * sizeof(uint32_t)));
                 HIP_TRY(c->cp_tal.ensure((size_t)total * sizeof(u64)));
+                HIP_TRY(c->cp_pieces.ensure((size_t)npieces * sizeof(CopraPiece)));
+                HIP_TRY(c->cp_total.ensure((size_t)n_ovf * sizeof(u64)));
                 HIP_TRY(launch_fill_u32(c->cp_key.as<uint32_t>(), 0xFFFFFFFFu, total, s));
                 HIP_TRY(launch_fill_u64(c->cp_tal.as<u64>(), 0, total, s));
+                HIP_TRY(launch_fill_u64(c->cp_total.as<u64>(), 0, n_ovf, s));
                 HIP_TRY(hipEventRecord(c->round_a, s));
                 LPA_TRY(timed(c, K_COPRA_GLOBAL, 0, 0, [&] {
-                    return launch_copra_global(a, a.ovf_rows, n_ovf, c->cp_off.as<u64>(), c->cp_key.as<uint32_t>(),
-                                               c->cp_tal.as<u64>(), s);
+                    return launch_copra_global(a, a.ovf_rows, n_ovf, c->cp_first.as<u64>(), per,
+                                               c->cp_pieces.as<CopraPiece>(), npieces, c->cp_off.as<u64>(),
+                                               c->cp_key.as<uint32_t>(), c->cp_tal.as<u64>(), c->cp_total.as<u64>(),
+                                               s);
                 }));
                 HIP_TRY(hipEventRecord(c->round_b, s));
-                HIP_TRY(hipMemcpyAsync(c->pinned, cw, (kCountWords + 3) * sizeof(u64), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(c->pinned, cw, (kCountWords + 2) * sizeof(u64), hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipStreamSynchronize(s));
                 (void)hipEventElapsedTime(&ms, c->round_a, c->round_b);
                 ms_t += ms;
             }
             for (int k = 0; k < kCountSlots; ++k) changed += c->pinned[(size_t)k * kCountStride];
             cur = nx;
-            if (const uint32_t bits = reinterpret_cast<uint32_t *>(c->pinned + kCountWords)[4]) return err_status(bits);
+            if (const uint32_t bits = reinterpret_cast<uint32_t *>(c->pinned + kCountWords + 1)[0])
+                return err_status(bits);
         }
         ms_rounds += ms_t;
         it = t;
@@ -1501,7 +1567,7 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
     if (c->opt.profile) collect_profile(c);
     double q = 0;
     uint64_t terms[4] = {0, 0, 0, 0};
-    if (c->opt.modularity) LPA_TRY(lpa_modularity(c, g, best_out, &q, terms));
+    if (c->opt.modularity) LPA_TRY(modularity_direct(c, G, best_out, &q, terms));
     if (stats) {
         stats->iterations = it;
         stats->converged = converged;
@@ -1916,7 +1982,9 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
                       &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist,
                       &c->cp_lab[0], &c->cp_lab[1], &c->cp_coef[0], &c->cp_coef[1], &c->cp_cnt[0], &c->cp_cnt[1],
-                      &c->cp_best[0], &c->cp_best[1], &c->cp_rows, &c->cp_ovf, &c->cp_off, &c->cp_key, &c->cp_tal};
+                      &c->cp_best[0], &c->cp_best[1], &c->cp_rows, &c->cp_ovf, &c->cp_off, &c->cp_key, &c->cp_tal,
+                      &c->cp_first, &c->cp_pieces, &c->cp_total, &c->cp_rows1, &c->cp_rows2,
+                      &c->cp_distinct};
     if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) b->release();

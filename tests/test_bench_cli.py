@@ -37,8 +37,9 @@ def test_help_lists_the_contract_flags():
 
 
 def test_traffic_is_null_once_the_kernel_sources_change(tmp_path, monkeypatch):
-    # a counter summary carries a hash of the kernel sources it was taken
-    # with; once a source changes, bench.py reports traffic as null
+    # a counter summary carries a hash of the sources its kernel is built
+    # from; once one of them changes, bench.py reports traffic as null, and
+    # a change to another kernel's source leaves it valid
     import hashlib
     import shutil
     sys.path.insert(0, ROOT)
@@ -46,9 +47,8 @@ def test_traffic_is_null_once_the_kernel_sources_change(tmp_path, monkeypatch):
     csrc = tmp_path / "paper_2301_09125_amd" / "csrc"
     shutil.copytree(os.path.join(ROOT, "paper_2301_09125_amd", "csrc"), csrc)
     h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update((csrc / f).read_bytes())
+    for f in sorted(["lpa_vote.hip", "lpa_vote_dev.h", "lpa_device.h", "lpa_internal.h"]):
+        h.update((csrc / f).read_bytes())
     (tmp_path / "profiles").mkdir()
     (tmp_path / "profiles" / "traffic_vote_hub_toy.txt").write_text(
         "# toy summary\nkernel: vote_hub\ntraffic_bytes_per_launch: 12345\n"
@@ -56,6 +56,9 @@ def test_traffic_is_null_once_the_kernel_sources_change(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.traffic_from_profile("toy", "vote_hub") == 12345
     assert bench.traffic_from_profile("other", "vote_hub") is None  # no summary
+    with open(csrc / "lpa_copra.hip", "a") as f:
+        f.write("\n// changed\n")
+    assert bench.traffic_from_profile("toy", "vote_hub") == 12345
     with open(csrc / "lpa_vote.hip", "a") as f:
         f.write("\n// changed\n")
     assert bench.traffic_from_profile("toy", "vote_hub") is None

@@ -3,9 +3,11 @@ orc_copra: best labels, per-round changed counts, round counts and the final
 state (kept labels, fixed-point belonging coefficients, counts) bit for bit,
 in both update orders and with both tie rules.
 
-The graphs reach every path: rows of deg * max_labels <= 512 (one wavefront
-each), longer rows (one block with an LDS table), and rows whose distinct
-labels outgrow that table (a 5000-arc star: tables in device memory).
+The graphs reach every path: rows of deg * max_labels <= 32 (16 lanes
+each) and <= 512 (one wavefront each), longer rows (one block with an LDS
+table, or in round 1 without one when each neighbour is listed once, and
+with one when a row repeats neighbours), and rows whose distinct labels
+outgrow that table (a broom's centre: tables in device memory).
 """
 import sys
 
@@ -87,14 +89,37 @@ def test_copra_max_labels_64_and_tolerances(gg, orc, lpa):
         assert_copra(orc, lpa, g, 64, "semisync", "hash", 2, tol=tol)
 
 
+def broom(gg, arms):
+    # a centre with `arms` leaves, each leaf with a pendant of its own: after
+    # round 1 every leaf holds the centre's label and its pendant's, so in
+    # round 2 the centre collects arms + 1 distinct labels
+    g = gg.from_edges(2 * arms + 1, [(0, i) for i in range(1, arms + 1)] + [(i, arms + i) for i in range(1, arms + 1)])
+    g.name = f"broom{arms}"
+    return g
+
+
 def test_copra_rows_beyond_the_lds_table(gg, orc, lpa):
-    # round 1 of a 5000-arc star: 5000 distinct labels at the centre, more
-    # than the block's LDS table takes, so that row is voted with a table in
-    # device memory; the R-MAT graph has rows of both kinds too
-    for g in (star(gg, 5000), gg.rmat(15, seed=15)):
+    # the broom's centre in round 2 (5001 distinct labels) is more than the
+    # block's LDS table takes: voted with a table in device memory; a
+    # 5000-arc star decides its centre in round 1 without a table; the
+    # R-MAT graph has rows of every kind
+    for g in (broom(gg, 5000), star(gg, 5000), gg.rmat(15, seed=15)):
         for order, tie in MODES:
             say("[copra] big rows", getattr(g, "name", ""), order, tie)
             assert_copra(orc, lpa, g, 4, order, tie, 3, tol=0.0, max_iter=6)
+
+
+def test_copra_long_row_with_repeated_neighbours(gg, orc, lpa):
+    # a 600-arc row that lists each of its 300 neighbours twice: round 1
+    # must sum the repeats (the table path, not the one-arc-per-label one)
+    rp = np.concatenate([[0, 600], 600 + np.arange(1, 301)]).astype(np.uint64)
+    col = np.concatenate([np.repeat(np.arange(1, 301), 2), np.zeros(300)]).astype(np.uint32)
+    g = gg.from_csr_arrays(301, rp, col, name="repeats600")
+    for order, tie in MODES:
+        for V in (1, 4):
+            assert_copra(orc, lpa, g, V, order, tie, 5, tol=0.0, max_iter=4)
+    gw = gg.from_csr_arrays(301, rp, col, w=np.arange(1, 901, dtype=np.uint32) % 7, name="repeats600_w")
+    assert_copra(orc, lpa, gw, 4, "sync", "lowest", 0, tol=0.0, max_iter=4)
 
 
 def test_copra_one_label_is_rak_without_self_weight(gg, orc, lpa):

@@ -141,6 +141,53 @@ def test_sbm_config_modes_full(gg, orc, lpa):
     assert q["sync", "hash"] > 0.4 and q["sync", "lowest"] < 0.1
 
 
+def copra_compare(orc, lpa, g, V, order, tie, seed=1, tol=0.01):
+    """COPRA (Section 3.3) at full size against orc_copra: best labels,
+    changed counts, rounds and the whole final state."""
+    t = time.time()
+    dg = lpa.DeviceGraph.from_csr(g, "cuda")
+    with lpa.Context(0, order={"sync": 0, "semisync": 1}[order], tie={"lowest": 0, "hash": 1}[tie], seed=seed,
+                     modularity=1) as c:
+        best, st, (sl, sc, sn) = c.run_copra(dg, max_labels=V, tol=tol, max_iter=20, state=True)
+    got = lpa.labels_to_numpy(best)
+    cnt = sn.cpu().numpy().view(np.uint32)
+    lab = sl.cpu().numpy().view(np.uint32)
+    coef = sc.cpu().numpy().view(np.uint32)
+    say(f"{g.name} COPRA V={V} {order}/{tie}: gpu {st.iterations} rounds {st.changed} in {st.ms_total:.1f} ms, "
+        f"Q={st.modularity:.4f}")
+    ref = orc.copra(g, max_labels=V, tol=tol, max_iter=20, order=order, tie=tie, seed=seed, raw=True)
+    say(f"{g.name} COPRA: oracle done in {time.time() - t:.1f}s")
+    assert st.changed == ref.changed and st.iterations == ref.iterations and st.converged == ref.converged
+    mism = np.flatnonzero(got != ref.labels)
+    assert mism.size == 0, f"{mism.size} best labels differ, first {mism[:8]}"
+    rl, rc, rn = ref.state_arrays
+    assert np.array_equal(cnt, rn)
+    used = np.arange(V)[None, :] < cnt[:, None]
+    assert np.array_equal(np.where(used, lab, 0), np.where(used, rl, 0))
+    assert np.array_equal(np.where(used, coef, 0), np.where(used, rc, 0))
+    return st
+
+
+@pytest.mark.timeout(900)
+def test_copra_rmat22_full(gg, orc, lpa):
+    # the copra22 bench configuration: max_labels 4, tol 0.01, synchronous, strict
+    g = gg.rmat(22, 16, 0.57, 0.19, 0.19, seed=22)
+    copra_compare(orc, lpa, g, 4, "sync", "lowest")
+
+
+@pytest.mark.timeout(900)
+def test_copra_road_and_sbm_full(gg, orc, lpa):
+    # max_labels 1 on road graphs (the paper's setting for them); the
+    # semi-synchronous order converges where synchronous rounds oscillate
+    g = gg.road(4096, 4096, 0.3, 0.01, 1, 8, seed=4096)
+    st = copra_compare(orc, lpa, g, 1, "semisync", "lowest")
+    assert st.converged and st.modularity > 0.6
+    g = gg.sbm(10000, 100, 0.1, 0.001, seed=1)
+    for order in ("sync", "semisync"):
+        st = copra_compare(orc, lpa, g, 4, order, "hash")
+        assert st.modularity > 0.45
+
+
 def _oracle_graph(orc, b, k):
     g = b.graph(k)
     return k, orc.rak(g, tol=0.05, max_iter=20, self_weight=1)
