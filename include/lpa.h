@@ -129,6 +129,16 @@ typedef struct {
                               of SplitMix64 output number 2c + 2 (c as above),
                               and the tied label of highest score wins */
     uint64_t seed;         /* draws of order and tie (any value) */
+    uint32_t reuse_csr;    /* nonzero: lpa_run and lpa_run_resume keep the
+                              binned, relabelled copy of the CSR (steps a1-a2,
+                              once per CSR) and reuse it when called again
+                              with the same row_ptr, col, w, n, m and bin
+                              thresholds.  The caller promises the arrays
+                              were not written in between.  Any other call
+                              that builds a copy (another graph, batches,
+                              modularity, frontier runs, the autotuner)
+                              replaces it.  Round 1 is then voted by the
+                              round kernels instead of the relabel pass. */
 } lpa_options;
 
 enum { LPA_ORDER_SYNC = 0, LPA_ORDER_SEMISYNC = 1 };

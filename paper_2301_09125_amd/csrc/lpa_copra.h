@@ -1,0 +1,66 @@
+// lpa_copra.h -- COPRA (arXiv 2301.09125, Section 3.3): the arguments of one
+// half-round and the launchers of lpa_copra.hip.
+#pragma once
+
+#include "lpa_internal.h"
+
+namespace lpa {
+
+// One COPRA half-round (lpa_copra.hip) on the caller's CSR: the state of
+// the round before (lab/coef: V slots per vertex, cnt valid slots, best
+// label) and the state written.  half 0 = every vertex votes; 1 / 2 = only
+// the vertices whose draw names that half, the others copy their state.
+struct CopraArgs {
+    Graph g;
+    uint32_t V;  // max_labels, 1..64
+    const uint32_t *lab_in, *coef_in, *cnt_in, *best_in;
+    uint32_t *lab_out, *coef_out, *cnt_out, *best_out;
+    uint32_t t, half, tie;
+    unsigned long long seed;
+    unsigned long long *changed;  // kCountWords counter words: best labels changed
+    uint32_t *ovf_rows;           // rows left to the device-memory table ...
+    uint32_t *ovf_count;          // ... and their number
+    uint32_t *err;                // ERR_TABLE if a table had no free slot
+    uint32_t first;               // every vertex is still alone (round 1, first half)
+    const uint8_t *distinct;      // per row: its neighbours are listed once
+};
+
+// A piece of a COPRA row voted through a device-memory table: arcs
+// [b0, b1) of row rows[i].
+struct CopraPiece {
+    uint32_t i;
+    uint32_t pad;
+    uint64_t b0, b1;
+};
+
+// ---- launchers: lpa_copra.hip --------------------------------------------
+// Check a caller's CSR (row_ptr, col < n, weighted degrees < 2^32) into
+// err; distinct (u8[n] or NULL) receives whether each row's neighbours are
+// strictly increasing.
+hipError_t launch_csr_check(const Graph &g, uint32_t *err, uint8_t *distinct, hipStream_t s);
+hipError_t launch_copra_init(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best,
+                             hipStream_t s);
+// Rows with arcs by class into rows0 (deg * V <= 32), rows1 (<= 512) and
+// rows2 (larger), count[0..3) (zeroed by the caller).
+hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,
+                             uint32_t *count, hipStream_t s);
+// Table sizes (next_pow2(2 * min(deg * V, n))) and piece counts (pieces of
+// at most `per` arcs) of the listed rows.
+hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count, uint32_t per,
+                              unsigned long long *size, unsigned long long *npieces, hipStream_t s);
+// One half-round over the three row lists (count: host copy of their sizes).
+hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *const *rows, const uint32_t *count,
+                              hipStream_t s);
+// Device-table slots one decision block scans.
+constexpr uint32_t kCopraSliceSlots = 16384;
+// The listed rows through device-memory tables (off: table offsets, count + 1
+// entries; first: first piece of each row, pieces of at most `per` arcs;
+// sfirst: first slice of each row's table, slices of kCopraSliceSlots;
+// rowstate: (5 + 2 V) * count u64 words.  Tables, totals and rowstate
+// zeroed (table keys empty) by the caller).
+hipError_t launch_copra_global(const CopraArgs &a, const uint32_t *rows, uint32_t count,
+                               const unsigned long long *first, uint32_t per, CopraPiece *pieces, uint64_t npieces,
+                               const unsigned long long *off, uint32_t *slab_key, unsigned long long *slab_tal,
+                               unsigned long long *total, const unsigned long long *sfirst, CopraPiece *slices,
+                               uint64_t nslices, unsigned long long *rowstate, hipStream_t s);
+}  // namespace lpa

@@ -27,16 +27,18 @@
 //   copra_block_k  the other rows: one block per row, a 4096-slot LDS
 //                  table; a row whose distinct labels would fill more than
 //                  3/4 of it is listed for
-//   copra_gpiece_k / copra_gfinal_k  the listed rows, with a table in
-//                  device memory of next_pow2(2 * min(deg * V, n)) slots (at
-//                  least twice the row's distinct labels) each: pieces of
-//                  the row pre-sum their entries in LDS and add them to it,
-//                  then one block per row decides.
+//   copra_gpiece_k, copra_gscan_k, copra_gdone_k  the listed rows, with a
+//                  table in device memory of next_pow2(2 * min(deg * V, n))
+//                  slots (at least twice the row's distinct labels) each:
+//                  pieces of the row pre-sum their entries in LDS and add
+//                  them to it, slices of the table are scanned in parallel
+//                  for the decision, one wavefront per row writes the state.
 // Rows without arcs are in no list: they stay alone, and both buffers hold
 // that state from the start.  Semi-synchronous rounds: two half-rounds, a
 // vertex votes in the half its SplitMix64 draw for the round names and
 // copies its state in the other.
 
+#include "lpa_copra.h"
 #include "lpa_device.h"
 
 namespace lpa {
@@ -46,6 +48,7 @@ constexpr uint32_t kCopraWaveSlots = 1024;
 constexpr uint32_t kCopraBlockSlots = 4096;
 constexpr uint32_t kCopraBlockFill = 3072;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+constexpr uint32_t kSliceSlots = kCopraSliceSlots;
 
 __device__ __forceinline__ bool copra_votes(const CopraArgs &a, uint32_t v) {
     if (!a.half) return true;
@@ -305,19 +308,8 @@ __global__ __launch_bounds__(256) void copra_wave_k(CopraArgs a, const uint32_t 
     block_count(chg, a.changed);
 }
 
-// A table entry: from LDS, or from device memory past the L1 cache (the
-// entries were written by device-scope atomics).
-template <bool GLOBAL, typename T>
-__device__ __forceinline__ T tload(const T *p) {
-    if constexpr (GLOBAL)
-        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        return *p;
-}
-
-// The vote of row v from a filled table of S slots (LDS, or device memory
-// when GLOBAL), by a 256-thread block; reductions and kept lists in LDS.
-template <bool GLOBAL>
+// The vote of row v from its filled LDS table of S slots, by a 256-thread
+// block; reductions and kept lists in LDS.
 __device__ __forceinline__ uint32_t copra_finish_block(const CopraArgs &a, uint32_t v, Tie tie, const uint32_t *key,
                                                        const u64 *tal, uint32_t S, u64 total, BlockRed *red,
                                                        uint32_t *klab, uint32_t *kcoef, uint32_t *kn) {
@@ -325,13 +317,13 @@ __device__ __forceinline__ uint32_t copra_finish_block(const CopraArgs &a, uint3
     u64 m1 = 0, z1 = 0, z2 = 0;
     uint32_t zo = 0;
     for (uint32_t s = threadIdx.x; s < S; s += 256)
-        if (tload<GLOBAL>(&key[s]) != kEmptyKey) m1 = umax64(m1, tload<GLOBAL>(&tal[s]) + 1);
+        if (key[s] != kEmptyKey) m1 = umax64(m1, tal[s] + 1);
     block_reduce(red[0], m1, z1, z2, zo);
     u64 bc = 0, ksum = 0, kcnt = 0;
     for (uint32_t s = threadIdx.x; s < S; s += 256) {
-        const uint32_t l = tload<GLOBAL>(&key[s]);
+        const uint32_t l = key[s];
         if (l == kEmptyKey) continue;
-        const u64 t = tload<GLOBAL>(&tal[s]);
+        const u64 t = tal[s];
         if (t + 1 == m1) bc = umax64(bc, tie_code(tie, l));
         if (t > 0 && t * V >= total) {
             ksum += t;
@@ -346,9 +338,9 @@ __device__ __forceinline__ uint32_t copra_finish_block(const CopraArgs &a, uint3
         return best;
     }
     for (uint32_t s = threadIdx.x; s < S; s += 256) {
-        const uint32_t l = tload<GLOBAL>(&key[s]);
+        const uint32_t l = key[s];
         if (l == kEmptyKey) continue;
-        const u64 t = tload<GLOBAL>(&tal[s]);
+        const u64 t = tal[s];
         if (t > 0 && t * V >= total) {
             const uint32_t j = atomicAdd(kn, 1u);
             klab[j] = l;
@@ -468,7 +460,7 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
             __syncthreads();
             continue;
         }
-        const uint32_t best = copra_finish_block<false>(a, v, tie, key, tal, kCopraBlockSlots, tw * kOne, red, klab, kcoef,
+        const uint32_t best = copra_finish_block(a, v, tie, key, tal, kCopraBlockSlots, tw * kOne, red, klab, kcoef,
                                                  &kn);
         if (threadIdx.x == 0) chg += a.best_in[v] != best;
         __syncthreads();  // tables and reductions are reused by the next row
@@ -524,26 +516,108 @@ __global__ __launch_bounds__(256) void copra_gpiece_k(CopraArgs a, const CopraPi
     }
 }
 
-// One block per listed row: the vote from its filled device-memory table.
-__global__ __launch_bounds__(256) void copra_gfinal_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count,
-                                                      const u64 *__restrict__ off, const uint32_t *slab_key,
-                                                      const u64 *slab_tal, const u64 *__restrict__ total) {
-    __shared__ BlockRed red[2];
-    __shared__ uint32_t klab[64], kcoef[64], kn;
-    u64 chg = 0;
+// The decision of the listed rows from their filled device-memory tables,
+// spread over slices of at most kSliceSlots slots (item = row index i of
+// the list, slots [s0, s1) of its table) so that no table is read by one
+// block alone.  Per listed row, R holds: m1 (largest tally + 1), bc (largest
+// tie code among the heaviest labels), ksum / kcnt (kept tallies), kn and
+// up to V kept (label, tally) pairs.  Pass 0 finds m1, pass 1 bc and the
+// kept sums, pass 2 lists the kept labels; copra_gdone_k writes the state.
+struct CopraRows {
+    u64 *m1, *bc, *ksum, *kcnt;
+    uint32_t *kn;
+    uint32_t *klab;  // V per row
+    u64 *ktal;       // V per row
+};
+
+template <int PASS>
+__global__ __launch_bounds__(256) void copra_gscan_k(CopraArgs a, const uint32_t *__restrict__ rows,
+                                                     const CopraPiece *__restrict__ slices, uint32_t count,
+                                                     const uint32_t *slab_key, const u64 *slab_tal,
+                                                     const u64 *__restrict__ total, CopraRows R) {
+    __shared__ BlockRed red;
+    const uint32_t V = a.V;
     for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
-        const uint32_t v = rows[it];
+        const CopraPiece sl = slices[it];
+        const uint32_t i = sl.i;
+        const u64 tot = total[i] * kOne;
+        const Tie tie = copra_tie(a, rows[i]);
+        const u64 m1 = PASS ? R.m1[i] : 0;
+        u64 x = 0, ks = 0, kc = 0;
+        uint32_t zo = 0;
+        for (uint64_t s = sl.b0 + threadIdx.x; s < sl.b1; s += 256) {
+            const uint32_t l = slab_key[s];
+            if (l == kEmptyKey) continue;
+            const u64 t = slab_tal[s];
+            if (PASS == 0) {
+                x = umax64(x, t + 1);
+            } else if (t > 0 && t * V >= tot) {
+                if (PASS == 1) {
+                    ks += t;
+                    ++kc;
+                } else {
+                    const uint32_t j = atomicAdd(&R.kn[i], 1u);  // at most V kept labels per row
+                    R.klab[(u64)i * V + j] = l;
+                    R.ktal[(u64)i * V + j] = t;
+                }
+            }
+            if (PASS == 1 && t + 1 == m1) x = umax64(x, tie_code(tie, l));
+        }
+        if (PASS < 2) {
+            block_reduce(red, x, ks, kc, zo);
+            if (threadIdx.x == 0) {
+                if (x) atomicMax(PASS == 0 ? &R.m1[i] : &R.bc[i], x);
+                if (ks) atomicAdd(&R.ksum[i], ks);
+                if (kc) atomicAdd(&R.kcnt[i], kc);
+            }
+            __syncthreads();  // the reduction slots are reused by the next slice
+        }
+    }
+}
+
+// One wavefront per listed row: the state from the decided quantities.
+__global__ __launch_bounds__(256) void copra_gdone_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count,
+                                                     CopraRows R) {
+    __shared__ uint32_t sklab[4][64], skcoef[4][64];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t V = a.V;
+    u64 chg = 0;
+    for (uint32_t i = blockIdx.x * 4 + wave; i < count; i += gridDim.x * 4) {
+        const uint32_t v = rows[i];
         const Tie tie = copra_tie(a, v);
-        const u64 o = off[it];
-        const uint32_t S = (uint32_t)(off[it + 1] - o);
-        if (threadIdx.x == 0) kn = 0;
-        __syncthreads();
-        const uint32_t best = copra_finish_block<true>(a, v, tie, slab_key + o, slab_tal + o, S, total[it] * kOne,
-                                                       red, klab, kcoef, &kn);
-        if (threadIdx.x == 0) chg += a.best_in[v] != best;
-        __syncthreads();
+        const uint32_t best = tie_label(tie, (uint32_t)R.bc[i]);
+        const uint32_t kn = (uint32_t)R.kcnt[i];
+        if (kn == 0) {
+            if (lane == 0) copra_alone(a, v, best);
+        } else {
+            const u64 ksum = R.ksum[i];
+            if (lane < kn) {
+                sklab[wave][lane] = R.klab[(u64)i * V + lane];
+                skcoef[wave][lane] = (uint32_t)(R.ktal[(u64)i * V + lane] * kOne / ksum);
+            }
+            wave_sync();
+            copra_store(a, v, lane, sklab[wave], skcoef[wave], kn, best);
+        }
+        if (lane == 0) chg += a.best_in[v] != best;
+        wave_sync();
     }
     block_count(chg, a.changed);
+}
+
+// Slices of the listed rows' tables: row i gets ceil(size / per) slices
+// starting at first[i], covering its slots [off[i], off[i+1]).
+__global__ void copra_slices_k(const u64 *off, uint32_t count, const u64 *first, uint32_t per,
+                               CopraPiece *slices) {
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const u64 b = off[i], e = off[i + 1];
+        const u64 p0 = first[i];
+        const u64 np = (e - b + per - 1) / per;
+        for (u64 j = threadIdx.x; j < np; j += blockDim.x) {
+            const uint64_t b0 = b + j * per;
+            slices[p0 + j] = CopraPiece{i, 0u, b0, b0 + per < e ? b0 + per : e};
+        }
+    }
 }
 
 // Pieces of the listed rows: row i gets ceil(deg / per) pieces starting at
@@ -714,17 +788,43 @@ hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *const *rows, c
 }
 hipError_t launch_copra_global(const CopraArgs &a, const uint32_t *rows, uint32_t count, const u64 *first,
                                uint32_t per, CopraPiece *pieces, uint64_t npieces, const u64 *off, uint32_t *slab_key,
-                               u64 *slab_tal, u64 *total, hipStream_t s) {
+                               u64 *slab_tal, u64 *total, const u64 *sfirst, CopraPiece *slices, uint64_t nslices,
+                               u64 *rowstate, hipStream_t s) {
     if (count == 0) return hipSuccess;
+    CopraRows R;
+    R.m1 = rowstate;
+    R.bc = rowstate + count;
+    R.ksum = rowstate + 2 * (u64)count;
+    R.kcnt = rowstate + 3 * (u64)count;
+    R.kn = reinterpret_cast<uint32_t *>(rowstate + 4 * (u64)count);
+    R.ktal = rowstate + 5 * (u64)count;
+    R.klab = reinterpret_cast<uint32_t *>(rowstate + 5 * (u64)count + (u64)count * a.V);
     copra_pieces_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(a.g, rows, count, first, per, pieces);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        copra_slices_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(off, count, sfirst, kSliceSlots, slices);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) {
         copra_gpiece_k<<<grid_for(npieces, 1, 8192), 256, 0, s>>>(a, pieces, (uint32_t)npieces, off, slab_key,
                                                                   slab_tal, total);
         e = hipGetLastError();
     }
+    const unsigned gs = grid_for(nslices, 1, 8192);
     if (e == hipSuccess) {
-        copra_gfinal_k<<<grid_for(count, 1, 4096), 256, 0, s>>>(a, rows, count, off, slab_key, slab_tal, total);
+        copra_gscan_k<0><<<gs, 256, 0, s>>>(a, rows, slices, (uint32_t)nslices, slab_key, slab_tal, total, R);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        copra_gscan_k<1><<<gs, 256, 0, s>>>(a, rows, slices, (uint32_t)nslices, slab_key, slab_tal, total, R);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        copra_gscan_k<2><<<gs, 256, 0, s>>>(a, rows, slices, (uint32_t)nslices, slab_key, slab_tal, total, R);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        copra_gdone_k<<<grid_for(count, 4, 4096), 256, 0, s>>>(a, rows, count, R);
         e = hipGetLastError();
     }
     return e;

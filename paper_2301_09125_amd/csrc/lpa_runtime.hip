@@ -28,6 +28,7 @@
 
 #include "lpa.h"
 #include "lpa_internal.h"
+#include "lpa_copra.h"
 
 using namespace lpa;
 typedef unsigned long long u64;
@@ -107,8 +108,12 @@ struct lpa_ctx {
     DevBuf t_w, t_m, t_v, t_part, t_grad, t_loss, t_z;                               // training
     DevBuf tune_labels, tune_hist;                                                    // autotuner
     DevBuf cp_lab[2], cp_coef[2], cp_cnt[2], cp_best[2], cp_rows, cp_ovf, cp_off, cp_key, cp_tal;  // COPRA
-    DevBuf cp_first, cp_pieces, cp_total, cp_rows1, cp_rows2, cp_distinct;
+    DevBuf cp_first, cp_pieces, cp_total, cp_rows1, cp_rows2, cp_distinct, cp_sfirst, cp_slices, cp_rowstate;
     std::map<std::vector<int>, lpa_options> tune_cache;
+    // the CSR and thresholds the internal copy was last built for by a
+    // prepare() that also set up the long-row state (empty = none)
+    std::vector<uint64_t> prep_key;
+    Plan prep_plan;
     bool slab_dirty = false;      // slab may hold entries (set after a timed-out batch)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t bexec = nullptr;
@@ -256,11 +261,18 @@ HubState hub_state(lpa_ctx *c) {
     return h;
 }
 
+// What an internal copy depends on: the CSR arrays, sizes and bin thresholds.
+std::vector<uint64_t> csr_key(const lpa_ctx *c, const lpa_csr *g) {
+    const lpa_options &o = c->opt;
+    return {(uint64_t)(uintptr_t)g->row_ptr, (uint64_t)(uintptr_t)g->col, (uint64_t)(uintptr_t)g->w, g->n, g->m,
+            o.thread_max, o.group_max, o.wave_max, o.wide_max, o.merge_max};
+}
+
 // Bin the vertices, validate row_ptr, build the internal CSR and lay out the
-// long rows.  with_slab: also prepare the global slabs used by the vote.
-// fuse: also run round 1 from the unique labels inside the relabel pass
-// (rows that list each neighbour once); La/fuse->L1 then get their initial
-// labels here.
+// long rows.  with_slab: also prepare the global slabs used by the vote (and
+// remember the copy under csr_key for reuse_csr).  fuse: also run round 1
+// from the unique labels inside the relabel pass (rows that list each
+// neighbour once); La/fuse->L1 then get their initial labels here.
 lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, bool with_slab,
                    const Round1Fuse *fuse = nullptr, uint32_t *La = nullptr) {
     const hipStream_t s = c->stream;
@@ -268,6 +280,7 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
     const uint32_t n = g->n;
     const uint32_t nblk = bin_blocks(n);
     const lpa_options &o = c->opt;
+    c->prep_key.clear();  // the internal copy is rebuilt below
     HIP_TRY(c->blk_counts.ensure((size_t)NBINS * nblk * sizeof(uint32_t)));
     HIP_TRY(c->blk_arcs.ensure((size_t)NBINS * nblk * sizeof(u64)));
     HIP_TRY(c->small.ensure(128));
@@ -383,7 +396,26 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
                                 c->col2.as<uint32_t>(), w2, c->rowflag.as<uint8_t>(), B.lo[BIN_GROUP],
                                 B.cnt[BIN_GROUP] + B.cnt[BIN_THREAD], B.lo[BIN_THREAD], BIN_GROUP, BIN_THREAD, 0,
                                 err_dev, fuse, s));
+    if (with_slab) {
+        c->prep_key = csr_key(c, g);
+        c->prep_plan = P;
+    }
+    return LPA_OK;
+}
 
+// Per-run state of the long rows, as prepare() leaves it (with_slab).
+lpa_status reset_hub_state(lpa_ctx *c, const Plan &P) {
+    const hipStream_t s = c->stream;
+    if (!P.H) return LPA_OK;
+    if (c->slab_dirty) {
+        HIP_TRY(launch_fill_u64(c->slab.as<u64>(), 0xFFFFFFFF00000000ull, c->slab.bytes / sizeof(u64), s));
+        c->slab_dirty = false;
+    }
+    HIP_TRY(launch_fill_u32(c->slab_pending.as<uint32_t>(), 0, 2, s));
+    HIP_TRY(launch_fill_u32(c->tcount.as<uint32_t>(), 0, P.H, s));
+    HIP_TRY(launch_fill_u64(c->best.as<u64>(), 0, P.H, s));
+    HIP_TRY(launch_fill_u64(c->own_sum.as<u64>(), 0, P.H, s));
+    HIP_TRY(launch_fill_u64(c->rowsum.as<u64>(), 0, P.H, s));
     return LPA_OK;
 }
 
@@ -553,9 +585,11 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     Plan P;
     HIP_TRY(c->La.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->Lb.ensure((size_t)n * sizeof(uint32_t)));
+    // the internal copy of this CSR, kept from an earlier call
+    const bool reuse = c->opt.reuse_csr && !c->prep_key.empty() && c->prep_key == csr_key(c, g);
     // from the unique labels, round 1 of the rows that list each neighbour
     // once is done while the internal CSR is built
-    const bool fused = !resume && max_iter > 0 && plain_order;
+    const bool fused = !reuse && !resume && max_iter > 0 && plain_order;
     HIP_TRY(c->r1_rows.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->r1_cnt.ensure(NBINS * sizeof(uint32_t)));
     const Round1Fuse fz{c->Lb.as<uint32_t>(), counters, c->opt.self_weight, c->r1_rows.as<uint32_t>(),
@@ -565,7 +599,12 @@ lpa_status run_impl(lpa_ctx *c, const lpa_csr *g, uint32_t *labels, double tol, 
     if (!c->prep_a) HIP_TRY(hipEventCreate(&c->prep_a));
     if (!c->prep_b) HIP_TRY(hipEventCreate(&c->prep_b));
     HIP_TRY(hipEventRecord(c->prep_a, s));
-    LPA_TRY(prepare(c, g, P, err_dev, true, fused ? &fz : nullptr, c->La.as<uint32_t>()));
+    if (reuse) {
+        P = c->prep_plan;
+        LPA_TRY(reset_hub_state(c, P));
+    } else {
+        LPA_TRY(prepare(c, g, P, err_dev, true, fused ? &fz : nullptr, c->La.as<uint32_t>()));
+    }
     if (!fused)
         HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(),
                                    resume ? labels : nullptr, n, s));
@@ -1508,18 +1547,28 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
                 HIP_TRY(hipMemcpyAsync(first.data(), c->cp_first.p, (size_t)n_ovf * sizeof(u64),
                                        hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipStreamSynchronize(s));
-                u64 total = 0, npieces = 0;
+                std::vector<u64> sfirst((size_t)n_ovf);
+                u64 total = 0, npieces = 0, nslices = 0;
                 for (uint32_t i = 0; i < n_ovf; ++i) {
                     const u64 sz = off[i], np = first[i];
                     off[i] = total;
                     first[i] = npieces;
+                    sfirst[i] = nslices;
                     total += sz;
                     npieces += np;
+                    nslices += (sz + kCopraSliceSlots - 1) / kCopraSliceSlots;
                 }
                 off[n_ovf] = total;
+                HIP_TRY(c->cp_sfirst.ensure((size_t)n_ovf * sizeof(u64)));
                 HIP_TRY(hipMemcpyAsync(c->cp_off.p, off.data(), off.size() * sizeof(u64), hipMemcpyHostToDevice, s));
                 HIP_TRY(hipMemcpyAsync(c->cp_first.p, first.data(), first.size() * sizeof(u64), hipMemcpyHostToDevice,
                                        s));
+                HIP_TRY(hipMemcpyAsync(c->cp_sfirst.p, sfirst.data(), sfirst.size() * sizeof(u64),
+                                       hipMemcpyHostToDevice, s));
+                const size_t rs_words = (size_t)(5 + 2 * V) * n_ovf;
+                HIP_TRY(c->cp_slices.ensure((size_t)nslices * sizeof(CopraPiece)));
+                HIP_TRY(c->cp_rowstate.ensure(rs_words * sizeof(u64)));
+                HIP_TRY(launch_fill_u64(c->cp_rowstate.as<u64>(), 0, rs_words, s));
                 HIP_TRY(c->cp_key.ensure((size_t)total * sizeof(uint32_t)));
                 HIP_TRY(c->cp_tal.ensure((size_t)total * sizeof(u64)));
                 HIP_TRY(c->cp_pieces.ensure((size_t)npieces * sizeof(CopraPiece)));
@@ -1532,7 +1581,8 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
                     return launch_copra_global(a, a.ovf_rows, n_ovf, c->cp_first.as<u64>(), per,
                                                c->cp_pieces.as<CopraPiece>(), npieces, c->cp_off.as<u64>(),
                                                c->cp_key.as<uint32_t>(), c->cp_tal.as<u64>(), c->cp_total.as<u64>(),
-                                               s);
+                                               c->cp_sfirst.as<u64>(), c->cp_slices.as<CopraPiece>(), nslices,
+                                               c->cp_rowstate.as<u64>(), s);
                 }));
                 HIP_TRY(hipEventRecord(c->round_b, s));
                 HIP_TRY(hipMemcpyAsync(c->pinned, cw, (kCountWords + 2) * sizeof(u64), hipMemcpyDeviceToHost, s));
@@ -1601,6 +1651,7 @@ void lpa_default_options(lpa_options *opt) {
     opt->order = LPA_ORDER_SYNC;
     opt->tie = LPA_TIE_LOWEST;
     opt->seed = 0;
+    opt->reuse_csr = 0;
 }
 
 lpa_status lpa_init(lpa_ctx **ctx, int device, void *stream, const lpa_options *opt) {
@@ -1984,7 +2035,7 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->cp_lab[0], &c->cp_lab[1], &c->cp_coef[0], &c->cp_coef[1], &c->cp_cnt[0], &c->cp_cnt[1],
                       &c->cp_best[0], &c->cp_best[1], &c->cp_rows, &c->cp_ovf, &c->cp_off, &c->cp_key, &c->cp_tal,
                       &c->cp_first, &c->cp_pieces, &c->cp_total, &c->cp_rows1, &c->cp_rows2,
-                      &c->cp_distinct};
+                      &c->cp_distinct, &c->cp_sfirst, &c->cp_slices, &c->cp_rowstate};
     if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) b->release();

@@ -46,7 +46,7 @@ class _Options(ctypes.Structure):
                 ("wide_max", ctypes.c_uint32), ("merge_max", ctypes.c_uint32), ("profile", ctypes.c_uint32),
                 ("modularity", ctypes.c_uint32), ("frontier", ctypes.c_uint32),
                 ("barrier_timeout_us", ctypes.c_uint32), ("order", ctypes.c_uint32), ("tie", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("reuse_csr", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):

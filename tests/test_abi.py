@@ -34,9 +34,9 @@ def test_default_options_and_strerror():
     o = lpa.default_options()
     assert o == {"self_weight": 1, "thread_max": 8, "group_max": 32, "wave_max": 128, "wide_max": 512, "merge_max": 512, "frontier": 0,
                  "profile": 0, "modularity": 0, "barrier_timeout_us": 0, "order": 0, "tie": 0,
-                 "seed": 0}
+                 "seed": 0, "reuse_csr": 0}
     lib = lpa.library()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.lpa_strerror(code)
     assert lib.lpa_strerror(-99) == b"unknown status"
 

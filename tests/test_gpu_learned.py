@@ -282,3 +282,35 @@ def test_trained_model_on_held_out_trace(torch_mod, gg, lpa, scale, seed, min_re
         f"rows skipped {skipped:.3f}, stable rows skipped {stable_skipped:.3f}")
     assert recall >= min_recall     # few changing rows missed
     assert stable_skipped >= 0.5     # most stable rows need no vote
+
+
+@pytest.mark.parametrize("kind", ["planted", "rmat"])
+def test_learned_quality_against_plain(torch_mod, gg, orc, lpa, kind):
+    """The committed network's runs against plain RAK on graphs it was not
+    trained on: modularity within 0.005 of the plain run's and NMI against
+    it reported.  Planted-partition graphs (the largest of a seeded
+    batch-style family, where the change rate falls below half and the
+    network is consulted) and R-MAT graphs, at tolerances 0.05 and 0.01."""
+    from paper_2301_09125_amd import train_frontier as TF
+    m = TF.load_model()
+    if kind == "planted":
+        b = gg.sbm_batch(64, 2000, 200000, seed=7)
+        graphs = [b.graph(int(k)) for k in np.argsort(np.diff(b.gv))[-4:]]
+    else:
+        graphs = [gg.rmat(s, 16, 0.57, 0.19, 0.19, seed=s + 100) for s in (18, 20)]
+    with lpa.Context(0, modularity=1) as c, lpa.Context(0, modularity=1) as lc:
+        for g in graphs:
+            dg = lpa.DeviceGraph.from_csr(g, "cuda")
+            for tol in (0.05, 0.01):
+                lab, st = c.run(dg, tol=tol, max_iter=20)
+                plain = lpa.labels_to_numpy(lab)
+                llab, lst, _ = lc.run_learned(dg, m, tol=tol, max_iter=20)
+                learned = lpa.labels_to_numpy(llab)
+                dq = lst.modularity - st.modularity
+                agree = orc.nmi(learned, plain)
+                say(f"{g.name} tol {tol}: plain {st.iterations} rounds Q {st.modularity:.5f}; learned "
+                    f"{lst.iterations} rounds ({lst.learned_rounds} learned) Q {lst.modularity:.5f}, "
+                    f"dQ {dq:+.5f}, NMI vs plain {agree:.4f}")
+                assert abs(dq) <= 0.005
+                assert lst.converged and lst.changed_last <= int(np.floor(tol * g.n))
+                assert agree > 0.85

@@ -474,3 +474,35 @@ def test_modes_unsupported_combinations(gg, lpa):
         with pytest.raises(lpa.LpaError) as ei:
             c.run_batch(lpa.DeviceGraph.from_csr(b.csr, "cuda"), b.gv)
         assert ei.value.code == lpa.LPA_EUNSUPPORTED
+
+
+def test_reuse_csr_equals_fresh(gg, orc, lpa):
+    """reuse_csr keeps the binned, relabelled copy between calls on the same
+    CSR (round 1 then runs in the round kernels): every call still equals
+    the oracle, across graphs that replace the copy, resumes, modes and the
+    reported modularity."""
+    gs = [gg.with_weights(gg.rmat(14, seed=31), 4, 1, 6), gg.rmat(15, seed=9), gg.sbm(2000, 20, 0.1, 0.005, seed=3)]
+    dgs = [dev(lpa, g) for g in gs]
+    with lpa.Context(0, reuse_csr=1, modularity=1) as c:
+        for rep in range(2):
+            for g, dg in zip(gs, dgs):
+                for _ in range(2):  # the second call reuses the copy
+                    ref = orc.rak(g, tol=0.05, max_iter=20, self_weight=1)
+                    lab, st = c.run(dg, tol=0.05, max_iter=20)
+                    got = lpa.labels_to_numpy(lab)
+                    assert st.changed == ref.changed and np.array_equal(got, ref.labels), (g.name, rep)
+                    m = orc.modularity(g, ref.labels)
+                    assert st.mod_terms == {"two_m": m.two_m, "sigma_in": m.sigma_in, "sum_k2": m.sum_k2}
+        # resume through the kept copy: 2 rounds, then the rest
+        g, dg = gs[1], dgs[1]
+        lab, st1 = c.run(dg, tol=0.05, max_iter=2)
+        lab, st2 = c.run_resume(dg, lab, tol=0.05, max_iter=20)
+        ref = orc.rak(g, tol=0.05, max_iter=2, self_weight=1)
+        ref = orc.rak(g, tol=0.05, max_iter=20, self_weight=1, init_labels=ref.labels)
+        assert np.array_equal(lpa.labels_to_numpy(lab), ref.labels) and st2.changed == ref.changed
+    for order, tie in (("semisync", "lowest"), ("sync", "hash")):
+        with lpa.Context(0, reuse_csr=1, order=ORDER[order], tie=TIE[tie], seed=4) as c:
+            for _ in range(2):
+                lab, st = c.run(dgs[0], tol=0.0, max_iter=8)
+                ref = orc.rak_ext(gs[0], tol=0.0, max_iter=8, self_weight=1, order=order, tie=tie, seed=4)
+                assert st.changed == ref.changed and np.array_equal(lpa.labels_to_numpy(lab), ref.labels)
