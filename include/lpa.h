@@ -244,10 +244,12 @@ lpa_status lpa_modularity(lpa_ctx *ctx, const lpa_csr *g, const uint32_t *labels
  * labels_out: device u32[n], the best label of every vertex (the disjoint
  * result).  state_labels / state_coefs: device u32[n * max_labels] or NULL:
  * vertex v's kept pairs in slots v * max_labels + i, i < state_count[v],
- * labels increasing; state_count: device u32[n] or NULL.  The CSR is read
- * as stored (no relabelled copy); the context holds about
- * 16 * max_labels + 20 bytes per vertex of state, and tables in device
- * memory for rows whose distinct labels outgrow the on-chip table (at most
+ * labels increasing (slots past state_count[v] are left as they were);
+ * state_count: device u32[n] or NULL.  The CSR is read as stored (no
+ * relabelled copy); the context holds two state records per vertex of
+ * 2 + 2 * max_labels u32 words rounded up to a power of two up to 128 bytes
+ * (64 bytes each for max_labels 4), and tables in device memory for rows
+ * whose distinct labels outgrow the on-chip table (at most
  * 24 * deg * max_labels bytes for such a row).  stats: as lpa_run (changed
  * counts are best-label changes; arcs_processed = m per round; with
  * options.modularity the modularity of labels_out).  Errors: as lpa_run,

@@ -6,15 +6,19 @@
 
 namespace lpa {
 
-// One COPRA half-round (lpa_copra.hip) on the caller's CSR: the state of
-// the round before (lab/coef: V slots per vertex, cnt valid slots, best
-// label) and the state written.  half 0 = every vertex votes; 1 / 2 = only
-// the vertices whose draw names that half, the others copy their state.
+// One COPRA half-round (lpa_copra.hip) on the caller's CSR.  The state of
+// vertex v is one record of `stride` u32 words at v * stride: word 0 the
+// count of kept labels, word 1 the best label, then (label, coefficient)
+// pairs, so that a neighbour's whole state is one gather of one line.
+// `in` is the state of the round before, `out` the state written.  half 0 =
+// every vertex votes; 1 / 2 = only the vertices whose draw names that half,
+// the others copy their record.
 struct CopraArgs {
     Graph g;
-    uint32_t V;  // max_labels, 1..64
-    const uint32_t *lab_in, *coef_in, *cnt_in, *best_in;
-    uint32_t *lab_out, *coef_out, *cnt_out, *best_out;
+    uint32_t V;       // max_labels, 1..64
+    uint32_t stride;  // u32 words per record (2 + 2 V rounded up)
+    const uint32_t *in;
+    uint32_t *out;
     uint32_t t, half, tie;
     unsigned long long seed;
     unsigned long long *changed;  // kCountWords counter words: best labels changed
@@ -24,6 +28,16 @@ struct CopraArgs {
     uint32_t first;               // every vertex is still alone (round 1, first half)
     const uint8_t *distinct;      // per row: its neighbours are listed once
 };
+
+// Words per state record: 2 + 2 V rounded up to a power of two up to 32
+// words (one 128-byte line holds the record), to a multiple of 32 beyond.
+inline uint32_t copra_stride(uint32_t V) {
+    const uint32_t w = 2 + 2 * V;
+    if (w > 32) return (w + 31) / 32 * 32;
+    uint32_t p = 1;
+    while (p < w) p <<= 1;
+    return p;
+}
 
 // A piece of a COPRA row voted through a device-memory table: arcs
 // [b0, b1) of row rows[i].
@@ -36,10 +50,16 @@ struct CopraPiece {
 // ---- launchers: lpa_copra.hip --------------------------------------------
 // Check a caller's CSR (row_ptr, col < n, weighted degrees < 2^32) into
 // err; distinct (u8[n] or NULL) receives whether each row's neighbours are
-// strictly increasing.
-hipError_t launch_csr_check(const Graph &g, uint32_t *err, uint8_t *distinct, hipStream_t s);
-hipError_t launch_copra_init(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best,
-                             hipStream_t s);
+// strictly increasing; wsum: u64[n] scratch for the rows longer than
+// kHeadArcs arcs.
+hipError_t launch_csr_check(const Graph &g, uint32_t *err, uint8_t *distinct, unsigned long long *wsum,
+                            hipStream_t s);
+// Every vertex alone with belonging 1, in the records of `rec`.
+hipError_t launch_copra_init(uint32_t n, uint32_t stride, uint32_t *rec, hipStream_t s);
+// Records to the caller's arrays: best labels, and (when not NULL) the kept
+// labels and coefficients (V slots per vertex) and their counts.
+hipError_t launch_copra_output(const uint32_t *rec, uint32_t n, uint32_t V, uint32_t stride, uint32_t *best,
+                               uint32_t *labs, uint32_t *coefs, uint32_t *cnt, hipStream_t s);
 // Rows with arcs by class into rows0 (deg * V <= 32), rows1 (<= 512) and
 // rows2 (larger), count[0..3) (zeroed by the caller).
 hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,

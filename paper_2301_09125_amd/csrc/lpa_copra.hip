@@ -17,9 +17,10 @@
 // collects nothing (no arcs) is its own community.  Kept labels are stored
 // in increasing label order.
 //
-// State: lab / coef u32[n * V] (slot i of vertex v at v * V + i, the first
-// cnt[v] slots valid), cnt u32[n], best u32[n], double-buffered.  The rounds
-// read the caller's CSR directly (original ids, no relabelled copy):
+// State: one record per vertex (count, best label, then up to V (label,
+// coefficient) pairs; a power-of-two number of words up to 128 bytes, so a
+// neighbour's state is one line), double-buffered.  The rounds read the
+// caller's CSR directly (original ids, no relabelled copy):
 //   copra_group_k  rows with deg * V <= 32: 16 lanes per row, a 64-slot
 //                  LDS table;
 //   copra_wave_k   rows with deg * V <= 512: one wavefront per row, an LDS
@@ -39,7 +40,7 @@
 // copies its state in the other.
 
 #include "lpa_copra.h"
-#include "lpa_device.h"
+#include "lpa_rows.h"
 
 namespace lpa {
 
@@ -81,21 +82,21 @@ __device__ __forceinline__ int copra_insert_bounded(uint32_t *key, u64 *tal, uin
 // Copy vertex v's state unchanged (the other half of a semi-synchronous round).
 __device__ __forceinline__ void copra_copy(const CopraArgs &a, uint32_t v, uint32_t lane, uint32_t lanes) {
     for (uint32_t i = lane; i < a.V; i += lanes) {
-        a.lab_out[(u64)v * a.V + i] = a.lab_in[(u64)v * a.V + i];
-        a.coef_out[(u64)v * a.V + i] = a.coef_in[(u64)v * a.V + i];
+        a.out[(u64)v * a.stride + 2 + 2 * i] = a.in[(u64)v * a.stride + 2 + 2 * i];
+        a.out[(u64)v * a.stride + 3 + 2 * i] = a.in[(u64)v * a.stride + 3 + 2 * i];
     }
     if (lane == 0) {
-        a.cnt_out[v] = a.cnt_in[v];
-        a.best_out[v] = a.best_in[v];
+        a.out[(u64)v * a.stride] = a.in[(u64)v * a.stride];
+        a.out[(u64)v * a.stride + 1] = a.in[(u64)v * a.stride + 1];
     }
 }
 
 // A vertex with nothing to collect: its own community.
 __device__ __forceinline__ void copra_alone(const CopraArgs &a, uint32_t v, uint32_t lab) {
-    a.lab_out[(u64)v * a.V] = lab;
-    a.coef_out[(u64)v * a.V] = kOne;
-    a.cnt_out[v] = 1;
-    a.best_out[v] = lab;
+    a.out[(u64)v * a.stride + 2] = lab;
+    a.out[(u64)v * a.stride + 3] = kOne;
+    a.out[(u64)v * a.stride] = 1;
+    a.out[(u64)v * a.stride + 1] = lab;
 }
 
 // Write the kept labels klab[0..kn) (coefficients before the remainder in
@@ -111,12 +112,12 @@ __device__ __forceinline__ void copra_store(const CopraArgs &a, uint32_t v, uint
     for (uint32_t j = 0; j < kn; ++j) rank += klab[j] < l;
     if (mine && l == best) c += kOne - given;
     if (mine) {
-        a.lab_out[(u64)v * a.V + rank] = l;
-        a.coef_out[(u64)v * a.V + rank] = c;
+        a.out[(u64)v * a.stride + 2 + 2 * rank] = l;
+        a.out[(u64)v * a.stride + 3 + 2 * rank] = c;
     }
     if (lane == 0) {
-        a.cnt_out[v] = kn;
-        a.best_out[v] = best;
+        a.out[(u64)v * a.stride] = kn;
+        a.out[(u64)v * a.stride + 1] = best;
     }
 }
 
@@ -157,11 +158,11 @@ __global__ __launch_bounds__(256) void copra_group_k(CopraArgs a, const uint32_t
             const bool in = k < e;
             const uint32_t u = in ? a.g.col[k] : 0u;
             const uint32_t we = in ? (a.g.w ? a.g.w[k] : 1u) : 0u;
-            const uint32_t c = in ? a.cnt_in[u] : 0u;
+            const uint32_t c = in ? a.in[(u64)u * a.stride] : 0u;
             tw += we;
             for (uint32_t i = 0; i < c; ++i)
-                if (copra_insert_bounded(key, tal, kCopraGroupSlots - 1, a.lab_in[(u64)u * V + i],
-                                         (u64)we * a.coef_in[(u64)u * V + i]) < 0)
+                if (copra_insert_bounded(key, tal, kCopraGroupSlots - 1, a.in[(u64)u * a.stride + 2 + 2 * i],
+                                         (u64)we * a.in[(u64)u * a.stride + 3 + 2 * i]) < 0)
                     atomicOr(a.err, ERR_TABLE);  // cannot happen: at most 32 entries
         }
         wave_sync();
@@ -209,15 +210,15 @@ __global__ __launch_bounds__(256) void copra_group_k(CopraArgs a, const uint32_t
                 uint32_t rank = 0;
                 for (uint32_t q = 0; q < kn; ++q) rank += sklab[grp][q] < l;
                 if (l == best) c += kOne - given;
-                a.lab_out[(u64)v * V + rank] = l;
-                a.coef_out[(u64)v * V + rank] = c;
+                a.out[(u64)v * a.stride + 2 + 2 * rank] = l;
+                a.out[(u64)v * a.stride + 3 + 2 * rank] = c;
             }
             if (gl == 0) {
-                a.cnt_out[v] = kn;
-                a.best_out[v] = best;
+                a.out[(u64)v * a.stride] = kn;
+                a.out[(u64)v * a.stride + 1] = best;
             }
         }
-        if (on && gl == 0) chg += a.best_in[v] != best;
+        if (on && gl == 0) chg += a.in[(u64)v * a.stride + 1] != best;
         wave_sync();  // the tables are cleared for the next rows
     }
     block_count(chg, a.changed);
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(256) void copra_wave_k(CopraArgs a, const uint32_t 
             copra_copy(a, v, lane, 64);
             continue;
         }
-        const uint32_t old_best = a.best_in[v];
+        const uint32_t old_best = a.in[(u64)v * a.stride + 1];
         const Tie tie = copra_tie(a, v);
         const uint32_t S = next_pow2((uint32_t)(2 * deg * V));
         for (uint32_t s = lane; s < S; s += 64) {
@@ -257,11 +258,11 @@ __global__ __launch_bounds__(256) void copra_wave_k(CopraArgs a, const uint32_t 
             const bool in = k < e;
             const uint32_t u = in ? a.g.col[k] : 0u;
             const uint32_t we = in ? (a.g.w ? a.g.w[k] : 1u) : 0u;
-            const uint32_t c = in ? a.cnt_in[u] : 0u;
+            const uint32_t c = in ? a.in[(u64)u * a.stride] : 0u;
             tw += we;
             for (uint32_t i = 0; i < c; ++i)
-                if (copra_insert_bounded(key, tal, S - 1, a.lab_in[(u64)u * V + i],
-                                         (u64)we * a.coef_in[(u64)u * V + i]) < 0)
+                if (copra_insert_bounded(key, tal, S - 1, a.in[(u64)u * a.stride + 2 + 2 * i],
+                                         (u64)we * a.in[(u64)u * a.stride + 3 + 2 * i]) < 0)
                     atomicOr(a.err, ERR_TABLE);  // cannot happen: distinct labels <= deg * V <= S / 2
         }
         wave_sync();
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
             // w(v,u) * 2^16, so the row is decided without a table
             if (threadIdx.x == 0) kn = 0;
             const uint32_t best = copra_first_block(a, v, tie, red, klab, kcoef, &kn);
-            if (threadIdx.x == 0) chg += a.best_in[v] != best;
+            if (threadIdx.x == 0) chg += a.in[(u64)v * a.stride + 1] != best;
             __syncthreads();
             continue;
         }
@@ -439,13 +440,13 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
             tw += we;
             if (__atomic_load_n(&full, __ATOMIC_RELAXED)) continue;
             const uint32_t u = a.g.col[k];
-            const uint32_t c = a.cnt_in[u];
+            const uint32_t c = a.in[(u64)u * a.stride];
             for (uint32_t i = 0; i < c; ++i) {
                 // the table is given up once 3/4 of it is claimed (or a probe
                 // finds no slot): the row then goes to the device-memory table
                 if (__atomic_load_n(&full, __ATOMIC_RELAXED)) break;
-                const int r = copra_insert_bounded(key, tal, kCopraBlockSlots - 1, a.lab_in[(u64)u * V + i],
-                                                   (u64)we * a.coef_in[(u64)u * V + i]);
+                const int r = copra_insert_bounded(key, tal, kCopraBlockSlots - 1, a.in[(u64)u * a.stride + 2 + 2 * i],
+                                                   (u64)we * a.in[(u64)u * a.stride + 3 + 2 * i]);
                 if (r < 0 || (r > 0 && atomicAdd(&claimed, 1u) + 1 >= kCopraBlockFill)) {
                     __atomic_store_n(&full, 1u, __ATOMIC_RELAXED);
                     break;
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
         }
         const uint32_t best = copra_finish_block(a, v, tie, key, tal, kCopraBlockSlots, tw * kOne, red, klab, kcoef,
                                                  &kn);
-        if (threadIdx.x == 0) chg += a.best_in[v] != best;
+        if (threadIdx.x == 0) chg += a.in[(u64)v * a.stride + 1] != best;
         __syncthreads();  // tables and reductions are reused by the next row
     }
     block_count(chg, a.changed);
@@ -495,10 +496,10 @@ __global__ __launch_bounds__(256) void copra_gpiece_k(CopraArgs a, const CopraPi
             const uint32_t we = a.g.w ? a.g.w[k] : 1u;
             tw += we;
             const uint32_t u = a.g.col[k];
-            const uint32_t c = a.cnt_in[u];
+            const uint32_t c = a.in[(u64)u * a.stride];
             for (uint32_t i = 0; i < c; ++i) {
-                const uint32_t l = a.lab_in[(u64)u * V + i];
-                const u64 x = (u64)we * a.coef_in[(u64)u * V + i];
+                const uint32_t l = a.in[(u64)u * a.stride + 2 + 2 * i];
+                const u64 x = (u64)we * a.in[(u64)u * a.stride + 3 + 2 * i];
                 // a piece has at most 2048 entries: the LDS table never fills
                 if (copra_insert_bounded(key, tal, kCopraBlockSlots - 1, l, x) < 0 &&
                     copra_insert_bounded(slab_key + o, slab_tal + o, S - 1, l, x) < 0)
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(256) void copra_gdone_k(CopraArgs a, const uint32_t
             wave_sync();
             copra_store(a, v, lane, sklab[wave], skcoef[wave], kn, best);
         }
-        if (lane == 0) chg += a.best_in[v] != best;
+        if (lane == 0) chg += a.in[(u64)v * a.stride + 1] != best;
         wave_sync();
     }
     block_count(chg, a.changed);
@@ -637,38 +638,80 @@ __global__ void copra_pieces_k(Graph g, const uint32_t *rows, uint32_t count, co
 }
 
 // Every vertex its own community with belonging 1.
-__global__ void copra_init_k(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best) {
+__global__ void copra_init_k(uint32_t n, uint32_t stride, uint32_t *rec) {
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        lab[(u64)v * V] = v;
-        coef[(u64)v * V] = kOne;
-        cnt[v] = 1;
-        best[v] = v;
+        uint32_t *r = rec + (u64)v * stride;
+        r[0] = 1;
+        r[1] = v;
+        r[2] = v;
+        r[3] = kOne;
+    }
+}
+
+// Records to the caller's arrays (one thread per vertex).
+__global__ void copra_output_k(const uint32_t *rec, uint32_t n, uint32_t V, uint32_t stride, uint32_t *best,
+                               uint32_t *labs, uint32_t *coefs, uint32_t *cnt) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t *r = rec + (u64)v * stride;
+        best[v] = r[1];
+        if (cnt) cnt[v] = r[0];
+        for (uint32_t i = 0; i < r[0]; ++i) {
+            if (labs) labs[(u64)v * V + i] = r[2 + 2 * i];
+            if (coefs) coefs[(u64)v * V + i] = r[3 + 2 * i];
+        }
     }
 }
 
 // Rows by class, appended in any order (the result does not depend on it):
 // class 0 deg * V <= 32, class 1 <= 512, class 2 larger; rows without arcs
-// are in no list (their state never changes: both buffers hold it).
-// One atomic per wavefront and class.
-__global__ void copra_list_k(Graph g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,
-                             uint32_t *count) {
+// are in no list (their state never changes: both buffers hold it).  Each
+// block takes a contiguous run of vertices, counts its rows per class, takes
+// its three list ranges with one device atomic per class, then writes: a
+// few hundred atomics in all, not one per wavefront on three hot words.
+constexpr uint32_t kListBlocks = 1024;
+__device__ __forceinline__ int copra_class(const Graph &g, uint32_t V, uint32_t v) {
+    const uint64_t d = (g.rp[v + 1] - g.rp[v]) * V;
+    return d == 0 ? -1 : d <= 32 ? 0 : d <= 512 ? 1 : 2;
+}
+__global__ __launch_bounds__(256) void copra_list_k(Graph g, uint32_t V, uint32_t *rows0, uint32_t *rows1,
+                                                    uint32_t *rows2, uint32_t *count) {
+    __shared__ uint32_t cnt[3], base[3];
     const uint32_t lane = threadIdx.x & 63;
-    for (uint32_t base = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u; base < g.n;
-         base += gridDim.x * blockDim.x) {
-        const uint32_t v = base + lane;
-        const uint64_t d = v < g.n ? (g.rp[v + 1] - g.rp[v]) * V : 0;
-        const int cls = v >= g.n || d == 0 ? -1 : d <= 32 ? 0 : d <= 512 ? 1 : 2;
-        uint32_t *dst[3] = {rows0, rows1, rows2};
+    const uint32_t per = (g.n + gridDim.x - 1) / gridDim.x;
+    const uint32_t lo = blockIdx.x * per, hi = min(lo + per, g.n);
+    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t mine[3] = {0, 0, 0};
+    for (uint32_t v = lo + threadIdx.x; v < hi; v += 256) {
+        const int c = copra_class(g, V, v);
+        if (c >= 0) ++mine[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t t = wave_sum(mine[c]);
+        if (lane == 0 && t) atomicAdd(&cnt[c], t);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&count[threadIdx.x], cnt[threadIdx.x]) : 0u;
+        cnt[threadIdx.x] = 0;  // reused as this block's write cursor
+    }
+    __syncthreads();
+    uint32_t *dst[3] = {rows0, rows1, rows2};
+    for (uint32_t v0 = lo + (threadIdx.x & ~63u); v0 < hi; v0 += 256) {  // wavefront-uniform steps
+        const uint32_t v = v0 + lane;
+        const int cls = v < hi ? copra_class(g, V, v) : -1;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const u64 m = __ballot(cls == c);
             if (!m) continue;
             const int lead = __ffsll((long long)m) - 1;
             uint32_t at = 0;
-            if ((int)lane == lead) at = atomicAdd(&count[c], (uint32_t)__popcll(m));
+            if ((int)lane == lead) at = atomicAdd(&cnt[c], (uint32_t)__popcll(m));
             at = (uint32_t)__shfl((int)at, lead, 64);
-            if (cls == c) dst[c][at + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = v;
+            if (cls == c)
+                dst[c][base[c] + at +
+                       __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = v;
         }
     }
 }
@@ -694,7 +737,7 @@ __global__ void copra_sizes_k(Graph g, uint32_t V, const uint32_t *rows, uint32_
 // 2^32.  With `distinct`, also whether each row's neighbours are strictly
 // increasing (each listed once).  One wavefront per 64 rows: rows of at most 8 arcs one lane each,
 // longer rows by the whole wavefront.
-__global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err, uint8_t *distinct) {
+__global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err, uint8_t *distinct, u64 *wsum) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (blockIdx.x == 0 && threadIdx.x == 0 && (g.rp[0] != 0 || g.rp[g.n] != g.m)) atomicOr(err, ERR_ROWPTR);
@@ -729,9 +772,11 @@ __global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err, uint8
             const int j = __ffsll((long long)longm) - 1;
             longm &= longm - 1;
             const uint64_t bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
+            // the first kHeadArcs arcs here, the rest in csr_check_tail_k
+            const uint64_t eh = ej - bj > kHeadArcs ? bj + kHeadArcs : ej;
             u64 tw = 0;
             bool inc = true;
-            for (uint64_t k = bj + lane; k < ej; k += 64) {
+            for (uint64_t k = bj + lane; k < eh; k += 64) {
                 const uint32_t u = g.col[k];
                 bits |= u >= g.n ? ERR_COL : 0u;
                 inc &= k + 1 >= ej || u < g.col[k + 1];
@@ -740,27 +785,77 @@ __global__ __launch_bounds__(256) void csr_check_k(Graph g, uint32_t *err, uint8
             tw = wave_sum(tw);
             bits |= tw > 0xFFFFFFFFull ? ERR_WOVF : 0u;
             const bool all_inc = __ballot(!inc) == 0;
-            if (distinct && lane == 0) distinct[base + j] = all_inc;
+            if (lane == 0) {
+                if (distinct) distinct[base + j] = all_inc;
+                if (eh < ej) wsum[base + j] = tw;  // the tail adds the rest
+            }
         }
     }
     if (bits) atomicOr(err, bits);
 }
 
-hipError_t launch_csr_check(const Graph &g, uint32_t *err, uint8_t *distinct, hipStream_t s) {
+// The tails of rows longer than kHeadArcs (see mod_tail_k): col < n, each
+// neighbour once, and the weighted degree, completed by device atomics on
+// wsum (the adder that completes the row sees its total).
+__global__ __launch_bounds__(256) void csr_check_tail_k(Graph g, uint32_t *err, uint8_t *distinct, u64 *wsum) {
+    __shared__ BlockRed R;
+    __shared__ uint32_t srow;
+    const u64 m = g.m;
+    const u64 nchunks = (m + kHeadArcs - 1) / kHeadArcs;
+    uint32_t bits = 0;
+    for (u64 c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const u64 c0 = c * kHeadArcs, c1 = c0 + kHeadArcs < m ? c0 + kHeadArcs : m;
+        __syncthreads();  // every wave has read the previous chunk's srow
+        if (threadIdx.x == 0) srow = row_of_arc(g, c0);
+        __syncthreads();
+        const uint32_t r = srow;
+        const uint64_t b = g.rp[r], e = g.rp[r + 1];
+        if (b > e || e > m) continue;  // malformed row: flagged by csr_check_k
+        const uint64_t t0 = c0 > b + kHeadArcs ? c0 : b + kHeadArcs, t1 = c1 < e ? c1 : e;
+        if (t0 >= t1) continue;  // uniform: the chunk meets no tail
+        u64 tw = 0, z = 0, z2 = 0;
+        uint32_t viol = 0;
+        for (uint64_t k = t0 + threadIdx.x; k < t1; k += 256) {
+            const uint32_t u = g.col[k];
+            bits |= u >= g.n ? ERR_COL : 0u;
+            viol |= (k + 1 < e && u >= g.col[k + 1]) ? 1u : 0u;
+            tw += g.w ? g.w[k] : 1u;
+        }
+        block_reduce(R, z, tw, z2, viol);
+        if (threadIdx.x == 0) {
+            if (viol && distinct) distinct[r] = 0;
+            const u64 before = atomicAdd(&wsum[r], tw);
+            if (before + tw > 0xFFFFFFFFull) bits |= ERR_WOVF;
+        }
+    }
+    if (bits) atomicOr(err, bits);
+}
+
+hipError_t launch_csr_check(const Graph &g, uint32_t *err, uint8_t *distinct, u64 *wsum, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    csr_check_k<<<grid_for(g.n, 256, 4096), 256, 0, s>>>(g, err, distinct);
+    csr_check_k<<<grid_for(g.n, 256, 4096), 256, 0, s>>>(g, err, distinct, wsum);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && g.m > kHeadArcs) {
+        csr_check_tail_k<<<grid_for(g.m, kHeadArcs, 4096), 256, 0, s>>>(g, err, distinct, wsum);
+        e = hipGetLastError();
+    }
+    return e;
+}
+hipError_t launch_copra_init(uint32_t n, uint32_t stride, uint32_t *rec, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    copra_init_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, stride, rec);
     return hipGetLastError();
 }
-hipError_t launch_copra_init(uint32_t n, uint32_t V, uint32_t *lab, uint32_t *coef, uint32_t *cnt, uint32_t *best,
-                             hipStream_t s) {
+hipError_t launch_copra_output(const uint32_t *rec, uint32_t n, uint32_t V, uint32_t stride, uint32_t *best,
+                               uint32_t *labs, uint32_t *coefs, uint32_t *cnt, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    copra_init_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, V, lab, coef, cnt, best);
+    copra_output_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(rec, n, V, stride, best, labs, coefs, cnt);
     return hipGetLastError();
 }
 hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,
                              uint32_t *count, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    copra_list_k<<<grid_for(g.n, 256, 8192), 256, 0, s>>>(g, V, rows0, rows1, rows2, count);
+    copra_list_k<<<grid_for(g.n, 256, kListBlocks), 256, 0, s>>>(g, V, rows0, rows1, rows2, count);
     return hipGetLastError();
 }
 hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count, uint32_t per,

@@ -17,7 +17,7 @@
 // a symmetric graph carries the same term and is not visited).  K_c still
 // takes every vertex, and for unit weights its degree needs no arc at all.
 
-#include "lpa_device.h"
+#include "lpa_rows.h"
 
 namespace lpa {
 
@@ -336,7 +336,8 @@ __global__ __launch_bounds__(256) void mod_hub_k(ModArgs a, const HubItem *__res
 // Any row length, on a CSR as the caller stores it (no binning): each
 // wavefront takes 64 rows; rows of at most 32 arcs are summed one lane
 // each, longer rows by the whole wavefront in 512-arc steps, one row after
-// another.  The row bounds and labels are checked here (a bad row is
+// another, up to their first kHeadArcs arcs (mod_tail_k sums the rest, so
+// no wavefront walks a hub alone).  The row bounds and labels are checked here (a bad row is
 // skipped and flagged, a bad label counts as label 0 and is flagged), so no
 // access leaves the arrays whatever the input.
 __global__ __launch_bounds__(256) void mod_any_k(ModArgs a) {
@@ -371,15 +372,59 @@ __global__ __launch_bounds__(256) void mod_any_k(ModArgs a) {
             longm &= longm - 1;
             const uint32_t lj = (uint32_t)__shfl((int)lv, j, 64);
             const uint64_t bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
+            // the first kHeadArcs arcs here, the rest in mod_tail_k
+            const uint64_t eh = ej - bj > kHeadArcs ? bj + kHeadArcs : ej;
             u64 kw = 0;
-            for (uint64_t k0 = bj; k0 < ej; k0 += kWaveArcs)
-                mod_arcs<kWaveArcs / 64, 64>(a, k0 + lane, ej, lj, kw, sin);
+            for (uint64_t k0 = bj; k0 < eh; k0 += kWaveArcs)
+                mod_arcs<kWaveArcs / 64, 64>(a, k0 + lane, eh, lj, kw, sin);
             kw = wave_sum(kw);
             tw += lane == 0 ? kw : 0;
             add_community(M, a.K, lane == 0, lj, kw);
         }
     }
     mod_finish(a, M, tw, sin);
+}
+
+// The arcs of rows beyond their first kHeadArcs (mod_any_k took those), in
+// chunks of kHeadArcs arcs: a chunk meets the tail of at most one row (a
+// row that starts inside the chunk has its tail beyond it), found by a
+// binary search over row_ptr.  K of the row's label, 2m and Sigma_in take
+// the chunk's part with one device atomic each.
+__global__ __launch_bounds__(256) void mod_tail_k(ModArgs a) {
+    __shared__ BlockRed R;
+    __shared__ uint32_t srow;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = threadIdx.x >> 6;
+    const u64 m = a.g.m;
+    const u64 nchunks = (m + kHeadArcs - 1) / kHeadArcs;
+    u64 tw = 0, sin = 0;
+    for (u64 c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const u64 c0 = c * kHeadArcs, c1 = c0 + kHeadArcs < m ? c0 + kHeadArcs : m;
+        __syncthreads();  // every wave has read the previous chunk's srow
+        if (threadIdx.x == 0) srow = row_of_arc(a.g, c0);
+        __syncthreads();
+        const uint32_t r = srow;
+        const uint64_t b = a.g.rp[r], e = a.g.rp[r + 1] < m ? a.g.rp[r + 1] : m;
+        const uint64_t t0 = c0 > b + kHeadArcs ? c0 : b + kHeadArcs, t1 = c1 < e ? c1 : e;
+        if (t0 >= t1) continue;  // uniform: the chunk meets no tail
+        uint32_t lv = a.labels[r];
+        lv = lv >= a.g.n ? 0u : lv;  // flagged by mod_any_k
+        u64 kv = 0;
+        for (uint64_t k0 = t0 + wave * kWaveArcs; k0 < t1; k0 += 4 * kWaveArcs)
+            mod_arcs<kWaveArcs / 64, 64>(a, k0 + lane, t1, lv, kv, sin);
+        u64 z = 0, z2 = 0;
+        uint32_t zo = 0;
+        block_reduce(R, z, kv, z2, zo);
+        if (threadIdx.x == 0 && kv) {
+            atomicAdd(&a.K[lv], kv);
+            tw += kv;
+        }
+    }
+    sin = wave_sum(sin);
+    if (lane == 0) {
+        if (sin) atomicAdd(&a.sums[1], sin);
+        if (wave == 0 && tw) atomicAdd(&a.sums[0], tw);
+    }
 }
 
 // One block: the u128 sum of the partials of mod_sumsq_k, with the two sums
@@ -452,7 +497,12 @@ hipError_t launch_mod_hub(const ModArgs &a, const HubItem *items, uint32_t count
 hipError_t launch_mod_any(const ModArgs &a, hipStream_t s) {
     if (a.g.n == 0) return hipSuccess;
     mod_any_k<<<grid_for(a.g.n, 256, kModGrid), 256, 0, s>>>(a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && a.g.m > kHeadArcs) {
+        mod_tail_k<<<grid_for(a.g.m, kHeadArcs, kModGrid), 256, 0, s>>>(a);
+        e = hipGetLastError();
+    }
+    return e;
 }
 hipError_t launch_mod_final(const u64 *partials, uint32_t nparts, const u64 *sums, const uint32_t *err, u64 *out,
                             hipStream_t s) {

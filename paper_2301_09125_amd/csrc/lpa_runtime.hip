@@ -107,8 +107,9 @@ struct lpa_ctx {
     DevBuf f_top1, f_top2, f_kw, f_last, f_front, f_stale, f_lists, f_small, f_model;  // frontier runs
     DevBuf t_w, t_m, t_v, t_part, t_grad, t_loss, t_z;                               // training
     DevBuf tune_labels, tune_hist;                                                    // autotuner
-    DevBuf cp_lab[2], cp_coef[2], cp_cnt[2], cp_best[2], cp_rows, cp_ovf, cp_off, cp_key, cp_tal;  // COPRA
-    DevBuf cp_first, cp_pieces, cp_total, cp_rows1, cp_rows2, cp_distinct, cp_sfirst, cp_slices, cp_rowstate;
+    DevBuf cp_rec[2], cp_rows, cp_ovf, cp_off, cp_key, cp_tal;  // COPRA
+    DevBuf cp_first, cp_pieces, cp_total, cp_rows1, cp_rows2, cp_distinct, cp_sfirst, cp_slices, cp_rowstate,
+        cp_wsum;
     std::map<std::vector<int>, lpa_options> tune_cache;
     // the CSR and thresholds the internal copy was last built for by a
     // prepare() that also set up the long-row state (empty = none)
@@ -1453,25 +1454,19 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
     LPA_TRY(ensure_pinned(c, kCountWords + 32));
     HIP_TRY(launch_fill_u64(cw, 0, kCountWords + 8, s));
     HIP_TRY(c->cp_distinct.ensure(n));
-    HIP_TRY(launch_csr_check(G, err, c->cp_distinct.as<uint8_t>(), s));
+    HIP_TRY(c->cp_wsum.ensure((size_t)n * sizeof(u64)));
+    HIP_TRY(launch_csr_check(G, err, c->cp_distinct.as<uint8_t>(), c->cp_wsum.as<u64>(), s));
     HIP_TRY(hipMemcpyAsync(c->pinned, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (const uint32_t bits = reinterpret_cast<uint32_t *>(c->pinned)[0]) return err_status(bits);
 
-    const size_t slots = (size_t)n * V;
-    for (int b = 0; b < 2; ++b) {
-        HIP_TRY(c->cp_lab[b].ensure(slots * sizeof(uint32_t)));
-        HIP_TRY(c->cp_coef[b].ensure(slots * sizeof(uint32_t)));
-        HIP_TRY(c->cp_cnt[b].ensure((size_t)n * sizeof(uint32_t)));
-        HIP_TRY(c->cp_best[b].ensure((size_t)n * sizeof(uint32_t)));
-    }
+    const uint32_t stride = copra_stride(V);
+    for (int b = 0; b < 2; ++b) HIP_TRY(c->cp_rec[b].ensure((size_t)n * stride * sizeof(uint32_t)));
     HIP_TRY(c->cp_rows.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->cp_rows1.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->cp_rows2.ensure((size_t)n * sizeof(uint32_t)));
     // both buffers start alone: rows without arcs are never voted again
-    for (int b = 0; b < 2; ++b)
-        HIP_TRY(launch_copra_init(n, V, c->cp_lab[b].as<uint32_t>(), c->cp_coef[b].as<uint32_t>(),
-                                  c->cp_cnt[b].as<uint32_t>(), c->cp_best[b].as<uint32_t>(), s));
+    for (int b = 0; b < 2; ++b) HIP_TRY(launch_copra_init(n, stride, c->cp_rec[b].as<uint32_t>(), s));
     HIP_TRY(launch_copra_list(G, V, c->cp_rows.as<uint32_t>(), c->cp_rows1.as<uint32_t>(),
                               c->cp_rows2.as<uint32_t>(), list_count, s));
     HIP_TRY(hipMemcpyAsync(c->pinned, list_count, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -1500,14 +1495,9 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
             CopraArgs a;
             a.g = G;
             a.V = V;
-            a.lab_in = c->cp_lab[cur].as<uint32_t>();
-            a.coef_in = c->cp_coef[cur].as<uint32_t>();
-            a.cnt_in = c->cp_cnt[cur].as<uint32_t>();
-            a.best_in = c->cp_best[cur].as<uint32_t>();
-            a.lab_out = c->cp_lab[nx].as<uint32_t>();
-            a.coef_out = c->cp_coef[nx].as<uint32_t>();
-            a.cnt_out = c->cp_cnt[nx].as<uint32_t>();
-            a.best_out = c->cp_best[nx].as<uint32_t>();
+            a.stride = stride;
+            a.in = c->cp_rec[cur].as<uint32_t>();
+            a.out = c->cp_rec[nx].as<uint32_t>();
             a.t = t;
             a.half = semi ? h + 1 : 0;
             a.tie = c->opt.tie;
@@ -1606,13 +1596,8 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
             break;
         }
     }
-    HIP_TRY(hipMemcpyAsync(best_out, c->cp_best[cur].p, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    if (state_lab)
-        HIP_TRY(hipMemcpyAsync(state_lab, c->cp_lab[cur].p, slots * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    if (state_coef)
-        HIP_TRY(hipMemcpyAsync(state_coef, c->cp_coef[cur].p, slots * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    if (state_cnt)
-        HIP_TRY(hipMemcpyAsync(state_cnt, c->cp_cnt[cur].p, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_copra_output(c->cp_rec[cur].as<uint32_t>(), n, V, stride, best_out, state_lab, state_coef,
+                                state_cnt, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (c->opt.profile) collect_profile(c);
     double q = 0;
@@ -2032,10 +2017,9 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->f_top1, &c->f_top2, &c->f_kw, &c->f_last, &c->f_front, &c->f_stale, &c->f_lists,
                       &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
                       &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist,
-                      &c->cp_lab[0], &c->cp_lab[1], &c->cp_coef[0], &c->cp_coef[1], &c->cp_cnt[0], &c->cp_cnt[1],
-                      &c->cp_best[0], &c->cp_best[1], &c->cp_rows, &c->cp_ovf, &c->cp_off, &c->cp_key, &c->cp_tal,
+                      &c->cp_rec[0], &c->cp_rec[1], &c->cp_rows, &c->cp_ovf, &c->cp_off, &c->cp_key, &c->cp_tal,
                       &c->cp_first, &c->cp_pieces, &c->cp_total, &c->cp_rows1, &c->cp_rows2,
-                      &c->cp_distinct, &c->cp_sfirst, &c->cp_slices, &c->cp_rowstate};
+                      &c->cp_distinct, &c->cp_sfirst, &c->cp_slices, &c->cp_rowstate, &c->cp_wsum};
     if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) b->release();
