@@ -236,7 +236,7 @@ def gather_ceiling(args, g, P):
 # while they are unchanged.
 _COMMON_SRC = ["lpa_device.h", "lpa_internal.h"]
 KERNEL_SOURCES = {
-    "batch_k": ["lpa_batch.hip", "lpa_vote_dev.h"] + _COMMON_SRC,
+    "batch_k": ["lpa_batch.hip", "lpa_sortnet.h", "lpa_vote_dev.h"] + _COMMON_SRC,
     "copra": ["lpa_copra.hip", "lpa_copra.h", "lpa_rows.h"] + _COMMON_SRC,
 }
 VOTE_SOURCES = ["lpa_vote.hip", "lpa_vote_dev.h"] + _COMMON_SRC

@@ -306,8 +306,8 @@ typedef struct {
  *   graph_vptr[G] = packed->n (empty graphs are allowed).
  * labels_out: device u32[n]; vertex v of graph g receives its final label
  *   as a local id (global label - graph_vptr[g]).
- * Errors: those of lpa_run, LPA_EINVAL also for a malformed graph_vptr or
- * an arc leaving its graph, and LPA_ETIMEDOUT. */
+ * Errors: those of lpa_run, LPA_EINVAL also for a malformed graph_vptr,
+ * an arc leaving its graph or packed->n above 2^32 - 32, and LPA_ETIMEDOUT. */
 lpa_status lpa_run_batch(lpa_ctx *ctx, const lpa_csr *packed, const uint64_t *graph_vptr, uint32_t G,
                          uint32_t *labels_out, double tol, uint32_t max_iter, lpa_batch_stats *stats);
 

@@ -10,8 +10,8 @@
 // in the buffer its last round wrote, so every graph ends exactly as a run of
 // that graph alone.
 //
-// Work units: one row (long, wide and wavefront bins), four 16-lane rows
-// (group bin) or 64 one-lane rows (thread bin), never spanning two graphs.
+// Work units: one row (long, wide and wavefront bins) or 64 rows of one lane
+// each (thread and group bins), never spanning two graphs.
 // One launch of co-resident blocks; per round:
 //   phase A  for each bin, the units of the graphs still voting are split
 //            into equal contiguous ranges, one per wavefront; a wavefront
@@ -26,6 +26,7 @@
 // number; a wait longer than the time limit raises ERR_TIMEOUT and every
 // block leaves the kernel, so the launch always ends.
 
+#include "lpa_sortnet.h"
 #include "lpa_vote_dev.h"
 
 namespace lpa {
@@ -34,7 +35,7 @@ constexpr int kBatchThreads = 1024;
 constexpr int kBatchWaves = kBatchThreads / 64;
 
 // rows per work unit of each bin
-__device__ __forceinline__ uint32_t unit_rows(int b) { return b == BIN_THREAD ? 64u : (b == BIN_GROUP ? 4u : 1u); }
+__device__ __forceinline__ uint32_t unit_rows(int b) { return b == BIN_THREAD || b == BIN_GROUP ? 64u : 1u; }
 
 // Grid-wide barrier over `nblocks` co-resident blocks.  The waiting blocks
 // poll the generation word with relaxed loads and acquire once, after it
@@ -181,166 +182,264 @@ __device__ __forceinline__ void row_head(const RoundArgs &a, uint32_t v, bool ac
     re = act ? b1 : b0;
 }
 
-// NU thread units (64 one-lane rows each) at once: every load of every unit
-// is issued before any unit waits for one.  ch[k] = rows of unit k changed.
-template <int NU>
-__device__ void units_thread(const BatchArgs &b, const RoundArgs &a, const UnitPos (&up)[NU], bool round1,
-                             uint32_t (&ch)[NU]) {
-    constexpr int D = kThreadMaxCap;
-    const uint32_t lane = threadIdx.x & 63;
-    uint32_t v[NU], own[NU], u[NU][D], lab[NU][D], wt[NU][D], valid[NU];
-    uint64_t rb[NU], re[NU];
-    bool act[NU];
+// One row of d <= D arcs per lane.  The lane reads arcs o .. o + D - 1 of
+// the unit (from cb, the unit's first arc; o4 = 4 o): those past its row
+// belong to later rows or to the pad of kLaneArcPad arcs behind the CSR, and
+// are masked (neighbour 0, label 0xFFFFFFFF - j, weight 0).  The labels are
+// sorted in registers by Batcher's network (with their weights when W), then
+// read run by run in increasing label order, keeping the first run of the
+// largest tally: (bt, bl).  The own label's self weight is applied after the
+// scan, from its plain tally ow (own_hit: it occurs among the neighbours), so
+// the scan needs no per-arc test for it.  R1 (round 1): every column id is
+// checked (< n, inside graph g) and the weighted degree summed into rs.
+template <int D, bool W, bool R1>
+__device__ __forceinline__ uint32_t lane_vote(const BatchArgs &b, const RoundArgs &a, const uint32_t *cb,
+                                              const uint32_t *wb, uint32_t o4, uint32_t d, uint32_t own, uint32_t g,
+                                              u64 &rs) {
+    const uint32_t *cl = (const uint32_t *)((const char *)cb + o4);
+    uint32_t u[D], lab[D], wt[D];
+    // every read is in bounds (the pad), so none waits behind a branch
 #pragma unroll
-    for (int k = 0; k < NU; ++k) {
-        v[k] = up[k].v0 + lane;
-        act[k] = v[k] < up[k].end;
-        row_head(a, v[k], act[k], rb[k], re[k], own[k]);
+    for (int j = 0; j < D; ++j) {
+        const uint32_t x = cl[j];
+        u[j] = (uint32_t)j < d ? x : 0u;
     }
-#pragma unroll
-    for (int k = 0; k < NU; ++k) load_arcs<D, 1>(a, rb[k], re[k], u[k], wt[k], valid[k]);
-    if (round1) {
-#pragma unroll
-        for (int k = 0; k < NU; ++k) check_graph<D>(b, u[k], valid[k], up[k].g);
-    }
-#pragma unroll
-    for (int k = 0; k < NU; ++k) gather_labels<D>(a, u[k], valid[k], lab[k]);
-#pragma unroll
-    for (int k = 0; k < NU; ++k) {
-        u64 rs = a.sw;
-        uint32_t tl[D];
+    if constexpr (W) {
+        const uint32_t *wl = (const uint32_t *)((const char *)wb + o4);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            rs += wt[k][j];
-            tl[j] = wt[k][j] + (lab[k][j] == own[k] ? a.sw : 0u);
+            const uint32_t x = wl[j];
+            wt[j] = (uint32_t)j < d ? x : 0u;
         }
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-#pragma unroll
-            for (int i = j + 1; i < D; ++i)
-                if (lab[k][j] == lab[k][i]) {
-                    tl[j] += wt[k][i];
-                    tl[i] += wt[k][j];
-                }
-        u64 best = a.sw ? vote_key(kStrict, own[k], a.sw) : 0ull;
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-            if (valid[k] >> j & 1u) best = umax64(best, vote_key(kStrict, lab[k][j], tl[j]));
-        bool c = false;
-        if (act[k]) {
-            const uint32_t nl = best ? key_label(kStrict, best) : own[k];
-            a.L_new[v[k]] = nl;
-            c = nl != own[k];
-            if (round1 && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
-        }
-        ch[k] = (uint32_t)__popcll(__ballot(c));
     }
+    if constexpr (R1) {
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            bad |= u[j] >= a.g.n;
+            u[j] = u[j] >= a.g.n ? 0u : u[j];
+        }
+        if (bad) atomicOr(a.err, ERR_COL);
+        check_graph<D>(b, u, d >= 32 ? 0xFFFFFFFFu : (1u << d) - 1u, g);
+#pragma unroll
+        for (int j = 0; j < D; ++j) rs += W ? wt[j] : ((uint32_t)j < d ? 1u : 0u);
+    }
+    uint32_t ow = 0;
+    bool own_hit = false;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const uint32_t x = a.L_old[u[j]];
+        lab[j] = (uint32_t)j < d ? x : 0xFFFFFFFFu - (uint32_t)j;
+        const bool mine = lab[j] == own;
+        own_hit |= mine;
+        ow += mine ? (W ? wt[j] : 1u) : 0u;
+    }
+    constexpr SortNet net = SortNetFor<D>::net;
+#pragma unroll
+    for (int c = 0; c < net.n; ++c) {
+        const int i = net.a[c], k = net.b[c];
+        if constexpr (W) {
+            const bool s = lab[k] < lab[i];
+            const uint32_t li = s ? lab[k] : lab[i], lk = s ? lab[i] : lab[k];
+            const uint32_t wi = s ? wt[k] : wt[i], wk = s ? wt[i] : wt[k];
+            lab[i] = li;
+            lab[k] = lk;
+            wt[i] = wi;
+            wt[k] = wk;
+        } else {
+            const uint32_t lo = lab[i] < lab[k] ? lab[i] : lab[k], hi = lab[i] < lab[k] ? lab[k] : lab[i];
+            lab[i] = lo;
+            lab[k] = hi;
+        }
+    }
+    // Tallies fit 32 bits: round 1 rejects rows whose weights and self weight
+    // sum past them.  The distinct pad labels tally 1 (0 when W) and come
+    // after every real label, so they never win while the row has an arc.
+    uint32_t bt = 0, bl = 0, run = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const bool same = j > 0 && lab[j] == lab[j > 0 ? j - 1 : 0];
+        run = (same ? run : 0u) + (W ? wt[j] : 1u);
+        const bool gt = run > bt;
+        bt = gt ? run : bt;
+        bl = gt ? lab[j] : bl;
+    }
+    if (d == 0) return own;                 // no arcs: the label stays
+    if (W && bt == 0) bl = lab[0];          // every tally 0: the lowest label
+    if (bl == own) return own;
+    const uint32_t ot = ow + a.sw;          // the own label with its self weight
+    if ((own_hit || a.sw) && (ot > bt || (ot == bt && own < bl))) return own;
+    return bl;
 }
 
-// NU group units (four 16-lane rows each) at once: the loads of every unit
-// are in flight together, then each unit tallies in the groups' tables T.
-template <int NU>
-__device__ void units_group(const BatchArgs &b, const RoundArgs &a, u64 *T, const UnitPos (&up)[NU], bool round1,
-                            uint32_t (&ch)[NU]) {
-    constexpr int G = kGroupLanes, CAP = kGroupSlots, A = CAP / (2 * G);
-    static_assert(G == 16, "a group is one DPP row");
-    const uint32_t lane = threadIdx.x & 63, gl = lane & (G - 1);
-    u64 *Tg = T + (lane / G) * CAP;
-    uint32_t v[NU], own[NU], u[NU][A], lab[NU][A], wt[NU][A], valid[NU];
-    uint64_t rb[NU], re[NU];
-    bool act[NU];
+// Unweighted one-lane units stage their labels in the wavefront's LDS:
+// 64 rows of at most 32 arcs, so at most kLaneStage labels.
+constexpr int kLaneStage = 64 * kSortNetMax;
+
+// The labels of the unit's arcs B .. B + nA - 1 (nA >= 1), read 64
+// consecutive arcs per pass (lanes past the end repeat the last arc) into
+// stage[0 .. nA).  R1: every column id is checked (< n, inside graph g).
+template <bool R1>
+__device__ __forceinline__ void stage_labels(const BatchArgs &b, const RoundArgs &a, const uint32_t *cb, uint32_t nA,
+                                             uint32_t g, uint32_t *stage) {
+    constexpr int P = 4;  // passes in flight
+    const uint32_t lane = threadIdx.x & 63;
+    bool bad_col = false, bad_graph = false;
+    for (uint32_t q0 = 0; q0 < nA; q0 += 64 * P) {
+        uint32_t q[P], u[P], x[P];
 #pragma unroll
-    for (int k = 0; k < NU; ++k) {
-        v[k] = up[k].v0 + lane / G;
-        act[k] = v[k] < up[k].end;
-        row_head(a, v[k], act[k], rb[k], re[k], own[k]);
-    }
+        for (int p = 0; p < P; ++p) {
+            q[p] = q0 + (uint32_t)p * 64u + lane;
+            q[p] = q[p] < nA ? q[p] : nA - 1;
+            u[p] = cb[q[p]];
+        }
+        if constexpr (R1) {
+            uint32_t gj[P];
 #pragma unroll
-    for (int k = 0; k < NU; ++k) load_arcs<A, G>(a, rb[k] + gl, re[k], u[k], wt[k], valid[k]);
-    if (round1) {
-#pragma unroll
-        for (int k = 0; k < NU; ++k) check_graph<A>(b, u[k], valid[k], up[k].g);
-    }
-#pragma unroll
-    for (int k = 0; k < NU; ++k) gather_labels<A>(a, u[k], valid[k], lab[k]);
-#pragma unroll
-    for (int k = 0; k < NU; ++k) {
-        u64 own_w = 0, rs = 0;
-        uint32_t own_hit = 0, rem = 0;
-        split_own<A>(lab[k], wt[k], valid[k], own[k], own_w, own_hit, rem, rs);
-        uint32_t S = next_pow2(2u * (uint32_t)(re[k] - rb[k]));
-        S = S < (uint32_t)G ? (uint32_t)G : (S > (uint32_t)CAP ? (uint32_t)CAP : S);
-#pragma unroll
-        for (int j = 0; j < A; ++j)
-            if (rem >> j & 1u) lds_insert(Tg, S - 1, lab[k][j], wt[k][j]);
-        wave_sync();
-        u64 best = 0;
-        for (uint32_t s = gl; s < S; s += G) {
-            const u64 x = Tg[s];
-            if (x != EMPTY_SLOT) {
-                best = umax64(best, slot_key(kStrict, x));
-                Tg[s] = EMPTY_SLOT;
+            for (int p = 0; p < P; ++p) {
+                bad_col |= u[p] >= a.g.n;
+                u[p] = u[p] >= a.g.n ? 0u : u[p];
+                gj[p] = b.gid[u[p]];
             }
+#pragma unroll
+            for (int p = 0; p < P; ++p) bad_graph |= gj[p] != g;
         }
-        best = row_max64(best);
-        own_w = row_sum64(own_w);
-        own_hit = row_sum32(own_hit);
-        rs = row_sum64(rs);
-        bool c = false;
-        if (act[k] && gl == 0) {
-            if (own_hit || a.sw) best = umax64(best, vote_key(kStrict, own[k], own_w + a.sw));
-            const uint32_t nl = best ? key_label(kStrict, best) : own[k];
-            a.L_new[v[k]] = nl;
-            c = nl != own[k];
-            if (round1 && rs + a.sw > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
-        }
-        wave_sync();
-        ch[k] = (uint32_t)__popcll(__ballot(c));
+#pragma unroll
+        for (int p = 0; p < P; ++p) x[p] = a.L_old[u[p]];
+#pragma unroll
+        for (int p = 0; p < P; ++p) stage[q[p]] = x[p];
+    }
+    if constexpr (R1) {
+        if (bad_col) atomicOr(a.err, ERR_COL);
+        if (bad_graph) atomicOr(b.err, ERR_GRAPH);
     }
 }
 
-// Units i0 .. i1-1 of the thread (GROUP = false) or group bin, NU at a time
-// (a unit past i1 is empty); changed counts go to each unit's graph, one
-// atomic per run of units of one graph.  (g, p0, p1, lo, end): the segment
-// of unit i0, as run_bin found it.
-template <int NU, bool GROUP>
+// lane_vote for an unweighted row whose labels sit in the LDS stage from
+// sl on (sl[j], j < d; what follows belongs to later rows or is stale, and
+// is masked as in lane_vote).
+template <int D>
+__device__ __forceinline__ uint32_t lane_vote_lds(const RoundArgs &a, const uint32_t *sl, uint32_t d, uint32_t own) {
+    uint32_t lab[D];
+    uint32_t ow = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const uint32_t x = sl[j];
+        lab[j] = (uint32_t)j < d ? x : 0xFFFFFFFFu - (uint32_t)j;
+        ow += lab[j] == own ? 1u : 0u;
+    }
+    constexpr SortNet net = SortNetFor<D>::net;
+#pragma unroll
+    for (int c = 0; c < net.n; ++c) {
+        const int i = net.a[c], k = net.b[c];
+        const uint32_t lo = lab[i] < lab[k] ? lab[i] : lab[k], hi = lab[i] < lab[k] ? lab[k] : lab[i];
+        lab[i] = lo;
+        lab[k] = hi;
+    }
+    uint32_t bt = 0, bl = 0, run = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const bool same = j > 0 && lab[j] == lab[j > 0 ? j - 1 : 0];
+        run = (same ? run : 0u) + 1u;
+        const bool gt = run > bt;
+        bt = gt ? run : bt;
+        bl = gt ? lab[j] : bl;
+    }
+    if (d == 0) return own;
+    if (bl == own) return own;
+    const uint32_t ot = ow + a.sw;
+    if ((ow || a.sw) && (ot > bt || (ot == bt && own < bl))) return own;
+    return bl;
+}
+
+// One unit of the thread or group bin: 64 rows, one per lane, each voted by
+// lane_vote (lane_vote_lds when unweighted) with the smallest network that
+// holds the unit's longest row (the bin bounds it by group_max <= 32; the
+// weighted round 1 takes the 32-input one).  T: the wavefront's LDS (at
+// least kLaneStage words plus kSortNetMax of slack behind the last one).
+template <bool W>
+__device__ uint32_t unit_lanes(const BatchArgs &b, const RoundArgs &a, u64 *T, const UnitPos &up, bool round1) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t v = up.v0 + lane;
+    const bool act = v < up.end;
+    uint64_t rb, re;
+    uint32_t own;
+    row_head(a, v, act, rb, re, own);
+    // the unit's rows hold at most 64 * 32 arcs from B on (lane 0's row is
+    // always one of them)
+    const uint64_t B = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(rb >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)rb);
+    const uint32_t d = (uint32_t)(re - rb);
+    const uint32_t o = act ? (uint32_t)(rb - B) : 0u;
+    const uint32_t *cb = a.g.col + B;
+    uint32_t nl;
+    u64 rs = a.sw;
+    if constexpr (!W) {
+        const uint32_t last = (up.end - up.v0 < 64u ? up.end - up.v0 : 64u) - 1u;
+        const uint32_t nA = (uint32_t)(a.g.rp[up.v0 + last + 1] - B);
+        uint32_t *stage = reinterpret_cast<uint32_t *>(T);
+        wave_sync();  // the previous unit's reads of the stage are done
+        if (nA) {
+            if (round1)
+                stage_labels<true>(b, a, cb, nA, up.g, stage);
+            else
+                stage_labels<false>(b, a, cb, nA, up.g, stage);
+        }
+        wave_sync();
+        const uint32_t *sl = stage + o;
+        if (__ballot(d > 16)) {
+            if (!__ballot(d > 24))
+                nl = lane_vote_lds<24>(a, sl, d, own);
+            else
+                nl = lane_vote_lds<32>(a, sl, d, own);
+        } else if (__ballot(d > 8)) {
+            nl = lane_vote_lds<16>(a, sl, d, own);
+        } else if (__ballot(d > 4)) {
+            nl = lane_vote_lds<8>(a, sl, d, own);
+        } else {
+            nl = lane_vote_lds<4>(a, sl, d, own);
+        }
+    } else {
+        const uint32_t o4 = o * 4u;
+        const uint32_t *wb = a.g.w + B;
+        if (round1)
+            nl = lane_vote<32, W, true>(b, a, cb, wb, o4, d, own, up.g, rs);
+        else if (__ballot(d > 16))
+            nl = lane_vote<32, W, false>(b, a, cb, wb, o4, d, own, up.g, rs);
+        else
+            nl = lane_vote<16, W, false>(b, a, cb, wb, o4, d, own, up.g, rs);
+    }
+    bool c = false;
+    if (act) {
+        a.L_new[v] = nl;
+        c = nl != own;
+        if (round1 && rs > 0xFFFFFFFFull) atomicOr(a.err, ERR_WOVF);
+    }
+    return (uint32_t)__popcll(__ballot(c));
+}
+
+// Units i0 .. i1-1 of the thread or group bin (64 rows each, one per lane);
+// changed counts go to each unit's graph, one atomic per run of units of
+// one graph.  (g, p0, p1, lo, end): the segment of unit i0, as run_bin found
+// it.
 __device__ void run_units(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, const uint32_t *pref, uint32_t i0,
                           uint32_t i1, uint32_t g, uint32_t p0, uint32_t p1, uint32_t lo, uint32_t end, bool round1) {
-    const uint32_t R = unit_rows(bin);
     uint32_t gacc = g, wch = 0;
-    for (uint32_t i = i0; i < i1; i += NU) {
-        UnitPos up[NU];
-#pragma unroll
-        for (int k = 0; k < NU; ++k) {
-            const uint32_t ik = i + k;
-            if (ik < i1) {
-                while (ik >= p1) {  // next segment that has units this round
-                    ++g;
-                    p0 = p1;
-                    p1 = pref[g + 1];
-                    lo = b.seg_lo[(size_t)bin * b.G + g];
-                    end = lo + b.seg_cnt[(size_t)bin * b.G + g];
-                }
-                up[k] = UnitPos{g, lo + (ik - p0) * R, end};
-            } else {
-                up[k] = UnitPos{g, 0u, 0u};
-            }
+    for (uint32_t i = i0; i < i1; ++i) {
+        if (i >= p1) {  // next segment that has units this round
+            if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
+            wch = 0;
+            do {
+                ++g;
+                p0 = p1;
+                p1 = pref[g + 1];
+            } while (i >= p1);
+            lo = b.seg_lo[(size_t)bin * b.G + g];
+            end = lo + b.seg_cnt[(size_t)bin * b.G + g];
+            gacc = g;
         }
-        uint32_t ch[NU];
-        if (GROUP)
-            units_group<NU>(b, a, T, up, round1, ch);
-        else
-            units_thread<NU>(b, a, up, round1, ch);
-#pragma unroll
-        for (int k = 0; k < NU; ++k) {
-            if (i + k >= i1) break;
-            if (up[k].g != gacc) {
-                if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
-                wch = 0;
-                gacc = up[k].g;
-            }
-            wch += ch[k];
-        }
+        const UnitPos up{g, lo + (i - p0) * 64u, end};
+        wch += a.g.w ? unit_lanes<true>(b, a, T, up, round1) : unit_lanes<false>(b, a, T, up, round1);
     }
     if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
 }
@@ -368,13 +467,9 @@ __device__ void run_range(const BatchArgs &b, const RoundArgs &a, u64 *T, int bi
     uint32_t g = g0;
     uint32_t p0 = pref[g], p1 = pref[g + 1];
     uint32_t lo = b.seg_lo[(size_t)bin * b.G + g], end = lo + b.seg_cnt[(size_t)bin * b.G + g];
-    // one-lane and 16-lane rows: several units in flight per wavefront
-    if (bin == BIN_THREAD) {
-        run_units<1, false>(b, a, T, bin, pref, i0, i1, g, p0, p1, lo, end, round1);
-        return;
-    }
-    if (bin == BIN_GROUP) {
-        run_units<4, true>(b, a, T, bin, pref, i0, i1, g, p0, p1, lo, end, round1);
+    // rows of at most group_max arcs: one lane each
+    if (bin == BIN_THREAD || bin == BIN_GROUP) {
+        run_units(b, a, T, bin, pref, i0, i1, g, p0, p1, lo, end, round1);
         return;
     }
     uint32_t wch = 0;
@@ -397,9 +492,9 @@ __device__ void run_range(const BatchArgs &b, const RoundArgs &a, u64 *T, int bi
 }
 
 // Units a wavefront takes at a time from its block's share of a bin: about
-// the same work per chunk (a one-lane unit is 64 rows, a group unit 4).
+// the same work per chunk (a thread or group unit is 64 rows).
 __device__ __forceinline__ uint32_t chunk_units(int bin) {
-    return bin == BIN_GROUP ? 16u : (bin == BIN_WAVE ? 4u : (bin == BIN_WIDE ? 2u : 1u));
+    return bin == BIN_WAVE ? 4u : (bin == BIN_WIDE ? 2u : 1u);
 }
 
 // The block's units of bin `bin` below `hi`, handed to its wavefronts a
@@ -555,13 +650,16 @@ __device__ void decide(const BatchArgs &b, uint32_t t) {
 
 template <int SLOTS>
 __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t nblocks) {
-    __shared__ u64 table[kBatchWaves * SLOTS];
+    // each wavefront's LDS: the SLOTS-slot table of its one-row units, or
+    // the label stage of its one-lane units (the same words: the table is
+    // cleared again at the start of every round, before the one-row bins);
+    // kSortNetMax words of slack behind the last wavefront's
+    constexpr int WL = SLOTS > kLaneStage / 2 ? SLOTS : kLaneStage / 2;
+    __shared__ u64 table[kBatchWaves * WL + kSortNetMax / 2];
     __shared__ uint32_t next_unit[kBatchBins];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    u64 *T = table + wave * SLOTS;
-    for (uint32_t s = lane; s < SLOTS; s += 64) T[s] = EMPTY_SLOT;
-    wave_sync();
+    u64 *T = table + wave * WL;
     if (blockIdx.x == 0 && threadIdx.x == 0) b.clock[0] = wall_clock64();
     // the work split of round 1: every graph votes
     if (blockIdx.x == 0) decide(b, 0);
@@ -598,6 +696,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
             if (lo < hi) seg = segment_of_unit(pref, b.G, lo);
         }
         if (wave == 0 && lane < (uint32_t)kBatchBins) next_unit[lane] = lo;
+        for (uint32_t s = lane; s < SLOTS; s += 64) T[s] = EMPTY_SLOT;
         __syncthreads();
         for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin)
             run_bin<SLOTS>(b, a, T, bin, (uint32_t)__builtin_amdgcn_readlane((int)hi, bin),

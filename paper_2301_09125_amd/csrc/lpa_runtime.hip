@@ -29,6 +29,7 @@
 #include "lpa.h"
 #include "lpa_internal.h"
 #include "lpa_copra.h"
+#include "lpa_sortnet.h"
 
 using namespace lpa;
 typedef unsigned long long u64;
@@ -288,8 +289,8 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
     HIP_TRY(c->old_of.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->new_of.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->rp2.ensure(((size_t)n + 1) * sizeof(uint64_t)));
-    HIP_TRY(c->col2.ensure((size_t)g->m * sizeof(uint32_t)));
-    if (g->w) HIP_TRY(c->w2.ensure((size_t)g->m * sizeof(uint32_t)));
+    HIP_TRY(c->col2.ensure(((size_t)g->m + kLaneArcPad) * sizeof(uint32_t)));
+    if (g->w) HIP_TRY(c->w2.ensure(((size_t)g->m + kLaneArcPad) * sizeof(uint32_t)));
     HIP_TRY(c->rowflag.ensure((size_t)n));
     uint32_t *totals = c->small.as<uint32_t>();
     u64 *arc_totals = reinterpret_cast<u64 *>(c->small.as<char>() + 32);
@@ -1189,6 +1190,8 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
     if (!gv && G) return LPA_EINVAL;
     if (!labels && g->n) return LPA_EINVAL;
     if (!(tol >= 0.0 && tol <= 1.0)) return LPA_EINVAL;
+    // the one-lane vote pads short rows with labels 0xFFFFFFFF - j, j < 32
+    if (g->n > 0xFFFFFFFFu - kSortNetMax + 1) return LPA_EINVAL;
     if (G == 0) {
         if (g->n) return LPA_EINVAL;
         clear_batch_stats(stats, 0);

@@ -140,6 +140,21 @@ def test_weighted_batch(gg, orc, lpa, ctx):
     check_graphs(orc, b, lab, st, range(b.G), 0.02, 15)
 
 
+@pytest.mark.parametrize("sw", [0, 2])
+def test_weighted_batch_with_zero_weights(gg, orc, lpa, sw):
+    # weights 0..2: rows whose every tally is 0 (the lowest label wins, or
+    # the own label when the self weight is positive) and own labels met
+    # only over zero-weight arcs
+    graphs = [gg.with_weights(g, 23, 0, 2) for g in mixed_graphs(gg)[1:]]
+    b = gg.pack(graphs)
+    c = lpa.Context(0, self_weight=sw)
+    try:
+        lab, st = run_batch(lpa, c, b, tol=0.0, max_iter=8)
+    finally:
+        c.close()
+    check_graphs(orc, b, lab, st, range(b.G), 0.0, 8, sw=sw)
+
+
 @pytest.mark.parametrize("sw", [0, 3])
 def test_self_weight(gg, orc, lpa, sw):
     b = gg.pack(mixed_graphs(gg))
