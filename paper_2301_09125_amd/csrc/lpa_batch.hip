@@ -282,7 +282,7 @@ constexpr int kLaneStage = 64 * kSortNetMax;
 template <bool R1>
 __device__ __forceinline__ void stage_labels(const BatchArgs &b, const RoundArgs &a, const uint32_t *cb, uint32_t nA,
                                              uint32_t g, uint32_t *stage) {
-    constexpr int P = 4;  // passes in flight
+    constexpr int P = 16;  // passes in flight: a unit of up to 1024 arcs in one round trip
     const uint32_t lane = threadIdx.x & 63;
     bool bad_col = false, bad_graph = false;
     for (uint32_t q0 = 0; q0 < nA; q0 += 64 * P) {
@@ -446,14 +446,20 @@ __device__ void run_units(const BatchArgs &b, const RoundArgs &a, u64 *T, int bi
 
 // The segment (graph) that holds unit i of a bin: the largest g with
 // pref[g] <= i, for non-decreasing pref with pref[0] = 0 <= i < pref[G].
-__device__ __forceinline__ uint32_t segment_of_unit(const uint32_t *pref, uint32_t G, uint32_t i) {
-    uint32_t lo = 0, hi = G;  // pref[lo] <= i < pref[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        if (pref[mid] <= i)
-            lo = mid;
-        else
-            hi = mid;
+// Searched by a whole wavefront, 64 probes per step (two dependent loads for
+// G <= 4096): the answer stays in [lo, lo + span) with pref[lo] <= i, and
+// the probes' test is monotone in the lane.
+__device__ __forceinline__ uint32_t segment_of_unit_wave(const uint32_t *pref, uint32_t G, uint32_t i) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t lo = 0, span = G;
+    while (span > 1) {
+        const uint32_t step = (span + 63) / 64;
+        const uint32_t off = lane * step;
+        const bool ok = off < span && pref[lo + off] <= i;
+        const u64 m = __ballot(ok);  // lane 0's probe is pref[lo] <= i
+        const uint32_t J = 63u - (uint32_t)__clzll((long long)m);
+        lo += J * step;
+        span = span - J * step < step ? span - J * step : step;
     }
     return lo;
 }
@@ -656,7 +662,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
     // kSortNetMax words of slack behind the last wavefront's
     constexpr int WL = SLOTS > kLaneStage / 2 ? SLOTS : kLaneStage / 2;
     __shared__ u64 table[kBatchWaves * WL + kSortNetMax / 2];
-    __shared__ uint32_t next_unit[kBatchBins];
+    __shared__ uint32_t next_unit[kBatchBins], share_hi[kBatchBins], share_seg[kBatchBins];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 *T = table + wave * WL;
@@ -686,21 +692,23 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
         a.orig = nullptr;
         const bool round1 = t == 1;
         // this block's share of every bin, [lo, hi), and the segment of its
-        // first unit: lane k of each wavefront works out bin k
-        uint32_t seg = 0, lo = 0, hi = 0;
-        if (lane < (uint32_t)kBatchBins) {
-            const uint32_t *pref = b.pref + (size_t)lane * (b.G + 1);
+        // first unit: wavefront k works out bin k
+        if (wave < (uint32_t)kBatchBins) {
+            const uint32_t *pref = b.pref + (size_t)wave * (b.G + 1);
             const uint32_t total = pref[b.G];
-            lo = (uint32_t)((u64)blockIdx.x * total / nblocks);
-            hi = (uint32_t)((u64)(blockIdx.x + 1) * total / nblocks);
-            if (lo < hi) seg = segment_of_unit(pref, b.G, lo);
+            const uint32_t lo = (uint32_t)((u64)blockIdx.x * total / nblocks);
+            const uint32_t hi = (uint32_t)((u64)(blockIdx.x + 1) * total / nblocks);
+            const uint32_t seg = lo < hi ? segment_of_unit_wave(pref, b.G, lo) : 0u;
+            if (lane == 0) {
+                next_unit[wave] = lo;
+                share_hi[wave] = hi;
+                share_seg[wave] = seg;
+            }
         }
-        if (wave == 0 && lane < (uint32_t)kBatchBins) next_unit[lane] = lo;
         for (uint32_t s = lane; s < SLOTS; s += 64) T[s] = EMPTY_SLOT;
         __syncthreads();
         for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin)
-            run_bin<SLOTS>(b, a, T, bin, (uint32_t)__builtin_amdgcn_readlane((int)hi, bin),
-                           (uint32_t)__builtin_amdgcn_readlane((int)seg, bin), &next_unit[bin], round1);
+            run_bin<SLOTS>(b, a, T, bin, share_hi[bin], share_seg[bin], &next_unit[bin], round1);
         if (!grid_barrier(b, nblocks)) return;
         if (blockIdx.x == 0) decide(b, t);
         if (!grid_barrier(b, nblocks)) return;
