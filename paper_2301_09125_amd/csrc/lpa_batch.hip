@@ -14,14 +14,18 @@
 // each (thread and group bins), never spanning two graphs.
 // One launch of co-resident blocks; per round:
 //   phase A  for each bin, the units of the graphs still voting are split
-//            into equal contiguous ranges, one per wavefront; a wavefront
-//            walks its range segment by segment and adds its changed count
-//            to a graph's counter once per segment.
+//            into equal contiguous ranges, one per block, whose wavefronts
+//            take chunks of it from an LDS counter; a wavefront adds its
+//            changed count to a graph's counter once per run of units of
+//            that graph.
 //   barrier
-//   phase B  block 0 applies every active graph's tolerance test, then
-//            prefix-sums the units of the graphs that go on (per bin) and
-//            records the segment each wavefront starts in.
-//   barrier  every block leaves once no graph is voting.
+//   phase B  every block applies the tolerance test of the graphs of its
+//            slice (G / nblocks graphs, rounded up to a power of two), then
+//            prefix-sums the units of the slice's graphs that go on (per
+//            bin) and publishes the slice's totals.
+//   barrier  every block leaves once no graph is voting; otherwise each
+//            block prefix-sums the slices' totals in LDS (a graph's prefix
+//            is its slice's base plus its prefix inside the slice).
 // Barriers count arrivals with an atomic and release on a generation
 // number; a wait longer than the time limit raises ERR_TIMEOUT and every
 // block leaves the kernel, so the launch always ends.
@@ -418,40 +422,26 @@ __device__ uint32_t unit_lanes(const BatchArgs &b, const RoundArgs &a, u64 *T, c
     return (uint32_t)__popcll(__ballot(c));
 }
 
-// Units i0 .. i1-1 of the thread or group bin (64 rows each, one per lane);
-// changed counts go to each unit's graph, one atomic per run of units of
-// one graph.  (g, p0, p1, lo, end): the segment of unit i0, as run_bin found
-// it.
-__device__ void run_units(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, const uint32_t *pref, uint32_t i0,
-                          uint32_t i1, uint32_t g, uint32_t p0, uint32_t p1, uint32_t lo, uint32_t end, bool round1) {
-    uint32_t gacc = g, wch = 0;
-    for (uint32_t i = i0; i < i1; ++i) {
-        if (i >= p1) {  // next segment that has units this round
-            if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
-            wch = 0;
-            do {
-                ++g;
-                p0 = p1;
-                p1 = pref[g + 1];
-            } while (i >= p1);
-            lo = b.seg_lo[(size_t)bin * b.G + g];
-            end = lo + b.seg_cnt[(size_t)bin * b.G + g];
-            gacc = g;
-        }
-        const UnitPos up{g, lo + (i - p0) * 64u, end};
-        wch += a.g.w ? unit_lanes<true>(b, a, T, up, round1) : unit_lanes<false>(b, a, T, up, round1);
+// The units of a bin as the blocks see them in a round: the prefix sum of
+// graph g is the base of its decision slice (the exclusive prefix of the
+// slices' totals, in LDS) plus its prefix inside the slice.
+struct PrefView {
+    const uint32_t *local;  // b.pref of the bin
+    const uint32_t *sbase;  // [slices] in LDS
+    uint32_t G, shift, total;
+    __device__ __forceinline__ uint32_t operator[](uint32_t g) const {
+        return g >= G ? total : sbase[g >> shift] + local[g];
     }
-    if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
-}
+};
 
-// The segment (graph) that holds unit i of a bin: the largest g with
-// pref[g] <= i, for non-decreasing pref with pref[0] = 0 <= i < pref[G].
-// Searched by a whole wavefront, 64 probes per step (two dependent loads for
-// G <= 4096): the answer stays in [lo, lo + span) with pref[lo] <= i, and
-// the probes' test is monotone in the lane.
-__device__ __forceinline__ uint32_t segment_of_unit_wave(const uint32_t *pref, uint32_t G, uint32_t i) {
+// The segment (graph) that holds unit i of a bin: the largest g in
+// [lo, lo + span) with pref[g] <= i, for non-decreasing pref, given
+// pref[lo] <= i < pref[lo + span].  Searched by a whole wavefront, 64 probes
+// per step (two dependent loads for span <= 4096): the answer stays in
+// [lo, lo + span) with pref[lo] <= i, and the probes' test is monotone in
+// the lane.
+__device__ __forceinline__ uint32_t segment_search(const PrefView &pref, uint32_t lo, uint32_t span, uint32_t i) {
     const uint32_t lane = threadIdx.x & 63;
-    uint32_t lo = 0, span = G;
     while (span > 1) {
         const uint32_t step = (span + 63) / 64;
         const uint32_t off = lane * step;
@@ -464,11 +454,42 @@ __device__ __forceinline__ uint32_t segment_of_unit_wave(const uint32_t *pref, u
     return lo;
 }
 
+// The segment that holds unit i, from segment g on (pref[g] <= i < pref[G]):
+// g itself when i < pref[g + 1], else a search of the segments after it
+// (never a walk over the empty segments of graphs that stopped voting).
+__device__ __forceinline__ uint32_t segment_from(const PrefView &pref, uint32_t G, uint32_t g, uint32_t i) {
+    if (i < pref[g + 1]) return g;
+    return segment_search(pref, g + 1, G - g - 1, i);
+}
+
+// Units i0 .. i1-1 of the thread or group bin (64 rows each, one per lane);
+// changed counts go to each unit's graph, one atomic per run of units of
+// one graph.  (g, p0, p1, lo, end): the segment of unit i0, as run_bin found
+// it.
+__device__ void run_units(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, const PrefView &pref, uint32_t i0,
+                          uint32_t i1, uint32_t g, uint32_t p0, uint32_t p1, uint32_t lo, uint32_t end, bool round1) {
+    uint32_t gacc = g, wch = 0;
+    for (uint32_t i = i0; i < i1; ++i) {
+        if (i >= p1) {  // next segment that has units this round
+            if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
+            wch = 0;
+            g = segment_from(pref, b.G, g, i);
+            p0 = pref[g];
+            p1 = pref[g + 1];
+            lo = b.seg_lo[(size_t)bin * b.G + g];
+            end = lo + b.seg_cnt[(size_t)bin * b.G + g];
+            gacc = g;
+        }
+        const UnitPos up{g, lo + (i - p0) * 64u, end};
+        wch += a.g.w ? unit_lanes<true>(b, a, T, up, round1) : unit_lanes<false>(b, a, T, up, round1);
+    }
+    if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[gacc], (u64)wch);
+}
+
 // Units [i0, i1) of bin `bin`; g0 is the segment that holds unit i0.
 template <int SLOTS>
-__device__ void run_range(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t i0, uint32_t i1,
-                          uint32_t g0, bool round1) {
-    const uint32_t *pref = b.pref + (size_t)bin * (b.G + 1);
+__device__ void run_range(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, const PrefView &pref, uint32_t i0,
+                          uint32_t i1, uint32_t g0, bool round1) {
     const uint32_t R = unit_rows(bin);
     uint32_t g = g0;
     uint32_t p0 = pref[g], p1 = pref[g + 1];
@@ -483,11 +504,9 @@ __device__ void run_range(const BatchArgs &b, const RoundArgs &a, u64 *T, int bi
         if (i >= p1) {  // next segment that has units this round
             if (wch && (threadIdx.x & 63) == 0) atomicAdd(&b.changed[g], (u64)wch);
             wch = 0;
-            do {
-                ++g;
-                p0 = p1;
-                p1 = pref[g + 1];
-            } while (i >= p1);
+            g = segment_from(pref, b.G, g, i);
+            p0 = pref[g];
+            p1 = pref[g + 1];
             lo = b.seg_lo[(size_t)bin * b.G + g];
             end = lo + b.seg_cnt[(size_t)bin * b.G + g];
         }
@@ -508,9 +527,8 @@ __device__ __forceinline__ uint32_t chunk_units(int bin) {
 // SIMDs issue less often (the younger ones) do less of the work instead of
 // finishing last; g is the segment of the block's first unit.
 template <int SLOTS>
-__device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, uint32_t hi, uint32_t g,
-                        uint32_t *next, bool round1) {
-    const uint32_t *pref = b.pref + (size_t)bin * (b.G + 1);
+__device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin, const PrefView &pref, uint32_t hi,
+                        uint32_t g, uint32_t *next, bool round1) {
     const uint32_t CH = chunk_units(bin);
     for (;;) {
         uint32_t i0 = 0;
@@ -518,118 +536,83 @@ __device__ void run_bin(const BatchArgs &b, const RoundArgs &a, u64 *T, int bin,
         i0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)i0, 0, 64));
         if (i0 >= hi) break;
         const uint32_t i1 = i0 + CH < hi ? i0 + CH : hi;
-        while (pref[g + 1] <= i0) ++g;  // a wavefront's chunks only move forward
-        run_range<SLOTS>(b, a, T, bin, i0, i1, g, round1);
+        g = segment_from(pref, b.G, g, i0);  // a wavefront's chunks only move forward
+        run_range<SLOTS>(b, a, T, bin, pref, i0, i1, g, round1);
     }
 }
 
-// Phase B, run by block 0 alone: tolerance tests of round t (none for
-// t = 0), then the per-bin prefix sums of the units of the graphs that go on
-// voting.  Each thread takes kDecideJ graphs per pass and issues all their
-// loads before it uses any (the data was written by other blocks, so every
-// load goes past this CU's caches).
+// Phase B, run by every block on its slice of the graphs,
+// [blockIdx.x << dshift, (blockIdx.x + 1) << dshift) clipped to G: the
+// tolerance tests of round t (none for t = 0), then the slice's per-bin
+// prefix sums of the units of its graphs that go on voting (pref, from 0 at
+// the slice's first graph) and their totals (btot[bin][block]); the block's
+// voting graphs are added to n_active[t & 1], and block 0 clears the other
+// word for round t + 1.  Each thread takes kDecideJ consecutive graphs per
+// pass and issues all their loads (state and segment sizes) at once, so a
+// slice of up to kDecideJ * kBatchThreads graphs costs one round trip to
+// memory and one block-wide scan.
 constexpr int kDecideJ = 4;
 __device__ void decide(const BatchArgs &b, uint32_t t) {
     constexpr int J = kDecideJ;
-    __shared__ uint32_t wsum[kBatchWaves][kBatchBins];
-    __shared__ uint32_t carry[kBatchBins];
-    __shared__ uint32_t n_on;
-    __shared__ u64 arcs_sum;
+    __shared__ uint32_t wsum[kBatchWaves][kBatchBins + 1];
+    __shared__ uint32_t carry[kBatchBins + 1];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t G = b.G;
-    if (tid == 0) {
-        n_on = 0;
-        arcs_sum = 0;
-    }
-    if (tid < kBatchBins) carry[tid] = 0;
+    const uint32_t s0 = blockIdx.x << b.dshift;
+    const uint32_t s1 = s0 < G ? (G - s0 < (1u << b.dshift) ? G : s0 + (1u << b.dshift)) : s0;
+    if (tid == 0 && blockIdx.x == 0) b.n_active[(t + 1) & 1] = 0;
+    if (tid <= kBatchBins) carry[tid] = 0;
     __syncthreads();
-    uint32_t on = 0;
-    u64 arcs = 0;
-    for (uint32_t base = 0; base < G; base += J * kBatchThreads) {
-        uint32_t gg[J], act[J];
+    for (uint32_t base = s0; base < s1; base += J * kBatchThreads) {
+        const uint32_t g0 = base + tid * J;
+        uint32_t act[J], cnt[J][kBatchBins];
         u64 ch[J], th[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            gg[j] = base + (uint32_t)j * kBatchThreads + tid;
-            const uint32_t gc = gg[j] < G ? gg[j] : 0u;  // index 0 exists: G >= 1
-            const uint32_t av = b.active[gc];
-            act[j] = gg[j] < G ? av : 0u;
+            const uint32_t gc = g0 + j < s1 ? g0 + j : s0;  // s0 < s1 here
+            act[j] = b.active[gc];
             ch[j] = b.changed[gc];
             th[j] = b.thr[gc];
-        }
-        uint32_t stop = 0;
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            if (!act[j]) continue;
-            if (t == 0) {
-                ++on;
-                continue;
-            }
-            const uint32_t g = gg[j];
-            b.changed[g] = 0;
-            b.last[g] = ch[j];
-            b.iters[g] = t;
-            if (t <= b.hist_len) b.hist[(u64)g * b.hist_len + (t - 1)] = ch[j];
-            const bool ok = ch[j] <= th[j];
-            if (ok || t == b.max_iter) {
-                b.conv[g] = ok ? 1 : 0;
-                b.active[g] = 0;
-                stop |= 1u << j;
-            } else {
-                ++on;
-            }
+            for (int k = 0; k < kBatchBins; ++k) cnt[j][k] = b.seg_cnt[(size_t)k * G + gc];
         }
-        // arcs voted by the graphs that stopped: t rounds each
-        uint64_t v0[J], v1[J];
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const uint32_t gc = (stop >> j & 1u) ? gg[j] : 0u;
-            v0[j] = b.gv[gc];
-            v1[j] = b.gv[gc + 1];
-        }
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const uint64_t r0 = b.orp[v0[j]], r1 = b.orp[v1[j]];
-            if (stop >> j & 1u) arcs += (u64)(r1 - r0) * t;
-        }
-    }
-    on = wave_sum(on);
-    arcs = wave_sum(arcs);
-    if (lane == 0 && on) atomicAdd(&n_on, on);
-    if (lane == 0 && arcs) atomicAdd(&arcs_sum, arcs);
-    __syncthreads();  // active[] of every graph is final
-    if (tid == 0 && arcs_sum) atomicAdd(b.arcs, arcs_sum);
-    // exclusive prefix sums over graphs: J consecutive graphs per thread,
-    // J * kBatchThreads per pass
-    for (uint32_t base = 0; base < G; base += J * kBatchThreads) {
-        const uint32_t g0 = base + tid * J;
-        uint32_t x[J][kBatchBins];
+        // x[j][k]: units of graph g0 + j in bin k if it goes on voting;
+        // x[j][kBatchBins]: 1 if it does
+        uint32_t x[J][kBatchBins + 1];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const uint32_t g = g0 + j;
-            const uint32_t gc = g < G ? g : 0u;
-            const uint32_t av = b.active[gc];
-            const bool live = g < G && av;
-#pragma unroll
-            for (int k = 0; k < kBatchBins; ++k) {
-                const uint32_t c = b.seg_cnt[(size_t)k * G + gc];
-                x[j][k] = live ? (c + unit_rows(k) - 1) / unit_rows(k) : 0u;
+            bool live = g < s1 && act[j];
+            if (live && t > 0) {
+                b.changed[g] = 0;
+                b.last[g] = ch[j];
+                b.iters[g] = t;
+                if (t <= b.hist_len) b.hist[(u64)g * b.hist_len + (t - 1)] = ch[j];
+                const bool ok = ch[j] <= th[j];
+                if (ok || t == b.max_iter) {
+                    b.conv[g] = ok ? 1 : 0;
+                    b.active[g] = 0;
+                    live = false;
+                }
             }
-        }
-        uint32_t ex[kBatchBins];
 #pragma unroll
-        for (int k = 0; k < kBatchBins; ++k) {
+            for (int k = 0; k < kBatchBins; ++k) x[j][k] = live ? (cnt[j][k] + unit_rows(k) - 1) / unit_rows(k) : 0u;
+            x[j][kBatchBins] = live ? 1u : 0u;
+        }
+        uint32_t ex[kBatchBins + 1];
+#pragma unroll
+        for (int k = 0; k <= kBatchBins; ++k) {
             uint32_t tot = 0;
 #pragma unroll
             for (int j = 0; j < J; ++j) tot += x[j][k];
-            uint32_t s = tot;
+            uint32_t sc = tot;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(s, off, 64);
-                if ((int)lane >= off) s += y;
+                const uint32_t y = __shfl_up(sc, off, 64);
+                if ((int)lane >= off) sc += y;
             }
-            if (lane == 63) wsum[wave][k] = s;
-            ex[k] = s - tot;  // exclusive within the wavefront
+            if (lane == 63) wsum[wave][k] = sc;
+            ex[k] = sc - tot;  // exclusive within the wavefront
         }
         __syncthreads();
 #pragma unroll
@@ -638,20 +621,35 @@ __device__ void decide(const BatchArgs &b, uint32_t t) {
             for (uint32_t q = 0; q < wave; ++q) off += wsum[q][k];
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                if (g0 + j < G) b.pref[(size_t)k * (G + 1) + g0 + j] = off;
+                if (g0 + j < s1) b.pref[(size_t)k * (G + 1) + g0 + j] = off;
                 off += x[j][k];
             }
         }
         __syncthreads();
-        if (tid < kBatchBins) {
-            uint32_t s = 0;
-            for (int q = 0; q < kBatchWaves; ++q) s += wsum[q][tid];
-            carry[tid] += s;
+        if (tid <= kBatchBins) {
+            uint32_t sc = 0;
+            for (int q = 0; q < kBatchWaves; ++q) sc += wsum[q][tid];
+            carry[tid] += sc;
         }
         __syncthreads();
     }
-    if (tid < kBatchBins) b.pref[(size_t)tid * (G + 1) + G] = carry[tid];
-    if (tid == 0) *b.n_active = n_on;
+    if (tid < kBatchBins) b.btot[(size_t)tid * kBatchMaxBlocks + blockIdx.x] = carry[tid];
+    if (tid == kBatchBins && carry[kBatchBins]) atomicAdd(&b.n_active[t & 1], carry[kBatchBins]);
+}
+
+// Arcs voted by the graphs of this block's decision slice, once every graph
+// has stopped: m_g times its rounds.
+__device__ void slice_arcs(const BatchArgs &b) {
+    const uint32_t G = b.G;
+    const uint32_t s0 = blockIdx.x << b.dshift;
+    const uint32_t s1 = s0 < G ? (G - s0 < (1u << b.dshift) ? G : s0 + (1u << b.dshift)) : s0;
+    u64 arcs = 0;
+    for (uint32_t g = s0 + threadIdx.x; g < s1; g += kBatchThreads) {
+        const uint64_t v0 = b.gv[g], v1 = b.gv[g + 1];
+        arcs += (u64)(b.orp[v1] - b.orp[v0]) * b.iters[g];
+    }
+    arcs = wave_sum(arcs);
+    if ((threadIdx.x & 63) == 0 && arcs) atomicAdd(b.arcs, arcs);
 }
 
 template <int SLOTS>
@@ -663,12 +661,14 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
     constexpr int WL = SLOTS > kLaneStage / 2 ? SLOTS : kLaneStage / 2;
     __shared__ u64 table[kBatchWaves * WL + kSortNetMax / 2];
     __shared__ uint32_t next_unit[kBatchBins], share_hi[kBatchBins], share_seg[kBatchBins];
+    // per bin: the exclusive prefix of the decision slices' unit totals
+    __shared__ uint32_t sbase[kBatchBins][kBatchMaxBlocks], stot[kBatchBins];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 *T = table + wave * WL;
     if (blockIdx.x == 0 && threadIdx.x == 0) b.clock[0] = wall_clock64();
     // the work split of round 1: every graph votes
-    if (blockIdx.x == 0) decide(b, 0);
+    decide(b, 0);
     if (!grid_barrier(b, nblocks)) return;
     for (uint32_t t = 1; t <= b.max_iter; ++t) {
         RoundArgs a;
@@ -691,30 +691,57 @@ __global__ __launch_bounds__(kBatchThreads) void batch_k(BatchArgs b, uint32_t n
         a.seed = 0;
         a.orig = nullptr;
         const bool round1 = t == 1;
-        // this block's share of every bin, [lo, hi), and the segment of its
-        // first unit: wavefront k works out bin k
+        // wavefront k works out bin k: the slices' bases (the exclusive
+        // prefix of btot[k][0 .. nblocks), up to 64 * 8 entries), then this
+        // block's share of the bin's units, [lo, hi), and the segment of its
+        // first unit
         if (wave < (uint32_t)kBatchBins) {
-            const uint32_t *pref = b.pref + (size_t)wave * (b.G + 1);
-            const uint32_t total = pref[b.G];
+            constexpr int C = kBatchMaxBlocks / 64;
+            uint32_t v[C], sum = 0;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const uint32_t j = lane * C + c;
+                v[c] = j < nblocks ? b.btot[(size_t)wave * kBatchMaxBlocks + j] : 0u;
+                sum += v[c];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if ((int)lane >= off) incl += y;
+            }
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                sbase[wave][lane * C + c] = run;
+                run += v[c];
+            }
+            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            wave_sync();
+            const PrefView pv{b.pref + (size_t)wave * (b.G + 1), sbase[wave], b.G, b.dshift, total};
             const uint32_t lo = (uint32_t)((u64)blockIdx.x * total / nblocks);
             const uint32_t hi = (uint32_t)((u64)(blockIdx.x + 1) * total / nblocks);
-            const uint32_t seg = lo < hi ? segment_of_unit_wave(pref, b.G, lo) : 0u;
+            const uint32_t seg = lo < hi ? segment_search(pv, 0, b.G, lo) : 0u;
             if (lane == 0) {
                 next_unit[wave] = lo;
                 share_hi[wave] = hi;
                 share_seg[wave] = seg;
+                stot[wave] = total;
             }
         }
         for (uint32_t s = lane; s < SLOTS; s += 64) T[s] = EMPTY_SLOT;
         __syncthreads();
-        for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin)
-            run_bin<SLOTS>(b, a, T, bin, share_hi[bin], share_seg[bin], &next_unit[bin], round1);
+        for (int bin = BIN_HUB; bin <= BIN_THREAD; ++bin) {
+            const PrefView pv{b.pref + (size_t)bin * (b.G + 1), sbase[bin], b.G, b.dshift, stot[bin]};
+            run_bin<SLOTS>(b, a, T, bin, pv, share_hi[bin], share_seg[bin], &next_unit[bin], round1);
+        }
         if (!grid_barrier(b, nblocks)) return;
-        if (blockIdx.x == 0) decide(b, t);
+        decide(b, t);
         if (!grid_barrier(b, nblocks)) return;
-        if (__hip_atomic_load(b.n_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+        if (__hip_atomic_load(&b.n_active[t & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
         if (__hip_atomic_load(b.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (ERR_COL | ERR_GRAPH)) break;
     }
+    slice_arcs(b);
     if (blockIdx.x == 0 && threadIdx.x == 0) b.clock[1] = wall_clock64();
 }
 

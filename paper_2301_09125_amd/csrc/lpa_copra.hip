@@ -405,7 +405,6 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
     __shared__ u64 tal[kCopraBlockSlots];
     __shared__ BlockRed red[3];
     __shared__ uint32_t klab[64], kcoef[64], kn, claimed, full;
-    const uint32_t V = a.V;
     u64 chg = 0;
     for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
         const uint32_t v = rows[it];
@@ -481,7 +480,6 @@ __global__ __launch_bounds__(256) void copra_gpiece_k(CopraArgs a, const CopraPi
                                                       u64 *slab_tal, u64 *total) {
     __shared__ uint32_t key[kCopraBlockSlots];
     __shared__ u64 tal[kCopraBlockSlots];
-    const uint32_t V = a.V;
     for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
         const CopraPiece pc = pieces[it];
         for (uint32_t s = threadIdx.x; s < kCopraBlockSlots; s += 256) {

@@ -181,6 +181,7 @@ struct ModArgs {
 // BIN_HUB .. BIN_THREAD vote; rows of graph g in bin k are the segment
 // seg_lo[k*G+g] .. + seg_cnt[k*G+g] of internal ids.
 constexpr int kBatchBins = 5;
+constexpr int kBatchMaxBlocks = 512;  // blocks of one batched launch (one decision slice each)
 
 struct BatchArgs {
     Graph g;                     // internal packed graph
@@ -201,7 +202,7 @@ struct BatchArgs {
     uint32_t hist_len;
     unsigned long long *arcs;    // arcs voted, summed over graphs
     unsigned long long *clock;   // [2] wall clock at the kernel's start and end (block 0)
-    uint32_t *n_active;          // graphs still voting
+    uint32_t *n_active;          // [2] graphs still voting after round t: word t & 1
     uint32_t *bar;               // [0] arrivals, [1] generation
     uint32_t *err;
     const uint64_t *slab_off;    // long rows: per-row global slab ...
@@ -212,7 +213,9 @@ struct BatchArgs {
     uint32_t *tcount;
     const uint32_t *seg_lo;      // [kBatchBins * G]
     const uint32_t *seg_cnt;     // [kBatchBins * G]
-    uint32_t *pref;              // [kBatchBins * (G+1)] units of voting graphs, prefix sums
+    uint32_t *pref;              // [kBatchBins * (G+1)] units of voting graphs, prefix sums inside each slice
+    uint32_t *btot;              // [kBatchBins * kBatchMaxBlocks] units of voting graphs per slice
+    uint32_t dshift;             // block k decides graphs [k << dshift, (k + 1) << dshift)
     uint64_t timeout_ticks;      // wall-clock ticks one barrier may wait
 };
 

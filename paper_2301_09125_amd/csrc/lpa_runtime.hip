@@ -1139,7 +1139,7 @@ namespace {
 
 struct BatchLayout {
     u64 *thr, *changed, *last, *hist, *arcs, *clock;
-    uint32_t *active, *iters, *n_active, *bar;
+    uint32_t *active, *iters, *n_active, *bar, *btot;
     int32_t *conv;
     size_t bytes;
 };
@@ -1162,8 +1162,9 @@ BatchLayout batch_layout(void *base, uint32_t G, uint32_t hist_len) {
     L.active = reinterpret_cast<uint32_t *>(take((size_t)G * 4));
     L.iters = reinterpret_cast<uint32_t *>(take((size_t)G * 4));
     L.conv = reinterpret_cast<int32_t *>(take((size_t)G * 4));
-    L.n_active = reinterpret_cast<uint32_t *>(take(4));
+    L.n_active = reinterpret_cast<uint32_t *>(take(8));
     L.bar = reinterpret_cast<uint32_t *>(take(8));
+    L.btot = reinterpret_cast<uint32_t *>(take((size_t)kBatchBins * kBatchMaxBlocks * 4));
     L.bytes = off;
     return L;
 }
@@ -1237,9 +1238,10 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         const Bins &B = P.bins;
         const int slots = batch_slots(B);
         const uint64_t units = (uint64_t)B.cnt[BIN_HUB] + B.cnt[BIN_WIDE] + B.cnt[BIN_WAVE] +
-                               (B.cnt[BIN_GROUP] + 3) / 4 + (B.cnt[BIN_THREAD] + 63) / 64;
+                               (B.cnt[BIN_GROUP] + 63) / 64 + (B.cnt[BIN_THREAD] + 63) / 64;
         const uint32_t wpb = (uint32_t)batch_waves_per_block();
-        const uint64_t cap_blocks = (uint64_t)batch_blocks_per_cu(slots) * c->num_cu;
+        const uint64_t cap_blocks =
+            std::min<uint64_t>((uint64_t)batch_blocks_per_cu(slots) * c->num_cu, kBatchMaxBlocks);
         const uint32_t nblocks =
             (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap_blocks, (units + wpb - 1) / wpb));
         HIP_TRY(c->bstate.ensure(batch_layout(nullptr, G, hist_len).bytes));
@@ -1289,6 +1291,9 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         b.seg_lo = seg_lo;
         b.seg_cnt = seg_cnt;
         b.pref = pref;
+        b.btot = L.btot;
+        b.dshift = 0;
+        while (((uint64_t)nblocks << b.dshift) < G) ++b.dshift;
         b.clock = L.clock;
         int rate_khz = 0;
         HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
@@ -1328,7 +1333,7 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
             if (e == hipSuccess) e = launch_fill_u64(L.last, 0, G, cs);
             if (e == hipSuccess && hist_len) e = launch_fill_u64(L.hist, 0, (uint64_t)G * hist_len, cs);
             if (e == hipSuccess) e = launch_fill_u64(L.arcs, 0, 1, cs);
-            if (e == hipSuccess) e = launch_fill_u32(L.n_active, G, 1, cs);
+            if (e == hipSuccess) e = launch_fill_u32(L.n_active, 0, 2, cs);
             if (e == hipSuccess) e = launch_fill_u32(L.bar, 0, 2, cs);
             if (e == hipSuccess) e = launch_fill_u64(L.clock, 0, 2, cs);
             if (e == hipSuccess && max_iter) e = launch_batch(b, nblocks, slots, cs);
