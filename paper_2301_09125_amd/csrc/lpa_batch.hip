@@ -41,21 +41,35 @@ constexpr int kBatchWaves = kBatchThreads / 64;
 // rows per work unit of each bin
 __device__ __forceinline__ uint32_t unit_rows(int b) { return b == BIN_THREAD || b == BIN_GROUP ? 64u : 1u; }
 
-// Grid-wide barrier over `nblocks` co-resident blocks.  The waiting blocks
-// poll the generation word with relaxed loads and acquire once, after it
-// moved: an acquiring load at device scope also invalidates the L2 of the
-// CU's die, so polling with it would keep evicting the labels of the blocks
-// that are still voting.
+// Grid-wide barrier over `nblocks` co-resident blocks, in two levels: the
+// blocks are split into up to kBarGroups groups (block k in group
+// k % groups), each counting its arrivals in a word of its own, and the last
+// arrival of each group counts the group in the top word; the last group's
+// last block advances the generation.  So no more than kBarGroups arrivals
+// meet on one word (every device-scope atomic on a word is serialised where
+// the dies meet).  The counters only grow (cleared before the launch): the
+// k-th arrival of a group of size s closes it when k % s == 0.  The waiting
+// blocks poll the generation word with relaxed loads and acquire once,
+// after it moved: an acquiring load at device scope also invalidates the L2
+// of the CU's die, so polling with it would keep evicting the labels of the
+// blocks that are still voting.
+constexpr uint32_t kBarGroups = 16;
+constexpr uint32_t kBarStride = 32;  // words between counters (128 bytes)
+static_assert(kBarStride * (1 + kBarGroups) <= (uint32_t)kBatchBarWords, "barrier words");
 __device__ __forceinline__ bool grid_barrier(const BatchArgs &b, uint32_t nblocks) {
     __shared__ int failed;
     __syncthreads();
     if (threadIdx.x == 0) {
         failed = 0;
+        const uint32_t ng = nblocks < kBarGroups ? nblocks : kBarGroups;
+        const uint32_t grp = blockIdx.x % ng;
+        const uint32_t gsize = (nblocks - grp + ng - 1) / ng;
         const uint32_t gen = __hip_atomic_load(&b.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
-        const uint32_t arrived = atomicAdd(&b.bar[0], 1u) + 1;
-        if (arrived == nblocks) {
-            __hip_atomic_store(&b.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool last = false;
+        if ((atomicAdd(&b.bar[kBarStride * (1 + grp)], 1u) + 1) % gsize == 0)
+            last = (atomicAdd(&b.bar[0], 1u) + 1) % ng == 0;
+        if (last) {
             __threadfence();
             __hip_atomic_fetch_add(&b.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {

@@ -182,6 +182,7 @@ struct ModArgs {
 // seg_lo[k*G+g] .. + seg_cnt[k*G+g] of internal ids.
 constexpr int kBatchBins = 5;
 constexpr int kBatchMaxBlocks = 512;  // blocks of one batched launch (one decision slice each)
+constexpr int kBatchBarWords = 32 * 17;  // the batched launch's barrier: 16 group counters 128 bytes apart
 
 struct BatchArgs {
     Graph g;                     // internal packed graph
@@ -203,7 +204,7 @@ struct BatchArgs {
     unsigned long long *arcs;    // arcs voted, summed over graphs
     unsigned long long *clock;   // [2] wall clock at the kernel's start and end (block 0)
     uint32_t *n_active;          // [2] graphs still voting after round t: word t & 1
-    uint32_t *bar;               // [0] arrivals, [1] generation
+    uint32_t *bar;               // [kBatchBarWords]: [0] group arrivals, [1] generation, then the groups' arrival counters
     uint32_t *err;
     const uint64_t *slab_off;    // long rows: per-row global slab ...
     const uint32_t *slab_mask;

@@ -1163,7 +1163,7 @@ BatchLayout batch_layout(void *base, uint32_t G, uint32_t hist_len) {
     L.iters = reinterpret_cast<uint32_t *>(take((size_t)G * 4));
     L.conv = reinterpret_cast<int32_t *>(take((size_t)G * 4));
     L.n_active = reinterpret_cast<uint32_t *>(take(8));
-    L.bar = reinterpret_cast<uint32_t *>(take(8));
+    L.bar = reinterpret_cast<uint32_t *>(take(kBatchBarWords * 4));
     L.btot = reinterpret_cast<uint32_t *>(take((size_t)kBatchBins * kBatchMaxBlocks * 4));
     L.bytes = off;
     return L;
@@ -1334,7 +1334,7 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
             if (e == hipSuccess && hist_len) e = launch_fill_u64(L.hist, 0, (uint64_t)G * hist_len, cs);
             if (e == hipSuccess) e = launch_fill_u64(L.arcs, 0, 1, cs);
             if (e == hipSuccess) e = launch_fill_u32(L.n_active, 0, 2, cs);
-            if (e == hipSuccess) e = launch_fill_u32(L.bar, 0, 2, cs);
+            if (e == hipSuccess) e = launch_fill_u32(L.bar, 0, kBatchBarWords, cs);
             if (e == hipSuccess) e = launch_fill_u64(L.clock, 0, 2, cs);
             if (e == hipSuccess && max_iter) e = launch_batch(b, nblocks, slots, cs);
             if (e == hipSuccess)
