@@ -357,6 +357,21 @@ def run_batch_bench(args, b, desc, P):
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_from_profile(args.workload, "batch_k"),
                 "avg_launch_ms": round(dev_ms, 4), "bytes_per_launch": int(bytes_step)}
+    # the same steps with the relabelled copy kept between calls (reuse_csr;
+    # binning and relabelling once per CSR and graph_vptr): not the value
+    bins = {} if tuned is None else {k: tuned[k] for k in ("thread_max", "group_max", "wave_max", "wide_max")}
+    rctx = P.Context(0, reuse_csr=1, **bins)
+    rctx.run_batch(dg, b.gv, tol=args.tol, max_iter=args.max_iter, labels_out=labels)  # builds the copy
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, rst = rctx.run_batch(dg, b.gv, tol=args.tol, max_iter=args.max_iter, labels_out=labels)
+    torch.cuda.synchronize()
+    reuse_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    rctx.close()
+    if not np.array_equal(rst.changed_hist, st0.changed_hist):
+        raise SystemExit("reuse_csr changed the result")
+    log(f"[bench] with the relabelled copy kept (reuse_csr): {reuse_ms:.3f} ms/step")
     cpu = None
     if args.cpu_seconds > 0:
         log("[bench] cpu baseline: oracle on a sample of whole graphs ...")
@@ -372,7 +387,9 @@ def run_batch_bench(args, b, desc, P):
                    "bins": None if tuned is None else {k: tuned[k] for k in ("thread_max", "group_max", "wave_max",
                                                                              "wide_max")},
                    "hbm_gbs_effective": round(bytes_step * args.steps / elapsed / 1e9, 1),
-                   "device_ms": round(dev_ms, 4)},
+                   "device_ms": round(dev_ms, 4),
+                   "reuse_csr_ms_per_step": round(reuse_ms, 4),
+                   "reuse_csr_gearcs_per_s": round(st0.arcs_processed / reuse_ms / 1e6, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

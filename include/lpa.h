@@ -133,12 +133,14 @@ typedef struct {
                               binned, relabelled copy of the CSR (steps a1-a2,
                               once per CSR) and reuse it when called again
                               with the same row_ptr, col, w, n, m and bin
-                              thresholds.  The caller promises the arrays
-                              were not written in between.  Any other call
-                              that builds a copy (another graph, batches,
-                              modularity, frontier runs, the autotuner)
-                              replaces it.  Round 1 is then voted by the
-                              round kernels instead of the relabel pass. */
+                              thresholds; lpa_run_batch likewise, with the
+                              same graph_vptr too.  The caller promises the
+                              arrays were not written in between.  Any other
+                              call that builds a copy (another graph or
+                              batch, modularity, frontier runs, the
+                              autotuner) replaces it.  Round 1 of lpa_run is
+                              then voted by the round kernels instead of the
+                              relabel pass. */
 } lpa_options;
 
 enum { LPA_ORDER_SYNC = 0, LPA_ORDER_SEMISYNC = 1 };

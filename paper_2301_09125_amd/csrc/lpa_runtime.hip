@@ -115,6 +115,7 @@ struct lpa_ctx {
     // the CSR and thresholds the internal copy was last built for by a
     // prepare() that also set up the long-row state (empty = none)
     std::vector<uint64_t> prep_key;
+    std::vector<uint64_t> bprep_key;  // prep_key, G and graph_vptr of the batch whose gid/segments are built
     Plan prep_plan;
     bool slab_dirty = false;      // slab may hold entries (set after a timed-out batch)
     hipStream_t cap_stream = nullptr;
@@ -283,6 +284,7 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
     const uint32_t nblk = bin_blocks(n);
     const lpa_options &o = c->opt;
     c->prep_key.clear();  // the internal copy is rebuilt below
+    c->bprep_key.clear();
     HIP_TRY(c->blk_counts.ensure((size_t)NBINS * nblk * sizeof(uint32_t)));
     HIP_TRY(c->blk_arcs.ensure((size_t)NBINS * nblk * sizeof(u64)));
     HIP_TRY(c->small.ensure(128));
@@ -1226,11 +1228,23 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         HIP_TRY(launch_fill_u64(c->counters.as<u64>(), 0, 1, s));
         LPA_TRY(ensure_pinned(c, 16));
         Plan P;
-        LPA_TRY(prepare(c, g, P, err_dev, true));
-        HIP_TRY(c->gvd.ensure(((size_t)G + 1) * sizeof(uint64_t)));
-        HIP_TRY(hipMemcpyAsync(c->gvd.p, gv, ((size_t)G + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(c->gid.ensure((size_t)n * sizeof(uint32_t)));
-        HIP_TRY(launch_batch_gid(c->old_of.as<uint32_t>(), n, c->gvd.as<uint64_t>(), G, c->gid.as<uint32_t>(), s));
+        // reuse_csr: the internal copy, the vertices' graphs and the graphs'
+        // segments kept from the last batch on the same CSR and graph_vptr
+        std::vector<uint64_t> bkey = csr_key(c, g);
+        bkey.push_back(G);
+        bkey.insert(bkey.end(), gv, gv + (size_t)G + 1);
+        const bool reuse = c->opt.reuse_csr && !c->prep_key.empty() && c->prep_key == csr_key(c, g) &&
+                           c->bprep_key == bkey;
+        if (reuse) {
+            P = c->prep_plan;
+            LPA_TRY(reset_hub_state(c, P));
+        } else {
+            LPA_TRY(prepare(c, g, P, err_dev, true));
+            HIP_TRY(c->gvd.ensure(((size_t)G + 1) * sizeof(uint64_t)));
+            HIP_TRY(hipMemcpyAsync(c->gvd.p, gv, ((size_t)G + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+            HIP_TRY(c->gid.ensure((size_t)n * sizeof(uint32_t)));
+            HIP_TRY(launch_batch_gid(c->old_of.as<uint32_t>(), n, c->gvd.as<uint64_t>(), G, c->gid.as<uint32_t>(), s));
+        }
         HIP_TRY(c->La.ensure((size_t)n * sizeof(uint32_t)));
         HIP_TRY(c->Lb.ensure((size_t)n * sizeof(uint32_t)));
         HIP_TRY(launch_init_labels(c->La.as<uint32_t>(), c->Lb.as<uint32_t>(), c->old_of.as<uint32_t>(), nullptr, n,
@@ -1252,7 +1266,10 @@ lpa_status run_batch_impl(lpa_ctx *c, const lpa_csr *g, const uint64_t *gv, uint
         HIP_TRY(c->bseg.ensure((2 * seg_words + pref_words) * sizeof(uint32_t)));
         uint32_t *seg_lo = c->bseg.as<uint32_t>(), *seg_cnt = seg_lo + seg_words;
         uint32_t *pref = seg_cnt + seg_words;
-        HIP_TRY(launch_batch_seg(c->gid.as<uint32_t>(), B, G, seg_lo, seg_cnt, s));
+        if (!reuse) {
+            HIP_TRY(launch_batch_seg(c->gid.as<uint32_t>(), B, G, seg_lo, seg_cnt, s));
+            c->bprep_key = bkey;
+        }
 
         BatchArgs b;
         std::memset(&b, 0, sizeof(b));

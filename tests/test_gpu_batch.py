@@ -140,6 +140,38 @@ def test_weighted_batch(gg, orc, lpa, ctx):
     check_graphs(orc, b, lab, st, range(b.G), 0.02, 15)
 
 
+def test_reuse_csr_batches(gg, orc, lpa):
+    # a context that keeps the relabelled copy gives what a fresh one gives:
+    # on repeated calls, on the same CSR split into other graphs (adjacent
+    # graphs merged: their arcs still stay inside), and after a call on
+    # another graph replaced the copy
+    b = gg.pack(mixed_graphs(gg))
+    dg = lpa.DeviceGraph.from_csr(b.csr, "cuda")
+    gv2 = np.delete(b.gv, [3, 6])
+    other = lpa.DeviceGraph.from_csr(gg.rmat(10, seed=21), "cuda")
+
+    def fresh(gv):
+        with lpa.Context(0) as c:
+            lab, st = c.run_batch(dg, gv, tol=0.05)
+            return lpa.labels_to_numpy(lab), st
+
+    ref1, st1 = fresh(b.gv)
+    ref2, st2 = fresh(gv2)
+    with lpa.Context(0, reuse_csr=1) as c:
+        for gv, ref, st_ref in ((b.gv, ref1, st1), (b.gv, ref1, st1), (gv2, ref2, st2), (gv2, ref2, st2),
+                                (b.gv, ref1, st1)):
+            lab, st = c.run_batch(dg, gv, tol=0.05)
+            assert np.array_equal(lpa.labels_to_numpy(lab), ref)
+            assert np.array_equal(st.iterations, st_ref.iterations)
+            assert np.array_equal(st.changed_hist, st_ref.changed_hist)
+            assert st.arcs_processed == st_ref.arcs_processed
+        c.run(other, tol=0.05)
+        lab, st = c.run_batch(dg, b.gv, tol=0.05)
+        assert np.array_equal(lpa.labels_to_numpy(lab), ref1)
+        assert np.array_equal(st.changed_hist, st1.changed_hist)
+    check_graphs(orc, b, ref1, st1, range(b.G), 0.05, 20)
+
+
 @pytest.mark.parametrize("sw", [0, 2])
 def test_weighted_batch_with_zero_weights(gg, orc, lpa, sw):
     # weights 0..2: rows whose every tally is 0 (the lowest label wins, or
