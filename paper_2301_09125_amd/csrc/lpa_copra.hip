@@ -397,17 +397,25 @@ __device__ __forceinline__ uint32_t copra_first_block(const CopraArgs &a, uint32
     return best;
 }
 
-// One block per row of deg * V > 512 (rows listed in `rows`), a 4096-slot
-// LDS table; rows with too many distinct labels are listed for the global
-// table.
+// One block per row of deg * V > 512 (rows listed in `rows`), an LDS table
+// of 2048 slots when deg * V <= 1024 (never more than 3/4 full) and of 4096
+// otherwise; rows with too many distinct labels are listed for the global
+// table.  While a row is finished, the bounds and the first 256 column ids
+// of the block's next row are already on their way.
 __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count) {
     __shared__ uint32_t key[kCopraBlockSlots];
     __shared__ u64 tal[kCopraBlockSlots];
     __shared__ BlockRed red[3];
     __shared__ uint32_t klab[64], kcoef[64], kn, claimed, full;
+    const uint32_t V = a.V;
     u64 chg = 0;
+    // the row prefetched by the previous turn (kNone: none)
+    uint32_t pv = kNone, pu = 0, pw = 0;
+    uint64_t pb = 0, pe = 0;
     for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
         const uint32_t v = rows[it];
+        const bool have = pv == v;
+        pv = kNone;
         if (!copra_votes(a, v)) {
             copra_copy(a, v, threadIdx.x, 256);
             continue;
@@ -422,7 +430,10 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
             __syncthreads();
             continue;
         }
-        for (uint32_t s = threadIdx.x; s < kCopraBlockSlots; s += 256) {
+        const uint64_t b = have ? pb : a.g.rp[v], e = have ? pe : a.g.rp[v + 1];
+        const uint32_t S = (e - b) * V <= kCopraBlockSlots / 4 ? kCopraBlockSlots / 2 : kCopraBlockSlots;
+        const uint32_t fill = S / 4 * 3;
+        for (uint32_t s = threadIdx.x; s < S; s += 256) {
             key[s] = kEmptyKey;
             tal[s] = 0;
         }
@@ -431,26 +442,43 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
             claimed = 0;
             full = 0;
         }
+        // the next row's bounds
+        const uint32_t vn = it + gridDim.x < count ? rows[it + gridDim.x] : kNone;
+        uint64_t nb = 0, ne = 0;
+        if (vn != kNone) {
+            nb = a.g.rp[vn];
+            ne = a.g.rp[vn + 1];
+        }
         __syncthreads();
-        const uint64_t b = a.g.rp[v], e = a.g.rp[v + 1];
         u64 tw = 0;
         for (uint64_t k = b + threadIdx.x; k < e; k += 256) {
-            const uint32_t we = a.g.w ? a.g.w[k] : 1u;
+            const bool first = have && k == b + threadIdx.x;
+            const uint32_t we = first ? pw : (a.g.w ? a.g.w[k] : 1u);
             tw += we;
             if (__atomic_load_n(&full, __ATOMIC_RELAXED)) continue;
-            const uint32_t u = a.g.col[k];
+            const uint32_t u = first ? pu : a.g.col[k];
             const uint32_t c = a.in[(u64)u * a.stride];
             for (uint32_t i = 0; i < c; ++i) {
                 // the table is given up once 3/4 of it is claimed (or a probe
                 // finds no slot): the row then goes to the device-memory table
                 if (__atomic_load_n(&full, __ATOMIC_RELAXED)) break;
-                const int r = copra_insert_bounded(key, tal, kCopraBlockSlots - 1, a.in[(u64)u * a.stride + 2 + 2 * i],
+                const int r = copra_insert_bounded(key, tal, S - 1, a.in[(u64)u * a.stride + 2 + 2 * i],
                                                    (u64)we * a.in[(u64)u * a.stride + 3 + 2 * i]);
-                if (r < 0 || (r > 0 && atomicAdd(&claimed, 1u) + 1 >= kCopraBlockFill)) {
+                if (r < 0 || (r > 0 && atomicAdd(&claimed, 1u) + 1 >= fill)) {
                     __atomic_store_n(&full, 1u, __ATOMIC_RELAXED);
                     break;
                 }
             }
+        }
+        // the next row's first column ids and weights, read while this one
+        // is finished
+        if (vn != kNone) {
+            const uint64_t k = nb + threadIdx.x;
+            pu = k < ne ? a.g.col[k] : 0u;
+            pw = k < ne ? (a.g.w ? a.g.w[k] : 1u) : 0u;
+            pb = nb;
+            pe = ne;
+            pv = vn;
         }
         u64 z1 = 0, z2 = 0;
         uint32_t zo = 0;
@@ -460,8 +488,7 @@ __global__ __launch_bounds__(256) void copra_block_k(CopraArgs a, const uint32_t
             __syncthreads();
             continue;
         }
-        const uint32_t best = copra_finish_block(a, v, tie, key, tal, kCopraBlockSlots, tw * kOne, red, klab, kcoef,
-                                                 &kn);
+        const uint32_t best = copra_finish_block(a, v, tie, key, tal, S, tw * kOne, red, klab, kcoef, &kn);
         if (threadIdx.x == 0) chg += a.in[(u64)v * a.stride + 1] != best;
         __syncthreads();  // tables and reductions are reused by the next row
     }
