@@ -60,15 +60,15 @@ hipError_t launch_copra_init(uint32_t n, uint32_t stride, uint32_t *rec, hipStre
 // labels and coefficients (V slots per vertex) and their counts.
 hipError_t launch_copra_output(const uint32_t *rec, uint32_t n, uint32_t V, uint32_t stride, uint32_t *best,
                                uint32_t *labs, uint32_t *coefs, uint32_t *cnt, hipStream_t s);
-// Rows with arcs by class into rows0 (deg * V <= 32), rows1 (<= 512) and
-// rows2 (larger), count[0..3) (zeroed by the caller).
-hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,
-                             uint32_t *count, hipStream_t s);
+// Rows with arcs by class of deg * V into rows[0] (<= 32), rows[1] (<= 128),
+// rows[2] (<= 512) and rows[3] (larger), count[0..4) (zeroed by the caller).
+constexpr int kCopraClasses = 4;
+hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *const *rows, uint32_t *count, hipStream_t s);
 // Table sizes (next_pow2(2 * min(deg * V, n))) and piece counts (pieces of
 // at most `per` arcs) of the listed rows.
 hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count, uint32_t per,
                               unsigned long long *size, unsigned long long *npieces, hipStream_t s);
-// One half-round over the three row lists (count: host copy of their sizes).
+// One half-round over the kCopraClasses row lists (count: host copy of their sizes).
 hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *const *rows, const uint32_t *count,
                               hipStream_t s);
 // Device-table slots one decision block scans.

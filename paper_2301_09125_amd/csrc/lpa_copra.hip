@@ -24,9 +24,11 @@
 //   copra_group_k  rows with deg * V <= 32: 16 lanes per row, a 64-slot
 //                  LDS table;
 //   copra_wave_k   rows with deg * V <= 512: one wavefront per row, an LDS
-//                  table of next_pow2(2 * deg * V) slots (<= 1024);
-//   copra_block_k  the other rows: one block per row, a 4096-slot LDS
-//                  table; a row whose distinct labels would fill more than
+//                  table of next_pow2(2 * deg * V) slots (<= 256 for the
+//                  rows of deg * V <= 128, which run with a quarter of the
+//                  LDS and so four times the blocks per CU; <= 1024);
+//   copra_block_k  the other rows: one block per row, an LDS table of
+//                  2048 or 4096 slots; a row whose distinct labels would fill more than
 //                  3/4 of it is listed for
 //   copra_gpiece_k, copra_gscan_k, copra_gdone_k  the listed rows, with a
 //                  table in device memory of next_pow2(2 * min(deg * V, n))
@@ -45,7 +47,8 @@
 namespace lpa {
 
 constexpr uint32_t kOne = 65536u;
-constexpr uint32_t kCopraWaveSlots = 1024;
+constexpr uint32_t kCopraWaveSlots = 1024;      // rows of deg * V <= 512
+constexpr uint32_t kCopraWaveSlotsSmall = 256;  // rows of deg * V <= 128 (a quarter of the LDS)
 constexpr uint32_t kCopraBlockSlots = 4096;
 constexpr uint32_t kCopraBlockFill = 3072;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
@@ -224,10 +227,12 @@ __global__ __launch_bounds__(256) void copra_group_k(CopraArgs a, const uint32_t
     block_count(chg, a.changed);
 }
 
-// One wavefront per row, rows with 32 < deg * V <= 512 (listed in `rows`).
+// One wavefront per row, rows with 32 < deg * V <= SLOTS / 2 (listed in
+// `rows`), tables of up to SLOTS slots.
+template <uint32_t SLOTS>
 __global__ __launch_bounds__(256) void copra_wave_k(CopraArgs a, const uint32_t *__restrict__ rows, uint32_t count) {
-    __shared__ uint32_t skey[4][kCopraWaveSlots];
-    __shared__ u64 stal[4][kCopraWaveSlots];
+    __shared__ uint32_t skey[4][SLOTS];
+    __shared__ u64 stal[4][SLOTS];
     __shared__ uint32_t sklab[4][64], skcoef[4][64], skn[4];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -696,38 +701,41 @@ __global__ void copra_output_k(const uint32_t *rec, uint32_t n, uint32_t V, uint
 constexpr uint32_t kListBlocks = 1024;
 __device__ __forceinline__ int copra_class(const Graph &g, uint32_t V, uint32_t v) {
     const uint64_t d = (g.rp[v + 1] - g.rp[v]) * V;
-    return d == 0 ? -1 : d <= 32 ? 0 : d <= 512 ? 1 : 2;
+    return d == 0 ? -1 : d <= 32 ? 0 : d <= 128 ? 1 : d <= 512 ? 2 : 3;
 }
-__global__ __launch_bounds__(256) void copra_list_k(Graph g, uint32_t V, uint32_t *rows0, uint32_t *rows1,
-                                                    uint32_t *rows2, uint32_t *count) {
-    __shared__ uint32_t cnt[3], base[3];
+struct CopraLists {
+    uint32_t *rows[kCopraClasses];
+};
+__global__ __launch_bounds__(256) void copra_list_k(Graph g, uint32_t V, CopraLists L, uint32_t *count) {
+    constexpr int NC = kCopraClasses;
+    __shared__ uint32_t cnt[NC], base[NC];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t per = (g.n + gridDim.x - 1) / gridDim.x;
     const uint32_t lo = blockIdx.x * per, hi = min(lo + per, g.n);
-    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    if (threadIdx.x < NC) cnt[threadIdx.x] = 0;
     __syncthreads();
-    uint32_t mine[3] = {0, 0, 0};
+    uint32_t mine[NC] = {0, 0, 0, 0};
     for (uint32_t v = lo + threadIdx.x; v < hi; v += 256) {
         const int c = copra_class(g, V, v);
-        if (c >= 0) ++mine[c];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) mine[k] += c == k ? 1u : 0u;
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NC; ++c) {
         const uint32_t t = wave_sum(mine[c]);
         if (lane == 0 && t) atomicAdd(&cnt[c], t);
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < NC) {
         base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&count[threadIdx.x], cnt[threadIdx.x]) : 0u;
         cnt[threadIdx.x] = 0;  // reused as this block's write cursor
     }
     __syncthreads();
-    uint32_t *dst[3] = {rows0, rows1, rows2};
     for (uint32_t v0 = lo + (threadIdx.x & ~63u); v0 < hi; v0 += 256) {  // wavefront-uniform steps
         const uint32_t v = v0 + lane;
         const int cls = v < hi ? copra_class(g, V, v) : -1;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NC; ++c) {
             const u64 m = __ballot(cls == c);
             if (!m) continue;
             const int lead = __ffsll((long long)m) - 1;
@@ -735,7 +743,7 @@ __global__ __launch_bounds__(256) void copra_list_k(Graph g, uint32_t V, uint32_
             if ((int)lane == lead) at = atomicAdd(&cnt[c], (uint32_t)__popcll(m));
             at = (uint32_t)__shfl((int)at, lead, 64);
             if (cls == c)
-                dst[c][base[c] + at +
+                L.rows[c][base[c] + at +
                        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = v;
         }
     }
@@ -877,10 +885,11 @@ hipError_t launch_copra_output(const uint32_t *rec, uint32_t n, uint32_t V, uint
     copra_output_k<<<grid_for(n, 256, 8192), 256, 0, s>>>(rec, n, V, stride, best, labs, coefs, cnt);
     return hipGetLastError();
 }
-hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *rows0, uint32_t *rows1, uint32_t *rows2,
-                             uint32_t *count, hipStream_t s) {
+hipError_t launch_copra_list(const Graph &g, uint32_t V, uint32_t *const *rows, uint32_t *count, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    copra_list_k<<<grid_for(g.n, 256, kListBlocks), 256, 0, s>>>(g, V, rows0, rows1, rows2, count);
+    CopraLists L;
+    for (int c = 0; c < kCopraClasses; ++c) L.rows[c] = rows[c];
+    copra_list_k<<<grid_for(g.n, 256, kListBlocks), 256, 0, s>>>(g, V, L, count);
     return hipGetLastError();
 }
 hipError_t launch_copra_sizes(const Graph &g, uint32_t V, const uint32_t *rows, uint32_t count, uint32_t per,
@@ -897,11 +906,15 @@ hipError_t launch_copra_round(const CopraArgs &a, const uint32_t *const *rows, c
         e = hipGetLastError();
     }
     if (e == hipSuccess && count[1]) {
-        copra_wave_k<<<grid_for(count[1], 4, 8192), 256, 0, s>>>(a, rows[1], count[1]);
+        copra_wave_k<kCopraWaveSlotsSmall><<<grid_for(count[1], 4, 8192), 256, 0, s>>>(a, rows[1], count[1]);
         e = hipGetLastError();
     }
     if (e == hipSuccess && count[2]) {
-        copra_block_k<<<grid_for(count[2], 1, 4096), 256, 0, s>>>(a, rows[2], count[2]);
+        copra_wave_k<kCopraWaveSlots><<<grid_for(count[2], 4, 8192), 256, 0, s>>>(a, rows[2], count[2]);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && count[3]) {
+        copra_block_k<<<grid_for(count[3], 1, 4096), 256, 0, s>>>(a, rows[3], count[3]);
         e = hipGetLastError();
     }
     return e;

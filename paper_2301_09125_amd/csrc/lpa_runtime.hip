@@ -109,7 +109,7 @@ struct lpa_ctx {
     DevBuf t_w, t_m, t_v, t_part, t_grad, t_loss, t_z;                               // training
     DevBuf tune_labels, tune_hist;                                                    // autotuner
     DevBuf cp_rec[2], cp_rows, cp_ovf, cp_off, cp_key, cp_tal;  // COPRA
-    DevBuf cp_first, cp_pieces, cp_total, cp_rows1, cp_rows2, cp_distinct, cp_sfirst, cp_slices, cp_rowstate,
+    DevBuf cp_first, cp_pieces, cp_total, cp_rows1, cp_rows2, cp_rows3, cp_distinct, cp_sfirst, cp_slices, cp_rowstate,
         cp_wsum;
     std::map<std::vector<int>, lpa_options> tune_cache;
     // the CSR and thresholds the internal copy was last built for by a
@@ -1469,8 +1469,8 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
     if (n == 0) return LPA_OK;
     const Graph G{g->row_ptr, g->col, g->w, n, g->m};
     // counters: kCountWords changed words, then the overflow count (word
-    // kCountWords), the error word (kCountWords + 1) and the three row-list
-    // sizes (kCountWords + 2 ..)
+    // kCountWords), the error word (kCountWords + 1) and the kCopraClasses
+    // row-list sizes (u32 from word kCountWords + 2 on)
     HIP_TRY(c->counters.ensure((kCountWords + 8) * sizeof(u64)));
     u64 *cw = c->counters.as<u64>();
     uint32_t *ovf_count = reinterpret_cast<uint32_t *>(cw + kCountWords);
@@ -1490,16 +1490,18 @@ lpa_status copra_impl(lpa_ctx *c, const lpa_csr *g, uint32_t V, uint32_t *best_o
     HIP_TRY(c->cp_rows.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->cp_rows1.ensure((size_t)n * sizeof(uint32_t)));
     HIP_TRY(c->cp_rows2.ensure((size_t)n * sizeof(uint32_t)));
+    HIP_TRY(c->cp_rows3.ensure((size_t)n * sizeof(uint32_t)));
     // both buffers start alone: rows without arcs are never voted again
     for (int b = 0; b < 2; ++b) HIP_TRY(launch_copra_init(n, stride, c->cp_rec[b].as<uint32_t>(), s));
-    HIP_TRY(launch_copra_list(G, V, c->cp_rows.as<uint32_t>(), c->cp_rows1.as<uint32_t>(),
-                              c->cp_rows2.as<uint32_t>(), list_count, s));
-    HIP_TRY(hipMemcpyAsync(c->pinned, list_count, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    uint32_t *const list_w[kCopraClasses] = {c->cp_rows.as<uint32_t>(), c->cp_rows1.as<uint32_t>(),
+                                             c->cp_rows2.as<uint32_t>(), c->cp_rows3.as<uint32_t>()};
+    HIP_TRY(launch_copra_list(G, V, list_w, list_count, s));
+    HIP_TRY(hipMemcpyAsync(c->pinned, list_count, kCopraClasses * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    uint32_t n_list[3];
+    uint32_t n_list[kCopraClasses];
     std::memcpy(n_list, c->pinned, sizeof(n_list));
-    const uint32_t *lists[3] = {c->cp_rows.as<uint32_t>(), c->cp_rows1.as<uint32_t>(), c->cp_rows2.as<uint32_t>()};
-    const uint32_t n_big = n_list[2];
+    const uint32_t *lists[kCopraClasses] = {list_w[0], list_w[1], list_w[2], list_w[3]};
+    const uint32_t n_big = n_list[kCopraClasses - 1];
     HIP_TRY(c->cp_ovf.ensure((size_t)(n_big ? n_big : 1) * sizeof(uint32_t)));
 
     const uint64_t thr = (uint64_t)std::floor(tol * (double)n);
@@ -2043,7 +2045,7 @@ void lpa_destroy(lpa_ctx *c) {
                       &c->f_small, &c->f_model, &c->t_w, &c->t_m, &c->t_v, &c->t_part, &c->t_grad,
                       &c->t_loss, &c->t_z, &c->tune_labels, &c->tune_hist,
                       &c->cp_rec[0], &c->cp_rec[1], &c->cp_rows, &c->cp_ovf, &c->cp_off, &c->cp_key, &c->cp_tal,
-                      &c->cp_first, &c->cp_pieces, &c->cp_total, &c->cp_rows1, &c->cp_rows2,
+                      &c->cp_first, &c->cp_pieces, &c->cp_total, &c->cp_rows1, &c->cp_rows2, &c->cp_rows3,
                       &c->cp_distinct, &c->cp_sfirst, &c->cp_slices, &c->cp_rowstate, &c->cp_wsum};
     if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
