@@ -77,6 +77,8 @@ typedef struct {
  *   reports its 4 heaviest labels and a bound on the rest; a row whose
  *   leader provably wins is decided from the reports, any other row merges
  *   its segments' full tallies in a global hashtable slab.
+ * (lpa_run; lpa_run_batch votes the rows of degree <= group_max one per lane,
+ * their labels sorted in registers.)
  * Any valid thresholds give the same labels; they only change speed.
  * 0 selects the default. */
 typedef struct {
