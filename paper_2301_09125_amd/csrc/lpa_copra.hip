@@ -50,7 +50,6 @@ constexpr uint32_t kOne = 65536u;
 constexpr uint32_t kCopraWaveSlots = 1024;      // rows of deg * V <= 512
 constexpr uint32_t kCopraWaveSlotsSmall = 256;  // rows of deg * V <= 128 (a quarter of the LDS)
 constexpr uint32_t kCopraBlockSlots = 4096;
-constexpr uint32_t kCopraBlockFill = 3072;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 constexpr uint32_t kSliceSlots = kCopraSliceSlots;
 

@@ -282,7 +282,8 @@ hipError_t launch_bin_count(const Graph &g, const BinCfg &cfg, uint32_t *blk_cou
 hipError_t launch_bin_scan(uint32_t *blk_counts, unsigned long long *blk_arcs, uint32_t nblk, uint32_t *totals,
                            unsigned long long *arc_totals, hipStream_t s);
 hipError_t launch_bin_scatter(const Graph &g, const BinCfg &cfg, const uint32_t *blk_offsets,
-                              const unsigned long long *blk_arc_offsets, uint32_t nblk, uint32_t *old_of,
+                              const unsigned long long *blk_arc_offsets, const uint32_t *totals,
+                              const unsigned long long *arc_totals, uint32_t nblk, uint32_t *old_of,
                               uint32_t *new_of, uint64_t *rp2, hipStream_t s);
 // Copy the caller's rows into the internal CSR (ids through new_of) and
 // flag rows that list each neighbour once.

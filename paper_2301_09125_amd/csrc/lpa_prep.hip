@@ -151,125 +151,121 @@ __global__ __launch_bounds__(256) void bin_count_k(Graph g, BinCfg cfg, uint32_t
     }
 }
 
-// Exclusive prefix sums of the per-block bin counts and arc counts, bin-major
-// (every block of bin 0, then bin 1, ...), in one block of 1024 threads.
-// Wavefront w owns a contiguous run of whole 64-entry chunks and reads it
-// coalesced, kScanJ chunks per step with their loads issued together (the
-// counts were written by other CUs, so each load goes to the memory side);
-// pass 1 sums each wavefront's run, pass 2 scans it chunk by chunk from the
-// wavefront's offset.
+// Exclusive prefix sums of the per-block counts and arc counts of one bin
+// (blockIdx.x), in one block of 1024 threads per bin, and the bin's totals;
+// bin_scatter_k adds the totals of the bins before it.  Wavefront w owns a
+// contiguous run of whole 64-entry chunks and reads it coalesced, kScanJ
+// chunks per step with their loads issued together (the counts were written
+// by other CUs, so each load goes to the memory side); pass 1 sums each
+// wavefront's run, pass 2 scans it chunk by chunk from the wavefront's offset.
 constexpr int kScanJ = 8;
 __global__ __launch_bounds__(1024) void bin_scan_k(uint32_t *blk_counts, u64 *blk_arcs, uint32_t nblk,
                                                    uint32_t *totals, u64 *arc_totals) {
-    __shared__ uint32_t wtot[16][NBINS];
-    __shared__ u64 watot[16][NBINS];
+    __shared__ uint32_t wtot[16];
+    __shared__ u64 watot[16];
     const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t b = blockIdx.x;
     const uint32_t chunks = (nblk + 63) / 64;
     const uint32_t cpw = (chunks + 15) / 16;
     const uint32_t lo = min(wave * cpw * 64, nblk), hi = min(lo + cpw * 64, nblk);
-#pragma unroll 1
-    for (int b = 0; b < NBINS; ++b) {
-        const uint32_t *cnt = blk_counts + (size_t)b * nblk;
-        const u64 *arc = blk_arcs + (size_t)b * nblk;
-        uint32_t x = 0;
-        u64 y = 0;
-        for (uint32_t i0 = lo; i0 < hi; i0 += 64 * kScanJ) {
-            uint32_t xs[kScanJ];
-            u64 ys[kScanJ];
+    uint32_t *cnt = blk_counts + (size_t)b * nblk;
+    u64 *arc = blk_arcs + (size_t)b * nblk;
+    uint32_t x = 0;
+    u64 y = 0;
+    for (uint32_t i0 = lo; i0 < hi; i0 += 64 * kScanJ) {
+        uint32_t xs[kScanJ];
+        u64 ys[kScanJ];
 #pragma unroll
-            for (int j = 0; j < kScanJ; ++j) {
-                const uint32_t i = i0 + 64u * j + lane;
-                const uint32_t ic = i < hi ? i : lo;  // lo < hi here: an entry of this run
-                xs[j] = cnt[ic];
-                ys[j] = arc[ic];
+        for (int j = 0; j < kScanJ; ++j) {
+            const uint32_t i = i0 + 64u * j + lane;
+            const uint32_t ic = i < hi ? i : lo;  // lo < hi here: an entry of this run
+            xs[j] = cnt[ic];
+            ys[j] = arc[ic];
+        }
+#pragma unroll
+        for (int j = 0; j < kScanJ; ++j)
+            if (i0 + 64u * j + lane < hi) {
+                x += xs[j];
+                y += ys[j];
             }
-#pragma unroll
-            for (int j = 0; j < kScanJ; ++j)
-                if (i0 + 64u * j + lane < hi) {
-                    x += xs[j];
-                    y += ys[j];
-                }
-        }
-        x = wave_sum(x);
-        y = wave_sum(y);
-        if (lane == 0) {
-            wtot[wave][b] = x;
-            watot[wave][b] = y;
-        }
+    }
+    x = wave_sum(x);
+    y = wave_sum(y);
+    if (lane == 0) {
+        wtot[wave] = x;
+        watot[wave] = y;
     }
     __syncthreads();
-    uint32_t base = 0;
-    u64 abase = 0;
-#pragma unroll 1
-    for (int b = 0; b < NBINS; ++b) {
-        uint32_t run = base, total = 0;
-        u64 arun = abase, atotal = 0;
-        for (uint32_t w = 0; w < 16; ++w) {
-            if (w < wave) {
-                run += wtot[w][b];
-                arun += watot[w][b];
-            }
-            total += wtot[w][b];
-            atotal += watot[w][b];
+    uint32_t run = 0, total = 0;
+    u64 arun = 0, atotal = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+        if (w < wave) {
+            run += wtot[w];
+            arun += watot[w];
         }
-        uint32_t *cnt = blk_counts + (size_t)b * nblk;
-        u64 *arc = blk_arcs + (size_t)b * nblk;
-        for (uint32_t i0 = lo; i0 < hi; i0 += 64 * kScanJ) {
-            uint32_t xs[kScanJ];
-            u64 ys[kScanJ];
+        total += wtot[w];
+        atotal += watot[w];
+    }
+    for (uint32_t i0 = lo; i0 < hi; i0 += 64 * kScanJ) {
+        uint32_t xs[kScanJ];
+        u64 ys[kScanJ];
 #pragma unroll
-            for (int j = 0; j < kScanJ; ++j) {
-                const uint32_t i = i0 + 64u * j + lane;
-                const uint32_t ic = i < hi ? i : lo;
-                const uint32_t xv = cnt[ic];
-                const u64 yv = arc[ic];
-                xs[j] = i < hi ? xv : 0u;
-                ys[j] = i < hi ? yv : 0ull;
-            }
+        for (int j = 0; j < kScanJ; ++j) {
+            const uint32_t i = i0 + 64u * j + lane;
+            const uint32_t ic = i < hi ? i : lo;
+            const uint32_t xv = cnt[ic];
+            const u64 yv = arc[ic];
+            xs[j] = i < hi ? xv : 0u;
+            ys[j] = i < hi ? yv : 0ull;
+        }
 #pragma unroll
-            for (int j = 0; j < kScanJ; ++j) {
-                uint32_t xi = xs[j];
-                u64 yi = ys[j];
+        for (int j = 0; j < kScanJ; ++j) {
+            uint32_t xi = xs[j];
+            u64 yi = ys[j];
 #pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t xu = __shfl_up(xi, off, 64);
-                    const u64 yu = __shfl_up(yi, off, 64);
-                    if ((int)lane >= off) {
-                        xi += xu;
-                        yi += yu;
-                    }
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t xu = __shfl_up(xi, off, 64);
+                const u64 yu = __shfl_up(yi, off, 64);
+                if ((int)lane >= off) {
+                    xi += xu;
+                    yi += yu;
                 }
-                const uint32_t i = i0 + 64u * j + lane;
-                if (i < hi) {
-                    cnt[i] = run + xi - xs[j];
-                    arc[i] = arun + yi - ys[j];
-                }
-                run += (uint32_t)__shfl((int)xi, 63, 64);
-                arun += __shfl(yi, 63, 64);
             }
+            const uint32_t i = i0 + 64u * j + lane;
+            if (i < hi) {
+                cnt[i] = run + xi - xs[j];
+                arc[i] = arun + yi - ys[j];
+            }
+            run += (uint32_t)__shfl((int)xi, 63, 64);
+            arun += __shfl(yi, 63, 64);
         }
-        if (t == 0) {
-            totals[b] = total;
-            arc_totals[b] = atotal;
-        }
-        base += total;
-        abase += atotal;
+    }
+    if (t == 0) {
+        totals[b] = total;
+        arc_totals[b] = atotal;
     }
 }
 
 // Internal id, internal row start and the two id maps.
 __global__ __launch_bounds__(256) void bin_scatter_k(Graph g, BinCfg cfg, const uint32_t *blk_offsets,
-                                                     const u64 *blk_arc_offsets,
-                                                     uint32_t nblk, uint32_t *old_of, uint32_t *new_of,
-                                                     uint64_t *rp2) {
+                                                     const u64 *blk_arc_offsets, const uint32_t *totals,
+                                                     const u64 *arc_totals, uint32_t nblk, uint32_t *old_of,
+                                                     uint32_t *new_of, uint64_t *rp2) {
     __shared__ uint32_t wcnt[4][NBINS];
     __shared__ u64 warc[4][NBINS];
     __shared__ uint32_t run[NBINS];
     __shared__ u64 arun[NBINS];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x < NBINS) {
-        run[threadIdx.x] = blk_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
-        arun[threadIdx.x] = blk_arc_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
+        // offsets inside the bin, plus the totals of the bins before it
+        uint32_t base = 0;
+        u64 abase = 0;
+        for (uint32_t b = 0; b < threadIdx.x; ++b) {
+            base += totals[b];
+            abase += arc_totals[b];
+        }
+        run[threadIdx.x] = base + blk_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
+        arun[threadIdx.x] = abase + blk_arc_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
     }
     for (int i = 0; i < 4; ++i) {
         const uint32_t v = blockIdx.x * kBinVerts + i * 256 + threadIdx.x;
@@ -327,13 +323,14 @@ hipError_t launch_bin_count(const Graph &g, const BinCfg &cfg, uint32_t *blk_cou
 }
 hipError_t launch_bin_scan(uint32_t *blk_counts, u64 *blk_arcs, uint32_t nblk, uint32_t *totals, u64 *arc_totals,
                            hipStream_t s) {
-    bin_scan_k<<<1, 1024, 0, s>>>(blk_counts, blk_arcs, nblk, totals, arc_totals);
+    bin_scan_k<<<NBINS, 1024, 0, s>>>(blk_counts, blk_arcs, nblk, totals, arc_totals);
     return hipGetLastError();
 }
 hipError_t launch_bin_scatter(const Graph &g, const BinCfg &cfg, const uint32_t *blk_offsets,
-                              const u64 *blk_arc_offsets, uint32_t nblk, uint32_t *old_of, uint32_t *new_of,
-                              uint64_t *rp2, hipStream_t s) {
-    bin_scatter_k<<<nblk, 256, 0, s>>>(g, cfg, blk_offsets, blk_arc_offsets, nblk, old_of, new_of, rp2);
+                              const u64 *blk_arc_offsets, const uint32_t *totals, const u64 *arc_totals,
+                              uint32_t nblk, uint32_t *old_of, uint32_t *new_of, uint64_t *rp2, hipStream_t s) {
+    bin_scatter_k<<<nblk, 256, 0, s>>>(g, cfg, blk_offsets, blk_arc_offsets, totals, arc_totals, nblk, old_of,
+                                       new_of, rp2);
     return hipGetLastError();
 }
 
@@ -422,40 +419,68 @@ __global__ __launch_bounds__(1024) void hub_scan_k(u64 *blk, uint32_t nb, u64 *o
 }
 
 // Offsets, segments, reduce items, flags, slab masks and merge lists of
-// every long row.
+// every long row.  A block's segment and reduce items are written by all its
+// threads together (item k of the block goes to the row whose prefix is the
+// last one <= k), since one row can hold thousands of them.
+__device__ __forceinline__ uint32_t last_at_most(const uint32_t *pre, uint32_t k) {
+    uint32_t j = 0;
+#pragma unroll
+    for (uint32_t step = 512; step >= 1; step >>= 1)
+        if (pre[j + step] <= k) j += step;
+    return j;  // the largest j <= 1023 with pre[j] <= k (pre[0] = 0, pre nondecreasing)
+}
+
 __global__ __launch_bounds__(1024) void hub_fill_k(const uint64_t *rp2, uint32_t H, uint32_t merge_max,
                                                    const u64 *blk, const u64 *tot, uint32_t *item_lo,
                                                    uint64_t *slab_off, uint64_t *touched_off, HubItem *items,
                                                    ReduceItem *ritems, uint32_t *hflags, uint32_t *slab_mask,
                                                    uint32_t *mrows) {
     __shared__ u64 wtot[16];
-    const uint32_t h = blockIdx.x * 1024 + threadIdx.x;
+    __shared__ uint32_t ipre[1025], rpre[1025];  // the block's item and reduce-item prefixes
+    const uint32_t h0 = blockIdx.x * 1024, h = h0 + threadIdx.x;
     HubRow r{0, 0, 0, 0, 0, 0};
     if (h < H) r = hub_row(rp2, h, merge_max);
     u64 c0 = blk[(size_t)blockIdx.x * 6 + 0], c1 = blk[(size_t)blockIdx.x * 6 + 1], c2 = blk[(size_t)blockIdx.x * 6 + 2];
     u64 c3 = blk[(size_t)blockIdx.x * 6 + 3], c4 = blk[(size_t)blockIdx.x * 6 + 4], c5 = blk[(size_t)blockIdx.x * 6 + 5];
+    const u64 ibase = c0, rbase = c3;
     const u64 pi = block_scan_1024(r.nseg, wtot, c0);
     const u64 ps = block_scan_1024(r.slots, wtot, c1);
     const u64 pt = block_scan_1024(r.d, wtot, c2);
     const u64 pr = block_scan_1024(r.red, wtot, c3);
     const u64 pw = block_scan_1024(r.mw, wtot, c4);
     const u64 pb = block_scan_1024(r.mb, wtot, c5);
-    if (h >= H) return;
-    item_lo[h] = (uint32_t)pi;
-    if (h == H - 1) item_lo[H] = (uint32_t)tot[0];
-    slab_off[h] = ps;
-    touched_off[h] = pt;
-    hflags[h] = (!r.mw && !r.mb) ? HUB_BIG : 0u;
-    slab_mask[h] = (uint32_t)(r.slots - 1);
-    const uint64_t b = rp2[h], e = rp2[h + 1];
-    uint32_t k = (uint32_t)pi;
-    for (uint64_t x = b; x < e; x += kWaveArcs) items[k++] = HubItem{h, 0, x, min(e, x + (uint64_t)kWaveArcs)};
-    uint32_t q = (uint32_t)pr;
-    for (uint64_t t = 0; t < r.d; t += 2048) ritems[q++] = ReduceItem{h, (uint32_t)t, (uint32_t)min(r.d, t + 2048), 0};
-    if (r.mw)
-        mrows[pw] = h;
-    else if (r.mb)
-        mrows[tot[4] + pb] = h;
+    ipre[threadIdx.x] = (uint32_t)(pi - ibase);
+    rpre[threadIdx.x] = (uint32_t)(pr - rbase);
+    if (threadIdx.x == 0) {
+        ipre[1024] = (uint32_t)(c0 - ibase);
+        rpre[1024] = (uint32_t)(c3 - rbase);
+    }
+    if (h < H) {
+        item_lo[h] = (uint32_t)pi;
+        if (h == H - 1) item_lo[H] = (uint32_t)tot[0];
+        slab_off[h] = ps;
+        touched_off[h] = pt;
+        hflags[h] = (!r.mw && !r.mb) ? HUB_BIG : 0u;
+        slab_mask[h] = (uint32_t)(r.slots - 1);
+        if (r.mw)
+            mrows[pw] = h;
+        else if (r.mb)
+            mrows[tot[4] + pb] = h;
+    }
+    __syncthreads();
+    const uint32_t ni = (uint32_t)(c0 - ibase), nr = (uint32_t)(c3 - rbase);
+    for (uint32_t k = threadIdx.x; k < ni; k += 1024) {
+        const uint32_t j = last_at_most(ipre, k);
+        const uint64_t b = rp2[h0 + j], e = rp2[h0 + j + 1];
+        const uint64_t x = b + (uint64_t)(k - ipre[j]) * kWaveArcs;
+        items[ibase + k] = HubItem{h0 + j, 0, x, min(e, x + (uint64_t)kWaveArcs)};
+    }
+    for (uint32_t k = threadIdx.x; k < nr; k += 1024) {
+        const uint32_t j = last_at_most(rpre, k);
+        const uint64_t d = rp2[h0 + j + 1] - rp2[h0 + j];
+        const uint64_t t = (uint64_t)(k - rpre[j]) * 2048;
+        ritems[rbase + k] = ReduceItem{h0 + j, (uint32_t)t, (uint32_t)min(d, t + 2048), 0};
+    }
 }
 
 hipError_t launch_hub_plan(const uint64_t *rp2, uint32_t H, uint32_t merge_max, u64 *blk, u64 *out, hipStream_t s) {

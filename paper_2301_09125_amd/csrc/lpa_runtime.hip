@@ -299,8 +299,8 @@ lpa_status prepare(lpa_ctx *c, const lpa_csr *g, Plan &P, uint32_t *err_dev, boo
     const BinCfg cfg{o.thread_max, o.group_max, o.wave_max, o.wide_max};
     HIP_TRY(launch_bin_count(G, cfg, c->blk_counts.as<uint32_t>(), c->blk_arcs.as<u64>(), nblk, err_dev, s));
     HIP_TRY(launch_bin_scan(c->blk_counts.as<uint32_t>(), c->blk_arcs.as<u64>(), nblk, totals, arc_totals, s));
-    HIP_TRY(launch_bin_scatter(G, cfg, c->blk_counts.as<uint32_t>(), c->blk_arcs.as<u64>(), nblk,
-                               c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(), s));
+    HIP_TRY(launch_bin_scatter(G, cfg, c->blk_counts.as<uint32_t>(), c->blk_arcs.as<u64>(), totals, arc_totals,
+                               nblk, c->old_of.as<uint32_t>(), c->new_of.as<uint32_t>(), c->rp2.as<uint64_t>(), s));
     HIP_TRY(launch_fill_u64(reinterpret_cast<u64 *>(c->rp2.as<uint64_t>() + n), g->m, 1, s));
     LPA_TRY(ensure_pinned(c, 16));
     HIP_TRY(hipMemcpyAsync(c->pinned, c->small.p, 32 + NBINS * sizeof(u64), hipMemcpyDeviceToHost, s));

@@ -757,25 +757,33 @@ __global__ __launch_bounds__(256) void hub_fallback_k(RoundArgs a, const HubItem
     ListedTable t{table + wave * kWaveSlots, lists + wave * kWaveArcs, 0, 0};
     for (uint32_t s = lane; s < kWaveSlots; s += 64) t.T[s] = EMPTY_SLOT;
     wave_sync();
-    for (uint32_t it = blockIdx.x * 4 + wave; it < count; it += gridDim.x * 4) {
-        const HubItem item = items[it];
-        const uint32_t h = item.r;
-        if (!(hs.flags[h] & HUB_FALLBACK)) continue;  // uniform over the wavefront
-        const uint32_t own = a.L_old[h];
-        uint32_t u[A], lab[A], wt[A];
-        uint32_t valid = 0;
-        load_arcs<A, 64>(a, item.b0 + lane, item.b1, u, wt, valid);
-        gather_labels<A>(a, u, valid, lab);
-        u64 own_w = 0, rs = 0;
-        uint32_t own_hit = 0, rem = 0;
-        split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
-        uint32_t S = next_pow2(2u * (uint32_t)(item.b1 - item.b0));
-        S = S < 64u ? 64u : (S > (uint32_t)kWaveSlots ? (uint32_t)kWaveSlots : S);
-        t.mask = S - 1;
-        listed_tally<A, 2>(t, lab, wt, rem);
-        wave_sync();
-        flush_listed_to_slab(t, hs, h);
-        wave_sync();
+    // The wavefront's items are wid, wid + stride, ...; their rows' flags are
+    // read 64 items at a time (one per lane), so the few segments of rows that
+    // fell back are found without a dependent load chain per item.
+    const uint64_t wid = blockIdx.x * 4 + wave, stride = gridDim.x * 4;
+    for (uint64_t j0 = 0; wid + j0 * stride < count; j0 += 64) {
+        const uint64_t i = wid + (j0 + lane) * stride;
+        bool fb = false;
+        if (i < count) fb = (hs.flags[items[i].r] & HUB_FALLBACK) != 0;
+        for (u64 m = __ballot(fb); m; m &= m - 1) {
+            const HubItem item = items[wid + (j0 + (uint64_t)__builtin_ctzll(m)) * stride];
+            const uint32_t h = item.r;
+            const uint32_t own = a.L_old[h];
+            uint32_t u[A], lab[A], wt[A];
+            uint32_t valid = 0;
+            load_arcs<A, 64>(a, item.b0 + lane, item.b1, u, wt, valid);
+            gather_labels<A>(a, u, valid, lab);
+            u64 own_w = 0, rs = 0;
+            uint32_t own_hit = 0, rem = 0;
+            split_own<A>(lab, wt, valid, own, own_w, own_hit, rem, rs);
+            uint32_t S = next_pow2(2u * (uint32_t)(item.b1 - item.b0));
+            S = S < 64u ? 64u : (S > (uint32_t)kWaveSlots ? (uint32_t)kWaveSlots : S);
+            t.mask = S - 1;
+            listed_tally<A, 2>(t, lab, wt, rem);
+            wave_sync();
+            flush_listed_to_slab(t, hs, h);
+            wave_sync();
+        }
     }
 }
 
@@ -810,51 +818,74 @@ __global__ __launch_bounds__(256) void hub_merge_wave_k(RoundArgs a, HubState hs
     }
     wave_sync();
     u64 wchg = 0;
-    for (uint32_t i = blockIdx.x * 4 + wave; i < count; i += gridDim.x * 4) {
-        const uint32_t h = rows[i];
-        const uint32_t flags = hs.flags[h];
-        if (first && !(flags & HUB_REPEATS)) continue;  // decided through best[]
-        if (flags & HUB_FALLBACK) continue;              // a segment spilled: slab pass
-        const RowMode rm = row_mode(a, h);
-        if (!rm.on) continue;  // the other half: hub_final_k copies its label
-        const Tie tie = rm.tie;
-        const uint32_t lo = hs.item_lo[h], ns = hs.item_lo[h + 1] - lo;
-        const u64 T = wave_sum((u64)(lane < ns ? hs.thr[lo + lane] : 0u));
-        for (uint32_t e = lane; e < ns * kTopK; e += 64) {
-            const u64 x = hs.cand[(u64)lo * kTopK + e];
-            if (x != EMPTY_SLOT) merge_insert(mk, lb, tr, MS - 1, (uint32_t)(x >> 32), (uint32_t)x, hs.thr[lo + e / kTopK]);
-        }
-        wave_sync();
-        const uint32_t own = a.L_old[h];
-        u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(tie, own, hs.own_sum[h] + a.sw) : 0ull;
-        for (uint32_t s = lane; s < MS; s += 64)
-            if (mk[s] != kNone) xkey = umax64(xkey, vote_key(tie, mk[s], lb[s]));
-        xkey = wave_max64(xkey);
-        const uint32_t xs = key_label(tie, xkey);
-        const u64 V = xkey >> 32;
-        bool bad = false;
-        for (uint32_t s = lane; s < MS; s += 64) {
-            const uint32_t lab = mk[s];
-            if (lab != kNone) {
-                if (lab != xs && vote_key(tie, lab, (u64)lb[s] + T - tr[s]) >= xkey) bad = true;
-                mk[s] = kNone;
-                lb[s] = 0;
-                tr[s] = 0;
+    // The wavefront's rows are rows[wid], rows[wid + stride], ...; 64 of them
+    // are looked up at once (one per lane: row, flags, segment range, own
+    // label and tally), then merged one after the other.
+    const uint64_t wid = blockIdx.x * 4 + wave, stride = gridDim.x * 4;
+    for (uint64_t j0 = 0; wid + j0 * stride < count; j0 += 64) {
+        const uint64_t ii = wid + (j0 + lane) * stride;
+        uint32_t hl = 0, fl = 0, lol = 0, nsl = 0, ownl = 0;
+        u64 osl = 0;
+        bool go = false;
+        if (ii < count) {
+            hl = rows[ii];
+            fl = hs.flags[hl];
+            // rows decided through best[] in round 1, rows whose segment
+            // spilled (slab pass), and the other half of a semi-synchronous
+            // round (hub_final_k copies its label) are not merged here
+            go = !(first && !(fl & HUB_REPEATS)) && !(fl & HUB_FALLBACK) && row_mode(a, hl).on;
+            if (go) {
+                lol = hs.item_lo[hl];
+                nsl = hs.item_lo[hl + 1] - lol;
+                ownl = a.L_old[hl];
+                osl = hs.own_sum[hl];
             }
         }
-        bad |= (T > 0 && T >= V);
-        const bool decided = __ballot(bad) == 0;
-        if (lane == 0) {
-            if (decided) {
-                const uint32_t nl = xkey ? xs : own;
-                a.L_new[h] = nl;
-                wchg += nl != own;
-            } else {
-                atomicOr(&hs.flags[h], HUB_FALLBACK);
-                atomicOr(hs.pending, 1u);
+        for (u64 m = __ballot(go); m; m &= m - 1) {
+            const int l = (int)__builtin_ctzll(m);
+            const uint32_t h = __builtin_amdgcn_readlane(hl, l);
+            const uint32_t flags = __builtin_amdgcn_readlane(fl, l);
+            const uint32_t lo = __builtin_amdgcn_readlane(lol, l), ns = __builtin_amdgcn_readlane(nsl, l);
+            const uint32_t own = __builtin_amdgcn_readlane(ownl, l);
+            const u64 own_sum = ((u64)__builtin_amdgcn_readlane((uint32_t)(osl >> 32), l) << 32) |
+                                __builtin_amdgcn_readlane((uint32_t)osl, l);
+            const Tie tie = row_mode(a, h).tie;
+            const u64 T = wave_sum((u64)(lane < ns ? hs.thr[lo + lane] : 0u));
+            for (uint32_t e = lane; e < ns * kTopK; e += 64) {
+                const u64 x = hs.cand[(u64)lo * kTopK + e];
+                if (x != EMPTY_SLOT) merge_insert(mk, lb, tr, MS - 1, (uint32_t)(x >> 32), (uint32_t)x, hs.thr[lo + e / kTopK]);
             }
+            wave_sync();
+            u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(tie, own, own_sum + a.sw) : 0ull;
+            for (uint32_t s = lane; s < MS; s += 64)
+                if (mk[s] != kNone) xkey = umax64(xkey, vote_key(tie, mk[s], lb[s]));
+            xkey = wave_max64(xkey);
+            const uint32_t xs = key_label(tie, xkey);
+            const u64 V = xkey >> 32;
+            bool bad = false;
+            for (uint32_t s = lane; s < MS; s += 64) {
+                const uint32_t lab = mk[s];
+                if (lab != kNone) {
+                    if (lab != xs && vote_key(tie, lab, (u64)lb[s] + T - tr[s]) >= xkey) bad = true;
+                    mk[s] = kNone;
+                    lb[s] = 0;
+                    tr[s] = 0;
+                }
+            }
+            bad |= (T > 0 && T >= V);
+            const bool decided = __ballot(bad) == 0;
+            if (lane == 0) {
+                if (decided) {
+                    const uint32_t nl = xkey ? xs : own;
+                    a.L_new[h] = nl;
+                    wchg += nl != own;
+                } else {
+                    atomicOr(&hs.flags[h], HUB_FALLBACK);
+                    atomicOr(hs.pending, 1u);
+                }
+            }
+            wave_sync();
         }
-        wave_sync();
     }
     block_count(lane == 0 ? wchg : 0, a.changed);
 }
@@ -930,26 +961,42 @@ __global__ __launch_bounds__(256) void hub_merge_block_k(RoundArgs a, HubState h
 __global__ __launch_bounds__(256) void hub_reduce_k(RoundArgs a, HubState hs, const ReduceItem *__restrict__ items,
                                                     uint32_t count) {
     __shared__ BlockRed R;
+    __shared__ uint32_t act[256];
+    __shared__ uint32_t nact;
     if (!*hs.pending) return;  // no slab was used this round
-    for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
-        const ReduceItem r = items[it];
-        const uint32_t t1 = min(r.t1, hs.tcount[r.hub]);
-        if (r.t0 >= t1) continue;  // uniform over the block
-        u64 *slab = hs.slab + hs.slab_off[r.hub];
-        const uint32_t *tlist = hs.touched + hs.touched_off[r.hub];
-        const Tie tie = row_mode(a, r.hub).tie;  // rows of the other half claimed no slot
-        u64 best = 0, z0 = 0, z1 = 0;
-        uint32_t z2 = 0;
-        for (uint32_t p = r.t0 + threadIdx.x; p < t1; p += 256) {
-            const uint32_t s = tlist[p];
-            if (s != kNone) {
-                best = umax64(best, slot_key(tie, slab[s]));
-                slab[s] = EMPTY_SLOT;
-            }
-        }
-        block_reduce(R, best, z0, z1, z2);
-        if (threadIdx.x == 0 && best) atomicMax(&hs.best[r.hub], best);
+    // The block's items are blockIdx.x, + gridDim.x, ...; 256 of them are
+    // checked at once (one per thread) and only those whose row claimed slots
+    // in their range are reduced, so skipped items cost no dependent loads.
+    for (uint64_t k0 = 0; blockIdx.x + k0 * gridDim.x < count; k0 += 256) {
+        __syncthreads();  // every thread has read the previous batch's count
+        if (threadIdx.x == 0) nact = 0;
         __syncthreads();
+        const uint64_t i = blockIdx.x + (k0 + threadIdx.x) * gridDim.x;
+        if (i < count) {
+            const ReduceItem r = items[i];
+            if (r.t0 < min(r.t1, hs.tcount[r.hub])) act[atomicAdd(&nact, 1u)] = (uint32_t)i;
+        }
+        __syncthreads();
+        const uint32_t na = nact;
+        for (uint32_t q = 0; q < na; ++q) {
+            const ReduceItem r = items[act[q]];
+            const uint32_t t1 = min(r.t1, hs.tcount[r.hub]);
+            u64 *slab = hs.slab + hs.slab_off[r.hub];
+            const uint32_t *tlist = hs.touched + hs.touched_off[r.hub];
+            const Tie tie = row_mode(a, r.hub).tie;  // rows of the other half claimed no slot
+            u64 best = 0, z0 = 0, z1 = 0;
+            uint32_t z2 = 0;
+            for (uint32_t p = r.t0 + threadIdx.x; p < t1; p += 256) {
+                const uint32_t s = tlist[p];
+                if (s != kNone) {
+                    best = umax64(best, slot_key(tie, slab[s]));
+                    slab[s] = EMPTY_SLOT;
+                }
+            }
+            block_reduce(R, best, z0, z1, z2);
+            if (threadIdx.x == 0 && best) atomicMax(&hs.best[r.hub], best);
+            __syncthreads();
+        }
     }
 }
 
