@@ -166,6 +166,20 @@ __device__ __forceinline__ u64 wave_max64(u64 x) {
     return lane63_64(x);
 }
 
+// Inclusive prefix sum over the wavefront's lanes: shifts right by 1, 2, 4
+// and 8 lanes inside each 16-lane row (lanes shifted in from outside the row
+// receive 0), then the row broadcasts carry the totals of the rows below.
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;  // row_shr:n
+__device__ __forceinline__ u64 wave_scan_incl64(u64 x) {
+    x += dpp64<kDppShr1>(x);
+    x += dpp64<kDppShr2>(x);
+    x += dpp64<kDppShr4>(x);
+    x += dpp64<kDppShr8>(x);
+    x += dpp64<kDppBcast15, 0xA>(x);
+    x += dpp64<kDppBcast31, 0xC>(x);
+    return x;
+}
+
 // Insert (lab, wv) into an LDS table of mask+1 slots with linear probing.
 // The caller guarantees more slots than distinct labels.
 __device__ __forceinline__ void lds_insert(u64 *T, uint32_t mask, uint32_t lab, uint32_t wv) {

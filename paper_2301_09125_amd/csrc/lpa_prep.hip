@@ -93,12 +93,30 @@ __device__ __forceinline__ int bin_of(uint64_t d, const BinCfg &c) {
                          : BIN_HUB;
 }
 
-// Bin of vertex v, or -1 when its row_ptr entries are malformed.
-__device__ __forceinline__ int vertex_bin(const Graph &g, uint32_t v, const BinCfg &c, uint64_t &d, bool &bad) {
-    const uint64_t a = g.rp[v], b = g.rp[v + 1];
-    bad = (b < a) || (b > g.m) || (v == 0 && a != 0) || (v + 1 == g.n && b != g.m);
-    d = bad ? 0 : b - a;
-    return bad ? -1 : bin_of(d, c);
+// Bins of the four vertices blockIdx.x * kBinVerts + i * 256 + threadIdx.x
+// (-1 past the last vertex or when the vertex's row_ptr entries are
+// malformed) and their degrees.  The eight row_ptr loads are issued before
+// any is used: rows past the last vertex read the last row's bounds.
+__device__ __forceinline__ void vertex_bins4(const Graph &g, const BinCfg &c, int (&bins)[4], uint64_t (&degs)[4],
+                                             bool &bad_any) {
+    uint64_t ra[4], rb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t v = blockIdx.x * kBinVerts + i * 256 + threadIdx.x;
+        const uint32_t vc = v < g.n ? v : g.n - 1;
+        ra[i] = g.rp[vc];
+        rb[i] = g.rp[vc + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t v = blockIdx.x * kBinVerts + i * 256 + threadIdx.x;
+        const uint64_t a = ra[i], b = rb[i];
+        const bool bad = (b < a) || (b > g.m) || (v == 0 && a != 0) || (v + 1 == g.n && b != g.m);
+        const bool in = v < g.n;
+        bad_any |= in && bad;
+        degs[i] = (in && !bad) ? b - a : 0;
+        bins[i] = (in && !bad) ? bin_of(degs[i], c) : -1;
+    }
 }
 
 __global__ __launch_bounds__(256) void bin_count_k(Graph g, BinCfg cfg, uint32_t *blk_counts, u64 *blk_arcs,
@@ -118,22 +136,17 @@ __global__ __launch_bounds__(256) void bin_count_k(Graph g, BinCfg cfg, uint32_t
         my_cnt[b] = 0;
     }
     bool bad_any = false;
+    int bins[4];
+    uint64_t degs[4];
+    vertex_bins4(g, cfg, bins, degs, bad_any);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t v = blockIdx.x * kBinVerts + i * 256 + threadIdx.x;
-        if (v < g.n) {
-            uint64_t d;
-            bool bad;
-            const int bin = vertex_bin(g, v, cfg, d, bad);
-            bad_any |= bad;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int b = 0; b < NBINS; ++b)
-                if (bin == b) {
-                    my_cnt[b] += 1;
-                    my_arcs[b] += d;
-                }
-        }
-    }
+        for (int b = 0; b < NBINS; ++b)
+            if (bins[i] == b) {
+                my_cnt[b] += 1;
+                my_arcs[b] += degs[i];
+            }
     if (bad_any) atomicOr(err, ERR_ROWPTR);
 #pragma unroll
     for (int b = 0; b < NBINS; ++b) {
@@ -256,37 +269,44 @@ __global__ __launch_bounds__(256) void bin_scatter_k(Graph g, BinCfg cfg, const 
     __shared__ uint32_t run[NBINS];
     __shared__ u64 arun[NBINS];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the four vertices' row bounds are loaded before the first barrier
+    // (malformed rows were reported by bin_count_k)
+    int bins[4];
+    uint64_t degs[4];
+    bool bad_any = false;
+    vertex_bins4(g, cfg, bins, degs, bad_any);
     if (threadIdx.x < NBINS) {
         // offsets inside the bin, plus the totals of the bins before it
-        uint32_t base = 0;
-        u64 abase = 0;
-        for (uint32_t b = 0; b < threadIdx.x; ++b) {
-            base += totals[b];
-            abase += arc_totals[b];
+        uint32_t tb[NBINS];
+        u64 ab[NBINS];
+#pragma unroll
+        for (int b = 0; b < NBINS; ++b) {
+            tb[b] = totals[b];
+            ab[b] = arc_totals[b];
         }
-        run[threadIdx.x] = base + blk_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
-        arun[threadIdx.x] = abase + blk_arc_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
+        uint32_t base = blk_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
+        u64 abase = blk_arc_offsets[(size_t)threadIdx.x * nblk + blockIdx.x];
+#pragma unroll
+        for (int b = 0; b < NBINS; ++b)
+            if ((uint32_t)b < threadIdx.x) {
+                base += tb[b];
+                abase += ab[b];
+            }
+        run[threadIdx.x] = base;
+        arun[threadIdx.x] = abase;
     }
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint32_t v = blockIdx.x * kBinVerts + i * 256 + threadIdx.x;
-        int bin = -1;
-        uint64_t d = 0;
-        if (v < g.n) {
-            bool bad;
-            bin = vertex_bin(g, v, cfg, d, bad);
-        }
+        const int bin = bins[i];
+        const uint64_t d = degs[i];
         uint32_t rank = 0;
         u64 aex = 0;
 #pragma unroll
         for (int b = 0; b < NBINS; ++b) {
             const u64 mask = __ballot(bin == b);
-            u64 x = bin == b ? (u64)d : 0ull;
-            const u64 x0 = x;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const u64 y = __shfl_up(x, off, 64);
-                if ((int)lane >= off) x += y;
-            }
+            const u64 x0 = bin == b ? (u64)d : 0ull;
+            const u64 x = wave_scan_incl64(x0);
             if (lane == 63) warc[wave][b] = x;
             if (lane == 0) wcnt[wave][b] = (uint32_t)__popcll(mask);
             if (bin == b) {

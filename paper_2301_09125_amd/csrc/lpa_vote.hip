@@ -249,8 +249,8 @@ __global__ __launch_bounds__(256) void vote_group_k(RoundArgs a, uint32_t lo, ui
 }
 
 // One wavefront per row of at most A*64 arcs, A arcs per lane, SLOTS LDS
-// slots; the own label and two peeled labels are summed in registers before
-// the table.  The next row's arcs are loaded while the current one is voted.
+// slots; the own label is summed in registers, every other arc goes to the
+// table.  The next row's arcs are loaded while the current one is voted.
 template <bool FIRST, bool FEAT, int A, int SLOTS>
 __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uint32_t cnt) {
     __shared__ u64 table[4 * SLOTS];
@@ -326,7 +326,6 @@ __global__ __launch_bounds__(256) void vote_wave_k(RoundArgs a, uint32_t lo, uin
                         best = umax64(best, vote_key(tie, lab[j], wt[j]));
                 }
         } else if (__ballot(rem != 0)) {  // some label other than the own one
-            wave_peel<A, 2>(T, mask, lab, wt, rem);
 #pragma unroll
             for (int j = 0; j < A; ++j)
                 if (rem >> j & 1u) lds_insert(T, mask, lab[j], wt[j]);
@@ -683,7 +682,7 @@ __global__ __launch_bounds__(256) void vote_hub_k(RoundArgs a, const HubItem *__
             t.mask = S - 1;
             if (flags & HUB_BIG) {
                 bool flushed = false;
-                rem = listed_tally<A, FIRST ? 0 : 2>(t, lab, w, rem, kHubSpill);
+                rem = listed_tally<A>(t, lab, w, rem, kHubSpill);
                 for (;;) {
                     wave_sync();
                     if (t.n) {
@@ -692,14 +691,14 @@ __global__ __launch_bounds__(256) void vote_hub_k(RoundArgs a, const HubItem *__
                         wave_sync();
                     }
                     if (!__ballot(rem != 0)) break;
-                    rem = listed_tally<A, 0>(t, lab, w, rem, kHubSpill);
+                    rem = listed_tally<A>(t, lab, w, rem, kHubSpill);
                 }
                 if (lane == 0 && flushed) atomicOr(hs.pending, 1u);
             } else {
                 const bool any = __ballot(rem != 0) != 0;
                 bool spilled = false;
                 if (any) {
-                    rem = listed_tally<A, FIRST ? 0 : 2>(t, lab, w, rem, kHubSpill);
+                    rem = listed_tally<A>(t, lab, w, rem, kHubSpill);
                     spilled = __ballot(rem != 0) != 0;
                     wave_sync();
                 }
@@ -779,7 +778,7 @@ __global__ __launch_bounds__(256) void hub_fallback_k(RoundArgs a, const HubItem
             uint32_t S = next_pow2(2u * (uint32_t)(item.b1 - item.b0));
             S = S < 64u ? 64u : (S > (uint32_t)kWaveSlots ? (uint32_t)kWaveSlots : S);
             t.mask = S - 1;
-            listed_tally<A, 2>(t, lab, wt, rem);
+            listed_tally<A>(t, lab, wt, rem);
             wave_sync();
             flush_listed_to_slab(t, hs, h);
             wave_sync();

@@ -205,35 +205,15 @@ __device__ __forceinline__ void listed_insert(ListedTable &t, bool go, uint32_t 
     }
 }
 
-// wave_peel for a listed table, then the insertion of the arcs left, one
-// column j at a time, stopping once the table holds more than `cap` labels.
-// Returns the bits of `rem` not inserted (0 when everything went in).  Each
-// step claims at most 64 slots, so a table of at least cap + 65 slots never
-// fills up.
-template <int A, int NPEEL>
+// Insert the arcs of `rem`, one column j at a time, stopping once the table
+// holds more than `cap` labels.  Returns the bits of `rem` not inserted (0
+// when everything went in).  Each step claims at most 64 slots, so a table of
+// at least cap + 65 slots never fills up.  (Summing the most frequent label
+// across the wavefront first, as wave_peel does, costs these tables more
+// than the LDS atomics it saves.)
+template <int A>
 __device__ __forceinline__ uint32_t listed_tally(ListedTable &t, const uint32_t (&lab)[A], const uint32_t (&wt)[A],
                                                  uint32_t rem, uint32_t cap = 0xFFFFFFFFu) {
-    const uint32_t lane = threadIdx.x & 63;
-#pragma unroll
-    for (int p = 0; p < NPEEL; ++p) {
-        const u64 m = __ballot(rem != 0);
-        if (!m) return 0;
-        const int lead = __ffsll((long long)m) - 1;
-        uint32_t mine = 0;
-#pragma unroll
-        for (int j = A - 1; j >= 0; --j)
-            if (rem >> j & 1u) mine = lab[j];
-        const uint32_t L = (uint32_t)__builtin_amdgcn_readlane((int)mine, lead);
-        uint32_t s = 0;
-#pragma unroll
-        for (int j = 0; j < A; ++j)
-            if ((rem >> j & 1u) && lab[j] == L) {
-                s += wt[j];
-                rem &= ~(1u << j);
-            }
-        s = wave_sum(s);
-        listed_insert(t, (int)lane == lead, L, s);
-    }
 #pragma unroll
     for (int j = 0; j < A; ++j) {
         if (t.n > cap) return rem;
