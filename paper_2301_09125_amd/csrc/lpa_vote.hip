@@ -840,20 +840,48 @@ __global__ __launch_bounds__(256) void hub_merge_wave_k(RoundArgs a, HubState hs
                 osl = hs.own_sum[hl];
             }
         }
-        for (u64 m = __ballot(go); m; m &= m - 1) {
+        // the reports of a row: its segments' thr (one per lane) and up to
+        // 2 * 64 candidates with their segments' thr; the next row's are
+        // requested before the current one is merged
+        constexpr int CQ = kMergeWaveSegs * kTopK / 64;
+        static_assert(CQ * 64 == kMergeWaveSegs * kTopK, "candidates per lane");
+        auto fetch_row = [&](int l, uint32_t &th, u64 (&cx)[CQ], uint32_t (&ct)[CQ]) {
+            const uint32_t lo = __builtin_amdgcn_readlane(lol, l), ns = __builtin_amdgcn_readlane(nsl, l);
+            th = lane < ns ? hs.thr[lo + lane] : 0u;
+#pragma unroll
+            for (int q = 0; q < CQ; ++q) {
+                const uint32_t e = lane + 64u * q;
+                const bool in = e < ns * kTopK;
+                cx[q] = in ? hs.cand[(u64)lo * kTopK + e] : EMPTY_SLOT;
+                ct[q] = in ? hs.thr[lo + e / kTopK] : 0u;
+            }
+        };
+        u64 m = __ballot(go);
+        uint32_t th = 0, ct[CQ];
+        u64 cx[CQ];
+        if (m) fetch_row((int)__builtin_ctzll(m), th, cx, ct);
+        for (; m; m &= m - 1) {
             const int l = (int)__builtin_ctzll(m);
             const uint32_t h = __builtin_amdgcn_readlane(hl, l);
             const uint32_t flags = __builtin_amdgcn_readlane(fl, l);
-            const uint32_t lo = __builtin_amdgcn_readlane(lol, l), ns = __builtin_amdgcn_readlane(nsl, l);
             const uint32_t own = __builtin_amdgcn_readlane(ownl, l);
             const u64 own_sum = ((u64)__builtin_amdgcn_readlane((uint32_t)(osl >> 32), l) << 32) |
                                 __builtin_amdgcn_readlane((uint32_t)osl, l);
             const Tie tie = row_mode(a, h).tie;
-            const u64 T = wave_sum((u64)(lane < ns ? hs.thr[lo + lane] : 0u));
-            for (uint32_t e = lane; e < ns * kTopK; e += 64) {
-                const u64 x = hs.cand[(u64)lo * kTopK + e];
-                if (x != EMPTY_SLOT) merge_insert(mk, lb, tr, MS - 1, (uint32_t)(x >> 32), (uint32_t)x, hs.thr[lo + e / kTopK]);
+            const uint32_t cth = th;
+            u64 ccx[CQ];
+            uint32_t cct[CQ];
+#pragma unroll
+            for (int q = 0; q < CQ; ++q) {
+                ccx[q] = cx[q];
+                cct[q] = ct[q];
             }
+            const u64 rest = m & (m - 1);
+            if (rest) fetch_row((int)__builtin_ctzll(rest), th, cx, ct);
+            const u64 T = wave_sum((u64)cth);
+#pragma unroll
+            for (int q = 0; q < CQ; ++q)
+                if (ccx[q] != EMPTY_SLOT) merge_insert(mk, lb, tr, MS - 1, (uint32_t)(ccx[q] >> 32), (uint32_t)ccx[q], cct[q]);
             wave_sync();
             u64 xkey = ((flags & HUB_OWN_SEEN) || a.sw) ? vote_key(tie, own, own_sum + a.sw) : 0ull;
             for (uint32_t s = lane; s < MS; s += 64)
