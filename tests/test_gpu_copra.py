@@ -77,7 +77,7 @@ def corpus(gg):
 @pytest.mark.parametrize("order,tie", MODES)
 def test_copra_corpus(gg, orc, lpa, order, tie):
     for g in corpus(gg):
-        for V in (1, 2, 4, 16):
+        for V in (1, 2, 3, 4, 7, 16):  # records of 4, 8, 8, 16, 16 and 64 words
             say("[copra]", order, tie, getattr(g, "name", ""), g.n, g.m, "V", V)
             assert_copra(orc, lpa, g, V, order, tie, 7 + V, tol=0.0, max_iter=8)
 
