@@ -26,8 +26,9 @@
 //
 // Work that would serialise on one address is avoided: every vertex's own
 // label is tallied in registers (most neighbours hold it in late rounds),
-// wavefronts pre-sum their most frequent labels before touching a table,
 // and changed counts go to per-block partials spread over cache lines.
+// (Pre-summing a wavefront's most frequent labels before its table, as the
+// batched kernel does, measured slower in these tables.)
 // Every kernel loop is wavefront-uniform and uses no block barrier, so the
 // wavefronts of a block proceed independently.
 //

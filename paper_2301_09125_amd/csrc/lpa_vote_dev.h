@@ -1,7 +1,8 @@
 // lpa_vote_dev.h -- device building blocks of a vote shared by the per-round
 // kernels (lpa_vote.hip) and the persistent batch kernel (lpa_batch.hip):
 // arc loading, label gathering, own-label tally, wavefront pre-aggregation
-// and the global slab used to merge the tallies of long rows.
+// (the batch kernel's), LDS tables and the global slab used to merge the
+// tallies of long rows.
 #pragma once
 
 #include "lpa_device.h"
